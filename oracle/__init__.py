@@ -1,0 +1,290 @@
+"""ORACLE -- test infrastructure only.
+
+ctypes wrapper around ``libnbgs_ref.so``, the plain sequential FP64 C reference
+of the per-time-step hard-contact solve (contact detection, greedy colouring,
+colour-ordered nonlinear block Gauss-Seidel, semi-implicit Euler) and of the
+warm-start MLP.  Only ``tests/``, the smoke check and the CPU-baseline leg of
+``bench.py`` may import this package; the GPU library never does.
+
+Inputs are numpy arrays (host memory).  A ``World`` borrows the body arrays of
+a :class:`scenegen.Scene` and mutates positions, orientations and velocities in
+place on ``integrate``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbgs_ref.so")
+SOURCES = [os.path.join(HERE, "nbgs_ref.c"), os.path.join(HERE, "mlp_ref.c")]
+
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_u64p = C.POINTER(C.c_uint64)
+
+
+class RefBodies(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, _dp) for f in
+                                      ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
+                                       "radius", "inv_mass", "inv_inertia")]
+
+
+class RefPlane(C.Structure):
+    _fields_ = [("point", C.c_double * 3), ("normal", C.c_double * 3)]
+
+
+class RefDomain(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("periodic", C.c_int32 * 3),
+                ("n_planes", C.c_int32), ("planes", C.POINTER(RefPlane))]
+
+
+class RefParams(C.Structure):
+    _fields_ = [("dt", C.c_double), ("gravity", C.c_double * 3), ("mu", C.c_double), ("tau", C.c_double),
+                ("relax", C.c_double), ("erp", C.c_double), ("colour_seed", C.c_uint64)]
+
+
+class RefContacts(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("j1", _i32p), ("j2", _i32p), ("key", _u64p)] + \
+               [(f, _dp) for f in ("nx", "ny", "nz", "xi", "a1", "a2")]
+
+
+class RefSolveStats(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("residual", C.c_double)]
+
+
+class RefWorldView(C.Structure):
+    _fields_ = [("n_contacts", C.c_int64), ("n_colours", C.c_int32), ("sweeps", C.c_int32),
+                ("residual", C.c_double), ("j1", _i32p), ("j2", _i32p), ("colour", _i32p), ("key", _u64p)] + \
+               [(f, _dp) for f in ("nx", "ny", "nz", "xi", "a1", "a2", "px", "py", "pz")] + \
+               [("order", _i64p), ("v", _dp), ("w", _dp), ("residual_hist", _dp)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (strict IEEE evaluation, no contraction)."""
+    srcs = [s for s in SOURCES if os.path.exists(s)]
+    if not force and os.path.exists(LIB_PATH) and all(os.path.getmtime(LIB_PATH) >= os.path.getmtime(s) for s in srcs):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB_PATH)
+        L.nbgs_ref_detect_brute.restype = C.c_int64
+        L.nbgs_ref_detect_grid.restype = C.c_int64
+        L.nbgs_ref_colour.restype = C.c_int32
+        L.nbgs_ref_splitmix64.restype = C.c_uint64
+        L.nbgs_ref_splitmix64.argtypes = [C.c_uint64]
+        L.nbgs_ref_world_create.restype = C.c_void_p
+        L.nbgs_ref_world_create.argtypes = [C.POINTER(RefBodies), C.POINTER(RefDomain), C.POINTER(RefParams)]
+        for f in ("destroy", "integrate"):
+            getattr(L, "nbgs_ref_world_" + f).argtypes = [C.c_void_p]
+        L.nbgs_ref_world_detect.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.nbgs_ref_world_solve.argtypes = [C.c_void_p, C.c_int32, C.c_double]
+        L.nbgs_ref_world_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double]
+        L.nbgs_ref_world_view_get.argtypes = [C.c_void_p, C.POINTER(RefWorldView)]
+        L.nbgs_ref_world_set_impulses.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.nbgs_ref_world_set_prev.argtypes = [C.c_void_p, C.c_int64, _u64p, _dp, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+class _Held:
+    """Keeps the numpy arrays behind a ctypes struct alive."""
+
+    def __init__(self):
+        self.arrays = []
+
+
+def make_bodies(sc, held: _Held) -> RefBodies:
+    cols = {}
+    for name, arr, k in (("x", sc.pos, 0), ("y", sc.pos, 1), ("z", sc.pos, 2), ("qw", sc.quat, 0),
+                         ("qx", sc.quat, 1), ("qy", sc.quat, 2), ("qz", sc.quat, 3), ("vx", sc.vel, 0),
+                         ("vy", sc.vel, 1), ("vz", sc.vel, 2), ("wx", sc.angvel, 0), ("wy", sc.angvel, 1),
+                         ("wz", sc.angvel, 2)):
+        cols[name] = np.ascontiguousarray(arr[:, k], dtype=np.float64)
+    for name in ("radius", "inv_mass", "inv_inertia"):
+        cols[name] = np.ascontiguousarray(getattr(sc, name), dtype=np.float64)
+    held.arrays.append(cols)
+    b = RefBodies(n=sc.n, **{k: _ptr(v) for k, v in cols.items()})
+    b._cols = cols
+    return b
+
+
+def make_domain(sc, held: _Held) -> RefDomain:
+    planes = (RefPlane * max(1, len(sc.planes)))()
+    for i, (pt, nm) in enumerate(sc.planes):
+        planes[i].point[:] = list(pt)
+        planes[i].normal[:] = list(nm)
+    held.arrays.append(planes)
+    return RefDomain(lo=(C.c_double * 3)(*sc.lo), hi=(C.c_double * 3)(*sc.hi),
+                     periodic=(C.c_int32 * 3)(*[int(bool(p)) for p in sc.periodic]),
+                     n_planes=len(sc.planes), planes=C.cast(planes, C.POINTER(RefPlane)))
+
+
+def make_params(sc) -> RefParams:
+    return RefParams(dt=sc.dt, gravity=(C.c_double * 3)(*sc.gravity), mu=sc.mu, tau=sc.tau, relax=sc.relax,
+                     erp=sc.erp, colour_seed=sc.colour_seed & 0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(x: int) -> int:
+    return int(lib().nbgs_ref_splitmix64(C.c_uint64(x & 0xFFFFFFFFFFFFFFFF)))
+
+
+def detect(sc, method: str = "brute") -> Dict[str, np.ndarray]:
+    """Contact set of a scene in key order: j1, j2, key, n (m x 3), xi, a1, a2."""
+    L = lib()
+    held = _Held()
+    b, d, p = make_bodies(sc, held), make_domain(sc, held), make_params(sc)
+    fn = L.nbgs_ref_detect_brute if method == "brute" else L.nbgs_ref_detect_grid
+    cap = max(16, 8 * sc.n)
+    while True:
+        out = {k: np.zeros(cap, dtype=t) for k, t in (("j1", np.int32), ("j2", np.int32), ("key", np.uint64),
+                                                       ("nx", np.float64), ("ny", np.float64), ("nz", np.float64),
+                                                       ("xi", np.float64), ("a1", np.float64), ("a2", np.float64))}
+        c = RefContacts(cap=cap, j1=_ptr(out["j1"], _i32p), j2=_ptr(out["j2"], _i32p), key=_ptr(out["key"], _u64p),
+                        **{k: _ptr(out[k]) for k in ("nx", "ny", "nz", "xi", "a1", "a2")})
+        m = fn(C.byref(b), C.byref(d), C.byref(p), C.byref(c))
+        if m <= cap:
+            break
+        cap = int(m)
+    res = {k: v[:m].copy() for k, v in out.items()}
+    res["n"] = np.stack([res.pop("nx"), res.pop("ny"), res.pop("nz")], axis=1)
+    return res
+
+
+def hull_radii(sc) -> np.ndarray:
+    held = _Held()
+    b, p = make_bodies(sc, held), make_params(sc)
+    h = np.zeros(sc.n)
+    lib().nbgs_ref_hull_radii(C.byref(b), C.byref(p), _ptr(h))
+    return h
+
+
+def colour(n_bodies: int, inv_mass: np.ndarray, j1: np.ndarray, j2: np.ndarray, key: np.ndarray, seed: int):
+    """Greedy colouring in descending splitmix64 priority; returns (colour per contact, number of colours)."""
+    m = int(j1.shape[0])
+    col = np.full(max(m, 1), -1, dtype=np.int32)
+    im = np.ascontiguousarray(inv_mass, dtype=np.float64)
+    j1c = np.ascontiguousarray(j1, dtype=np.int32)
+    j2c = np.ascontiguousarray(j2, dtype=np.int32)
+    kc = np.ascontiguousarray(key, dtype=np.uint64)
+    nc = lib().nbgs_ref_colour(C.c_int64(n_bodies), _ptr(im), C.c_int64(m), _ptr(j1c, _i32p), _ptr(j2c, _i32p),
+                               _ptr(kc, _u64p), C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _ptr(col, _i32p))
+    return col[:m].copy(), int(nc)
+
+
+def sweep_order(col: np.ndarray, n_colours: int) -> np.ndarray:
+    m = int(col.shape[0])
+    order = np.zeros(max(m, 1), dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    lib().nbgs_ref_sweep_order(C.c_int64(m), _ptr(c, _i32p), C.c_int32(n_colours), _ptr(order, _i64p))
+    return order[:m].copy()
+
+
+class World:
+    """Stateful oracle scene (borrowed Scene arrays are written back on integrate)."""
+
+    def __init__(self, sc):
+        self.sc = sc
+        self._held = _Held()
+        self._b = make_bodies(sc, self._held)
+        self._d = make_domain(sc, self._held)
+        self._p = make_params(sc)
+        self._w = lib().nbgs_ref_world_create(C.byref(self._b), C.byref(self._d), C.byref(self._p))
+
+    def __del__(self):
+        try:
+            if self._w:
+                lib().nbgs_ref_world_destroy(self._w)
+                self._w = None
+        except Exception:
+            pass
+
+    def _pull(self):
+        cols = self._b._cols
+        for name, arr, k in (("x", "pos", 0), ("y", "pos", 1), ("z", "pos", 2), ("qw", "quat", 0),
+                             ("qx", "quat", 1), ("qy", "quat", 2), ("qz", "quat", 3), ("vx", "vel", 0),
+                             ("vy", "vel", 1), ("vz", "vel", 2), ("wx", "angvel", 0), ("wy", "angvel", 1),
+                             ("wz", "angvel", 2)):
+            getattr(self.sc, arr)[:, k] = cols[name]
+
+    def push(self):
+        """Copy the Scene's arrays into the oracle's body columns (after an external edit)."""
+        cols = self._b._cols
+        for name, arr, k in (("x", "pos", 0), ("y", "pos", 1), ("z", "pos", 2), ("qw", "quat", 0),
+                             ("qx", "quat", 1), ("qy", "quat", 2), ("qz", "quat", 3), ("vx", "vel", 0),
+                             ("vy", "vel", 1), ("vz", "vel", 2), ("wx", "angvel", 0), ("wy", "angvel", 1),
+                             ("wz", "angvel", 2)):
+            cols[name][:] = getattr(self.sc, arr)[:, k]
+
+    def detect(self, grid: bool = False, warm: bool = True):
+        lib().nbgs_ref_world_detect(self._w, int(grid), int(warm))
+        return self
+
+    def set_impulses(self, P: np.ndarray):
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        cols = [np.ascontiguousarray(P[:, k]) for k in range(3)]
+        lib().nbgs_ref_world_set_impulses(self._w, *[_ptr(c) for c in cols])
+
+    def set_prev(self, key: np.ndarray, P: np.ndarray):
+        key = np.ascontiguousarray(key, dtype=np.uint64)
+        cols = [np.ascontiguousarray(P[:, k], dtype=np.float64) for k in range(3)]
+        lib().nbgs_ref_world_set_prev(self._w, C.c_int64(key.shape[0]), _ptr(key, _u64p), *[_ptr(c) for c in cols])
+
+    def solve(self, max_sweeps: int, target: float = 0.0):
+        lib().nbgs_ref_world_solve(self._w, int(max_sweeps), float(target))
+        return self
+
+    def integrate(self):
+        lib().nbgs_ref_world_integrate(self._w)
+        self._pull()
+        return self
+
+    def step(self, max_sweeps: int, target: float = 0.0, grid: bool = False, warm: bool = True):
+        lib().nbgs_ref_world_step(self._w, int(grid), int(warm), int(max_sweeps), float(target))
+        self._pull()
+        return self
+
+    def view(self) -> Dict[str, np.ndarray]:
+        v = RefWorldView()
+        lib().nbgs_ref_world_view_get(self._w, C.byref(v))
+        m = int(v.n_contacts)
+        n = self.sc.n
+
+        def arr(p, count, dtype):
+            if count == 0:
+                return np.zeros(0, dtype=dtype)
+            return np.ctypeslib.as_array(p, shape=(count,)).astype(dtype, copy=True)
+
+        out = dict(n_contacts=m, n_colours=int(v.n_colours), sweeps=int(v.sweeps), residual=float(v.residual),
+                   j1=arr(v.j1, m, np.int32), j2=arr(v.j2, m, np.int32), colour=arr(v.colour, m, np.int32),
+                   key=arr(v.key, m, np.uint64), xi=arr(v.xi, m, np.float64), a1=arr(v.a1, m, np.float64),
+                   a2=arr(v.a2, m, np.float64), order=arr(v.order, m, np.int64))
+        out["n"] = np.stack([arr(v.nx, m, np.float64), arr(v.ny, m, np.float64), arr(v.nz, m, np.float64)], axis=1)
+        out["P"] = np.stack([arr(v.px, m, np.float64), arr(v.py, m, np.float64), arr(v.pz, m, np.float64)], axis=1)
+        out["v"] = arr(v.v, 3 * n, np.float64).reshape(n, 3)
+        out["w"] = arr(v.w, 3 * n, np.float64).reshape(n, 3)
+        hist = arr(v.residual_hist, int(v.sweeps), np.float64) if v.residual_hist else np.zeros(0)
+        out["residual_hist"] = hist
+        return out
