@@ -1,0 +1,212 @@
+/*
+ * nbgs.h -- C ABI of the MI355X (gfx950) hard-contact granular solver.
+ *
+ * One time step of the method of Preclik & Ruede, "Ultrascale Simulations of
+ * Non-smooth Granular Dynamics" (single-process form of Alg. 2, Sect. 6.6):
+ *   nbgs_detect     contact detection with intersection hulls (Sect. 4,
+ *                   eq. (expansionradius), eq. (contactpos) for spheres and
+ *                   wall planes), colouring of the contacts, initial impulses
+ *                   (zero or previous step, Sect. 5);
+ *   nbgs_solve      nonlinear block Gauss-Seidel sweeps (Alg. 1 with one
+ *                   subdomain, run colour by colour; per contact the 3x3
+ *                   Coulomb one-contact problem of eqs. (nonpenetration) and
+ *                   (coulomb) is solved and projected onto the friction cone);
+ *   nbgs_integrate  semi-implicit Euler of eq. (integrationscheme) with
+ *                   quaternion renormalisation (Sect. 3);
+ *   nbgs_step       the three in sequence.
+ *
+ * Conventions (shared by every entry point)
+ *   - Pointers marked [device] are HIP device pointers, [host] are host
+ *     pointers.  Body arrays are owned by the caller (e.g. torch tensors) and
+ *     borrowed by the scene for its lifetime; nbgs_integrate / nbgs_step write
+ *     positions, orientations and velocities in place.  Everything else the
+ *     scene needs it allocates itself and frees in nbgs_scene_destroy.
+ *   - All device work is enqueued on the stream passed to nbgs_scene_create
+ *     (NULL = the legacy default stream).  Entry points that return counts in a
+ *     host nbgs_stats synchronise that stream before returning.
+ *   - Every entry point returns an nbgs_status and never throws; the detail of
+ *     the last non-OK status of the calling thread is in nbgs_last_error().
+ *   - Units: the solver works with contact impulses P = dt * lambda, where
+ *     lambda is the contact force of eq. (integrationscheme).
+ *   - Contact j joins bodies j1 < j2; wall plane w acts as body n_bodies + w and
+ *     is always j2.  The normal points from j2 towards j1 (outward from j2),
+ *     the contact point lies on the surface of j2 (eq. (contactpos)), and the
+ *     impulse acts +P on j1 and -P on j2 (eq. (wrench)).  The pair key is
+ *     (j1 << 32) | j2; the canonical contact order is ascending key.
+ */
+#ifndef NBGS_H
+#define NBGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBGS_ABI_VERSION 1
+
+typedef enum {
+    NBGS_OK = 0,
+    NBGS_ERR_INVALID_ARG = 1,   /* bad pointer, size or parameter value */
+    NBGS_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed */
+    NBGS_ERR_CAPACITY = 3,      /* a fixed limit was exceeded (colours > 255, counts >= 2^31, buffer too small) */
+    NBGS_ERR_DEVICE = 4,        /* a HIP call failed */
+    NBGS_ERR_NOT_CONVERGED = 5, /* residual target not reached within max_sweeps (impulses are still valid) */
+    NBGS_ERR_STATE = 6,         /* wrong call order, e.g. solve before detect */
+    NBGS_ERR_NUMERIC = 7,       /* NaN or Inf met in the residual */
+    NBGS_ERR_UNSUPPORTED = 8
+} nbgs_status;
+
+typedef struct nbgs_scene_s *nbgs_scene_t;
+
+/* Arithmetic of the sweeps.  Detection, the residual and integration are FP64
+ * in both modes; NBGS_FP32_SWEEP keeps the velocity accumulators, the impulses
+ * and the per-contact sweep record in FP32. */
+typedef enum { NBGS_FP64 = 0, NBGS_FP32_SWEEP = 1 } nbgs_precision;
+
+/* Initial impulses of a solve (Sect. 5: zero, or the previous step's). */
+typedef enum { NBGS_WS_ZERO = 0, NBGS_WS_PREVIOUS = 1 } nbgs_warm_start;
+
+/* Body state, structure of arrays of length n, FP64, [device].  Spheres only:
+ * radius is the bounding radius r_i of eq. (expansionradius).  inv_mass = 0
+ * marks a static body, which must then also have inv_inertia = 0;
+ * inv_inertia = 0 with inv_mass > 0 is a rotation-locked body.  The inertia is
+ * isotropic (inv_inertia is 1/I of a body whose principal moments are equal,
+ * Sect. 2), so the gyroscopic term w x I w vanishes. */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;
+    double *qw, *qx, *qy, *qz;
+    double *vx, *vy, *vz;
+    double *wx, *wy, *wz;
+    const double *radius, *inv_mass, *inv_inertia;
+} nbgs_bodies;
+
+/* A wall: a global body of infinite inertia and zero velocity (Sect. 6.4). */
+typedef struct {
+    double point[3];
+    double normal[3]; /* unit length, pointing into the domain */
+} nbgs_plane;
+
+/* Domain box [lo, hi).  Periodic axes use minimum-image separations and wrap
+ * positions after integration; they need hi - lo >= 3 cell edges (a cell edge
+ * is at least twice the largest r + h).  planes: [host], copied at create. */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t periodic[3];
+    int32_t n_planes;
+    const nbgs_plane *planes;
+} nbgs_domain;
+
+typedef struct {
+    double dt;          /* time step, > 0 */
+    double gravity[3];  /* external acceleration of every dynamic body */
+    double mu;          /* coefficient of friction, eq. (coulomb), >= 0 */
+    double tau;         /* hull safety margin of eq. (expansionradius), >= 0 */
+    double relax;       /* relaxation parameter omega of Alg. 1, in (0, 1] */
+    double erp;         /* scale of the xi/dt penetration correction when xi < 0 (Sect. 3), in [0, 1] */
+    int32_t precision;  /* nbgs_precision */
+    int32_t warm_start; /* nbgs_warm_start */
+    uint64_t colour_seed; /* seed of the contact priorities of the colouring */
+} nbgs_params;
+
+typedef struct {
+    int64_t n_contacts;
+    int32_t n_colours;
+    int32_t sweeps;   /* sweeps done by the last solve */
+    double residual;  /* R of the last sweep: |dP|_2 / |P|_2 over all contacts of that sweep */
+} nbgs_stats;
+
+/* ABI version of the loaded library (NBGS_ABI_VERSION). */
+int32_t nbgs_abi_version(void);
+
+/* Message of the calling thread's last non-OK status ("" if none).  The
+ * pointer stays valid until the next failing call on the same thread. */
+const char *nbgs_last_error(void);
+
+/* Create a scene that borrows the body arrays.  bodies, domain, params:
+ * [host] structs (the body pointers inside are [device]).  hip_stream: a
+ * hipStream_t or NULL.  Errors: INVALID_ARG (n < 1, n >= 2^31 - 64, null
+ * pointer, dt <= 0, relax not in (0,1], a static body with inv_inertia != 0,
+ * a non-unit plane normal), OUT_OF_MEMORY, DEVICE.  *out receives the handle,
+ * which the caller releases with nbgs_scene_destroy. */
+nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *domain, const nbgs_params *params,
+                              void *hip_stream, nbgs_scene_t *out);
+
+/* Release the scene and everything it allocated (synchronises its stream).
+ * The body arrays are not touched.  NULL is accepted. */
+nbgs_status nbgs_scene_destroy(nbgs_scene_t scene);
+
+/* Replace the parameters (e.g. switch precision or warm start between steps).
+ * Same checks as nbgs_scene_create. */
+nbgs_status nbgs_scene_set_params(nbgs_scene_t scene, const nbgs_params *params);
+
+/* Contact detection for the current body state (Sect. 4): hull radii
+ * h_i = dt(|v_i| + |w_i| r_i) + tau, every pair whose hulls intersect
+ * (|x_i - x_k| <= (r_i + h_i) + (r_k + h_k)) and every sphere/wall pair with
+ * gap <= h_i + tau becomes a contact; pairs of two static bodies are skipped.
+ * Then the contacts are coloured (greedy first-fit in descending
+ * splitmix64(key ^ colour_seed) priority, conflicts = shared body with
+ * inv_mass > 0) and ordered by (colour, key) for the sweeps, and the initial
+ * impulses are set (params.warm_start).  stats: [host] or NULL (then only
+ * n_contacts of the scene is known after the next synchronising call).
+ * Errors: CAPACITY (more than 255 colours, counts >= 2^31), OUT_OF_MEMORY,
+ * DEVICE. */
+nbgs_status nbgs_detect(nbgs_scene_t scene, nbgs_stats *stats);
+
+/* NBGS sweeps over the detected contacts (Alg. 1, one subdomain, colour
+ * order).  max_sweeps >= 1.  residual_target > 0: stop after the first sweep
+ * whose R <= residual_target (NOT_CONVERGED if none within max_sweeps);
+ * residual_target <= 0: exactly max_sweeps sweeps.  stats: [host] or NULL.
+ * Errors: STATE (no detect since the last integrate), NUMERIC (NaN residual),
+ * NOT_CONVERGED, DEVICE. */
+nbgs_status nbgs_solve(nbgs_scene_t scene, int32_t max_sweeps, double residual_target, nbgs_stats *stats);
+
+/* Semi-implicit Euler (eq. (integrationscheme)): v <- v', w <- w',
+ * x <- x + dt v', q <- normalise(q + dt Q(q) w'), periodic wrap.  Saves the
+ * (key, impulse) table for the next step's warm start.  Errors: STATE (no
+ * solve since the last detect), DEVICE. */
+nbgs_status nbgs_integrate(nbgs_scene_t scene);
+
+/* nbgs_detect + nbgs_solve + nbgs_integrate.  NOT_CONVERGED from the solve is
+ * returned after the integration has still been done. */
+nbgs_status nbgs_step(nbgs_scene_t scene, int32_t max_sweeps, double residual_target, nbgs_stats *stats);
+
+/* Copy the current contact list in canonical (key) order into caller buffers
+ * [device], each NULL-able: j1, j2, key, colour of length cap; normal and
+ * impulse as three consecutive planes of cap doubles (x[cap], y[cap], z[cap]);
+ * xi of length cap.  impulse holds the initial impulses after nbgs_detect and
+ * the solved ones after nbgs_solve.  *n_out [host] receives the contact
+ * count; CAPACITY if it exceeds cap (nothing copied).  Synchronises. */
+nbgs_status nbgs_get_contacts(nbgs_scene_t scene, int64_t cap, int32_t *j1, int32_t *j2, uint64_t *key,
+                              int32_t *colour, double *normal, double *xi, double *impulse, int64_t *n_out);
+
+/* Copy the velocity accumulators v', w' after the last solve into [device]
+ * buffers of 3 n doubles each (planes x[n], y[n], z[n]).  STATE before the
+ * first solve. */
+nbgs_status nbgs_get_accumulators(nbgs_scene_t scene, double *v, double *w);
+
+/* Residual history of the last solve: R of sweeps 1..min(cap, sweeps) into
+ * hist [host]; *n_out [host] = number of sweeps.  Synchronises. */
+nbgs_status nbgs_get_residuals(nbgs_scene_t scene, int32_t cap, double *hist, int32_t *n_out);
+
+/* Replace the previous-step table used by NBGS_WS_PREVIOUS: n entries, keys
+ * [device] strictly ascending, impulse [device] three planes of n doubles.
+ * The next nbgs_detect matches every contact's key in it, re-projects the
+ * impulse onto the new normal and cone (P_n = max(0, n.P), |P_t| <= mu P_n)
+ * and starts unmatched contacts at zero. */
+nbgs_status nbgs_set_warm_start(nbgs_scene_t scene, int64_t n, const uint64_t *keys, const double *impulse);
+
+/* Device milliseconds of the phases of the last step (HIP events on the
+ * scene's stream): out[0] detect (hull, sort, cells, pairs, narrow phase),
+ * out[1] colouring and ordering, out[2] accumulator init, out[3] sweeps
+ * incl. residuals, out[4] integrate.  n: entries wanted (<= 5).
+ * Synchronises. */
+nbgs_status nbgs_get_phase_times(nbgs_scene_t scene, int32_t n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBGS_H */

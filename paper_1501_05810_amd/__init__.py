@@ -1,0 +1,335 @@
+"""Python binding of ``libnbgs.so``, the gfx950 hard-contact granular solver.
+
+Argument marshalling only: every step of the time step (detection, colouring,
+accumulator init, NBGS sweeps, integration) runs in the library's HIP kernels.
+Device memory and the stream come from PyTorch.  The functions ``nbgs_*`` map
+one to one onto the C ABI of ``include/nbgs.h``; :class:`GpuScene` is a small
+convenience wrapper that owns the torch tensors of one scene.
+
+Importing this package fails loudly if the library has not been built (there
+is no CPU fallback): run ``python -m paper_1501_05810_amd.build`` or
+``__graft_entry__.build()``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbgs.so")
+
+NBGS_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "CAPACITY", 4: "DEVICE", 5: "NOT_CONVERGED",
+                6: "STATE", 7: "NUMERIC", 8: "UNSUPPORTED"}
+NBGS_ERR_NOT_CONVERGED = 5
+NBGS_FP64, NBGS_FP32_SWEEP = 0, 1
+NBGS_WS_ZERO, NBGS_WS_PREVIOUS = 0, 1
+
+_vp = C.c_void_p
+
+
+class nbgs_bodies(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, _vp) for f in
+                                      ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
+                                       "radius", "inv_mass", "inv_inertia")]
+
+
+class nbgs_plane(C.Structure):
+    _fields_ = [("point", C.c_double * 3), ("normal", C.c_double * 3)]
+
+
+class nbgs_domain(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("periodic", C.c_int32 * 3),
+                ("n_planes", C.c_int32), ("planes", C.POINTER(nbgs_plane))]
+
+
+class nbgs_params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("gravity", C.c_double * 3), ("mu", C.c_double), ("tau", C.c_double),
+                ("relax", C.c_double), ("erp", C.c_double), ("precision", C.c_int32), ("warm_start", C.c_int32),
+                ("colour_seed", C.c_uint64)]
+
+
+class nbgs_stats(C.Structure):
+    _fields_ = [("n_contacts", C.c_int64), ("n_colours", C.c_int32), ("sweeps", C.c_int32),
+                ("residual", C.c_double)]
+
+
+class NbgsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"nbgs status {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+# (name, restype, argtypes) of every entry point declared in include/nbgs.h
+_SIGNATURES = [
+    ("nbgs_abi_version", C.c_int32, []),
+    ("nbgs_last_error", C.c_char_p, []),
+    ("nbgs_scene_create", C.c_int, [C.POINTER(nbgs_bodies), C.POINTER(nbgs_domain), C.POINTER(nbgs_params), _vp,
+                                    C.POINTER(_vp)]),
+    ("nbgs_scene_destroy", C.c_int, [_vp]),
+    ("nbgs_scene_set_params", C.c_int, [_vp, C.POINTER(nbgs_params)]),
+    ("nbgs_detect", C.c_int, [_vp, C.POINTER(nbgs_stats)]),
+    ("nbgs_solve", C.c_int, [_vp, C.c_int32, C.c_double, C.POINTER(nbgs_stats)]),
+    ("nbgs_integrate", C.c_int, [_vp]),
+    ("nbgs_step", C.c_int, [_vp, C.c_int32, C.c_double, C.POINTER(nbgs_stats)]),
+    ("nbgs_get_contacts", C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_int64)]),
+    ("nbgs_get_accumulators", C.c_int, [_vp, _vp, _vp]),
+    ("nbgs_get_residuals", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    ("nbgs_set_warm_start", C.c_int, [_vp, C.c_int64, _vp, _vp]),
+    ("nbgs_get_phase_times", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
+]
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1501_05810_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, allow=()):
+    if status != NBGS_OK and status not in allow:
+        raise NbgsError(status, lib().nbgs_last_error().decode())
+    return status
+
+
+# ---------------------------------------------------------- raw entry points
+
+def nbgs_abi_version() -> int:
+    return int(lib().nbgs_abi_version())
+
+
+def nbgs_last_error() -> str:
+    return lib().nbgs_last_error().decode()
+
+
+def nbgs_scene_create(bodies: nbgs_bodies, domain: nbgs_domain, params: nbgs_params, stream: int = 0) -> int:
+    h = _vp()
+    _check(lib().nbgs_scene_create(C.byref(bodies), C.byref(domain), C.byref(params), _vp(stream), C.byref(h)))
+    return h.value
+
+
+def nbgs_scene_destroy(h: int) -> None:
+    _check(lib().nbgs_scene_destroy(_vp(h)))
+
+
+def nbgs_scene_set_params(h: int, params: nbgs_params) -> None:
+    _check(lib().nbgs_scene_set_params(_vp(h), C.byref(params)))
+
+
+def nbgs_detect(h: int) -> nbgs_stats:
+    st = nbgs_stats()
+    _check(lib().nbgs_detect(_vp(h), C.byref(st)))
+    return st
+
+
+def nbgs_solve(h: int, max_sweeps: int, residual_target: float = 0.0, allow_not_converged: bool = True):
+    st = nbgs_stats()
+    code = _check(lib().nbgs_solve(_vp(h), int(max_sweeps), float(residual_target), C.byref(st)),
+                  allow=(NBGS_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    return st, code
+
+
+def nbgs_integrate(h: int) -> None:
+    _check(lib().nbgs_integrate(_vp(h)))
+
+
+def nbgs_step(h: int, max_sweeps: int, residual_target: float = 0.0, allow_not_converged: bool = True):
+    st = nbgs_stats()
+    code = _check(lib().nbgs_step(_vp(h), int(max_sweeps), float(residual_target), C.byref(st)),
+                  allow=(NBGS_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    return st, code
+
+
+def nbgs_get_contacts(h: int, cap: int, j1=0, j2=0, key=0, colour=0, normal=0, xi=0, impulse=0) -> int:
+    n = C.c_int64()
+    _check(lib().nbgs_get_contacts(_vp(h), int(cap), _vp(j1), _vp(j2), _vp(key), _vp(colour), _vp(normal), _vp(xi),
+                                   _vp(impulse), C.byref(n)))
+    return int(n.value)
+
+
+def nbgs_get_accumulators(h: int, v_ptr: int, w_ptr: int) -> None:
+    _check(lib().nbgs_get_accumulators(_vp(h), _vp(v_ptr), _vp(w_ptr)))
+
+
+def nbgs_get_residuals(h: int, cap: int) -> np.ndarray:
+    buf = (C.c_double * max(1, cap))()
+    n = C.c_int32()
+    _check(lib().nbgs_get_residuals(_vp(h), int(cap), buf, C.byref(n)))
+    return np.array(buf[:min(cap, n.value)], dtype=np.float64)
+
+
+def nbgs_set_warm_start(h: int, n: int, keys_ptr: int, impulse_ptr: int) -> None:
+    _check(lib().nbgs_set_warm_start(_vp(h), int(n), _vp(keys_ptr), _vp(impulse_ptr)))
+
+
+def nbgs_get_phase_times(h: int, n: int = 5) -> np.ndarray:
+    buf = (C.c_double * n)()
+    _check(lib().nbgs_get_phase_times(_vp(h), int(n), buf))
+    return np.array(buf[:], dtype=np.float64)
+
+
+# ------------------------------------------------------------- convenience
+
+PRECISIONS = {"fp64": NBGS_FP64, "fp32": NBGS_FP32_SWEEP}
+WARM = {"zero": NBGS_WS_ZERO, "previous": NBGS_WS_PREVIOUS}
+BODY_FIELDS = ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
+               "radius", "inv_mass", "inv_inertia")
+
+
+def make_params(sc, precision="fp64", warm_start="previous") -> nbgs_params:
+    return nbgs_params(dt=sc.dt, gravity=(C.c_double * 3)(*sc.gravity), mu=sc.mu, tau=sc.tau, relax=sc.relax,
+                       erp=sc.erp, precision=PRECISIONS[precision], warm_start=WARM[warm_start],
+                       colour_seed=sc.colour_seed & 0xFFFFFFFFFFFFFFFF)
+
+
+class GpuScene:
+    """One scene on the GPU: body tensors (float64, SoA) plus the library handle.
+
+    ``sc`` is a :class:`scenegen.Scene` (numpy arrays); its arrays are copied to
+    the device once.  ``state()`` copies the current body state back.
+    """
+
+    def __init__(self, sc, device="cuda", precision="fp64", warm_start="previous", stream=None):
+        import torch
+
+        self.torch = torch
+        self.sc = sc
+        self.device = torch.device(device)
+        self.n = sc.n
+        cols = {"x": sc.pos[:, 0], "y": sc.pos[:, 1], "z": sc.pos[:, 2], "qw": sc.quat[:, 0], "qx": sc.quat[:, 1],
+                "qy": sc.quat[:, 2], "qz": sc.quat[:, 3], "vx": sc.vel[:, 0], "vy": sc.vel[:, 1],
+                "vz": sc.vel[:, 2], "wx": sc.angvel[:, 0], "wy": sc.angvel[:, 1], "wz": sc.angvel[:, 2],
+                "radius": sc.radius, "inv_mass": sc.inv_mass, "inv_inertia": sc.inv_inertia}
+        self.t = {k: torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device=self.device)
+                  for k, v in cols.items()}
+        self._bodies = nbgs_bodies(n=self.n, **{k: self.t[k].data_ptr() for k in BODY_FIELDS})
+        self._planes = (nbgs_plane * max(1, len(sc.planes)))()
+        for i, (pt, nm) in enumerate(sc.planes):
+            self._planes[i].point[:] = list(pt)
+            self._planes[i].normal[:] = list(nm)
+        self._domain = nbgs_domain(lo=(C.c_double * 3)(*sc.lo), hi=(C.c_double * 3)(*sc.hi),
+                                   periodic=(C.c_int32 * 3)(*[int(bool(p)) for p in sc.periodic]),
+                                   n_planes=len(sc.planes), planes=C.cast(self._planes, C.POINTER(nbgs_plane)))
+        self.precision = precision
+        self.warm_start = warm_start
+        self._params = make_params(sc, precision, warm_start)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.handle = nbgs_scene_create(self._bodies, self._domain, self._params, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            nbgs_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, precision=None, warm_start=None, **overrides):
+        if precision is not None:
+            self.precision = precision
+        if warm_start is not None:
+            self.warm_start = warm_start
+        for k, v in overrides.items():
+            setattr(self.sc, k, v)
+        self._params = make_params(self.sc, self.precision, self.warm_start)
+        nbgs_scene_set_params(self.handle, self._params)
+
+    @staticmethod
+    def _stats(st: nbgs_stats) -> Dict:
+        return dict(n_contacts=int(st.n_contacts), n_colours=int(st.n_colours), sweeps=int(st.sweeps),
+                    residual=float(st.residual))
+
+    def detect(self) -> Dict:
+        return self._stats(nbgs_detect(self.handle))
+
+    def solve(self, max_sweeps: int, target: float = 0.0) -> Dict:
+        st, code = nbgs_solve(self.handle, max_sweeps, target)
+        d = self._stats(st)
+        d["converged"] = code == NBGS_OK
+        return d
+
+    def integrate(self):
+        nbgs_integrate(self.handle)
+
+    def step(self, max_sweeps: int, target: float = 0.0) -> Dict:
+        st, code = nbgs_step(self.handle, max_sweeps, target)
+        d = self._stats(st)
+        d["converged"] = code == NBGS_OK
+        return d
+
+    def contacts(self) -> Dict[str, np.ndarray]:
+        torch = self.torch
+        n0 = C.c_int64()
+        lib().nbgs_get_contacts(_vp(self.handle), 0, None, None, None, None, None, None, None, C.byref(n0))
+        m = int(n0.value)
+        cap = max(1, m)
+        dev = self.device
+        j1 = torch.empty(cap, dtype=torch.int32, device=dev)
+        j2 = torch.empty(cap, dtype=torch.int32, device=dev)
+        key = torch.empty(cap, dtype=torch.int64, device=dev)
+        col = torch.empty(cap, dtype=torch.int32, device=dev)
+        nrm = torch.empty(3 * cap, dtype=torch.float64, device=dev)
+        xi = torch.empty(cap, dtype=torch.float64, device=dev)
+        imp = torch.empty(3 * cap, dtype=torch.float64, device=dev)
+        nbgs_get_contacts(self.handle, cap, j1.data_ptr(), j2.data_ptr(), key.data_ptr(), col.data_ptr(),
+                          nrm.data_ptr(), xi.data_ptr(), imp.data_ptr())
+        out = dict(j1=j1[:m].cpu().numpy(), j2=j2[:m].cpu().numpy(), key=key[:m].cpu().numpy().view(np.uint64),
+                   colour=col[:m].cpu().numpy(), xi=xi[:m].cpu().numpy())
+        out["n"] = nrm.view(3, cap)[:, :m].T.cpu().numpy().copy()
+        out["P"] = imp.view(3, cap)[:, :m].T.cpu().numpy().copy()
+        return out
+
+    def accumulators(self):
+        torch = self.torch
+        v = torch.empty(3 * self.n, dtype=torch.float64, device=self.device)
+        w = torch.empty(3 * self.n, dtype=torch.float64, device=self.device)
+        nbgs_get_accumulators(self.handle, v.data_ptr(), w.data_ptr())
+        self.stream.synchronize()
+        return v.view(3, self.n).T.cpu().numpy().copy(), w.view(3, self.n).T.cpu().numpy().copy()
+
+    def residuals(self, cap: int = 100000) -> np.ndarray:
+        return nbgs_get_residuals(self.handle, cap)
+
+    def set_warm_start(self, keys: np.ndarray, P: np.ndarray):
+        torch = self.torch
+        n = int(keys.shape[0])
+        k = torch.tensor(np.ascontiguousarray(keys).view(np.int64), device=self.device)
+        p = torch.tensor(np.ascontiguousarray(P.T), dtype=torch.float64, device=self.device).reshape(-1)
+        nbgs_set_warm_start(self.handle, n, k.data_ptr(), p.data_ptr())
+        self.stream.synchronize()
+
+    def phase_times(self) -> np.ndarray:
+        return nbgs_get_phase_times(self.handle, 5)
+
+    def state(self) -> Dict[str, np.ndarray]:
+        self.stream.synchronize()
+        t = {k: v.cpu().numpy() for k, v in self.t.items()}
+        return dict(pos=np.stack([t["x"], t["y"], t["z"]], 1), quat=np.stack([t["qw"], t["qx"], t["qy"], t["qz"]], 1),
+                    vel=np.stack([t["vx"], t["vy"], t["vz"]], 1), angvel=np.stack([t["wx"], t["wy"], t["wz"]], 1))
+
+    def load_state(self, pos=None, quat=None, vel=None, angvel=None):
+        """Overwrite body state columns from numpy arrays (host -> device)."""
+        torch = self.torch
+        for arr, names in ((pos, ("x", "y", "z")), (quat, ("qw", "qx", "qy", "qz")), (vel, ("vx", "vy", "vz")),
+                           (angvel, ("wx", "wy", "wz"))):
+            if arr is None:
+                continue
+            for k, name in enumerate(names):
+                self.t[name].copy_(torch.from_numpy(np.ascontiguousarray(arr[:, k])))

@@ -1,0 +1,799 @@
+// C ABI and host-side orchestration of one time step (single-process form of
+// Alg. 2: detection, colouring, accumulator init, NBGS sweeps, integration).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+#include <algorithm>
+
+#include "nbgs_internal.h"
+
+namespace nbgs {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+struct ContactBuf {
+    DevBuf<int32_t> j1, j2, colour;
+    DevBuf<uint64_t> key;
+    DevBuf<double> nx, ny, nz, xi, a1, a2, px, py, pz;
+    nbgs_status reserve(size_t n) {
+        NBGS_TRY(j1.reserve(n));
+        NBGS_TRY(j2.reserve(n));
+        NBGS_TRY(colour.reserve(n));
+        NBGS_TRY(key.reserve(n));
+        for (DevBuf<double> *b : {&nx, &ny, &nz, &xi, &a1, &a2, &px, &py, &pz}) NBGS_TRY(b->reserve(n));
+        return NBGS_OK;
+    }
+    ContactsView view() {
+        ContactsView v;
+        v.j1 = j1.p;
+        v.j2 = j2.p;
+        v.key = key.p;
+        v.nx = nx.p;
+        v.ny = ny.p;
+        v.nz = nz.p;
+        v.xi = xi.p;
+        v.a1 = a1.p;
+        v.a2 = a2.p;
+        v.px = px.p;
+        v.py = py.p;
+        v.pz = pz.p;
+        v.colour = colour.p;
+        return v;
+    }
+};
+
+template <class T>
+struct SweepBuf {
+    DevBuf<int32_t> j1, j2, perm;
+    DevBuf<T> nx, ny, nz, bias, a1, a2, px, py, pz;
+    nbgs_status reserve(size_t n) {
+        NBGS_TRY(j1.reserve(n));
+        NBGS_TRY(j2.reserve(n));
+        NBGS_TRY(perm.reserve(n));
+        for (DevBuf<T> *b : {&nx, &ny, &nz, &bias, &a1, &a2, &px, &py, &pz}) NBGS_TRY(b->reserve(n));
+        return NBGS_OK;
+    }
+    SweepView<T> view() {
+        SweepView<T> v;
+        v.j1 = j1.p;
+        v.j2 = j2.p;
+        v.perm = perm.p;
+        v.nx = nx.p;
+        v.ny = ny.p;
+        v.nz = nz.p;
+        v.bias = bias.p;
+        v.a1 = a1.p;
+        v.a2 = a2.p;
+        v.px = px.p;
+        v.py = py.p;
+        v.pz = pz.p;
+        return v;
+    }
+};
+
+enum Phase { kDetect = 0, kColour = 1, kInit = 2, kSweeps = 3, kIntegrate = 4, kNumPhases = 5 };
+
+}  // namespace nbgs
+
+using namespace nbgs;
+
+struct nbgs_scene_s {
+    BodiesView b{};
+    PlaneSet planes{};
+    double lo[3], hi[3];
+    int32_t periodic[3];
+    nbgs_params p{};
+    hipStream_t s = nullptr;
+    Grid grid{};
+
+    // per body
+    DevBuf<double> h;
+    DevBuf<uint32_t> keys, ids, keys2, ids2;
+    DevBuf<double4> sxr;
+    DevBuf<int32_t> cnt, off;
+    DevBuf<int32_t> deg2, off2, cursor;
+    DevBuf<double> vel64;
+    DevBuf<float> vel32;
+    // cells
+    DevBuf<int32_t> cell_start, cell_end;
+    DevBuf<uint32_t> cell_stamp;
+    uint32_t stamp = 0;
+    // scratch
+    DevBuf<int32_t> radix_hist;
+    DevBuf<char> scan_tmp;
+    DevBuf<int32_t> small;  // [0] total, [1] remaining, [2] overflow, [8..12) ctrl, [16..272) colour histogram
+    DevBuf<unsigned long long> maxbits;
+    int32_t *pinned = nullptr;  // host mirror of small
+    // contacts
+    ContactBuf cb[2];
+    int cur = 0;
+    bool table_in_cur = false;
+    int64_t nc = 0, n_prev = 0;
+    DevBuf<int32_t> inc2;
+    DevBuf<uint32_t> ckeys, cids, ckeys2, cids2;
+    SweepBuf<double> sw64;
+    SweepBuf<float> sw32;
+    int32_t n_colours = 0;
+    std::vector<int64_t> col_off;
+    std::vector<int64_t> part_off;
+    int64_t n_partials = 0;
+    DevBuf<double> partials;
+    DevBuf<double> res_hist;
+    int32_t precision_used = NBGS_FP64;
+    int state = 0;  // 0 idle, 1 detected, 2 solved
+    nbgs_stats stats{};
+    hipEvent_t ev[kNumPhases + 1] = {};
+    bool ev_ok[kNumPhases + 1] = {};
+
+    int32_t *total() { return small.p + 0; }
+    int32_t *remaining() { return small.p + 1; }
+    int32_t *overflow() { return small.p + 2; }
+    int32_t *ctrl() { return small.p + 8; }
+    int32_t *chist() { return small.p + 16; }
+};
+
+namespace {
+
+constexpr int kSmallInts = 16 + 256;
+
+nbgs_status check_params(const nbgs_params *p) {
+    if (!p) {
+        set_error("params is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) {
+        set_error("dt must be positive and finite");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (!(p->relax > 0.0 && p->relax <= 1.0)) {
+        set_error("relax must lie in (0, 1]");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (!(p->erp >= 0.0 && p->erp <= 1.0)) {
+        set_error("erp must lie in [0, 1]");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) {
+        set_error("mu must be non-negative");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) {
+        set_error("tau must be non-negative");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (p->precision != NBGS_FP64 && p->precision != NBGS_FP32_SWEEP) {
+        set_error("unknown precision %d", p->precision);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (p->warm_start != NBGS_WS_ZERO && p->warm_start != NBGS_WS_PREVIOUS) {
+        set_error("unknown warm start mode %d", p->warm_start);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->gravity[a])) {
+            set_error("gravity must be finite");
+            return NBGS_ERR_INVALID_ARG;
+        }
+    return NBGS_OK;
+}
+
+void record(nbgs_scene_t sc, int i) {
+    if (sc->ev[i]) sc->ev_ok[i] = hipEventRecord(sc->ev[i], sc->s) == hipSuccess;
+}
+
+int bits_for(int64_t n) {
+    int b = 0;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+// Cell grid for the largest hull diameter 2 max(r + h).
+nbgs_status make_grid(nbgs_scene_t sc, double max_reach) {
+    Grid &g = sc->grid;
+    const double cell = 2.0 * max_reach * (1.0 + 1e-9);
+    int64_t dims[3];
+    double edge[3];
+    for (int a = 0; a < 3; ++a) {
+        const double L = sc->hi[a] - sc->lo[a];
+        g.lo[a] = sc->lo[a];
+        g.hi[a] = sc->hi[a];
+        g.L[a] = L;
+        g.periodic[a] = sc->periodic[a];
+        double c = std::floor(L / cell);
+        if (!(c >= 1.0)) c = 1.0;
+        if (c > 1.0e6) c = 1.0e6;
+        if (sc->periodic[a] && c < 3.0) c = 1.0;  // one cell: every partner is tested by minimum image
+        dims[a] = (int64_t)c;
+        edge[a] = sc->periodic[a] ? L / c : cell;
+    }
+    // keep the table within a few cells per body
+    const int64_t cap = std::max<int64_t>(8 * (int64_t)sc->b.n, 1 << 16);
+    while (dims[0] * dims[1] * dims[2] > cap) {
+        for (int a = 0; a < 3; ++a) {
+            if (dims[a] <= 1) continue;
+            int64_t c = std::max<int64_t>(1, dims[a] / 2);
+            if (sc->periodic[a] && c < 3) c = 1;
+            dims[a] = c;
+            edge[a] = sc->periodic[a] ? g.L[a] / (double)c : edge[a] * 2.0;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        g.dims[a] = (int32_t)dims[a];
+        g.edge[a] = edge[a];
+    }
+    g.ncells = (int32_t)(dims[0] * dims[1] * dims[2]);
+    g.key_bits = bits_for(g.ncells);
+    return NBGS_OK;
+}
+
+template <class T>
+SweepBuf<T> &sweep_buf(nbgs_scene_t sc);
+template <>
+SweepBuf<double> &sweep_buf<double>(nbgs_scene_t sc) {
+    return sc->sw64;
+}
+template <>
+SweepBuf<float> &sweep_buf<float>(nbgs_scene_t sc) {
+    return sc->sw32;
+}
+template <class T>
+DevBuf<T> &vel_buf(nbgs_scene_t sc);
+template <>
+DevBuf<double> &vel_buf<double>(nbgs_scene_t sc) {
+    return sc->vel64;
+}
+template <>
+DevBuf<float> &vel_buf<float>(nbgs_scene_t sc) {
+    return sc->vel32;
+}
+
+nbgs_status sync_small(nbgs_scene_t sc, int first, int count) {
+    NBGS_HIP(hipMemcpyAsync(sc->pinned + first, sc->small.p + first, sizeof(int32_t) * count, hipMemcpyDeviceToHost,
+                            sc->s));
+    NBGS_HIP(hipStreamSynchronize(sc->s));
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status gather_for_sweeps(nbgs_scene_t sc, const uint32_t *perm) {
+    SweepBuf<T> &sw = sweep_buf<T>(sc);
+    NBGS_TRY(sw.reserve((size_t)sc->nc));
+    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), perm, sc->nc, sc->p.dt, sc->p.erp, sw.view(), sc->s);
+}
+
+nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    record(sc, kDetect);
+    if (sc->table_in_cur) {  // the solved impulses of the last step become the lookup table
+        sc->cur = 1 - sc->cur;
+        sc->table_in_cur = false;
+    }
+    ContactBuf &prev = sc->cb[1 - sc->cur];
+    // hull radii and the largest hull
+    NBGS_HIP(hipMemsetAsync(sc->maxbits.p, 0, sizeof(unsigned long long), s));
+    NBGS_TRY(launch_hull(sc->b, sc->p.dt, sc->p.tau, sc->h.p, sc->maxbits.p, s));
+    unsigned long long bits = 0;
+    NBGS_HIP(hipMemcpyAsync(sc->pinned, sc->maxbits.p, sizeof(bits), hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipStreamSynchronize(s));
+    std::memcpy(&bits, sc->pinned, sizeof(bits));
+    double max_reach;
+    std::memcpy(&max_reach, &bits, sizeof(max_reach));
+    if (!std::isfinite(max_reach)) {
+        set_error("non-finite velocity or radius in the body state");
+        return NBGS_ERR_NUMERIC;
+    }
+    NBGS_TRY(make_grid(sc, max_reach));
+    // cell list
+    NBGS_TRY(launch_cell_keys(sc->b, sc->grid, sc->keys.p, sc->ids.p, s));
+    bool alt = false;
+    NBGS_TRY(radix_sort_pairs(sc->keys.p, sc->ids.p, sc->keys2.p, sc->ids2.p, N, sc->grid.key_bits,
+                              sc->radix_hist.p, sc->scan_tmp.p, sc->scan_tmp.cap, &alt, s));
+    const uint32_t *skeys = alt ? sc->keys2.p : sc->keys.p;
+    const uint32_t *sids = alt ? sc->ids2.p : sc->ids.p;
+    if ((size_t)sc->grid.ncells > sc->cell_stamp.cap) {
+        NBGS_TRY(sc->cell_start.reserve(sc->grid.ncells));
+        NBGS_TRY(sc->cell_end.reserve(sc->grid.ncells));
+        NBGS_TRY(sc->cell_stamp.reserve(sc->grid.ncells));
+        NBGS_HIP(hipMemsetAsync(sc->cell_stamp.p, 0, sizeof(uint32_t) * sc->cell_stamp.cap, s));
+        sc->stamp = 0;
+    }
+    if (++sc->stamp == 0) {  // wrapped: clear the table once
+        NBGS_HIP(hipMemsetAsync(sc->cell_stamp.p, 0, sizeof(uint32_t) * sc->cell_stamp.cap, s));
+        sc->stamp = 1;
+    }
+    NBGS_TRY(launch_cells(sc->b, sc->grid, skeys, sids, sc->h.p, sc->cell_start.p, sc->cell_end.p,
+                          sc->cell_stamp.p, sc->stamp, sc->sxr.p, s));
+    // count, scan, emit
+    NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
+                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p, s));
+    NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, N, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
+    NBGS_TRY(sync_small(sc, 0, 1));
+    const int64_t nc = sc->pinned[0];
+    if (nc < 0 || nc > (int64_t)0x7fffff00) {
+        set_error("contact count out of range");
+        return NBGS_ERR_CAPACITY;
+    }
+    sc->nc = nc;
+    ContactBuf &cb = sc->cb[sc->cur];
+    NBGS_TRY(cb.reserve((size_t)nc));
+    NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
+                              sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->off.p, cb.view(), s));
+    // initial impulses
+    if (sc->p.warm_start == NBGS_WS_PREVIOUS && sc->n_prev > 0)
+        NBGS_TRY(launch_warm_match(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, sc->n_prev, sc->p.mu,
+                                   s));
+    else
+        NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
+    record(sc, kColour);
+    // colouring: body -> contacts where it is j2 (as j1 it owns the segment off[i] .. off[i] + cnt[i])
+    NBGS_TRY(sc->inc2.reserve((size_t)(nc > 0 ? nc : 1)));
+    NBGS_TRY(launch_j2_degree(cb.view(), nc, N, sc->b.inv_mass, sc->deg2.p, s));
+    NBGS_TRY(exclusive_scan_i32(sc->deg2.p, sc->off2.p, (int64_t)N + 1, nullptr, sc->scan_tmp.p, sc->scan_tmp.cap, s));
+    NBGS_HIP(hipMemcpyAsync(sc->cursor.p, sc->off2.p, sizeof(int32_t) * ((size_t)N + 1), hipMemcpyDeviceToDevice, s));
+    NBGS_TRY(launch_j2_fill(cb.view(), nc, N, sc->b.inv_mass, sc->cursor.p, sc->inc2.p, s));
+    if (nc > 0) {
+        NBGS_HIP(hipMemsetAsync(cb.colour.p, 0xff, sizeof(int32_t) * nc, s));
+        sc->pinned[1] = (int32_t)nc;
+        sc->pinned[2] = 0;
+        NBGS_HIP(hipMemcpyAsync(sc->remaining(), sc->pinned + 1, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        int batch = 2, rounds = 0;
+        for (;;) {
+            for (int r = 0; r < batch; ++r)
+                NBGS_TRY(launch_jp_round(cb.view(), nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p, sc->off2.p,
+                                         sc->inc2.p, sc->p.colour_seed, sc->remaining(), sc->overflow(), s));
+            rounds += batch;
+            NBGS_TRY(sync_small(sc, 1, 2));
+            if (sc->pinned[2]) {
+                set_error("more than 255 colours needed");
+                return NBGS_ERR_CAPACITY;
+            }
+            if (sc->pinned[1] == 0) break;
+            if (rounds > 100000) {
+                set_error("colouring did not finish");
+                return NBGS_ERR_DEVICE;
+            }
+            batch = batch < 8 ? batch * 2 : 8;
+        }
+    }
+    // colour-major order: stable sort of (colour, canonical index)
+    NBGS_TRY(launch_colour_hist(cb.view(), nc, sc->chist(), s));
+    NBGS_TRY(sync_small(sc, 16, 256));
+    sc->n_colours = 0;
+    for (int c = 0; c < 256; ++c)
+        if (sc->pinned[16 + c]) sc->n_colours = c + 1;
+    sc->col_off.assign((size_t)sc->n_colours + 1, 0);
+    for (int c = 0; c < sc->n_colours; ++c) sc->col_off[c + 1] = sc->col_off[c] + sc->pinned[16 + c];
+    sc->part_off.assign((size_t)sc->n_colours + 1, 0);
+    for (int c = 0; c < sc->n_colours; ++c) {
+        const int64_t m = sc->col_off[c + 1] - sc->col_off[c];
+        sc->part_off[c + 1] = sc->part_off[c] + (m + kSweepBlock - 1) / kSweepBlock;
+    }
+    sc->n_partials = sc->part_off[sc->n_colours];
+    NBGS_TRY(sc->partials.reserve(2 * (size_t)(sc->n_partials > 0 ? sc->n_partials : 1)));
+    NBGS_TRY(sc->ckeys.reserve((size_t)nc + 1));
+    NBGS_TRY(sc->cids.reserve((size_t)nc + 1));
+    NBGS_TRY(sc->ckeys2.reserve((size_t)nc + 1));
+    NBGS_TRY(sc->cids2.reserve((size_t)nc + 1));
+    NBGS_TRY(launch_colour_keys(cb.view(), nc, sc->ckeys.p, sc->cids.p, s));
+    if ((size_t)radix_hist_entries(nc) > sc->radix_hist.cap) NBGS_TRY(sc->radix_hist.reserve(radix_hist_entries(nc)));
+    const size_t need_tmp = exclusive_scan_tmp_bytes((int64_t)radix_hist_entries(nc));
+    if (need_tmp > sc->scan_tmp.cap) NBGS_TRY(sc->scan_tmp.reserve(need_tmp));
+    bool calt = false;
+    NBGS_TRY(radix_sort_pairs(sc->ckeys.p, sc->cids.p, sc->ckeys2.p, sc->cids2.p, nc, 8, sc->radix_hist.p,
+                              sc->scan_tmp.p, sc->scan_tmp.cap, &calt, s));
+    const uint32_t *perm = calt ? sc->cids2.p : sc->cids.p;
+    if (nc == 1) perm = sc->cids.p;
+    if (sc->p.precision == NBGS_FP32_SWEEP) NBGS_TRY(gather_for_sweeps<float>(sc, perm));
+    else NBGS_TRY(gather_for_sweeps<double>(sc, perm));
+    sc->precision_used = sc->p.precision;
+    sc->state = 1;
+    sc->stats.n_contacts = nc;
+    sc->stats.n_colours = sc->n_colours;
+    sc->stats.sweeps = 0;
+    sc->stats.residual = 0.0;
+    record(sc, kInit);
+    if (stats) *stats = sc->stats;
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    SweepBuf<T> &sw = sweep_buf<T>(sc);
+    DevBuf<T> &vel = vel_buf<T>(sc);
+    NBGS_TRY(vel.reserve(8 * (size_t)N));
+    NBGS_TRY(sc->res_hist.reserve((size_t)max_sweeps));
+    record(sc, kInit);
+    NBGS_TRY(launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel.p, s));
+    if (sc->p.warm_start != NBGS_WS_ZERO)
+        for (int c = 0; c < sc->n_colours; ++c)
+            NBGS_TRY(launch_warm_scatter<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, s));
+    record(sc, kSweeps);
+    NBGS_HIP(hipMemsetAsync(sc->ctrl(), 0, 4 * sizeof(int32_t), s));
+    SweepParams sp{sc->p.mu, sc->p.relax};
+    int32_t launched = 0, chunk = target > 0.0 ? 4 : max_sweeps;
+    bool done = false;
+    while (launched < max_sweeps && !done) {
+        const int32_t k = std::min(chunk, max_sweeps - launched);
+        for (int32_t it = 0; it < k; ++it) {
+            for (int c = 0; c < sc->n_colours; ++c)
+                NBGS_TRY(launch_sweep_colour<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, sp,
+                                                sc->partials.p + 2 * sc->part_off[c], sc->ctrl(), s));
+            NBGS_TRY(launch_residual(sc->partials.p, (int32_t)sc->n_partials, target, sc->ctrl(), sc->res_hist.p, s));
+        }
+        launched += k;
+        if (target > 0.0 && launched < max_sweeps) {
+            NBGS_TRY(sync_small(sc, 8, 3));
+            done = sc->pinned[8] != 0;
+            chunk = std::min(chunk * 2, 64);
+        }
+    }
+    NBGS_TRY(launch_save_impulses<T>(sw.view(), sc->nc, sc->cb[sc->cur].view(), s));
+    record(sc, kIntegrate);
+    sc->state = 2;
+    if (stats || target > 0.0) {
+        NBGS_TRY(sync_small(sc, 8, 3));
+        const int32_t sweeps = sc->pinned[8 + 1];
+        double R = 0.0;
+        if (sweeps > 0) {
+            NBGS_HIP(hipMemcpyAsync(sc->pinned + 32, sc->res_hist.p + (sweeps - 1), sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+            NBGS_HIP(hipStreamSynchronize(s));
+            std::memcpy(&R, sc->pinned + 32, sizeof(double));
+        }
+        sc->stats.sweeps = sweeps;
+        sc->stats.residual = R;
+        if (stats) *stats = sc->stats;
+        if (sc->pinned[8 + 2]) {
+            set_error("non-finite residual after sweep %d", sweeps);
+            return NBGS_ERR_NUMERIC;
+        }
+        if (target > 0.0 && !(R <= target)) {
+            set_error("residual %.3e above target %.3e after %d sweeps", R, target, sweeps);
+            return NBGS_ERR_NOT_CONVERGED;
+        }
+    } else {
+        sc->stats.sweeps = max_sweeps;
+    }
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status integrate_impl(nbgs_scene_t sc) {
+    record(sc, kIntegrate);
+    NBGS_TRY(launch_integrate<T>(sc->b, sc->grid, sc->p.dt, vel_buf<T>(sc).p, sc->s));
+    record(sc, kNumPhases);
+    sc->table_in_cur = true;
+    sc->n_prev = sc->nc;
+    sc->state = 0;
+    return NBGS_OK;
+}
+
+}  // namespace
+
+namespace nbgs {
+const char *last_error_cstr();
+}
+
+#define NBGS_GUARD(sc)                                                                                          \
+    do {                                                                                                        \
+        if (!(sc)) {                                                                                            \
+            set_error("scene handle is NULL");                                                                  \
+            return NBGS_ERR_INVALID_ARG;                                                                        \
+        }                                                                                                       \
+    } while (0)
+
+extern "C" {
+
+int32_t nbgs_abi_version(void) { return NBGS_ABI_VERSION; }
+
+const char *nbgs_last_error(void) { return nbgs::last_error_cstr(); }
+
+nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *domain, const nbgs_params *params,
+                              void *hip_stream, nbgs_scene_t *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!bodies || !domain) {
+        set_error("bodies or domain is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    NBGS_TRY(check_params(params));
+    if (bodies->n < 1 || bodies->n >= (int64_t)0x7fffffc0) {
+        set_error("body count %lld out of range", (long long)bodies->n);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    const void *ptrs[] = {bodies->x,  bodies->y,  bodies->z,  bodies->qw, bodies->qx, bodies->qy,
+                          bodies->qz, bodies->vx, bodies->vy, bodies->vz, bodies->wx, bodies->wy,
+                          bodies->wz, bodies->radius, bodies->inv_mass, bodies->inv_inertia};
+    for (const void *q : ptrs)
+        if (!q) {
+            set_error("a body array pointer is NULL");
+            return NBGS_ERR_INVALID_ARG;
+        }
+    if (domain->n_planes < 0 || domain->n_planes > PlaneSet::kMax || (domain->n_planes > 0 && !domain->planes)) {
+        set_error("n_planes must lie in [0, %d] with a plane array", PlaneSet::kMax);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!(domain->hi[a] > domain->lo[a]) || !std::isfinite(domain->hi[a] - domain->lo[a])) {
+            set_error("domain box must have hi > lo on every axis");
+            return NBGS_ERR_INVALID_ARG;
+        }
+    for (int w = 0; w < domain->n_planes; ++w) {
+        const double *nm = domain->planes[w].normal;
+        const double len = std::sqrt(nm[0] * nm[0] + nm[1] * nm[1] + nm[2] * nm[2]);
+        if (!(std::fabs(len - 1.0) < 1e-12)) {
+            set_error("plane %d normal is not unit length", w);
+            return NBGS_ERR_INVALID_ARG;
+        }
+    }
+    nbgs_scene_t sc = new (std::nothrow) nbgs_scene_s();
+    if (!sc) {
+        set_error("host allocation failed");
+        return NBGS_ERR_OUT_OF_MEMORY;
+    }
+    sc->s = (hipStream_t)hip_stream;
+    BodiesView &b = sc->b;
+    b.n = (int32_t)bodies->n;
+    b.x = bodies->x;
+    b.y = bodies->y;
+    b.z = bodies->z;
+    b.qw = bodies->qw;
+    b.qx = bodies->qx;
+    b.qy = bodies->qy;
+    b.qz = bodies->qz;
+    b.vx = bodies->vx;
+    b.vy = bodies->vy;
+    b.vz = bodies->vz;
+    b.wx = bodies->wx;
+    b.wy = bodies->wy;
+    b.wz = bodies->wz;
+    b.radius = bodies->radius;
+    b.inv_mass = bodies->inv_mass;
+    b.inv_inertia = bodies->inv_inertia;
+    sc->planes.n = domain->n_planes;
+    for (int w = 0; w < domain->n_planes; ++w)
+        for (int a = 0; a < 3; ++a) {
+            sc->planes.p[w][a] = domain->planes[w].point[a];
+            sc->planes.nrm[w][a] = domain->planes[w].normal[a];
+        }
+    for (int a = 0; a < 3; ++a) {
+        sc->lo[a] = domain->lo[a];
+        sc->hi[a] = domain->hi[a];
+        sc->periodic[a] = domain->periodic[a] ? 1 : 0;
+    }
+    sc->p = *params;
+    const size_t N = (size_t)b.n;
+    nbgs_status st = NBGS_OK;
+    auto chk = [&](nbgs_status x) {
+        if (st == NBGS_OK) st = x;
+    };
+    chk(sc->h.reserve(N, 1.0));
+    chk(sc->keys.reserve(N, 1.0));
+    chk(sc->ids.reserve(N, 1.0));
+    chk(sc->keys2.reserve(N, 1.0));
+    chk(sc->ids2.reserve(N, 1.0));
+    chk(sc->sxr.reserve(N, 1.0));
+    chk(sc->cnt.reserve(N + 1, 1.0));
+    chk(sc->off.reserve(N + 1, 1.0));
+    chk(sc->deg2.reserve(N + 1, 1.0));
+    chk(sc->off2.reserve(N + 1, 1.0));
+    chk(sc->cursor.reserve(N + 1, 1.0));
+    chk(sc->radix_hist.reserve(radix_hist_entries((int64_t)N + 1), 1.0));
+    chk(sc->scan_tmp.reserve(exclusive_scan_tmp_bytes((int64_t)radix_hist_entries((int64_t)N + 1) + N + 1), 1.0));
+    chk(sc->small.reserve(kSmallInts, 1.0));
+    chk(sc->maxbits.reserve(1, 1.0));
+    if (st == NBGS_OK && hipHostMalloc((void **)&sc->pinned, sizeof(int32_t) * kSmallInts * 2) != hipSuccess) {
+        set_error("pinned host allocation failed");
+        st = NBGS_ERR_OUT_OF_MEMORY;
+    }
+    for (int i = 0; i <= kNumPhases && st == NBGS_OK; ++i)
+        if (hipEventCreate(&sc->ev[i]) != hipSuccess) sc->ev[i] = nullptr;
+    if (st == NBGS_OK) {
+        // static bodies must not rotate either (walls and fixed spheres have infinite inertia)
+        std::vector<double> im(N), ii(N);
+        if (hipMemcpy(im.data(), b.inv_mass, N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(ii.data(), b.inv_inertia, N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            set_error("could not read inv_mass / inv_inertia (not device pointers?)");
+            st = NBGS_ERR_INVALID_ARG;
+        } else {
+            for (size_t i = 0; i < N; ++i)
+                if (!(im[i] >= 0.0) || !(ii[i] >= 0.0) || (im[i] == 0.0 && ii[i] != 0.0)) {
+                    set_error("body %zu: inverse mass/inertia must be >= 0 and a static body (1/m = 0) needs 1/I = 0",
+                              i);
+                    st = NBGS_ERR_INVALID_ARG;
+                    break;
+                }
+        }
+    }
+    if (st != NBGS_OK) {
+        nbgs_scene_destroy(sc);
+        return st;
+    }
+    *out = sc;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_scene_destroy(nbgs_scene_t sc) {
+    if (!sc) return NBGS_OK;
+    (void)hipStreamSynchronize(sc->s);
+    for (int i = 0; i <= kNumPhases; ++i)
+        if (sc->ev[i]) (void)hipEventDestroy(sc->ev[i]);
+    if (sc->pinned) (void)hipHostFree(sc->pinned);
+    delete sc;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_scene_set_params(nbgs_scene_t sc, const nbgs_params *params) {
+    NBGS_GUARD(sc);
+    NBGS_TRY(check_params(params));
+    sc->p = *params;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_detect(nbgs_scene_t sc, nbgs_stats *stats) {
+    NBGS_GUARD(sc);
+    sc->state = 0;
+    return detect_impl(sc, stats);
+}
+
+nbgs_status nbgs_solve(nbgs_scene_t sc, int32_t max_sweeps, double residual_target, nbgs_stats *stats) {
+    NBGS_GUARD(sc);
+    if (sc->state < 1) {
+        set_error("nbgs_solve needs a preceding nbgs_detect");
+        return NBGS_ERR_STATE;
+    }
+    if (max_sweeps < 1) {
+        set_error("max_sweeps must be >= 1");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (sc->precision_used == NBGS_FP32_SWEEP) return solve_impl<float>(sc, max_sweeps, residual_target, stats);
+    return solve_impl<double>(sc, max_sweeps, residual_target, stats);
+}
+
+nbgs_status nbgs_integrate(nbgs_scene_t sc) {
+    NBGS_GUARD(sc);
+    if (sc->state != 2) {
+        set_error("nbgs_integrate needs a preceding nbgs_solve");
+        return NBGS_ERR_STATE;
+    }
+    if (sc->precision_used == NBGS_FP32_SWEEP) return integrate_impl<float>(sc);
+    return integrate_impl<double>(sc);
+}
+
+nbgs_status nbgs_step(nbgs_scene_t sc, int32_t max_sweeps, double residual_target, nbgs_stats *stats) {
+    NBGS_GUARD(sc);
+    NBGS_TRY(nbgs_detect(sc, nullptr));
+    nbgs_status st = nbgs_solve(sc, max_sweeps, residual_target, stats);
+    if (st != NBGS_OK && st != NBGS_ERR_NOT_CONVERGED) return st;
+    NBGS_TRY(nbgs_integrate(sc));
+    return st;
+}
+
+nbgs_status nbgs_get_contacts(nbgs_scene_t sc, int64_t cap, int32_t *j1, int32_t *j2, uint64_t *key,
+                              int32_t *colour, double *normal, double *xi, double *impulse, int64_t *n_out) {
+    NBGS_GUARD(sc);
+    if (n_out) *n_out = sc->nc;
+    if (sc->nc > cap) {
+        set_error("%lld contacts do not fit into %lld", (long long)sc->nc, (long long)cap);
+        return NBGS_ERR_CAPACITY;
+    }
+    const int64_t m = sc->nc;
+    if (m == 0) return NBGS_OK;
+    ContactBuf &cb = sc->cb[sc->table_in_cur ? sc->cur : sc->cur];
+    hipStream_t s = sc->s;
+    auto cp = [&](void *dst, const void *src, size_t bytes) -> nbgs_status {
+        if (!dst) return NBGS_OK;
+        NBGS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+        return NBGS_OK;
+    };
+    NBGS_TRY(cp(j1, cb.j1.p, m * sizeof(int32_t)));
+    NBGS_TRY(cp(j2, cb.j2.p, m * sizeof(int32_t)));
+    NBGS_TRY(cp(key, cb.key.p, m * sizeof(uint64_t)));
+    NBGS_TRY(cp(colour, cb.colour.p, m * sizeof(int32_t)));
+    NBGS_TRY(cp(xi, cb.xi.p, m * sizeof(double)));
+    if (normal) {
+        NBGS_TRY(cp(normal, cb.nx.p, m * sizeof(double)));
+        NBGS_TRY(cp(normal + cap, cb.ny.p, m * sizeof(double)));
+        NBGS_TRY(cp(normal + 2 * cap, cb.nz.p, m * sizeof(double)));
+    }
+    if (impulse) {
+        NBGS_TRY(cp(impulse, cb.px.p, m * sizeof(double)));
+        NBGS_TRY(cp(impulse + cap, cb.py.p, m * sizeof(double)));
+        NBGS_TRY(cp(impulse + 2 * cap, cb.pz.p, m * sizeof(double)));
+    }
+    NBGS_HIP(hipStreamSynchronize(s));
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_accumulators(nbgs_scene_t sc, double *v, double *w) {
+    NBGS_GUARD(sc);
+    if (!v || !w) {
+        set_error("v and w must be device buffers of 3 n doubles");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (sc->precision_used == NBGS_FP32_SWEEP) {
+        if (!sc->vel32.p) {
+            set_error("no solve yet");
+            return NBGS_ERR_STATE;
+        }
+        return launch_export_accumulators<float>(sc->vel32.p, sc->b.n, v, w, sc->s);
+    }
+    if (!sc->vel64.p) {
+        set_error("no solve yet");
+        return NBGS_ERR_STATE;
+    }
+    return launch_export_accumulators<double>(sc->vel64.p, sc->b.n, v, w, sc->s);
+}
+
+nbgs_status nbgs_get_residuals(nbgs_scene_t sc, int32_t cap, double *hist, int32_t *n_out) {
+    NBGS_GUARD(sc);
+    NBGS_HIP(hipStreamSynchronize(sc->s));
+    int32_t ctrl[4] = {0, 0, 0, 0};
+    if (sc->small.p) NBGS_HIP(hipMemcpy(ctrl, sc->ctrl(), sizeof(ctrl), hipMemcpyDeviceToHost));
+    const int32_t n = ctrl[1];
+    if (n_out) *n_out = n;
+    const int32_t k = std::min(cap, n);
+    if (k > 0 && hist) NBGS_HIP(hipMemcpy(hist, sc->res_hist.p, sizeof(double) * k, hipMemcpyDeviceToHost));
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_set_warm_start(nbgs_scene_t sc, int64_t n, const uint64_t *keys, const double *impulse) {
+    NBGS_GUARD(sc);
+    if (n < 0 || (n > 0 && (!keys || !impulse))) {
+        set_error("bad warm-start table");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (sc->table_in_cur) {
+        sc->cur = 1 - sc->cur;
+        sc->table_in_cur = false;
+    }
+    ContactBuf &prev = sc->cb[1 - sc->cur];
+    NBGS_TRY(prev.reserve((size_t)(n > 0 ? n : 1)));
+    if (n > 0) {
+        NBGS_HIP(hipMemcpyAsync(prev.key.p, keys, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, sc->s));
+        NBGS_HIP(hipMemcpyAsync(prev.px.p, impulse, n * sizeof(double), hipMemcpyDeviceToDevice, sc->s));
+        NBGS_HIP(hipMemcpyAsync(prev.py.p, impulse + n, n * sizeof(double), hipMemcpyDeviceToDevice, sc->s));
+        NBGS_HIP(hipMemcpyAsync(prev.pz.p, impulse + 2 * n, n * sizeof(double), hipMemcpyDeviceToDevice, sc->s));
+    }
+    sc->n_prev = n;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_phase_times(nbgs_scene_t sc, int32_t n, double *out) {
+    NBGS_GUARD(sc);
+    if (!out || n < 0 || n > kNumPhases) {
+        set_error("out must hold up to %d values", kNumPhases);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    NBGS_HIP(hipStreamSynchronize(sc->s));
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.0f;
+        if (sc->ev_ok[i] && sc->ev_ok[i + 1] && hipEventElapsedTime(&ms, sc->ev[i], sc->ev[i + 1]) == hipSuccess)
+            out[i] = ms;
+        else
+            out[i] = 0.0;
+    }
+    return NBGS_OK;
+}
+
+}  // extern "C"

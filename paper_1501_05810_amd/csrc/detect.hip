@@ -1,0 +1,365 @@
+// Contact detection on a uniform cell grid (Sect. 4 of the paper).
+//
+// Broad phase: every body's intersection hull S_i + ball(h_i), with
+// h_i = dt (|v_i| + |w_i| r_i) + tau (eq. (expansionradius)), lies in the cell
+// of its centre, and the cell edge is at least the largest hull diameter, so
+// partners of a body are found in the 27 surrounding cells.  Bodies are radix
+// sorted by cell key; a stamp-validated table gives each occupied cell its
+// range of sorted positions (no per-step clearing of the table).
+//
+// Narrow phase: eq. (contactpos) has a closed form for spheres (contact point
+// on the surface of j2, normal from j2 to j1) and for wall planes.
+//
+// Output order: body i's contacts with partners k > i, ascending k, then its
+// wall contacts; bodies in ascending index.  That is ascending pair key, the
+// canonical order, built by count -> exclusive scan -> emit, so it does not
+// depend on thread scheduling.
+//
+// The hull test and the geometry are evaluated with the same operations in
+// the same order as the plain definition (compiled without contraction), so
+// the contact set is bit-exact, not merely close.
+#include "nbgs_internal.h"
+
+namespace nbgs {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
+
+__global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double tau, double *h,
+                                                 unsigned long long *max_bits) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double rh = 0.0;
+    if (i < b.n) {
+        const double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
+        const double wx = b.wx[i], wy = b.wy[i], wz = b.wz[i];
+        const double r = b.radius[i];
+        const double speed = sqrt(vx * vx + vy * vy + vz * vz);
+        const double spin = sqrt(wx * wx + wy * wy + wz * wz);
+        const double hi = dt * (speed + spin * r) + tau;
+        h[i] = hi;
+        rh = r + hi;
+        if (!(rh == rh)) rh = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf: caught on the host
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rh = fmax(rh, __shfl_xor(rh, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(max_bits, (unsigned long long)__double_as_longlong(rh));
+}
+
+__device__ inline int cell_coord(double x, double lo, double edge, int dims) {
+    double c = floor((x - lo) / edge);
+    c = fmax(0.0, fmin(c, (double)(dims - 1)));  // NaN -> 0
+    return (int)c;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_keys(BodiesView b, Grid g, uint32_t *keys, uint32_t *ids) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= b.n) return;
+    const int cx = cell_coord(b.x[i], g.lo[0], g.edge[0], g.dims[0]);
+    const int cy = cell_coord(b.y[i], g.lo[1], g.edge[1], g.dims[1]);
+    const int cz = cell_coord(b.z[i], g.lo[2], g.edge[2], g.dims[2]);
+    keys[i] = (uint32_t)((cz * g.dims[1] + cy) * g.dims[0] + cx);
+    ids[i] = (uint32_t)i;
+}
+
+// Cell ranges from the sorted keys, and a sorted copy of (centre, +-(r + h))
+// for coalesced neighbour reads; the sign marks static bodies.
+__global__ void __launch_bounds__(kBlock) k_cells(BodiesView b, int32_t n, const uint32_t *skeys,
+                                                  const uint32_t *sids, const double *h, int32_t *cell_start,
+                                                  int32_t *cell_end, uint32_t *cell_stamp, uint32_t stamp,
+                                                  double4 *sxr) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t key = skeys[p];
+    if (p == 0 || skeys[p - 1] != key) {
+        cell_start[key] = p;
+        cell_stamp[key] = stamp;
+    }
+    if (p == n - 1 || skeys[p + 1] != key) cell_end[key] = p + 1;
+    const int i = (int)sids[p];
+    const double rh = b.radius[i] + h[i];
+    sxr[p] = make_double4(b.x[i], b.y[i], b.z[i], b.inv_mass[i] == 0.0 ? -rh : rh);
+}
+
+__device__ inline double min_image(double d, int periodic, double L) {
+    if (!periodic) return d;
+    if (d > 0.5 * L) return d - L;
+    if (d < -0.5 * L) return d + L;
+    return d;
+}
+
+struct NeighbourRange {
+    int lo[3], hi[3];
+};
+
+__device__ inline NeighbourRange neighbour_range(uint32_t key, const Grid &g, int c[3]) {
+    c[0] = (int)(key % (uint32_t)g.dims[0]);
+    const uint32_t t = key / (uint32_t)g.dims[0];
+    c[1] = (int)(t % (uint32_t)g.dims[1]);
+    c[2] = (int)(t / (uint32_t)g.dims[1]);
+    NeighbourRange r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (g.dims[a] == 1) {
+            r.lo[a] = 0;
+            r.hi[a] = 0;
+        } else {
+            r.lo[a] = -1;
+            r.hi[a] = 1;
+        }
+    }
+    return r;
+}
+
+// Linear index of neighbour cell c + d, or -1 outside a non-periodic axis.
+__device__ inline int neighbour_cell(const Grid &g, const int c[3], int dx, int dy, int dz) {
+    int q[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (q[a] < 0 || q[a] >= g.dims[a]) {
+            if (!g.periodic[a]) return -1;
+            q[a] = q[a] < 0 ? q[a] + g.dims[a] : q[a] - g.dims[a];
+        }
+    }
+    return (q[2] * g.dims[1] + q[1]) * g.dims[0] + q[0];
+}
+
+// Hull overlap of sorted entries (own, other): |x_i - x_k|^2 <= ((r_i + h_i) + (r_k + h_k))^2.
+__device__ inline bool hull_hit(const double4 &a, const double4 &o, const Grid &g) {
+    const double dx = min_image(a.x - o.x, g.periodic[0], g.L[0]);
+    const double dy = min_image(a.y - o.y, g.periodic[1], g.L[1]);
+    const double dz = min_image(a.z - o.z, g.periodic[2], g.L[2]);
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double reach = fabs(a.w) + fabs(o.w);
+    return d2 <= reach * reach;
+}
+
+__device__ inline bool plane_hit(const PlaneSet &pl, int w, double x, double y, double z, double r, double h,
+                                 double tau, double *gap_out) {
+    const double s = pl.nrm[w][0] * (x - pl.p[w][0]) + pl.nrm[w][1] * (y - pl.p[w][1]) + pl.nrm[w][2] * (z - pl.p[w][2]);
+    const double gap = s - r;
+    *gap_out = gap;
+    return gap <= h + tau;
+}
+
+template <bool kEmit>
+__device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const uint32_t *sids, const double4 *sxr,
+                                     const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                                     uint32_t stamp, int p, int i, int32_t *out_k) {
+    const double4 me = sxr[p];
+    int c[3];
+    const NeighbourRange nr = neighbour_range(skeys[p], g, c);
+    int m = 0;
+    for (int dz = nr.lo[2]; dz <= nr.hi[2]; ++dz)
+        for (int dy = nr.lo[1]; dy <= nr.hi[1]; ++dy)
+            for (int dx = nr.lo[0]; dx <= nr.hi[0]; ++dx) {
+                const int cell = neighbour_cell(g, c, dx, dy, dz);
+                if (cell < 0 || cell_stamp[cell] != stamp) continue;
+                const int q1 = cell_end[cell];
+                for (int q = cell_start[cell]; q < q1; ++q) {
+                    const int k = (int)sids[q];
+                    if (k <= i) continue;
+                    const double4 o = sxr[q];
+                    if (me.w < 0.0 && o.w < 0.0) continue;  // two static bodies
+                    if (!hull_hit(me, o, g)) continue;
+                    if (kEmit) out_k[m] = k;
+                    ++m;
+                }
+            }
+    return m;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g, PlaneSet pl, double tau,
+                                                       const uint32_t *skeys, const uint32_t *sids,
+                                                       const double4 *sxr, const double *h,
+                                                       const int32_t *cell_start, const int32_t *cell_end,
+                                                       const uint32_t *cell_stamp, uint32_t stamp, int32_t *cnt) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= b.n) return;
+    const int i = (int)sids[p];
+    int m = visit_partners<false>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, nullptr);
+    if (b.inv_mass[i] != 0.0) {
+        const double4 me = sxr[p];
+        const double r = b.radius[i], hi = h[i];
+        double gap;
+        for (int w = 0; w < pl.n; ++w)
+            if (plane_hit(pl, w, me.x, me.y, me.z, r, hi, tau, &gap)) ++m;
+    }
+    cnt[i] = m;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g, PlaneSet pl, double tau,
+                                                      const uint32_t *skeys, const uint32_t *sids,
+                                                      const double4 *sxr, const double *h,
+                                                      const int32_t *cell_start, const int32_t *cell_end,
+                                                      const uint32_t *cell_stamp, uint32_t stamp, const int32_t *off,
+                                                      ContactsView c) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= b.n) return;
+    const int i = (int)sids[p];
+    const int base = off[i];
+    int32_t *ks = c.j2 + base;
+    const int m = visit_partners<true>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, ks);
+    // partners in ascending index (insertion sort of a short list)
+    for (int a = 1; a < m; ++a) {
+        const int v = ks[a];
+        int t = a - 1;
+        while (t >= 0 && ks[t] > v) {
+            ks[t + 1] = ks[t];
+            --t;
+        }
+        ks[t + 1] = v;
+    }
+    const double xi_ = b.x[i], yi = b.y[i], zi = b.z[i], ri = b.radius[i];
+    for (int t = 0; t < m; ++t) {
+        const int k = ks[t];
+        const int j = base + t;
+        const double dx = min_image(xi_ - b.x[k], g.periodic[0], g.L[0]);
+        const double dy = min_image(yi - b.y[k], g.periodic[1], g.L[1]);
+        const double dz = min_image(zi - b.z[k], g.periodic[2], g.L[2]);
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const double d = sqrt(d2);
+        double nx, ny, nz;
+        if (d2 > 0.0) {
+            nx = dx / d;
+            ny = dy / d;
+            nz = dz / d;
+        } else {
+            nx = 0.0;
+            ny = 0.0;
+            nz = 1.0;
+        }
+        const double rk = b.radius[k];
+        const double xi = (d - ri) - rk;
+        c.j1[j] = i;
+        c.key[j] = ((uint64_t)(uint32_t)i << 32) | (uint64_t)(uint32_t)k;
+        c.nx[j] = nx;
+        c.ny[j] = ny;
+        c.nz[j] = nz;
+        c.xi[j] = xi;
+        c.a1[j] = ri + xi;
+        c.a2[j] = rk;
+    }
+    if (b.inv_mass[i] != 0.0) {
+        int t = m;
+        const double hi = h[i];
+        double gap;
+        for (int w = 0; w < pl.n; ++w) {
+            if (!plane_hit(pl, w, xi_, yi, zi, ri, hi, tau, &gap)) continue;
+            const int j = base + t++;
+            const int k = b.n + w;
+            c.j1[j] = i;
+            c.j2[j] = k;
+            c.key[j] = ((uint64_t)(uint32_t)i << 32) | (uint64_t)(uint32_t)k;
+            c.nx[j] = pl.nrm[w][0];
+            c.ny[j] = pl.nrm[w][1];
+            c.nz[j] = pl.nrm[w][2];
+            c.xi[j] = gap;
+            c.a1[j] = ri + gap;
+            c.a2[j] = 0.0;
+        }
+    }
+}
+
+// Previous-step impulse of the same pair, re-projected onto the new cone:
+// P_n = max(0, n.P), tangential part clipped to mu P_n.
+__global__ void __launch_bounds__(kBlock) k_warm_match(ContactsView c, int64_t nc, const uint64_t *prev_key,
+                                                       const double *prev_px, const double *prev_py,
+                                                       const double *prev_pz, int64_t n_prev, double mu) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    const uint64_t key = c.key[j];
+    int64_t lo = 0, hi = n_prev;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (prev_key[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    double P0 = 0.0, P1 = 0.0, P2 = 0.0;
+    if (lo < n_prev && prev_key[lo] == key) {
+        const double n0 = c.nx[j], n1 = c.ny[j], n2 = c.nz[j];
+        const double q0 = prev_px[lo], q1 = prev_py[lo], q2 = prev_pz[lo];
+        double pn = n0 * q0 + n1 * q1 + n2 * q2;
+        double t0 = q0 - pn * n0, t1 = q1 - pn * n1, t2 = q2 - pn * n2;
+        if (pn < 0.0) pn = 0.0;
+        const double tl = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+        const double lim = mu * pn;
+        if (tl > lim) {
+            const double s = tl > 0.0 ? lim / tl : 0.0;
+            t0 = t0 * s;
+            t1 = t1 * s;
+            t2 = t2 * s;
+        }
+        P0 = pn * n0 + t0;
+        P1 = pn * n1 + t1;
+        P2 = pn * n2 + t2;
+    }
+    c.px[j] = P0;
+    c.py[j] = P1;
+    c.pz[j] = P2;
+}
+
+}  // namespace
+
+nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
+                        hipStream_t s) {
+    k_hull<<<grid_for(b.n), kBlock, 0, s>>>(b, dt, tau, h, max_bits);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, uint32_t *keys, uint32_t *ids, hipStream_t s) {
+    k_cell_keys<<<grid_for(b.n), kBlock, 0, s>>>(b, g, keys, ids);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
+                         const double *h, int32_t *cell_start, int32_t *cell_end, uint32_t *cell_stamp,
+                         uint32_t stamp, double4 *sxr, hipStream_t s) {
+    (void)g;
+    k_cells<<<grid_for(b.n), kBlock, 0, s>>>(b, b.n, skeys, sids, h, cell_start, cell_end, cell_stamp, stamp, sxr);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, double tau,
+                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
+                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                              uint32_t stamp, int32_t *cnt, hipStream_t s) {
+    k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, tau, skeys, sids, sxr, h, cell_start, cell_end,
+                                                  cell_stamp, stamp, cnt);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, double tau,
+                             const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
+                             const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                             uint32_t stamp, const int32_t *off, ContactsView c, hipStream_t s) {
+    k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, tau, skeys, sids, sxr, h, cell_start, cell_end,
+                                                 cell_stamp, stamp, off, c);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_warm_match(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
+                              const double *prev_py, const double *prev_pz, int64_t n_prev, double mu,
+                              hipStream_t s) {
+    if (nc == 0) return NBGS_OK;
+    k_warm_match<<<grid_for(nc), kBlock, 0, s>>>(c, nc, prev_key, prev_px, prev_py, prev_pz, n_prev, mu);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_zero_impulses(ContactsView c, int64_t nc, hipStream_t s) {
+    if (nc == 0) return NBGS_OK;
+    NBGS_HIP(hipMemsetAsync(c.px, 0, sizeof(double) * nc, s));
+    NBGS_HIP(hipMemsetAsync(c.py, 0, sizeof(double) * nc, s));
+    NBGS_HIP(hipMemsetAsync(c.pz, 0, sizeof(double) * nc, s));
+    return NBGS_OK;
+}
+
+}  // namespace nbgs

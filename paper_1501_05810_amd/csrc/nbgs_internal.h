@@ -1,0 +1,173 @@
+// Internal declarations of the gfx950 hard-contact solver library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nbgs.h"
+
+namespace nbgs {
+
+// ----------------------------------------------------------------- errors
+
+void set_error(const char *fmt, ...);
+
+#define NBGS_HIP(call)                                                                                          \
+    do {                                                                                                        \
+        hipError_t e_ = (call);                                                                                 \
+        if (e_ != hipSuccess) {                                                                                 \
+            ::nbgs::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__);       \
+            return NBGS_ERR_DEVICE;                                                                             \
+        }                                                                                                       \
+    } while (0)
+
+#define NBGS_TRY(expr)                                                                                          \
+    do {                                                                                                        \
+        nbgs_status s_ = (expr);                                                                                \
+        if (s_ != NBGS_OK) return s_;                                                                           \
+    } while (0)
+
+// A device allocation that only grows.  Contents are not preserved on growth.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    nbgs_status reserve(size_t n, double slack = 1.25) {
+        if (n <= cap && p) return NBGS_OK;
+        release();
+        size_t want = n < 16 ? 16 : (size_t)((double)n * slack) + 16;
+        hipError_t e = hipMalloc((void **)&p, want * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            set_error("hipMalloc of %zu bytes failed: %s", want * sizeof(T), hipGetErrorString(e));
+            return NBGS_ERR_OUT_OF_MEMORY;
+        }
+        cap = want;
+        return NBGS_OK;
+    }
+};
+
+// ------------------------------------------------------------ device views
+
+struct BodiesView {  // borrowed caller arrays
+    int32_t n;
+    double *x, *y, *z, *qw, *qx, *qy, *qz, *vx, *vy, *vz, *wx, *wy, *wz;
+    const double *radius, *inv_mass, *inv_inertia;
+};
+
+struct PlaneSet {  // walls, passed by value to kernels
+    static constexpr int kMax = 16;
+    int32_t n;
+    double p[kMax][3];
+    double nrm[kMax][3];
+};
+
+struct Grid {
+    double lo[3];
+    double hi[3];
+    double edge[3];
+    int32_t dims[3];
+    int32_t periodic[3];
+    double L[3];
+    int32_t ncells;
+    int32_t key_bits;
+};
+
+// Canonical (key-ordered) contact list, structure of arrays.
+struct ContactsView {
+    int32_t *j1, *j2;
+    uint64_t *key;
+    double *nx, *ny, *nz, *xi, *a1, *a2;
+    double *px, *py, *pz;  // initial / solved impulse (world frame)
+    int32_t *colour;
+};
+
+// Sweep-ordered (colour-major) per-contact record.
+template <class T>
+struct SweepView {
+    int32_t *j1, *j2;
+    int32_t *perm;  // sweep position -> canonical index
+    T *nx, *ny, *nz, *bias, *a1, *a2, *px, *py, *pz;
+};
+
+// ------------------------------------------------------- kernel launchers
+
+// scan.hip / sort.hip
+nbgs_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev, void *tmp,
+                               size_t tmp_bytes, hipStream_t s);
+size_t exclusive_scan_tmp_bytes(int64_t n);
+nbgs_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, int64_t n,
+                             int32_t key_bits, int32_t *hist_tmp, void *scan_tmp, size_t scan_tmp_bytes,
+                             bool *result_in_alt, hipStream_t s);
+size_t radix_hist_entries(int64_t n);
+
+// detect.hip
+nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
+                        hipStream_t s);
+nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, uint32_t *keys, uint32_t *ids, hipStream_t s);
+nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
+                         const double *h, int32_t *cell_start, int32_t *cell_end, uint32_t *cell_stamp,
+                         uint32_t stamp, double4 *sxr, hipStream_t s);
+nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, double tau,
+                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
+                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                              uint32_t stamp, int32_t *cnt, hipStream_t s);
+nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, double tau,
+                             const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
+                             const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                             uint32_t stamp, const int32_t *off, ContactsView c, hipStream_t s);
+nbgs_status launch_warm_match(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
+                              const double *prev_py, const double *prev_pz, int64_t n_prev, double mu,
+                              hipStream_t s);
+nbgs_status launch_zero_impulses(ContactsView c, int64_t nc, hipStream_t s);
+
+// colour.hip
+nbgs_status launch_j2_degree(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *deg2,
+                             hipStream_t s);
+nbgs_status launch_j2_fill(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *cursor,
+                           int32_t *inc2, hipStream_t s);
+nbgs_status launch_jp_round(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass,
+                            const int32_t *off1, const int32_t *cnt1, const int32_t *off2, const int32_t *inc2,
+                            uint64_t seed, int32_t *remaining, int32_t *overflow, hipStream_t s);
+nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t *hist, hipStream_t s);
+nbgs_status launch_colour_keys(const ContactsView &c, int64_t nc, uint32_t *keys, uint32_t *ids, hipStream_t s);
+template <class T>
+nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, int64_t nc, double dt, double erp,
+                                SweepView<T> sv, hipStream_t s);
+
+// sweep.hip
+struct SweepParams {
+    double mu, relax;
+};
+template <class T>
+nbgs_status launch_init_bodies(const BodiesView &b, const double g[3], double dt, T *vel, hipStream_t s);
+template <class T>
+nbgs_status launch_warm_scatter(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, hipStream_t s);
+template <class T>
+nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, SweepParams sp,
+                                double *partials, const int32_t *ctrl, hipStream_t s);
+nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl,
+                            double *hist, hipStream_t s);
+template <class T>
+nbgs_status launch_integrate(const BodiesView &b, const Grid &g, double dt, const T *vel, hipStream_t s);
+template <class T>
+nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hipStream_t s);
+template <class T>
+nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, hipStream_t s);
+
+constexpr int kSweepBlock = 256;
+
+}  // namespace nbgs

@@ -1,0 +1,403 @@
+// Nonlinear block Gauss-Seidel sweeps, accumulator init and integration.
+//
+// Velocity accumulators (Sect. 6.3, velocity form): each body holds v', w' of
+// the current iterate in one 8-element record {v'x, v'y, v'z, w'x, w'y, w'z,
+// 1/m, 1/I} -- 64 B in FP64, 32 B in FP32 -- so a contact gathers a body with
+// one aligned 64 B (or 32 B) access.  Contacts are stored colour-major as a
+// structure of arrays; one thread relaxes one contact.  Within a colour no
+// two contacts share a dynamic body, so the read-modify-write of the two body
+// records needs no atomics, and the per-body update order across colours is
+// the colour order: the sweep is the sequential Gauss-Seidel in (colour, key)
+// order, bit for bit.
+//
+// Relaxing contact j (Alg. 1, eqs. (nonpenetration) and (coulomb)):
+//   du   = v'1 - v'2 - (a1 w'1 + a2 w'2) x n      relative contact velocity
+//   u_n  = xi'/dt + n.du,  u_t = du - (n.du) n
+//   W    = diag(w_n, w_t, w_t),  w_n = 1/m1 + 1/m2,  w_t = w_n + a1^2/I1 + a2^2/I2
+//   b    = u - W P_j                               own impulse taken out
+//   P*_n = max(0, -b_n / w_n);  P*_t = -b_t / w_t, scaled onto |P*_t| <= mu P*_n
+//   P_j <- omega P* + (1 - omega) P_j; apply the change to both bodies.
+#include "nbgs_internal.h"
+
+namespace nbgs {
+
+namespace {
+
+constexpr int kBlock = kSweepBlock;
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <class T>
+struct Rec {
+    T v[3], w[3], im, ii;
+};
+
+__device__ inline Rec<double> load_rec(const double *vel, int b) {
+    const double2 *p = reinterpret_cast<const double2 *>(vel + 8 * (int64_t)b);
+    const double2 a = p[0], c = p[1], d = p[2], e = p[3];
+    Rec<double> r;
+    r.v[0] = a.x;
+    r.v[1] = a.y;
+    r.v[2] = c.x;
+    r.w[0] = c.y;
+    r.w[1] = d.x;
+    r.w[2] = d.y;
+    r.im = e.x;
+    r.ii = e.y;
+    return r;
+}
+
+__device__ inline Rec<float> load_rec(const float *vel, int b) {
+    const float4 *p = reinterpret_cast<const float4 *>(vel + 8 * (int64_t)b);
+    const float4 a = p[0], c = p[1];
+    Rec<float> r;
+    r.v[0] = a.x;
+    r.v[1] = a.y;
+    r.v[2] = a.z;
+    r.w[0] = a.w;
+    r.w[1] = c.x;
+    r.w[2] = c.y;
+    r.im = c.z;
+    r.ii = c.w;
+    return r;
+}
+
+// Store v', w' (the constants stay).
+__device__ inline void store_vel(double *vel, int b, const Rec<double> &r) {
+    double2 *p = reinterpret_cast<double2 *>(vel + 8 * (int64_t)b);
+    p[0] = make_double2(r.v[0], r.v[1]);
+    p[1] = make_double2(r.v[2], r.w[0]);
+    p[2] = make_double2(r.w[1], r.w[2]);
+}
+
+__device__ inline void store_vel(float *vel, int b, const Rec<float> &r) {
+    float4 *p = reinterpret_cast<float4 *>(vel + 8 * (int64_t)b);
+    p[0] = make_float4(r.v[0], r.v[1], r.v[2], r.w[0]);
+    float2 *q = reinterpret_cast<float2 *>(vel + 8 * (int64_t)b + 4);
+    q[0] = make_float2(r.w[1], r.w[2]);
+}
+
+template <class T>
+__device__ inline Rec<T> zero_rec() {
+    Rec<T> r;
+    r.v[0] = r.v[1] = r.v[2] = T(0);
+    r.w[0] = r.w[1] = r.w[2] = T(0);
+    r.im = r.ii = T(0);
+    return r;
+}
+
+// Impulse change dP at the contact point: +dP on body 1 (arm -a1 n),
+// -dP on body 2 (arm +a2 n), eq. (wrench).
+template <class T>
+__device__ inline void apply(Rec<T> &r1, Rec<T> &r2, const T n[3], T a1, T a2, const T dP[3]) {
+    const T m0 = n[1] * dP[2] - n[2] * dP[1];
+    const T m1 = n[2] * dP[0] - n[0] * dP[2];
+    const T m2 = n[0] * dP[1] - n[1] * dP[0];
+    r1.v[0] = r1.v[0] + r1.im * dP[0];
+    r1.v[1] = r1.v[1] + r1.im * dP[1];
+    r1.v[2] = r1.v[2] + r1.im * dP[2];
+    r1.w[0] = r1.w[0] - r1.ii * a1 * m0;
+    r1.w[1] = r1.w[1] - r1.ii * a1 * m1;
+    r1.w[2] = r1.w[2] - r1.ii * a1 * m2;
+    r2.v[0] = r2.v[0] - r2.im * dP[0];
+    r2.v[1] = r2.v[1] - r2.im * dP[1];
+    r2.v[2] = r2.v[2] - r2.im * dP[2];
+    r2.w[0] = r2.w[0] - r2.ii * a2 * m0;
+    r2.w[1] = r2.w[1] - r2.ii * a2 * m1;
+    r2.w[2] = r2.w[2] - r2.ii * a2 * m2;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_init_bodies(BodiesView b, double gx, double gy, double gz, double dt,
+                                                        T *vel) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= b.n) return;
+    const double im = b.inv_mass[i];
+    const bool dyn = im > 0.0;
+    T *r = vel + 8 * (int64_t)i;
+    r[0] = (T)(dyn ? b.vx[i] + dt * gx : b.vx[i]);
+    r[1] = (T)(dyn ? b.vy[i] + dt * gy : b.vy[i]);
+    r[2] = (T)(dyn ? b.vz[i] + dt * gz : b.vz[i]);
+    r[3] = (T)b.wx[i];
+    r[4] = (T)b.wy[i];
+    r[5] = (T)b.wz[i];
+    r[6] = (T)im;
+    r[7] = (T)b.inv_inertia[i];
+}
+
+// Initial impulses applied in colour order (one launch per colour), so every
+// body receives them in the same order as in the sweeps.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_warm_scatter(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb,
+                                                         T *vel) {
+    const int64_t p = begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= end) return;
+    const T P[3] = {sv.px[p], sv.py[p], sv.pz[p]};
+    if (P[0] == T(0) && P[1] == T(0) && P[2] == T(0)) return;
+    const int b1 = sv.j1[p], b2 = sv.j2[p];
+    const T n[3] = {sv.nx[p], sv.ny[p], sv.nz[p]};
+    Rec<T> r1 = load_rec(vel, b1);
+    Rec<T> r2 = b2 < nb ? load_rec(vel, b2) : zero_rec<T>();
+    apply(r1, r2, n, sv.a1[p], sv.a2[p], P);
+    if (r1.im > T(0)) store_vel(vel, b1, r1);
+    if (b2 < nb && r2.im > T(0)) store_vel(vel, b2, r2);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One colour of one sweep.  partials receives (sum |dP|^2, sum |P|^2) of this
+// block; ctrl[0] != 0 means an earlier sweep already met the residual target.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_sweep(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel,
+                                                  T mu, T relax, double *partials, const int32_t *ctrl) {
+    if (ctrl[0]) return;
+    const int64_t p = begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double sd = 0.0, sp = 0.0;
+    if (p < end) {
+        const int b1 = sv.j1[p], b2 = sv.j2[p];
+        const T n[3] = {sv.nx[p], sv.ny[p], sv.nz[p]};
+        const T bias = sv.bias[p], a1 = sv.a1[p], a2 = sv.a2[p];
+        const T P[3] = {sv.px[p], sv.py[p], sv.pz[p]};
+        Rec<T> r1 = load_rec(vel, b1);
+        Rec<T> r2 = b2 < nb ? load_rec(vel, b2) : zero_rec<T>();
+        // relative velocity at the contact point
+        const T s0 = a1 * r1.w[0] + a2 * r2.w[0];
+        const T s1 = a1 * r1.w[1] + a2 * r2.w[1];
+        const T s2 = a1 * r1.w[2] + a2 * r2.w[2];
+        T du[3];
+        du[0] = (r1.v[0] - r2.v[0]) - (s1 * n[2] - s2 * n[1]);
+        du[1] = (r1.v[1] - r2.v[1]) - (s2 * n[0] - s0 * n[2]);
+        du[2] = (r1.v[2] - r2.v[2]) - (s0 * n[1] - s1 * n[0]);
+        const T dun = n[0] * du[0] + n[1] * du[1] + n[2] * du[2];
+        const T un = bias + dun;
+        const T ut[3] = {du[0] - dun * n[0], du[1] - dun * n[1], du[2] - dun * n[2]};
+        // own impulse in the contact frame
+        const T Pn = n[0] * P[0] + n[1] * P[1] + n[2] * P[2];
+        const T Pt[3] = {P[0] - Pn * n[0], P[1] - Pn * n[1], P[2] - Pn * n[2]};
+        const T wn = r1.im + r2.im;
+        const T wt = wn + r1.ii * a1 * a1 + r2.ii * a2 * a2;
+        const T bn = un - wn * Pn;
+        const T bt[3] = {ut[0] - wt * Pt[0], ut[1] - wt * Pt[1], ut[2] - wt * Pt[2]};
+        // one-contact solve: normal clamp, radial projection onto the cone
+        T pn = -bn / wn;
+        if (!(pn > T(0))) pn = T(0);
+        T t0 = -bt[0] / wt, t1 = -bt[1] / wt, t2 = -bt[2] / wt;
+        const T tl = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+        const T lim = mu * pn;
+        if (tl > lim) {
+            const T sc = lim / tl;
+            t0 = t0 * sc;
+            t1 = t1 * sc;
+            t2 = t2 * sc;
+        }
+        const T Ps[3] = {pn * n[0] + t0, pn * n[1] + t1, pn * n[2] + t2};
+        T Pnew[3], dP[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Pnew[a] = relax * Ps[a] + (T(1) - relax) * P[a];
+            dP[a] = Pnew[a] - P[a];
+        }
+        apply(r1, r2, n, a1, a2, dP);
+        if (r1.im > T(0)) store_vel(vel, b1, r1);
+        if (b2 < nb && r2.im > T(0)) store_vel(vel, b2, r2);
+        sv.px[p] = Pnew[0];
+        sv.py[p] = Pnew[1];
+        sv.pz[p] = Pnew[2];
+        const double d0 = dP[0], d1 = dP[1], d2 = dP[2];
+        const double q0 = Pnew[0], q1 = Pnew[1], q2 = Pnew[2];
+        sd = d0 * d0 + d1 * d1 + d2 * d2;
+        sp = q0 * q0 + q1 * q1 + q2 * q2;
+    }
+    __shared__ double red[2][kBlock / 64];
+    sd = wave_sum(sd);
+    sp = wave_sum(sp);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wave] = sd;
+        red[1][wave] = sp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, c = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            a += red[0][w];
+            c += red[1][w];
+        }
+        partials[2 * blockIdx.x + 0] = a;
+        partials[2 * blockIdx.x + 1] = c;
+    }
+}
+
+// R_k = sqrt(sum |dP|^2) / max(sqrt(sum |P|^2), 1e-300), summed in a fixed
+// order.  ctrl = {done, sweeps completed, numeric error}.
+__global__ void __launch_bounds__(kBlock) k_residual(const double *partials, int32_t n_partials, double target,
+                                                     int32_t *ctrl, double *hist) {
+    if (ctrl[0]) return;
+    double a = 0.0, c = 0.0;
+    for (int q = threadIdx.x; q < n_partials; q += kBlock) {
+        a += partials[2 * q + 0];
+        c += partials[2 * q + 1];
+    }
+    __shared__ double red[2][kBlock];
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = c;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double den = sqrt(red[1][0]);
+        const double R = sqrt(red[0][0]) / (den > 1e-300 ? den : 1e-300);
+        const int k = ctrl[1];
+        hist[k] = R;
+        ctrl[1] = k + 1;
+        if (!(R == R) || R > 1.0e300) {
+            ctrl[2] = 1;
+            ctrl[0] = 1;
+        } else if (target > 0.0 && R <= target) {
+            ctrl[0] = 1;
+        }
+    }
+}
+
+// eq. (integrationscheme) with quaternion renormalisation; periodic wrap.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g, double dt, const T *vel) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= b.n) return;
+    const T *r = vel + 8 * (int64_t)i;
+    const double vx = (double)r[0], vy = (double)r[1], vz = (double)r[2];
+    const double ox = (double)r[3], oy = (double)r[4], oz = (double)r[5];
+    b.vx[i] = vx;
+    b.vy[i] = vy;
+    b.vz[i] = vz;
+    b.wx[i] = ox;
+    b.wy[i] = oy;
+    b.wz[i] = oz;
+    double pos[3] = {b.x[i] + dt * vx, b.y[i] + dt * vy, b.z[i] + dt * vz};
+    double qw = b.qw[i], qx = b.qx[i], qy = b.qy[i], qz = b.qz[i];
+    const double dw = 0.5 * (-qx * ox - qy * oy - qz * oz);
+    const double dx = 0.5 * (qw * ox + qz * oy - qy * oz);
+    const double dy = 0.5 * (-qz * ox + qw * oy + qx * oz);
+    const double dz = 0.5 * (qy * ox - qx * oy + qw * oz);
+    qw = qw + dt * dw;
+    qx = qx + dt * dx;
+    qy = qy + dt * dy;
+    qz = qz + dt * dz;
+    const double len = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    b.qw[i] = qw / len;
+    b.qx[i] = qx / len;
+    b.qy[i] = qy / len;
+    b.qz[i] = qz / len;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!g.periodic[a]) continue;
+        if (pos[a] >= g.hi[a]) pos[a] = pos[a] - g.L[a];
+        else if (pos[a] < g.lo[a]) pos[a] = pos[a] + g.L[a];
+    }
+    b.x[i] = pos[0];
+    b.y[i] = pos[1];
+    b.z[i] = pos[2];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nc) return;
+    const int j = sv.perm[p];
+    c.px[j] = (double)sv.px[p];
+    c.py[j] = (double)sv.py[p];
+    c.pz[j] = (double)sv.pz[p];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_export(const T *vel, int32_t nb, double *v, double *w) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nb) return;
+    const T *r = vel + 8 * (int64_t)i;
+    v[i] = (double)r[0];
+    v[nb + i] = (double)r[1];
+    v[2 * (int64_t)nb + i] = (double)r[2];
+    w[i] = (double)r[3];
+    w[nb + i] = (double)r[4];
+    w[2 * (int64_t)nb + i] = (double)r[5];
+}
+
+}  // namespace
+
+template <class T>
+nbgs_status launch_init_bodies(const BodiesView &b, const double g[3], double dt, T *vel, hipStream_t s) {
+    k_init_bodies<T><<<grid_for(b.n), kBlock, 0, s>>>(b, g[0], g[1], g[2], dt, vel);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status launch_warm_scatter(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, hipStream_t s) {
+    if (end <= begin) return NBGS_OK;
+    k_warm_scatter<T><<<grid_for(end - begin), kBlock, 0, s>>>(sv, begin, end, nb, vel);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, SweepParams sp,
+                                double *partials, const int32_t *ctrl, hipStream_t s) {
+    if (end <= begin) return NBGS_OK;
+    k_sweep<T><<<grid_for(end - begin), kBlock, 0, s>>>(sv, begin, end, nb, vel, (T)sp.mu, (T)sp.relax, partials,
+                                                        ctrl);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl, double *hist,
+                            hipStream_t s) {
+    k_residual<<<1, kBlock, 0, s>>>(partials, n_partials, target, ctrl, hist);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status launch_integrate(const BodiesView &b, const Grid &g, double dt, const T *vel, hipStream_t s) {
+    k_integrate<T><<<grid_for(b.n), kBlock, 0, s>>>(b, g, dt, vel);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hipStream_t s) {
+    if (nc == 0) return NBGS_OK;
+    k_save_impulses<T><<<grid_for(nc), kBlock, 0, s>>>(sv, nc, c);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, hipStream_t s) {
+    k_export<T><<<grid_for(nb), kBlock, 0, s>>>(vel, nb, v, w);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+#define NBGS_INSTANTIATE(T)                                                                                       \
+    template nbgs_status launch_init_bodies<T>(const BodiesView &, const double[3], double, T *, hipStream_t);    \
+    template nbgs_status launch_warm_scatter<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, hipStream_t);      \
+    template nbgs_status launch_sweep_colour<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, SweepParams,       \
+                                                double *, const int32_t *, hipStream_t);                          \
+    template nbgs_status launch_integrate<T>(const BodiesView &, const Grid &, double, const T *, hipStream_t);   \
+    template nbgs_status launch_save_impulses<T>(SweepView<T>, int64_t, ContactsView, hipStream_t);              \
+    template nbgs_status launch_export_accumulators<T>(const T *, int32_t, double *, double *, hipStream_t);
+
+NBGS_INSTANTIATE(double)
+NBGS_INSTANTIATE(float)
+
+}  // namespace nbgs
