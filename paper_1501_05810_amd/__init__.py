@@ -91,6 +91,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1501_05810_amd.build`")
+        # Load torch first: its HIP runtime then satisfies the library's
+        # libamdhip64.so.7 dependency (same soname), so the process holds one
+        # HIP runtime and the library works on torch's allocations and streams.
+        import torch  # noqa: F401
+
         L = C.CDLL(LIB_PATH)
         for name, res, args in _SIGNATURES:
             fn = getattr(L, name)
