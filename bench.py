@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-time-step hard-contact solve on one MI355X.
+
+Workload: dense settled packing of 1,000,000 polydisperse spheres (radii
+U[0.45, 0.55], density 1), laterally periodic 100 x 100 box on a floor plane,
+solid fraction about 0.6, mu = 0.5, dt = 1e-4, gravity -9.81 z, previous-step
+warm start.  A step is one full pass of the hot path: contact detection (hull
+radii, cell list, pair search, narrow phase), colouring and colour-major
+ordering, accumulator init, 50 NBGS sweeps, integration.
+
+Printed JSON line (one, rank 0):
+  value         contact updates per second over the timed steps (FP64 sweeps,
+                50 sweeps/step, whole-step wall time, inputs resident in HBM);
+  roofline      the NBGS sweep kernel: compulsory bytes per launch over its
+                average launch time (HIP event pair per launch, live);
+  cpu_baseline  the oracle (sequential FP64 C) on one host core, one step of a
+                bounded sample of the same packing.
+Further fields: steps/s to residual 1e-6 (FP64 and FP32 sweeps), sweeps used,
+phase times, contact statistics.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sample_tiles: int, sweeps: int):
+    """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres)."""
+    import oracle
+    import scenegen as sg
+
+    sc = sg.dense_packing(tiles=sample_tiles)
+    w = oracle.World(sc)
+    t0 = time.perf_counter()
+    w.step(sweeps, grid=True, warm=False)
+    t1 = time.perf_counter()
+    v = w.view()
+    upd = v["n_contacts"] * sweeps
+    return dict(value=upd / (t1 - t0), unit="contact updates/s", cores=1, kind="oracle",
+                sample=f"1 step ({sweeps} FP64 sweeps, detection, colouring, integration) of a "
+                       f"{sample_tiles}x{sample_tiles}-tile cut of the packing: {sc.n} spheres, "
+                       f"{v['n_contacts']} contacts, {t1 - t0:.1f} s on one host core",
+                seconds=t1 - t0)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sweeps", type=int, default=50)
+    ap.add_argument("--tiles", type=int, default=10, help="tiles per side of the packing (10 -> 1,000,000 spheres)")
+    ap.add_argument("--residual-steps", type=int, default=3, help="steps timed in the to-residual mode (0: skip)")
+    ap.add_argument("--target", type=float, default=1e-6)
+    ap.add_argument("--max-sweeps", type=int, default=2000)
+    ap.add_argument("--cpu-tiles", type=int, default=3, help="sample for the oracle timing (0: skip)")
+    ap.add_argument("--no-profile", action="store_true", help="time the steps without per-launch events")
+    a = ap.parse_args()
+
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not part of this "
+              f"build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1501_05810_amd as nb
+    import scenegen as sg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sc = sg.dense_packing(tiles=a.tiles)
+    log(f"scene: {sc.n} spheres, box {sc.hi}")
+    g = nb.GpuScene(sc.copy(), device=dev, precision="fp64", warm_start="previous")
+
+    # ---------------------------------------------------- fixed sweeps, FP64
+    for i in range(a.warmup):
+        st = g.step(a.sweeps)
+        log(f"warmup {i}: {st}")
+    g.set_profiling(not a.no_profile)
+    torch.cuda.synchronize()
+    contacts = []
+    colours = []
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        nb.nbgs_detect(g.handle)
+        st, _ = nb.nbgs_solve(g.handle, a.sweeps, 0.0)
+        nb.nbgs_integrate(g.handle)
+        contacts.append(int(st.n_contacts))
+        colours.append(int(st.n_colours))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile()
+    phases = g.phase_times()
+    g.set_profiling(False)
+    wall = t1 - t0
+    updates = float(np.sum(contacts)) * a.sweeps
+    value = updates / wall
+    log(f"timed: {a.steps} steps in {wall:.3f} s, {value:.3e} contact updates/s, phases(ms) {phases}")
+
+    roof = None
+    if prof["sweep_launches"] > 0 and prof["sweep_kernel_ms"] > 0:
+        per_launch_bytes = prof["sweep_bytes"] / prof["sweep_launches"]
+        per_launch_ms = prof["sweep_kernel_ms"] / prof["sweep_launches"]
+        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sweep<double>", "bytes_per_launch": round(per_launch_bytes),
+                "avg_launch_us": round(per_launch_ms * 1e3, 2), "launches": prof["sweep_launches"],
+                "sweep_only_updates_per_s": prof["contact_updates"] / (prof["sweep_kernel_ms"] * 1e-3)}
+
+    # ------------------------------------------------ to residual 1e-6 modes
+    resid = {}
+    if a.residual_steps > 0:
+        for prec in ("fp64", "fp32"):
+            gr = nb.GpuScene(sc.copy(), device=dev, precision=prec, warm_start="previous")
+            gr.step(a.sweeps)  # warm-start table from one fixed-sweep step
+            torch.cuda.synchronize()
+            sweeps_used = []
+            conv = []
+            r0 = time.perf_counter()
+            for i in range(a.residual_steps):
+                st = gr.step(a.max_sweeps, a.target)
+                sweeps_used.append(st["sweeps"])
+                conv.append(bool(st["converged"]))
+            torch.cuda.synchronize()
+            r1 = time.perf_counter()
+            resid[prec] = {"steps_per_s": a.residual_steps / (r1 - r0), "sweeps_per_step": sweeps_used,
+                           "converged": conv, "seconds_per_step": (r1 - r0) / a.residual_steps}
+            log(f"to-residual {prec}: {resid[prec]}")
+            gr.close()
+
+    cpu = None
+    if a.cpu_tiles > 0:
+        cpu = cpu_baseline(a.cpu_tiles, a.sweeps)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": "NBGS contact updates/s + steps/s to residual 1e-6, 1M polydisperse spheres",
+        "value": value,
+        "unit": "contact updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: oracle-settled periodic tile of 10,000 spheres replicated to the packing",
+        "config": {"workload": f"dense settled packing, {sc.n} polydisperse spheres r~U[0.45,0.55], "
+                               f"periodic 100x100 floor box, phi~0.6, mu=0.5, dt=1e-4, {a.sweeps} FP64 NBGS "
+                               f"sweeps/step, previous-step warm start",
+                   "n_bodies": sc.n, "contacts_per_step": float(np.mean(contacts)),
+                   "contacts_per_body": float(np.mean(contacts)) / sc.n, "colours": int(np.max(colours)),
+                   "sweeps_per_step": a.sweeps},
+        "steps_per_s": a.steps / wall,
+        "phase_ms_last_step": {"detect": phases[0], "colour_order": phases[1], "init": phases[2],
+                               "sweeps": phases[3], "integrate": phases[4]},
+        "to_residual_1e-6": resid,
+        "roofline": roof,
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+    }
+    print(json.dumps(out), flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -205,6 +205,44 @@ nbgs_status nbgs_set_warm_start(nbgs_scene_t scene, int64_t n, const uint64_t *k
  * Synchronises. */
 nbgs_status nbgs_get_phase_times(nbgs_scene_t scene, int32_t n, double *out);
 
+/* Launch shape of the sweep kernel (results do not depend on it: every
+ * contact is relaxed by the same arithmetic).  block: threads per workgroup,
+ * 64, 128, 256 or 512; contacts_per_thread: 1, 2 or 4; xcd_remap: 1 maps
+ * consecutive workgroups, which the dispatcher deals round-robin over the
+ * 8 XCDs, onto contiguous contact ranges per XCD (shared body records stay
+ * in one L2), 0 keeps the identity mapping; nontemporal: 1 puts the
+ * non-temporal hint on the streamed per-contact arrays.  Default 256 / 1 / 1 / 0. */
+typedef struct {
+    int32_t block;
+    int32_t contacts_per_thread;
+    int32_t xcd_remap;
+    int32_t nontemporal;
+} nbgs_tuning;
+
+/* Set / read the sweep launch shape used for precision (nbgs_precision).
+ * INVALID_ARG for an unsupported shape. */
+nbgs_status nbgs_set_tuning(nbgs_scene_t scene, int32_t precision, const nbgs_tuning *tuning);
+nbgs_status nbgs_get_tuning(nbgs_scene_t scene, int32_t precision, nbgs_tuning *tuning);
+
+/* Sweep-kernel profile accumulated while profiling is enabled. */
+typedef struct {
+    double sweep_kernel_ms;  /* sum of device times of the sweep launches (HIP event pair per launch) */
+    int64_t sweep_launches;  /* non-empty colour launches timed */
+    double sweep_bytes;      /* compulsory bytes of those launches: per contact its record (ids, normal, xi/dt,
+                                arms, impulse read + write: 104 B FP64, 56 B FP32), per dynamic body touched its
+                                record read + v', w' written (112 B FP64, 56 B FP32) */
+    int64_t contact_updates; /* contact relaxations done by those launches */
+} nbgs_profile;
+
+/* Enable (1) or disable (0) profiling of the sweep launches of later
+ * nbgs_solve calls; enabling resets the accumulated profile.  While enabled,
+ * every sweep launch is bracketed by two HIP events on the scene's stream and
+ * nbgs_solve synchronises at its end. */
+nbgs_status nbgs_set_profiling(nbgs_scene_t scene, int32_t enable);
+
+/* Copy the accumulated profile into *out [host]. */
+nbgs_status nbgs_get_profile(nbgs_scene_t scene, nbgs_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -88,6 +88,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.nbgs_ref_detect_brute.restype = C.c_int64
         L.nbgs_ref_detect_grid.restype = C.c_int64
+        L.nbgs_ref_detect_body.restype = C.c_int64
         L.nbgs_ref_colour.restype = C.c_int32
         L.nbgs_ref_splitmix64.restype = C.c_uint64
         L.nbgs_ref_splitmix64.argtypes = [C.c_uint64]
@@ -171,6 +172,35 @@ def detect(sc, method: str = "brute") -> Dict[str, np.ndarray]:
     res = {k: v[:m].copy() for k, v in out.items()}
     res["n"] = np.stack([res.pop("nx"), res.pop("ny"), res.pop("nz")], axis=1)
     return res
+
+
+def detect_body(sc, i: int, held=None, structs=None) -> Dict[str, np.ndarray]:
+    """Contacts involving body i (as j1 or j2) in key order, by testing i against every body and wall."""
+    L = lib()
+    if structs is None:
+        held = _Held()
+        structs = (make_bodies(sc, held), make_domain(sc, held), make_params(sc))
+    b, d, p = structs
+    cap = 64
+    while True:
+        out = {k: np.zeros(cap, dtype=t) for k, t in (("j1", np.int32), ("j2", np.int32), ("key", np.uint64),
+                                                       ("nx", np.float64), ("ny", np.float64), ("nz", np.float64),
+                                                       ("xi", np.float64), ("a1", np.float64), ("a2", np.float64))}
+        c = RefContacts(cap=cap, j1=_ptr(out["j1"], _i32p), j2=_ptr(out["j2"], _i32p), key=_ptr(out["key"], _u64p),
+                        **{k: _ptr(out[k]) for k in ("nx", "ny", "nz", "xi", "a1", "a2")})
+        m = L.nbgs_ref_detect_body(C.byref(b), C.byref(d), C.byref(p), C.c_int64(i), C.byref(c))
+        if m <= cap:
+            break
+        cap = int(m)
+    res = {k: v[:m].copy() for k, v in out.items()}
+    res["n"] = np.stack([res.pop("nx"), res.pop("ny"), res.pop("nz")], axis=1)
+    return res
+
+
+def body_structs(sc):
+    """ctypes views of a scene, reusable across many detect_body calls."""
+    held = _Held()
+    return held, (make_bodies(sc, held), make_domain(sc, held), make_params(sc))
 
 
 def hull_radii(sc) -> np.ndarray:

@@ -140,13 +140,13 @@ static int sphere_pair(const ref_bodies *b, const ref_domain *dom, const double 
  * plane's hull radius is tau (it does not move).  Signed distance of the
  * centre s = n_w . (x_i - p_w); xi = s - r_i; the contact point is the foot
  * of the perpendicular on the plane. */
-static int sphere_plane(const ref_bodies *b, const ref_plane *pl, const double *h, double tau, int64_t i,
+static int sphere_plane(const ref_bodies *b, const ref_plane *pl, double h_i, double tau, int64_t i,
                         double *n, double *xi, double *a1, double *a2)
 {
     double s = pl->normal[0] * (b->x[i] - pl->point[0]) + pl->normal[1] * (b->y[i] - pl->point[1]) +
                pl->normal[2] * (b->z[i] - pl->point[2]);
     double gap = s - b->radius[i];
-    if (!(gap <= h[i] + tau)) return 0;
+    if (!(gap <= h_i + tau)) return 0;
     n[0] = pl->normal[0];
     n[1] = pl->normal[1];
     n[2] = pl->normal[2];
@@ -188,10 +188,62 @@ int64_t nbgs_ref_detect_brute(const ref_bodies *b, const ref_domain *dom, const 
         }
         if (is_static(b, i)) continue;
         for (int32_t w = 0; w < dom->n_planes; ++w)
-            if (sphere_plane(b, &dom->planes[w], h, p->tau, i, n, &xi, &a1, &a2))
+            if (sphere_plane(b, &dom->planes[w], h[i], p->tau, i, n, &xi, &a1, &a2))
                 put_contact(out, m++, i, b->n + w, n, xi, a1, a2);
     }
     free(h);
+    return m;
+}
+
+/* Contacts of one body i only, by testing it against every other body and
+ * every wall (the definition restricted to pairs containing i), in key order.
+ * Lets large scenes be checked on sampled bodies.  Returns the count. */
+int64_t nbgs_ref_detect_body(const ref_bodies *b, const ref_domain *dom, const ref_params *p, int64_t i,
+                             ref_contacts *out)
+{
+    /* hull radii of body i and of each partner, eq. (expansionradius) */
+    double h_i, h_k;
+    int64_t m = 0;
+    double n[3], xi, a1, a2;
+    {
+        double speed = sqrt(b->vx[i] * b->vx[i] + b->vy[i] * b->vy[i] + b->vz[i] * b->vz[i]);
+        double spin = sqrt(b->wx[i] * b->wx[i] + b->wy[i] * b->wy[i] + b->wz[i] * b->wz[i]);
+        h_i = p->dt * (speed + spin * b->radius[i]) + p->tau;
+    }
+    for (int64_t k = 0; k < b->n; ++k) {
+        if (k == i) continue;
+        if (is_static(b, i) && is_static(b, k)) continue;
+        double speed = sqrt(b->vx[k] * b->vx[k] + b->vy[k] * b->vy[k] + b->vz[k] * b->vz[k]);
+        double spin = sqrt(b->wx[k] * b->wx[k] + b->wy[k] * b->wy[k] + b->wz[k] * b->wz[k]);
+        h_k = p->dt * (speed + spin * b->radius[k]) + p->tau;
+        int64_t lo = k < i ? k : i, hi = k < i ? i : k;
+        const double h_lo = lo == i ? h_i : h_k, h_hi = hi == i ? h_i : h_k;
+        double dx = min_image(b->x[lo] - b->x[hi], dom, 0);
+        double dy = min_image(b->y[lo] - b->y[hi], dom, 1);
+        double dz = min_image(b->z[lo] - b->z[hi], dom, 2);
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double reach = (b->radius[lo] + h_lo) + (b->radius[hi] + h_hi);
+        if (!(d2 <= reach * reach)) continue;
+        double d = sqrt(d2);
+        if (d2 > 0.0) {
+            n[0] = dx / d;
+            n[1] = dy / d;
+            n[2] = dz / d;
+        } else {
+            n[0] = 0.0;
+            n[1] = 0.0;
+            n[2] = 1.0;
+        }
+        xi = (d - b->radius[lo]) - b->radius[hi];
+        a1 = b->radius[lo] + xi;
+        a2 = b->radius[hi];
+        put_contact(out, m++, lo, hi, n, xi, a1, a2);
+    }
+    if (!is_static(b, i))
+        for (int32_t w = 0; w < dom->n_planes; ++w)
+            if (sphere_plane(b, &dom->planes[w], h_i, p->tau, i, n, &xi, &a1, &a2))
+                put_contact(out, m++, i, b->n + w, n, xi, a1, a2);
+    /* partners k < i give keys (k, i), then (i, k > i), then walls: ascending already */
     return m;
 }
 
@@ -290,7 +342,7 @@ int64_t nbgs_ref_detect_grid(const ref_bodies *b, const ref_domain *dom, const r
         }
         if (is_static(b, i)) continue;
         for (int32_t w = 0; w < dom->n_planes; ++w)
-            if (sphere_plane(b, &dom->planes[w], h, p->tau, i, n, &xi, &a1, &a2))
+            if (sphere_plane(b, &dom->planes[w], h[i], p->tau, i, n, &xi, &a1, &a2))
                 put_contact(out, m++, i, N + w, n, xi, a1, a2);
     }
     free(cand);

@@ -57,6 +57,16 @@ class nbgs_stats(C.Structure):
                 ("residual", C.c_double)]
 
 
+class nbgs_profile(C.Structure):
+    _fields_ = [("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int64), ("sweep_bytes", C.c_double),
+                ("contact_updates", C.c_int64)]
+
+
+class nbgs_tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("contacts_per_thread", C.c_int32), ("xcd_remap", C.c_int32),
+                ("nontemporal", C.c_int32)]
+
+
 class NbgsError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"nbgs status {STATUS_NAMES.get(status, status)}: {msg}")
@@ -80,6 +90,10 @@ _SIGNATURES = [
     ("nbgs_get_residuals", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("nbgs_set_warm_start", C.c_int, [_vp, C.c_int64, _vp, _vp]),
     ("nbgs_get_phase_times", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
+    ("nbgs_set_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
+    ("nbgs_get_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
+    ("nbgs_set_profiling", C.c_int, [_vp, C.c_int32]),
+    ("nbgs_get_profile", C.c_int, [_vp, C.POINTER(nbgs_profile)]),
 ]
 
 _lib = None
@@ -185,6 +199,31 @@ def nbgs_get_phase_times(h: int, n: int = 5) -> np.ndarray:
     buf = (C.c_double * n)()
     _check(lib().nbgs_get_phase_times(_vp(h), int(n), buf))
     return np.array(buf[:], dtype=np.float64)
+
+
+def nbgs_set_tuning(h: int, precision: int, block: int, contacts_per_thread: int, xcd_remap: int,
+                    nontemporal: int = 0) -> None:
+    t = nbgs_tuning(block=block, contacts_per_thread=contacts_per_thread, xcd_remap=xcd_remap,
+                    nontemporal=nontemporal)
+    _check(lib().nbgs_set_tuning(_vp(h), int(precision), C.byref(t)))
+
+
+def nbgs_get_tuning(h: int, precision: int) -> Dict:
+    t = nbgs_tuning()
+    _check(lib().nbgs_get_tuning(_vp(h), int(precision), C.byref(t)))
+    return dict(block=t.block, contacts_per_thread=t.contacts_per_thread, xcd_remap=t.xcd_remap,
+                nontemporal=t.nontemporal)
+
+
+def nbgs_set_profiling(h: int, enable: bool) -> None:
+    _check(lib().nbgs_set_profiling(_vp(h), int(bool(enable))))
+
+
+def nbgs_get_profile(h: int) -> Dict:
+    p = nbgs_profile()
+    _check(lib().nbgs_get_profile(_vp(h), C.byref(p)))
+    return dict(sweep_kernel_ms=p.sweep_kernel_ms, sweep_launches=int(p.sweep_launches), sweep_bytes=p.sweep_bytes,
+                contact_updates=int(p.contact_updates))
 
 
 # ------------------------------------------------------------- convenience
@@ -319,6 +358,19 @@ class GpuScene:
         p = torch.tensor(np.ascontiguousarray(P.T), dtype=torch.float64, device=self.device).reshape(-1)
         nbgs_set_warm_start(self.handle, n, k.data_ptr(), p.data_ptr())
         self.stream.synchronize()
+
+    def set_tuning(self, block=256, contacts_per_thread=1, xcd_remap=1, nontemporal=0, precision=None):
+        prec = PRECISIONS[precision or self.precision]
+        nbgs_set_tuning(self.handle, prec, block, contacts_per_thread, xcd_remap, nontemporal)
+
+    def tuning(self, precision=None) -> Dict:
+        return nbgs_get_tuning(self.handle, PRECISIONS[precision or self.precision])
+
+    def set_profiling(self, enable: bool = True):
+        nbgs_set_profiling(self.handle, enable)
+
+    def profile(self) -> Dict:
+        return nbgs_get_profile(self.handle)
 
     def phase_times(self) -> np.ndarray:
         return nbgs_get_phase_times(self.handle, 5)

@@ -115,7 +115,7 @@ struct nbgs_scene_s {
     // scratch
     DevBuf<int32_t> radix_hist;
     DevBuf<char> scan_tmp;
-    DevBuf<int32_t> small;  // [0] total, [1] remaining, [2] overflow, [8..12) ctrl, [16..272) colour histogram
+    DevBuf<int32_t> small;  // [0] total, [1] remaining, [2] overflow, [8..12) ctrl, [16..528) colour histograms
     DevBuf<unsigned long long> maxbits;
     int32_t *pinned = nullptr;  // host mirror of small
     // contacts
@@ -124,12 +124,16 @@ struct nbgs_scene_s {
     bool table_in_cur = false;
     int64_t nc = 0, n_prev = 0;
     DevBuf<int32_t> inc2;
+    DevBuf<uint64_t> prio;
+    bool prev_colours = false;  // the previous table holds the colours of its contact set
+    int32_t colour_passes = 0;  // > 0: passes from the previous colours, < 0: Jones-Plassmann rounds
     DevBuf<uint32_t> ckeys, cids, ckeys2, cids2;
     SweepBuf<double> sw64;
     SweepBuf<float> sw32;
     int32_t n_colours = 0;
     std::vector<int64_t> col_off;
     std::vector<int64_t> part_off;
+    SweepTune tune[2];  // per precision (NBGS_FP64, NBGS_FP32_SWEEP)
     int64_t n_partials = 0;
     DevBuf<double> partials;
     DevBuf<double> res_hist;
@@ -138,6 +142,11 @@ struct nbgs_scene_s {
     nbgs_stats stats{};
     hipEvent_t ev[kNumPhases + 1] = {};
     bool ev_ok[kNumPhases + 1] = {};
+    std::vector<int64_t> col_dyn;  // dynamic bodies touched per colour
+    // sweep-kernel profiling (event pair around every sweep launch)
+    bool profiling = false;
+    std::vector<hipEvent_t> pev;
+    nbgs_profile prof{};
 
     int32_t *total() { return small.p + 0; }
     int32_t *remaining() { return small.p + 1; }
@@ -148,7 +157,7 @@ struct nbgs_scene_s {
 
 namespace {
 
-constexpr int kSmallInts = 16 + 256;
+constexpr int kSmallInts = 16 + 512;
 
 nbgs_status check_params(const nbgs_params *p) {
     if (!p) {
@@ -333,20 +342,41 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_TRY(cb.reserve((size_t)nc));
     NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->off.p, cb.view(), s));
-    // initial impulses
-    if (sc->p.warm_start == NBGS_WS_PREVIOUS && sc->n_prev > 0)
-        NBGS_TRY(launch_warm_match(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, sc->n_prev, sc->p.mu,
-                                   s));
-    else
-        NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
+    // initial impulses and, when the previous table carries colours, the start of the colouring
+    const bool warm_impulses = sc->p.warm_start == NBGS_WS_PREVIOUS && sc->n_prev > 0;
+    const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
+    NBGS_TRY(launch_match_prev(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p, sc->n_prev,
+                               sc->p.mu, warm_impulses, warm_colours, s));
+    if (!warm_impulses) NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
     record(sc, kColour);
     // colouring: body -> contacts where it is j2 (as j1 it owns the segment off[i] .. off[i] + cnt[i])
     NBGS_TRY(sc->inc2.reserve((size_t)(nc > 0 ? nc : 1)));
+    NBGS_TRY(sc->prio.reserve((size_t)(nc > 0 ? nc : 1)));
+    NBGS_TRY(launch_prio(cb.view(), nc, sc->p.colour_seed, sc->prio.p, s));
     NBGS_TRY(launch_j2_degree(cb.view(), nc, N, sc->b.inv_mass, sc->deg2.p, s));
     NBGS_TRY(exclusive_scan_i32(sc->deg2.p, sc->off2.p, (int64_t)N + 1, nullptr, sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_HIP(hipMemcpyAsync(sc->cursor.p, sc->off2.p, sizeof(int32_t) * ((size_t)N + 1), hipMemcpyDeviceToDevice, s));
     NBGS_TRY(launch_j2_fill(cb.view(), nc, N, sc->b.inv_mass, sc->cursor.p, sc->inc2.p, s));
-    if (nc > 0) {
+    sc->colour_passes = 0;
+    if (nc > 0 && warm_colours) {
+        // greedy rule repeated from the previous colours until a pass changes nothing
+        for (int pass = 0;; ++pass) {
+            NBGS_HIP(hipMemsetAsync(sc->remaining(), 0, 2 * sizeof(int32_t), s));
+            NBGS_TRY(launch_colour_fix(cb.view(), sc->prio.p, nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p, sc->off2.p,
+                                       sc->inc2.p, sc->remaining(), sc->overflow(), s));
+            NBGS_TRY(sync_small(sc, 1, 2));
+            sc->colour_passes = pass + 1;
+            if (sc->pinned[2]) {
+                set_error("more than 255 colours needed");
+                return NBGS_ERR_CAPACITY;
+            }
+            if (sc->pinned[1] == 0) break;
+            if (pass > 100000) {
+                set_error("colouring did not settle");
+                return NBGS_ERR_DEVICE;
+            }
+        }
+    } else if (nc > 0) {
         NBGS_HIP(hipMemsetAsync(cb.colour.p, 0xff, sizeof(int32_t) * nc, s));
         sc->pinned[1] = (int32_t)nc;
         sc->pinned[2] = 0;
@@ -354,8 +384,8 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
         int batch = 2, rounds = 0;
         for (;;) {
             for (int r = 0; r < batch; ++r)
-                NBGS_TRY(launch_jp_round(cb.view(), nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p, sc->off2.p,
-                                         sc->inc2.p, sc->p.colour_seed, sc->remaining(), sc->overflow(), s));
+                NBGS_TRY(launch_jp_round(cb.view(), sc->prio.p, nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p,
+                                         sc->off2.p, sc->inc2.p, sc->remaining(), sc->overflow(), s));
             rounds += batch;
             NBGS_TRY(sync_small(sc, 1, 2));
             if (sc->pinned[2]) {
@@ -369,22 +399,20 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
             }
             batch = batch < 8 ? batch * 2 : 8;
         }
+        sc->colour_passes = -rounds;
     }
     // colour-major order: stable sort of (colour, canonical index)
-    NBGS_TRY(launch_colour_hist(cb.view(), nc, sc->chist(), s));
-    NBGS_TRY(sync_small(sc, 16, 256));
+    NBGS_TRY(launch_colour_hist(cb.view(), nc, N, sc->b.inv_mass, sc->chist(), s));
+    NBGS_TRY(sync_small(sc, 16, 512));
     sc->n_colours = 0;
     for (int c = 0; c < 256; ++c)
         if (sc->pinned[16 + c]) sc->n_colours = c + 1;
     sc->col_off.assign((size_t)sc->n_colours + 1, 0);
-    for (int c = 0; c < sc->n_colours; ++c) sc->col_off[c + 1] = sc->col_off[c] + sc->pinned[16 + c];
-    sc->part_off.assign((size_t)sc->n_colours + 1, 0);
+    sc->col_dyn.assign((size_t)sc->n_colours, 0);
     for (int c = 0; c < sc->n_colours; ++c) {
-        const int64_t m = sc->col_off[c + 1] - sc->col_off[c];
-        sc->part_off[c + 1] = sc->part_off[c] + (m + kSweepBlock - 1) / kSweepBlock;
+        sc->col_off[c + 1] = sc->col_off[c] + sc->pinned[16 + c];
+        sc->col_dyn[c] = sc->pinned[16 + 256 + c];
     }
-    sc->n_partials = sc->part_off[sc->n_colours];
-    NBGS_TRY(sc->partials.reserve(2 * (size_t)(sc->n_partials > 0 ? sc->n_partials : 1)));
     NBGS_TRY(sc->ckeys.reserve((size_t)nc + 1));
     NBGS_TRY(sc->cids.reserve((size_t)nc + 1));
     NBGS_TRY(sc->ckeys2.reserve((size_t)nc + 1));
@@ -411,6 +439,45 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     return NBGS_OK;
 }
 
+nbgs_status ensure_profile_events(nbgs_scene_t sc, size_t launches) {
+    while (sc->pev.size() < 2 * launches) {
+        hipEvent_t e;
+        NBGS_HIP(hipEventCreate(&e));
+        sc->pev.push_back(e);
+    }
+    return NBGS_OK;
+}
+
+// Compulsory bytes of one sweep launch: the contact record (ids, normal,
+// xi/dt, arms, impulse read and written) plus, per dynamic body touched, its
+// record read (v', w', 1/m, 1/I) and v', w' written.
+template <class T>
+constexpr double contact_bytes() {
+    return 2 * 4 + 6 * sizeof(T) + 2 * 3 * sizeof(T);
+}
+template <class T>
+constexpr double body_bytes() {
+    return 8 * sizeof(T) + 6 * sizeof(T);
+}
+
+template <class T>
+nbgs_status accumulate_profile(nbgs_scene_t sc, int32_t sweeps) {
+    NBGS_HIP(hipStreamSynchronize(sc->s));
+    size_t pe = 0;
+    for (int32_t k = 0; k < sweeps; ++k)
+        for (int c = 0; c < sc->n_colours; ++c, ++pe) {
+            float ms = 0.0f;
+            NBGS_HIP(hipEventElapsedTime(&ms, sc->pev[2 * pe], sc->pev[2 * pe + 1]));
+            const int64_t m = sc->col_off[c + 1] - sc->col_off[c];
+            if (m == 0) continue;
+            sc->prof.sweep_kernel_ms += ms;
+            sc->prof.sweep_launches += 1;
+            sc->prof.contact_updates += m;
+            sc->prof.sweep_bytes += contact_bytes<T>() * (double)m + body_bytes<T>() * (double)sc->col_dyn[c];
+        }
+    return NBGS_OK;
+}
+
 template <class T>
 nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats) {
     hipStream_t s = sc->s;
@@ -425,16 +492,31 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
         for (int c = 0; c < sc->n_colours; ++c)
             NBGS_TRY(launch_warm_scatter<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, s));
     record(sc, kSweeps);
+    const SweepTune &tune = sc->tune[sc->precision_used == NBGS_FP32_SWEEP ? 1 : 0];
+    sc->part_off.assign((size_t)sc->n_colours + 1, 0);
+    for (int c = 0; c < sc->n_colours; ++c) {
+        const int64_t m = sc->col_off[c + 1] - sc->col_off[c];
+        sc->part_off[c + 1] = sc->part_off[c] + (m + sweep_tile(tune) - 1) / sweep_tile(tune);
+    }
+    sc->n_partials = sc->part_off[sc->n_colours];
+    NBGS_TRY(sc->partials.reserve(2 * (size_t)(sc->n_partials > 0 ? sc->n_partials : 1)));
     NBGS_HIP(hipMemsetAsync(sc->ctrl(), 0, 4 * sizeof(int32_t), s));
     SweepParams sp{sc->p.mu, sc->p.relax};
     int32_t launched = 0, chunk = target > 0.0 ? 4 : max_sweeps;
     bool done = false;
+    const bool prof = sc->profiling;
+    if (prof) NBGS_TRY(ensure_profile_events(sc, (size_t)max_sweeps * sc->n_colours));
+    size_t pe = 0;
     while (launched < max_sweeps && !done) {
         const int32_t k = std::min(chunk, max_sweeps - launched);
         for (int32_t it = 0; it < k; ++it) {
-            for (int c = 0; c < sc->n_colours; ++c)
-                NBGS_TRY(launch_sweep_colour<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, sp,
+            for (int c = 0; c < sc->n_colours; ++c) {
+                if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * pe], s));
+                NBGS_TRY(launch_sweep_colour<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, sp, tune,
                                                 sc->partials.p + 2 * sc->part_off[c], sc->ctrl(), s));
+                if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * pe + 1], s));
+                ++pe;
+            }
             NBGS_TRY(launch_residual(sc->partials.p, (int32_t)sc->n_partials, target, sc->ctrl(), sc->res_hist.p, s));
         }
         launched += k;
@@ -460,6 +542,7 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
         sc->stats.sweeps = sweeps;
         sc->stats.residual = R;
         if (stats) *stats = sc->stats;
+        if (prof) NBGS_TRY(accumulate_profile<T>(sc, sweeps));
         if (sc->pinned[8 + 2]) {
             set_error("non-finite residual after sweep %d", sweeps);
             return NBGS_ERR_NUMERIC;
@@ -470,6 +553,7 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
         }
     } else {
         sc->stats.sweeps = max_sweeps;
+        if (prof) NBGS_TRY(accumulate_profile<T>(sc, max_sweeps));
     }
     return NBGS_OK;
 }
@@ -481,6 +565,7 @@ nbgs_status integrate_impl(nbgs_scene_t sc) {
     record(sc, kNumPhases);
     sc->table_in_cur = true;
     sc->n_prev = sc->nc;
+    sc->prev_colours = true;
     sc->state = 0;
     return NBGS_OK;
 }
@@ -638,6 +723,7 @@ nbgs_status nbgs_scene_destroy(nbgs_scene_t sc) {
     (void)hipStreamSynchronize(sc->s);
     for (int i = 0; i <= kNumPhases; ++i)
         if (sc->ev[i]) (void)hipEventDestroy(sc->ev[i]);
+    for (hipEvent_t e : sc->pev) (void)hipEventDestroy(e);
     if (sc->pinned) (void)hipHostFree(sc->pinned);
     delete sc;
     return NBGS_OK;
@@ -776,6 +862,7 @@ nbgs_status nbgs_set_warm_start(nbgs_scene_t sc, int64_t n, const uint64_t *keys
         NBGS_HIP(hipMemcpyAsync(prev.pz.p, impulse + 2 * n, n * sizeof(double), hipMemcpyDeviceToDevice, sc->s));
     }
     sc->n_prev = n;
+    sc->prev_colours = false;
     return NBGS_OK;
 }
 
@@ -793,6 +880,57 @@ nbgs_status nbgs_get_phase_times(nbgs_scene_t sc, int32_t n, double *out) {
         else
             out[i] = 0.0;
     }
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_set_tuning(nbgs_scene_t sc, int32_t precision, const nbgs_tuning *t) {
+    NBGS_GUARD(sc);
+    if (!t || (precision != NBGS_FP64 && precision != NBGS_FP32_SWEEP)) {
+        set_error("bad tuning arguments");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    SweepTune st;
+    st.block = t->block;
+    st.cpt = t->contacts_per_thread;
+    st.xcd_remap = t->xcd_remap;
+    st.nontemporal = t->nontemporal;
+    if (!sweep_tune_supported(st)) {
+        set_error("unsupported tuning: block %d, contacts_per_thread %d, xcd_remap %d, nontemporal %d", t->block,
+                  t->contacts_per_thread, t->xcd_remap, t->nontemporal);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    sc->tune[precision] = st;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_tuning(nbgs_scene_t sc, int32_t precision, nbgs_tuning *t) {
+    NBGS_GUARD(sc);
+    if (!t || (precision != NBGS_FP64 && precision != NBGS_FP32_SWEEP)) {
+        set_error("bad tuning arguments");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    const SweepTune &st = sc->tune[precision];
+    t->block = st.block;
+    t->contacts_per_thread = st.cpt;
+    t->xcd_remap = st.xcd_remap;
+    t->nontemporal = st.nontemporal;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_set_profiling(nbgs_scene_t sc, int32_t enable) {
+    NBGS_GUARD(sc);
+    sc->profiling = enable != 0;
+    sc->prof = nbgs_profile{};
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_profile(nbgs_scene_t sc, nbgs_profile *out) {
+    NBGS_GUARD(sc);
+    if (!out) {
+        set_error("out is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    *out = sc->prof;
     return NBGS_OK;
 }
 

@@ -13,6 +13,15 @@
 // exactly the sequential greedy colouring in priority order.  A neighbour seen
 // as uncoloured because its colour is not visible yet only delays a contact by
 // a round; it never changes the colour chosen.
+//
+// Between time steps the contact graph changes little, so a step starts from
+// the previous step's colours (matched by pair key) and repeats the greedy
+// rule  colour(j) = smallest colour not held by a higher-priority neighbour
+// over all contacts until a pass changes nothing.  The rule's fixed point is
+// unique -- by induction over the longest chain of decreasing priority ending
+// at j, after pass r every contact whose chain is at most r long holds its
+// greedy colour and keeps it -- so the result is again the greedy colouring;
+// only the number of passes depends on the start.
 #include "nbgs_internal.h"
 
 namespace nbgs {
@@ -55,26 +64,34 @@ struct Probe {
     bool blocked;
 };
 
-__device__ inline void probe(Probe &pr, const ContactsView &c, int64_t l, uint64_t seed) {
+// l precedes j in the greedy order (higher priority, ties: smaller key)
+__device__ inline bool precedes(uint64_t pl, uint64_t kl, uint64_t pj, uint64_t kj) {
+    return pl > pj || (pl == pj && kl < kj);
+}
+
+__device__ inline void probe(Probe &pr, const ContactsView &c, const uint64_t *prio, int64_t l) {
     const int cl = __hip_atomic_load(&c.colour[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cl >= 0) {
         pr.used[cl >> 6] |= 1ull << (cl & 63);
         return;
     }
-    const uint64_t kl = c.key[l];
-    const uint64_t pl = splitmix64(kl ^ seed);
-    if (pl > pr.prio || (pl == pr.prio && kl < pr.key)) pr.blocked = true;
+    if (precedes(prio[l], c.key[l], pr.prio, pr.key)) pr.blocked = true;
 }
 
-__global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, int64_t nc, int32_t nb,
+__global__ void __launch_bounds__(kBlock) k_prio(const uint64_t *key, int64_t nc, uint64_t seed, uint64_t *prio) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j < nc) prio[j] = splitmix64(key[j] ^ seed);
+}
+
+__global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, const uint64_t *prio, int64_t nc, int32_t nb,
                                                      const double *inv_mass, const int32_t *off1,
                                                      const int32_t *cnt1, const int32_t *off2, const int32_t *inc2,
-                                                     uint64_t seed, int32_t *remaining, int32_t *overflow) {
+                                                     int32_t *remaining, int32_t *overflow) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc || c.colour[j] >= 0) return;
     Probe pr;
     pr.key = c.key[j];
-    pr.prio = splitmix64(pr.key ^ seed);
+    pr.prio = prio[j];
     pr.blocked = false;
 #pragma unroll
     for (int w = 0; w < kMaxColours / 64; ++w) pr.used[w] = 0;
@@ -84,11 +101,11 @@ __global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, int64_t nc,
         if (b >= nb || !(inv_mass[b] > 0.0)) continue;
         const int a0 = off1[b], a1 = a0 + cnt1[b];
         for (int l = a0; l < a1 && !pr.blocked; ++l)
-            if (l != j) probe(pr, c, l, seed);
+            if (l != j) probe(pr, c, prio, l);
         const int q1 = off2[b + 1];
         for (int q = off2[b]; q < q1 && !pr.blocked; ++q) {
             const int l = inc2[q];
-            if (l != j) probe(pr, c, l, seed);
+            if (l != j) probe(pr, c, prio, l);
         }
     }
     if (pr.blocked) return;
@@ -105,14 +122,66 @@ __global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, int64_t nc,
     atomicSub(remaining, 1);
 }
 
-__global__ void __launch_bounds__(kBlock) k_colour_hist(const int32_t *colour, int64_t nc, int32_t *hist) {
-    __shared__ int cnt[kMaxColours];
-    for (int d = threadIdx.x; d < kMaxColours; d += kBlock) cnt[d] = 0;
+// hist[c]: contacts of colour c; hist[256 + c]: dynamic bodies they touch
+// (the body records a sweep launch of colour c reads and writes).
+// One pass of colour(j) <- smallest colour not held by a higher-priority
+// neighbour; *changed counts the contacts whose colour moved.
+__global__ void __launch_bounds__(kBlock) k_colour_fix(ContactsView c, const uint64_t *prio, int64_t nc, int32_t nb,
+                                                       const double *inv_mass, const int32_t *off1,
+                                                       const int32_t *cnt1, const int32_t *off2,
+                                                       const int32_t *inc2, int32_t *changed, int32_t *overflow) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    const uint64_t kj = c.key[j], pj = prio[j];
+    uint64_t used[kMaxColours / 64] = {0, 0, 0, 0};
+    const int ends[2] = {c.j1[j], c.j2[j]};
+    for (int e = 0; e < 2; ++e) {
+        const int b = ends[e];
+        if (b >= nb || !(inv_mass[b] > 0.0)) continue;
+        const int a0 = off1[b], a1 = a0 + cnt1[b];
+        for (int l = a0; l < a1; ++l) {
+            if (l == j || !precedes(prio[l], c.key[l], pj, kj)) continue;
+            const int cl = __hip_atomic_load(&c.colour[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            used[(cl >> 6) & 3] |= 1ull << (cl & 63);
+        }
+        const int q1 = off2[b + 1];
+        for (int q = off2[b]; q < q1; ++q) {
+            const int l = inc2[q];
+            if (l == j || !precedes(prio[l], c.key[l], pj, kj)) continue;
+            const int cl = __hip_atomic_load(&c.colour[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            used[(cl >> 6) & 3] |= 1ull << (cl & 63);
+        }
+    }
+    int col = -1;
+#pragma unroll
+    for (int w = 0; w < kMaxColours / 64; ++w) {
+        if (col < 0 && used[w] != ~0ull) col = 64 * w + __ffsll((long long)~used[w]) - 1;
+    }
+    if (col < 0) {
+        atomicExch(overflow, 1);
+        col = kMaxColours - 1;
+    }
+    if (col != c.colour[j]) {
+        __hip_atomic_store(&c.colour[j], col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(changed, 1);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_colour_hist(ContactsView c, int64_t nc, int32_t nb,
+                                                        const double *inv_mass, int32_t *hist) {
+    __shared__ int cnt[2 * kMaxColours];
+    for (int d = threadIdx.x; d < 2 * kMaxColours; d += kBlock) cnt[d] = 0;
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < nc) atomicAdd(&cnt[colour[j] & (kMaxColours - 1)], 1);
+    if (j < nc) {
+        const int col = c.colour[j] & (kMaxColours - 1);
+        atomicAdd(&cnt[col], 1);
+        const int b1 = c.j1[j], b2 = c.j2[j];
+        const int dyn = (inv_mass[b1] > 0.0 ? 1 : 0) + (b2 < nb && inv_mass[b2] > 0.0 ? 1 : 0);
+        atomicAdd(&cnt[kMaxColours + col], dyn);
+    }
     __syncthreads();
-    for (int d = threadIdx.x; d < kMaxColours; d += kBlock)
+    for (int d = threadIdx.x; d < 2 * kMaxColours; d += kBlock)
         if (cnt[d]) atomicAdd(&hist[d], cnt[d]);
 }
 
@@ -165,20 +234,38 @@ nbgs_status launch_j2_fill(const ContactsView &c, int64_t nc, int32_t nb, const 
     return NBGS_OK;
 }
 
-nbgs_status launch_jp_round(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass,
-                            const int32_t *off1, const int32_t *cnt1, const int32_t *off2, const int32_t *inc2,
-                            uint64_t seed, int32_t *remaining, int32_t *overflow, hipStream_t s) {
+nbgs_status launch_prio(const ContactsView &c, int64_t nc, uint64_t seed, uint64_t *prio, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_jp_round<<<grid_for(nc), kBlock, 0, s>>>(c, nc, nb, inv_mass, off1, cnt1, off2, inc2, seed, remaining,
+    k_prio<<<grid_for(nc), kBlock, 0, s>>>(c.key, nc, seed, prio);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_jp_round(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
+                            const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
+                            const int32_t *inc2, int32_t *remaining, int32_t *overflow, hipStream_t s) {
+    if (nc == 0) return NBGS_OK;
+    k_jp_round<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, remaining,
                                                overflow);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
-nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t *hist, hipStream_t s) {
-    NBGS_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * kMaxColours, s));
+nbgs_status launch_colour_fix(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
+                              const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
+                              const int32_t *inc2, int32_t *changed, int32_t *overflow, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_colour_hist<<<grid_for(nc), kBlock, 0, s>>>(c.colour, nc, hist);
+    k_colour_fix<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, changed,
+                                                 overflow);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *hist,
+                               hipStream_t s) {
+    NBGS_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * 2 * kMaxColours, s));
+    if (nc == 0) return NBGS_OK;
+    k_colour_hist<<<grid_for(nc), kBlock, 0, s>>>(c, nc, nb, inv_mass, hist);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

@@ -263,11 +263,15 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g, Plan
     }
 }
 
-// Previous-step impulse of the same pair, re-projected onto the new cone:
-// P_n = max(0, n.P), tangential part clipped to mu P_n.
-__global__ void __launch_bounds__(kBlock) k_warm_match(ContactsView c, int64_t nc, const uint64_t *prev_key,
+// Look each contact's pair key up in the previous step's key-sorted table.
+// impulses: the previous impulse of the same pair re-projected onto the new
+// cone (P_n = max(0, n.P), tangential part clipped to mu P_n), zero if the pair
+// is new.  colours: the previous colour as the start of the colouring passes
+// (0 if new).
+__global__ void __launch_bounds__(kBlock) k_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key,
                                                        const double *prev_px, const double *prev_py,
-                                                       const double *prev_pz, int64_t n_prev, double mu) {
+                                                       const double *prev_pz, const int32_t *prev_colour,
+                                                       int64_t n_prev, double mu, int impulses, int colours) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc) return;
     const uint64_t key = c.key[j];
@@ -277,8 +281,11 @@ __global__ void __launch_bounds__(kBlock) k_warm_match(ContactsView c, int64_t n
         if (prev_key[mid] < key) lo = mid + 1;
         else hi = mid;
     }
+    const bool found = lo < n_prev && prev_key[lo] == key;
+    if (colours) c.colour[j] = found ? prev_colour[lo] : 0;
+    if (!impulses) return;
     double P0 = 0.0, P1 = 0.0, P2 = 0.0;
-    if (lo < n_prev && prev_key[lo] == key) {
+    if (found) {
         const double n0 = c.nx[j], n1 = c.ny[j], n2 = c.nz[j];
         const double q0 = prev_px[lo], q1 = prev_py[lo], q2 = prev_pz[lo];
         double pn = n0 * q0 + n1 * q1 + n2 * q2;
@@ -345,11 +352,12 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
     return NBGS_OK;
 }
 
-nbgs_status launch_warm_match(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
-                              const double *prev_py, const double *prev_pz, int64_t n_prev, double mu,
-                              hipStream_t s) {
-    if (nc == 0) return NBGS_OK;
-    k_warm_match<<<grid_for(nc), kBlock, 0, s>>>(c, nc, prev_key, prev_px, prev_py, prev_pz, n_prev, mu);
+nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
+                              const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
+                              int64_t n_prev, double mu, bool impulses, bool colours, hipStream_t s) {
+    if (nc == 0 || (!impulses && !colours)) return NBGS_OK;
+    k_match_prev<<<grid_for(nc), kBlock, 0, s>>>(c, nc, prev_key, prev_px, prev_py, prev_pz, prev_colour, n_prev, mu,
+                                                 impulses ? 1 : 0, colours ? 1 : 0);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

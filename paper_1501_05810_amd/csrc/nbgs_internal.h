@@ -129,9 +129,9 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
                              uint32_t stamp, const int32_t *off, ContactsView c, hipStream_t s);
-nbgs_status launch_warm_match(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
-                              const double *prev_py, const double *prev_pz, int64_t n_prev, double mu,
-                              hipStream_t s);
+nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
+                              const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
+                              int64_t n_prev, double mu, bool impulses, bool colours, hipStream_t s);
 nbgs_status launch_zero_impulses(ContactsView c, int64_t nc, hipStream_t s);
 
 // colour.hip
@@ -139,10 +139,15 @@ nbgs_status launch_j2_degree(const ContactsView &c, int64_t nc, int32_t nb, cons
                              hipStream_t s);
 nbgs_status launch_j2_fill(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *cursor,
                            int32_t *inc2, hipStream_t s);
-nbgs_status launch_jp_round(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass,
-                            const int32_t *off1, const int32_t *cnt1, const int32_t *off2, const int32_t *inc2,
-                            uint64_t seed, int32_t *remaining, int32_t *overflow, hipStream_t s);
-nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t *hist, hipStream_t s);
+nbgs_status launch_prio(const ContactsView &c, int64_t nc, uint64_t seed, uint64_t *prio, hipStream_t s);
+nbgs_status launch_jp_round(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
+                            const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
+                            const int32_t *inc2, int32_t *remaining, int32_t *overflow, hipStream_t s);
+nbgs_status launch_colour_fix(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
+                              const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
+                              const int32_t *inc2, int32_t *changed, int32_t *overflow, hipStream_t s);
+nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *hist,
+                               hipStream_t s);
 nbgs_status launch_colour_keys(const ContactsView &c, int64_t nc, uint32_t *keys, uint32_t *ids, hipStream_t s);
 template <class T>
 nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, int64_t nc, double dt, double erp,
@@ -156,9 +161,17 @@ template <class T>
 nbgs_status launch_init_bodies(const BodiesView &b, const double g[3], double dt, T *vel, hipStream_t s);
 template <class T>
 nbgs_status launch_warm_scatter(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, hipStream_t s);
+struct SweepTune {
+    int32_t block = 256;   // threads per workgroup
+    int32_t cpt = 1;       // contacts per thread
+    int32_t xcd_remap = 1; // contiguous tile runs per XCD
+    int32_t nontemporal = 0; // non-temporal hint on the streamed contact arrays
+};
+int64_t sweep_tile(const SweepTune &t);
+bool sweep_tune_supported(const SweepTune &t);
 template <class T>
 nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, SweepParams sp,
-                                double *partials, const int32_t *ctrl, hipStream_t s);
+                                const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s);
 nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl,
                             double *hist, hipStream_t s);
 template <class T>

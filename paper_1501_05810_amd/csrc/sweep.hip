@@ -149,37 +149,89 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// One colour of one sweep.  partials receives (sum |dP|^2, sum |P|^2) of this
-// block; ctrl[0] != 0 means an earlier sweep already met the residual target.
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_sweep(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel,
-                                                  T mu, T relax, double *partials, const int32_t *ctrl) {
+// Streamed contact arrays are read once and written once per sweep; with NT
+// the accesses carry the non-temporal hint so that they do not evict the body
+// records, which every colour of the sweep touches again.
+template <bool NT, class V>
+__device__ inline V ld(const V *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, class V>
+__device__ inline void st(V *p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Workgroup -> contact tile.  With xcd_remap, consecutive workgroups (which
+// the dispatcher deals round-robin over the 8 XCDs) are mapped so that every
+// XCD walks one contiguous run of tiles: neighbouring contacts, and the body
+// records they share, stay in the L2 of one XCD.
+__device__ inline unsigned tile_of(unsigned b, unsigned G, int xcd_remap) {
+    if (!xcd_remap) return b;
+    const unsigned x = b & 7u, i = b >> 3, q = G >> 3, r = G & 7u;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// One colour of one sweep; each thread relaxes CPT contacts (strided by the
+// block size, all loads issued before any arithmetic).  partials receives
+// (sum |dP|^2, sum |P|^2) of the tile; ctrl[0] != 0 means an earlier sweep
+// already met the residual target.
+template <class T, int BLOCK, int CPT, bool NT>
+__global__ void __launch_bounds__(BLOCK) k_sweep(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel,
+                                                 T mu, T relax, double *partials, const int32_t *ctrl,
+                                                 int xcd_remap) {
     if (ctrl[0]) return;
-    const int64_t p = begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const unsigned tile = tile_of(blockIdx.x, gridDim.x, xcd_remap);
+    const int64_t p0 = begin + (int64_t)tile * (BLOCK * CPT) + threadIdx.x;
     double sd = 0.0, sp = 0.0;
-    if (p < end) {
-        const int b1 = sv.j1[p], b2 = sv.j2[p];
-        const T n[3] = {sv.nx[p], sv.ny[p], sv.nz[p]};
-        const T bias = sv.bias[p], a1 = sv.a1[p], a2 = sv.a2[p];
-        const T P[3] = {sv.px[p], sv.py[p], sv.pz[p]};
-        Rec<T> r1 = load_rec(vel, b1);
-        Rec<T> r2 = b2 < nb ? load_rec(vel, b2) : zero_rec<T>();
+    int b1[CPT], b2[CPT];
+    bool ok[CPT];
+    T n[CPT][3], bias[CPT], a1[CPT], a2[CPT], P[CPT][3];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        const int64_t p = p0 + (int64_t)k * BLOCK;
+        ok[k] = p < end;
+        const int64_t q = ok[k] ? p : begin;
+        b1[k] = ld<NT>(sv.j1 + q);
+        b2[k] = ld<NT>(sv.j2 + q);
+        n[k][0] = ld<NT>(sv.nx + q);
+        n[k][1] = ld<NT>(sv.ny + q);
+        n[k][2] = ld<NT>(sv.nz + q);
+        bias[k] = ld<NT>(sv.bias + q);
+        a1[k] = ld<NT>(sv.a1 + q);
+        a2[k] = ld<NT>(sv.a2 + q);
+        P[k][0] = ld<NT>(sv.px + q);
+        P[k][1] = ld<NT>(sv.py + q);
+        P[k][2] = ld<NT>(sv.pz + q);
+    }
+    Rec<T> r1[CPT], r2[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        r1[k] = load_rec(vel, b1[k]);
+        r2[k] = b2[k] < nb ? load_rec(vel, b2[k]) : zero_rec<T>();
+    }
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        if (!ok[k]) continue;
+        const T *nk = n[k];
         // relative velocity at the contact point
-        const T s0 = a1 * r1.w[0] + a2 * r2.w[0];
-        const T s1 = a1 * r1.w[1] + a2 * r2.w[1];
-        const T s2 = a1 * r1.w[2] + a2 * r2.w[2];
+        const T s0 = a1[k] * r1[k].w[0] + a2[k] * r2[k].w[0];
+        const T s1 = a1[k] * r1[k].w[1] + a2[k] * r2[k].w[1];
+        const T s2 = a1[k] * r1[k].w[2] + a2[k] * r2[k].w[2];
         T du[3];
-        du[0] = (r1.v[0] - r2.v[0]) - (s1 * n[2] - s2 * n[1]);
-        du[1] = (r1.v[1] - r2.v[1]) - (s2 * n[0] - s0 * n[2]);
-        du[2] = (r1.v[2] - r2.v[2]) - (s0 * n[1] - s1 * n[0]);
-        const T dun = n[0] * du[0] + n[1] * du[1] + n[2] * du[2];
-        const T un = bias + dun;
-        const T ut[3] = {du[0] - dun * n[0], du[1] - dun * n[1], du[2] - dun * n[2]};
+        du[0] = (r1[k].v[0] - r2[k].v[0]) - (s1 * nk[2] - s2 * nk[1]);
+        du[1] = (r1[k].v[1] - r2[k].v[1]) - (s2 * nk[0] - s0 * nk[2]);
+        du[2] = (r1[k].v[2] - r2[k].v[2]) - (s0 * nk[1] - s1 * nk[0]);
+        const T dun = nk[0] * du[0] + nk[1] * du[1] + nk[2] * du[2];
+        const T un = bias[k] + dun;
+        const T ut[3] = {du[0] - dun * nk[0], du[1] - dun * nk[1], du[2] - dun * nk[2]};
         // own impulse in the contact frame
-        const T Pn = n[0] * P[0] + n[1] * P[1] + n[2] * P[2];
-        const T Pt[3] = {P[0] - Pn * n[0], P[1] - Pn * n[1], P[2] - Pn * n[2]};
-        const T wn = r1.im + r2.im;
-        const T wt = wn + r1.ii * a1 * a1 + r2.ii * a2 * a2;
+        const T *Pk = P[k];
+        const T Pn = nk[0] * Pk[0] + nk[1] * Pk[1] + nk[2] * Pk[2];
+        const T Pt[3] = {Pk[0] - Pn * nk[0], Pk[1] - Pn * nk[1], Pk[2] - Pn * nk[2]};
+        const T wn = r1[k].im + r2[k].im;
+        const T wt = wn + r1[k].ii * a1[k] * a1[k] + r2[k].ii * a2[k] * a2[k];
         const T bn = un - wn * Pn;
         const T bt[3] = {ut[0] - wt * Pt[0], ut[1] - wt * Pt[1], ut[2] - wt * Pt[2]};
         // one-contact solve: normal clamp, radial projection onto the cone
@@ -194,25 +246,26 @@ __global__ void __launch_bounds__(kBlock) k_sweep(SweepView<T> sv, int64_t begin
             t1 = t1 * sc;
             t2 = t2 * sc;
         }
-        const T Ps[3] = {pn * n[0] + t0, pn * n[1] + t1, pn * n[2] + t2};
+        const T Ps[3] = {pn * nk[0] + t0, pn * nk[1] + t1, pn * nk[2] + t2};
         T Pnew[3], dP[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            Pnew[a] = relax * Ps[a] + (T(1) - relax) * P[a];
-            dP[a] = Pnew[a] - P[a];
+            Pnew[a] = relax * Ps[a] + (T(1) - relax) * Pk[a];
+            dP[a] = Pnew[a] - Pk[a];
         }
-        apply(r1, r2, n, a1, a2, dP);
-        if (r1.im > T(0)) store_vel(vel, b1, r1);
-        if (b2 < nb && r2.im > T(0)) store_vel(vel, b2, r2);
-        sv.px[p] = Pnew[0];
-        sv.py[p] = Pnew[1];
-        sv.pz[p] = Pnew[2];
+        apply(r1[k], r2[k], nk, a1[k], a2[k], dP);
+        if (r1[k].im > T(0)) store_vel(vel, b1[k], r1[k]);
+        if (b2[k] < nb && r2[k].im > T(0)) store_vel(vel, b2[k], r2[k]);
+        const int64_t p = p0 + (int64_t)k * BLOCK;
+        st<NT>(sv.px + p, Pnew[0]);
+        st<NT>(sv.py + p, Pnew[1]);
+        st<NT>(sv.pz + p, Pnew[2]);
         const double d0 = dP[0], d1 = dP[1], d2 = dP[2];
         const double q0 = Pnew[0], q1 = Pnew[1], q2 = Pnew[2];
-        sd = d0 * d0 + d1 * d1 + d2 * d2;
-        sp = q0 * q0 + q1 * q1 + q2 * q2;
+        sd += d0 * d0 + d1 * d1 + d2 * d2;
+        sp += q0 * q0 + q1 * q1 + q2 * q2;
     }
-    __shared__ double red[2][kBlock / 64];
+    __shared__ double red[2][BLOCK / 64];
     sd = wave_sum(sd);
     sp = wave_sum(sp);
     const int wave = threadIdx.x >> 6;
@@ -224,12 +277,12 @@ __global__ void __launch_bounds__(kBlock) k_sweep(SweepView<T> sv, int64_t begin
     if (threadIdx.x == 0) {
         double a = 0.0, c = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) {
+        for (int w = 0; w < BLOCK / 64; ++w) {
             a += red[0][w];
             c += red[1][w];
         }
-        partials[2 * blockIdx.x + 0] = a;
-        partials[2 * blockIdx.x + 1] = c;
+        partials[2 * tile + 0] = a;
+        partials[2 * tile + 1] = c;
     }
 }
 
@@ -349,14 +402,46 @@ nbgs_status launch_warm_scatter(SweepView<T> sv, int64_t begin, int64_t end, int
     return NBGS_OK;
 }
 
+int64_t sweep_tile(const SweepTune &t) { return (int64_t)t.block * t.cpt; }
+
+bool sweep_tune_supported(const SweepTune &t) {
+    const bool blk = t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512;
+    return blk && (t.cpt == 1 || t.cpt == 2 || t.cpt == 4) && (t.xcd_remap == 0 || t.xcd_remap == 1) &&
+           (t.nontemporal == 0 || t.nontemporal == 1);
+}
+
 template <class T>
 nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, SweepParams sp,
-                                double *partials, const int32_t *ctrl, hipStream_t s) {
+                                const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s) {
     if (end <= begin) return NBGS_OK;
-    k_sweep<T><<<grid_for(end - begin), kBlock, 0, s>>>(sv, begin, end, nb, vel, (T)sp.mu, (T)sp.relax, partials,
-                                                        ctrl);
-    NBGS_HIP(hipGetLastError());
-    return NBGS_OK;
+    const unsigned grid = (unsigned)((end - begin + sweep_tile(t) - 1) / sweep_tile(t));
+    const T mu = (T)sp.mu, relax = (T)sp.relax;
+#define NBGS_SWEEP_CASE(B, C)                                                                                      \
+    if (t.block == B && t.cpt == C) {                                                                              \
+        if (t.nontemporal)                                                                                         \
+            k_sweep<T, B, C, true><<<grid, B, 0, s>>>(sv, begin, end, nb, vel, mu, relax, partials, ctrl,          \
+                                                      t.xcd_remap);                                               \
+        else                                                                                                       \
+            k_sweep<T, B, C, false><<<grid, B, 0, s>>>(sv, begin, end, nb, vel, mu, relax, partials, ctrl,         \
+                                                       t.xcd_remap);                                              \
+        NBGS_HIP(hipGetLastError());                                                                               \
+        return NBGS_OK;                                                                                            \
+    }
+    NBGS_SWEEP_CASE(64, 1)
+    NBGS_SWEEP_CASE(64, 2)
+    NBGS_SWEEP_CASE(64, 4)
+    NBGS_SWEEP_CASE(128, 1)
+    NBGS_SWEEP_CASE(128, 2)
+    NBGS_SWEEP_CASE(128, 4)
+    NBGS_SWEEP_CASE(256, 1)
+    NBGS_SWEEP_CASE(256, 2)
+    NBGS_SWEEP_CASE(256, 4)
+    NBGS_SWEEP_CASE(512, 1)
+    NBGS_SWEEP_CASE(512, 2)
+    NBGS_SWEEP_CASE(512, 4)
+#undef NBGS_SWEEP_CASE
+    set_error("unsupported sweep tuning block=%d cpt=%d", t.block, t.cpt);
+    return NBGS_ERR_INVALID_ARG;
 }
 
 nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl, double *hist,
@@ -392,7 +477,7 @@ nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, doub
     template nbgs_status launch_init_bodies<T>(const BodiesView &, const double[3], double, T *, hipStream_t);    \
     template nbgs_status launch_warm_scatter<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, hipStream_t);      \
     template nbgs_status launch_sweep_colour<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, SweepParams,       \
-                                                double *, const int32_t *, hipStream_t);                          \
+                                                const SweepTune &, double *, const int32_t *, hipStream_t);       \
     template nbgs_status launch_integrate<T>(const BodiesView &, const Grid &, double, const T *, hipStream_t);   \
     template nbgs_status launch_save_impulses<T>(SweepView<T>, int64_t, ContactsView, hipStream_t);              \
     template nbgs_status launch_export_accumulators<T>(const T *, int32_t, double *, double *, hipStream_t);

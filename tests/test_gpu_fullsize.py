@@ -1,0 +1,143 @@
+"""Full-size parity at the benchmark workloads, in the benchmark's launch configuration.
+
+At 10^6 to 1.7 x 10^7 bodies the oracle cannot redo a whole step, so:
+  * detection is checked on sampled bodies, whose contact lists the oracle
+    computes one by one (each body against every other body and wall) --
+    bit-exact keys, normals and signed distances;
+  * colouring is checked for validity on every contact and for the greedy
+    property (each smaller colour is held by a higher-priority neighbour, no
+    higher-priority neighbour holds the same one) on sampled contacts;
+  * the solve is checked through properties that hold at any size: every
+    impulse lies in its friction cone with P_n >= 0, and the change of total
+    linear momentum equals gravity plus the wall impulses (sphere-sphere
+    impulses cancel, eq. (wrench));
+  * integration is checked as x_new = wrap(x_old + dt v_new), |q| = 1.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _nb():
+    import paper_1501_05810_amd as nb
+
+    return nb
+
+
+def _sampled_detection(sc, c, samples, rng):
+    held, structs = oracle.body_structs(sc)
+    order = np.argsort(np.concatenate([c["j1"], c["j2"]]), kind="stable")
+    ends = np.concatenate([c["j1"], c["j2"]])[order]
+    idx = np.concatenate([np.arange(len(c["j1"])), np.arange(len(c["j1"]))])[order]
+    for i in rng.choice(sc.n, size=samples, replace=False):
+        ref = oracle.detect_body(sc, int(i), held, structs)
+        lo, hi = np.searchsorted(ends, i, "left"), np.searchsorted(ends, i, "right")
+        mine = np.sort(idx[lo:hi])
+        assert np.array_equal(c["key"][mine], ref["key"]), f"body {i}"
+        assert np.array_equal(c["n"][mine], ref["n"]), f"body {i}"
+        assert np.array_equal(c["xi"][mine], ref["xi"]), f"body {i}"
+
+
+def _colouring_valid(sc, c):
+    col = c["colour"].astype(np.int64)
+    assert col.min() >= 0
+    dyn1 = sc.inv_mass[c["j1"]] > 0
+    j2 = c["j2"]
+    sph2 = j2 < sc.n
+    dyn2 = np.zeros_like(sph2)
+    dyn2[sph2] = sc.inv_mass[j2[sph2]] > 0
+    pairs = np.concatenate([col[dyn1] * sc.n + c["j1"][dyn1], col[dyn2] * sc.n + j2[dyn2]])
+    assert np.unique(pairs).size == pairs.size, "two contacts of one colour share a dynamic body"
+
+
+def _greedy_sampled(sc, c, seed, samples, rng):
+    key = c["key"]
+    for j in rng.choice(len(key), size=samples, replace=False):
+        ends = [b for b in (int(c["j1"][j]), int(c["j2"][j])) if b < sc.n and sc.inv_mass[b] > 0]
+        nbr = np.zeros(len(key), bool)
+        for b in ends:
+            nbr |= (c["j1"] == b) | (c["j2"] == b)
+        nbr[j] = False
+        pj = oracle.splitmix64(int(key[j]) ^ seed)
+        higher = [l for l in np.nonzero(nbr)[0]
+                  if (oracle.splitmix64(int(key[l]) ^ seed), -int(key[l])) > (pj, -int(key[j]))]
+        hcols = {int(c["colour"][l]) for l in higher}
+        assert int(c["colour"][j]) not in hcols
+        assert set(range(int(c["colour"][j]))) <= hcols
+
+
+def _solve_properties(sc, g, c, before_vel):
+    P = c["P"]
+    n = c["n"]
+    Pn = np.einsum("ij,ij->i", n, P)
+    Pt = P - Pn[:, None] * n
+    scale = np.abs(P).max()
+    assert Pn.min() >= -1e-12 * scale
+    assert np.all(np.linalg.norm(Pt, axis=1) <= sc.mu * Pn * (1 + 1e-9) + 1e-12 * scale)
+    v, _ = g.accumulators()
+    m = np.where(sc.inv_mass > 0, 1.0 / np.where(sc.inv_mass > 0, sc.inv_mass, 1.0), 0.0)
+    dp = (m[:, None] * (v - before_vel)).sum(0)
+    wall = c["j2"] >= sc.n
+    want = sc.dt * np.asarray(sc.gravity) * m.sum() + P[wall].sum(0)
+    ref = (m[:, None] * np.abs(v - before_vel)).sum() + 1e-300
+    assert np.abs(dp - want).max() <= 1e-9 * ref, (dp, want)
+
+
+def _integration_properties(sc, before, after):
+    x = before["pos"] + sc.dt * after["vel"]
+    for a in range(3):
+        if sc.periodic[a]:
+            L = sc.hi[a] - sc.lo[a]
+            x[:, a] = np.where(x[:, a] >= sc.hi[a], x[:, a] - L, np.where(x[:, a] < sc.lo[a], x[:, a] + L, x[:, a]))
+    assert np.array_equal(after["pos"], x)
+    assert np.abs(np.linalg.norm(after["quat"], axis=1) - 1).max() < 1e-14
+
+
+@pytest.mark.skipif(not os.path.exists(sg.DENSE_TILE), reason="dense tile not generated")
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_packing_1m(precision):
+    nb = _nb()
+    sc = sg.dense_packing(tiles=10)
+    assert sc.n == 1_000_000
+    g = nb.GpuScene(sc.copy(), precision=precision)
+    rng = np.random.default_rng(1)
+    st = g.detect()
+    c = g.contacts()
+    assert st["n_contacts"] == len(c["key"]) and st["n_contacts"] > 2 * sc.n
+    if precision == "fp64":
+        _sampled_detection(sc, c, 60, rng)
+        _colouring_valid(sc, c)
+        _greedy_sampled(sc, c, sc.colour_seed, 20, rng)
+    before = g.state()
+    g.solve(50)
+    c = g.contacts()
+    _solve_properties(sc, g, c, before["vel"] + sc.dt * np.asarray(sc.gravity) * 0.0)
+    g.integrate()
+    _integration_properties(sc, before, g.state())
+    g.close()
+
+
+def test_dilute_gas_16m():
+    nb = _nb()
+    sc = sg.dilute_gas()
+    assert sc.n == 16_777_216
+    g = nb.GpuScene(sc.copy())
+    rng = np.random.default_rng(3)
+    st = g.detect()
+    c = g.contacts()
+    assert st["n_contacts"] == len(c["key"])
+    _sampled_detection(sc, c, 12, rng)
+    _colouring_valid(sc, c)
+    before = g.state()
+    g.solve(10)
+    c = g.contacts()
+    _solve_properties(sc, g, c, before["vel"])
+    g.integrate()
+    _integration_properties(sc, before, g.state())
+    g.close()

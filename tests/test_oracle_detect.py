@@ -231,3 +231,15 @@ def test_sweep_order_is_colour_then_key():
         kk = v["key"][order][col == c]
         assert np.all(np.diff(kk.view(np.int64)) > 0)
     assert sorted(order.tolist()) == list(range(v["n_contacts"]))
+
+
+@pytest.mark.parametrize("seed,periodic", [(0, (False, False, False)), (2, (True, True, True))])
+def test_detect_body_matches_full_list(seed, periodic):
+    sc = sg.random_cluster(seed, 120, box=6.0, periodic=periodic, overlap=0.1)
+    full = oracle.detect(sc, "brute")
+    held, structs = oracle.body_structs(sc)
+    for i in range(0, sc.n, 7):
+        one = oracle.detect_body(sc, i, held, structs)
+        mask = (full["j1"] == i) | (full["j2"] == i)
+        for k in ("j1", "j2", "key", "xi", "a1", "a2", "n"):
+            np.testing.assert_array_equal(one[k], full[k][mask])
