@@ -318,3 +318,79 @@ class World:
         hist = arr(v.residual_hist, int(v.sweeps), np.float64) if v.residual_hist else np.zeros(0)
         out["residual_hist"] = hist
         return out
+
+
+# ------------------------------------------------------------- learned warm start
+
+MLP_NF, MLP_NH, MLP_NO = 12, 128, 3
+
+
+def mlp_param_count() -> int:
+    return int(lib().nbgs_ref_mlp_param_count())
+
+
+def _c(a, dt=np.float64):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def mlp_forward(w: np.ndarray, x: np.ndarray) -> np.ndarray:
+    w, x = _c(w), _c(x)
+    n = x.shape[0]
+    y = np.zeros((n, MLP_NO))
+    lib().nbgs_ref_mlp_forward(_ptr(w), C.c_int64(n), _ptr(x), _ptr(y))
+    return y
+
+
+def mlp_loss_grad(w: np.ndarray, x: np.ndarray, t: np.ndarray):
+    w, x, t = _c(w), _c(x), _c(t)
+    g = np.zeros(mlp_param_count())
+    f = lib().nbgs_ref_mlp_loss_grad
+    f.restype = C.c_double
+    loss = f(_ptr(w), C.c_int64(x.shape[0]), _ptr(x), _ptr(t), _ptr(g))
+    return float(loss), g
+
+
+def mlp_adam(w, g, m, v, k, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam step k (>= 1) on float64 arrays."""
+    lib().nbgs_ref_mlp_adam(_ptr(w), _ptr(_c(g)), _ptr(m), _ptr(v), C.c_int64(k), C.c_double(lr),
+                            C.c_double(beta1), C.c_double(beta2), C.c_double(eps))
+
+
+def mlp_features(sc, contacts: Dict[str, np.ndarray], P0: np.ndarray, vs: float, ms: float, rs: float):
+    """Features (n x 12) and frames (n x 9) of the contacts of scene sc at the start of a step."""
+    nc = int(contacts["j1"].shape[0])
+    feat = np.zeros((max(nc, 1), MLP_NF))
+    frame = np.zeros((max(nc, 1), 9))
+    n = _c(contacts["n"])
+    cols = [_c(sc.vel[:, 0]), _c(sc.vel[:, 1]), _c(sc.vel[:, 2]), _c(sc.angvel[:, 0]), _c(sc.angvel[:, 1]),
+            _c(sc.angvel[:, 2]), _c(sc.radius), _c(sc.inv_mass), _c(sc.inv_inertia)]
+    g = _c(sc.gravity)
+    j1, j2 = _c(contacts["j1"], np.int32), _c(contacts["j2"], np.int32)
+    nx, ny, nz = _c(n[:, 0]), _c(n[:, 1]), _c(n[:, 2])
+    xi, a1, a2 = _c(contacts["xi"]), _c(contacts["a1"]), _c(contacts["a2"])
+    P0 = _c(P0).reshape(-1, 3)
+    px, py, pz = _c(P0[:, 0]), _c(P0[:, 1]), _c(P0[:, 2])
+    lib().nbgs_ref_mlp_features(C.c_int64(sc.n), *[_ptr(c) for c in cols], _ptr(g), C.c_double(sc.dt),
+                                C.c_double(sc.mu), C.c_double(sc.erp), C.c_int64(nc), _ptr(j1, _i32p),
+                                _ptr(j2, _i32p), _ptr(nx), _ptr(ny), _ptr(nz), _ptr(xi), _ptr(a1), _ptr(a2),
+                                _ptr(px), _ptr(py), _ptr(pz), C.c_double(vs), C.c_double(ms), C.c_double(rs),
+                                _ptr(feat), _ptr(frame))
+    return feat[:nc].copy(), frame[:nc].copy()
+
+
+def mlp_decode(y: np.ndarray, frame: np.ndarray, ms: float, vs: float, mu: float) -> np.ndarray:
+    y, frame = _c(y), _c(frame)
+    nc = y.shape[0]
+    out = [np.zeros(max(nc, 1)) for _ in range(3)]
+    lib().nbgs_ref_mlp_decode(C.c_int64(nc), _ptr(y), _ptr(frame), C.c_double(ms), C.c_double(vs), C.c_double(mu),
+                              *[_ptr(o) for o in out])
+    return np.stack([o[:nc] for o in out], axis=1)
+
+
+def mlp_targets(frame: np.ndarray, P: np.ndarray, ms: float, vs: float) -> np.ndarray:
+    frame, P = _c(frame), _c(P).reshape(-1, 3)
+    nc = P.shape[0]
+    t = np.zeros((max(nc, 1), 3))
+    lib().nbgs_ref_mlp_targets(C.c_int64(nc), _ptr(frame), _ptr(_c(P[:, 0])), _ptr(_c(P[:, 1])),
+                               _ptr(_c(P[:, 2])), C.c_double(ms), C.c_double(vs), _ptr(t))
+    return t[:nc].copy()

@@ -12,9 +12,9 @@ step (no warm start: impulses of impacts are never re-applied).
            injected), 600 steps: the last rattlers come to rest.
 The column carries its weight through contacts that the fixed sweep counts do
 not fully converge, so neighbours overlap slightly.  The overlaps are then
-removed geometrically: repeatedly, every pair with signed distance xi < 0 is
-pushed apart by -xi/2 along its normal (a wall contact by -xi), the pushes of
-one pass summed per body and applied with factor 0.6, until min xi > -1e-7.
+removed geometrically: in passes over the overlapping pairs, ordered by the
+height of the lower body, the upper body is moved out along the pair normal by
+the current overlap (a wall contact moves its sphere up), until min xi > -1e-7.
 Velocities are zero in the stored tile.  Replicating the tile 10 x 10 gives
 the 1,000,000-sphere packing.
 
@@ -59,32 +59,65 @@ def settle(seed=2, n=10_000, footprint=10.0, log=print):
     return sc
 
 
-def remove_overlaps(sc, tol=1e-7, factor=0.6, max_passes=5000, log=print):
-    """Push overlapping neighbours apart until every signed distance is above -tol."""
+def remove_overlaps(sc, tol=1e-7, max_passes=400, log=print):
+    """Push overlapping neighbours apart until every signed distance is above -tol.
+
+    One pass visits the overlapping pairs in order of the lower body's height
+    and moves the upper body out along the pair normal by the current overlap
+    (a wall contact moves its sphere along the wall normal), so the expansion
+    of a compressed column travels bottom-up within a pass.
+    """
     sc.vel[:] = 0.0
     sc.angvel[:] = 0.0
+    L = [sc.hi[a] - sc.lo[a] for a in range(3)]
+    per = [bool(p) for p in sc.periodic]
+    lo = list(sc.lo)
+    r = sc.radius.tolist()
     for it in range(max_passes):
         c = oracle.detect(sc, "grid")
         xi = c["xi"]
-        bad = xi < 0.0
-        if not bad.any() or xi.min() > -tol:
-            log(f"overlap removal: {it} passes, min xi {xi.min():.3e}")
+        if xi.size == 0 or xi.min() > -tol:
+            log(f"overlap removal: {it} passes, min xi {xi.min() if xi.size else 0.0:.3e}")
             return sc
-        j1, j2, n = c["j1"][bad], c["j2"][bad], c["n"][bad]
-        depth = -xi[bad]
-        disp = np.zeros_like(sc.pos)
-        wall = j2 >= sc.n
-        sph = ~wall
-        np.add.at(disp, j1[sph], 0.5 * depth[sph, None] * n[sph])
-        np.add.at(disp, j2[sph], -0.5 * depth[sph, None] * n[sph])
-        np.add.at(disp, j1[wall], depth[wall, None] * n[wall])
-        sc.pos += factor * disp
+        bad = np.nonzero(xi < -0.5 * tol)[0]
+        j1, j2 = c["j1"][bad], c["j2"][bad]
+        z = sc.pos[:, 2]
+        zlow = np.where(j2 >= sc.n, z[j1], np.minimum(z[j1], z[np.minimum(j2, sc.n - 1)]))
+        pos = sc.pos.tolist()
+        for q in np.argsort(zlow, kind="stable"):
+            i, k = int(j1[q]), int(j2[q])
+            if k >= sc.n:
+                pt, nm = sc.planes[k - sc.n]
+                s = sum(nm[a] * (pos[i][a] - pt[a]) for a in range(3))
+                gap = s - r[i]
+                if gap < 0.0:
+                    for a in range(3):
+                        pos[i][a] -= gap * nm[a]
+                continue
+            d = [pos[i][a] - pos[k][a] for a in range(3)]
+            for a in range(3):
+                if per[a]:
+                    if d[a] > 0.5 * L[a]:
+                        d[a] -= L[a]
+                    elif d[a] < -0.5 * L[a]:
+                        d[a] += L[a]
+            dist = (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) ** 0.5
+            gap = dist - r[i] - r[k]
+            if gap >= 0.0 or dist == 0.0:
+                continue
+            u = [d[a] / dist for a in range(3)]  # from k towards i
+            if pos[i][2] >= pos[k][2]:
+                for a in range(3):
+                    pos[i][a] -= gap * u[a]
+            else:
+                for a in range(3):
+                    pos[k][a] += gap * u[a]
+        sc.pos[:] = np.asarray(pos)
         for a in range(3):
-            if sc.periodic[a]:
-                L = sc.hi[a] - sc.lo[a]
-                sc.pos[:, a] = sc.lo[a] + np.mod(sc.pos[:, a] - sc.lo[a], L)
-        if it % 50 == 0:
-            log(f"overlap removal pass {it}: {int(bad.sum())} overlapping pairs, min xi {xi.min():.3e}")
+            if per[a]:
+                sc.pos[:, a] = lo[a] + np.mod(sc.pos[:, a] - lo[a], L[a])
+        if it % 5 == 0:
+            log(f"overlap removal pass {it}: {bad.size} overlapping pairs, min xi {xi.min():.3e}")
     raise RuntimeError("overlap removal did not converge")
 
 
@@ -92,9 +125,18 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=scenes.DENSE_TILE)
     ap.add_argument("--n", type=int, default=10_000)
+    ap.add_argument("--settled-cache", default=None, help="npz of the settled state (written if missing)")
     a = ap.parse_args()
     say = lambda m: print(m, flush=True)  # noqa: E731
-    sc = settle(n=a.n, log=say)
+    if a.settled_cache and os.path.exists(a.settled_cache):
+        sc = scenes.settling_column(2, footprint=10.0, n=a.n, spacing=1.12, dt=2e-3, mu=0.5, tau=0.005)
+        with np.load(a.settled_cache) as z:
+            sc.pos[:] = z["pos"]
+        say(f"settled state from {a.settled_cache}")
+    else:
+        sc = settle(n=a.n, log=say)
+        if a.settled_cache:
+            np.savez(a.settled_cache, pos=sc.pos)
     sc = remove_overlaps(sc, log=say)
     c = oracle.detect(sc, "grid")
     height = float((sc.pos[:, 2] + sc.radius).max())
