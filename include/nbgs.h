@@ -243,6 +243,47 @@ nbgs_status nbgs_set_profiling(nbgs_scene_t scene, int32_t enable);
 /* Copy the accumulated profile into *out [host]. */
 nbgs_status nbgs_get_profile(nbgs_scene_t scene, nbgs_profile *out);
 
+/* ------------------------------------------------ learned warm start (MLP)
+ *
+ * A 12-128-128-3 ReLU network that predicts each contact's impulse at the
+ * start of a step from local features (the initial solution of Alg. 1 may be
+ * any guess, Sect. 5).  BF16 matrix-core inference and training with FP32
+ * accumulation and FP32 master weights.  Weight vector layout (18,563 floats):
+ * W1[12][128], b1[128], W2[128][128], b2[128], W3[128][3], b3[3], layer
+ * y = x W + b, ReLU after the first two layers. */
+typedef struct nbgs_mlp_s *nbgs_mlp_t;
+
+/* Number of weights (18,563). */
+int32_t nbgs_mlp_param_count(void);
+
+/* Create a network with deterministic initial weights (He-uniform hidden
+ * layers, output layer scaled by 0.1, zero biases; uniforms from
+ * splitmix64(seed + index)).  hip_stream as for scenes. */
+nbgs_status nbgs_mlp_create(uint64_t seed, void *hip_stream, nbgs_mlp_t *out);
+nbgs_status nbgs_mlp_destroy(nbgs_mlp_t mlp);
+
+/* Replace / read the FP32 master weights ([host], 18,563 floats).  Setting
+ * weights resets the Adam state. */
+nbgs_status nbgs_mlp_set_weights(nbgs_mlp_t mlp, const float *weights);
+nbgs_status nbgs_mlp_get_weights(nbgs_mlp_t mlp, float *weights);
+
+/* out[n][3] = network(feat[n][12]); [device] row-major FP32.  Features and
+ * hidden activations are rounded to BF16 for the matrix cores. */
+nbgs_status nbgs_mlp_forward(nbgs_mlp_t mlp, const float *feat, int64_t n, float *out);
+
+/* Gradient of L = 1/(2n) sum |out - target|^2 over the n samples into grad
+ * [device, 18,563 floats, may be NULL]; *loss [host, may be NULL] = L.
+ * Deterministic (fixed reduction order). */
+nbgs_status nbgs_mlp_loss_grad(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n, float *grad,
+                               double *loss);
+
+/* Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) over `epochs` passes of
+ * minibatches of `batch` samples drawn in a splitmix64 Fisher-Yates order
+ * from shuffle_seed; feat [device n x 12], target [device n x 3].
+ * *final_loss [host, may be NULL] = mean L over the last epoch. */
+nbgs_status nbgs_mlp_train(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n, int32_t epochs,
+                           int32_t batch, float lr, uint64_t shuffle_seed, double *final_loss);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,6 +90,15 @@ _SIGNATURES = [
     ("nbgs_get_residuals", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("nbgs_set_warm_start", C.c_int, [_vp, C.c_int64, _vp, _vp]),
     ("nbgs_get_phase_times", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
+    ("nbgs_mlp_param_count", C.c_int32, []),
+    ("nbgs_mlp_create", C.c_int, [C.c_uint64, _vp, C.POINTER(_vp)]),
+    ("nbgs_mlp_destroy", C.c_int, [_vp]),
+    ("nbgs_mlp_set_weights", C.c_int, [_vp, C.POINTER(C.c_float)]),
+    ("nbgs_mlp_get_weights", C.c_int, [_vp, C.POINTER(C.c_float)]),
+    ("nbgs_mlp_forward", C.c_int, [_vp, _vp, C.c_int64, _vp]),
+    ("nbgs_mlp_loss_grad", C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, C.POINTER(C.c_double)]),
+    ("nbgs_mlp_train", C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
+                                 C.POINTER(C.c_double)]),
     ("nbgs_set_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
     ("nbgs_get_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
     ("nbgs_set_profiling", C.c_int, [_vp, C.c_int32]),
@@ -224,6 +233,97 @@ def nbgs_get_profile(h: int) -> Dict:
     _check(lib().nbgs_get_profile(_vp(h), C.byref(p)))
     return dict(sweep_kernel_ms=p.sweep_kernel_ms, sweep_launches=int(p.sweep_launches), sweep_bytes=p.sweep_bytes,
                 contact_updates=int(p.contact_updates))
+
+
+def nbgs_mlp_param_count() -> int:
+    return int(lib().nbgs_mlp_param_count())
+
+
+def nbgs_mlp_create(seed: int = 0, stream: int = 0) -> int:
+    h = _vp()
+    _check(lib().nbgs_mlp_create(C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _vp(stream), C.byref(h)))
+    return h.value
+
+
+def nbgs_mlp_destroy(h: int) -> None:
+    _check(lib().nbgs_mlp_destroy(_vp(h)))
+
+
+def nbgs_mlp_set_weights(h: int, w: np.ndarray) -> None:
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _check(lib().nbgs_mlp_set_weights(_vp(h), w.ctypes.data_as(C.POINTER(C.c_float))))
+
+
+def nbgs_mlp_get_weights(h: int) -> np.ndarray:
+    w = np.zeros(nbgs_mlp_param_count(), dtype=np.float32)
+    _check(lib().nbgs_mlp_get_weights(_vp(h), w.ctypes.data_as(C.POINTER(C.c_float))))
+    return w
+
+
+def nbgs_mlp_forward(h: int, feat_ptr: int, n: int, out_ptr: int) -> None:
+    _check(lib().nbgs_mlp_forward(_vp(h), _vp(feat_ptr), int(n), _vp(out_ptr)))
+
+
+def nbgs_mlp_loss_grad(h: int, feat_ptr: int, target_ptr: int, n: int, grad_ptr: int = 0) -> float:
+    loss = C.c_double()
+    _check(lib().nbgs_mlp_loss_grad(_vp(h), _vp(feat_ptr), _vp(target_ptr), int(n), _vp(grad_ptr), C.byref(loss)))
+    return float(loss.value)
+
+
+def nbgs_mlp_train(h: int, feat_ptr: int, target_ptr: int, n: int, epochs: int, batch: int, lr: float,
+                   seed: int = 0) -> float:
+    loss = C.c_double()
+    _check(lib().nbgs_mlp_train(_vp(h), _vp(feat_ptr), _vp(target_ptr), int(n), int(epochs), int(batch),
+                                C.c_float(lr), C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), C.byref(loss)))
+    return float(loss.value)
+
+
+class GpuMlp:
+    """Owner of an nbgs_mlp_t; tensors in and out are torch CUDA float32."""
+
+    def __init__(self, seed: int = 0, stream=None):
+        import torch
+
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = nbgs_mlp_create(seed, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            nbgs_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        nbgs_mlp_set_weights(self.handle, w)
+
+    def weights(self) -> np.ndarray:
+        return nbgs_mlp_get_weights(self.handle)
+
+    def forward(self, feat):
+        torch = self.torch
+        feat = feat.contiguous().float()
+        out = torch.empty((feat.shape[0], 3), dtype=torch.float32, device=feat.device)
+        nbgs_mlp_forward(self.handle, feat.data_ptr(), feat.shape[0], out.data_ptr())
+        self.stream.synchronize()
+        return out
+
+    def loss_grad(self, feat, target):
+        torch = self.torch
+        feat, target = feat.contiguous().float(), target.contiguous().float()
+        grad = torch.empty(nbgs_mlp_param_count(), dtype=torch.float32, device=feat.device)
+        loss = nbgs_mlp_loss_grad(self.handle, feat.data_ptr(), target.data_ptr(), feat.shape[0], grad.data_ptr())
+        return loss, grad
+
+    def train(self, feat, target, epochs=20, batch=4096, lr=1e-3, seed=0) -> float:
+        feat, target = feat.contiguous().float(), target.contiguous().float()
+        return nbgs_mlp_train(self.handle, feat.data_ptr(), target.data_ptr(), feat.shape[0], epochs, batch, lr,
+                              seed)
 
 
 # ------------------------------------------------------------- convenience

@@ -1,0 +1,587 @@
+// Learned warm start: a 12-128-128-3 ReLU multilayer perceptron that predicts
+// each contact's impulse at the start of a time step (any initial solution of
+// Alg. 1 is admissible, Sect. 5), run and trained with BF16 matrix cores.
+//
+// Every layer is a product [rows x K] . [K x N] computed with
+// v_mfma_f32_16x16x16_bf16 (FP32 accumulation).  Lane l of a wavefront holds,
+// for one 16x16x16 step:
+//   A (16 rows x 16 k):  row l % 16, k = 4 (l / 16) + e,  e = 0..3
+//   B (16 k x 16 cols):  col l % 16, k = 4 (l / 16) + e
+//   D (16 x 16, FP32):   col l % 16, row = 4 (l / 16) + e
+// Weights are kept as FP32 master copies and repacked after every update into
+// BF16 B-fragments (each lane reads its 4 values as one 8-byte load); the
+// transposed fragments of W2 and W3 serve the backward products.  Hidden
+// activations pass between layers through LDS in BF16.
+//
+// Weight vector layout (18,563 values): W1[12][128], b1[128], W2[128][128],
+// b2[128], W3[128][3], b3[3]; y = x W + b per layer, ReLU after layers 1, 2.
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "nbgs_internal.h"
+
+namespace nbgs {
+
+namespace {
+
+constexpr int NF = 12, NH = 128, NO = 3;
+constexpr int OFF_W1 = 0, OFF_B1 = NF * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH,
+              OFF_B3 = OFF_W3 + NH * NO, NPAR = OFF_B3 + NO;
+// fragment tables (in 4-value groups of one lane)
+constexpr int F1 = 0;                   // W1:   nt(8) x lane(64) x 4
+constexpr int F2 = F1 + 8 * 64 * 4;     // W2:   kt(8) x nt(8) x lane x 4
+constexpr int F3 = F2 + 64 * 64 * 4;    // W3:   kt(8) x lane x 4 (cols 3..15 zero)
+constexpr int G3 = F3 + 8 * 64 * 4;     // W3^T: nt(8) x lane x 4 (k 3..15 zero)
+constexpr int G2 = G3 + 8 * 64 * 4;     // W2^T: kt(8) x nt(8) x lane x 4
+constexpr int NFRAG = G2 + 64 * 64 * 4; // 38,912 BF16 values
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet).
+__device__ inline unsigned short to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float from_bf16(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ inline bf16x4 frag(const unsigned short *t, int idx4) {
+    return *reinterpret_cast<const bf16x4 *>(t + 4 * idx4);
+}
+
+__global__ void __launch_bounds__(256) k_pack(const float *w, unsigned short *fr) {
+    const int o = blockIdx.x * 256 + threadIdx.x;
+    if (o >= NFRAG) return;
+    const int e = o & 3, g = o >> 2;
+    float v = 0.0f;
+    if (o < F2) {  // W1 B-fragments: k = feature, n = hidden
+        const int lane = g & 63, nt = g >> 6;
+        const int k = 4 * (lane >> 4) + e, n = nt * 16 + (lane & 15);
+        v = k < NF ? w[OFF_W1 + k * NH + n] : 0.0f;
+    } else if (o < F3) {
+        const int h = g - F2 / 4, lane = h & 63, nt = (h >> 6) & 7, kt = h >> 9;
+        const int k = kt * 16 + 4 * (lane >> 4) + e, n = nt * 16 + (lane & 15);
+        v = w[OFF_W2 + k * NH + n];
+    } else if (o < G3) {
+        const int h = g - F3 / 4, lane = h & 63, kt = h >> 6;
+        const int k = kt * 16 + 4 * (lane >> 4) + e, n = lane & 15;
+        v = n < NO ? w[OFF_W3 + k * NO + n] : 0.0f;
+    } else if (o < G2) {  // W3^T: k = output, n = hidden
+        const int h = g - G3 / 4, lane = h & 63, nt = h >> 6;
+        const int k = 4 * (lane >> 4) + e, n = nt * 16 + (lane & 15);
+        v = k < NO ? w[OFF_W3 + n * NO + k] : 0.0f;
+    } else {  // W2^T
+        const int h = g - G2 / 4, lane = h & 63, nt = (h >> 6) & 7, kt = h >> 9;
+        const int k = kt * 16 + 4 * (lane >> 4) + e, n = nt * 16 + (lane & 15);
+        v = w[OFF_W2 + n * NH + k];
+    }
+    fr[o] = to_bf16(v);
+}
+
+// Rows of LDS tiles are padded by 4 BF16 values to spread banks.
+constexpr int HS = NH + 4;  // hidden row stride
+constexpr int XS = 16 + 4;  // feature / output row stride
+
+// Forward of the 16-row tile at LDS rows r0..r0+15 of x (BF16, XS stride):
+// h1, h2 (BF16, HS stride) receive the post-ReLU activations, the return
+// value the output pre-activation in D layout (cols 0..2 valid).
+__device__ inline f32x4 forward_tile(const unsigned short *fr, const float *w, const unsigned short *x,
+                                     unsigned short *h1, unsigned short *h2, int r0, int lane) {
+    const int r = lane & 15, kq = lane >> 4;
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x4 a;
+    for (int e = 0; e < 4; ++e) a[e] = (short)x[(r0 + r) * XS + 4 * kq + e];
+    for (int nt = 0; nt < 8; ++nt) {
+        const f32x4 d = mfma(a, frag(fr, F1 / 4 + nt * 64 + lane), zero);
+        const int col = nt * 16 + (lane & 15);
+        const float b = w[OFF_B1 + col];
+        for (int e = 0; e < 4; ++e) {
+            const float v = d[e] + b;
+            h1[(r0 + 4 * kq + e) * HS + col] = to_bf16(v > 0.0f ? v : 0.0f);
+        }
+    }
+    __syncthreads();  // every wave of the block calls this in lockstep
+    f32x4 acc[8];
+    for (int nt = 0; nt < 8; ++nt) acc[nt] = zero;
+    for (int kt = 0; kt < 8; ++kt) {
+        const bf16x4 a2 = *reinterpret_cast<const bf16x4 *>(h1 + (r0 + r) * HS + kt * 16 + 4 * kq);
+        for (int nt = 0; nt < 8; ++nt) acc[nt] = mfma(a2, frag(fr, F2 / 4 + (kt * 8 + nt) * 64 + lane), acc[nt]);
+    }
+    for (int nt = 0; nt < 8; ++nt) {
+        const int col = nt * 16 + (lane & 15);
+        const float b = w[OFF_B2 + col];
+        for (int e = 0; e < 4; ++e) {
+            const float v = acc[nt][e] + b;
+            h2[(r0 + 4 * kq + e) * HS + col] = to_bf16(v > 0.0f ? v : 0.0f);
+        }
+    }
+    __syncthreads();
+    f32x4 y = zero;
+    for (int kt = 0; kt < 8; ++kt) {
+        const bf16x4 a3 = *reinterpret_cast<const bf16x4 *>(h2 + (r0 + r) * HS + kt * 16 + 4 * kq);
+        y = mfma(a3, frag(fr, F3 / 4 + kt * 64 + lane), y);
+    }
+    return y;
+}
+
+// Inference: y[n][3] = MLP(x[n][12]); a block of 4 waves handles 64 rows.
+__global__ void __launch_bounds__(256) k_forward(const unsigned short *fr, const float *w, const float *x, int64_t n,
+                                                 float *y) {
+    __shared__ unsigned short xs[64 * XS];
+    __shared__ unsigned short h1[64 * HS];
+    __shared__ unsigned short h2[64 * HS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t tiles = (n + 63) / 64;
+    for (int64_t bt = blockIdx.x; bt < tiles; bt += gridDim.x) {
+        for (int q = threadIdx.x; q < 64 * 16; q += 256) {
+            const int row = q >> 4, k = q & 15;
+            const int64_t s = bt * 64 + row;
+            xs[row * XS + k] = to_bf16((s < n && k < NF) ? x[s * NF + k] : 0.0f);
+        }
+        __syncthreads();
+        const f32x4 d = forward_tile(fr, w, xs, h1, h2, wave * 16, lane);
+        const int col = lane & 15, kq = lane >> 4;
+        if (col < NO)
+            for (int e = 0; e < 4; ++e) {
+                const int64_t s = bt * 64 + wave * 16 + 4 * kq + e;
+                if (s < n) y[s * NO + col] = d[e] + w[OFF_B3 + col];
+            }
+        __syncthreads();
+    }
+}
+
+// Gradient of L = 1/(2B) sum |y - t|^2 over the minibatch idx[off .. off+bsz)
+// (idx may be NULL: identity).  Block b writes its partial gradient to
+// part[b][NPAR] and its partial sum of squared errors to lpart[b].
+__global__ void __launch_bounds__(256) k_grad(const unsigned short *fr, const float *w, const float *x, const float *t,
+                                              const int32_t *idx, int64_t off, int64_t bsz, float *part,
+                                              float *lpart) {
+    __shared__ unsigned short xs[64 * XS];
+    __shared__ unsigned short h1[64 * HS];
+    __shared__ unsigned short h2[64 * HS];
+    __shared__ unsigned short dy[64 * XS];
+    __shared__ unsigned short g2[64 * HS];
+    __shared__ unsigned short g1[64 * HS];
+    __shared__ float lred[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
+    const int r = lane & 15, kq = lane >> 4;
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 aw2[16], aw1[2], aw3[2];
+    for (int q = 0; q < 16; ++q) aw2[q] = zero;
+    aw1[0] = aw1[1] = aw3[0] = aw3[1] = zero;
+    float db1 = 0.0f, db2 = 0.0f, db3 = 0.0f, loss = 0.0f;
+    const float inv_b = 1.0f / (float)bsz;
+    const int64_t tiles = (bsz + 63) / 64;
+    for (int64_t bt = blockIdx.x; bt < tiles; bt += gridDim.x) {
+        for (int q = tid; q < 64 * 16; q += 256) {
+            const int row = q >> 4, k = q & 15;
+            const int64_t pos = bt * 64 + row;
+            float v = 0.0f;
+            if (pos < bsz && k < NF) {
+                const int64_t s = idx ? (int64_t)idx[off + pos] : off + pos;
+                v = x[s * NF + k];
+            }
+            xs[row * XS + k] = to_bf16(v);
+        }
+        __syncthreads();
+        // forward of this wave's 16 rows; dY = (y - t) / B
+        const f32x4 d = forward_tile(fr, w, xs, h1, h2, wave * 16, lane);
+        {
+            const int col = lane & 15;
+            for (int e = 0; e < 4; ++e) {
+                const int row = wave * 16 + 4 * kq + e;
+                const int64_t pos = bt * 64 + row;
+                float g = 0.0f;
+                if (col < NO && pos < bsz) {
+                    const int64_t s = idx ? (int64_t)idx[off + pos] : off + pos;
+                    const float err = d[e] + w[OFF_B3 + col] - t[s * NO + col];
+                    loss += err * err;
+                    g = err * inv_b;
+                }
+                dy[row * XS + col] = to_bf16(g);
+            }
+        }
+        __syncthreads();
+        // dH2 = (dY W3^T) * [h2 > 0]
+        {
+            const bf16x4 a = *reinterpret_cast<const bf16x4 *>(dy + (wave * 16 + r) * XS + 4 * kq);
+            for (int nt = 0; nt < 8; ++nt) {
+                const f32x4 g = mfma(a, frag(fr, G3 / 4 + nt * 64 + lane), zero);
+                const int col = nt * 16 + (lane & 15);
+                for (int e = 0; e < 4; ++e) {
+                    const int row = wave * 16 + 4 * kq + e;
+                    g2[row * HS + col] = h2[row * HS + col] != 0 ? to_bf16(g[e]) : (unsigned short)0;
+                }
+            }
+        }
+        __syncthreads();
+        // dH1 = (dH2 W2^T) * [h1 > 0]
+        {
+            f32x4 acc[8];
+            for (int nt = 0; nt < 8; ++nt) acc[nt] = zero;
+            for (int kt = 0; kt < 8; ++kt) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(g2 + (wave * 16 + r) * HS + kt * 16 + 4 * kq);
+                for (int nt = 0; nt < 8; ++nt)
+                    acc[nt] = mfma(a, frag(fr, G2 / 4 + (kt * 8 + nt) * 64 + lane), acc[nt]);
+            }
+            for (int nt = 0; nt < 8; ++nt) {
+                const int col = nt * 16 + (lane & 15);
+                for (int e = 0; e < 4; ++e) {
+                    const int row = wave * 16 + 4 * kq + e;
+                    g1[row * HS + col] = h1[row * HS + col] != 0 ? to_bf16(acc[nt][e]) : (unsigned short)0;
+                }
+            }
+        }
+        __syncthreads();
+        // weight gradients over the 64 rows (K = samples, 4 steps of 16); wave w owns fixed output tiles
+        for (int kt = 0; kt < 4; ++kt) {
+            const int s0 = kt * 16 + 4 * kq;
+            // dW2 = H1^T dH2: tiles (mt = 2w, 2w+1) x (nt = 0..7)
+            for (int m = 0; m < 2; ++m) {
+                const int i = (2 * wave + m) * 16 + r;
+                bf16x4 a;
+                for (int e = 0; e < 4; ++e) a[e] = (short)h1[(s0 + e) * HS + i];
+                for (int nt = 0; nt < 8; ++nt) {
+                    bf16x4 b;
+                    for (int e = 0; e < 4; ++e) b[e] = (short)g2[(s0 + e) * HS + nt * 16 + r];
+                    aw2[m * 8 + nt] = mfma(a, b, aw2[m * 8 + nt]);
+                }
+            }
+            // dW3 = H2^T dY: tiles mt = 2w, 2w+1
+            {
+                bf16x4 b;
+                for (int e = 0; e < 4; ++e) b[e] = (short)dy[(s0 + e) * XS + r];
+                for (int m = 0; m < 2; ++m) {
+                    const int i = (2 * wave + m) * 16 + r;
+                    bf16x4 a;
+                    for (int e = 0; e < 4; ++e) a[e] = (short)h2[(s0 + e) * HS + i];
+                    aw3[m] = mfma(a, b, aw3[m]);
+                }
+            }
+            // dW1 = X^T dH1: tiles nt = 2w, 2w+1
+            {
+                bf16x4 a;
+                for (int e = 0; e < 4; ++e) a[e] = (short)xs[(s0 + e) * XS + r];
+                for (int m = 0; m < 2; ++m) {
+                    const int nt = 2 * wave + m;
+                    bf16x4 b;
+                    for (int e = 0; e < 4; ++e) b[e] = (short)g1[(s0 + e) * HS + nt * 16 + r];
+                    aw1[m] = mfma(a, b, aw1[m]);
+                }
+            }
+        }
+        // bias gradients: column sums in row order
+        if (tid < NH) {
+            float s1 = 0.0f, s2 = 0.0f;
+            for (int row = 0; row < 64; ++row) {
+                s1 += from_bf16(g1[row * HS + tid]);
+                s2 += from_bf16(g2[row * HS + tid]);
+            }
+            db1 += s1;
+            db2 += s2;
+        } else if (tid < NH + NO) {
+            float s3 = 0.0f;
+            for (int row = 0; row < 64; ++row) s3 += from_bf16(dy[row * XS + (tid - NH)]);
+            db3 += s3;
+        }
+        __syncthreads();
+    }
+    float *pg = part + (int64_t)blockIdx.x * NPAR;
+    for (int m = 0; m < 2; ++m)
+        for (int nt = 0; nt < 8; ++nt) {
+            const int j = nt * 16 + r;
+            for (int e = 0; e < 4; ++e) {
+                const int i = (2 * wave + m) * 16 + 4 * kq + e;
+                pg[OFF_W2 + i * NH + j] = aw2[m * 8 + nt][e];
+            }
+        }
+    for (int m = 0; m < 2; ++m) {
+        for (int e = 0; e < 4; ++e) {
+            const int i = (2 * wave + m) * 16 + 4 * kq + e;
+            if (r < NO) pg[OFF_W3 + i * NO + r] = aw3[m][e];
+            const int f = 4 * kq + e, j = (2 * wave + m) * 16 + r;
+            if (f < NF) pg[OFF_W1 + f * NH + j] = aw1[m][e];
+        }
+    }
+    if (tid < NH) {
+        pg[OFF_B1 + tid] = db1;
+        pg[OFF_B2 + tid] = db2;
+    } else if (tid < NH + NO) {
+        pg[OFF_B3 + tid - NH] = db3;
+    }
+    for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
+    if (lane == 0) lred[wave] = loss;
+    __syncthreads();
+    if (tid == 0) lpart[blockIdx.x] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
+}
+
+// Sum of the per-block partials in block order (deterministic).
+__global__ void __launch_bounds__(256) k_reduce(const float *part, int nblocks, float *grad) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= NPAR) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * NPAR + p];
+    grad[p] = s;
+}
+
+__global__ void __launch_bounds__(256) k_adam(float *w, const float *g, float *m, float *v, float lr, float b1,
+                                              float b2, float eps, float c1, float c2) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= NPAR) return;
+    const float gp = g[p];
+    const float mp = b1 * m[p] + (1.0f - b1) * gp;
+    const float vp = b2 * v[p] + (1.0f - b2) * gp * gp;
+    m[p] = mp;
+    v[p] = vp;
+    w[p] = w[p] - lr * (mp / c1) / (sqrtf(vp / c2) + eps);
+}
+
+}  // namespace
+
+int mlp_param_count() { return NPAR; }
+int mlp_frag_count() { return NFRAG; }
+int mlp_grad_blocks(int64_t bsz) {
+    const int64_t tiles = (bsz + 63) / 64;
+    return (int)std::min<int64_t>(tiles, 1024);
+}
+
+nbgs_status launch_mlp_pack(const float *w, unsigned short *fr, hipStream_t s) {
+    k_pack<<<(NFRAG + 255) / 256, 256, 0, s>>>(w, fr);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_mlp_forward(const unsigned short *fr, const float *w, const float *x, int64_t n, float *y,
+                               hipStream_t s) {
+    if (n <= 0) return NBGS_OK;
+    const int64_t tiles = (n + 63) / 64;
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 2048);
+    k_forward<<<grid, 256, 0, s>>>(fr, w, x, n, y);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_mlp_grad(const unsigned short *fr, const float *w, const float *x, const float *t,
+                            const int32_t *idx, int64_t off, int64_t bsz, float *part, float *lpart, float *grad,
+                            hipStream_t s) {
+    const int nb = mlp_grad_blocks(bsz);
+    k_grad<<<nb, 256, 0, s>>>(fr, w, x, t, idx, off, bsz, part, lpart);
+    NBGS_HIP(hipGetLastError());
+    k_reduce<<<(NPAR + 255) / 256, 256, 0, s>>>(part, nb, grad);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_mlp_adam(float *w, const float *g, float *m, float *v, int64_t step, float lr, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);
+    k_adam<<<(NPAR + 255) / 256, 256, 0, s>>>(w, g, m, v, lr, b1, b2, eps, c1, c2);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+}  // namespace nbgs
+
+// ------------------------------------------------------------------ C ABI
+
+struct nbgs_mlp_s {
+    hipStream_t s = nullptr;
+    nbgs::DevBuf<float> w, m, v, grad, part, lpart;
+    nbgs::DevBuf<unsigned short> fr;
+    nbgs::DevBuf<int32_t> idx;
+    int64_t step = 0;
+    float *host = nullptr;  // pinned staging
+};
+
+using namespace nbgs;
+
+namespace {
+
+// Deterministic initial weights: uniform in +-sqrt(6 / fan_in) for the two
+// hidden layers (He uniform), +-sqrt(6 / fan_in) / 10 for the output layer,
+// zero biases; the uniform numbers come from splitmix64(seed + index).
+void init_weights(uint64_t seed, std::vector<float> &w) {
+    w.assign(NPAR, 0.0f);
+    auto uni = [&](int64_t i) {
+        uint64_t z = seed + (uint64_t)i * 0x9e3779b97f4a7c15ull + 0x9e3779b97f4a7c15ull;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z = z ^ (z >> 31);
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    };
+    for (int i = 0; i < NF * NH; ++i) w[OFF_W1 + i] = (float)(uni(OFF_W1 + i) * std::sqrt(6.0 / NF));
+    for (int i = 0; i < NH * NH; ++i) w[OFF_W2 + i] = (float)(uni(OFF_W2 + i) * std::sqrt(6.0 / NH));
+    for (int i = 0; i < NH * NO; ++i) w[OFF_W3 + i] = (float)(uni(OFF_W3 + i) * std::sqrt(6.0 / NH) * 0.1);
+}
+
+nbgs_status upload(nbgs_mlp_t mlp, const float *host_w) {
+    NBGS_HIP(hipMemcpyAsync(mlp->w.p, host_w, sizeof(float) * NPAR, hipMemcpyHostToDevice, mlp->s));
+    NBGS_HIP(hipMemsetAsync(mlp->m.p, 0, sizeof(float) * NPAR, mlp->s));
+    NBGS_HIP(hipMemsetAsync(mlp->v.p, 0, sizeof(float) * NPAR, mlp->s));
+    mlp->step = 0;
+    NBGS_TRY(launch_mlp_pack(mlp->w.p, mlp->fr.p, mlp->s));
+    NBGS_HIP(hipStreamSynchronize(mlp->s));
+    return NBGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nbgs_status nbgs_mlp_create(uint64_t seed, void *hip_stream, nbgs_mlp_t *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    nbgs_mlp_t mlp = new (std::nothrow) nbgs_mlp_s();
+    if (!mlp) {
+        set_error("host allocation failed");
+        return NBGS_ERR_OUT_OF_MEMORY;
+    }
+    mlp->s = (hipStream_t)hip_stream;
+    nbgs_status st = NBGS_OK;
+    for (DevBuf<float> *b : {&mlp->w, &mlp->m, &mlp->v, &mlp->grad})
+        if (st == NBGS_OK) st = b->reserve(NPAR, 1.0);
+    if (st == NBGS_OK) st = mlp->fr.reserve(NFRAG, 1.0);
+    if (st == NBGS_OK && hipHostMalloc((void **)&mlp->host, sizeof(float) * (NPAR + 64)) != hipSuccess) {
+        set_error("pinned host allocation failed");
+        st = NBGS_ERR_OUT_OF_MEMORY;
+    }
+    if (st == NBGS_OK) {
+        std::vector<float> w;
+        init_weights(seed, w);
+        std::memcpy(mlp->host, w.data(), sizeof(float) * NPAR);
+        st = upload(mlp, mlp->host);
+    }
+    if (st != NBGS_OK) {
+        nbgs_mlp_destroy(mlp);
+        return st;
+    }
+    *out = mlp;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_mlp_destroy(nbgs_mlp_t mlp) {
+    if (!mlp) return NBGS_OK;
+    (void)hipStreamSynchronize(mlp->s);
+    if (mlp->host) (void)hipHostFree(mlp->host);
+    delete mlp;
+    return NBGS_OK;
+}
+
+int32_t nbgs_mlp_param_count(void) { return NPAR; }
+
+nbgs_status nbgs_mlp_set_weights(nbgs_mlp_t mlp, const float *w) {
+    if (!mlp || !w) {
+        set_error("mlp or weights NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    std::memcpy(mlp->host, w, sizeof(float) * NPAR);
+    return upload(mlp, mlp->host);
+}
+
+nbgs_status nbgs_mlp_get_weights(nbgs_mlp_t mlp, float *w) {
+    if (!mlp || !w) {
+        set_error("mlp or weights NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    NBGS_HIP(hipMemcpyAsync(mlp->host, mlp->w.p, sizeof(float) * NPAR, hipMemcpyDeviceToHost, mlp->s));
+    NBGS_HIP(hipStreamSynchronize(mlp->s));
+    std::memcpy(w, mlp->host, sizeof(float) * NPAR);
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_mlp_forward(nbgs_mlp_t mlp, const float *feat, int64_t n, float *out) {
+    if (!mlp || n < 0 || (n > 0 && (!feat || !out))) {
+        set_error("bad arguments to nbgs_mlp_forward");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    return launch_mlp_forward(mlp->fr.p, mlp->w.p, feat, n, out, mlp->s);
+}
+
+nbgs_status nbgs_mlp_loss_grad(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n, float *grad,
+                               double *loss) {
+    if (!mlp || n < 1 || !feat || !target) {
+        set_error("bad arguments to nbgs_mlp_loss_grad");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    const int nb = mlp_grad_blocks(n);
+    NBGS_TRY(mlp->part.reserve((size_t)nb * NPAR));
+    NBGS_TRY(mlp->lpart.reserve((size_t)nb));
+    NBGS_TRY(launch_mlp_grad(mlp->fr.p, mlp->w.p, feat, target, nullptr, 0, n, mlp->part.p, mlp->lpart.p,
+                             grad ? grad : mlp->grad.p, mlp->s));
+    if (loss) {
+        std::vector<float> lp(nb);
+        NBGS_HIP(hipMemcpyAsync(mlp->host, mlp->lpart.p, sizeof(float) * std::min(nb, 64), hipMemcpyDeviceToHost,
+                                mlp->s));
+        NBGS_HIP(hipStreamSynchronize(mlp->s));
+        if (nb > 64) NBGS_HIP(hipMemcpy(lp.data(), mlp->lpart.p, sizeof(float) * nb, hipMemcpyDeviceToHost));
+        else std::memcpy(lp.data(), mlp->host, sizeof(float) * nb);
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += lp[b];
+        *loss = s / (2.0 * (double)n);
+    }
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_mlp_train(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n, int32_t epochs,
+                           int32_t batch, float lr, uint64_t shuffle_seed, double *final_loss) {
+    if (!mlp || n < 1 || !feat || !target || epochs < 1 || batch < 1 || !(lr > 0.0f)) {
+        set_error("bad arguments to nbgs_mlp_train");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    const int64_t bsz_max = std::min<int64_t>(batch, n);
+    const int nb = mlp_grad_blocks(bsz_max);
+    NBGS_TRY(mlp->part.reserve((size_t)nb * NPAR));
+    NBGS_TRY(mlp->lpart.reserve((size_t)nb));
+    NBGS_TRY(mlp->idx.reserve((size_t)n));
+    std::vector<int32_t> perm(n);
+    double last = 0.0;
+    for (int32_t ep = 0; ep < epochs; ++ep) {
+        // Fisher-Yates with splitmix64 draws
+        for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+        uint64_t st = shuffle_seed + 0x632be59bd9b4e019ull * (uint64_t)(ep + 1);
+        for (int64_t i = n - 1; i > 0; --i) {
+            st += 0x9e3779b97f4a7c15ull;
+            uint64_t z = st;
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+            z = z ^ (z >> 31);
+            const int64_t j = (int64_t)(z % (uint64_t)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        NBGS_HIP(hipMemcpyAsync(mlp->idx.p, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, mlp->s));
+        NBGS_HIP(hipStreamSynchronize(mlp->s));  // perm is reused next epoch
+        double ep_loss = 0.0;
+        int64_t ep_count = 0;
+        for (int64_t off = 0; off < n; off += bsz_max) {
+            const int64_t bsz = std::min<int64_t>(bsz_max, n - off);
+            NBGS_TRY(launch_mlp_grad(mlp->fr.p, mlp->w.p, feat, target, mlp->idx.p, off, bsz, mlp->part.p,
+                                     mlp->lpart.p, mlp->grad.p, mlp->s));
+            NBGS_TRY(launch_mlp_adam(mlp->w.p, mlp->grad.p, mlp->m.p, mlp->v.p, ++mlp->step, lr, mlp->s));
+            NBGS_TRY(launch_mlp_pack(mlp->w.p, mlp->fr.p, mlp->s));
+            if (ep == epochs - 1) {
+                const int nbl = mlp_grad_blocks(bsz);
+                std::vector<float> lp(nbl);
+                NBGS_HIP(hipMemcpyAsync(lp.data(), mlp->lpart.p, sizeof(float) * nbl, hipMemcpyDeviceToHost, mlp->s));
+                NBGS_HIP(hipStreamSynchronize(mlp->s));
+                for (int b = 0; b < nbl; ++b) ep_loss += lp[b];
+                ep_count += bsz;
+            }
+        }
+        if (ep == epochs - 1) last = ep_loss / (2.0 * (double)ep_count);
+    }
+    if (final_loss) *final_loss = last;
+    NBGS_HIP(hipStreamSynchronize(mlp->s));
+    return NBGS_OK;
+}
+
+}  // extern "C"

@@ -181,6 +181,18 @@ nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hi
 template <class T>
 nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, hipStream_t s);
 
+// mlp.hip
+int mlp_param_count();
+int mlp_frag_count();
+int mlp_grad_blocks(int64_t bsz);
+nbgs_status launch_mlp_pack(const float *w, unsigned short *fr, hipStream_t s);
+nbgs_status launch_mlp_forward(const unsigned short *fr, const float *w, const float *x, int64_t n, float *y,
+                               hipStream_t s);
+nbgs_status launch_mlp_grad(const unsigned short *fr, const float *w, const float *x, const float *t,
+                            const int32_t *idx, int64_t off, int64_t bsz, float *part, float *lpart, float *grad,
+                            hipStream_t s);
+nbgs_status launch_mlp_adam(float *w, const float *g, float *m, float *v, int64_t step, float lr, hipStream_t s);
+
 constexpr int kSweepBlock = 256;
 
 }  // namespace nbgs
