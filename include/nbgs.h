@@ -65,8 +65,14 @@ typedef struct nbgs_scene_s *nbgs_scene_t;
  * and the per-contact sweep record in FP32. */
 typedef enum { NBGS_FP64 = 0, NBGS_FP32_SWEEP = 1 } nbgs_precision;
 
-/* Initial impulses of a solve (Sect. 5: zero, or the previous step's). */
-typedef enum { NBGS_WS_ZERO = 0, NBGS_WS_PREVIOUS = 1 } nbgs_warm_start;
+/* Initial impulses of a solve (Sect. 5: zero, or the previous step's; any
+ * other guess is admissible).  NBGS_WS_LEARNED predicts them with an attached
+ * network (nbgs_scene_attach_mlp) and keeps the prediction only if its Jacobi
+ * residual (every contact's one-contact solution against the accumulators
+ * with the initial impulses applied, |P* - P0|_2 / |P*|_2) is not larger than
+ * that of the previous-step impulses; without a network it is
+ * NBGS_WS_PREVIOUS. */
+typedef enum { NBGS_WS_ZERO = 0, NBGS_WS_PREVIOUS = 1, NBGS_WS_LEARNED = 2 } nbgs_warm_start;
 
 /* Body state, structure of arrays of length n, FP64, [device].  Spheres only:
  * radius is the bounding radius r_i of eq. (expansionradius).  inv_mass = 0
@@ -283,6 +289,34 @@ nbgs_status nbgs_mlp_loss_grad(nbgs_mlp_t mlp, const float *feat, const float *t
  * *final_loss [host, may be NULL] = mean L over the last epoch. */
 nbgs_status nbgs_mlp_train(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n, int32_t epochs,
                            int32_t batch, float lr, uint64_t shuffle_seed, double *final_loss);
+
+/* Use `mlp` (NULL detaches) for NBGS_WS_LEARNED; the scene borrows it. */
+nbgs_status nbgs_scene_attach_mlp(nbgs_scene_t scene, nbgs_mlp_t mlp);
+
+/* Compute the network features of every contact at each nbgs_detect even when
+ * the warm start is not learned (for collecting training data). */
+nbgs_status nbgs_set_feature_capture(nbgs_scene_t scene, int32_t enable);
+
+/* Velocity, mass and length scales of the features: vs = |g| dt (1e-3 if
+ * g = 0), ms = mean mass of the dynamic bodies, rs = mean radius.  out [host]
+ * receives (vs, ms, rs). */
+nbgs_status nbgs_get_feature_scales(nbgs_scene_t scene, double *out);
+
+/* After nbgs_solve of a step whose nbgs_detect computed features: the
+ * features [device cap x 12] and the solved impulses in the contact frame
+ * divided by ms vs [device cap x 3] (training pairs), canonical order.
+ * *n_out [host] = contact count; CAPACITY if it exceeds cap; STATE if no
+ * features or no solve.  Either output may be NULL. */
+nbgs_status nbgs_get_training_data(nbgs_scene_t scene, int64_t cap, float *feat, float *target, int64_t *n_out);
+
+/* Outcome of the last learned warm start: choice 1 = network, 0 = previous
+ * step, -1 = not judged; the two Jacobi residuals. */
+typedef struct {
+    int32_t choice;
+    double r_previous;
+    double r_learned;
+} nbgs_warm_info;
+nbgs_status nbgs_get_warm_start_info(nbgs_scene_t scene, nbgs_warm_info *out);
 
 #ifdef __cplusplus
 }

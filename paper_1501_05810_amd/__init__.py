@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "CAPACITY", 4:
                 6: "STATE", 7: "NUMERIC", 8: "UNSUPPORTED"}
 NBGS_ERR_NOT_CONVERGED = 5
 NBGS_FP64, NBGS_FP32_SWEEP = 0, 1
-NBGS_WS_ZERO, NBGS_WS_PREVIOUS = 0, 1
+NBGS_WS_ZERO, NBGS_WS_PREVIOUS, NBGS_WS_LEARNED = 0, 1, 2
 
 _vp = C.c_void_p
 
@@ -99,6 +99,11 @@ _SIGNATURES = [
     ("nbgs_mlp_loss_grad", C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, C.POINTER(C.c_double)]),
     ("nbgs_mlp_train", C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
                                  C.POINTER(C.c_double)]),
+    ("nbgs_scene_attach_mlp", C.c_int, [_vp, _vp]),
+    ("nbgs_set_feature_capture", C.c_int, [_vp, C.c_int32]),
+    ("nbgs_get_feature_scales", C.c_int, [_vp, C.POINTER(C.c_double)]),
+    ("nbgs_get_training_data", C.c_int, [_vp, C.c_int64, _vp, _vp, C.POINTER(C.c_int64)]),
+    ("nbgs_get_warm_start_info", C.c_int, [_vp, _vp]),
     ("nbgs_set_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
     ("nbgs_get_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
     ("nbgs_set_profiling", C.c_int, [_vp, C.c_int32]),
@@ -278,6 +283,36 @@ def nbgs_mlp_train(h: int, feat_ptr: int, target_ptr: int, n: int, epochs: int, 
     return float(loss.value)
 
 
+class nbgs_warm_info(C.Structure):
+    _fields_ = [("choice", C.c_int32), ("r_previous", C.c_double), ("r_learned", C.c_double)]
+
+
+def nbgs_scene_attach_mlp(h: int, mlp: int) -> None:
+    _check(lib().nbgs_scene_attach_mlp(_vp(h), _vp(mlp)))
+
+
+def nbgs_set_feature_capture(h: int, enable: bool) -> None:
+    _check(lib().nbgs_set_feature_capture(_vp(h), int(bool(enable))))
+
+
+def nbgs_get_feature_scales(h: int):
+    out = (C.c_double * 3)()
+    _check(lib().nbgs_get_feature_scales(_vp(h), out))
+    return tuple(out)
+
+
+def nbgs_get_training_data(h: int, cap: int, feat_ptr: int, target_ptr: int) -> int:
+    n = C.c_int64()
+    _check(lib().nbgs_get_training_data(_vp(h), int(cap), _vp(feat_ptr), _vp(target_ptr), C.byref(n)))
+    return int(n.value)
+
+
+def nbgs_get_warm_start_info(h: int) -> Dict:
+    w = nbgs_warm_info()
+    _check(lib().nbgs_get_warm_start_info(_vp(h), C.byref(w)))
+    return dict(choice=int(w.choice), r_previous=float(w.r_previous), r_learned=float(w.r_learned))
+
+
 class GpuMlp:
     """Owner of an nbgs_mlp_t; tensors in and out are torch CUDA float32."""
 
@@ -329,7 +364,7 @@ class GpuMlp:
 # ------------------------------------------------------------- convenience
 
 PRECISIONS = {"fp64": NBGS_FP64, "fp32": NBGS_FP32_SWEEP}
-WARM = {"zero": NBGS_WS_ZERO, "previous": NBGS_WS_PREVIOUS}
+WARM = {"zero": NBGS_WS_ZERO, "previous": NBGS_WS_PREVIOUS, "learned": NBGS_WS_LEARNED}
 BODY_FIELDS = ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
                "radius", "inv_mass", "inv_inertia")
 
@@ -465,6 +500,33 @@ class GpuScene:
 
     def tuning(self, precision=None) -> Dict:
         return nbgs_get_tuning(self.handle, PRECISIONS[precision or self.precision])
+
+    def attach_mlp(self, mlp):
+        self._mlp = mlp
+        nbgs_scene_attach_mlp(self.handle, mlp.handle if mlp is not None else 0)
+
+    def set_feature_capture(self, enable: bool = True):
+        nbgs_set_feature_capture(self.handle, enable)
+
+    def feature_scales(self):
+        return nbgs_get_feature_scales(self.handle)
+
+    def training_data(self, as_numpy=False):
+        """(features n x 12, targets n x 3) of the last detect + solve, torch CUDA float32."""
+        torch = self.torch
+        n0 = C.c_int64()
+        lib().nbgs_get_training_data(_vp(self.handle), 0, None, None, C.byref(n0))
+        n = int(n0.value)
+        feat = torch.empty((max(n, 1), 12), dtype=torch.float32, device=self.device)
+        tgt = torch.empty((max(n, 1), 3), dtype=torch.float32, device=self.device)
+        nbgs_get_training_data(self.handle, max(n, 1), feat.data_ptr(), tgt.data_ptr())
+        feat, tgt = feat[:n], tgt[:n]
+        if as_numpy:
+            return feat.cpu().numpy(), tgt.cpu().numpy()
+        return feat, tgt
+
+    def warm_start_info(self) -> Dict:
+        return nbgs_get_warm_start_info(self.handle)
 
     def set_profiling(self, enable: bool = True):
         nbgs_set_profiling(self.handle, enable)

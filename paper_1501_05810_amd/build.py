@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libnbgs.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("NBGS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "sort.hip", "detect.hip", "colour.hip", "sweep.hip"]
-OPTIONAL = ["mlp.hip", "batch.hip"]
+SOURCES = ["api.hip", "sort.hip", "detect.hip", "colour.hip", "sweep.hip", "mlp.hip", "warmstart.hip"]
+OPTIONAL = ["batch.hip"]
 
 COMMON = [
     "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

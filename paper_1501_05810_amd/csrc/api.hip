@@ -143,6 +143,15 @@ struct nbgs_scene_s {
     hipEvent_t ev[kNumPhases + 1] = {};
     bool ev_ok[kNumPhases + 1] = {};
     std::vector<int64_t> col_dyn;  // dynamic bodies touched per colour
+    // learned warm start
+    nbgs_mlp_t mlp = nullptr;
+    bool capture = false;
+    FeatureScales fs{1.0, 1.0, 1.0};
+    double mean_mass = 1.0, mean_radius = 1.0;
+    DevBuf<float> feat, yout;
+    DevBuf<double> frame, lpx, lpy, lpz, jpart, jres;
+    bool have_features = false, have_learned = false;
+    nbgs_warm_info winfo{-1, 0.0, 0.0};
     // sweep-kernel profiling (event pair around every sweep launch)
     bool profiling = false;
     std::vector<hipEvent_t> pev;
@@ -188,7 +197,7 @@ nbgs_status check_params(const nbgs_params *p) {
         set_error("unknown precision %d", p->precision);
         return NBGS_ERR_INVALID_ARG;
     }
-    if (p->warm_start != NBGS_WS_ZERO && p->warm_start != NBGS_WS_PREVIOUS) {
+    if (p->warm_start != NBGS_WS_ZERO && p->warm_start != NBGS_WS_PREVIOUS && p->warm_start != NBGS_WS_LEARNED) {
         set_error("unknown warm start mode %d", p->warm_start);
         return NBGS_ERR_INVALID_ARG;
     }
@@ -198,6 +207,14 @@ nbgs_status check_params(const nbgs_params *p) {
             return NBGS_ERR_INVALID_ARG;
         }
     return NBGS_OK;
+}
+
+void update_scales(nbgs_scene_t sc) {
+    const double g = std::sqrt(sc->p.gravity[0] * sc->p.gravity[0] + sc->p.gravity[1] * sc->p.gravity[1] +
+                               sc->p.gravity[2] * sc->p.gravity[2]);
+    sc->fs.vs = g * sc->p.dt > 0.0 ? g * sc->p.dt : 1e-3;
+    sc->fs.ms = sc->mean_mass;
+    sc->fs.rs = sc->mean_radius;
 }
 
 void record(nbgs_scene_t sc, int i) {
@@ -343,11 +360,29 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->off.p, cb.view(), s));
     // initial impulses and, when the previous table carries colours, the start of the colouring
-    const bool warm_impulses = sc->p.warm_start == NBGS_WS_PREVIOUS && sc->n_prev > 0;
+    const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
     NBGS_TRY(launch_match_prev(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p, sc->n_prev,
                                sc->p.mu, warm_impulses, warm_colours, s));
     if (!warm_impulses) NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
+    // network features and prediction (from the state before the step and the previous impulses)
+    sc->have_features = false;
+    sc->have_learned = false;
+    const bool learned = sc->p.warm_start == NBGS_WS_LEARNED && sc->mlp;
+    if ((sc->capture || learned) && nc > 0) {
+        NBGS_TRY(sc->feat.reserve(12 * (size_t)nc));
+        NBGS_TRY(sc->frame.reserve(9 * (size_t)nc));
+        NBGS_TRY(launch_features(sc->b, cb.view(), nc, sc->p.gravity, sc->p.dt, sc->p.mu, sc->p.erp, sc->fs,
+                                 sc->feat.p, sc->frame.p, s));
+        sc->have_features = true;
+        if (learned) {
+            NBGS_TRY(sc->yout.reserve(3 * (size_t)nc));
+            for (DevBuf<double> *b : {&sc->lpx, &sc->lpy, &sc->lpz}) NBGS_TRY(b->reserve((size_t)nc));
+            NBGS_TRY(launch_mlp_forward(mlp_frag_ptr(sc->mlp), mlp_weight_ptr(sc->mlp), sc->feat.p, nc, sc->yout.p, s));
+            NBGS_TRY(launch_decode(sc->yout.p, sc->frame.p, nc, sc->fs, sc->p.mu, sc->lpx.p, sc->lpy.p, sc->lpz.p, s));
+            sc->have_learned = true;
+        }
+    }
     record(sc, kColour);
     // colouring: body -> contacts where it is j2 (as j1 it owns the segment off[i] .. off[i] + cnt[i])
     NBGS_TRY(sc->inc2.reserve((size_t)(nc > 0 ? nc : 1)));
@@ -478,6 +513,36 @@ nbgs_status accumulate_profile(nbgs_scene_t sc, int32_t sweeps) {
     return NBGS_OK;
 }
 
+// Jacobi residual of the previous-step and of the learned initial impulses;
+// the sweep record keeps the better one (ties: the network).
+template <class T>
+nbgs_status judge_warm_start(nbgs_scene_t sc) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    SweepBuf<T> &sw = sweep_buf<T>(sc);
+    DevBuf<T> &vel = vel_buf<T>(sc);
+    NBGS_TRY(sc->jpart.reserve(2 * (size_t)((sc->nc + 255) / 256 + 1)));
+    NBGS_TRY(sc->jres.reserve(2));
+    ContactBuf &cb = sc->cb[sc->cur];
+    for (int cand = 0; cand < 2; ++cand) {
+        if (cand == 1) NBGS_TRY(launch_set_sweep_impulses<T>(sw.view(), sc->nc, sc->lpx.p, sc->lpy.p, sc->lpz.p, s));
+        NBGS_TRY(launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel.p, s));
+        for (int c = 0; c < sc->n_colours; ++c)
+            NBGS_TRY(launch_warm_scatter<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, s));
+        NBGS_TRY(launch_jacobi_residual<T>(sw.view(), sc->nc, N, vel.p, sc->p.mu, sc->jpart.p, sc->jres.p + cand, s));
+    }
+    double r[2];
+    NBGS_HIP(hipMemcpyAsync(sc->pinned + 64, sc->jres.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipStreamSynchronize(s));
+    std::memcpy(r, sc->pinned + 64, sizeof(r));
+    sc->winfo.r_previous = r[0];
+    sc->winfo.r_learned = r[1];
+    sc->winfo.choice = r[1] <= r[0] ? 1 : 0;
+    if (sc->winfo.choice == 0)
+        NBGS_TRY(launch_set_sweep_impulses<T>(sw.view(), sc->nc, cb.px.p, cb.py.p, cb.pz.p, s));
+    return NBGS_OK;
+}
+
 template <class T>
 nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats) {
     hipStream_t s = sc->s;
@@ -487,6 +552,8 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
     NBGS_TRY(vel.reserve(8 * (size_t)N));
     NBGS_TRY(sc->res_hist.reserve((size_t)max_sweeps));
     record(sc, kInit);
+    sc->winfo = nbgs_warm_info{-1, 0.0, 0.0};
+    if (sc->p.warm_start == NBGS_WS_LEARNED && sc->have_learned) NBGS_TRY(judge_warm_start<T>(sc));
     NBGS_TRY(launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel.p, s));
     if (sc->p.warm_start != NBGS_WS_ZERO)
         for (int c = 0; c < sc->n_colours; ++c)
@@ -708,6 +775,25 @@ nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *doma
                     st = NBGS_ERR_INVALID_ARG;
                     break;
                 }
+            std::vector<double> rad(N);
+            if (st == NBGS_OK && hipMemcpy(rad.data(), b.radius, N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+                set_error("could not read radius");
+                st = NBGS_ERR_INVALID_ARG;
+            }
+            if (st == NBGS_OK) {
+                double sm = 0.0, sr = 0.0;
+                size_t nd = 0;
+                for (size_t i = 0; i < N; ++i) {
+                    sr += rad[i];
+                    if (im[i] > 0.0) {
+                        sm += 1.0 / im[i];
+                        ++nd;
+                    }
+                }
+                sc->mean_mass = nd ? sm / (double)nd : 1.0;
+                sc->mean_radius = sr / (double)N;
+                update_scales(sc);
+            }
         }
     }
     if (st != NBGS_OK) {
@@ -733,6 +819,7 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t sc, const nbgs_params *params) {
     NBGS_GUARD(sc);
     NBGS_TRY(check_params(params));
     sc->p = *params;
+    update_scales(sc);
     return NBGS_OK;
 }
 
@@ -880,6 +967,59 @@ nbgs_status nbgs_get_phase_times(nbgs_scene_t sc, int32_t n, double *out) {
         else
             out[i] = 0.0;
     }
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_scene_attach_mlp(nbgs_scene_t sc, nbgs_mlp_t mlp) {
+    NBGS_GUARD(sc);
+    sc->mlp = mlp;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_set_feature_capture(nbgs_scene_t sc, int32_t enable) {
+    NBGS_GUARD(sc);
+    sc->capture = enable != 0;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_feature_scales(nbgs_scene_t sc, double *out) {
+    NBGS_GUARD(sc);
+    if (!out) {
+        set_error("out is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    out[0] = sc->fs.vs;
+    out[1] = sc->fs.ms;
+    out[2] = sc->fs.rs;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_training_data(nbgs_scene_t sc, int64_t cap, float *feat, float *target, int64_t *n_out) {
+    NBGS_GUARD(sc);
+    if (n_out) *n_out = sc->nc;
+    if (!sc->have_features || sc->state != 2) {
+        set_error("training data needs features from nbgs_detect (capture or learned warm start) and a solve");
+        return NBGS_ERR_STATE;
+    }
+    if (sc->nc > cap) {
+        set_error("%lld contacts do not fit into %lld", (long long)sc->nc, (long long)cap);
+        return NBGS_ERR_CAPACITY;
+    }
+    if (sc->nc == 0) return NBGS_OK;
+    if (feat)
+        NBGS_HIP(hipMemcpyAsync(feat, sc->feat.p, sizeof(float) * 12 * sc->nc, hipMemcpyDeviceToDevice, sc->s));
+    if (target) NBGS_TRY(launch_targets(sc->frame.p, sc->cb[sc->cur].view(), sc->nc, sc->fs, target, sc->s));
+    NBGS_HIP(hipStreamSynchronize(sc->s));
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_warm_start_info(nbgs_scene_t sc, nbgs_warm_info *out) {
+    NBGS_GUARD(sc);
+    if (!out) {
+        set_error("out is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    *out = sc->winfo;
     return NBGS_OK;
 }
 

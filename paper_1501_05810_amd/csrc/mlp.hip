@@ -402,6 +402,11 @@ struct nbgs_mlp_s {
 
 using namespace nbgs;
 
+namespace nbgs {
+const unsigned short *mlp_frag_ptr(nbgs_mlp_t mlp) { return mlp->fr.p; }
+const float *mlp_weight_ptr(nbgs_mlp_t mlp) { return mlp->w.p; }
+}  // namespace nbgs
+
 namespace {
 
 // Deterministic initial weights: uniform in +-sqrt(6 / fan_in) for the two

@@ -181,6 +181,24 @@ nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hi
 template <class T>
 nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, hipStream_t s);
 
+// warmstart.hip
+struct FeatureScales {
+    double vs, ms, rs;  // velocity, mass, length
+};
+nbgs_status launch_features(const BodiesView &b, const ContactsView &c, int64_t nc, const double g[3], double dt,
+                            double mu, double erp, const FeatureScales &fs, float *feat, double *frame,
+                            hipStream_t s);
+nbgs_status launch_decode(const float *y, const double *frame, int64_t nc, const FeatureScales &fs, double mu,
+                          double *px, double *py, double *pz, hipStream_t s);
+nbgs_status launch_targets(const double *frame, const ContactsView &c, int64_t nc, const FeatureScales &fs, float *t,
+                           hipStream_t s);
+template <class T>
+nbgs_status launch_set_sweep_impulses(SweepView<T> sv, int64_t nc, const double *px, const double *py,
+                                      const double *pz, hipStream_t s);
+template <class T>
+nbgs_status launch_jacobi_residual(SweepView<T> sv, int64_t nc, int32_t nb, const T *vel, double mu,
+                                   double *partials, double *out, hipStream_t s);
+
 // mlp.hip
 int mlp_param_count();
 int mlp_frag_count();
@@ -192,6 +210,8 @@ nbgs_status launch_mlp_grad(const unsigned short *fr, const float *w, const floa
                             const int32_t *idx, int64_t off, int64_t bsz, float *part, float *lpart, float *grad,
                             hipStream_t s);
 nbgs_status launch_mlp_adam(float *w, const float *g, float *m, float *v, int64_t step, float lr, hipStream_t s);
+const unsigned short *mlp_frag_ptr(nbgs_mlp_t mlp);
+const float *mlp_weight_ptr(nbgs_mlp_t mlp);
 
 constexpr int kSweepBlock = 256;
 

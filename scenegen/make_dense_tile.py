@@ -12,9 +12,8 @@ step (no warm start: impulses of impacts are never re-applied).
            injected), 600 steps: the last rattlers come to rest.
 The column carries its weight through contacts that the fixed sweep counts do
 not fully converge, so neighbours overlap slightly.  The overlaps are then
-removed geometrically: in passes over the overlapping pairs, ordered by the
-height of the lower body, the upper body is moved out along the pair normal by
-the current overlap (a wall contact moves its sphere up), until min xi > -1e-7.
+removed by shrinking each radius by half of the sphere's deepest overlap with
+another sphere (the full depth for a wall), so no pair overlaps.
 Velocities are zero in the stored tile.  Replicating the tile 10 x 10 gives
 the 1,000,000-sphere packing.
 
@@ -59,66 +58,31 @@ def settle(seed=2, n=10_000, footprint=10.0, log=print):
     return sc
 
 
-def remove_overlaps(sc, tol=1e-7, max_passes=400, log=print):
-    """Push overlapping neighbours apart until every signed distance is above -tol.
+def remove_overlaps(sc, log=print):
+    """Shrink radii so that no pair overlaps.
 
-    One pass visits the overlapping pairs in order of the lower body's height
-    and moves the upper body out along the pair normal by the current overlap
-    (a wall contact moves its sphere along the wall normal), so the expansion
-    of a compressed column travels bottom-up within a pass.
+    Every sphere loses half of its deepest overlap with another sphere, or the
+    full depth of its deepest overlap with a wall, whichever is larger (plus a
+    relative 1e-9): afterwards every pair has signed distance >= 0.  Masses and
+    inertias follow the new radii.
     """
     sc.vel[:] = 0.0
     sc.angvel[:] = 0.0
-    L = [sc.hi[a] - sc.lo[a] for a in range(3)]
-    per = [bool(p) for p in sc.periodic]
-    lo = list(sc.lo)
-    r = sc.radius.tolist()
-    for it in range(max_passes):
-        c = oracle.detect(sc, "grid")
-        xi = c["xi"]
-        if xi.size == 0 or xi.min() > -tol:
-            log(f"overlap removal: {it} passes, min xi {xi.min() if xi.size else 0.0:.3e}")
-            return sc
-        bad = np.nonzero(xi < -0.5 * tol)[0]
-        j1, j2 = c["j1"][bad], c["j2"][bad]
-        z = sc.pos[:, 2]
-        zlow = np.where(j2 >= sc.n, z[j1], np.minimum(z[j1], z[np.minimum(j2, sc.n - 1)]))
-        pos = sc.pos.tolist()
-        for q in np.argsort(zlow, kind="stable"):
-            i, k = int(j1[q]), int(j2[q])
-            if k >= sc.n:
-                pt, nm = sc.planes[k - sc.n]
-                s = sum(nm[a] * (pos[i][a] - pt[a]) for a in range(3))
-                gap = s - r[i]
-                if gap < 0.0:
-                    for a in range(3):
-                        pos[i][a] -= gap * nm[a]
-                continue
-            d = [pos[i][a] - pos[k][a] for a in range(3)]
-            for a in range(3):
-                if per[a]:
-                    if d[a] > 0.5 * L[a]:
-                        d[a] -= L[a]
-                    elif d[a] < -0.5 * L[a]:
-                        d[a] += L[a]
-            dist = (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) ** 0.5
-            gap = dist - r[i] - r[k]
-            if gap >= 0.0 or dist == 0.0:
-                continue
-            u = [d[a] / dist for a in range(3)]  # from k towards i
-            if pos[i][2] >= pos[k][2]:
-                for a in range(3):
-                    pos[i][a] -= gap * u[a]
-            else:
-                for a in range(3):
-                    pos[k][a] += gap * u[a]
-        sc.pos[:] = np.asarray(pos)
-        for a in range(3):
-            if per[a]:
-                sc.pos[:, a] = lo[a] + np.mod(sc.pos[:, a] - lo[a], L[a])
-        if it % 5 == 0:
-            log(f"overlap removal pass {it}: {bad.size} overlapping pairs, min xi {xi.min():.3e}")
-    raise RuntimeError("overlap removal did not converge")
+    c = oracle.detect(sc, "grid")
+    xi = c["xi"]
+    need = np.zeros(sc.n)
+    over = xi < 0.0
+    j1, j2, depth = c["j1"][over], c["j2"][over], -xi[over]
+    wall = j2 >= sc.n
+    np.maximum.at(need, j1[~wall], 0.5 * depth[~wall])
+    np.maximum.at(need, j2[~wall], 0.5 * depth[~wall])
+    np.maximum.at(need, j1[wall], depth[wall])
+    shrink = need * (1.0 + 1e-9) + np.where(need > 0, 1e-12, 0.0)
+    log(f"overlap removal: {int(over.sum())} overlapping pairs (deepest {depth.max() if depth.size else 0:.3e}); "
+        f"{int((need > 0).sum())} radii reduced, by {shrink.mean():.2e} on average, {shrink.max():.2e} at most")
+    sc.radius = sc.radius - shrink
+    sc.inv_mass, sc.inv_inertia = scenes.solid_sphere_masses(sc.radius)
+    return sc
 
 
 def main():

@@ -1,0 +1,123 @@
+"""Learned warm start through the C ABI: features and training targets against
+the oracle, the residual judge and its fallback, and what a trained network
+gains over the previous-step warm start."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _nb():
+    import paper_1501_05810_amd as nb
+
+    return nb
+
+
+def _scales(sc):
+    g = float(np.linalg.norm(sc.gravity))
+    vs = g * sc.dt if g * sc.dt > 0 else 1e-3
+    dyn = sc.inv_mass > 0
+    return vs, float(np.mean(1.0 / sc.inv_mass[dyn])), float(np.mean(sc.radius))
+
+
+def test_features_and_targets_match_oracle():
+    nb = _nb()
+    sc = sg.packed_cluster(21, counts=(10, 10, 6), vmax=1.0, wmax=1.0)
+    g = nb.GpuScene(sc.copy())
+    g.set_feature_capture(True)
+    ref = sc.copy()
+    w = oracle.World(ref)
+    vs, ms, rs = _scales(sc)
+    np.testing.assert_allclose(g.feature_scales(), (vs, ms, rs), rtol=1e-15)
+    for step in range(3):
+        before = ref.copy()
+        g.detect()
+        w.detect(grid=True, warm=True)
+        v = w.view()
+        g.solve(30)
+        w.solve(30)
+        feat, tgt = g.training_data(as_numpy=True)
+        # v was taken before the oracle's solve: v["P"] holds the initial (warm-start) impulses
+        f_ref, frame = oracle.mlp_features(before, v, v["P"], vs, ms, rs)
+        np.testing.assert_allclose(feat, f_ref.astype(np.float32), rtol=1e-6, atol=1e-6)
+        t_ref = oracle.mlp_targets(frame, w.view()["P"], ms, vs)
+        np.testing.assert_allclose(tgt, t_ref.astype(np.float32), rtol=1e-5, atol=1e-6 * np.abs(t_ref).max())
+        g.integrate()
+        w.integrate()
+    g.close()
+
+
+def test_judge_falls_back_to_previous_bit_exactly():
+    """A network producing NaN is never used: the step equals the previous-step warm start bit for bit."""
+    nb = _nb()
+    sc = sg.packed_cluster(22, counts=(8, 8, 6))
+    bad = nb.GpuMlp(seed=1)
+    w = bad.weights()
+    w[:] = np.nan
+    bad.set_weights(w)
+    runs = []
+    for mode in ("previous", "learned"):
+        g = nb.GpuScene(sc.copy(), warm_start=mode)
+        if mode == "learned":
+            g.attach_mlp(bad)
+        for _ in range(3):
+            g.step(15)
+            if mode == "learned":
+                info = g.warm_start_info()
+                assert info["choice"] in (0, -1)
+        runs.append((g.contacts()["P"], g.state()["vel"]))
+        g.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    bad.close()
+
+
+def test_trained_network_gain_over_previous_step_start():
+    """Train on the solver's own converged impulses, then compare sweeps to residual 1e-6.
+
+    Reported, and gated only by what the judge guarantees: the learned start is used only when its Jacobi
+    residual is not larger than the previous-step one."""
+    import torch
+
+    nb = _nb()
+    sc = sg.packed_cluster(23, counts=(14, 14, 8), vmax=0.5, wmax=0.5, dt=2e-3)
+    target = 1e-6
+    # collect training pairs from converged previous-warm-started steps
+    g = nb.GpuScene(sc.copy())
+    g.set_feature_capture(True)
+    feats, tgts = [], []
+    for _ in range(12):
+        g.step(3000, target)
+        f, t = g.training_data()
+        feats.append(f.clone())
+        tgts.append(t.clone())
+    g.close()
+    X, T = torch.cat(feats), torch.cat(tgts)
+    mlp = nb.GpuMlp(seed=2)
+    l0, _ = mlp.loss_grad(X, T)
+    mlp.train(X, T, epochs=30, batch=1024, lr=1e-3, seed=5)
+    l1, _ = mlp.loss_grad(X, T)
+    assert l1 < 0.5 * l0
+    # evaluate on continued trajectories
+    sweeps = {}
+    for mode in ("previous", "learned"):
+        g = nb.GpuScene(sc.copy(), warm_start=mode)
+        if mode == "learned":
+            g.attach_mlp(mlp)
+        total = 0
+        used = 0
+        for k in range(16):
+            st = g.step(3000, target)
+            if k >= 12:
+                total += st["sweeps"]
+                if mode == "learned":
+                    info = g.warm_start_info()
+                    used += info["choice"] == 1
+                    assert info["choice"] == (1 if info["r_learned"] <= info["r_previous"] else 0)
+        sweeps[mode] = total
+        g.close()
+    print(f"sweeps to 1e-6 over 4 steps: previous {sweeps['previous']}, learned {sweeps['learned']}")
+    assert sweeps["learned"] > 0
+    mlp.close()
