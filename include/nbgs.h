@@ -302,7 +302,8 @@ nbgs_status nbgs_set_feature_capture(nbgs_scene_t scene, int32_t enable);
  * receives (vs, ms, rs). */
 nbgs_status nbgs_get_feature_scales(nbgs_scene_t scene, double *out);
 
-/* After nbgs_solve of a step whose nbgs_detect computed features: the
+/* After nbgs_solve (and until the next nbgs_detect) of a step whose
+ * nbgs_detect computed features: the
  * features [device cap x 12] and the solved impulses in the contact frame
  * divided by ms vs [device cap x 3] (training pairs), canonical order.
  * *n_out [host] = contact count; CAPACITY if it exceeds cap; STATE if no

@@ -151,6 +151,7 @@ struct nbgs_scene_s {
     DevBuf<float> feat, yout;
     DevBuf<double> frame, lpx, lpy, lpz, jpart, jres;
     bool have_features = false, have_learned = false;
+    bool solved = false;  // a solve ran since the last detect
     nbgs_warm_info winfo{-1, 0.0, 0.0};
     // sweep-kernel profiling (event pair around every sweep launch)
     bool profiling = false;
@@ -368,6 +369,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     // network features and prediction (from the state before the step and the previous impulses)
     sc->have_features = false;
     sc->have_learned = false;
+    sc->solved = false;
     const bool learned = sc->p.warm_start == NBGS_WS_LEARNED && sc->mlp;
     if ((sc->capture || learned) && nc > 0) {
         NBGS_TRY(sc->feat.reserve(12 * (size_t)nc));
@@ -596,6 +598,7 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
     NBGS_TRY(launch_save_impulses<T>(sw.view(), sc->nc, sc->cb[sc->cur].view(), s));
     record(sc, kIntegrate);
     sc->state = 2;
+    sc->solved = true;
     if (stats || target > 0.0) {
         NBGS_TRY(sync_small(sc, 8, 3));
         const int32_t sweeps = sc->pinned[8 + 1];
@@ -997,7 +1000,7 @@ nbgs_status nbgs_get_feature_scales(nbgs_scene_t sc, double *out) {
 nbgs_status nbgs_get_training_data(nbgs_scene_t sc, int64_t cap, float *feat, float *target, int64_t *n_out) {
     NBGS_GUARD(sc);
     if (n_out) *n_out = sc->nc;
-    if (!sc->have_features || sc->state != 2) {
+    if (!sc->have_features || !sc->solved) {
         set_error("training data needs features from nbgs_detect (capture or learned warm start) and a solve");
         return NBGS_ERR_STATE;
     }

@@ -72,7 +72,7 @@ def _greedy_sampled(sc, c, seed, samples, rng):
         assert set(range(int(c["colour"][j]))) <= hcols
 
 
-def _solve_properties(sc, g, c, before_vel):
+def _solve_properties(sc, g, c, before_vel, mom_tol=1e-9):
     P = c["P"]
     n = c["n"]
     Pn = np.einsum("ij,ij->i", n, P)
@@ -86,7 +86,7 @@ def _solve_properties(sc, g, c, before_vel):
     wall = c["j2"] >= sc.n
     want = sc.dt * np.asarray(sc.gravity) * m.sum() + P[wall].sum(0)
     ref = (m[:, None] * np.abs(v - before_vel)).sum() + 1e-300
-    assert np.abs(dp - want).max() <= 1e-9 * ref, (dp, want)
+    assert np.abs(dp - want).max() <= mom_tol * ref, (dp, want)
 
 
 def _integration_properties(sc, before, after):
@@ -117,7 +117,8 @@ def test_dense_packing_1m(precision):
     before = g.state()
     g.solve(50)
     c = g.contacts()
-    _solve_properties(sc, g, c, before["vel"] + sc.dt * np.asarray(sc.gravity) * 0.0)
+    # FP32 accumulators conserve momentum to FP32 round-off only
+    _solve_properties(sc, g, c, before["vel"], mom_tol=1e-9 if precision == "fp64" else 1e-5)
     g.integrate()
     _integration_properties(sc, before, g.state())
     g.close()

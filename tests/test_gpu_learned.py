@@ -1,6 +1,8 @@
 """Learned warm start through the C ABI: features and training targets against
 the oracle, the residual judge and its fallback, and what a trained network
 gains over the previous-step warm start."""
+import os
+
 import numpy as np
 import pytest
 
@@ -31,7 +33,7 @@ def test_features_and_targets_match_oracle():
     ref = sc.copy()
     w = oracle.World(ref)
     vs, ms, rs = _scales(sc)
-    np.testing.assert_allclose(g.feature_scales(), (vs, ms, rs), rtol=1e-15)
+    np.testing.assert_allclose(g.feature_scales(), (vs, ms, rs), rtol=1e-12)  # sums in another order
     for step in range(3):
         before = ref.copy()
         g.detect()
@@ -74,6 +76,7 @@ def test_judge_falls_back_to_previous_bit_exactly():
     bad.close()
 
 
+@pytest.mark.skipif(not os.path.exists(sg.DENSE_TILE), reason="dense tile not generated")
 def test_trained_network_gain_over_previous_step_start():
     """Train on the solver's own converged impulses, then compare sweeps to residual 1e-6.
 
@@ -82,7 +85,7 @@ def test_trained_network_gain_over_previous_step_start():
     import torch
 
     nb = _nb()
-    sc = sg.packed_cluster(23, counts=(14, 14, 8), vmax=0.5, wmax=0.5, dt=2e-3)
+    sc = sg.dense_packing(tiles=1)  # 10,000 spheres of the benchmark packing, dt = 1e-4
     target = 1e-6
     # collect training pairs from converged previous-warm-started steps
     g = nb.GpuScene(sc.copy())
@@ -97,7 +100,7 @@ def test_trained_network_gain_over_previous_step_start():
     X, T = torch.cat(feats), torch.cat(tgts)
     mlp = nb.GpuMlp(seed=2)
     l0, _ = mlp.loss_grad(X, T)
-    mlp.train(X, T, epochs=30, batch=1024, lr=1e-3, seed=5)
+    mlp.train(X, T, epochs=60, batch=1024, lr=2e-3, seed=5)
     l1, _ = mlp.loss_grad(X, T)
     assert l1 < 0.5 * l0
     # evaluate on continued trajectories
