@@ -3,8 +3,8 @@
 
 Workload: dense settled packing of 1,000,000 polydisperse spheres (radii
 U[0.45, 0.55], density 1), laterally periodic 100 x 100 box on a floor plane,
-solid fraction about 0.6, mu = 0.5, dt = 1e-4, gravity -9.81 z, previous-step
-warm start.  A step is one full pass of the hot path: contact detection (hull
+solid fraction about 0.6, coordination about 6, mu = 0.5, dt = 1e-4, gravity
+-9.81 z, penetration correction scaled to zero, previous-step warm start.  A step is one full pass of the hot path: contact detection (hull
 radii, cell list, pair search, narrow phase), colouring and colour-major
 ordering, accumulator init, 50 NBGS sweeps, integration.
 
@@ -67,7 +67,21 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=2000)
     ap.add_argument("--cpu-tiles", type=int, default=3, help="sample for the oracle timing (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="time the steps without per-launch events")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (to scale HBM traffic counters)")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
     a = ap.parse_args()
+
+    if a.calibrate_copy > 0:
+        import torch
+
+        src = torch.ones(a.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
 
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not part of this "
@@ -84,11 +98,13 @@ def main():
     torch.cuda.set_device(dev)
     sc = sg.dense_packing(tiles=a.tiles)
     log(f"scene: {sc.n} spheres, box {sc.hi}")
-    g = nb.GpuScene(sc.copy(), device=dev, precision="fp64", warm_start="previous")
+    g = nb.GpuScene(sc.copy(), device=dev, precision=a.precision, warm_start="previous")
 
     # ---------------------------------------------------- fixed sweeps, FP64
     for i in range(a.warmup):
-        st = g.step(a.sweeps)
+        # the first warm-up step builds the column's load from zero impulses (Gauss-Seidel needs many sweeps
+        # for that); later steps start from the previous step's impulses
+        st = g.step(a.max_sweeps, a.target) if i == 0 else g.step(a.sweeps)
         log(f"warmup {i}: {st}")
     g.set_profiling(not a.no_profile)
     torch.cuda.synchronize()
@@ -118,7 +134,8 @@ def main():
         achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep<double>", "bytes_per_launch": round(per_launch_bytes),
+                "kernel": "k_sweep<%s>" % ("double" if a.precision == "fp64" else "float"),
+                "bytes_per_launch": round(per_launch_bytes),
                 "avg_launch_us": round(per_launch_ms * 1e3, 2), "launches": prof["sweep_launches"],
                 "sweep_only_updates_per_s": prof["contact_updates"] / (prof["sweep_kernel_ms"] * 1e-3)}
 
@@ -127,7 +144,8 @@ def main():
     if a.residual_steps > 0:
         for prec in ("fp64", "fp32"):
             gr = nb.GpuScene(sc.copy(), device=dev, precision=prec, warm_start="previous")
-            gr.step(a.sweeps)  # warm-start table from one fixed-sweep step
+            gr.step(a.max_sweeps, a.target)  # load built from zero impulses, as in the warm-up above
+            gr.step(a.sweeps)
             torch.cuda.synchronize()
             sweeps_used = []
             conv = []
@@ -159,10 +177,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if a.precision == "fp64" else "f32 sweeps, f64 detection/integration",
         "data": "synthetic: oracle-settled periodic tile of 10,000 spheres replicated to the packing",
         "config": {"workload": f"dense settled packing, {sc.n} polydisperse spheres r~U[0.45,0.55], "
-                               f"periodic 100x100 floor box, phi~0.6, mu=0.5, dt=1e-4, {a.sweeps} FP64 NBGS "
+                               f"periodic 100x100 floor box, phi~0.6, mu=0.5, dt=1e-4, {a.sweeps} {a.precision.upper()} NBGS "
                                f"sweeps/step, previous-step warm start",
                    "n_bodies": sc.n, "contacts_per_step": float(np.mean(contacts)),
                    "contacts_per_body": float(np.mean(contacts)) / sc.n, "colours": int(np.max(colours)),

@@ -250,7 +250,7 @@ def load_tile(path=DENSE_TILE):
         return {k: z[k] for k in z.files}
 
 
-def dense_packing(tiles=10, path=DENSE_TILE, dt=1e-4, mu=0.5, tau=0.005) -> Scene:
+def dense_packing(tiles=10, path=DENSE_TILE, dt=1e-4, mu=0.5, tau=0.005, erp=0.0) -> Scene:
     """Dense settled polydisperse packing on a floor, periodic in x and y.
 
     A periodic tile settled under gravity by the oracle (positions, radii,
@@ -258,8 +258,10 @@ def dense_packing(tiles=10, path=DENSE_TILE, dt=1e-4, mu=0.5, tau=0.005) -> Scen
     Because the tile is periodic in x and y with its footprint as period, the
     replicated packing is again a valid periodic packing.  ``tiles=10`` with
     the 10,000-sphere tile gives the 1,000,000-sphere packing (footprint
-    100 x 100, radii U[0.45, 0.55], solid fraction about 0.6).  Bodies are
-    numbered tile by tile, bottom-up inside each tile.
+    100 x 100, radii U[0.45, 0.55], solid fraction about 0.6).  The settled
+    packing keeps the slight overlaps of its settling, so the penetration
+    correction is scaled down to zero (erp = 0).  Bodies are numbered tile by
+    tile, bottom-up inside each tile.
     """
     t = load_tile(path)
     p0, r0, L = t["pos"], t["radius"], float(t["footprint"])
@@ -271,7 +273,7 @@ def dense_packing(tiles=10, path=DENSE_TILE, dt=1e-4, mu=0.5, tau=0.005) -> Scen
     top = float(np.max(pos[:, 2] + radius)) + 1.0
     lo, hi = (0.0, 0.0, 0.0), (L * tiles, L * tiles, top)
     sc = _make(pos, radius, lo=lo, hi=hi, periodic=(True, True, False),
-               planes=[((0.0, 0.0, 0.0), (0.0, 0.0, 1.0))], dt=dt, mu=mu, tau=tau)
+               planes=[((0.0, 0.0, 0.0), (0.0, 0.0, 1.0))], dt=dt, mu=mu, tau=tau, erp=erp)
     if "vel" in t:
         sc.vel = np.tile(t["vel"], (tiles * tiles, 1))
         sc.angvel = np.tile(t["angvel"], (tiles * tiles, 1))
