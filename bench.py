@@ -36,6 +36,42 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# compulsory bytes of one contact update (contact record read, impulse written) and of one body record
+# read-modify-write (v', w' read and written, 1/m, 1/I read)
+CONTACT_BYTES = {"fp64": 104.0, "fp32": 56.0}
+BODY_BYTES = {"fp64": 112.0, "fp32": 56.0}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_dense1m_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1501_05810_amd", "csrc", f) for f in ("sweep.hip", "nbgs_internal.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
+    scaled by what they read for a plain copy), or None once the kernel sources differ from those profiled."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            line = line.strip().strip("`")
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    v = vals.get(f"traffic_bytes_per_launch_{precision}")
+    return float(v.replace(",", "")) if v else None
+
+
 def cpu_baseline(sample_tiles: int, sweeps: int):
     """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres)."""
     import oracle
@@ -65,8 +101,9 @@ def main():
     ap.add_argument("--residual-steps", type=int, default=3, help="steps timed in the to-residual mode (0: skip)")
     ap.add_argument("--target", type=float, default=1e-6)
     ap.add_argument("--max-sweeps", type=int, default=2000)
-    ap.add_argument("--cpu-tiles", type=int, default=3, help="sample for the oracle timing (0: skip)")
-    ap.add_argument("--no-profile", action="store_true", help="time the steps without per-launch events")
+    ap.add_argument("--cpu-tiles", type=int, default=10, help="sample for the oracle timing (0: skip)")
+    ap.add_argument("--profile-steps", type=int, default=5,
+                    help="steps re-run with a HIP event pair per sweep launch, for the roofline (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (to scale HBM traffic counters)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
@@ -106,38 +143,52 @@ def main():
         # for that); later steps start from the previous step's impulses
         st = g.step(a.max_sweeps, a.target) if i == 0 else g.step(a.sweeps)
         log(f"warmup {i}: {st}")
-    g.set_profiling(not a.no_profile)
-    torch.cuda.synchronize()
-    contacts = []
-    colours = []
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        nb.nbgs_detect(g.handle)
-        st, _ = nb.nbgs_solve(g.handle, a.sweeps, 0.0)
-        nb.nbgs_integrate(g.handle)
-        contacts.append(int(st.n_contacts))
-        colours.append(int(st.n_colours))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = g.profile()
-    phases = g.phase_times()
-    g.set_profiling(False)
-    wall = t1 - t0
+    def run_steps(k, profiled):
+        g.set_profiling(profiled)
+        torch.cuda.synchronize()
+        cs, cols = [], []
+        t0 = time.perf_counter()
+        for i in range(k):
+            nb.nbgs_detect(g.handle)
+            st, _ = nb.nbgs_solve(g.handle, a.sweeps, 0.0)
+            nb.nbgs_integrate(g.handle)
+            cs.append(int(st.n_contacts))
+            cols.append(int(st.n_colours))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = g.profile() if profiled else None
+        g.set_profiling(False)
+        return t1 - t0, cs, cols, g.phase_times(), prof
+
+    # timed region: whole steps, no per-launch events
+    wall, contacts, colours, phases, _ = run_steps(a.steps, False)
     updates = float(np.sum(contacts)) * a.sweeps
     value = updates / wall
     log(f"timed: {a.steps} steps in {wall:.3f} s, {value:.3e} contact updates/s, phases(ms) {phases}")
 
+    # roofline: the same steps again with a HIP event pair around every sweep launch
     roof = None
-    if prof["sweep_launches"] > 0 and prof["sweep_kernel_ms"] > 0:
-        per_launch_bytes = prof["sweep_bytes"] / prof["sweep_launches"]
-        per_launch_ms = prof["sweep_kernel_ms"] / prof["sweep_launches"]
-        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep<%s>" % ("double" if a.precision == "fp64" else "float"),
-                "bytes_per_launch": round(per_launch_bytes),
-                "avg_launch_us": round(per_launch_ms * 1e3, 2), "launches": prof["sweep_launches"],
-                "sweep_only_updates_per_s": prof["contact_updates"] / (prof["sweep_kernel_ms"] * 1e-3)}
+    if a.profile_steps > 0:
+        pwall, pcontacts, _, _, prof = run_steps(a.profile_steps, True)
+        log(f"profiled: {a.profile_steps} steps in {pwall:.3f} s, {prof}")
+        if prof["sweep_launches"] > 0 and prof["sweep_kernel_ms"] > 0:
+            per_launch_bytes = prof["sweep_bytes"] / prof["sweep_launches"]
+            per_launch_ms = prof["sweep_kernel_ms"] / prof["sweep_launches"]
+            achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+            traffic = measured_traffic(a.precision)
+            # secondary model: every body record read and written once per sweep, as if it stayed cached
+            # between the colours of a sweep
+            sweep_model_bytes = (CONTACT_BYTES[a.precision] * float(np.mean(pcontacts))
+                                 + BODY_BYTES[a.precision] * float(np.sum(sc.inv_mass > 0))) * a.sweeps
+            sweep_ms_per_step = prof["sweep_kernel_ms"] / a.profile_steps
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": "k_sweep<%s>" % ("double" if a.precision == "fp64" else "float"),
+                    "bytes_per_launch": round(per_launch_bytes),
+                    "avg_launch_us": round(per_launch_ms * 1e3, 2), "launches": prof["sweep_launches"],
+                    "sweep_only_updates_per_s": prof["contact_updates"] / (prof["sweep_kernel_ms"] * 1e-3),
+                    "ms_per_step_profiled": pwall / a.profile_steps * 1e3,
+                    "sweep_model_frac": round(sweep_model_bytes / (sweep_ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     # ------------------------------------------------ to residual 1e-6 modes
     resid = {}

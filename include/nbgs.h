@@ -217,12 +217,19 @@ nbgs_status nbgs_get_phase_times(nbgs_scene_t scene, int32_t n, double *out);
  * consecutive workgroups, which the dispatcher deals round-robin over the
  * 8 XCDs, onto contiguous contact ranges per XCD (shared body records stay
  * in one L2), 0 keeps the identity mapping; nontemporal: 1 puts the
- * non-temporal hint on the streamed per-contact arrays.  Default 256 / 1 / 1 / 0. */
+ * non-temporal hint on the streamed per-contact arrays; full_store: 1 writes
+ * each touched body record back whole (its constants unchanged), so the write
+ * covers the record's aligned bytes; persistent: 1 launches at most the
+ * workgroups the device holds resident at once, each walking several tiles,
+ * a multiple of 8 launches at most that many workgroups, 0 one per tile.
+ * Results do not depend on any of these.  Default 256 / 1 / 1 / 0 / 0 / 0. */
 typedef struct {
     int32_t block;
     int32_t contacts_per_thread;
     int32_t xcd_remap;
     int32_t nontemporal;
+    int32_t full_store;
+    int32_t persistent;
 } nbgs_tuning;
 
 /* Set / read the sweep launch shape used for precision (nbgs_precision).

@@ -64,7 +64,7 @@ class nbgs_profile(C.Structure):
 
 class nbgs_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("contacts_per_thread", C.c_int32), ("xcd_remap", C.c_int32),
-                ("nontemporal", C.c_int32)]
+                ("nontemporal", C.c_int32), ("full_store", C.c_int32), ("persistent", C.c_int32)]
 
 
 class NbgsError(RuntimeError):
@@ -216,9 +216,9 @@ def nbgs_get_phase_times(h: int, n: int = 5) -> np.ndarray:
 
 
 def nbgs_set_tuning(h: int, precision: int, block: int, contacts_per_thread: int, xcd_remap: int,
-                    nontemporal: int = 0) -> None:
+                    nontemporal: int = 0, full_store: int = 0, persistent: int = 0) -> None:
     t = nbgs_tuning(block=block, contacts_per_thread=contacts_per_thread, xcd_remap=xcd_remap,
-                    nontemporal=nontemporal)
+                    nontemporal=nontemporal, full_store=full_store, persistent=persistent)
     _check(lib().nbgs_set_tuning(_vp(h), int(precision), C.byref(t)))
 
 
@@ -226,7 +226,7 @@ def nbgs_get_tuning(h: int, precision: int) -> Dict:
     t = nbgs_tuning()
     _check(lib().nbgs_get_tuning(_vp(h), int(precision), C.byref(t)))
     return dict(block=t.block, contacts_per_thread=t.contacts_per_thread, xcd_remap=t.xcd_remap,
-                nontemporal=t.nontemporal)
+                nontemporal=t.nontemporal, full_store=t.full_store, persistent=t.persistent)
 
 
 def nbgs_set_profiling(h: int, enable: bool) -> None:
@@ -494,9 +494,10 @@ class GpuScene:
         nbgs_set_warm_start(self.handle, n, k.data_ptr(), p.data_ptr())
         self.stream.synchronize()
 
-    def set_tuning(self, block=256, contacts_per_thread=1, xcd_remap=1, nontemporal=0, precision=None):
+    def set_tuning(self, block=256, contacts_per_thread=1, xcd_remap=1, nontemporal=0, full_store=0, persistent=0,
+                   precision=None):
         prec = PRECISIONS[precision or self.precision]
-        nbgs_set_tuning(self.handle, prec, block, contacts_per_thread, xcd_remap, nontemporal)
+        nbgs_set_tuning(self.handle, prec, block, contacts_per_thread, xcd_remap, nontemporal, full_store, persistent)
 
     def tuning(self, precision=None) -> Dict:
         return nbgs_get_tuning(self.handle, PRECISIONS[precision or self.precision])

@@ -1037,9 +1037,12 @@ nbgs_status nbgs_set_tuning(nbgs_scene_t sc, int32_t precision, const nbgs_tunin
     st.cpt = t->contacts_per_thread;
     st.xcd_remap = t->xcd_remap;
     st.nontemporal = t->nontemporal;
+    st.full_store = t->full_store;
+    st.persistent = t->persistent;
     if (!sweep_tune_supported(st)) {
-        set_error("unsupported tuning: block %d, contacts_per_thread %d, xcd_remap %d, nontemporal %d", t->block,
-                  t->contacts_per_thread, t->xcd_remap, t->nontemporal);
+        set_error("unsupported tuning: block %d, contacts_per_thread %d, xcd_remap %d, nontemporal %d, full_store %d, "
+                  "persistent %d",
+                  t->block, t->contacts_per_thread, t->xcd_remap, t->nontemporal, t->full_store, t->persistent);
         return NBGS_ERR_INVALID_ARG;
     }
     sc->tune[precision] = st;
@@ -1057,6 +1060,8 @@ nbgs_status nbgs_get_tuning(nbgs_scene_t sc, int32_t precision, nbgs_tuning *t) 
     t->contacts_per_thread = st.cpt;
     t->xcd_remap = st.xcd_remap;
     t->nontemporal = st.nontemporal;
+    t->full_store = st.full_store;
+    t->persistent = st.persistent;
     return NBGS_OK;
 }
 

@@ -45,7 +45,14 @@ __global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) rh = fmax(rh, __shfl_xor(rh, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(max_bits, (unsigned long long)__double_as_longlong(rh));
+    __shared__ double wmax[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = rh;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // one atomic per block: the largest hull is order-independent
+        double m = wmax[0];
+        for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, wmax[w]);
+        atomicMax(max_bits, (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 __device__ inline int cell_coord(double x, double lo, double edge, int dims) {

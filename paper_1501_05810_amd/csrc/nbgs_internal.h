@@ -166,6 +166,8 @@ struct SweepTune {
     int32_t cpt = 1;       // contacts per thread
     int32_t xcd_remap = 1; // contiguous tile runs per XCD
     int32_t nontemporal = 0; // non-temporal hint on the streamed contact arrays
+    int32_t full_store = 0;  // write whole body records back
+    int32_t persistent = 0;  // at most one resident round of workgroups, each walking several tiles
 };
 int64_t sweep_tile(const SweepTune &t);
 bool sweep_tune_supported(const SweepTune &t);

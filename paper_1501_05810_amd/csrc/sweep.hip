@@ -62,19 +62,28 @@ __device__ inline Rec<float> load_rec(const float *vel, int b) {
     return r;
 }
 
-// Store v', w' (the constants stay).
+// Store v', w'.  With FULL the whole record is written back (the constants
+// unchanged), so the write covers the record's aligned 64 B (32 B) instead of
+// leaving a partially written memory burst.
+template <bool FULL = false>
 __device__ inline void store_vel(double *vel, int b, const Rec<double> &r) {
     double2 *p = reinterpret_cast<double2 *>(vel + 8 * (int64_t)b);
     p[0] = make_double2(r.v[0], r.v[1]);
     p[1] = make_double2(r.v[2], r.w[0]);
     p[2] = make_double2(r.w[1], r.w[2]);
+    if (FULL) p[3] = make_double2(r.im, r.ii);
 }
 
+template <bool FULL = false>
 __device__ inline void store_vel(float *vel, int b, const Rec<float> &r) {
     float4 *p = reinterpret_cast<float4 *>(vel + 8 * (int64_t)b);
     p[0] = make_float4(r.v[0], r.v[1], r.v[2], r.w[0]);
-    float2 *q = reinterpret_cast<float2 *>(vel + 8 * (int64_t)b + 4);
-    q[0] = make_float2(r.w[1], r.w[2]);
+    if (FULL) {
+        p[1] = make_float4(r.w[1], r.w[2], r.im, r.ii);
+    } else {
+        float2 *q = reinterpret_cast<float2 *>(vel + 8 * (int64_t)b + 4);
+        q[0] = make_float2(r.w[1], r.w[2]);
+    }
 }
 
 template <class T>
@@ -163,26 +172,36 @@ __device__ inline void st(V *p, V v) {
     else *p = v;
 }
 
-// Workgroup -> contact tile.  With xcd_remap, consecutive workgroups (which
-// the dispatcher deals round-robin over the 8 XCDs) are mapped so that every
-// XCD walks one contiguous run of tiles: neighbouring contacts, and the body
-// records they share, stay in the L2 of one XCD.
-__device__ inline unsigned tile_of(unsigned b, unsigned G, int xcd_remap) {
-    if (!xcd_remap) return b;
-    const unsigned x = b & 7u, i = b >> 3, q = G >> 3, r = G & 7u;
-    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+// Workgroups -> contact tiles.  Without xcd_remap, workgroup b relaxes tiles
+// b, b + P, b + 2P, ... (P = gridDim.x).  With xcd_remap the G tiles are cut
+// into 8 contiguous ranges, one per XCD (the dispatcher deals consecutive
+// workgroups round-robin over the 8 XCDs), and the workgroups of XCD x walk
+// range x: neighbouring contacts, and the body records they share, stay in the
+// L2 of one XCD.  P == G gives one tile per workgroup; P < G (a persistent
+// grid) must then be a multiple of 8 so that every XCD has a workgroup.
+struct TileWalk {
+    unsigned t, end, step;
+};
+
+__device__ inline TileWalk tile_walk(unsigned b, unsigned P, unsigned G, int xcd_remap) {
+    if (!xcd_remap) return {b, G, P};
+    const unsigned x = b & 7u, i = b >> 3;
+    const unsigned q = G >> 3, r = G & 7u;
+    const unsigned lo = x * q + (x < r ? x : r);
+    const unsigned hi = lo + q + (x < r ? 1u : 0u);
+    const unsigned nx = (P >> 3) + ((x < (P & 7u)) ? 1u : 0u);
+    return {lo + i, hi, nx};
 }
 
-// One colour of one sweep; each thread relaxes CPT contacts (strided by the
-// block size, all loads issued before any arithmetic).  partials receives
-// (sum |dP|^2, sum |P|^2) of the tile; ctrl[0] != 0 means an earlier sweep
-// already met the residual target.
-template <class T, int BLOCK, int CPT, bool NT>
-__global__ void __launch_bounds__(BLOCK) k_sweep(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel,
-                                                 T mu, T relax, double *partials, const int32_t *ctrl,
-                                                 int xcd_remap) {
-    if (ctrl[0]) return;
-    const unsigned tile = tile_of(blockIdx.x, gridDim.x, xcd_remap);
+// One tile of one colour: each thread relaxes CPT contacts (strided by the
+// block size, all contact loads issued before any arithmetic).  partials
+// receives (sum |dP|^2, sum |P|^2) of the tile; ctrl[0] != 0 means an earlier
+// sweep already met the residual target (checked after the contact loads are
+// in flight, so the flag's latency is hidden behind them).
+template <class T, int BLOCK, int CPT, bool NT, bool FULL>
+__device__ inline void sweep_tile_body(const SweepView<T> &sv, int64_t begin, int64_t end, int32_t nb, T *vel, T mu,
+                                       T relax, double *partials, const int32_t *ctrl, unsigned tile,
+                                       double (*red)[BLOCK / 64]) {
     const int64_t p0 = begin + (int64_t)tile * (BLOCK * CPT) + threadIdx.x;
     double sd = 0.0, sp = 0.0;
     int b1[CPT], b2[CPT];
@@ -205,6 +224,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepView<T> sv, int64_t begin,
         P[k][1] = ld<NT>(sv.py + q);
         P[k][2] = ld<NT>(sv.pz + q);
     }
+    if (ctrl[0]) return;  // uniform over the grid: the flag does not change during a launch
     Rec<T> r1[CPT], r2[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
@@ -254,8 +274,8 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepView<T> sv, int64_t begin,
             dP[a] = Pnew[a] - Pk[a];
         }
         apply(r1[k], r2[k], nk, a1[k], a2[k], dP);
-        if (r1[k].im > T(0)) store_vel(vel, b1[k], r1[k]);
-        if (b2[k] < nb && r2[k].im > T(0)) store_vel(vel, b2[k], r2[k]);
+        if (r1[k].im > T(0)) store_vel<FULL>(vel, b1[k], r1[k]);
+        if (b2[k] < nb && r2[k].im > T(0)) store_vel<FULL>(vel, b2[k], r2[k]);
         const int64_t p = p0 + (int64_t)k * BLOCK;
         st<NT>(sv.px + p, Pnew[0]);
         st<NT>(sv.py + p, Pnew[1]);
@@ -265,7 +285,6 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepView<T> sv, int64_t begin,
         sd += d0 * d0 + d1 * d1 + d2 * d2;
         sp += q0 * q0 + q1 * q1 + q2 * q2;
     }
-    __shared__ double red[2][BLOCK / 64];
     sd = wave_sum(sd);
     sp = wave_sum(sp);
     const int wave = threadIdx.x >> 6;
@@ -284,23 +303,39 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepView<T> sv, int64_t begin,
         partials[2 * tile + 0] = a;
         partials[2 * tile + 1] = c;
     }
+    __syncthreads();  // red is reused by the workgroup's next tile
+}
+
+// One colour of one sweep over G tiles by gridDim.x workgroups.
+template <class T, int BLOCK, int CPT, bool NT, bool FULL>
+__global__ void __launch_bounds__(BLOCK) k_sweep(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel,
+                                                 T mu, T relax, double *partials, const int32_t *ctrl, unsigned G,
+                                                 int xcd_remap) {
+    __shared__ double red[2][BLOCK / 64];
+    const TileWalk w = tile_walk(blockIdx.x, gridDim.x, G, xcd_remap);
+    for (unsigned t = w.t; t < w.end; t += w.step)
+        sweep_tile_body<T, BLOCK, CPT, NT, FULL>(sv, begin, end, nb, vel, mu, relax, partials, ctrl, t, red);
 }
 
 // R_k = sqrt(sum |dP|^2) / max(sqrt(sum |P|^2), 1e-300), summed in a fixed
 // order.  ctrl = {done, sweeps completed, numeric error}.
-__global__ void __launch_bounds__(kBlock) k_residual(const double *partials, int32_t n_partials, double target,
-                                                     int32_t *ctrl, double *hist) {
+constexpr int kResBlock = 1024;
+
+__global__ void __launch_bounds__(kResBlock) k_residual(const double *partials, int32_t n_partials, double target,
+                                                        int32_t *ctrl, double *hist) {
     if (ctrl[0]) return;
     double a = 0.0, c = 0.0;
-    for (int q = threadIdx.x; q < n_partials; q += kBlock) {
-        a += partials[2 * q + 0];
-        c += partials[2 * q + 1];
+    const double2 *pp = reinterpret_cast<const double2 *>(partials);
+    for (int q = threadIdx.x; q < n_partials; q += kResBlock) {
+        const double2 v = pp[q];
+        a += v.x;
+        c += v.y;
     }
-    __shared__ double red[2][kBlock];
+    __shared__ double red[2][kResBlock];
     red[0][threadIdx.x] = a;
     red[1][threadIdx.x] = c;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
+    for (int s = kResBlock / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
             red[0][threadIdx.x] += red[0][threadIdx.x + s];
             red[1][threadIdx.x] += red[1][threadIdx.x + s];
@@ -407,23 +442,51 @@ int64_t sweep_tile(const SweepTune &t) { return (int64_t)t.block * t.cpt; }
 bool sweep_tune_supported(const SweepTune &t) {
     const bool blk = t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512;
     return blk && (t.cpt == 1 || t.cpt == 2 || t.cpt == 4) && (t.xcd_remap == 0 || t.xcd_remap == 1) &&
-           (t.nontemporal == 0 || t.nontemporal == 1);
+           (t.nontemporal == 0 || t.nontemporal == 1) && (t.full_store == 0 || t.full_store == 1) &&
+           (t.persistent == 0 || t.persistent == 1 || (t.persistent >= 8 && t.persistent % 8 == 0));
+}
+
+// Workgroups of a persistent sweep grid: what the device holds resident at
+// once (blocks per CU at this kernel's register use, times the CU count),
+// rounded down to a multiple of 8.
+template <class K>
+unsigned persistent_cap(K kernel, int block) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
+    const unsigned cap = (unsigned)per_cu * (unsigned)cus;
+    return cap < 8 ? 8u : cap & ~7u;
 }
 
 template <class T>
 nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, SweepParams sp,
                                 const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s) {
     if (end <= begin) return NBGS_OK;
-    const unsigned grid = (unsigned)((end - begin + sweep_tile(t) - 1) / sweep_tile(t));
+    const unsigned G = (unsigned)((end - begin + sweep_tile(t) - 1) / sweep_tile(t));
     const T mu = (T)sp.mu, relax = (T)sp.relax;
+#define NBGS_SWEEP_LAUNCH(B, C, NT, FULL)                                                                          \
+    do {                                                                                                           \
+        auto kern = k_sweep<T, B, C, NT, FULL>;                                                                    \
+        unsigned grid = G;                                                                                         \
+        if (t.persistent == 1) {                                                                                   \
+            static const unsigned cap = persistent_cap(kern, B);                                                   \
+            if (cap < grid) grid = cap;                                                                            \
+        } else if (t.persistent > 1 && (unsigned)t.persistent < grid) {                                            \
+            grid = (unsigned)t.persistent;                                                                         \
+        }                                                                                                          \
+        kern<<<grid, B, 0, s>>>(sv, begin, end, nb, vel, mu, relax, partials, ctrl, G, t.xcd_remap);               \
+    } while (0)
 #define NBGS_SWEEP_CASE(B, C)                                                                                      \
     if (t.block == B && t.cpt == C) {                                                                              \
-        if (t.nontemporal)                                                                                         \
-            k_sweep<T, B, C, true><<<grid, B, 0, s>>>(sv, begin, end, nb, vel, mu, relax, partials, ctrl,          \
-                                                      t.xcd_remap);                                               \
-        else                                                                                                       \
-            k_sweep<T, B, C, false><<<grid, B, 0, s>>>(sv, begin, end, nb, vel, mu, relax, partials, ctrl,         \
-                                                       t.xcd_remap);                                              \
+        if (t.nontemporal && t.full_store) NBGS_SWEEP_LAUNCH(B, C, true, true);                                    \
+        else if (t.nontemporal) NBGS_SWEEP_LAUNCH(B, C, true, false);                                              \
+        else if (t.full_store) NBGS_SWEEP_LAUNCH(B, C, false, true);                                               \
+        else NBGS_SWEEP_LAUNCH(B, C, false, false);                                                                \
         NBGS_HIP(hipGetLastError());                                                                               \
         return NBGS_OK;                                                                                            \
     }
@@ -440,13 +503,14 @@ nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int
     NBGS_SWEEP_CASE(512, 2)
     NBGS_SWEEP_CASE(512, 4)
 #undef NBGS_SWEEP_CASE
+#undef NBGS_SWEEP_LAUNCH
     set_error("unsupported sweep tuning block=%d cpt=%d", t.block, t.cpt);
     return NBGS_ERR_INVALID_ARG;
 }
 
 nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl, double *hist,
                             hipStream_t s) {
-    k_residual<<<1, kBlock, 0, s>>>(partials, n_partials, target, ctrl, hist);
+    k_residual<<<1, kResBlock, 0, s>>>(partials, n_partials, target, ctrl, hist);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

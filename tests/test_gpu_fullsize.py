@@ -72,14 +72,17 @@ def _greedy_sampled(sc, c, seed, samples, rng):
         assert set(range(int(c["colour"][j]))) <= hcols
 
 
-def _solve_properties(sc, g, c, before_vel, mom_tol=1e-9):
+def _solve_properties(sc, g, c, before_vel, mom_tol=1e-9, cone_rel=1e-12):
+    """cone_rel: slack per contact relative to |P_j|.  FP32 sweeps store P and use the normal rounded to FP32,
+    so re-splitting P along the FP64 normal shows the cone boundary to FP32 rounding only."""
     P = c["P"]
     n = c["n"]
     Pn = np.einsum("ij,ij->i", n, P)
     Pt = P - Pn[:, None] * n
     scale = np.abs(P).max()
-    assert Pn.min() >= -1e-12 * scale
-    assert np.all(np.linalg.norm(Pt, axis=1) <= sc.mu * Pn * (1 + 1e-9) + 1e-12 * scale)
+    Pabs = np.linalg.norm(P, axis=1)
+    assert Pn.min() >= -1e-12 * scale - np.max(cone_rel * Pabs)
+    assert np.all(np.linalg.norm(Pt, axis=1) <= sc.mu * Pn * (1 + 1e-9) + 1e-12 * scale + cone_rel * Pabs)
     v, _ = g.accumulators()
     m = np.where(sc.inv_mass > 0, 1.0 / np.where(sc.inv_mass > 0, sc.inv_mass, 1.0), 0.0)
     dp = (m[:, None] * (v - before_vel)).sum(0)
@@ -117,8 +120,11 @@ def test_dense_packing_1m(precision):
     before = g.state()
     g.solve(50)
     c = g.contacts()
-    # FP32 accumulators conserve momentum to FP32 round-off only
-    _solve_properties(sc, g, c, before["vel"], mom_tol=1e-9 if precision == "fp64" else 1e-5)
+    # FP32 accumulators conserve momentum, and FP32 impulses meet the cone, to FP32 round-off only
+    if precision == "fp64":
+        _solve_properties(sc, g, c, before["vel"])
+    else:
+        _solve_properties(sc, g, c, before["vel"], mom_tol=1e-5, cone_rel=1e-6)
     g.integrate()
     _integration_properties(sc, before, g.state())
     g.close()

@@ -319,15 +319,18 @@ def test_colouring_from_previous_step_equals_greedy():
     g.close()
 
 
-@pytest.mark.parametrize("block,cpt,xcd", [(64, 1, 0), (128, 2, 1), (256, 4, 1), (512, 1, 1), (512, 4, 0)])
+@pytest.mark.parametrize("shape", [(64, 1, 0), (128, 2, 1), (256, 4, 1), (512, 1, 1), (512, 4, 0),
+                                   (256, 1, 1, 1, 1), (128, 2, 1, 0, 1), (64, 1, 1, 0, 0, 8), (64, 2, 0, 1, 1, 16),
+                                   (128, 1, 1, 0, 0, 24), (256, 1, 1, 1, 1, 1)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_launch_shapes_are_bit_identical(block, cpt, xcd, precision):
-    """Every supported sweep launch shape relaxes each contact with the same arithmetic: impulses and
-    velocities are bit-identical."""
+def test_launch_shapes_are_bit_identical(shape, precision):
+    """Every supported sweep launch shape (block, contacts per thread, XCD remap, non-temporal hint, whole-record
+    store, persistent workgroup cap) relaxes each contact with the same arithmetic: impulses and velocities are
+    bit-identical.  Caps of 8 to 24 workgroups make each workgroup walk many tiles of a colour."""
     nb = _nb()
     sc = sg.packed_cluster(10, counts=(16, 16, 8))
     outs = []
-    for shape in ((256, 1, 1), (block, cpt, xcd)):
+    for shape in ((256, 1, 1), shape):
         g = nb.GpuScene(sc.copy(), precision=precision)
         g.set_tuning(*shape)
         for _ in range(2):
