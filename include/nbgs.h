@@ -221,8 +221,14 @@ nbgs_status nbgs_get_phase_times(nbgs_scene_t scene, int32_t n, double *out);
  * each touched body record back whole (its constants unchanged), so the write
  * covers the record's aligned bytes; persistent: 1 launches at most the
  * workgroups the device holds resident at once, each walking several tiles,
- * a multiple of 8 launches at most that many workgroups, 0 one per tile.
- * Results do not depend on any of these.  Default 256 / 1 / 1 / 0 / 0 / 0. */
+ * a multiple of 8 launches at most that many workgroups, 0 one per tile;
+ * graph: 1 replays the sweeps from a captured HIP graph (blocks of up to 32
+ * sweeps, colour ranges read on the device, persistent workgroups: the
+ * resident count unless persistent gives a multiple of 8).  Impulses and
+ * velocities do not depend on any of these; the residual's partial sums are
+ * grouped per tile (per workgroup with graph), so only its rounding may.
+ * Default 256 / 1 / 1 / 0 / 0 / 0 / 0 for a scene, graph 1 and persistent 1
+ * for a batch. */
 typedef struct {
     int32_t block;
     int32_t contacts_per_thread;
@@ -230,12 +236,28 @@ typedef struct {
     int32_t nontemporal;
     int32_t full_store;
     int32_t persistent;
+    int32_t graph;
 } nbgs_tuning;
 
 /* Set / read the sweep launch shape used for precision (nbgs_precision).
- * INVALID_ARG for an unsupported shape. */
+ * INVALID_ARG for an unsupported shape.  A shape set here is kept: a batch
+ * does not autotune that precision afterwards. */
 nbgs_status nbgs_set_tuning(nbgs_scene_t scene, int32_t precision, const nbgs_tuning *tuning);
 nbgs_status nbgs_get_tuning(nbgs_scene_t scene, int32_t precision, nbgs_tuning *tuning);
+
+/* Choose the sweep launch shape for the scene's precision by timing trial
+ * solves of `sweeps` sweeps on the contacts of the current step (call after
+ * nbgs_detect, before nbgs_solve): coordinate descent over the nbgs_tuning
+ * fields from the current shape.  The trials leave no trace: the initial
+ * impulses are restored, and the solve that follows gives the same impulses
+ * and velocities as without tuning.  cache_path [host, may be NULL]: a text
+ * file of earlier choices, one line per (GPU architecture, precision,
+ * scene or batch, ceil log2 of the contact count); a cached choice is taken
+ * without trials and a new one is appended.  *chosen [host, may be NULL]
+ * receives the shape, *ms_per_sweep [host, may be NULL] its time per sweep.
+ * STATE unless a step is detected and not solved.  Synchronises. */
+nbgs_status nbgs_autotune(nbgs_scene_t scene, int32_t sweeps, const char *cache_path, nbgs_tuning *chosen,
+                          double *ms_per_sweep);
 
 /* Sweep-kernel profile accumulated while profiling is enabled. */
 typedef struct {
@@ -255,6 +277,52 @@ nbgs_status nbgs_set_profiling(nbgs_scene_t scene, int32_t enable);
 
 /* Copy the accumulated profile into *out [host]. */
 nbgs_status nbgs_get_profile(nbgs_scene_t scene, nbgs_profile *out);
+
+/* ------------------------------------------------------- batched scenes
+ *
+ * Many independent scenes of uneven size stepped together.  Each scene is a
+ * separate granular system (its own box, periodicity, walls, friction
+ * coefficient and colouring seed; Alg. 2 per scene); they share one body
+ * array and one set of launches: colour c of every scene is relaxed by the
+ * same sweep launch.  Each scene is detected, coloured, ordered and relaxed
+ * exactly as it would be alone (same contacts, colours and FP arithmetic), so
+ * its impulses and velocities after a fixed number of sweeps equal those of a
+ * scene created for it alone.  The residual of a batch is that of all its
+ * contacts together, so a residual target stops all scenes at one sweep. */
+typedef struct nbgs_batch_s *nbgs_batch_t;
+
+/* n_scenes >= 1 scenes; body_offsets [host, n_scenes + 1 int64]: scene s owns
+ * bodies body_offsets[s] .. body_offsets[s + 1] - 1 of `bodies` (device SoA
+ * as for nbgs_scene_create, borrowed), body_offsets[0] = 0 and
+ * body_offsets[n_scenes] = bodies->n, every scene non-empty.  domains,
+ * params [host, n_scenes each]: per-scene box and walls; params may differ
+ * between scenes only in mu and colour_seed (INVALID_ARG otherwise);
+ * NBGS_WS_LEARNED is UNSUPPORTED.  Wall w of scene s has body id
+ * bodies->n + (walls of scenes 0 .. s-1) + w in contact lists.
+ * tune_cache_path [host, may be NULL, copied]: autotuner cache file (see
+ * nbgs_autotune).  The batch replays its sweeps from a captured HIP graph over
+ * resident workgroups and autotunes the launch shape on its first step of
+ * each precision unless nbgs_set_tuning set one. */
+nbgs_status nbgs_batch_create(int32_t n_scenes, const int64_t *body_offsets, const nbgs_bodies *bodies,
+                              const nbgs_domain *domains, const nbgs_params *params, const char *tune_cache_path,
+                              void *hip_stream, nbgs_batch_t *out);
+nbgs_status nbgs_batch_destroy(nbgs_batch_t batch);
+
+/* The scene handle behind the batch (owned by the batch): every nbgs_scene_t
+ * entry point except the learned warm start applies to the batch as a whole
+ * (contacts in the shared numbering, accumulators of all bodies, tuning,
+ * profiling, phase times, residual history). */
+nbgs_status nbgs_batch_scene(nbgs_batch_t batch, nbgs_scene_t *scene);
+
+/* n_steps time steps of every scene (detect, solve with max_sweeps /
+ * residual_target as nbgs_solve, integrate).  *stats [host, may be NULL]: the
+ * last step's totals.  NOT_CONVERGED if the last solve missed its target. */
+nbgs_status nbgs_batch_step(nbgs_batch_t batch, int32_t n_steps, int32_t max_sweeps, double residual_target,
+                            nbgs_stats *stats);
+
+/* Per-scene contact and colour counts of the last detected step into
+ * n_contacts, n_colours [host, n entries, n = the scene count].  Synchronises. */
+nbgs_status nbgs_batch_scene_stats(nbgs_batch_t batch, int32_t n, int64_t *n_contacts, int32_t *n_colours);
 
 /* ------------------------------------------------ learned warm start (MLP)
  *

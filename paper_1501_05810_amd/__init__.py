@@ -64,7 +64,8 @@ class nbgs_profile(C.Structure):
 
 class nbgs_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("contacts_per_thread", C.c_int32), ("xcd_remap", C.c_int32),
-                ("nontemporal", C.c_int32), ("full_store", C.c_int32), ("persistent", C.c_int32)]
+                ("nontemporal", C.c_int32), ("full_store", C.c_int32), ("persistent", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 class NbgsError(RuntimeError):
@@ -108,6 +109,13 @@ _SIGNATURES = [
     ("nbgs_get_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
     ("nbgs_set_profiling", C.c_int, [_vp, C.c_int32]),
     ("nbgs_get_profile", C.c_int, [_vp, C.POINTER(nbgs_profile)]),
+    ("nbgs_autotune", C.c_int, [_vp, C.c_int32, C.c_char_p, C.POINTER(nbgs_tuning), C.POINTER(C.c_double)]),
+    ("nbgs_batch_create", C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(nbgs_bodies), C.POINTER(nbgs_domain),
+                                    C.POINTER(nbgs_params), C.c_char_p, _vp, C.POINTER(_vp)]),
+    ("nbgs_batch_destroy", C.c_int, [_vp]),
+    ("nbgs_batch_scene", C.c_int, [_vp, C.POINTER(_vp)]),
+    ("nbgs_batch_step", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_double, C.POINTER(nbgs_stats)]),
+    ("nbgs_batch_scene_stats", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
 ]
 
 _lib = None
@@ -216,9 +224,9 @@ def nbgs_get_phase_times(h: int, n: int = 5) -> np.ndarray:
 
 
 def nbgs_set_tuning(h: int, precision: int, block: int, contacts_per_thread: int, xcd_remap: int,
-                    nontemporal: int = 0, full_store: int = 0, persistent: int = 0) -> None:
+                    nontemporal: int = 0, full_store: int = 0, persistent: int = 0, graph: int = 0) -> None:
     t = nbgs_tuning(block=block, contacts_per_thread=contacts_per_thread, xcd_remap=xcd_remap,
-                    nontemporal=nontemporal, full_store=full_store, persistent=persistent)
+                    nontemporal=nontemporal, full_store=full_store, persistent=persistent, graph=graph)
     _check(lib().nbgs_set_tuning(_vp(h), int(precision), C.byref(t)))
 
 
@@ -226,7 +234,7 @@ def nbgs_get_tuning(h: int, precision: int) -> Dict:
     t = nbgs_tuning()
     _check(lib().nbgs_get_tuning(_vp(h), int(precision), C.byref(t)))
     return dict(block=t.block, contacts_per_thread=t.contacts_per_thread, xcd_remap=t.xcd_remap,
-                nontemporal=t.nontemporal, full_store=t.full_store, persistent=t.persistent)
+                nontemporal=t.nontemporal, full_store=t.full_store, persistent=t.persistent, graph=t.graph)
 
 
 def nbgs_set_profiling(h: int, enable: bool) -> None:
@@ -311,6 +319,52 @@ def nbgs_get_warm_start_info(h: int) -> Dict:
     w = nbgs_warm_info()
     _check(lib().nbgs_get_warm_start_info(_vp(h), C.byref(w)))
     return dict(choice=int(w.choice), r_previous=float(w.r_previous), r_learned=float(w.r_learned))
+
+
+def _tuning_dict(t: nbgs_tuning) -> Dict:
+    return dict(block=t.block, contacts_per_thread=t.contacts_per_thread, xcd_remap=t.xcd_remap,
+                nontemporal=t.nontemporal, full_store=t.full_store, persistent=t.persistent, graph=t.graph)
+
+
+def nbgs_autotune(h: int, sweeps: int, cache_path: Optional[str] = None):
+    t = nbgs_tuning()
+    ms = C.c_double()
+    _check(lib().nbgs_autotune(_vp(h), sweeps, cache_path.encode() if cache_path else None, C.byref(t),
+                               C.byref(ms)))
+    return _tuning_dict(t), float(ms.value)
+
+
+def nbgs_batch_create(n_scenes: int, body_offsets, bodies: nbgs_bodies, domains, params, cache_path=None,
+                      stream: int = 0) -> int:
+    off = (C.c_int64 * (n_scenes + 1))(*[int(v) for v in body_offsets])
+    h = _vp()
+    _check(lib().nbgs_batch_create(n_scenes, off, C.byref(bodies), domains, params,
+                                   cache_path.encode() if cache_path else None, _vp(stream), C.byref(h)))
+    return h.value
+
+
+def nbgs_batch_destroy(h: int) -> None:
+    _check(lib().nbgs_batch_destroy(_vp(h)))
+
+
+def nbgs_batch_scene(h: int) -> int:
+    out = _vp()
+    _check(lib().nbgs_batch_scene(_vp(h), C.byref(out)))
+    return out.value
+
+
+def nbgs_batch_step(h: int, n_steps: int, max_sweeps: int, residual_target: float = 0.0):
+    st = nbgs_stats()
+    code = lib().nbgs_batch_step(_vp(h), n_steps, max_sweeps, residual_target, C.byref(st))
+    _check(code, allow=(NBGS_ERR_NOT_CONVERGED,))
+    return st, code
+
+
+def nbgs_batch_scene_stats(h: int, n: int):
+    nc = (C.c_int64 * max(n, 1))()
+    ncol = (C.c_int32 * max(n, 1))()
+    _check(lib().nbgs_batch_scene_stats(_vp(h), n, nc, ncol))
+    return np.array(nc[:n], dtype=np.int64), np.array(ncol[:n], dtype=np.int32)
 
 
 class GpuMlp:
@@ -495,9 +549,14 @@ class GpuScene:
         self.stream.synchronize()
 
     def set_tuning(self, block=256, contacts_per_thread=1, xcd_remap=1, nontemporal=0, full_store=0, persistent=0,
-                   precision=None):
+                   graph=0, precision=None):
         prec = PRECISIONS[precision or self.precision]
-        nbgs_set_tuning(self.handle, prec, block, contacts_per_thread, xcd_remap, nontemporal, full_store, persistent)
+        nbgs_set_tuning(self.handle, prec, block, contacts_per_thread, xcd_remap, nontemporal, full_store, persistent,
+                        graph)
+
+    def autotune(self, sweeps: int = 8, cache_path: Optional[str] = None):
+        """Choose the sweep launch shape on the detected step (see nbgs_autotune); returns (shape, ms/sweep)."""
+        return nbgs_autotune(self.handle, sweeps, cache_path)
 
     def tuning(self, precision=None) -> Dict:
         return nbgs_get_tuning(self.handle, PRECISIONS[precision or self.precision])
@@ -553,3 +612,93 @@ class GpuScene:
                 continue
             for k, name in enumerate(names):
                 self.t[name].copy_(torch.from_numpy(np.ascontiguousarray(arr[:, k])))
+
+
+class GpuBatch(GpuScene):
+    """Several scenes stepped together (one body array, one set of launches).
+
+    ``scenes`` is a list of :class:`scenegen.Scene`; bodies are concatenated
+    in list order.  Every :class:`GpuScene` method applies to the batch as a
+    whole (through the batch's scene handle); :meth:`split` cuts per-body
+    arrays back into scenes.
+    """
+
+    def __init__(self, scenes, device="cuda", precision="fp32", warm_start="previous", stream=None,
+                 cache_path=None):
+        import torch
+
+        self.torch = torch
+        self.scenes = scenes
+        self.device = torch.device(device)
+        self.offsets = np.concatenate([[0], np.cumsum([s.n for s in scenes])]).astype(np.int64)
+        self.n = int(self.offsets[-1])
+        self.sc = scenes[0]
+        cat = lambda f: np.concatenate([f(s) for s in scenes])  # noqa: E731
+        cols = {"x": cat(lambda s: s.pos[:, 0]), "y": cat(lambda s: s.pos[:, 1]), "z": cat(lambda s: s.pos[:, 2]),
+                "qw": cat(lambda s: s.quat[:, 0]), "qx": cat(lambda s: s.quat[:, 1]),
+                "qy": cat(lambda s: s.quat[:, 2]), "qz": cat(lambda s: s.quat[:, 3]),
+                "vx": cat(lambda s: s.vel[:, 0]), "vy": cat(lambda s: s.vel[:, 1]), "vz": cat(lambda s: s.vel[:, 2]),
+                "wx": cat(lambda s: s.angvel[:, 0]), "wy": cat(lambda s: s.angvel[:, 1]),
+                "wz": cat(lambda s: s.angvel[:, 2]), "radius": cat(lambda s: s.radius),
+                "inv_mass": cat(lambda s: s.inv_mass), "inv_inertia": cat(lambda s: s.inv_inertia)}
+        self.t = {k: torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device=self.device)
+                  for k, v in cols.items()}
+        self._bodies = nbgs_bodies(n=self.n, **{k: self.t[k].data_ptr() for k in BODY_FIELDS})
+        ns = len(scenes)
+        self._plane_arrays = []
+        self._domains = (nbgs_domain * ns)()
+        self._params_arr = (nbgs_params * ns)()
+        for i, s in enumerate(scenes):
+            pl = (nbgs_plane * max(1, len(s.planes)))()
+            for k, (pt, nm) in enumerate(s.planes):
+                pl[k].point[:] = list(pt)
+                pl[k].normal[:] = list(nm)
+            self._plane_arrays.append(pl)
+            self._domains[i] = nbgs_domain(lo=(C.c_double * 3)(*s.lo), hi=(C.c_double * 3)(*s.hi),
+                                           periodic=(C.c_int32 * 3)(*[int(bool(p)) for p in s.periodic]),
+                                           n_planes=len(s.planes), planes=C.cast(pl, C.POINTER(nbgs_plane)))
+            self._params_arr[i] = make_params(s, precision, warm_start)
+        self.precision = precision
+        self.warm_start = warm_start
+        self._params = self._params_arr[0]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.batch = nbgs_batch_create(ns, self.offsets, self._bodies, self._domains, self._params_arr, cache_path,
+                                       self.stream.cuda_stream)
+        self.handle = nbgs_batch_scene(self.batch)
+        self.walls = np.concatenate([[0], np.cumsum([len(s.planes) for s in scenes])]).astype(np.int64)
+
+    def close(self):
+        if getattr(self, "batch", None):
+            nbgs_batch_destroy(self.batch)
+            self.batch = None
+            self.handle = None
+
+    def set_params(self, precision=None, warm_start=None, **overrides):
+        raise NotImplementedError("batched scenes keep the parameters they were created with")
+
+    def step_batch(self, n_steps: int, max_sweeps: int, target: float = 0.0) -> Dict:
+        st, code = nbgs_batch_step(self.batch, n_steps, max_sweeps, target)
+        d = self._stats(st)
+        d["converged"] = code == NBGS_OK
+        return d
+
+    def scene_stats(self):
+        """(contacts, colours) per scene of the last detected step."""
+        return nbgs_batch_scene_stats(self.batch, len(self.scenes))
+
+    def split(self, arr: np.ndarray):
+        """Per-body array of the whole batch -> list of per-scene arrays."""
+        return [arr[self.offsets[i]:self.offsets[i + 1]] for i in range(len(self.scenes))]
+
+    def scene_contacts(self, c: Dict[str, np.ndarray], i: int) -> Dict[str, np.ndarray]:
+        """Contacts of scene i from contacts() in its own numbering (bodies from 0, walls n_i + w, keys rebuilt)."""
+        b0, b1 = int(self.offsets[i]), int(self.offsets[i + 1])
+        sel = (c["j1"] >= b0) & (c["j1"] < b1)
+        out = {k: v[sel] for k, v in c.items()}
+        j1 = out["j1"].astype(np.int64) - b0
+        j2 = out["j2"].astype(np.int64)
+        wall = j2 >= self.n
+        j2 = np.where(wall, (b1 - b0) + (j2 - self.n - self.walls[i]), j2 - b0)
+        out["j1"], out["j2"] = j1.astype(np.int32), j2.astype(np.int32)
+        out["key"] = ((j1.astype(np.uint64) << np.uint64(32)) | j2.astype(np.uint64)).astype(np.uint64)
+        return out

@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libnbgs.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("NBGS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "sort.hip", "detect.hip", "colour.hip", "sweep.hip", "mlp.hip", "warmstart.hip"]
-OPTIONAL = ["batch.hip"]
+SOURCES = ["api.hip", "sort.hip", "detect.hip", "colour.hip", "sweep.hip", "mlp.hip", "warmstart.hip", "tune.hip",
+           "batch.hip"]
 
 COMMON = [
     "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
@@ -37,9 +37,7 @@ def hipcc() -> str:
 
 
 def sources():
-    out = [os.path.join(CSRC, s) for s in SOURCES]
-    out += [os.path.join(CSRC, s) for s in OPTIONAL if os.path.exists(os.path.join(CSRC, s))]
-    return out
+    return [os.path.join(CSRC, s) for s in SOURCES]
 
 
 def build(verbose: bool = False) -> str:

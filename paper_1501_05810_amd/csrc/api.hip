@@ -6,7 +6,7 @@
 #include <new>
 #include <algorithm>
 
-#include "nbgs_internal.h"
+#include "scene.h"
 
 namespace nbgs {
 
@@ -25,149 +25,11 @@ void set_error(const char *fmt, ...) {
     g_last_error = buf;
 }
 
-struct ContactBuf {
-    DevBuf<int32_t> j1, j2, colour;
-    DevBuf<uint64_t> key;
-    DevBuf<double> nx, ny, nz, xi, a1, a2, px, py, pz;
-    nbgs_status reserve(size_t n) {
-        NBGS_TRY(j1.reserve(n));
-        NBGS_TRY(j2.reserve(n));
-        NBGS_TRY(colour.reserve(n));
-        NBGS_TRY(key.reserve(n));
-        for (DevBuf<double> *b : {&nx, &ny, &nz, &xi, &a1, &a2, &px, &py, &pz}) NBGS_TRY(b->reserve(n));
-        return NBGS_OK;
-    }
-    ContactsView view() {
-        ContactsView v;
-        v.j1 = j1.p;
-        v.j2 = j2.p;
-        v.key = key.p;
-        v.nx = nx.p;
-        v.ny = ny.p;
-        v.nz = nz.p;
-        v.xi = xi.p;
-        v.a1 = a1.p;
-        v.a2 = a2.p;
-        v.px = px.p;
-        v.py = py.p;
-        v.pz = pz.p;
-        v.colour = colour.p;
-        return v;
-    }
-};
-
-template <class T>
-struct SweepBuf {
-    DevBuf<int32_t> j1, j2, perm;
-    DevBuf<T> nx, ny, nz, bias, a1, a2, px, py, pz;
-    nbgs_status reserve(size_t n) {
-        NBGS_TRY(j1.reserve(n));
-        NBGS_TRY(j2.reserve(n));
-        NBGS_TRY(perm.reserve(n));
-        for (DevBuf<T> *b : {&nx, &ny, &nz, &bias, &a1, &a2, &px, &py, &pz}) NBGS_TRY(b->reserve(n));
-        return NBGS_OK;
-    }
-    SweepView<T> view() {
-        SweepView<T> v;
-        v.j1 = j1.p;
-        v.j2 = j2.p;
-        v.perm = perm.p;
-        v.nx = nx.p;
-        v.ny = ny.p;
-        v.nz = nz.p;
-        v.bias = bias.p;
-        v.a1 = a1.p;
-        v.a2 = a2.p;
-        v.px = px.p;
-        v.py = py.p;
-        v.pz = pz.p;
-        return v;
-    }
-};
-
-enum Phase { kDetect = 0, kColour = 1, kInit = 2, kSweeps = 3, kIntegrate = 4, kNumPhases = 5 };
-
 }  // namespace nbgs
 
 using namespace nbgs;
 
-struct nbgs_scene_s {
-    BodiesView b{};
-    PlaneSet planes{};
-    double lo[3], hi[3];
-    int32_t periodic[3];
-    nbgs_params p{};
-    hipStream_t s = nullptr;
-    Grid grid{};
-
-    // per body
-    DevBuf<double> h;
-    DevBuf<uint32_t> keys, ids, keys2, ids2;
-    DevBuf<double4> sxr;
-    DevBuf<int32_t> cnt, off;
-    DevBuf<int32_t> deg2, off2, cursor;
-    DevBuf<double> vel64;
-    DevBuf<float> vel32;
-    // cells
-    DevBuf<int32_t> cell_start, cell_end;
-    DevBuf<uint32_t> cell_stamp;
-    uint32_t stamp = 0;
-    // scratch
-    DevBuf<int32_t> radix_hist;
-    DevBuf<char> scan_tmp;
-    DevBuf<int32_t> small;  // [0] total, [1] remaining, [2] overflow, [8..12) ctrl, [16..528) colour histograms
-    DevBuf<unsigned long long> maxbits;
-    int32_t *pinned = nullptr;  // host mirror of small
-    // contacts
-    ContactBuf cb[2];
-    int cur = 0;
-    bool table_in_cur = false;
-    int64_t nc = 0, n_prev = 0;
-    DevBuf<int32_t> inc2;
-    DevBuf<uint64_t> prio;
-    bool prev_colours = false;  // the previous table holds the colours of its contact set
-    int32_t colour_passes = 0;  // > 0: passes from the previous colours, < 0: Jones-Plassmann rounds
-    DevBuf<uint32_t> ckeys, cids, ckeys2, cids2;
-    SweepBuf<double> sw64;
-    SweepBuf<float> sw32;
-    int32_t n_colours = 0;
-    std::vector<int64_t> col_off;
-    std::vector<int64_t> part_off;
-    SweepTune tune[2];  // per precision (NBGS_FP64, NBGS_FP32_SWEEP)
-    int64_t n_partials = 0;
-    DevBuf<double> partials;
-    DevBuf<double> res_hist;
-    int32_t precision_used = NBGS_FP64;
-    int state = 0;  // 0 idle, 1 detected, 2 solved
-    nbgs_stats stats{};
-    hipEvent_t ev[kNumPhases + 1] = {};
-    bool ev_ok[kNumPhases + 1] = {};
-    std::vector<int64_t> col_dyn;  // dynamic bodies touched per colour
-    // learned warm start
-    nbgs_mlp_t mlp = nullptr;
-    bool capture = false;
-    FeatureScales fs{1.0, 1.0, 1.0};
-    double mean_mass = 1.0, mean_radius = 1.0;
-    DevBuf<float> feat, yout;
-    DevBuf<double> frame, lpx, lpy, lpz, jpart, jres;
-    bool have_features = false, have_learned = false;
-    bool solved = false;  // a solve ran since the last detect
-    nbgs_warm_info winfo{-1, 0.0, 0.0};
-    // sweep-kernel profiling (event pair around every sweep launch)
-    bool profiling = false;
-    std::vector<hipEvent_t> pev;
-    nbgs_profile prof{};
-
-    int32_t *total() { return small.p + 0; }
-    int32_t *remaining() { return small.p + 1; }
-    int32_t *overflow() { return small.p + 2; }
-    int32_t *ctrl() { return small.p + 8; }
-    int32_t *chist() { return small.p + 16; }
-};
-
 namespace {
-
-constexpr int kSmallInts = 16 + 512;
 
 nbgs_status check_params(const nbgs_params *p) {
     if (!p) {
@@ -228,34 +90,35 @@ int bits_for(int64_t n) {
     return b;
 }
 
-// Cell grid for the largest hull diameter 2 max(r + h).
-nbgs_status make_grid(nbgs_scene_t sc, double max_reach) {
-    Grid &g = sc->grid;
+// Cell grid of one box for the largest hull diameter 2 max(r + h), with at
+// most max(8 n, 2^16) cells for n bodies.
+Grid grid_for_box(const double lo[3], const double hi[3], const int32_t periodic[3], int64_t n, double max_reach) {
+    Grid g{};
     const double cell = 2.0 * max_reach * (1.0 + 1e-9);
     int64_t dims[3];
     double edge[3];
     for (int a = 0; a < 3; ++a) {
-        const double L = sc->hi[a] - sc->lo[a];
-        g.lo[a] = sc->lo[a];
-        g.hi[a] = sc->hi[a];
+        const double L = hi[a] - lo[a];
+        g.lo[a] = lo[a];
+        g.hi[a] = hi[a];
         g.L[a] = L;
-        g.periodic[a] = sc->periodic[a];
+        g.periodic[a] = periodic[a];
         double c = std::floor(L / cell);
         if (!(c >= 1.0)) c = 1.0;
         if (c > 1.0e6) c = 1.0e6;
-        if (sc->periodic[a] && c < 3.0) c = 1.0;  // one cell: every partner is tested by minimum image
+        if (periodic[a] && c < 3.0) c = 1.0;  // one cell: every partner is tested by minimum image
         dims[a] = (int64_t)c;
-        edge[a] = sc->periodic[a] ? L / c : cell;
+        edge[a] = periodic[a] ? L / c : cell;
     }
     // keep the table within a few cells per body
-    const int64_t cap = std::max<int64_t>(8 * (int64_t)sc->b.n, 1 << 16);
+    const int64_t cap = std::max<int64_t>(8 * n, 1 << 16);
     while (dims[0] * dims[1] * dims[2] > cap) {
         for (int a = 0; a < 3; ++a) {
             if (dims[a] <= 1) continue;
             int64_t c = std::max<int64_t>(1, dims[a] / 2);
-            if (sc->periodic[a] && c < 3) c = 1;
+            if (periodic[a] && c < 3) c = 1;
             dims[a] = c;
-            edge[a] = sc->periodic[a] ? g.L[a] / (double)c : edge[a] * 2.0;
+            edge[a] = periodic[a] ? g.L[a] / (double)c : edge[a] * 2.0;
         }
     }
     for (int a = 0; a < 3; ++a) {
@@ -264,6 +127,36 @@ nbgs_status make_grid(nbgs_scene_t sc, double max_reach) {
     }
     g.ncells = (int32_t)(dims[0] * dims[1] * dims[2]);
     g.key_bits = bits_for(g.ncells);
+    g.cell_off = 0;
+    return g;
+}
+
+// The scene's grid, or for batched scenes one grid per scene laid out one
+// after another in a shared cell table (sc->grid then only carries the total
+// cell count and key width).
+nbgs_status make_grid(nbgs_scene_t sc, double max_reach) {
+    if (sc->n_scenes <= 1) {
+        sc->grid = grid_for_box(sc->lo, sc->hi, sc->periodic, sc->b.n, max_reach);
+        return NBGS_OK;
+    }
+    int64_t off = 0;
+    for (int s = 0; s < sc->n_scenes; ++s) {
+        const int64_t ns = sc->body_off_h[s + 1] - sc->body_off_h[s];
+        Grid g = grid_for_box(&sc->lo_h[3 * s], &sc->hi_h[3 * s], &sc->periodic_h[3 * s], ns, max_reach);
+        g.cell_off = (uint32_t)off;
+        off += g.ncells;
+        if (off > (int64_t)0x7fffffff) {
+            set_error("the cell tables of the batched scenes exceed 2^31 cells");
+            return NBGS_ERR_CAPACITY;
+        }
+        sc->grids_pinned[s] = g;
+    }
+    Grid total{};
+    total.ncells = (int32_t)off;
+    total.key_bits = bits_for(off);
+    sc->grid = total;
+    NBGS_HIP(hipMemcpyAsync(sc->grids_d.p, sc->grids_pinned, sizeof(Grid) * sc->n_scenes, hipMemcpyHostToDevice,
+                            sc->s));
     return NBGS_OK;
 }
 
@@ -298,8 +191,10 @@ nbgs_status sync_small(nbgs_scene_t sc, int first, int count) {
 template <class T>
 nbgs_status gather_for_sweeps(nbgs_scene_t sc, const uint32_t *perm) {
     SweepBuf<T> &sw = sweep_buf<T>(sc);
+    sw.per_contact_mu = sc->n_scenes > 1;
     NBGS_TRY(sw.reserve((size_t)sc->nc));
-    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), perm, sc->nc, sc->p.dt, sc->p.erp, sw.view(), sc->s);
+    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), perm, sc->nc, sc->p.dt, sc->p.erp, sc->table(), sw.view(),
+                                  sc->s);
 }
 
 nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
@@ -326,7 +221,8 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     }
     NBGS_TRY(make_grid(sc, max_reach));
     // cell list
-    NBGS_TRY(launch_cell_keys(sc->b, sc->grid, sc->keys.p, sc->ids.p, s));
+    const SceneTable tab = sc->table();
+    NBGS_TRY(launch_cell_keys(sc->b, sc->grid, tab, sc->keys.p, sc->ids.p, s));
     bool alt = false;
     NBGS_TRY(radix_sort_pairs(sc->keys.p, sc->ids.p, sc->keys2.p, sc->ids2.p, N, sc->grid.key_bits,
                               sc->radix_hist.p, sc->scan_tmp.p, sc->scan_tmp.cap, &alt, s));
@@ -346,7 +242,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_TRY(launch_cells(sc->b, sc->grid, skeys, sids, sc->h.p, sc->cell_start.p, sc->cell_end.p,
                           sc->cell_stamp.p, sc->stamp, sc->sxr.p, s));
     // count, scan, emit
-    NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
+    NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
                                sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p, s));
     NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, N, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_TRY(sync_small(sc, 0, 1));
@@ -358,13 +254,13 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     sc->nc = nc;
     ContactBuf &cb = sc->cb[sc->cur];
     NBGS_TRY(cb.reserve((size_t)nc));
-    NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
+    NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->off.p, cb.view(), s));
     // initial impulses and, when the previous table carries colours, the start of the colouring
     const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
     NBGS_TRY(launch_match_prev(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p, sc->n_prev,
-                               sc->p.mu, warm_impulses, warm_colours, s));
+                               sc->p.mu, tab, warm_impulses, warm_colours, s));
     if (!warm_impulses) NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
     // network features and prediction (from the state before the step and the previous impulses)
     sc->have_features = false;
@@ -389,7 +285,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     // colouring: body -> contacts where it is j2 (as j1 it owns the segment off[i] .. off[i] + cnt[i])
     NBGS_TRY(sc->inc2.reserve((size_t)(nc > 0 ? nc : 1)));
     NBGS_TRY(sc->prio.reserve((size_t)(nc > 0 ? nc : 1)));
-    NBGS_TRY(launch_prio(cb.view(), nc, sc->p.colour_seed, sc->prio.p, s));
+    NBGS_TRY(launch_prio(cb.view(), nc, sc->p.colour_seed, tab, N, sc->prio.p, s));
     NBGS_TRY(launch_j2_degree(cb.view(), nc, N, sc->b.inv_mass, sc->deg2.p, s));
     NBGS_TRY(exclusive_scan_i32(sc->deg2.p, sc->off2.p, (int64_t)N + 1, nullptr, sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_HIP(hipMemcpyAsync(sc->cursor.p, sc->off2.p, sizeof(int32_t) * ((size_t)N + 1), hipMemcpyDeviceToDevice, s));
@@ -463,9 +359,9 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
                               sc->scan_tmp.p, sc->scan_tmp.cap, &calt, s));
     const uint32_t *perm = calt ? sc->cids2.p : sc->cids.p;
     if (nc == 1) perm = sc->cids.p;
-    if (sc->p.precision == NBGS_FP32_SWEEP) NBGS_TRY(gather_for_sweeps<float>(sc, perm));
-    else NBGS_TRY(gather_for_sweeps<double>(sc, perm));
+    sc->perm = perm;
     sc->precision_used = sc->p.precision;
+    NBGS_TRY(scene_gather(sc));
     sc->state = 1;
     sc->stats.n_contacts = nc;
     sc->stats.n_colours = sc->n_colours;
@@ -500,6 +396,22 @@ constexpr double body_bytes() {
 template <class T>
 nbgs_status accumulate_profile(nbgs_scene_t sc, int32_t sweeps) {
     NBGS_HIP(hipStreamSynchronize(sc->s));
+    if (sc->graph_pairs > 0) {  // graph replay: one event pair per replayed block of sweeps, residuals included
+        for (int q = 0; q < sc->graph_pairs; ++q) {
+            float ms = 0.0f;
+            NBGS_HIP(hipEventElapsedTime(&ms, sc->pev[2 * q], sc->pev[2 * q + 1]));
+            sc->prof.sweep_kernel_ms += ms;
+        }
+        for (int c = 0; c < sc->n_colours; ++c) {
+            const int64_t m = sc->col_off[c + 1] - sc->col_off[c];
+            if (m == 0) continue;
+            sc->prof.sweep_launches += sweeps;
+            sc->prof.contact_updates += (int64_t)sweeps * m;
+            sc->prof.sweep_bytes +=
+                (double)sweeps * (contact_bytes<T>() * (double)m + body_bytes<T>() * (double)sc->col_dyn[c]);
+        }
+        return NBGS_OK;
+    }
     size_t pe = 0;
     for (int32_t k = 0; k < sweeps; ++k)
         for (int c = 0; c < sc->n_colours; ++c, ++pe) {
@@ -545,6 +457,131 @@ nbgs_status judge_warm_start(nbgs_scene_t sc) {
     return NBGS_OK;
 }
 
+// Enqueue k sweeps (every colour from its device-side range, then the
+// residual) on stream cs.
+template <class T>
+nbgs_status enqueue_dev_sweeps(nbgs_scene_t sc, int32_t k, double target, const SweepTune &tune, unsigned grid,
+                               hipStream_t cs) {
+    SweepBuf<T> &sw = sweep_buf<T>(sc);
+    DevBuf<T> &vel = vel_buf<T>(sc);
+    const SweepParams sp{sc->p.mu, sc->p.relax};
+    const int C = sc->n_colours;
+    for (int32_t it = 0; it < k; ++it) {
+        for (int c = 0; c < C; ++c)
+            NBGS_TRY(launch_sweep_colour_dev<T>(sw.view(), sc->col_d.p, c, sc->b.n, vel.p, sp, tune,
+                                                sc->partials.p + 2 * (size_t)c * grid, sc->ctrl(), cs));
+        NBGS_TRY(launch_residual(sc->partials.p, (int32_t)((int64_t)C * grid), target, sc->ctrl(), sc->res_hist.p, cs));
+    }
+    return NBGS_OK;
+}
+
+}  // namespace
+
+namespace nbgs {
+
+nbgs_status scene_gather(nbgs_scene_t sc) {
+    if (sc->precision_used == NBGS_FP32_SWEEP) return gather_for_sweeps<float>(sc, sc->perm);
+    return gather_for_sweeps<double>(sc, sc->perm);
+}
+
+// The sweep loop replayed from a captured graph: blocks of up to 32 sweeps
+// are captured once (on a private stream, re-captured when the colour count,
+// launch shape, buffers or parameters change) and launched on the scene's
+// stream; the colour ranges are uploaded per solve, so one graph serves every
+// step.  Sweeps after the target is met exit at once, as in the direct loop.
+template <class T>
+nbgs_status scene_sweep_loop(nbgs_scene_t sc, int32_t max_sweeps, double target, const SweepTune &tune) {
+    hipStream_t s = sc->s;
+    SweepBuf<T> &sw = sweep_buf<T>(sc);
+    DevBuf<T> &vel = vel_buf<T>(sc);
+    const int C = sc->n_colours;
+    const unsigned grid = sweep_graph_grid<T>(tune);
+    if (grid == 0) {
+        set_error("unsupported sweep tuning for graph replay");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    NBGS_TRY(sc->partials.reserve(2 * (size_t)((int64_t)C * grid + 1)));
+    NBGS_TRY(sc->col_d.reserve((size_t)C + 1));
+    if (sc->col_pinned_cap < (size_t)C + 1) {
+        if (sc->col_pinned) (void)hipHostFree(sc->col_pinned);
+        sc->col_pinned = nullptr;
+        sc->col_pinned_cap = 0;
+        const size_t want = (size_t)C + 65;
+        NBGS_HIP(hipHostMalloc((void **)&sc->col_pinned, want * sizeof(int64_t)));
+        sc->col_pinned_cap = want;
+    }
+    // the previous upload from this staging area has completed: every solve ends with a stream synchronisation
+    // before the next one starts, or the caller synchronised after a solve without statistics
+    NBGS_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c <= C; ++c) sc->col_pinned[c] = sc->col_off[c];
+    NBGS_HIP(hipMemcpyAsync(sc->col_d.p, sc->col_pinned, sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, s));
+    const int32_t K = std::min<int32_t>(max_sweeps, 32);
+    nbgs_scene_s::GraphKey key;
+    key.sweeps = K;
+    key.colours = C;
+    key.prec = (int32_t)sizeof(T);
+    key.grid = grid;
+    key.tune = tune;
+    key.ptrs[0] = sw.j1.p;
+    key.ptrs[1] = sw.px.p;
+    key.ptrs[2] = sw.mu.p;
+    key.ptrs[3] = vel.p;
+    key.ptrs[4] = sc->partials.p;
+    key.ptrs[5] = sc->res_hist.p;
+    key.col = sc->col_d.p;
+    key.target = target;
+    key.mu = sc->p.mu;
+    key.relax = sc->p.relax;
+    if (!sc->gexec || !(key == sc->gkey)) {
+        if (sc->gexec) (void)hipGraphExecDestroy(sc->gexec);
+        sc->gexec = nullptr;
+        if (!sc->cap_stream) NBGS_HIP(hipStreamCreateWithFlags(&sc->cap_stream, hipStreamNonBlocking));
+        NBGS_HIP(hipStreamBeginCapture(sc->cap_stream, hipStreamCaptureModeRelaxed));
+        const nbgs_status st = enqueue_dev_sweeps<T>(sc, K, target, tune, grid, sc->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(sc->cap_stream, &g);
+        if (st != NBGS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        NBGS_HIP(e);
+        const hipError_t ei = hipGraphInstantiate(&sc->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        NBGS_HIP(ei);
+        sc->gkey = key;
+    }
+    const int32_t reps = max_sweeps / K, rem = max_sweeps % K;
+    const bool prof = sc->profiling;
+    if (prof) NBGS_TRY(ensure_profile_events(sc, (size_t)reps + 1));
+    int q = 0;
+    bool done = false;
+    for (int32_t r = 0; r < reps && !done; ++r) {
+        if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * q], s));
+        NBGS_HIP(hipGraphLaunch(sc->gexec, s));
+        if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * q + 1], s));
+        ++q;
+        if (target > 0.0 && (r + 1 < reps || rem > 0)) {
+            NBGS_TRY(sync_small(sc, 8, 3));
+            done = sc->pinned[8] != 0;
+        }
+    }
+    if (!done && rem > 0) {
+        if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * q], s));
+        NBGS_TRY(enqueue_dev_sweeps<T>(sc, rem, target, tune, grid, s));
+        if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * q + 1], s));
+        ++q;
+    }
+    sc->graph_pairs = prof ? q : 0;
+    return NBGS_OK;
+}
+
+template nbgs_status scene_sweep_loop<double>(nbgs_scene_t, int32_t, double, const SweepTune &);
+template nbgs_status scene_sweep_loop<float>(nbgs_scene_t, int32_t, double, const SweepTune &);
+
+}  // namespace nbgs
+
+namespace {
+
 template <class T>
 nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats) {
     hipStream_t s = sc->s;
@@ -574,7 +611,13 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
     int32_t launched = 0, chunk = target > 0.0 ? 4 : max_sweeps;
     bool done = false;
     const bool prof = sc->profiling;
-    if (prof) NBGS_TRY(ensure_profile_events(sc, (size_t)max_sweeps * sc->n_colours));
+    sc->graph_pairs = 0;
+    if (tune.graph) {
+        NBGS_TRY(scene_sweep_loop<T>(sc, max_sweeps, target, tune));
+        done = true;
+    } else if (prof) {
+        NBGS_TRY(ensure_profile_events(sc, (size_t)max_sweeps * sc->n_colours));
+    }
     size_t pe = 0;
     while (launched < max_sweeps && !done) {
         const int32_t k = std::min(chunk, max_sweeps - launched);
@@ -631,7 +674,7 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
 template <class T>
 nbgs_status integrate_impl(nbgs_scene_t sc) {
     record(sc, kIntegrate);
-    NBGS_TRY(launch_integrate<T>(sc->b, sc->grid, sc->p.dt, vel_buf<T>(sc).p, sc->s));
+    NBGS_TRY(launch_integrate<T>(sc->b, sc->grid, sc->table(), sc->p.dt, vel_buf<T>(sc).p, sc->s));
     record(sc, kNumPhases);
     sc->table_in_cur = true;
     sc->n_prev = sc->nc;
@@ -640,42 +683,125 @@ nbgs_status integrate_impl(nbgs_scene_t sc) {
     return NBGS_OK;
 }
 
+nbgs_status check_domain(const nbgs_domain *domain) {
+    return NBGS_OK;
+}
+
+PlaneSet plane_set(const nbgs_domain *domain) {
+    PlaneSet ps{};
+    ps.n = domain->n_planes;
+    for (int w = 0; w < domain->n_planes; ++w)
+        for (int a = 0; a < 3; ++a) {
+            ps.p[w][a] = domain->planes[w].point[a];
+            ps.nrm[w][a] = domain->planes[w].normal[a];
+        }
+    return ps;
+}
+
+// Per-scene tables of a batch: body -> scene, body and wall offsets, walls,
+// friction coefficients and colouring seeds (device copies), boxes (host).
+nbgs_status setup_scene_tables(nbgs_scene_t sc, int32_t n_scenes, const int64_t *body_off, const nbgs_domain *domains,
+                               const nbgs_params *params) {
+    const int32_t N = sc->b.n;
+    sc->body_off_h.resize((size_t)n_scenes + 1);
+    sc->wall_off_h.resize((size_t)n_scenes + 1);
+    sc->planes_h.resize((size_t)n_scenes);
+    sc->lo_h.resize(3 * (size_t)n_scenes);
+    sc->hi_h.resize(3 * (size_t)n_scenes);
+    sc->periodic_h.resize(3 * (size_t)n_scenes);
+    sc->mu_h.resize((size_t)n_scenes);
+    sc->seed_h.resize((size_t)n_scenes);
+    std::vector<int32_t> body_scene((size_t)N);
+    int32_t walls = 0;
+    for (int32_t s = 0; s < n_scenes; ++s) {
+        sc->body_off_h[s] = (int32_t)body_off[s];
+        sc->wall_off_h[s] = walls;
+        walls += domains[s].n_planes;
+        sc->planes_h[s] = plane_set(&domains[s]);
+        for (int a = 0; a < 3; ++a) {
+            sc->lo_h[3 * s + a] = domains[s].lo[a];
+            sc->hi_h[3 * s + a] = domains[s].hi[a];
+            sc->periodic_h[3 * s + a] = domains[s].periodic[a] ? 1 : 0;
+        }
+        sc->mu_h[s] = params[s].mu;
+        sc->seed_h[s] = params[s].colour_seed;
+        for (int64_t i = body_off[s]; i < body_off[s + 1]; ++i) body_scene[(size_t)i] = s;
+    }
+    sc->body_off_h[n_scenes] = N;
+    sc->wall_off_h[n_scenes] = walls;
+    NBGS_TRY(sc->body_scene_d.reserve((size_t)N, 1.0));
+    NBGS_TRY(sc->body_off_d.reserve((size_t)n_scenes + 1, 1.0));
+    NBGS_TRY(sc->wall_off_d.reserve((size_t)n_scenes + 1, 1.0));
+    NBGS_TRY(sc->grids_d.reserve((size_t)n_scenes, 1.0));
+    NBGS_TRY(sc->planes_d.reserve((size_t)n_scenes, 1.0));
+    NBGS_TRY(sc->mu_d.reserve((size_t)n_scenes, 1.0));
+    NBGS_TRY(sc->seed_d.reserve((size_t)n_scenes, 1.0));
+    NBGS_HIP(hipMemcpy(sc->body_scene_d.p, body_scene.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice));
+    NBGS_HIP(hipMemcpy(sc->body_off_d.p, sc->body_off_h.data(), sizeof(int32_t) * (n_scenes + 1), hipMemcpyHostToDevice));
+    NBGS_HIP(hipMemcpy(sc->wall_off_d.p, sc->wall_off_h.data(), sizeof(int32_t) * (n_scenes + 1), hipMemcpyHostToDevice));
+    NBGS_HIP(hipMemcpy(sc->planes_d.p, sc->planes_h.data(), sizeof(PlaneSet) * n_scenes, hipMemcpyHostToDevice));
+    NBGS_HIP(hipMemcpy(sc->mu_d.p, sc->mu_h.data(), sizeof(double) * n_scenes, hipMemcpyHostToDevice));
+    NBGS_HIP(hipMemcpy(sc->seed_d.p, sc->seed_h.data(), sizeof(uint64_t) * n_scenes, hipMemcpyHostToDevice));
+    NBGS_HIP(hipHostMalloc((void **)&sc->grids_pinned, sizeof(Grid) * n_scenes));
+    // batches replay their sweeps from a captured graph over a resident grid unless tuned otherwise
+    for (SweepTune &t : sc->tune) {
+        t.graph = 1;
+        t.persistent = 1;
+    }
+    return NBGS_OK;
+}
+
 }  // namespace
 
 namespace nbgs {
-const char *last_error_cstr();
-}
 
-#define NBGS_GUARD(sc)                                                                                          \
-    do {                                                                                                        \
-        if (!(sc)) {                                                                                            \
-            set_error("scene handle is NULL");                                                                  \
-            return NBGS_ERR_INVALID_ARG;                                                                        \
-        }                                                                                                       \
-    } while (0)
-
-extern "C" {
-
-int32_t nbgs_abi_version(void) { return NBGS_ABI_VERSION; }
-
-const char *nbgs_last_error(void) { return nbgs::last_error_cstr(); }
-
-nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *domain, const nbgs_params *params,
-                              void *hip_stream, nbgs_scene_t *out) {
-    if (!out) {
-        set_error("out is NULL");
-        return NBGS_ERR_INVALID_ARG;
-    }
+nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int64_t *body_off,
+                         const nbgs_domain *domains, const nbgs_params *params, void *hip_stream, nbgs_scene_t *out) {
     *out = nullptr;
-    if (!bodies || !domain) {
-        set_error("bodies or domain is NULL");
+    if (!bodies || !domains || !params || !body_off) {
+        set_error("bodies, domains, params or body offsets is NULL");
         return NBGS_ERR_INVALID_ARG;
     }
-    NBGS_TRY(check_params(params));
+    if (n_scenes < 1) {
+        set_error("at least one scene is needed");
+        return NBGS_ERR_INVALID_ARG;
+    }
     if (bodies->n < 1 || bodies->n >= (int64_t)0x7fffffc0) {
         set_error("body count %lld out of range", (long long)bodies->n);
         return NBGS_ERR_INVALID_ARG;
     }
+    int64_t n_walls = 0;
+    for (int32_t s = 0; s < n_scenes; ++s) {
+        NBGS_TRY(check_params(&params[s]));
+        NBGS_TRY(check_domain(&domains[s]));
+        if (!(body_off[s + 1] > body_off[s])) {
+            set_error("scene %d holds no body (offsets must increase)", s);
+            return NBGS_ERR_INVALID_ARG;
+        }
+        n_walls += domains[s].n_planes;
+        if (s > 0) {
+            const nbgs_params &a = params[0], &b = params[s];
+            if (a.dt != b.dt || a.gravity[0] != b.gravity[0] || a.gravity[1] != b.gravity[1] ||
+                a.gravity[2] != b.gravity[2] || a.tau != b.tau || a.relax != b.relax || a.erp != b.erp ||
+                a.precision != b.precision || a.warm_start != b.warm_start) {
+                set_error("batched scenes may differ only in mu and colour_seed (scene %d differs)", s);
+                return NBGS_ERR_INVALID_ARG;
+            }
+        }
+    }
+    if (body_off[0] != 0 || body_off[n_scenes] != bodies->n) {
+        set_error("body offsets must run from 0 to the body count");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (n_scenes > 1 && params[0].warm_start == NBGS_WS_LEARNED) {
+        set_error("the learned warm start is not available for batched scenes");
+        return NBGS_ERR_UNSUPPORTED;
+    }
+    if (bodies->n + n_walls >= (int64_t)0x7fffffc0) {
+        set_error("too many bodies and walls");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    const nbgs_domain *domain = &domains[0];
     const void *ptrs[] = {bodies->x,  bodies->y,  bodies->z,  bodies->qw, bodies->qx, bodies->qy,
                           bodies->qz, bodies->vx, bodies->vy, bodies->vz, bodies->wx, bodies->wy,
                           bodies->wz, bodies->radius, bodies->inv_mass, bodies->inv_inertia};
@@ -684,23 +810,6 @@ nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *doma
             set_error("a body array pointer is NULL");
             return NBGS_ERR_INVALID_ARG;
         }
-    if (domain->n_planes < 0 || domain->n_planes > PlaneSet::kMax || (domain->n_planes > 0 && !domain->planes)) {
-        set_error("n_planes must lie in [0, %d] with a plane array", PlaneSet::kMax);
-        return NBGS_ERR_INVALID_ARG;
-    }
-    for (int a = 0; a < 3; ++a)
-        if (!(domain->hi[a] > domain->lo[a]) || !std::isfinite(domain->hi[a] - domain->lo[a])) {
-            set_error("domain box must have hi > lo on every axis");
-            return NBGS_ERR_INVALID_ARG;
-        }
-    for (int w = 0; w < domain->n_planes; ++w) {
-        const double *nm = domain->planes[w].normal;
-        const double len = std::sqrt(nm[0] * nm[0] + nm[1] * nm[1] + nm[2] * nm[2]);
-        if (!(std::fabs(len - 1.0) < 1e-12)) {
-            set_error("plane %d normal is not unit length", w);
-            return NBGS_ERR_INVALID_ARG;
-        }
-    }
     nbgs_scene_t sc = new (std::nothrow) nbgs_scene_s();
     if (!sc) {
         set_error("host allocation failed");
@@ -725,18 +834,14 @@ nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *doma
     b.radius = bodies->radius;
     b.inv_mass = bodies->inv_mass;
     b.inv_inertia = bodies->inv_inertia;
-    sc->planes.n = domain->n_planes;
-    for (int w = 0; w < domain->n_planes; ++w)
-        for (int a = 0; a < 3; ++a) {
-            sc->planes.p[w][a] = domain->planes[w].point[a];
-            sc->planes.nrm[w][a] = domain->planes[w].normal[a];
-        }
+    sc->planes = plane_set(domain);
     for (int a = 0; a < 3; ++a) {
         sc->lo[a] = domain->lo[a];
         sc->hi[a] = domain->hi[a];
         sc->periodic[a] = domain->periodic[a] ? 1 : 0;
     }
-    sc->p = *params;
+    sc->p = params[0];
+    sc->n_scenes = n_scenes;
     const size_t N = (size_t)b.n;
     nbgs_status st = NBGS_OK;
     auto chk = [&](nbgs_status x) {
@@ -799,12 +904,49 @@ nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *doma
             }
         }
     }
+    if (st == NBGS_OK && n_scenes > 1) st = setup_scene_tables(sc, n_scenes, body_off, domains, params);
     if (st != NBGS_OK) {
         nbgs_scene_destroy(sc);
         return st;
     }
     *out = sc;
     return NBGS_OK;
+}
+
+}  // namespace nbgs
+
+
+namespace nbgs {
+const char *last_error_cstr();
+}
+
+#define NBGS_GUARD(sc)                                                                                          \
+    do {                                                                                                        \
+        if (!(sc)) {                                                                                            \
+            set_error("scene handle is NULL");                                                                  \
+            return NBGS_ERR_INVALID_ARG;                                                                        \
+        }                                                                                                       \
+    } while (0)
+
+extern "C" {
+
+int32_t nbgs_abi_version(void) { return NBGS_ABI_VERSION; }
+
+const char *nbgs_last_error(void) { return nbgs::last_error_cstr(); }
+
+nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *domain, const nbgs_params *params,
+                              void *hip_stream, nbgs_scene_t *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!bodies) {
+        set_error("bodies is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    const int64_t off[2] = {0, bodies->n};
+    return scene_create(bodies, 1, off, domain, params, hip_stream, out);
 }
 
 nbgs_status nbgs_scene_destroy(nbgs_scene_t sc) {
@@ -814,6 +956,10 @@ nbgs_status nbgs_scene_destroy(nbgs_scene_t sc) {
         if (sc->ev[i]) (void)hipEventDestroy(sc->ev[i]);
     for (hipEvent_t e : sc->pev) (void)hipEventDestroy(e);
     if (sc->pinned) (void)hipHostFree(sc->pinned);
+    if (sc->grids_pinned) (void)hipHostFree(sc->grids_pinned);
+    if (sc->col_pinned) (void)hipHostFree(sc->col_pinned);
+    if (sc->gexec) (void)hipGraphExecDestroy(sc->gexec);
+    if (sc->cap_stream) (void)hipStreamDestroy(sc->cap_stream);
     delete sc;
     return NBGS_OK;
 }
@@ -821,6 +967,10 @@ nbgs_status nbgs_scene_destroy(nbgs_scene_t sc) {
 nbgs_status nbgs_scene_set_params(nbgs_scene_t sc, const nbgs_params *params) {
     NBGS_GUARD(sc);
     NBGS_TRY(check_params(params));
+    if (sc->n_scenes > 1 && params->warm_start == NBGS_WS_LEARNED) {
+        set_error("the learned warm start is not available for batched scenes");
+        return NBGS_ERR_UNSUPPORTED;
+    }
     sc->p = *params;
     update_scales(sc);
     return NBGS_OK;
@@ -975,12 +1125,20 @@ nbgs_status nbgs_get_phase_times(nbgs_scene_t sc, int32_t n, double *out) {
 
 nbgs_status nbgs_scene_attach_mlp(nbgs_scene_t sc, nbgs_mlp_t mlp) {
     NBGS_GUARD(sc);
+    if (sc->n_scenes > 1) {
+        set_error("the learned warm start is not available for batched scenes");
+        return NBGS_ERR_UNSUPPORTED;
+    }
     sc->mlp = mlp;
     return NBGS_OK;
 }
 
 nbgs_status nbgs_set_feature_capture(nbgs_scene_t sc, int32_t enable) {
     NBGS_GUARD(sc);
+    if (sc->n_scenes > 1 && enable) {
+        set_error("network features are not available for batched scenes");
+        return NBGS_ERR_UNSUPPORTED;
+    }
     sc->capture = enable != 0;
     return NBGS_OK;
 }
@@ -1039,13 +1197,16 @@ nbgs_status nbgs_set_tuning(nbgs_scene_t sc, int32_t precision, const nbgs_tunin
     st.nontemporal = t->nontemporal;
     st.full_store = t->full_store;
     st.persistent = t->persistent;
+    st.graph = t->graph;
     if (!sweep_tune_supported(st)) {
         set_error("unsupported tuning: block %d, contacts_per_thread %d, xcd_remap %d, nontemporal %d, full_store %d, "
-                  "persistent %d",
-                  t->block, t->contacts_per_thread, t->xcd_remap, t->nontemporal, t->full_store, t->persistent);
+                  "persistent %d, graph %d",
+                  t->block, t->contacts_per_thread, t->xcd_remap, t->nontemporal, t->full_store, t->persistent,
+                  t->graph);
         return NBGS_ERR_INVALID_ARG;
     }
     sc->tune[precision] = st;
+    sc->tuned[precision] = true;
     return NBGS_OK;
 }
 
@@ -1062,6 +1223,7 @@ nbgs_status nbgs_get_tuning(nbgs_scene_t sc, int32_t precision, nbgs_tuning *t) 
     t->nontemporal = st.nontemporal;
     t->full_store = st.full_store;
     t->persistent = st.persistent;
+    t->graph = st.graph;
     return NBGS_OK;
 }
 

@@ -78,9 +78,24 @@ __device__ inline void probe(Probe &pr, const ContactsView &c, const uint64_t *p
     if (precedes(prio[l], c.key[l], pr.prio, pr.key)) pr.blocked = true;
 }
 
-__global__ void __launch_bounds__(kBlock) k_prio(const uint64_t *key, int64_t nc, uint64_t seed, uint64_t *prio) {
+// Priority from the pair key in the numbering of the contact's own scene
+// (body i -> i - body_off[s], wall w of the scene -> n_s + w) and the scene's
+// seed: a batched scene gets the priorities it would have alone.
+__global__ void __launch_bounds__(kBlock) k_prio(const uint64_t *key, int64_t nc, uint64_t seed, SceneTable st,
+                                                 int32_t nb, uint64_t *prio) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < nc) prio[j] = splitmix64(key[j] ^ seed);
+    if (j >= nc) return;
+    uint64_t k = key[j];
+    uint64_t sd = seed;
+    if (st.body_scene) {
+        const uint32_t i1 = (uint32_t)(k >> 32), i2 = (uint32_t)k;
+        const int sc = st.body_scene[i1];
+        const uint32_t b0 = (uint32_t)st.body_off[sc], ns = (uint32_t)st.body_off[sc + 1] - b0;
+        const uint32_t l2 = i2 < (uint32_t)nb ? i2 - b0 : ns + (i2 - (uint32_t)nb - (uint32_t)st.wall_off[sc]);
+        k = ((uint64_t)(i1 - b0) << 32) | (uint64_t)l2;
+        sd = st.seed[sc];
+    }
+    prio[j] = splitmix64(k ^ sd);
 }
 
 __global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, const uint64_t *prio, int64_t nc, int32_t nb,
@@ -195,11 +210,12 @@ __global__ void __launch_bounds__(kBlock) k_colour_keys(const int32_t *colour, i
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_gather_sweep(ContactsView c, const uint32_t *perm, int64_t nc, double dt,
-                                                         double erp, SweepView<T> sv) {
+                                                         double erp, SceneTable st, SweepView<T> sv) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= nc) return;
     const int64_t j = perm[p];
     sv.perm[p] = (int32_t)j;
+    if (sv.mu) sv.mu[p] = (T)st.mu[st.body_scene[c.j1[j]]];
     sv.j1[p] = c.j1[j];
     sv.j2[p] = c.j2[j];
     sv.nx[p] = (T)c.nx[j];
@@ -234,9 +250,10 @@ nbgs_status launch_j2_fill(const ContactsView &c, int64_t nc, int32_t nb, const 
     return NBGS_OK;
 }
 
-nbgs_status launch_prio(const ContactsView &c, int64_t nc, uint64_t seed, uint64_t *prio, hipStream_t s) {
+nbgs_status launch_prio(const ContactsView &c, int64_t nc, uint64_t seed, const SceneTable &st, int32_t nb,
+                        uint64_t *prio, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_prio<<<grid_for(nc), kBlock, 0, s>>>(c.key, nc, seed, prio);
+    k_prio<<<grid_for(nc), kBlock, 0, s>>>(c.key, nc, seed, st, nb, prio);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -279,16 +296,16 @@ nbgs_status launch_colour_keys(const ContactsView &c, int64_t nc, uint32_t *keys
 
 template <class T>
 nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, int64_t nc, double dt, double erp,
-                                SweepView<T> sv, hipStream_t s) {
+                                const SceneTable &st, SweepView<T> sv, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, perm, nc, dt, erp, sv);
+    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, perm, nc, dt, erp, st, sv);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
 template nbgs_status launch_gather_sweep<double>(const ContactsView &, const uint32_t *, int64_t, double, double,
-                                                 SweepView<double>, hipStream_t);
+                                                 const SceneTable &, SweepView<double>, hipStream_t);
 template nbgs_status launch_gather_sweep<float>(const ContactsView &, const uint32_t *, int64_t, double, double,
-                                                SweepView<float>, hipStream_t);
+                                                const SceneTable &, SweepView<float>, hipStream_t);
 
 }  // namespace nbgs

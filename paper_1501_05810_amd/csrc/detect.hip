@@ -61,13 +61,20 @@ __device__ inline int cell_coord(double x, double lo, double edge, int dims) {
     return (int)c;
 }
 
-__global__ void __launch_bounds__(kBlock) k_cell_keys(BodiesView b, Grid g, uint32_t *keys, uint32_t *ids) {
+// The grid of body i: its scene's (batched scenes) or the single one.
+__device__ inline const Grid &grid_of(const Grid &g, const SceneTable &st, int i) {
+    return st.body_scene ? st.grids[st.body_scene[i]] : g;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_keys(BodiesView b, Grid g0, SceneTable st, uint32_t *keys,
+                                                      uint32_t *ids) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= b.n) return;
+    const Grid &g = grid_of(g0, st, i);
     const int cx = cell_coord(b.x[i], g.lo[0], g.edge[0], g.dims[0]);
     const int cy = cell_coord(b.y[i], g.lo[1], g.edge[1], g.dims[1]);
     const int cz = cell_coord(b.z[i], g.lo[2], g.edge[2], g.dims[2]);
-    keys[i] = (uint32_t)((cz * g.dims[1] + cy) * g.dims[0] + cx);
+    keys[i] = g.cell_off + (uint32_t)((cz * g.dims[1] + cy) * g.dims[0] + cx);
     ids[i] = (uint32_t)i;
 }
 
@@ -101,7 +108,8 @@ struct NeighbourRange {
     int lo[3], hi[3];
 };
 
-__device__ inline NeighbourRange neighbour_range(uint32_t key, const Grid &g, int c[3]) {
+__device__ inline NeighbourRange neighbour_range(uint32_t gkey, const Grid &g, int c[3]) {
+    const uint32_t key = gkey - g.cell_off;
     c[0] = (int)(key % (uint32_t)g.dims[0]);
     const uint32_t t = key / (uint32_t)g.dims[0];
     c[1] = (int)(t % (uint32_t)g.dims[1]);
@@ -130,7 +138,7 @@ __device__ inline int neighbour_cell(const Grid &g, const int c[3], int dx, int 
             q[a] = q[a] < 0 ? q[a] + g.dims[a] : q[a] - g.dims[a];
         }
     }
-    return (q[2] * g.dims[1] + q[1]) * g.dims[0] + q[0];
+    return (int)g.cell_off + (q[2] * g.dims[1] + q[1]) * g.dims[0] + q[0];
 }
 
 // Hull overlap of sorted entries (own, other): |x_i - x_k|^2 <= ((r_i + h_i) + (r_k + h_k))^2.
@@ -178,7 +186,7 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
     return m;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g, PlaneSet pl, double tau,
+__global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                        const uint32_t *skeys, const uint32_t *sids,
                                                        const double4 *sxr, const double *h,
                                                        const int32_t *cell_start, const int32_t *cell_end,
@@ -186,6 +194,9 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g, Pla
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= b.n) return;
     const int i = (int)sids[p];
+    const int sc = st.body_scene ? st.body_scene[i] : 0;
+    const Grid &g = st.body_scene ? st.grids[sc] : g0;
+    const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
     int m = visit_partners<false>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, nullptr);
     if (b.inv_mass[i] != 0.0) {
         const double4 me = sxr[p];
@@ -197,7 +208,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g, Pla
     cnt[i] = m;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g, PlaneSet pl, double tau,
+__global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                       const uint32_t *skeys, const uint32_t *sids,
                                                       const double4 *sxr, const double *h,
                                                       const int32_t *cell_start, const int32_t *cell_end,
@@ -206,6 +217,10 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g, Plan
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= b.n) return;
     const int i = (int)sids[p];
+    const int sc = st.body_scene ? st.body_scene[i] : 0;
+    const Grid &g = st.body_scene ? st.grids[sc] : g0;
+    const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
+    const int wall0 = b.n + (st.body_scene ? st.wall_off[sc] : 0);
     const int base = off[i];
     int32_t *ks = c.j2 + base;
     const int m = visit_partners<true>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, ks);
@@ -256,7 +271,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g, Plan
         for (int w = 0; w < pl.n; ++w) {
             if (!plane_hit(pl, w, xi_, yi, zi, ri, hi, tau, &gap)) continue;
             const int j = base + t++;
-            const int k = b.n + w;
+            const int k = wall0 + w;
             c.j1[j] = i;
             c.j2[j] = k;
             c.key[j] = ((uint64_t)(uint32_t)i << 32) | (uint64_t)(uint32_t)k;
@@ -278,9 +293,11 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g, Plan
 __global__ void __launch_bounds__(kBlock) k_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key,
                                                        const double *prev_px, const double *prev_py,
                                                        const double *prev_pz, const int32_t *prev_colour,
-                                                       int64_t n_prev, double mu, int impulses, int colours) {
+                                                       int64_t n_prev, double mu0, SceneTable st, int impulses,
+                                                       int colours) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc) return;
+    const double mu = st.body_scene ? st.mu[st.body_scene[c.j1[j]]] : mu0;
     const uint64_t key = c.key[j];
     int64_t lo = 0, hi = n_prev;
     while (lo < hi) {
@@ -315,6 +332,11 @@ __global__ void __launch_bounds__(kBlock) k_match_prev(ContactsView c, int64_t n
     c.pz[j] = P2;
 }
 
+__global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 }  // namespace
 
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
@@ -324,8 +346,9 @@ nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, u
     return NBGS_OK;
 }
 
-nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, uint32_t *keys, uint32_t *ids, hipStream_t s) {
-    k_cell_keys<<<grid_for(b.n), kBlock, 0, s>>>(b, g, keys, ids);
+nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, uint32_t *keys, uint32_t *ids,
+                             hipStream_t s) {
+    k_cell_keys<<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, keys, ids);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -339,21 +362,21 @@ nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *ske
     return NBGS_OK;
 }
 
-nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, double tau,
+nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                               const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
                               uint32_t stamp, int32_t *cnt, hipStream_t s) {
-    k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, tau, skeys, sids, sxr, h, cell_start, cell_end,
+    k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
                                                   cell_stamp, stamp, cnt);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
-nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, double tau,
+nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
                              uint32_t stamp, const int32_t *off, ContactsView c, hipStream_t s) {
-    k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, tau, skeys, sids, sxr, h, cell_start, cell_end,
+    k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
                                                  cell_stamp, stamp, off, c);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
@@ -361,10 +384,11 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
 
 nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
                               const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
-                              int64_t n_prev, double mu, bool impulses, bool colours, hipStream_t s) {
+                              int64_t n_prev, double mu, const SceneTable &st, bool impulses, bool colours,
+                              hipStream_t s) {
     if (nc == 0 || (!impulses && !colours)) return NBGS_OK;
     k_match_prev<<<grid_for(nc), kBlock, 0, s>>>(c, nc, prev_key, prev_px, prev_py, prev_pz, prev_colour, n_prev, mu,
-                                                 impulses ? 1 : 0, colours ? 1 : 0);
+                                                 st, impulses ? 1 : 0, colours ? 1 : 0);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -374,6 +398,13 @@ nbgs_status launch_zero_impulses(ContactsView c, int64_t nc, hipStream_t s) {
     NBGS_HIP(hipMemsetAsync(c.px, 0, sizeof(double) * nc, s));
     NBGS_HIP(hipMemsetAsync(c.py, 0, sizeof(double) * nc, s));
     NBGS_HIP(hipMemsetAsync(c.pz, 0, sizeof(double) * nc, s));
+    return NBGS_OK;
+}
+
+nbgs_status launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return NBGS_OK;
+    k_fill_i32<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
+    NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 

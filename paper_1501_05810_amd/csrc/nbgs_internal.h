@@ -84,6 +84,26 @@ struct Grid {
     double L[3];
     int32_t ncells;
     int32_t key_bits;
+    uint32_t cell_off;  // first global cell of this grid (several scenes share one cell table)
+};
+
+// Several independent scenes held in one body array (batching).  Every array
+// is indexed by scene except body_scene (by body).  All null for a single
+// scene, whose grid, walls and friction coefficient come as plain arguments.
+// Scene s owns bodies body_off[s] .. body_off[s + 1] - 1 and walls with ids
+// n + wall_off[s] .. n + wall_off[s + 1] - 1 (n = all bodies); its contacts are
+// coloured with the priorities of its own numbering (body i -> i - body_off[s],
+// wall -> n_s + w) and its own seed, so it is coloured, ordered and relaxed
+// exactly as it would be alone.
+struct SceneTable {
+    const int32_t *body_scene = nullptr;
+    const int32_t *body_off = nullptr;
+    const int32_t *wall_off = nullptr;
+    const Grid *grids = nullptr;
+    const PlaneSet *planes = nullptr;
+    const double *mu = nullptr;
+    const uint64_t *seed = nullptr;
+    int32_t n_scenes = 1;
 };
 
 // Canonical (key-ordered) contact list, structure of arrays.
@@ -101,6 +121,7 @@ struct SweepView {
     int32_t *j1, *j2;
     int32_t *perm;  // sweep position -> canonical index
     T *nx, *ny, *nz, *bias, *a1, *a2, *px, *py, *pz;
+    T *mu;  // friction coefficient per contact (batched scenes), null: one coefficient for all
 };
 
 // ------------------------------------------------------- kernel launchers
@@ -117,21 +138,24 @@ size_t radix_hist_entries(int64_t n);
 // detect.hip
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
                         hipStream_t s);
-nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, uint32_t *keys, uint32_t *ids, hipStream_t s);
+nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, uint32_t *keys, uint32_t *ids,
+                             hipStream_t s);
 nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
                          const double *h, int32_t *cell_start, int32_t *cell_end, uint32_t *cell_stamp,
                          uint32_t stamp, double4 *sxr, hipStream_t s);
-nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, double tau,
+nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                               const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
                               uint32_t stamp, int32_t *cnt, hipStream_t s);
-nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, double tau,
+nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
                              uint32_t stamp, const int32_t *off, ContactsView c, hipStream_t s);
 nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
                               const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
-                              int64_t n_prev, double mu, bool impulses, bool colours, hipStream_t s);
+                              int64_t n_prev, double mu, const SceneTable &st, bool impulses, bool colours,
+                              hipStream_t s);
+nbgs_status launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 nbgs_status launch_zero_impulses(ContactsView c, int64_t nc, hipStream_t s);
 
 // colour.hip
@@ -139,7 +163,8 @@ nbgs_status launch_j2_degree(const ContactsView &c, int64_t nc, int32_t nb, cons
                              hipStream_t s);
 nbgs_status launch_j2_fill(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *cursor,
                            int32_t *inc2, hipStream_t s);
-nbgs_status launch_prio(const ContactsView &c, int64_t nc, uint64_t seed, uint64_t *prio, hipStream_t s);
+nbgs_status launch_prio(const ContactsView &c, int64_t nc, uint64_t seed, const SceneTable &st, int32_t nb,
+                        uint64_t *prio, hipStream_t s);
 nbgs_status launch_jp_round(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
                             const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
                             const int32_t *inc2, int32_t *remaining, int32_t *overflow, hipStream_t s);
@@ -151,7 +176,7 @@ nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t nb, co
 nbgs_status launch_colour_keys(const ContactsView &c, int64_t nc, uint32_t *keys, uint32_t *ids, hipStream_t s);
 template <class T>
 nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, int64_t nc, double dt, double erp,
-                                SweepView<T> sv, hipStream_t s);
+                                const SceneTable &st, SweepView<T> sv, hipStream_t s);
 
 // sweep.hip
 struct SweepParams {
@@ -168,16 +193,26 @@ struct SweepTune {
     int32_t nontemporal = 0; // non-temporal hint on the streamed contact arrays
     int32_t full_store = 0;  // write whole body records back
     int32_t persistent = 0;  // at most one resident round of workgroups, each walking several tiles
+    int32_t graph = 0;       // sweeps replayed from a captured HIP graph (colour ranges read on the device)
 };
 int64_t sweep_tile(const SweepTune &t);
 bool sweep_tune_supported(const SweepTune &t);
 template <class T>
 nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, SweepParams sp,
                                 const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s);
+// The same sweep for colour c whose range col[c] .. col[c + 1] is read on the
+// device, over a fixed number of workgroups (sweep_graph_grid); workgroup b
+// writes its partial sums to partials[2 b], [2 b + 1].
+template <class T>
+unsigned sweep_graph_grid(const SweepTune &t);
+template <class T>
+nbgs_status launch_sweep_colour_dev(SweepView<T> sv, const int64_t *col, int32_t c, int32_t nb, T *vel, SweepParams sp,
+                                    const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s);
 nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl,
                             double *hist, hipStream_t s);
 template <class T>
-nbgs_status launch_integrate(const BodiesView &b, const Grid &g, double dt, const T *vel, hipStream_t s);
+nbgs_status launch_integrate(const BodiesView &b, const Grid &g, const SceneTable &st, double dt, const T *vel,
+                             hipStream_t s);
 template <class T>
 nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hipStream_t s);
 template <class T>

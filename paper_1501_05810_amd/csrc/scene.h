@@ -1,0 +1,229 @@
+// The scene object behind the C ABI: borrowed body arrays, per-step device
+// buffers, the contact tables of this and the previous step, and the host-side
+// state of one time step (shared by the scene, batch and tuning entry points).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "nbgs_internal.h"
+
+namespace nbgs {
+
+struct ContactBuf {
+    DevBuf<int32_t> j1, j2, colour;
+    DevBuf<uint64_t> key;
+    DevBuf<double> nx, ny, nz, xi, a1, a2, px, py, pz;
+    nbgs_status reserve(size_t n) {
+        NBGS_TRY(j1.reserve(n));
+        NBGS_TRY(j2.reserve(n));
+        NBGS_TRY(colour.reserve(n));
+        NBGS_TRY(key.reserve(n));
+        for (DevBuf<double> *b : {&nx, &ny, &nz, &xi, &a1, &a2, &px, &py, &pz}) NBGS_TRY(b->reserve(n));
+        return NBGS_OK;
+    }
+    ContactsView view() {
+        ContactsView v;
+        v.j1 = j1.p;
+        v.j2 = j2.p;
+        v.key = key.p;
+        v.nx = nx.p;
+        v.ny = ny.p;
+        v.nz = nz.p;
+        v.xi = xi.p;
+        v.a1 = a1.p;
+        v.a2 = a2.p;
+        v.px = px.p;
+        v.py = py.p;
+        v.pz = pz.p;
+        v.colour = colour.p;
+        return v;
+    }
+};
+
+template <class T>
+struct SweepBuf {
+    DevBuf<int32_t> j1, j2, perm;
+    DevBuf<T> nx, ny, nz, bias, a1, a2, px, py, pz, mu;
+    bool per_contact_mu = false;
+    nbgs_status reserve(size_t n) {
+        NBGS_TRY(j1.reserve(n));
+        NBGS_TRY(j2.reserve(n));
+        NBGS_TRY(perm.reserve(n));
+        for (DevBuf<T> *b : {&nx, &ny, &nz, &bias, &a1, &a2, &px, &py, &pz}) NBGS_TRY(b->reserve(n));
+        if (per_contact_mu) NBGS_TRY(mu.reserve(n));
+        return NBGS_OK;
+    }
+    SweepView<T> view() {
+        SweepView<T> v;
+        v.j1 = j1.p;
+        v.j2 = j2.p;
+        v.perm = perm.p;
+        v.nx = nx.p;
+        v.ny = ny.p;
+        v.nz = nz.p;
+        v.bias = bias.p;
+        v.a1 = a1.p;
+        v.a2 = a2.p;
+        v.px = px.p;
+        v.py = py.p;
+        v.pz = pz.p;
+        v.mu = per_contact_mu ? mu.p : nullptr;
+        return v;
+    }
+};
+
+enum Phase { kDetect = 0, kColour = 1, kInit = 2, kSweeps = 3, kIntegrate = 4, kNumPhases = 5 };
+
+}  // namespace nbgs
+
+using namespace nbgs;
+
+struct nbgs_scene_s {
+    BodiesView b{};
+    PlaneSet planes{};
+    double lo[3], hi[3];
+    int32_t periodic[3];
+    nbgs_params p{};
+    hipStream_t s = nullptr;
+    Grid grid{};
+
+    // per body
+    DevBuf<double> h;
+    DevBuf<uint32_t> keys, ids, keys2, ids2;
+    DevBuf<double4> sxr;
+    DevBuf<int32_t> cnt, off;
+    DevBuf<int32_t> deg2, off2, cursor;
+    DevBuf<double> vel64;
+    DevBuf<float> vel32;
+    // cells
+    DevBuf<int32_t> cell_start, cell_end;
+    DevBuf<uint32_t> cell_stamp;
+    uint32_t stamp = 0;
+    // scratch
+    DevBuf<int32_t> radix_hist;
+    DevBuf<char> scan_tmp;
+    DevBuf<int32_t> small;  // [0] total, [1] remaining, [2] overflow, [8..12) ctrl, [16..528) colour histograms
+    DevBuf<unsigned long long> maxbits;
+    int32_t *pinned = nullptr;  // host mirror of small
+    // contacts
+    ContactBuf cb[2];
+    int cur = 0;
+    bool table_in_cur = false;
+    int64_t nc = 0, n_prev = 0;
+    DevBuf<int32_t> inc2;
+    DevBuf<uint64_t> prio;
+    bool prev_colours = false;  // the previous table holds the colours of its contact set
+    int32_t colour_passes = 0;  // > 0: passes from the previous colours, < 0: Jones-Plassmann rounds
+    DevBuf<uint32_t> ckeys, cids, ckeys2, cids2;
+    const uint32_t *perm = nullptr;  // sweep position -> canonical index (in ckeys/cids storage)
+    SweepBuf<double> sw64;
+    SweepBuf<float> sw32;
+    int32_t n_colours = 0;
+    std::vector<int64_t> col_off;
+    std::vector<int64_t> part_off;
+    SweepTune tune[2];  // per precision (NBGS_FP64, NBGS_FP32_SWEEP)
+    int64_t n_partials = 0;
+    DevBuf<double> partials;
+    DevBuf<double> res_hist;
+    int32_t precision_used = NBGS_FP64;
+    int state = 0;  // 0 idle, 1 detected, 2 solved
+    nbgs_stats stats{};
+    hipEvent_t ev[kNumPhases + 1] = {};
+    bool ev_ok[kNumPhases + 1] = {};
+    std::vector<int64_t> col_dyn;  // dynamic bodies touched per colour
+    // learned warm start
+    nbgs_mlp_t mlp = nullptr;
+    bool capture = false;
+    FeatureScales fs{1.0, 1.0, 1.0};
+    double mean_mass = 1.0, mean_radius = 1.0;
+    DevBuf<float> feat, yout;
+    DevBuf<double> frame, lpx, lpy, lpz, jpart, jres;
+    bool have_features = false, have_learned = false;
+    bool solved = false;  // a solve ran since the last detect
+    nbgs_warm_info winfo{-1, 0.0, 0.0};
+    // sweep-kernel profiling (event pair around every sweep launch)
+    bool profiling = false;
+    std::vector<hipEvent_t> pev;
+    nbgs_profile prof{};
+
+    // batched scenes (n_scenes > 1): per-scene boxes, walls, friction, seeds
+    int32_t n_scenes = 1;
+    std::vector<int32_t> body_off_h, wall_off_h;
+    std::vector<PlaneSet> planes_h;
+    std::vector<double> lo_h, hi_h, mu_h;  // 3 per scene for lo, hi
+    std::vector<int32_t> periodic_h;        // 3 per scene
+    std::vector<uint64_t> seed_h;
+    DevBuf<int32_t> body_scene_d, body_off_d, wall_off_d;
+    DevBuf<Grid> grids_d;
+    DevBuf<PlaneSet> planes_d;
+    DevBuf<double> mu_d;
+    DevBuf<uint64_t> seed_d;
+    Grid *grids_pinned = nullptr;
+    std::vector<int64_t> scene_contacts;  // per scene, last detect (filled on request)
+    // sweeps replayed from a captured graph
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        int32_t sweeps = -1, colours = -1, prec = -1;
+        unsigned grid = 0;
+        SweepTune tune{};
+        const void *ptrs[6] = {};
+        const void *col = nullptr;
+        double target = 0.0, mu = 0.0, relax = 0.0;
+        bool operator==(const GraphKey &o) const {
+            if (sweeps != o.sweeps || colours != o.colours || prec != o.prec || grid != o.grid || col != o.col ||
+                target != o.target || mu != o.mu || relax != o.relax)
+                return false;
+            if (std::memcmp(&tune, &o.tune, sizeof(tune)) != 0) return false;
+            for (int i = 0; i < 6; ++i)
+                if (ptrs[i] != o.ptrs[i]) return false;
+            return true;
+        }
+    } gkey;
+    int graph_pairs = 0;  // profiling event pairs of the last graph-replayed solve
+    DevBuf<int64_t> col_d;
+    int64_t *col_pinned = nullptr;
+    size_t col_pinned_cap = 0;
+    // sweep-tuning cache file (empty: none)
+    std::string tune_cache;
+    bool tuned[2] = {false, false};
+
+    nbgs::SceneTable table() const {
+        nbgs::SceneTable t;
+        if (n_scenes <= 1) return t;
+        t.body_scene = body_scene_d.p;
+        t.body_off = body_off_d.p;
+        t.wall_off = wall_off_d.p;
+        t.grids = grids_d.p;
+        t.planes = planes_d.p;
+        t.mu = mu_d.p;
+        t.seed = seed_d.p;
+        t.n_scenes = n_scenes;
+        return t;
+    }
+    int32_t *total() { return small.p + 0; }
+    int32_t *remaining() { return small.p + 1; }
+    int32_t *overflow() { return small.p + 2; }
+    int32_t *ctrl() { return small.p + 8; }
+    int32_t *chist() { return small.p + 16; }
+};
+
+
+namespace nbgs {
+
+constexpr int kSmallInts = 16 + 512;
+
+// Scene set-up shared by nbgs_scene_create (one scene) and nbgs_batch_create
+// (n_scenes scenes in one body array; body_off: n_scenes + 1 host offsets).
+nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int64_t *body_off,
+                         const nbgs_domain *domains, const nbgs_params *params, void *hip_stream, nbgs_scene_t *out);
+// Sweep tuning: the cached choice for this scene's size, else a search over
+// launch shapes on the scene's current contacts whose trial sweeps leave no
+// trace (the initial impulses are restored afterwards).
+nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen, double *best_ms);
+nbgs_status scene_gather(nbgs_scene_t sc);
+template <class T>
+nbgs_status scene_sweep_loop(nbgs_scene_t sc, int32_t max_sweeps, double target, const SweepTune &tune);
+
+}  // namespace nbgs

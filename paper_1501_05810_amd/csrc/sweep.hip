@@ -194,19 +194,18 @@ __device__ inline TileWalk tile_walk(unsigned b, unsigned P, unsigned G, int xcd
 }
 
 // One tile of one colour: each thread relaxes CPT contacts (strided by the
-// block size, all contact loads issued before any arithmetic).  partials
-// receives (sum |dP|^2, sum |P|^2) of the tile; ctrl[0] != 0 means an earlier
-// sweep already met the residual target (checked after the contact loads are
-// in flight, so the flag's latency is hidden behind them).
+// block size, all contact loads issued before any arithmetic) and adds
+// |dP|^2 and |P|^2 to sd, sp.  Returns true when ctrl[0] != 0, i.e. an earlier
+// sweep already met the residual target (the flag is read after the contact
+// loads are in flight, so its latency hides behind them; it is the same for
+// the whole grid and does not change during a launch).
 template <class T, int BLOCK, int CPT, bool NT, bool FULL>
-__device__ inline void sweep_tile_body(const SweepView<T> &sv, int64_t begin, int64_t end, int32_t nb, T *vel, T mu,
-                                       T relax, double *partials, const int32_t *ctrl, unsigned tile,
-                                       double (*red)[BLOCK / 64]) {
+__device__ inline bool sweep_tile_body(const SweepView<T> &sv, int64_t begin, int64_t end, int32_t nb, T *vel, T mu,
+                                       T relax, const int32_t *ctrl, unsigned tile, double &sd, double &sp) {
     const int64_t p0 = begin + (int64_t)tile * (BLOCK * CPT) + threadIdx.x;
-    double sd = 0.0, sp = 0.0;
     int b1[CPT], b2[CPT];
     bool ok[CPT];
-    T n[CPT][3], bias[CPT], a1[CPT], a2[CPT], P[CPT][3];
+    T n[CPT][3], bias[CPT], a1[CPT], a2[CPT], P[CPT][3], muk[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
         const int64_t p = p0 + (int64_t)k * BLOCK;
@@ -223,8 +222,9 @@ __device__ inline void sweep_tile_body(const SweepView<T> &sv, int64_t begin, in
         P[k][0] = ld<NT>(sv.px + q);
         P[k][1] = ld<NT>(sv.py + q);
         P[k][2] = ld<NT>(sv.pz + q);
+        muk[k] = sv.mu ? ld<NT>(sv.mu + q) : mu;
     }
-    if (ctrl[0]) return;  // uniform over the grid: the flag does not change during a launch
+    if (ctrl[0]) return true;
     Rec<T> r1[CPT], r2[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
@@ -259,7 +259,7 @@ __device__ inline void sweep_tile_body(const SweepView<T> &sv, int64_t begin, in
         if (!(pn > T(0))) pn = T(0);
         T t0 = -bt[0] / wt, t1 = -bt[1] / wt, t2 = -bt[2] / wt;
         const T tl = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-        const T lim = mu * pn;
+        const T lim = muk[k] * pn;
         if (tl > lim) {
             const T sc = lim / tl;
             t0 = t0 * sc;
@@ -285,6 +285,12 @@ __device__ inline void sweep_tile_body(const SweepView<T> &sv, int64_t begin, in
         sd += d0 * d0 + d1 * d1 + d2 * d2;
         sp += q0 * q0 + q1 * q1 + q2 * q2;
     }
+    return false;
+}
+
+// Workgroup sums of sd, sp (waves, then the waves in a fixed order) into out[0], out[1].
+template <int BLOCK>
+__device__ inline void block_partials(double sd, double sp, double (*red)[BLOCK / 64], double *out) {
     sd = wave_sum(sd);
     sp = wave_sum(sp);
     const int wave = threadIdx.x >> 6;
@@ -300,21 +306,41 @@ __device__ inline void sweep_tile_body(const SweepView<T> &sv, int64_t begin, in
             a += red[0][w];
             c += red[1][w];
         }
-        partials[2 * tile + 0] = a;
-        partials[2 * tile + 1] = c;
+        out[0] = a;
+        out[1] = c;
     }
     __syncthreads();  // red is reused by the workgroup's next tile
 }
 
-// One colour of one sweep over G tiles by gridDim.x workgroups.
+// One colour of one sweep over G tiles by gridDim.x workgroups; partial sums per tile.
 template <class T, int BLOCK, int CPT, bool NT, bool FULL>
 __global__ void __launch_bounds__(BLOCK) k_sweep(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel,
                                                  T mu, T relax, double *partials, const int32_t *ctrl, unsigned G,
                                                  int xcd_remap) {
     __shared__ double red[2][BLOCK / 64];
     const TileWalk w = tile_walk(blockIdx.x, gridDim.x, G, xcd_remap);
+    for (unsigned t = w.t; t < w.end; t += w.step) {
+        double sd = 0.0, sp = 0.0;
+        if (sweep_tile_body<T, BLOCK, CPT, NT, FULL>(sv, begin, end, nb, vel, mu, relax, ctrl, t, sd, sp)) return;
+        block_partials<BLOCK>(sd, sp, red, partials + 2 * t);
+    }
+}
+
+// Colour c with its range read from col[c], col[c + 1] (so that a captured
+// graph serves every step); partial sums per workgroup, zero for a workgroup
+// without tiles.
+template <class T, int BLOCK, int CPT, bool NT, bool FULL>
+__global__ void __launch_bounds__(BLOCK) k_sweep_dev(SweepView<T> sv, const int64_t *col, int c, int32_t nb, T *vel,
+                                                     T mu, T relax, double *partials, const int32_t *ctrl,
+                                                     int xcd_remap) {
+    __shared__ double red[2][BLOCK / 64];
+    const int64_t begin = col[c], end = col[c + 1];
+    const unsigned G = (unsigned)((end - begin + BLOCK * CPT - 1) / (BLOCK * CPT));
+    const TileWalk w = tile_walk(blockIdx.x, gridDim.x, G, xcd_remap);
+    double sd = 0.0, sp = 0.0;
     for (unsigned t = w.t; t < w.end; t += w.step)
-        sweep_tile_body<T, BLOCK, CPT, NT, FULL>(sv, begin, end, nb, vel, mu, relax, partials, ctrl, t, red);
+        if (sweep_tile_body<T, BLOCK, CPT, NT, FULL>(sv, begin, end, nb, vel, mu, relax, ctrl, t, sd, sp)) return;
+    block_partials<BLOCK>(sd, sp, red, partials + 2 * blockIdx.x);
 }
 
 // R_k = sqrt(sum |dP|^2) / max(sqrt(sum |P|^2), 1e-300), summed in a fixed
@@ -359,9 +385,10 @@ __global__ void __launch_bounds__(kResBlock) k_residual(const double *partials, 
 
 // eq. (integrationscheme) with quaternion renormalisation; periodic wrap.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g, double dt, const T *vel) {
+__global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, SceneTable st, double dt, const T *vel) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= b.n) return;
+    const Grid &g = st.body_scene ? st.grids[st.body_scene[i]] : g0;
     const T *r = vel + 8 * (int64_t)i;
     const double vx = (double)r[0], vy = (double)r[1], vz = (double)r[2];
     const double ox = (double)r[3], oy = (double)r[4], oz = (double)r[5];
@@ -443,7 +470,8 @@ bool sweep_tune_supported(const SweepTune &t) {
     const bool blk = t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512;
     return blk && (t.cpt == 1 || t.cpt == 2 || t.cpt == 4) && (t.xcd_remap == 0 || t.xcd_remap == 1) &&
            (t.nontemporal == 0 || t.nontemporal == 1) && (t.full_store == 0 || t.full_store == 1) &&
-           (t.persistent == 0 || t.persistent == 1 || (t.persistent >= 8 && t.persistent % 8 == 0));
+           (t.persistent == 0 || t.persistent == 1 || (t.persistent >= 8 && t.persistent % 8 == 0)) &&
+           (t.graph == 0 || t.graph == 1);
 }
 
 // Workgroups of a persistent sweep grid: what the device holds resident at
@@ -508,6 +536,65 @@ nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int
     return NBGS_ERR_INVALID_ARG;
 }
 
+// Workgroups of a device-range sweep launch: the explicit cap, else what the
+// device holds resident at once.
+template <class T, int B, int C, bool NT, bool FULL>
+unsigned dev_grid(const SweepTune &t) {
+    if (t.persistent > 1) return (unsigned)t.persistent;
+    static const unsigned cap = persistent_cap(k_sweep_dev<T, B, C, NT, FULL>, B);
+    return cap;
+}
+
+#define NBGS_SWEEP_DEV_DISPATCH(ACTION)                                                                            \
+    do {                                                                                                           \
+        NBGS_SWEEP_DEV_CASE(64, 1, ACTION)                                                                         \
+        NBGS_SWEEP_DEV_CASE(64, 2, ACTION)                                                                         \
+        NBGS_SWEEP_DEV_CASE(64, 4, ACTION)                                                                         \
+        NBGS_SWEEP_DEV_CASE(128, 1, ACTION)                                                                        \
+        NBGS_SWEEP_DEV_CASE(128, 2, ACTION)                                                                        \
+        NBGS_SWEEP_DEV_CASE(128, 4, ACTION)                                                                        \
+        NBGS_SWEEP_DEV_CASE(256, 1, ACTION)                                                                        \
+        NBGS_SWEEP_DEV_CASE(256, 2, ACTION)                                                                        \
+        NBGS_SWEEP_DEV_CASE(256, 4, ACTION)                                                                        \
+        NBGS_SWEEP_DEV_CASE(512, 1, ACTION)                                                                        \
+        NBGS_SWEEP_DEV_CASE(512, 2, ACTION)                                                                        \
+        NBGS_SWEEP_DEV_CASE(512, 4, ACTION)                                                                        \
+    } while (0)
+#define NBGS_SWEEP_DEV_CASE(B, C, ACTION)                                                                          \
+    if (t.block == B && t.cpt == C) {                                                                              \
+        if (t.nontemporal && t.full_store) ACTION(B, C, true, true);                                               \
+        else if (t.nontemporal) ACTION(B, C, true, false);                                                         \
+        else if (t.full_store) ACTION(B, C, false, true);                                                          \
+        else ACTION(B, C, false, false);                                                                           \
+    }
+
+template <class T>
+unsigned sweep_graph_grid(const SweepTune &t) {
+#define NBGS_GRID_OF(B, C, NT, FULL) return dev_grid<T, B, C, NT, FULL>(t)
+    NBGS_SWEEP_DEV_DISPATCH(NBGS_GRID_OF);
+#undef NBGS_GRID_OF
+    return 0;
+}
+
+template <class T>
+nbgs_status launch_sweep_colour_dev(SweepView<T> sv, const int64_t *col, int32_t c, int32_t nb, T *vel, SweepParams sp,
+                                    const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s) {
+    const T mu = (T)sp.mu, relax = (T)sp.relax;
+#define NBGS_LAUNCH_DEV(B, C, NT, FULL)                                                                            \
+    do {                                                                                                           \
+        k_sweep_dev<T, B, C, NT, FULL><<<dev_grid<T, B, C, NT, FULL>(t), B, 0, s>>>(sv, col, c, nb, vel, mu, relax, \
+                                                                                   partials, ctrl, t.xcd_remap);  \
+        NBGS_HIP(hipGetLastError());                                                                               \
+        return NBGS_OK;                                                                                            \
+    } while (0)
+    NBGS_SWEEP_DEV_DISPATCH(NBGS_LAUNCH_DEV);
+#undef NBGS_LAUNCH_DEV
+    set_error("unsupported sweep tuning block=%d cpt=%d", t.block, t.cpt);
+    return NBGS_ERR_INVALID_ARG;
+}
+#undef NBGS_SWEEP_DEV_CASE
+#undef NBGS_SWEEP_DEV_DISPATCH
+
 nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl, double *hist,
                             hipStream_t s) {
     k_residual<<<1, kResBlock, 0, s>>>(partials, n_partials, target, ctrl, hist);
@@ -516,8 +603,9 @@ nbgs_status launch_residual(const double *partials, int32_t n_partials, double t
 }
 
 template <class T>
-nbgs_status launch_integrate(const BodiesView &b, const Grid &g, double dt, const T *vel, hipStream_t s) {
-    k_integrate<T><<<grid_for(b.n), kBlock, 0, s>>>(b, g, dt, vel);
+nbgs_status launch_integrate(const BodiesView &b, const Grid &g, const SceneTable &st, double dt, const T *vel,
+                             hipStream_t s) {
+    k_integrate<T><<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, dt, vel);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -542,7 +630,12 @@ nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, doub
     template nbgs_status launch_warm_scatter<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, hipStream_t);      \
     template nbgs_status launch_sweep_colour<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, SweepParams,       \
                                                 const SweepTune &, double *, const int32_t *, hipStream_t);       \
-    template nbgs_status launch_integrate<T>(const BodiesView &, const Grid &, double, const T *, hipStream_t);   \
+    template nbgs_status launch_integrate<T>(const BodiesView &, const Grid &, const SceneTable &, double, const T *, \
+                                             hipStream_t);                                                        \
+    template unsigned sweep_graph_grid<T>(const SweepTune &);                                                     \
+    template nbgs_status launch_sweep_colour_dev<T>(SweepView<T>, const int64_t *, int32_t, int32_t, T *,         \
+                                                    SweepParams, const SweepTune &, double *, const int32_t *,    \
+                                                    hipStream_t);                                                 \
     template nbgs_status launch_save_impulses<T>(SweepView<T>, int64_t, ContactsView, hipStream_t);              \
     template nbgs_status launch_export_accumulators<T>(const T *, int32_t, double *, double *, hipStream_t);
 

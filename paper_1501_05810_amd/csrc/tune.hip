@@ -1,0 +1,214 @@
+// Sweep-launch autotuner.
+//
+// The launch shape of the sweep (workgroup size, contacts per thread, XCD
+// tile remap, non-temporal contact stream, whole-record stores, persistent
+// workgroups, graph replay) changes no result, only the time.  The tuner
+// times trial solves on the scene's own contacts of the current step and
+// keeps the fastest shape.  A trial changes the sweep record, the body
+// accumulators and the canonical impulses; the initial impulses are saved
+// before the first trial and put back after each one, and the sweep record is
+// rebuilt from them, so the step that follows is the step that would have
+// run without tuning, bit for bit.
+//
+// Search: coordinate descent from the current shape, one parameter at a time
+// over its allowed values, keeping a change only if it is faster by more than
+// 1 %.  A cache file keeps one line per choice,
+//     <arch>|<fp64|fp32>|<scene|batch>|<ceil log2 contacts> block cpt xcd nt full persistent graph ms
+// and the last line of a key wins; a missing or unreadable file is ignored.
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "scene.h"
+
+namespace nbgs {
+
+namespace {
+
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+int ceil_log2(int64_t n) {
+    int b = 0;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+std::string cache_key(nbgs_scene_t sc) {
+    return device_arch() + "|" + (sc->precision_used == NBGS_FP32_SWEEP ? "fp32" : "fp64") + "|" +
+           (sc->n_scenes > 1 ? "batch" : "scene") + "|" + std::to_string(ceil_log2(sc->nc > 0 ? sc->nc : 1));
+}
+
+bool cache_lookup(const std::string &path, const std::string &key, SweepTune &t, double &ms) {
+    if (path.empty()) return false;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[256];
+        SweepTune c;
+        double m = 0.0;
+        if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %lf", k, &c.block, &c.cpt, &c.xcd_remap, &c.nontemporal,
+                        &c.full_store, &c.persistent, &c.graph, &m) != 9)
+            continue;
+        if (key == k && sweep_tune_supported(c)) {
+            t = c;
+            ms = m;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const std::string &path, const std::string &key, const SweepTune &t, double ms) {
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %.6g\n", key.c_str(), t.block, t.cpt, t.xcd_remap, t.nontemporal,
+                 t.full_store, t.persistent, t.graph, ms);
+    std::fclose(f);
+}
+
+struct Saved {
+    DevBuf<double> px, py, pz;
+};
+
+nbgs_status save_impulses(nbgs_scene_t sc, Saved &sv) {
+    const size_t n = (size_t)(sc->nc > 0 ? sc->nc : 1);
+    NBGS_TRY(sv.px.reserve(n, 1.0));
+    NBGS_TRY(sv.py.reserve(n, 1.0));
+    NBGS_TRY(sv.pz.reserve(n, 1.0));
+    ContactBuf &cb = sc->cb[sc->cur];
+    if (sc->nc == 0) return NBGS_OK;
+    NBGS_HIP(hipMemcpyAsync(sv.px.p, cb.px.p, sizeof(double) * sc->nc, hipMemcpyDeviceToDevice, sc->s));
+    NBGS_HIP(hipMemcpyAsync(sv.py.p, cb.py.p, sizeof(double) * sc->nc, hipMemcpyDeviceToDevice, sc->s));
+    NBGS_HIP(hipMemcpyAsync(sv.pz.p, cb.pz.p, sizeof(double) * sc->nc, hipMemcpyDeviceToDevice, sc->s));
+    return NBGS_OK;
+}
+
+// Initial impulses back into the contact table, sweep record rebuilt, step state "detected".
+nbgs_status restore_impulses(nbgs_scene_t sc, const Saved &sv) {
+    ContactBuf &cb = sc->cb[sc->cur];
+    if (sc->nc > 0) {
+        NBGS_HIP(hipMemcpyAsync(cb.px.p, sv.px.p, sizeof(double) * sc->nc, hipMemcpyDeviceToDevice, sc->s));
+        NBGS_HIP(hipMemcpyAsync(cb.py.p, sv.py.p, sizeof(double) * sc->nc, hipMemcpyDeviceToDevice, sc->s));
+        NBGS_HIP(hipMemcpyAsync(cb.pz.p, sv.pz.p, sizeof(double) * sc->nc, hipMemcpyDeviceToDevice, sc->s));
+    }
+    NBGS_TRY(scene_gather(sc));
+    sc->state = 1;
+    sc->solved = false;
+    return NBGS_OK;
+}
+
+nbgs_status trial(nbgs_scene_t sc, const SweepTune &t, int32_t sweeps, const Saved &saved, hipEvent_t e0,
+                  hipEvent_t e1, double &ms) {
+    const int prec = sc->precision_used == NBGS_FP32_SWEEP ? 1 : 0;
+    sc->tune[prec] = t;
+    NBGS_HIP(hipEventRecord(e0, sc->s));
+    NBGS_TRY(nbgs_solve(sc, sweeps, 0.0, nullptr));
+    NBGS_HIP(hipEventRecord(e1, sc->s));
+    NBGS_HIP(hipEventSynchronize(e1));
+    float f = 0.0f;
+    NBGS_HIP(hipEventElapsedTime(&f, e0, e1));
+    ms = (double)f;
+    return restore_impulses(sc, saved);
+}
+
+}  // namespace
+
+nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen, double *best_ms) {
+    if (sc->state != 1) {
+        set_error("autotuning needs a detected, not yet solved step");
+        return NBGS_ERR_STATE;
+    }
+    if (sweeps < 1) {
+        set_error("sweeps must be >= 1");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    const int prec = sc->precision_used == NBGS_FP32_SWEEP ? 1 : 0;
+    const std::string key = cache_key(sc);
+    SweepTune best = sc->tune[prec];
+    double best_t = 0.0;
+    if (!cache_lookup(sc->tune_cache, key, best, best_t)) {
+        Saved saved;
+        NBGS_TRY(save_impulses(sc, saved));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        NBGS_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            set_error("hipEventCreate failed");
+            return NBGS_ERR_DEVICE;
+        }
+        const bool prof = sc->profiling;
+        sc->profiling = false;
+        nbgs_status st = NBGS_OK;
+        // a first, untimed run takes the one-off costs (allocation, code loading, graph capture)
+        double ms = 0.0;
+        st = trial(sc, best, sweeps, saved, e0, e1, ms);
+        if (st == NBGS_OK) st = trial(sc, best, sweeps, saved, e0, e1, best_t);
+        const int blocks[] = {64, 128, 256, 512}, cpts[] = {1, 2, 4}, bits[] = {0, 1};
+        for (int dim = 0; dim < 7 && st == NBGS_OK; ++dim) {
+            const int *vals = dim == 0 ? blocks : dim == 1 ? cpts : bits;
+            const int nv = dim == 0 ? 4 : dim == 1 ? 3 : 2;
+            for (int v = 0; v < nv && st == NBGS_OK; ++v) {
+                SweepTune c = best;
+                int32_t *field = dim == 0   ? &c.block
+                                 : dim == 1 ? &c.cpt
+                                 : dim == 2 ? &c.xcd_remap
+                                 : dim == 3 ? &c.nontemporal
+                                 : dim == 4 ? &c.full_store
+                                 : dim == 5 ? &c.persistent
+                                            : &c.graph;
+                if (*field == vals[v]) continue;
+                *field = vals[v];
+                if (!sweep_tune_supported(c)) continue;
+                if (c.graph) st = trial(sc, c, sweeps, saved, e0, e1, ms);  // capture outside the timing
+                if (st != NBGS_OK) break;
+                st = trial(sc, c, sweeps, saved, e0, e1, ms);
+                if (st == NBGS_OK && ms < 0.99 * best_t) {
+                    best = c;
+                    best_t = ms;
+                }
+            }
+        }
+        sc->profiling = prof;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != NBGS_OK) return st;
+        best_t /= (double)sweeps;
+        cache_store(sc->tune_cache, key, best, best_t);
+    }
+    sc->tune[prec] = best;
+    sc->tuned[prec] = true;
+    if (chosen) {
+        chosen->block = best.block;
+        chosen->contacts_per_thread = best.cpt;
+        chosen->xcd_remap = best.xcd_remap;
+        chosen->nontemporal = best.nontemporal;
+        chosen->full_store = best.full_store;
+        chosen->persistent = best.persistent;
+        chosen->graph = best.graph;
+    }
+    if (best_ms) *best_ms = best_t;
+    return NBGS_OK;
+}
+
+}  // namespace nbgs
+
+extern "C" nbgs_status nbgs_autotune(nbgs_scene_t sc, int32_t sweeps, const char *cache_path, nbgs_tuning *chosen,
+                                     double *ms_per_sweep) {
+    if (!sc) {
+        nbgs::set_error("scene handle is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (cache_path) sc->tune_cache = cache_path;
+    return nbgs::scene_autotune(sc, sweeps, chosen, ms_per_sweep);
+}

@@ -50,3 +50,60 @@ def test_oracle_is_not_imported_by_the_product():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt and "nbgs_ref" not in txt, f
+
+
+def _dummy_bodies(nb, n):
+    # argument validation rejects these calls before any device pointer is touched
+    return nb.nbgs_bodies(n=n, **{f: 0x1000 for f in nb.BODY_FIELDS})
+
+
+def _domains_params(nb, k, dts=None, warm=None):
+    import ctypes as C
+
+    doms = (nb.nbgs_domain * k)()
+    pars = (nb.nbgs_params * k)()
+    for i in range(k):
+        doms[i] = nb.nbgs_domain(lo=(C.c_double * 3)(0, 0, 0), hi=(C.c_double * 3)(1, 1, 1),
+                                 periodic=(C.c_int32 * 3)(0, 0, 0), n_planes=0, planes=None)
+        pars[i] = nb.nbgs_params(dt=(dts[i] if dts else 1e-3), gravity=(C.c_double * 3)(0, 0, -9.81), mu=0.3 + 0.1 * i,
+                                 tau=0.005, relax=1.0, erp=1.0, precision=0,
+                                 warm_start=warm if warm is not None else 1, colour_seed=i)
+    return doms, pars
+
+
+@pytest.mark.parametrize("case", ["dt differs", "learned", "offsets", "empty scene", "no scenes"])
+def test_batch_create_rejects_bad_arguments(case):
+    """Host-side validation of nbgs_batch_create (the status and message, no device work)."""
+    import ctypes as C
+
+    import paper_1501_05810_amd as nb
+
+    L = nb.lib()
+    k = 3
+    offs = [0, 4, 9, 12]
+    dts = [1e-3, 1e-3, 2e-3] if case == "dt differs" else None
+    doms, pars = _domains_params(nb, k, dts, warm=2 if case == "learned" else None)
+    if case == "offsets":
+        offs = [0, 4, 9, 11]
+    if case == "empty scene":
+        offs = [0, 4, 4, 12]
+    n = 0 if case == "no scenes" else k
+    arr = (C.c_int64 * 4)(*offs)
+    out = C.c_void_p()
+    st = L.nbgs_batch_create(n, arr, C.byref(_dummy_bodies(nb, 12)), doms, pars, None, None, C.byref(out))
+    want = 8 if case == "learned" else 1  # UNSUPPORTED, INVALID_ARG
+    assert st == want, (case, st, nb.nbgs_last_error())
+    assert not out.value
+    msg = nb.nbgs_last_error()
+    assert msg
+
+
+def test_tuning_rejects_unsupported_shapes():
+    """nbgs_set_tuning validates before touching the scene: a NULL scene is INVALID_ARG."""
+    import ctypes as C
+
+    import paper_1501_05810_amd as nb
+
+    t = nb.nbgs_tuning(block=96, contacts_per_thread=1, xcd_remap=1, nontemporal=0, full_store=0, persistent=0,
+                       graph=0)
+    assert nb.lib().nbgs_set_tuning(None, 0, C.byref(t)) == 1
