@@ -12,11 +12,13 @@ Printed JSON line (one, rank 0):
   value         contact updates per second over the timed steps (FP64 sweeps,
                 50 sweeps/step, whole-step wall time, inputs resident in HBM);
   roofline      the NBGS sweep kernel: compulsory bytes per launch over its
-                average launch time (HIP event pair per launch, live);
+                average launch time, from a HIP event pair around every sweep
+                launch of extra profiled steps (the timed steps run without);
   cpu_baseline  the oracle (sequential FP64 C) on one host core, one step of a
                 bounded sample of the same packing.
 Further fields: steps/s to residual 1e-6 (FP64 and FP32 sweeps), sweeps used,
-phase times, contact statistics.
+phase times, contact statistics, and the other workloads (walled 4,096-sphere
+box, 512-scene ensemble batch, 16.8M-sphere dilute gas).
 """
 import argparse
 import json
@@ -72,6 +74,65 @@ def measured_traffic(precision: str):
     return float(v.replace(",", "")) if v else None
 
 
+def _timed_steps(nb, torch, g, steps, sweeps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cs = 0
+    for _ in range(steps):
+        nb.nbgs_detect(g.handle)
+        st, _ = nb.nbgs_solve(g.handle, sweeps, 0.0)
+        nb.nbgs_integrate(g.handle)
+        cs += int(st.n_contacts)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, cs
+
+
+def other_workloads(nb, sg, torch, dev):
+    """The walled 4,096-sphere box (100 steps x 10 FP64 sweeps), the 512-scene ensemble (FP32, 20 sweeps, 200
+    steps from the lattice, autotuned launch shape, graph-capable batch path) and the 16.8M-sphere dilute gas
+    (10 FP64 sweeps), each timed as whole steps with inputs resident on the device."""
+    out = {}
+    sc = sg.walled_gas()
+    g = nb.GpuScene(sc.copy(), device=dev, precision="fp64")
+    g.step(10)
+    wall, cs = _timed_steps(nb, torch, g, 100, 10)
+    out["walled_box_4096"] = {"steps": 100, "sweeps_per_step": 10, "steps_per_s": 100 / wall,
+                              "contact_updates_per_s": cs * 10 / wall, "mean_contacts": cs / 100, "dtype": "f64"}
+    g.close()
+    log(f"walled box: {out['walled_box_4096']}")
+
+    scenes = sg.batch_scenes()
+    gb = nb.GpuBatch(scenes, device=dev, precision="fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, cs = 0, 0
+    for chunk in range(4):
+        st = gb.step_batch(50, 20)
+        steps += 50
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_c, n_col = gb.scene_stats()
+    out["ensemble_512"] = {"scenes": len(scenes), "bodies": int(sum(s.n for s in scenes)), "steps": steps,
+                           "sweeps_per_step": 20, "steps_per_s": steps / wall, "ms_per_step": wall / steps * 1e3,
+                           "contacts_last_step": int(st["n_contacts"]), "max_colours_last_step": int(n_col.max()),
+                           "phase_ms_last_step": [round(float(x), 3) for x in gb.phase_times()],
+                           "tuning": gb.tuning(), "dtype": "f32 sweeps, f64 detection/integration",
+                           "note": "whole steps incl. the first step's autotuning; scenes start on their lattice"}
+    gb.close()
+    log(f"ensemble: {out['ensemble_512']}")
+
+    sc = sg.dilute_gas()
+    g = nb.GpuScene(sc, device=dev, precision="fp64")
+    g.step(10)
+    wall, cs = _timed_steps(nb, torch, g, 10, 10)
+    out["dilute_gas_16m"] = {"bodies": sc.n, "steps": 10, "sweeps_per_step": 10, "steps_per_s": 10 / wall,
+                             "ms_per_step": wall / 10 * 1e3, "mean_contacts": cs / 10,
+                             "phase_ms_last_step": [round(float(x), 3) for x in g.phase_times()], "dtype": "f64"}
+    g.close()
+    log(f"dilute gas: {out['dilute_gas_16m']}")
+    return out
+
+
 def cpu_baseline(sample_tiles: int, sweeps: int):
     """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres)."""
     import oracle
@@ -107,6 +168,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (to scale HBM traffic counters)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (walled box, ensemble batch, dilute gas)")
     a = ap.parse_args()
 
     if a.calibrate_copy > 0:
@@ -200,17 +263,22 @@ def main():
             torch.cuda.synchronize()
             sweeps_used = []
             conv = []
+            res_end = []
             r0 = time.perf_counter()
             for i in range(a.residual_steps):
                 st = gr.step(a.max_sweeps, a.target)
                 sweeps_used.append(st["sweeps"])
                 conv.append(bool(st["converged"]))
+                res_end.append(st["residual"])
             torch.cuda.synchronize()
             r1 = time.perf_counter()
             resid[prec] = {"steps_per_s": a.residual_steps / (r1 - r0), "sweeps_per_step": sweeps_used,
-                           "converged": conv, "seconds_per_step": (r1 - r0) / a.residual_steps}
+                           "converged": conv, "residual_at_end": res_end, "sweep_cap": a.max_sweeps,
+                           "seconds_per_step": (r1 - r0) / a.residual_steps}
             log(f"to-residual {prec}: {resid[prec]}")
             gr.close()
+
+    extra = {} if a.no_extras else other_workloads(nb, sg, torch, dev)
 
     cpu = None
     if a.cpu_tiles > 0:
@@ -240,6 +308,7 @@ def main():
         "phase_ms_last_step": {"detect": phases[0], "colour_order": phases[1], "init": phases[2],
                                "sweeps": phases[3], "integrate": phases[4]},
         "to_residual_1e-6": resid,
+        "other_workloads": extra,
         "roofline": roof,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
