@@ -240,7 +240,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
         sc->stamp = 1;
     }
     NBGS_TRY(launch_cells(sc->b, sc->grid, skeys, sids, sc->h.p, sc->cell_start.p, sc->cell_end.p,
-                          sc->cell_stamp.p, sc->stamp, sc->sxr.p, s));
+                          sc->cell_stamp.p, sc->stamp, sc->sxr.p, sc->cellpos.p, s));
     // count, scan, emit
     NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
                                sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p, s));
@@ -255,7 +255,8 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     ContactBuf &cb = sc->cb[sc->cur];
     NBGS_TRY(cb.reserve((size_t)nc));
     NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
-                              sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->off.p, cb.view(), s));
+                              sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p, sc->off.p,
+                              sc->cellpos.p, cb.view(), s));
     // initial impulses and, when the previous table carries colours, the start of the colouring
     const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
@@ -854,6 +855,7 @@ nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int6
     chk(sc->ids2.reserve(N, 1.0));
     chk(sc->sxr.reserve(N, 1.0));
     chk(sc->cnt.reserve(N + 1, 1.0));
+    chk(sc->cellpos.reserve(N, 1.0));
     chk(sc->off.reserve(N + 1, 1.0));
     chk(sc->deg2.reserve(N + 1, 1.0));
     chk(sc->off2.reserve(N + 1, 1.0));

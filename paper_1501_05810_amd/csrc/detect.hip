@@ -78,12 +78,13 @@ __global__ void __launch_bounds__(kBlock) k_cell_keys(BodiesView b, Grid g0, Sce
     ids[i] = (uint32_t)i;
 }
 
-// Cell ranges from the sorted keys, and a sorted copy of (centre, +-(r + h))
-// for coalesced neighbour reads; the sign marks static bodies.
+// Cell ranges from the sorted keys, a sorted copy of (centre, +-(r + h))
+// for coalesced neighbour reads (the sign marks static bodies), and each
+// body's sorted position.
 __global__ void __launch_bounds__(kBlock) k_cells(BodiesView b, int32_t n, const uint32_t *skeys,
                                                   const uint32_t *sids, const double *h, int32_t *cell_start,
                                                   int32_t *cell_end, uint32_t *cell_stamp, uint32_t stamp,
-                                                  double4 *sxr) {
+                                                  double4 *sxr, int32_t *cellpos) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     const uint32_t key = skeys[p];
@@ -93,6 +94,7 @@ __global__ void __launch_bounds__(kBlock) k_cells(BodiesView b, int32_t n, const
     }
     if (p == n - 1 || skeys[p + 1] != key) cell_end[key] = p + 1;
     const int i = (int)sids[p];
+    cellpos[i] = p;
     const double rh = b.radius[i] + h[i];
     sxr[p] = make_double4(b.x[i], b.y[i], b.z[i], b.inv_mass[i] == 0.0 ? -rh : rh);
 }
@@ -208,15 +210,18 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, Pl
     cnt[i] = m;
 }
 
+// One thread per body in index order, so that consecutive threads write
+// consecutive segments of the canonical list; bodies without contacts leave
+// at once.
 __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                       const uint32_t *skeys, const uint32_t *sids,
                                                       const double4 *sxr, const double *h,
                                                       const int32_t *cell_start, const int32_t *cell_end,
-                                                      const uint32_t *cell_stamp, uint32_t stamp, const int32_t *off,
-                                                      ContactsView c) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= b.n) return;
-    const int i = (int)sids[p];
+                                                      const uint32_t *cell_stamp, uint32_t stamp, const int32_t *cnt,
+                                                      const int32_t *off, const int32_t *cellpos, ContactsView c) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= b.n || cnt[i] == 0) return;
+    const int p = cellpos[i];
     const int sc = st.body_scene ? st.body_scene[i] : 0;
     const Grid &g = st.body_scene ? st.grids[sc] : g0;
     const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
@@ -355,9 +360,10 @@ nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTabl
 
 nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
                          const double *h, int32_t *cell_start, int32_t *cell_end, uint32_t *cell_stamp,
-                         uint32_t stamp, double4 *sxr, hipStream_t s) {
+                         uint32_t stamp, double4 *sxr, int32_t *cellpos, hipStream_t s) {
     (void)g;
-    k_cells<<<grid_for(b.n), kBlock, 0, s>>>(b, b.n, skeys, sids, h, cell_start, cell_end, cell_stamp, stamp, sxr);
+    k_cells<<<grid_for(b.n), kBlock, 0, s>>>(b, b.n, skeys, sids, h, cell_start, cell_end, cell_stamp, stamp, sxr,
+                                             cellpos);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -375,9 +381,10 @@ nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet
 nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
-                             uint32_t stamp, const int32_t *off, ContactsView c, hipStream_t s) {
+                             uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
+                             ContactsView c, hipStream_t s) {
     k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
-                                                 cell_stamp, stamp, off, c);
+                                                 cell_stamp, stamp, cnt, off, cellpos, c);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

@@ -142,7 +142,7 @@ nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTabl
                              hipStream_t s);
 nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
                          const double *h, int32_t *cell_start, int32_t *cell_end, uint32_t *cell_stamp,
-                         uint32_t stamp, double4 *sxr, hipStream_t s);
+                         uint32_t stamp, double4 *sxr, int32_t *cellpos, hipStream_t s);
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                               const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
@@ -150,7 +150,8 @@ nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet
 nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
-                             uint32_t stamp, const int32_t *off, ContactsView c, hipStream_t s);
+                             uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
+                             ContactsView c, hipStream_t s);
 nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
                               const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
                               int64_t n_prev, double mu, const SceneTable &st, bool impulses, bool colours,

@@ -92,7 +92,7 @@ struct nbgs_scene_s {
     DevBuf<double> h;
     DevBuf<uint32_t> keys, ids, keys2, ids2;
     DevBuf<double4> sxr;
-    DevBuf<int32_t> cnt, off;
+    DevBuf<int32_t> cnt, off, cellpos;
     DevBuf<int32_t> deg2, off2, cursor;
     DevBuf<double> vel64;
     DevBuf<float> vel32;
