@@ -133,6 +133,96 @@ def other_workloads(nb, sg, torch, dev):
     return out
 
 
+def _clone(nb, sg, g, sc, dev, precision, warm_start):
+    """A new scene in the state of g (bodies and its last impulses as the previous-step table)."""
+    st = g.state()
+    c = g.contacts()
+    s2 = sc.copy()
+    s2.pos, s2.quat, s2.vel, s2.angvel = st["pos"], st["quat"], st["vel"], st["angvel"]
+    g2 = nb.GpuScene(s2, device=dev, precision=precision, warm_start=warm_start)
+    g2.set_warm_start(c["key"], c["P"])
+    return g2
+
+
+def learned_warm_start(nb, sg, torch, dev, sc, cap, target, steps, train_steps=2, samples=1 << 20):
+    """Learned warm start on the dense packing: train the network on the solver's own impulses (FP64 solves capped
+    at `cap` sweeps), then continue from one state with the previous-step and the learned start, FP64 and FP32
+    sweeps, each step solved to `target` or the cap; also the network's inference and training throughput."""
+    import numpy as np
+
+    out = {}
+    g = nb.GpuScene(sc.copy(), device=dev, precision="fp64", warm_start="previous")
+    g.step(cap, target)
+    g.set_feature_capture(True)
+    feats, tgts = [], []
+    for _ in range(train_steps):
+        g.step(cap, target)
+        f, t = g.training_data()
+        feats.append(f.clone())
+        tgts.append(t.clone())
+    g.set_feature_capture(False)
+    X, T = torch.cat(feats), torch.cat(tgts)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    pick = torch.randperm(X.shape[0], generator=gen)[:samples].to(X.device)
+    X, T = X[pick].contiguous(), T[pick].contiguous()
+    mlp = nb.GpuMlp(seed=3)
+    l0, _ = mlp.loss_grad(X, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mlp.train(X, T, epochs=20, batch=4096, lr=1e-3, seed=11)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    l1, _ = mlp.loss_grad(X, T)
+    flops_fwd = 2 * (12 * 128 + 128 * 128 + 128 * 3)
+    n_adam = 20 * (X.shape[0] // 4096)
+    out["training"] = {"samples": int(X.shape[0]), "epochs": 20, "batch": 4096, "lr": 1e-3,
+                       "loss_before": float(l0), "loss_after": float(l1), "seconds": t_train,
+                       "tflops": 3 * flops_fwd * 4096 * n_adam / t_train / 1e12}
+    # inference throughput over one step's contacts
+    n = feats[-1].shape[0]
+    y = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    xf = feats[-1].contiguous()
+    nb.nbgs_mlp_forward(mlp.handle, xf.data_ptr(), n, y.data_ptr())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        nb.nbgs_mlp_forward(mlp.handle, xf.data_ptr(), n, y.data_ptr())
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    out["inference"] = {"contacts": int(n), "ms": ms, "tflops": flops_fwd * n / (ms * 1e-3) / 1e12,
+                        "peak_tflops_bf16": 2500.0, "frac": flops_fwd * n / (ms * 1e-3) / 1e12 / 2500.0}
+    # the same state continued with each start
+    runs = {}
+    for prec in ("fp64", "fp32"):
+        for ws in ("previous", "learned"):
+            g2 = _clone(nb, sg, g, sc, dev, prec, ws)
+            if ws == "learned":
+                g2.attach_mlp(mlp)
+            rec = {"sweeps": [], "residual_at_end": [], "seconds": [], "choice": []}
+            for _ in range(steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = g2.step(cap, target)
+                torch.cuda.synchronize()
+                rec["seconds"].append(time.perf_counter() - t0)
+                rec["sweeps"].append(st["sweeps"])
+                rec["residual_at_end"].append(st["residual"])
+                if ws == "learned":
+                    info = g2.warm_start_info()
+                    rec["choice"].append({"network": info["choice"] == 1, "r_previous": info["r_previous"],
+                                          "r_learned": info["r_learned"]})
+            rec["seconds_per_step"] = float(np.mean(rec["seconds"]))
+            runs[f"{ws}_{prec}"] = rec
+            g2.close()
+            log(f"warm start {ws} {prec}: {rec}")
+    out["runs"] = runs
+    g.close()
+    mlp.close()
+    return out
+
+
 def cpu_baseline(sample_tiles: int, sweeps: int):
     """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres)."""
     import oracle
@@ -223,7 +313,9 @@ def main():
         g.set_profiling(False)
         return t1 - t0, cs, cols, g.phase_times(), prof
 
-    # timed region: whole steps, no per-launch events
+    # timed region: whole steps, no per-launch events; with a fixed sweep count only the last sweep's residual
+    # (the one reported) is formed
+    g.set_residual_history(False)
     wall, contacts, colours, phases, _ = run_steps(a.steps, False)
     updates = float(np.sum(contacts)) * a.sweeps
     value = updates / wall
@@ -278,6 +370,10 @@ def main():
             log(f"to-residual {prec}: {resid[prec]}")
             gr.close()
 
+    learned = None
+    if a.residual_steps > 0 and not a.no_extras:
+        learned = learned_warm_start(nb, sg, torch, dev, sc, a.max_sweeps, a.target, a.residual_steps)
+
     extra = {} if a.no_extras else other_workloads(nb, sg, torch, dev)
 
     cpu = None
@@ -308,6 +404,7 @@ def main():
         "phase_ms_last_step": {"detect": phases[0], "colour_order": phases[1], "init": phases[2],
                                "sweeps": phases[3], "integrate": phases[4]},
         "to_residual_1e-6": resid,
+        "learned_warm_start": learned,
         "other_workloads": extra,
         "roofline": roof,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},

@@ -194,8 +194,16 @@ nbgs_status nbgs_get_contacts(nbgs_scene_t scene, int64_t cap, int32_t *j1, int3
 nbgs_status nbgs_get_accumulators(nbgs_scene_t scene, double *v, double *w);
 
 /* Residual history of the last solve: R of sweeps 1..min(cap, sweeps) into
- * hist [host]; *n_out [host] = number of sweeps.  Synchronises. */
+ * hist [host]; *n_out [host] = number of sweeps.  Entries of sweeps whose
+ * residual was not formed (see nbgs_set_residual_history) are NaN.
+ * Synchronises. */
 nbgs_status nbgs_get_residuals(nbgs_scene_t scene, int32_t cap, double *hist, int32_t *n_out);
+
+/* enable = 1 (default): the residual R_k of every sweep is formed.  enable =
+ * 0: a solve without a residual target forms only the last sweep's residual
+ * (the one nbgs_stats reports); impulses and velocities are unchanged.  A
+ * solve with a target always forms every sweep's residual. */
+nbgs_status nbgs_set_residual_history(nbgs_scene_t scene, int32_t enable);
 
 /* Replace the previous-step table used by NBGS_WS_PREVIOUS: n entries, keys
  * [device] strictly ascending, impulse [device] three planes of n doubles.

@@ -90,6 +90,7 @@ _SIGNATURES = [
     ("nbgs_get_accumulators", C.c_int, [_vp, _vp, _vp]),
     ("nbgs_get_residuals", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("nbgs_set_warm_start", C.c_int, [_vp, C.c_int64, _vp, _vp]),
+    ("nbgs_set_residual_history", C.c_int, [_vp, C.c_int32]),
     ("nbgs_get_phase_times", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     ("nbgs_mlp_param_count", C.c_int32, []),
     ("nbgs_mlp_create", C.c_int, [C.c_uint64, _vp, C.POINTER(_vp)]),
@@ -215,6 +216,10 @@ def nbgs_get_residuals(h: int, cap: int) -> np.ndarray:
 
 def nbgs_set_warm_start(h: int, n: int, keys_ptr: int, impulse_ptr: int) -> None:
     _check(lib().nbgs_set_warm_start(_vp(h), int(n), _vp(keys_ptr), _vp(impulse_ptr)))
+
+
+def nbgs_set_residual_history(h: int, enable: bool) -> None:
+    _check(lib().nbgs_set_residual_history(_vp(h), 1 if enable else 0))
 
 
 def nbgs_get_phase_times(h: int, n: int = 5) -> np.ndarray:
@@ -539,6 +544,9 @@ class GpuScene:
 
     def residuals(self, cap: int = 100000) -> np.ndarray:
         return nbgs_get_residuals(self.handle, cap)
+
+    def set_residual_history(self, enable: bool = True):
+        nbgs_set_residual_history(self.handle, enable)
 
     def set_warm_start(self, keys: np.ndarray, P: np.ndarray):
         torch = self.torch

@@ -189,12 +189,12 @@ nbgs_status sync_small(nbgs_scene_t sc, int first, int count) {
 }
 
 template <class T>
-nbgs_status gather_for_sweeps(nbgs_scene_t sc, const uint32_t *perm) {
+nbgs_status gather_for_sweeps(nbgs_scene_t sc) {
     SweepBuf<T> &sw = sweep_buf<T>(sc);
     sw.per_contact_mu = sc->n_scenes > 1;
     NBGS_TRY(sw.reserve((size_t)sc->nc));
-    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), perm, sc->nc, sc->p.dt, sc->p.erp, sc->table(), sw.view(),
-                                  sc->s);
+    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), sc->spos.p, sc->nc, sc->p.dt, sc->p.erp, sc->table(),
+                                  sw.view(), sc->s);
 }
 
 nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
@@ -361,6 +361,8 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     const uint32_t *perm = calt ? sc->cids2.p : sc->cids.p;
     if (nc == 1) perm = sc->cids.p;
     sc->perm = perm;
+    NBGS_TRY(sc->spos.reserve((size_t)nc + 1));
+    NBGS_TRY(launch_invert(perm, nc, sc->spos.p, s));
     sc->precision_used = sc->p.precision;
     NBGS_TRY(scene_gather(sc));
     sc->state = 1;
@@ -462,7 +464,7 @@ nbgs_status judge_warm_start(nbgs_scene_t sc) {
 // residual) on stream cs.
 template <class T>
 nbgs_status enqueue_dev_sweeps(nbgs_scene_t sc, int32_t k, double target, const SweepTune &tune, unsigned grid,
-                               hipStream_t cs) {
+                               hipStream_t cs, bool residuals) {
     SweepBuf<T> &sw = sweep_buf<T>(sc);
     DevBuf<T> &vel = vel_buf<T>(sc);
     const SweepParams sp{sc->p.mu, sc->p.relax};
@@ -471,7 +473,9 @@ nbgs_status enqueue_dev_sweeps(nbgs_scene_t sc, int32_t k, double target, const 
         for (int c = 0; c < C; ++c)
             NBGS_TRY(launch_sweep_colour_dev<T>(sw.view(), sc->col_d.p, c, sc->b.n, vel.p, sp, tune,
                                                 sc->partials.p + 2 * (size_t)c * grid, sc->ctrl(), cs));
-        NBGS_TRY(launch_residual(sc->partials.p, (int32_t)((int64_t)C * grid), target, sc->ctrl(), sc->res_hist.p, cs));
+        if (residuals)
+            NBGS_TRY(launch_residual(sc->partials.p, (int32_t)((int64_t)C * grid), target, sc->ctrl(), sc->res_hist.p,
+                                     cs));
     }
     return NBGS_OK;
 }
@@ -481,8 +485,8 @@ nbgs_status enqueue_dev_sweeps(nbgs_scene_t sc, int32_t k, double target, const 
 namespace nbgs {
 
 nbgs_status scene_gather(nbgs_scene_t sc) {
-    if (sc->precision_used == NBGS_FP32_SWEEP) return gather_for_sweeps<float>(sc, sc->perm);
-    return gather_for_sweeps<double>(sc, sc->perm);
+    if (sc->precision_used == NBGS_FP32_SWEEP) return gather_for_sweeps<float>(sc);
+    return gather_for_sweeps<double>(sc);
 }
 
 // The sweep loop replayed from a captured graph: blocks of up to 32 sweeps
@@ -533,12 +537,15 @@ nbgs_status scene_sweep_loop(nbgs_scene_t sc, int32_t max_sweeps, double target,
     key.target = target;
     key.mu = sc->p.mu;
     key.relax = sc->p.relax;
+    // without a target and without history only the last sweep's residual is formed (after the replays)
+    const bool every = target > 0.0 || sc->res_history;
+    key.every = every;
     if (!sc->gexec || !(key == sc->gkey)) {
         if (sc->gexec) (void)hipGraphExecDestroy(sc->gexec);
         sc->gexec = nullptr;
         if (!sc->cap_stream) NBGS_HIP(hipStreamCreateWithFlags(&sc->cap_stream, hipStreamNonBlocking));
         NBGS_HIP(hipStreamBeginCapture(sc->cap_stream, hipStreamCaptureModeRelaxed));
-        const nbgs_status st = enqueue_dev_sweeps<T>(sc, K, target, tune, grid, sc->cap_stream);
+        const nbgs_status st = enqueue_dev_sweeps<T>(sc, K, target, tune, grid, sc->cap_stream, every);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(sc->cap_stream, &g);
         if (st != NBGS_OK) {
@@ -568,10 +575,13 @@ nbgs_status scene_sweep_loop(nbgs_scene_t sc, int32_t max_sweeps, double target,
     }
     if (!done && rem > 0) {
         if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * q], s));
-        NBGS_TRY(enqueue_dev_sweeps<T>(sc, rem, target, tune, grid, s));
+        NBGS_TRY(enqueue_dev_sweeps<T>(sc, rem, target, tune, grid, s, every));
         if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * q + 1], s));
         ++q;
     }
+    if (!every)
+        NBGS_TRY(launch_residual(sc->partials.p, (int32_t)((int64_t)C * grid), target, sc->ctrl(), sc->res_hist.p, s,
+                                 max_sweeps - 1));
     sc->graph_pairs = prof ? q : 0;
     return NBGS_OK;
 }
@@ -620,6 +630,8 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
         NBGS_TRY(ensure_profile_events(sc, (size_t)max_sweeps * sc->n_colours));
     }
     size_t pe = 0;
+    const bool every = target > 0.0 || sc->res_history;
+    sc->hist_partial = !every;
     while (launched < max_sweeps && !done) {
         const int32_t k = std::min(chunk, max_sweeps - launched);
         for (int32_t it = 0; it < k; ++it) {
@@ -630,7 +642,11 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
                 if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * pe + 1], s));
                 ++pe;
             }
-            NBGS_TRY(launch_residual(sc->partials.p, (int32_t)sc->n_partials, target, sc->ctrl(), sc->res_hist.p, s));
+            const bool last = launched + it + 1 == max_sweeps;
+            if (every) NBGS_TRY(launch_residual(sc->partials.p, (int32_t)sc->n_partials, target, sc->ctrl(), sc->res_hist.p, s));
+            else if (last)
+                NBGS_TRY(launch_residual(sc->partials.p, (int32_t)sc->n_partials, target, sc->ctrl(), sc->res_hist.p, s,
+                                         max_sweeps - 1));
         }
         launched += k;
         if (target > 0.0 && launched < max_sweeps) {
@@ -1081,7 +1097,17 @@ nbgs_status nbgs_get_residuals(nbgs_scene_t sc, int32_t cap, double *hist, int32
     const int32_t n = ctrl[1];
     if (n_out) *n_out = n;
     const int32_t k = std::min(cap, n);
-    if (k > 0 && hist) NBGS_HIP(hipMemcpy(hist, sc->res_hist.p, sizeof(double) * k, hipMemcpyDeviceToHost));
+    if (k > 0 && hist) {
+        NBGS_HIP(hipMemcpy(hist, sc->res_hist.p, sizeof(double) * k, hipMemcpyDeviceToHost));
+        if (sc->hist_partial)  // only the last sweep was summed
+            for (int32_t i = 0; i < k && i < n - 1; ++i) hist[i] = std::nan("");
+    }
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_set_residual_history(nbgs_scene_t sc, int32_t enable) {
+    NBGS_GUARD(sc);
+    sc->res_history = enable != 0;
     return NBGS_OK;
 }
 

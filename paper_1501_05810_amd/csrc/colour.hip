@@ -208,12 +208,21 @@ __global__ void __launch_bounds__(kBlock) k_colour_keys(const int32_t *colour, i
     ids[j] = (uint32_t)j;
 }
 
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_gather_sweep(ContactsView c, const uint32_t *perm, int64_t nc, double dt,
-                                                         double erp, SceneTable st, SweepView<T> sv) {
+// Sweep position of every canonical contact (inverse of the colour sort's permutation).
+__global__ void __launch_bounds__(kBlock) k_invert(const uint32_t *perm, int64_t nc, int32_t *pos) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= nc) return;
-    const int64_t j = perm[p];
+    if (p < nc) pos[perm[p]] = (int32_t)p;
+}
+
+// Canonical record j -> sweep position pos[j].  One thread per canonical
+// contact: the reads stream, and the writes of a colour land in ascending
+// positions, which the L2 merges into whole lines.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_gather_sweep(ContactsView c, const int32_t *pos, int64_t nc, double dt,
+                                                         double erp, SceneTable st, SweepView<T> sv) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    const int64_t p = pos[j];
     sv.perm[p] = (int32_t)j;
     if (sv.mu) sv.mu[p] = (T)st.mu[st.body_scene[c.j1[j]]];
     sv.j1[p] = c.j1[j];
@@ -294,18 +303,25 @@ nbgs_status launch_colour_keys(const ContactsView &c, int64_t nc, uint32_t *keys
     return NBGS_OK;
 }
 
-template <class T>
-nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, int64_t nc, double dt, double erp,
-                                const SceneTable &st, SweepView<T> sv, hipStream_t s) {
+nbgs_status launch_invert(const uint32_t *perm, int64_t nc, int32_t *pos, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, perm, nc, dt, erp, st, sv);
+    k_invert<<<grid_for(nc), kBlock, 0, s>>>(perm, nc, pos);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
-template nbgs_status launch_gather_sweep<double>(const ContactsView &, const uint32_t *, int64_t, double, double,
+template <class T>
+nbgs_status launch_gather_sweep(const ContactsView &c, const int32_t *pos, int64_t nc, double dt, double erp,
+                                const SceneTable &st, SweepView<T> sv, hipStream_t s) {
+    if (nc == 0) return NBGS_OK;
+    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, pos, nc, dt, erp, st, sv);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template nbgs_status launch_gather_sweep<double>(const ContactsView &, const int32_t *, int64_t, double, double,
                                                  const SceneTable &, SweepView<double>, hipStream_t);
-template nbgs_status launch_gather_sweep<float>(const ContactsView &, const uint32_t *, int64_t, double, double,
+template nbgs_status launch_gather_sweep<float>(const ContactsView &, const int32_t *, int64_t, double, double,
                                                 const SceneTable &, SweepView<float>, hipStream_t);
 
 }  // namespace nbgs

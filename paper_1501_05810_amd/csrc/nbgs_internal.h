@@ -175,8 +175,9 @@ nbgs_status launch_colour_fix(const ContactsView &c, const uint64_t *prio, int64
 nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *hist,
                                hipStream_t s);
 nbgs_status launch_colour_keys(const ContactsView &c, int64_t nc, uint32_t *keys, uint32_t *ids, hipStream_t s);
+nbgs_status launch_invert(const uint32_t *perm, int64_t nc, int32_t *pos, hipStream_t s);
 template <class T>
-nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, int64_t nc, double dt, double erp,
+nbgs_status launch_gather_sweep(const ContactsView &c, const int32_t *pos, int64_t nc, double dt, double erp,
                                 const SceneTable &st, SweepView<T> sv, hipStream_t s);
 
 // sweep.hip
@@ -210,7 +211,7 @@ template <class T>
 nbgs_status launch_sweep_colour_dev(SweepView<T> sv, const int64_t *col, int32_t c, int32_t nb, T *vel, SweepParams sp,
                                     const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s);
 nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl,
-                            double *hist, hipStream_t s);
+                            double *hist, hipStream_t s, int32_t at = -1);
 template <class T>
 nbgs_status launch_integrate(const BodiesView &b, const Grid &g, const SceneTable &st, double dt, const T *vel,
                              hipStream_t s);

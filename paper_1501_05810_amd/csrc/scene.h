@@ -117,6 +117,7 @@ struct nbgs_scene_s {
     int32_t colour_passes = 0;  // > 0: passes from the previous colours, < 0: Jones-Plassmann rounds
     DevBuf<uint32_t> ckeys, cids, ckeys2, cids2;
     const uint32_t *perm = nullptr;  // sweep position -> canonical index (in ckeys/cids storage)
+    DevBuf<int32_t> spos;            // canonical index -> sweep position
     SweepBuf<double> sw64;
     SweepBuf<float> sw32;
     int32_t n_colours = 0;
@@ -171,9 +172,10 @@ struct nbgs_scene_s {
         const void *ptrs[6] = {};
         const void *col = nullptr;
         double target = 0.0, mu = 0.0, relax = 0.0;
+        bool every = true;  // residual after every sweep
         bool operator==(const GraphKey &o) const {
             if (sweeps != o.sweeps || colours != o.colours || prec != o.prec || grid != o.grid || col != o.col ||
-                target != o.target || mu != o.mu || relax != o.relax)
+                target != o.target || mu != o.mu || relax != o.relax || every != o.every)
                 return false;
             if (std::memcmp(&tune, &o.tune, sizeof(tune)) != 0) return false;
             for (int i = 0; i < 6; ++i)
@@ -182,6 +184,8 @@ struct nbgs_scene_s {
         }
     } gkey;
     int graph_pairs = 0;  // profiling event pairs of the last graph-replayed solve
+    bool res_history = true;   // residual of every sweep even without a target
+    bool hist_partial = false;  // the last solve summed only its last sweep
     DevBuf<int64_t> col_d;
     int64_t *col_pinned = nullptr;
     size_t col_pinned_cap = 0;

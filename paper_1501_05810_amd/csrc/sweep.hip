@@ -347,8 +347,10 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dev(SweepView<T> sv, const int6
 // order.  ctrl = {done, sweeps completed, numeric error}.
 constexpr int kResBlock = 1024;
 
+// at >= 0: this is sweep `at` (0-based) of the solve, the earlier sweeps were
+// not summed; at < 0: the sweep after the last one counted in ctrl[1].
 __global__ void __launch_bounds__(kResBlock) k_residual(const double *partials, int32_t n_partials, double target,
-                                                        int32_t *ctrl, double *hist) {
+                                                        int32_t *ctrl, double *hist, int32_t at) {
     if (ctrl[0]) return;
     double a = 0.0, c = 0.0;
     const double2 *pp = reinterpret_cast<const double2 *>(partials);
@@ -371,7 +373,7 @@ __global__ void __launch_bounds__(kResBlock) k_residual(const double *partials, 
     if (threadIdx.x == 0) {
         const double den = sqrt(red[1][0]);
         const double R = sqrt(red[0][0]) / (den > 1e-300 ? den : 1e-300);
-        const int k = ctrl[1];
+        const int k = at >= 0 ? at : ctrl[1];
         hist[k] = R;
         ctrl[1] = k + 1;
         if (!(R == R) || R > 1.0e300) {
@@ -596,8 +598,8 @@ nbgs_status launch_sweep_colour_dev(SweepView<T> sv, const int64_t *col, int32_t
 #undef NBGS_SWEEP_DEV_DISPATCH
 
 nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl, double *hist,
-                            hipStream_t s) {
-    k_residual<<<1, kResBlock, 0, s>>>(partials, n_partials, target, ctrl, hist);
+                            hipStream_t s, int32_t at) {
+    k_residual<<<1, kResBlock, 0, s>>>(partials, n_partials, target, ctrl, hist, at);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

@@ -171,3 +171,24 @@ def test_batch_of_the_ensemble_generator_runs():
         assert g.detect()["n_contacts"] == n_c[i], i
         g.close()
     gb.close()
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_residual_history_off_changes_nothing_but_the_history(graph):
+    nb = _nb()
+    sc = sg.packed_cluster(14, counts=(10, 10, 6))
+    runs = []
+    for hist in (True, False):
+        g = nb.GpuScene(sc.copy())
+        g.set_tuning(graph=graph, persistent=1 if graph else 0)
+        g.set_residual_history(hist)
+        for _ in range(2):
+            st = g.step(40)
+        runs.append((g.contacts()["P"], g.state()["vel"], g.residuals(), st))
+        g.close()
+    (Pa, va, ra, sa), (Pb, vb, rb, sb) = runs
+    assert np.array_equal(Pa, Pb) and np.array_equal(va, vb)
+    assert sa["sweeps"] == sb["sweeps"] == 40 and len(ra) == len(rb) == 40
+    assert sa["residual"] == ra[-1] and sb["residual"] == rb[-1]
+    assert ra[-1] == rb[-1]  # the same partial sums, summed the same way
+    assert np.all(np.isnan(rb[:-1])) and np.all(np.isfinite(ra))
