@@ -145,9 +145,12 @@ def _clone(nb, sg, g, sc, dev, precision, warm_start):
 
 
 def learned_warm_start(nb, sg, torch, dev, sc, cap, target, steps, train_steps=2, samples=1 << 20):
-    """Learned warm start on the dense packing: train the network on the solver's own impulses (FP64 solves capped
-    at `cap` sweeps), then continue from one state with the previous-step and the learned start, FP64 and FP32
-    sweeps, each step solved to `target` or the cap; also the network's inference and training throughput."""
+    """Learned warm start on the dense packing.  The network supplies the initial impulse of contacts that the
+    previous step did not have; it is trained on the solver's own impulses (FP64 solves capped at `cap` sweeps)
+    with the previous-impulse features set to zero, as they are for a new contact.  Two situations are compared,
+    FP64 and FP32 sweeps, each step solved to `target` or the cap: a continued run (every contact matched, so the
+    learned start equals the previous-step start) and a cold start of the packing (no previous impulses: zero start
+    against the network's).  Also the network's inference and training throughput."""
     import numpy as np
 
     out = {}
@@ -162,6 +165,7 @@ def learned_warm_start(nb, sg, torch, dev, sc, cap, target, steps, train_steps=2
         tgts.append(t.clone())
     g.set_feature_capture(False)
     X, T = torch.cat(feats), torch.cat(tgts)
+    X[:, 9:12] = 0.0  # a new contact has no previous impulse
     gen = torch.Generator(device="cpu").manual_seed(7)
     pick = torch.randperm(X.shape[0], generator=gen)[:samples].to(X.device)
     X, T = X[pick].contiguous(), T[pick].contiguous()
@@ -193,34 +197,45 @@ def learned_warm_start(nb, sg, torch, dev, sc, cap, target, steps, train_steps=2
     ms = e0.elapsed_time(e1) / 10
     out["inference"] = {"contacts": int(n), "ms": ms, "tflops": flops_fwd * n / (ms * 1e-3) / 1e12,
                         "peak_tflops_bf16": 2500.0, "frac": flops_fwd * n / (ms * 1e-3) / 1e12 / 2500.0}
-    # the same state continued with each start
+    # the same state continued with each start, and a cold start of the packing
     runs = {}
-    for prec in ("fp64", "fp32"):
-        for ws in ("previous", "learned"):
-            g2 = _clone(nb, sg, g, sc, dev, prec, ws)
-            if ws == "learned":
-                g2.attach_mlp(mlp)
-            rec = {"sweeps": [], "residual_at_end": [], "seconds": [], "choice": []}
-            for _ in range(steps):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                st = g2.step(cap, target)
-                torch.cuda.synchronize()
-                rec["seconds"].append(time.perf_counter() - t0)
-                rec["sweeps"].append(st["sweeps"])
-                rec["residual_at_end"].append(st["residual"])
-                if ws == "learned":
-                    info = g2.warm_start_info()
-                    rec["choice"].append({"network": info["choice"] == 1, "r_previous": info["r_previous"],
-                                          "r_learned": info["r_learned"]})
-            rec["seconds_per_step"] = float(np.mean(rec["seconds"]))
-            runs[f"{ws}_{prec}"] = rec
-            g2.close()
-            log(f"warm start {ws} {prec}: {rec}")
+    for case in ("continued", "cold"):
+        for prec in ("fp64", "fp32"):
+            for ws in ("previous", "learned"):
+                if case == "continued":
+                    g2 = _clone(nb, sg, g, sc, dev, prec, ws)
+                else:
+                    g2 = nb.GpuScene(sc.copy(), device=dev, precision=prec, warm_start=ws)
+                runs[f"{case}_{ws}_{prec}"] = _warm_run(nb, torch, g2, mlp, ws, cap, target,
+                                                        steps if case == "continued" else 1)
+                g2.close()
     out["runs"] = runs
     g.close()
     mlp.close()
     return out
+
+
+def _warm_run(nb, torch, g2, mlp, ws, cap, target, steps):
+    import numpy as np
+
+    if ws == "learned":
+        g2.attach_mlp(mlp)
+    rec = {"sweeps": [], "residual_at_end": [], "seconds": [], "choice": []}
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = g2.step(cap, target)
+        torch.cuda.synchronize()
+        rec["seconds"].append(time.perf_counter() - t0)
+        rec["sweeps"].append(st["sweeps"])
+        rec["residual_at_end"].append(st["residual"])
+        if ws == "learned":
+            info = g2.warm_start_info()
+            rec["choice"].append({"network": info["choice"] == 1, "r_previous": info["r_previous"],
+                                  "r_learned": info["r_learned"]})
+    rec["seconds_per_step"] = float(np.mean(rec["seconds"]))
+    log(f"warm start {ws}: {rec}")
+    return rec
 
 
 def cpu_baseline(sample_tiles: int, sweeps: int):

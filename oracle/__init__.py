@@ -378,12 +378,21 @@ def mlp_features(sc, contacts: Dict[str, np.ndarray], P0: np.ndarray, vs: float,
     return feat[:nc].copy(), frame[:nc].copy()
 
 
-def mlp_decode(y: np.ndarray, frame: np.ndarray, ms: float, vs: float, mu: float) -> np.ndarray:
+def mlp_decode(y: np.ndarray, frame: np.ndarray, ms: float, vs: float, mu: float, matched=None,
+               P0=None) -> np.ndarray:
+    """Learned initial impulses: the decoded network output, or for matched contacts their previous impulse P0."""
     y, frame = _c(y), _c(frame)
     nc = y.shape[0]
     out = [np.zeros(max(nc, 1)) for _ in range(3)]
+    if matched is None:
+        mp, p0 = None, [None, None, None]
+    else:
+        mp = _ptr(np.ascontiguousarray(matched, dtype=np.int32), _i32p)
+        P0 = _c(P0).reshape(-1, 3)
+        cols = [_c(P0[:, k]) for k in range(3)]
+        p0 = [_ptr(cc) for cc in cols]
     lib().nbgs_ref_mlp_decode(C.c_int64(nc), _ptr(y), _ptr(frame), C.c_double(ms), C.c_double(vs), C.c_double(mu),
-                              *[_ptr(o) for o in out])
+                              mp, *p0, *[_ptr(o) for o in out])
     return np.stack([o[:nc] for o in out], axis=1)
 
 

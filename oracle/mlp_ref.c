@@ -228,11 +228,22 @@ void nbgs_ref_mlp_features(int64_t nb, const double *vx, const double *vy, const
 }
 
 /* Network output y (frame components scaled by ms vs) -> world impulse,
- * projected onto the cone (P_n >= 0, |P_t| <= mu P_n). */
-void nbgs_ref_mlp_decode(int64_t nc, const double *y, const double *frame, double ms, double vs, double mu, double *px,
+ * projected onto the cone (P_n >= 0, |P_t| <= mu P_n).  The learned start of
+ * a contact that the previous step also had (matched[j] != 0) is its
+ * previous impulse P0 (the initial solution may be the previous step's
+ * reactions, Sect. 5); the network supplies the start of new contacts only.
+ * matched may be NULL (every contact decoded). */
+void nbgs_ref_mlp_decode(int64_t nc, const double *y, const double *frame, double ms, double vs, double mu,
+                         const int32_t *matched, const double *p0x, const double *p0y, const double *p0z, double *px,
                          double *py, double *pz)
 {
     for (int64_t j = 0; j < nc; ++j) {
+        if (matched && matched[j]) {
+            px[j] = p0x[j];
+            py[j] = p0y[j];
+            pz[j] = p0z[j];
+            continue;
+        }
         const double *fr = frame + 9 * j;
         double s = ms * vs;
         double pn = y[NO * j + 0] * s, pt = y[NO * j + 1] * s, po = y[NO * j + 2] * s;

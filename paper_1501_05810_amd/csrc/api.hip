@@ -262,7 +262,10 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
     NBGS_TRY(launch_match_prev(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p, sc->n_prev,
                                sc->p.mu, tab, warm_impulses, warm_colours, s));
-    if (!warm_impulses) NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
+    if (!warm_impulses) {
+        NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
+        NBGS_TRY(launch_fill_i32(cb.matched.p, nc, 0, s));
+    }
     // network features and prediction (from the state before the step and the previous impulses)
     sc->have_features = false;
     sc->have_learned = false;
@@ -278,7 +281,8 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
             NBGS_TRY(sc->yout.reserve(3 * (size_t)nc));
             for (DevBuf<double> *b : {&sc->lpx, &sc->lpy, &sc->lpz}) NBGS_TRY(b->reserve((size_t)nc));
             NBGS_TRY(launch_mlp_forward(mlp_frag_ptr(sc->mlp), mlp_weight_ptr(sc->mlp), sc->feat.p, nc, sc->yout.p, s));
-            NBGS_TRY(launch_decode(sc->yout.p, sc->frame.p, nc, sc->fs, sc->p.mu, sc->lpx.p, sc->lpy.p, sc->lpz.p, s));
+            NBGS_TRY(launch_decode(sc->yout.p, sc->frame.p, cb.view(), nc, sc->fs, sc->p.mu, sc->lpx.p, sc->lpy.p,
+                                   sc->lpz.p, s));
             sc->have_learned = true;
         }
     }

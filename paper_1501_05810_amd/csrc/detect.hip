@@ -313,6 +313,7 @@ __global__ void __launch_bounds__(kBlock) k_match_prev(ContactsView c, int64_t n
     const bool found = lo < n_prev && prev_key[lo] == key;
     if (colours) c.colour[j] = found ? prev_colour[lo] : 0;
     if (!impulses) return;
+    c.matched[j] = found ? 1 : 0;
     double P0 = 0.0, P1 = 0.0, P2 = 0.0;
     if (found) {
         const double n0 = c.nx[j], n1 = c.ny[j], n2 = c.nz[j];

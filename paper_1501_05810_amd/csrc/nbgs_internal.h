@@ -113,6 +113,7 @@ struct ContactsView {
     double *nx, *ny, *nz, *xi, *a1, *a2;
     double *px, *py, *pz;  // initial / solved impulse (world frame)
     int32_t *colour;
+    int32_t *matched;  // 1 if the previous step had the pair (its impulse is the warm start), else 0
 };
 
 // Sweep-ordered (colour-major) per-contact record.
@@ -227,8 +228,8 @@ struct FeatureScales {
 nbgs_status launch_features(const BodiesView &b, const ContactsView &c, int64_t nc, const double g[3], double dt,
                             double mu, double erp, const FeatureScales &fs, float *feat, double *frame,
                             hipStream_t s);
-nbgs_status launch_decode(const float *y, const double *frame, int64_t nc, const FeatureScales &fs, double mu,
-                          double *px, double *py, double *pz, hipStream_t s);
+nbgs_status launch_decode(const float *y, const double *frame, const ContactsView &c, int64_t nc,
+                          const FeatureScales &fs, double mu, double *px, double *py, double *pz, hipStream_t s);
 nbgs_status launch_targets(const double *frame, const ContactsView &c, int64_t nc, const FeatureScales &fs, float *t,
                            hipStream_t s);
 template <class T>

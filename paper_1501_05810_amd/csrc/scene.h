@@ -11,13 +11,14 @@
 namespace nbgs {
 
 struct ContactBuf {
-    DevBuf<int32_t> j1, j2, colour;
+    DevBuf<int32_t> j1, j2, colour, matched;
     DevBuf<uint64_t> key;
     DevBuf<double> nx, ny, nz, xi, a1, a2, px, py, pz;
     nbgs_status reserve(size_t n) {
         NBGS_TRY(j1.reserve(n));
         NBGS_TRY(j2.reserve(n));
         NBGS_TRY(colour.reserve(n));
+        NBGS_TRY(matched.reserve(n));
         NBGS_TRY(key.reserve(n));
         for (DevBuf<double> *b : {&nx, &ny, &nz, &xi, &a1, &a2, &px, &py, &pz}) NBGS_TRY(b->reserve(n));
         return NBGS_OK;
@@ -37,6 +38,7 @@ struct ContactBuf {
         v.py = py.p;
         v.pz = pz.p;
         v.colour = colour.p;
+        v.matched = matched.p;
         return v;
     }
 };

@@ -120,10 +120,18 @@ __global__ void __launch_bounds__(kBlock) k_features(BodiesView b, ContactsView 
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_decode(const float *y, const double *frame, int64_t nc, FeatureScales fs,
-                                                   double mu, double *px, double *py, double *pz) {
+// The learned start of a contact the previous step also had is its previous
+// impulse (Sect. 5); the network supplies the start of new contacts.
+__global__ void __launch_bounds__(kBlock) k_decode(const float *y, const double *frame, ContactsView c, int64_t nc,
+                                                   FeatureScales fs, double mu, double *px, double *py, double *pz) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc) return;
+    if (c.matched[j]) {
+        px[j] = c.px[j];
+        py[j] = c.py[j];
+        pz[j] = c.pz[j];
+        return;
+    }
     const double *fr = frame + 9 * j;
     const double s = fs.ms * fs.vs;
     double pn = (double)y[3 * j + 0] * s, pt = (double)y[3 * j + 1] * s, po = (double)y[3 * j + 2] * s;
@@ -273,10 +281,10 @@ nbgs_status launch_features(const BodiesView &b, const ContactsView &c, int64_t 
     return NBGS_OK;
 }
 
-nbgs_status launch_decode(const float *y, const double *frame, int64_t nc, const FeatureScales &fs, double mu,
-                          double *px, double *py, double *pz, hipStream_t s) {
+nbgs_status launch_decode(const float *y, const double *frame, const ContactsView &c, int64_t nc,
+                          const FeatureScales &fs, double mu, double *px, double *py, double *pz, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_decode<<<grid_for(nc), kBlock, 0, s>>>(y, frame, nc, fs, mu, px, py, pz);
+    k_decode<<<grid_for(nc), kBlock, 0, s>>>(y, frame, c, nc, fs, mu, px, py, pz);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

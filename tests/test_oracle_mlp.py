@@ -127,3 +127,11 @@ def test_decode_inverts_targets_inside_the_cone():
     # outside the cone the decode clips: negative normal part -> zero impulse
     t[:, 0] = -1.0
     np.testing.assert_array_equal(oracle.mlp_decode(t, frame, 2.0, 0.5, mu), np.zeros_like(P))
+    # contacts the previous step also had keep their previous impulse, bit for bit; new ones are decoded
+    matched = (np.arange(50) % 3 == 0).astype(np.int32)
+    P0 = rng.normal(size=(50, 3))
+    t = oracle.mlp_targets(frame, P, 2.0, 0.5)
+    out = oracle.mlp_decode(t, frame, 2.0, 0.5, mu, matched=matched, P0=P0)
+    m = matched.astype(bool)
+    np.testing.assert_array_equal(out[m], P0[m])
+    np.testing.assert_allclose(out[~m], P[~m], atol=1e-14)
