@@ -210,6 +210,17 @@ def learned_warm_start(nb, sg, torch, dev, sc, cap, target, steps, train_steps=2
                                                         steps if case == "continued" else 1)
                 g2.close()
     out["runs"] = runs
+    # wall clock to the residual that the plain FP64 form (zero start) reaches at the cap of a cold start
+    r_plain = runs["cold_previous_fp64"]["residual_at_end"][0]
+    reach = {"target": r_plain}
+    for prec in ("fp64", "fp32"):
+        for ws in ("previous", "learned"):
+            g2 = nb.GpuScene(sc.copy(), device=dev, precision=prec, warm_start=ws)
+            rec = _warm_run(nb, torch, g2, mlp, ws, cap, r_plain, 1)
+            reach[f"{ws}_{prec}"] = {"seconds": rec["seconds"][0], "sweeps": rec["sweeps"][0],
+                                     "residual": rec["residual_at_end"][0]}
+            g2.close()
+    out["cold_start_time_to_plain_residual"] = reach
     g.close()
     mlp.close()
     return out

@@ -356,8 +356,9 @@ nbgs_status nbgs_mlp_destroy(nbgs_mlp_t mlp);
 nbgs_status nbgs_mlp_set_weights(nbgs_mlp_t mlp, const float *weights);
 nbgs_status nbgs_mlp_get_weights(nbgs_mlp_t mlp, float *weights);
 
-/* out[n][3] = network(feat[n][12]); [device] row-major FP32.  Features and
- * hidden activations are rounded to BF16 for the matrix cores. */
+/* out[n][3] = network(feat[n][12]); [device] row-major FP32, feat 16-byte
+ * aligned (INVALID_ARG otherwise).  Features and hidden activations are
+ * rounded to BF16 for the matrix cores. */
 nbgs_status nbgs_mlp_forward(nbgs_mlp_t mlp, const float *feat, int64_t n, float *out);
 
 /* Gradient of L = 1/(2n) sum |out - target|^2 over the n samples into grad

@@ -38,6 +38,25 @@ constexpr int NFRAG = G2 + 64 * 64 * 4; // 38,912 BF16 values
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 hbf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU of four FP32 values rounded to BF16 (round to nearest even, two values
+// per conversion instruction); ReLU is taken on the BF16 bit patterns as
+// 16-bit integers, where every negative value (and -0) is below 0.
+__device__ inline bf16x4 relu_bf16(f32x4 v) {
+    const f32x2 lo = {v[0], v[1]}, hi = {v[2], v[3]};
+    const s16x2 z = {0, 0};
+    const s16x2 a = __builtin_elementwise_max(__builtin_bit_cast(s16x2, __builtin_convertvector(lo, hbf16x2)), z);
+    const s16x2 b = __builtin_elementwise_max(__builtin_bit_cast(s16x2, __builtin_convertvector(hi, hbf16x2)), z);
+    bf16x4 r;
+    r[0] = a[0];
+    r[1] = a[1];
+    r[2] = b[0];
+    r[3] = b[1];
+    return r;
+}
 
 // FP32 -> BF16, round to nearest even (NaN kept quiet).
 __device__ inline unsigned short to_bf16(float f) {
@@ -131,29 +150,77 @@ __device__ inline f32x4 forward_tile(const unsigned short *fr, const float *w, c
     return y;
 }
 
-// Inference: y[n][3] = MLP(x[n][12]); a block of 4 waves handles 64 rows.
+// Inference: y[n][3] = MLP(x[n][12]), computed transposed, H^T = W^T X^T:
+// the weights are the A operand and a wave's 16 rows the B operand.  A
+// B-fragment of W is the A-fragment of W^T (same lane layout), so the packed
+// tables serve as they are, and the D layout of one layer (column = row of
+// the batch, row = feature) is the B layout of the next: activations stay in
+// registers, and each wave keeps all weight fragments in registers while it
+// walks its 16-row tiles.
 __global__ void __launch_bounds__(256) k_forward(const unsigned short *fr, const float *w, const float *x, int64_t n,
                                                  float *y) {
-    __shared__ unsigned short xs[64 * XS];
-    __shared__ unsigned short h1[64 * HS];
-    __shared__ unsigned short h2[64 * HS];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t tiles = (n + 63) / 64;
-    for (int64_t bt = blockIdx.x; bt < tiles; bt += gridDim.x) {
-        for (int q = threadIdx.x; q < 64 * 16; q += 256) {
-            const int row = q >> 4, k = q & 15;
-            const int64_t s = bt * 64 + row;
-            xs[row * XS + k] = to_bf16((s < n && k < NF) ? x[s * NF + k] : 0.0f);
+    __shared__ __align__(16) float bias[2 * NH + 16];
+    for (int q = threadIdx.x; q < 2 * NH + 16; q += 256)
+        bias[q] = q < NH ? w[OFF_B1 + q] : q < 2 * NH ? w[OFF_B2 + q - NH] : (q - 2 * NH < NO ? w[OFF_B3 + q - 2 * NH] : 0.0f);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kq = lane >> 4;
+    bf16x4 a1[8], a2[64], a3[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        a1[t] = frag(fr, F1 / 4 + t * 64 + lane);
+        a3[t] = frag(fr, F3 / 4 + t * 64 + lane);
+    }
+#pragma unroll
+    for (int t = 0; t < 64; ++t) a2[t] = frag(fr, F2 / 4 + t * 64 + lane);
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t tiles = (n + 15) / 16;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    // the inputs of the B fragment of x^T for tile t (column = row t*16 + col, k = feature 4 kq + e, 16-byte
+    // aligned), zero past the end; converted to BF16 only when used, so the load of the next tile stays in flight
+    auto load_x = [&](int64_t t) {
+        const int64_t row = t * 16 + col;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (row < n && 4 * kq < NF) v = *reinterpret_cast<const float4 *>(x + row * NF + 4 * kq);
+        return v;
+    };
+    int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    float4 xr = load_x(t), xr1 = load_x(t + nwaves);
+    for (; t < tiles; t += nwaves) {
+        const int64_t row = t * 16 + col;
+        const float4 xn = load_x(t + 2 * nwaves);  // rows two tiles ahead load while this one computes
+        bf16x4 xb;
+        xb[0] = (short)to_bf16(xr.x);
+        xb[1] = (short)to_bf16(xr.y);
+        xb[2] = (short)to_bf16(xr.z);
+        xb[3] = (short)to_bf16(xr.w);
+        // the accumulators start at the bias of their four output features (D rows 4 kq .. 4 kq + 3)
+        bf16x4 h1[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+            h1[mt] = relu_bf16(mfma(a1[mt], xb, *reinterpret_cast<const f32x4 *>(bias + mt * 16 + 4 * kq)));
+        f32x4 acc[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) acc[mt] = *reinterpret_cast<const f32x4 *>(bias + NH + mt * 16 + 4 * kq);
+#pragma unroll
+        for (int kt = 0; kt < 8; ++kt)
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) acc[mt] = mfma(a2[kt * 8 + mt], h1[kt], acc[mt]);
+        bf16x4 h2[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) h2[mt] = relu_bf16(acc[mt]);
+        f32x4 yo = *reinterpret_cast<const f32x4 *>(bias + 2 * NH + 4 * kq), yo2 = zero;  // two chains
+#pragma unroll
+        for (int kt = 0; kt < 8; kt += 2) {
+            yo = mfma(a3[kt], h2[kt], yo);
+            yo2 = mfma(a3[kt + 1], h2[kt + 1], yo2);
         }
-        __syncthreads();
-        const f32x4 d = forward_tile(fr, w, xs, h1, h2, wave * 16, lane);
-        const int col = lane & 15, kq = lane >> 4;
-        if (col < NO)
-            for (int e = 0; e < 4; ++e) {
-                const int64_t s = bt * 64 + wave * 16 + 4 * kq + e;
-                if (s < n) y[s * NO + col] = d[e] + w[OFF_B3 + col];
-            }
-        __syncthreads();
+        yo = yo + yo2;
+        if (kq == 0 && row < n)
+#pragma unroll
+            for (int e = 0; e < NO; ++e) y[row * NO + e] = yo[e];
+        xr = xr1;
+        xr1 = xn;
     }
 }
 
@@ -361,8 +428,16 @@ nbgs_status launch_mlp_pack(const float *w, unsigned short *fr, hipStream_t s) {
 nbgs_status launch_mlp_forward(const unsigned short *fr, const float *w, const float *x, int64_t n, float *y,
                                hipStream_t s) {
     if (n <= 0) return NBGS_OK;
+    // one block of four waves per CU (the weight fragments fill the register file), each wave walking many
+    // 16-row tiles
     const int64_t tiles = (n + 63) / 64;
-    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 2048);
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, cus);
     k_forward<<<grid, 256, 0, s>>>(fr, w, x, n, y);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
@@ -507,6 +582,10 @@ nbgs_status nbgs_mlp_get_weights(nbgs_mlp_t mlp, float *w) {
 nbgs_status nbgs_mlp_forward(nbgs_mlp_t mlp, const float *feat, int64_t n, float *out) {
     if (!mlp || n < 0 || (n > 0 && (!feat || !out))) {
         set_error("bad arguments to nbgs_mlp_forward");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (reinterpret_cast<uintptr_t>(feat) % 16 != 0) {
+        set_error("nbgs_mlp_forward needs 16-byte aligned features");
         return NBGS_ERR_INVALID_ARG;
     }
     return launch_mlp_forward(mlp->fr.p, mlp->w.p, feat, n, out, mlp->s);
