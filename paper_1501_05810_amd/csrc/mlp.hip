@@ -10,7 +10,9 @@
 //   D (16 x 16, FP32):   col l % 16, row = 4 (l / 16) + e
 // Weights are kept as FP32 master copies and repacked after every update into
 // BF16 B-fragments (each lane reads its 4 values as one 8-byte load); the
-// transposed fragments of W2 and W3 serve the backward products.  Hidden
+// transposed fragments of W2 and W3 serve the backward products, and
+// v_mfma_f32_16x16x32_bf16 A-fragments of W2^T and W3^T (8 values per lane)
+// the inference.  Hidden
 // activations pass between layers through LDS in BF16.
 //
 // Weight vector layout (18,563 values): W1[12][128], b1[128], W2[128][128],
@@ -34,11 +36,34 @@ constexpr int F2 = F1 + 8 * 64 * 4;     // W2:   kt(8) x nt(8) x lane x 4
 constexpr int F3 = F2 + 64 * 64 * 4;    // W3:   kt(8) x lane x 4 (cols 3..15 zero)
 constexpr int G3 = F3 + 8 * 64 * 4;     // W3^T: nt(8) x lane x 4 (k 3..15 zero)
 constexpr int G2 = G3 + 8 * 64 * 4;     // W2^T: kt(8) x nt(8) x lane x 4
-constexpr int NFRAG = G2 + 64 * 64 * 4; // 38,912 BF16 values
+constexpr int H2 = G2 + 64 * 64 * 4;    // W2^T as 16x16x32 A-fragments: kt2(4) x mt(8) x lane x 8
+constexpr int H3 = H2 + 32 * 64 * 8;    // W3^T as 16x16x32 A-fragments: kt2(4) x lane x 8 (rows 3..15 zero)
+constexpr int NFRAG = H3 + 4 * 64 * 8;  // 57,344 BF16 values
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 hbf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 hbf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(hbf16x8, a), __builtin_bit_cast(hbf16x8, b), c,
+                                                    0, 0, 0);
+}
+
+// Two 4-value fragments side by side: the 8 k-values of one lane of a 16x16x32 operand.
+__device__ inline s16x8 cat8(bf16x4 lo, bf16x4 hi) {
+    s16x8 r;
+    r[0] = lo[0];
+    r[1] = lo[1];
+    r[2] = lo[2];
+    r[3] = lo[3];
+    r[4] = hi[0];
+    r[5] = hi[1];
+    r[6] = hi[2];
+    r[7] = hi[3];
+    return r;
+}
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 
@@ -96,10 +121,28 @@ __global__ void __launch_bounds__(256) k_pack(const float *w, unsigned short *fr
         const int h = g - G3 / 4, lane = h & 63, nt = h >> 6;
         const int k = 4 * (lane >> 4) + e, n = nt * 16 + (lane & 15);
         v = k < NO ? w[OFF_W3 + n * NO + k] : 0.0f;
-    } else {  // W2^T
+    } else if (o < H2) {  // W2^T
         const int h = g - G2 / 4, lane = h & 63, nt = (h >> 6) & 7, kt = h >> 9;
         const int k = kt * 16 + 4 * (lane >> 4) + e, n = nt * 16 + (lane & 15);
         v = w[OFF_W2 + n * NH + k];
+    } else {
+        // 16x16x32 A-fragments of W^T for the transposed inference.  Lane (m = lane % 16, q = lane / 16),
+        // element e8 = 0..7 carries the input feature f = 32 kt2 + 4 q + e8 (e8 < 4) or 32 kt2 + 16 + 4 q +
+        // e8 - 4 (e8 >= 4): the features that lane holds of two consecutive 16-feature output tiles of the
+        // previous layer, so that those tiles form the B operand as they are (the contraction order over k is
+        // free as long as A and B use the same one).
+        const int h = o < H3 ? o - H2 : o - H3;
+        const int e8 = h & 7, lane = (h >> 3) & 63, q = lane >> 4;
+        const int fidx = h >> 9;  // fragment: kt2 * 8 + mt (W2), kt2 (W3)
+        const int kt2 = o < H3 ? fidx >> 3 : fidx;
+        const int f = 32 * kt2 + (e8 < 4 ? 4 * q + e8 : 16 + 4 * q + e8 - 4);
+        if (o < H3) {
+            const int mt = fidx & 7, m = mt * 16 + (lane & 15);
+            v = w[OFF_W2 + f * NH + m];
+        } else {
+            const int m = lane & 15;
+            v = m < NO ? w[OFF_W3 + f * NO + m] : 0.0f;
+        }
     }
     fr[o] = to_bf16(v);
 }
@@ -151,12 +194,13 @@ __device__ inline f32x4 forward_tile(const unsigned short *fr, const float *w, c
 }
 
 // Inference: y[n][3] = MLP(x[n][12]), computed transposed, H^T = W^T X^T:
-// the weights are the A operand and a wave's 16 rows the B operand.  A
-// B-fragment of W is the A-fragment of W^T (same lane layout), so the packed
-// tables serve as they are, and the D layout of one layer (column = row of
-// the batch, row = feature) is the B layout of the next: activations stay in
-// registers, and each wave keeps all weight fragments in registers while it
-// walks its 16-row tiles.
+// the weights are the A operand and a wave's 16 rows the B operand.  The D
+// layout of one layer (column = row of the batch, row = feature) is the B
+// layout of the next, so activations stay in registers.  Layer 1 (K = 12,
+// padded to 16) uses 16x16x16 products, whose A-fragment of W^T is the packed
+// B-fragment of W (same lane layout); layers 2 and 3 use the double-rate
+// 16x16x32 products with their own fragment tables.  Each wave keeps all
+// weight fragments in registers while it walks its 16-row tiles.
 __global__ void __launch_bounds__(256) k_forward(const unsigned short *fr, const float *w, const float *x, int64_t n,
                                                  float *y) {
     __shared__ __align__(16) float bias[2 * NH + 16];
@@ -165,14 +209,14 @@ __global__ void __launch_bounds__(256) k_forward(const unsigned short *fr, const
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
-    bf16x4 a1[8], a2[64], a3[8];
+    bf16x4 a1[8];
+    s16x8 a2[32], a3[4];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        a1[t] = frag(fr, F1 / 4 + t * 64 + lane);
-        a3[t] = frag(fr, F3 / 4 + t * 64 + lane);
-    }
+    for (int t = 0; t < 8; ++t) a1[t] = frag(fr, F1 / 4 + t * 64 + lane);
 #pragma unroll
-    for (int t = 0; t < 64; ++t) a2[t] = frag(fr, F2 / 4 + t * 64 + lane);
+    for (int t = 0; t < 32; ++t) a2[t] = *reinterpret_cast<const s16x8 *>(fr + H2 + 8 * (t * 64 + lane));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a3[t] = *reinterpret_cast<const s16x8 *>(fr + H3 + 8 * (t * 64 + lane));
     const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
     const int64_t tiles = (n + 15) / 16;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -203,17 +247,19 @@ __global__ void __launch_bounds__(256) k_forward(const unsigned short *fr, const
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) acc[mt] = *reinterpret_cast<const f32x4 *>(bias + NH + mt * 16 + 4 * kq);
 #pragma unroll
-        for (int kt = 0; kt < 8; ++kt)
+        for (int kt2 = 0; kt2 < 4; ++kt2) {
+            const s16x8 b = cat8(h1[2 * kt2], h1[2 * kt2 + 1]);
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) acc[mt] = mfma(a2[kt * 8 + mt], h1[kt], acc[mt]);
+            for (int mt = 0; mt < 8; ++mt) acc[mt] = mfma32(a2[kt2 * 8 + mt], b, acc[mt]);
+        }
         bf16x4 h2[8];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) h2[mt] = relu_bf16(acc[mt]);
         f32x4 yo = *reinterpret_cast<const f32x4 *>(bias + 2 * NH + 4 * kq), yo2 = zero;  // two chains
 #pragma unroll
-        for (int kt = 0; kt < 8; kt += 2) {
-            yo = mfma(a3[kt], h2[kt], yo);
-            yo2 = mfma(a3[kt + 1], h2[kt + 1], yo2);
+        for (int kt2 = 0; kt2 < 4; kt2 += 2) {
+            yo = mfma32(a3[kt2], cat8(h2[2 * kt2], h2[2 * kt2 + 1]), yo);
+            yo2 = mfma32(a3[kt2 + 1], cat8(h2[2 * kt2 + 2], h2[2 * kt2 + 3]), yo2);
         }
         yo = yo + yo2;
         if (kq == 0 && row < n)
