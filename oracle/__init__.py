@@ -62,7 +62,8 @@ class RefWorldView(C.Structure):
     _fields_ = [("n_contacts", C.c_int64), ("n_colours", C.c_int32), ("sweeps", C.c_int32),
                 ("residual", C.c_double), ("j1", _i32p), ("j2", _i32p), ("colour", _i32p), ("key", _u64p)] + \
                [(f, _dp) for f in ("nx", "ny", "nz", "xi", "a1", "a2", "px", "py", "pz")] + \
-               [("order", _i64p), ("v", _dp), ("w", _dp), ("residual_hist", _dp)]
+               [("order", _i64p), ("v", _dp), ("w", _dp), ("residual_hist", _dp), ("sdom", _i32p),
+                ("n_sub", C.c_int32)]
 
 
 def build(force: bool = False) -> str:
@@ -102,6 +103,8 @@ def lib():
         L.nbgs_ref_world_view_get.argtypes = [C.c_void_p, C.POINTER(RefWorldView)]
         L.nbgs_ref_world_set_impulses.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.nbgs_ref_world_set_prev.argtypes = [C.c_void_p, C.c_int64, _u64p, _dp, _dp, _dp]
+        L.nbgs_ref_world_set_subdomains.argtypes = [C.c_void_p, C.c_double]
+        L.nbgs_ref_subdomains.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -211,17 +214,57 @@ def hull_radii(sc) -> np.ndarray:
     return h
 
 
-def colour(n_bodies: int, inv_mass: np.ndarray, j1: np.ndarray, j2: np.ndarray, key: np.ndarray, seed: int):
-    """Greedy colouring in descending splitmix64 priority; returns (colour per contact, number of colours)."""
+def colour(n_bodies: int, inv_mass: np.ndarray, j1: np.ndarray, j2: np.ndarray, key: np.ndarray, seed: int,
+           sdom=None):
+    """Greedy colouring in descending splitmix64 priority (conflicts only inside a subdomain when sdom is
+    given); returns (colour per contact, number of colours)."""
     m = int(j1.shape[0])
     col = np.full(max(m, 1), -1, dtype=np.int32)
     im = np.ascontiguousarray(inv_mass, dtype=np.float64)
     j1c = np.ascontiguousarray(j1, dtype=np.int32)
     j2c = np.ascontiguousarray(j2, dtype=np.int32)
     kc = np.ascontiguousarray(key, dtype=np.uint64)
+    sd = None if sdom is None else _ptr(np.ascontiguousarray(sdom, dtype=np.int32), _i32p)
     nc = lib().nbgs_ref_colour(C.c_int64(n_bodies), _ptr(im), C.c_int64(m), _ptr(j1c, _i32p), _ptr(j2c, _i32p),
-                               _ptr(kc, _u64p), C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _ptr(col, _i32p))
+                               _ptr(kc, _u64p), C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), sd, _ptr(col, _i32p))
     return col[:m].copy(), int(nc)
+
+
+def subdomains(sc, j1: np.ndarray, edge: float):
+    """Subdomain (block of body j1's centre) of every contact; returns (sdom, number of blocks)."""
+    held = _Held()
+    b = make_bodies(sc, held)
+    dom = make_domain(sc, held)
+    m = int(j1.shape[0])
+    out = np.zeros(max(m, 1), dtype=np.int32)
+    j1c = np.ascontiguousarray(j1, dtype=np.int32)
+    n = lib().nbgs_ref_subdomains(C.byref(b), C.byref(dom), C.c_double(edge), C.c_int64(m), _ptr(j1c, _i32p),
+                                  _ptr(out, _i32p))
+    return out[:m].copy(), int(n)
+
+
+def solve_sub(sc, c: Dict[str, np.ndarray], order: np.ndarray, sdom: np.ndarray, P0: np.ndarray, sweeps: int):
+    """Subdomain NBGS on a given contact list, sweep order and subdomain of every contact (the order must group
+    the subdomains in ascending order).  Returns (P, v', w', residual history)."""
+    held = _Held()
+    b = make_bodies(sc, held)
+    prm = make_params(sc)
+    m = int(c["j1"].shape[0])
+    f = lambda a, t=np.float64: np.ascontiguousarray(a, dtype=t)  # noqa: E731
+    j1, j2 = f(c["j1"], np.int32), f(c["j2"], np.int32)
+    nx, ny, nz = f(c["n"][:, 0]), f(c["n"][:, 1]), f(c["n"][:, 2])
+    xi, a1, a2 = f(c["xi"]), f(c["a1"]), f(c["a2"])
+    px, py, pz = f(P0[:, 0]).copy(), f(P0[:, 1]).copy(), f(P0[:, 2]).copy()
+    od, sd = f(order, np.int64), f(sdom, np.int32)
+    v = np.zeros(3 * sc.n)
+    w = np.zeros(3 * sc.n)
+    hist = np.zeros(max(sweeps, 1))
+    st = RefSolveStats()
+    lib().nbgs_ref_solve_sub(C.byref(b), C.byref(prm), C.c_int64(m), _ptr(j1, _i32p), _ptr(j2, _i32p), _ptr(nx),
+                             _ptr(ny), _ptr(nz), _ptr(xi), _ptr(a1), _ptr(a2), _ptr(od, _i64p), _ptr(sd, _i32p),
+                             _ptr(px), _ptr(py), _ptr(pz), C.c_int32(sweeps), C.c_double(0.0), _ptr(v), _ptr(w),
+                             _ptr(hist), C.byref(st))
+    return np.stack([px, py, pz], axis=1), v.reshape(-1, 3), w.reshape(-1, 3), hist[:st.sweeps].copy()
 
 
 def sweep_order(col: np.ndarray, n_colours: int) -> np.ndarray:
@@ -317,7 +360,14 @@ class World:
         out["w"] = arr(v.w, 3 * n, np.float64).reshape(n, 3)
         hist = arr(v.residual_hist, int(v.sweeps), np.float64) if v.residual_hist else np.zeros(0)
         out["residual_hist"] = hist
+        out["sdom"] = arr(v.sdom, m, np.int32) if v.sdom else None
+        out["n_sub"] = int(v.n_sub)
         return out
+
+    def set_subdomains(self, edge: float):
+        """edge > 0: subdomain NBGS with blocks of about this edge from the next detection on; 0: classic."""
+        lib().nbgs_ref_world_set_subdomains(self._w, C.c_double(edge))
+        return self
 
 
 # ------------------------------------------------------------- learned warm start

@@ -376,12 +376,13 @@ static int cmp_priority(const void *a, const void *b)
 
 /* Greedy first-fit colouring of the contact conflict graph, visiting contacts
  * in descending priority pi_j = splitmix64(key_j ^ seed) (ties: ascending
- * key).  Two contacts conflict iff they share a body with inverse mass > 0;
- * planes (index >= n_bodies) and static spheres never conflict.  Each contact
- * takes the smallest colour not used by an already coloured conflicting
- * contact.  Returns the number of colours. */
+ * key).  Two contacts conflict iff they share a body with inverse mass > 0
+ * (and, when sdom is given, lie in the same subdomain); planes (index >=
+ * n_bodies) and static spheres never conflict.  Each contact takes the
+ * smallest colour not used by an already coloured conflicting contact.
+ * Returns the number of colours. */
 int32_t nbgs_ref_colour(int64_t n_bodies, const double *inv_mass, int64_t nc, const int32_t *j1, const int32_t *j2,
-                        const uint64_t *key, uint64_t seed, int32_t *colour)
+                        const uint64_t *key, uint64_t seed, const int32_t *sdom, int32_t *colour)
 {
     if (nc == 0) return 0;
     /* body -> incident contacts */
@@ -421,6 +422,7 @@ int32_t nbgs_ref_colour(int64_t n_bodies, const double *inv_mass, int64_t nc, co
             for (int64_t q = deg[body]; q < deg[body + 1]; ++q) {
                 int32_t c = colour[inc[q]];
                 if (c < 0) continue;
+                if (sdom && sdom[inc[q]] != sdom[j]) continue;
                 if ((size_t)c >= used_cap) {
                     size_t nc2 = used_cap;
                     while ((size_t)c >= nc2) nc2 *= 2;
@@ -453,6 +455,50 @@ void nbgs_ref_sweep_order(int64_t nc, const int32_t *colour, int32_t n_colours, 
     for (int32_t c = 0; c < n_colours; ++c)
         for (int64_t j = 0; j < nc; ++j)
             if (colour[j] == c) order[t++] = j;
+}
+
+/* Subdomains (Alg. 1's s_c(j), the domain partitioning of Sect. 6.1): the
+ * box is cut into nb_a = max(1, floor(L_a / edge)) blocks per axis of edge
+ * L_a / nb_a, and contact j belongs to the block holding the centre of body
+ * j1 (block coordinates clamped into the box).  Block id (c_z nb_y + c_y)
+ * nb_x + c_x.  Returns the number of blocks. */
+int32_t nbgs_ref_subdomains(const ref_bodies *b, const ref_domain *dom, double edge, int64_t nc, const int32_t *j1,
+                            int32_t *sdom)
+{
+    int64_t nb[3];
+    double e[3];
+    for (int a = 0; a < 3; ++a) {
+        double L = dom->hi[a] - dom->lo[a];
+        double c = floor(L / edge);
+        if (!(c >= 1.0)) c = 1.0;
+        nb[a] = (int64_t)c;
+        e[a] = L / c;
+    }
+    for (int64_t j = 0; j < nc; ++j) {
+        int64_t i = j1[j];
+        double x[3] = {b->x[i], b->y[i], b->z[i]};
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            double f = floor((x[a] - dom->lo[a]) / e[a]);
+            f = fmax(0.0, fmin(f, (double)(nb[a] - 1)));
+            c[a] = (int64_t)f;
+        }
+        sdom[j] = (int32_t)((c[2] * nb[1] + c[1]) * nb[0] + c[0]);
+    }
+    return (int32_t)(nb[0] * nb[1] * nb[2]);
+}
+
+/* Sweep order of the subdomain solver: contacts sorted by (subdomain, colour,
+ * key); the list is in key order, so a stable grouping suffices. */
+void nbgs_ref_sweep_order_sub(int64_t nc, const int32_t *sdom, int32_t n_sub, const int32_t *colour, int32_t n_colours,
+                              int64_t *order)
+{
+    int64_t nbin = (int64_t)n_sub * (n_colours > 0 ? n_colours : 1);
+    int64_t *start = (int64_t *)calloc((size_t)nbin + 1, sizeof(int64_t));
+    for (int64_t j = 0; j < nc; ++j) start[(int64_t)sdom[j] * n_colours + colour[j] + 1]++;
+    for (int64_t q = 0; q < nbin; ++q) start[q + 1] += start[q];
+    for (int64_t j = 0; j < nc; ++j) order[start[(int64_t)sdom[j] * n_colours + colour[j]]++] = j;
+    free(start);
 }
 
 /* ----------------------------------------------------------- warm start */
@@ -681,6 +727,174 @@ void nbgs_ref_solve(const ref_bodies *b, const ref_params *p, int64_t nc, const 
     }
 }
 
+/* Velocities of body i as a contact of subdomain s sees them: accumulator
+ * plus the subdomain's correction (Sect. 6.3); zero for a wall. */
+static void seen_velocity(int64_t N, const double *V, const double *Wv, const double *dv, const double *dw, int64_t i,
+                          double *v, double *w)
+{
+    for (int a = 0; a < 3; ++a) {
+        v[a] = i < N ? V[3 * i + a] + dv[3 * i + a] : 0.0;
+        w[a] = i < N ? Wv[3 * i + a] + dw[3 * i + a] : 0.0;
+    }
+}
+
+/* One pass over all subdomains.  mode 0 applies the initial impulses, mode 1
+ * relaxes every contact (Alg. 1).  Within subdomain s the contacts are taken
+ * in sweep order and see the accumulators V, W of the last iteration plus the
+ * corrections dv, dw of the contacts of s relaxed before them; afterwards the
+ * corrections are added to the next accumulators Vn, Wn, subdomain by
+ * subdomain in ascending order. */
+static void sub_pass(int mode, const ref_bodies *b, const ref_params *p, int64_t nc, const int32_t *j1,
+                     const int32_t *j2, const double *nx, const double *ny, const double *nz, const double *xi,
+                     const double *a1, const double *a2, const int64_t *order, const int32_t *sdom, double *px,
+                     double *py, double *pz, double *V, double *Wv, double *Vn, double *Wn, double *dv, double *dw,
+                     int64_t *stamp, int64_t *touched, double *sum_dp, double *sum_p)
+{
+    int64_t N = b->n;
+    const double *im = b->inv_mass, *ii = b->inv_inertia;
+    memcpy(Vn, V, sizeof(double) * 3 * (size_t)N);
+    memcpy(Wn, Wv, sizeof(double) * 3 * (size_t)N);
+    *sum_dp = 0.0;
+    *sum_p = 0.0;
+    int64_t t = 0;
+    while (t < nc) {
+        int32_t s = sdom[order[t]];
+        int64_t u = t;
+        while (u < nc && sdom[order[u]] == s) ++u;
+        /* corrections of subdomain s start at zero */
+        int64_t nt = 0;
+        for (int64_t q = t; q < u; ++q) {
+            int64_t j = order[q];
+            int64_t ends[2] = {j1[j], j2[j]};
+            for (int e = 0; e < 2; ++e) {
+                int64_t i = ends[e];
+                if (i >= N || !(im[i] > 0.0) || stamp[i] == (int64_t)s + 1) continue;
+                stamp[i] = (int64_t)s + 1;
+                touched[nt++] = i;
+                for (int a = 0; a < 3; ++a) {
+                    dv[3 * i + a] = 0.0;
+                    dw[3 * i + a] = 0.0;
+                }
+            }
+        }
+        for (int64_t q = t; q < u; ++q) {
+            int64_t j = order[q];
+            int32_t b1 = j1[j], b2 = j2[j];
+            double n[3] = {nx[j], ny[j], nz[j]};
+            double P[3] = {px[j], py[j], pz[j]};
+            if (mode == 0) {
+                if (P[0] != 0.0 || P[1] != 0.0 || P[2] != 0.0) apply_impulse(N, im, ii, dv, dw, b1, b2, n, a1[j], a2[j], P);
+                continue;
+            }
+            double v1[3], w1[3], v2[3], w2[3];
+            seen_velocity(N, V, Wv, dv, dw, b1, v1, w1);
+            seen_velocity(N, V, Wv, dv, dw, b2, v2, w2);
+            double im1 = im[b1], ii1 = ii[b1];
+            double im2 = b2 < N ? im[b2] : 0.0, ii2 = b2 < N ? ii[b2] : 0.0;
+            double s0 = a1[j] * w1[0] + a2[j] * w2[0];
+            double s1 = a1[j] * w1[1] + a2[j] * w2[1];
+            double s2 = a1[j] * w1[2] + a2[j] * w2[2];
+            double du[3];
+            du[0] = (v1[0] - v2[0]) - (s1 * n[2] - s2 * n[1]);
+            du[1] = (v1[1] - v2[1]) - (s2 * n[0] - s0 * n[2]);
+            du[2] = (v1[2] - v2[2]) - (s0 * n[1] - s1 * n[0]);
+            double dun = n[0] * du[0] + n[1] * du[1] + n[2] * du[2];
+            double corr = xi[j] < 0.0 ? p->erp * xi[j] : xi[j];
+            double un = corr / p->dt + dun;
+            double ut[3] = {du[0] - dun * n[0], du[1] - dun * n[1], du[2] - dun * n[2]};
+            double Pn = n[0] * P[0] + n[1] * P[1] + n[2] * P[2];
+            double Pt[3] = {P[0] - Pn * n[0], P[1] - Pn * n[1], P[2] - Pn * n[2]};
+            double wn = im1 + im2;
+            double wt = wn + ii1 * a1[j] * a1[j] + ii2 * a2[j] * a2[j];
+            double bn = un - wn * Pn;
+            double bt[3] = {ut[0] - wt * Pt[0], ut[1] - wt * Pt[1], ut[2] - wt * Pt[2]};
+            double Ps[3];
+            one_contact(bn, bt, wn, wt, p->mu, n, Ps);
+            double Pnew[3], dP[3];
+            for (int a = 0; a < 3; ++a) {
+                Pnew[a] = p->relax * Ps[a] + (1.0 - p->relax) * P[a];
+                dP[a] = Pnew[a] - P[a];
+            }
+            apply_impulse(N, im, ii, dv, dw, b1, b2, n, a1[j], a2[j], dP);
+            px[j] = Pnew[0];
+            py[j] = Pnew[1];
+            pz[j] = Pnew[2];
+            *sum_dp += dP[0] * dP[0] + dP[1] * dP[1] + dP[2] * dP[2];
+            *sum_p += Pnew[0] * Pnew[0] + Pnew[1] * Pnew[1] + Pnew[2] * Pnew[2];
+        }
+        for (int64_t k = 0; k < nt; ++k) {
+            int64_t i = touched[k];
+            for (int a = 0; a < 3; ++a) {
+                Vn[3 * i + a] = Vn[3 * i + a] + dv[3 * i + a];
+                Wn[3 * i + a] = Wn[3 * i + a] + dw[3 * i + a];
+            }
+        }
+        t = u;
+    }
+    memcpy(V, Vn, sizeof(double) * 3 * (size_t)N);
+    memcpy(Wv, Wn, sizeof(double) * 3 * (size_t)N);
+}
+
+/* Subdomain NBGS of one time step (Alg. 1 with the subdomain affinity sdom),
+ * in the velocity form of Sect. 6.3.  Contact j of subdomain s sees the
+ * newest impulses of the contacts of s relaxed before it and the last
+ * iteration's impulses of every other contact: its bodies' velocities are the
+ * accumulators of the last iteration plus the corrections made by s in this
+ * iteration.  At the end of an iteration the corrections of all subdomains
+ * are added to the accumulators.  The initial impulses enter the same way, as
+ * the corrections of a first pass.  order lists the contacts grouped by
+ * ascending subdomain (sweep order inside each).  Arguments as
+ * nbgs_ref_solve. */
+void nbgs_ref_solve_sub(const ref_bodies *b, const ref_params *p, int64_t nc, const int32_t *j1, const int32_t *j2,
+                        const double *nx, const double *ny, const double *nz, const double *xi, const double *a1,
+                        const double *a2, const int64_t *order, const int32_t *sdom, double *px, double *py,
+                        double *pz, int32_t max_sweeps, double target, double *v_out, double *w_out,
+                        double *residual_hist, ref_solve_stats *stats)
+{
+    int64_t N = b->n;
+    size_t n3 = 3 * (size_t)(N > 0 ? N : 1);
+    const double *im = b->inv_mass;
+    double *V = v_out, *Wv = w_out;
+    for (int64_t i = 0; i < N; ++i) {
+        int dyn = im[i] > 0.0;
+        V[3 * i + 0] = dyn ? b->vx[i] + p->dt * p->gravity[0] : b->vx[i];
+        V[3 * i + 1] = dyn ? b->vy[i] + p->dt * p->gravity[1] : b->vy[i];
+        V[3 * i + 2] = dyn ? b->vz[i] + p->dt * p->gravity[2] : b->vz[i];
+        Wv[3 * i + 0] = b->wx[i];
+        Wv[3 * i + 1] = b->wy[i];
+        Wv[3 * i + 2] = b->wz[i];
+    }
+    double *Vn = (double *)malloc(sizeof(double) * n3), *Wn = (double *)malloc(sizeof(double) * n3);
+    double *dv = (double *)calloc(n3, sizeof(double)), *dw = (double *)calloc(n3, sizeof(double));
+    int64_t *stamp = (int64_t *)calloc((size_t)(N > 0 ? N : 1), sizeof(int64_t));
+    int64_t *touched = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+    double sdp, sp;
+    sub_pass(0, b, p, nc, j1, j2, nx, ny, nz, xi, a1, a2, order, sdom, px, py, pz, V, Wv, Vn, Wn, dv, dw, stamp,
+             touched, &sdp, &sp);
+    int32_t k = 0;
+    double R = 0.0;
+    while (k < max_sweeps) {
+        for (int64_t i = 0; i < N; ++i) stamp[i] = 0;
+        sub_pass(1, b, p, nc, j1, j2, nx, ny, nz, xi, a1, a2, order, sdom, px, py, pz, V, Wv, Vn, Wn, dv, dw, stamp,
+                 touched, &sdp, &sp);
+        double den = sqrt(sp);
+        R = sqrt(sdp) / (den > 1e-300 ? den : 1e-300);
+        if (residual_hist) residual_hist[k] = R;
+        ++k;
+        if (target > 0.0 && R <= target) break;
+    }
+    free(Vn);
+    free(Wn);
+    free(dv);
+    free(dw);
+    free(stamp);
+    free(touched);
+    if (stats) {
+        stats->sweeps = k;
+        stats->residual = R;
+    }
+}
+
 /* ------------------------------------------------------------- integrate */
 
 /* eq. (integrationscheme): v <- v', w <- w', x <- x + dt v',
@@ -748,6 +962,9 @@ typedef struct {
     ref_solve_stats stats;
     double *residual_hist;
     int32_t hist_cap;
+    double sub_edge; /* > 0: subdomain NBGS with blocks of about this edge */
+    int32_t *sdom;
+    int32_t n_sub;
 } ref_world;
 
 /* Read-only view of a world's current contact state. */
@@ -762,6 +979,8 @@ typedef struct {
     const int64_t *order;       /* sweep order */
     const double *v, *w;        /* accumulators v', w' after the last solve, xyz interleaved */
     const double *residual_hist;
+    const int32_t *sdom; /* subdomain of every contact (subdomain mode), else NULL */
+    int32_t n_sub;
 } ref_world_view;
 
 static void contacts_alloc(ref_contacts *c, int64_t cap)
@@ -825,6 +1044,7 @@ void nbgs_ref_world_destroy(ref_world *W)
     free(W->prev_py);
     free(W->prev_pz);
     free(W->residual_hist);
+    free(W->sdom);
     free(W);
 }
 
@@ -847,8 +1067,17 @@ void nbgs_ref_world_detect(ref_world *W, int32_t use_grid, int32_t warm)
     W->px = (double *)realloc(W->px, n * sizeof(double));
     W->py = (double *)realloc(W->py, n * sizeof(double));
     W->pz = (double *)realloc(W->pz, n * sizeof(double));
-    W->n_colours = nbgs_ref_colour(W->b.n, W->b.inv_mass, m, W->c.j1, W->c.j2, W->c.key, W->p.colour_seed, W->colour);
-    nbgs_ref_sweep_order(m, W->colour, W->n_colours, W->order);
+    if (W->sub_edge > 0.0) {
+        W->sdom = (int32_t *)realloc(W->sdom, n * sizeof(int32_t));
+        W->n_sub = nbgs_ref_subdomains(&W->b, &W->dom, W->sub_edge, m, W->c.j1, W->sdom);
+        W->n_colours =
+            nbgs_ref_colour(W->b.n, W->b.inv_mass, m, W->c.j1, W->c.j2, W->c.key, W->p.colour_seed, W->sdom, W->colour);
+        nbgs_ref_sweep_order_sub(m, W->sdom, W->n_sub, W->colour, W->n_colours, W->order);
+    } else {
+        W->n_colours =
+            nbgs_ref_colour(W->b.n, W->b.inv_mass, m, W->c.j1, W->c.j2, W->c.key, W->p.colour_seed, NULL, W->colour);
+        nbgs_ref_sweep_order(m, W->colour, W->n_colours, W->order);
+    }
     if (warm && W->n_prev > 0) {
         nbgs_ref_warm_match(m, W->c.key, W->c.nx, W->c.ny, W->c.nz, W->p.mu, W->n_prev, W->prev_key, W->prev_px,
                             W->prev_py, W->prev_pz, W->px, W->py, W->pz);
@@ -875,8 +1104,13 @@ void nbgs_ref_world_solve(ref_world *W, int32_t max_sweeps, double target)
         W->residual_hist = (double *)realloc(W->residual_hist, sizeof(double) * (size_t)max_sweeps);
         W->hist_cap = max_sweeps;
     }
-    nbgs_ref_solve(&W->b, &W->p, W->nc, W->c.j1, W->c.j2, W->c.nx, W->c.ny, W->c.nz, W->c.xi, W->c.a1, W->c.a2,
-                   W->order, W->px, W->py, W->pz, max_sweeps, target, W->v, W->w, W->residual_hist, &W->stats);
+    if (W->sub_edge > 0.0)
+        nbgs_ref_solve_sub(&W->b, &W->p, W->nc, W->c.j1, W->c.j2, W->c.nx, W->c.ny, W->c.nz, W->c.xi, W->c.a1,
+                           W->c.a2, W->order, W->sdom, W->px, W->py, W->pz, max_sweeps, target, W->v, W->w,
+                           W->residual_hist, &W->stats);
+    else
+        nbgs_ref_solve(&W->b, &W->p, W->nc, W->c.j1, W->c.j2, W->c.nx, W->c.ny, W->c.nz, W->c.xi, W->c.a1, W->c.a2,
+                       W->order, W->px, W->py, W->pz, max_sweeps, target, W->v, W->w, W->residual_hist, &W->stats);
     /* keep (key, impulse) for the next step's warm start */
     if (W->nc > W->prev_cap) {
         W->prev_cap = W->nc;
@@ -927,7 +1161,13 @@ void nbgs_ref_world_view_get(const ref_world *W, ref_world_view *out)
     out->v = W->v;
     out->w = W->w;
     out->residual_hist = W->residual_hist;
+    out->sdom = W->sub_edge > 0.0 ? W->sdom : NULL;
+    out->n_sub = W->sub_edge > 0.0 ? W->n_sub : 0;
 }
+
+/* edge > 0: later detections assign subdomains and solves run the subdomain
+ * NBGS; edge = 0: one subdomain, the classic NBGS. */
+void nbgs_ref_world_set_subdomains(ref_world *W, double edge) { W->sub_edge = edge > 0.0 ? edge : 0.0; }
 
 /* Replace the previous-step impulse table (key-sorted) used by the warm start. */
 void nbgs_ref_world_set_prev(ref_world *W, int64_t n, const uint64_t *key, const double *px, const double *py,
