@@ -199,6 +199,22 @@ nbgs_status nbgs_get_accumulators(nbgs_scene_t scene, double *v, double *w);
  * Synchronises. */
 nbgs_status nbgs_get_residuals(nbgs_scene_t scene, int32_t cap, double *hist, int32_t *n_out);
 
+/* Solver of later steps: edge = 0 (default) the NBGS in colour order (one
+ * subdomain, the classic Gauss-Seidel of Alg. 1); edge > 0 the subdomain
+ * NBGS of Alg. 1, whose subdomain affinity s_c(j) is the block holding body
+ * j1's centre when the box is cut into max(1, floor(L_a / edge)) blocks of
+ * edge L_a / that count per axis (domain partitioning, Sect. 6.1).  A contact
+ * sees the newest impulses of the contacts of its subdomain relaxed before it
+ * (colouring restricted to the subdomain, order (subdomain, colour, key)) and
+ * the last iteration's impulses of all others; with accumulated velocities
+ * and per-subdomain velocity corrections summed at the end of every sweep in
+ * ascending subdomain (Sect. 6.3).  Use a relaxation below 1 (the paper's
+ * runs use 0.75): across subdomains the iteration is a Jacobi one.
+ * CAPACITY at detection if a subdomain touches too many bodies for the
+ * workgroup's local memory (about 540 in FP64): use a smaller edge.
+ * UNSUPPORTED for batches and with the learned warm start. */
+nbgs_status nbgs_set_subdomains(nbgs_scene_t scene, double edge);
+
 /* enable = 1 (default): the residual R_k of every sweep is formed.  enable =
  * 0: a solve without a residual target forms only the last sweep's residual
  * (the one nbgs_stats reports); impulses and velocities are unchanged.  A

@@ -91,6 +91,7 @@ _SIGNATURES = [
     ("nbgs_get_residuals", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("nbgs_set_warm_start", C.c_int, [_vp, C.c_int64, _vp, _vp]),
     ("nbgs_set_residual_history", C.c_int, [_vp, C.c_int32]),
+    ("nbgs_set_subdomains", C.c_int, [_vp, C.c_double]),
     ("nbgs_get_phase_times", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     ("nbgs_mlp_param_count", C.c_int32, []),
     ("nbgs_mlp_create", C.c_int, [C.c_uint64, _vp, C.POINTER(_vp)]),
@@ -216,6 +217,10 @@ def nbgs_get_residuals(h: int, cap: int) -> np.ndarray:
 
 def nbgs_set_warm_start(h: int, n: int, keys_ptr: int, impulse_ptr: int) -> None:
     _check(lib().nbgs_set_warm_start(_vp(h), int(n), _vp(keys_ptr), _vp(impulse_ptr)))
+
+
+def nbgs_set_subdomains(h: int, edge: float) -> None:
+    _check(lib().nbgs_set_subdomains(_vp(h), float(edge)))
 
 
 def nbgs_set_residual_history(h: int, enable: bool) -> None:
@@ -547,6 +552,11 @@ class GpuScene:
 
     def set_residual_history(self, enable: bool = True):
         nbgs_set_residual_history(self.handle, enable)
+
+    def set_subdomains(self, edge: float):
+        """edge > 0: subdomain NBGS with blocks of about this edge from the next step on; 0: colour-order NBGS."""
+        nbgs_set_subdomains(self.handle, edge)
+        return self
 
     def set_warm_start(self, keys: np.ndarray, P: np.ndarray):
         torch = self.torch

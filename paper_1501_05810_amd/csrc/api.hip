@@ -181,6 +181,17 @@ DevBuf<float> &vel_buf<float>(nbgs_scene_t sc) {
     return sc->vel32;
 }
 
+template <class T>
+DevBuf<T> &corr_buf(nbgs_scene_t sc);
+template <>
+DevBuf<double> &corr_buf<double>(nbgs_scene_t sc) {
+    return sc->corr64;
+}
+template <>
+DevBuf<float> &corr_buf<float>(nbgs_scene_t sc) {
+    return sc->corr32;
+}
+
 nbgs_status sync_small(nbgs_scene_t sc, int first, int count) {
     NBGS_HIP(hipMemcpyAsync(sc->pinned + first, sc->small.p + first, sizeof(int32_t) * count, hipMemcpyDeviceToHost,
                             sc->s));
@@ -192,9 +203,10 @@ template <class T>
 nbgs_status gather_for_sweeps(nbgs_scene_t sc) {
     SweepBuf<T> &sw = sweep_buf<T>(sc);
     sw.per_contact_mu = sc->n_scenes > 1;
+    sw.sub = sc->sub_active;
     NBGS_TRY(sw.reserve((size_t)sc->nc));
-    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), sc->spos.p, sc->nc, sc->p.dt, sc->p.erp, sc->table(),
-                                  sw.view(), sc->s);
+    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), sc->spos.p, sc->sub_active ? sc->sdom.p : nullptr, sc->nc,
+                                  sc->p.dt, sc->p.erp, sc->table(), sw.view(), sc->s);
 }
 
 nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
@@ -287,6 +299,10 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
         }
     }
     record(sc, kColour);
+    // subdomain solver: the colouring is restricted to the contacts of one subdomain
+    sc->sub_active = sc->sub_edge > 0.0 && nc > 0;
+    if (sc->sub_active) NBGS_TRY(subdomain_assign(sc));
+    const int32_t *sdom = sc->sub_active ? sc->sdom.p : nullptr;
     // colouring: body -> contacts where it is j2 (as j1 it owns the segment off[i] .. off[i] + cnt[i])
     NBGS_TRY(sc->inc2.reserve((size_t)(nc > 0 ? nc : 1)));
     NBGS_TRY(sc->prio.reserve((size_t)(nc > 0 ? nc : 1)));
@@ -301,7 +317,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
         for (int pass = 0;; ++pass) {
             NBGS_HIP(hipMemsetAsync(sc->remaining(), 0, 2 * sizeof(int32_t), s));
             NBGS_TRY(launch_colour_fix(cb.view(), sc->prio.p, nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p, sc->off2.p,
-                                       sc->inc2.p, sc->remaining(), sc->overflow(), s));
+                                       sc->inc2.p, sdom, sc->remaining(), sc->overflow(), s));
             NBGS_TRY(sync_small(sc, 1, 2));
             sc->colour_passes = pass + 1;
             if (sc->pinned[2]) {
@@ -323,7 +339,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
         for (;;) {
             for (int r = 0; r < batch; ++r)
                 NBGS_TRY(launch_jp_round(cb.view(), sc->prio.p, nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p,
-                                         sc->off2.p, sc->inc2.p, sc->remaining(), sc->overflow(), s));
+                                         sc->off2.p, sc->inc2.p, sdom, sc->remaining(), sc->overflow(), s));
             rounds += batch;
             NBGS_TRY(sync_small(sc, 1, 2));
             if (sc->pinned[2]) {
@@ -355,13 +371,14 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_TRY(sc->cids.reserve((size_t)nc + 1));
     NBGS_TRY(sc->ckeys2.reserve((size_t)nc + 1));
     NBGS_TRY(sc->cids2.reserve((size_t)nc + 1));
-    NBGS_TRY(launch_colour_keys(cb.view(), nc, sc->ckeys.p, sc->cids.p, s));
+    NBGS_TRY(launch_colour_keys(cb.view(), sdom, nc, sc->ckeys.p, sc->cids.p, s));
     if ((size_t)radix_hist_entries(nc) > sc->radix_hist.cap) NBGS_TRY(sc->radix_hist.reserve(radix_hist_entries(nc)));
     const size_t need_tmp = exclusive_scan_tmp_bytes((int64_t)radix_hist_entries(nc));
     if (need_tmp > sc->scan_tmp.cap) NBGS_TRY(sc->scan_tmp.reserve(need_tmp));
     bool calt = false;
-    NBGS_TRY(radix_sort_pairs(sc->ckeys.p, sc->cids.p, sc->ckeys2.p, sc->cids2.p, nc, 8, sc->radix_hist.p,
-                              sc->scan_tmp.p, sc->scan_tmp.cap, &calt, s));
+    NBGS_TRY(radix_sort_pairs(sc->ckeys.p, sc->cids.p, sc->ckeys2.p, sc->cids2.p, nc,
+                              sdom ? 8 + bits_for(sc->n_sub) : 8, sc->radix_hist.p, sc->scan_tmp.p, sc->scan_tmp.cap,
+                              &calt, s));
     const uint32_t *perm = calt ? sc->cids2.p : sc->cids.p;
     if (nc == 1) perm = sc->cids.p;
     sc->perm = perm;
@@ -369,6 +386,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_TRY(launch_invert(perm, nc, sc->spos.p, s));
     sc->precision_used = sc->p.precision;
     NBGS_TRY(scene_gather(sc));
+    if (sc->sub_active) NBGS_TRY(subdomain_prepare(sc));
     sc->state = 1;
     sc->stats.n_contacts = nc;
     sc->stats.n_colours = sc->n_colours;
@@ -488,6 +506,8 @@ nbgs_status enqueue_dev_sweeps(nbgs_scene_t sc, int32_t k, double target, const 
 
 namespace nbgs {
 
+nbgs_status scene_sync_small(nbgs_scene_t sc, int first, int count) { return sync_small(sc, first, count); }
+
 nbgs_status scene_gather(nbgs_scene_t sc) {
     if (sc->precision_used == NBGS_FP32_SWEEP) return gather_for_sweeps<float>(sc);
     return gather_for_sweeps<double>(sc);
@@ -597,6 +617,90 @@ template nbgs_status scene_sweep_loop<float>(nbgs_scene_t, int32_t, double, cons
 
 namespace {
 
+// Stop flag, sweep count and last residual after a solve; NUMERIC / NOT_CONVERGED as nbgs_solve reports them.
+template <class T>
+nbgs_status finish_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats, bool sub) {
+    hipStream_t s = sc->s;
+    SweepBuf<T> &sw = sweep_buf<T>(sc);
+    NBGS_TRY(launch_save_impulses<T>(sw.view(), sc->nc, sc->cb[sc->cur].view(), s));
+    record(sc, kIntegrate);
+    sc->state = 2;
+    sc->solved = true;
+    NBGS_TRY(sync_small(sc, 8, 3));
+    const int32_t sweeps = sc->pinned[8 + 1];
+    double R = 0.0;
+    if (sweeps > 0) {
+        NBGS_HIP(hipMemcpyAsync(sc->pinned + 32, sc->res_hist.p + (sweeps - 1), sizeof(double), hipMemcpyDeviceToHost,
+                                s));
+        NBGS_HIP(hipStreamSynchronize(s));
+        std::memcpy(&R, sc->pinned + 32, sizeof(double));
+    }
+    sc->stats.sweeps = sweeps;
+    sc->stats.residual = R;
+    if (stats) *stats = sc->stats;
+    if (sub && sc->profiling) {
+        for (int32_t k = 0; k < sweeps && k < max_sweeps; ++k) {
+            float ms = 0.0f;
+            NBGS_HIP(hipEventElapsedTime(&ms, sc->pev[2 * k], sc->pev[2 * k + 1]));
+            sc->prof.sweep_kernel_ms += ms;
+        }
+        // compulsory bytes of a sweep: every contact record, every slot read (v', w', 1/m, 1/I) and its
+        // correction written and read back, every corrected body's v', w' read and written
+        const double tb = (double)sizeof(T);
+        const double per_sweep = (2 * 4 + 12 * tb) * (double)sc->nc + 4 * 2 * (double)sc->nc +
+                                 (8 * tb + 6 * tb + 6 * tb) * (double)sc->n_slots + 12 * tb * (double)sc->b.n;
+        sc->prof.sweep_launches += sweeps;
+        sc->prof.contact_updates += (int64_t)sweeps * sc->nc;
+        sc->prof.sweep_bytes += per_sweep * sweeps;
+    }
+    if (sc->pinned[8 + 2]) {
+        set_error("non-finite residual after sweep %d", sweeps);
+        return NBGS_ERR_NUMERIC;
+    }
+    if (target > 0.0 && !(R <= target)) {
+        set_error("residual %.3e above target %.3e after %d sweeps", R, target, sweeps);
+        return NBGS_ERR_NOT_CONVERGED;
+    }
+    return NBGS_OK;
+}
+
+// Subdomain NBGS: the initial impulses enter as a first correction pass, then
+// sweeps until the target or the sweep count, one pass (all subdomains) plus
+// the correction reduction per sweep.
+template <class T>
+nbgs_status sub_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats) {
+    hipStream_t s = sc->s;
+    DevBuf<T> &vel = vel_buf<T>(sc);
+    DevBuf<T> &corr = corr_buf<T>(sc);
+    NBGS_TRY(corr.reserve(6 * (size_t)(sc->n_slots > 0 ? sc->n_slots : 1)));
+    NBGS_TRY(sc->partials.reserve(2 * (size_t)sc->n_sub));
+    NBGS_HIP(hipMemsetAsync(sc->ctrl(), 0, 4 * sizeof(int32_t), s));
+    sc->hist_partial = false;
+    sc->graph_pairs = 0;
+    NBGS_TRY(subdomain_pass<T>(sc, 0, vel.p, corr.p));
+    record(sc, kSweeps);
+    const bool prof = sc->profiling;
+    if (prof) NBGS_TRY(ensure_profile_events(sc, (size_t)max_sweeps));
+    int32_t launched = 0, chunk = target > 0.0 ? 4 : max_sweeps;
+    bool done = false;
+    while (launched < max_sweeps && !done) {
+        const int32_t k = std::min(chunk, max_sweeps - launched);
+        for (int32_t it = 0; it < k; ++it) {
+            if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it)], s));
+            NBGS_TRY(subdomain_pass<T>(sc, 1, vel.p, corr.p));
+            if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it) + 1], s));
+            NBGS_TRY(launch_residual(sc->partials.p, sc->n_sub, target, sc->ctrl(), sc->res_hist.p, s));
+        }
+        launched += k;
+        if (target > 0.0 && launched < max_sweeps) {
+            NBGS_TRY(sync_small(sc, 8, 3));
+            done = sc->pinned[8] != 0;
+            chunk = std::min(chunk * 2, 64);
+        }
+    }
+    return finish_solve<T>(sc, max_sweeps, target, stats, true);
+}
+
 template <class T>
 nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats) {
     hipStream_t s = sc->s;
@@ -609,6 +713,7 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
     sc->winfo = nbgs_warm_info{-1, 0.0, 0.0};
     if (sc->p.warm_start == NBGS_WS_LEARNED && sc->have_learned) NBGS_TRY(judge_warm_start<T>(sc));
     NBGS_TRY(launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel.p, s));
+    if (sc->sub_active) return sub_solve<T>(sc, max_sweeps, target, stats);
     if (sc->p.warm_start != NBGS_WS_ZERO)
         for (int c = 0; c < sc->n_colours; ++c)
             NBGS_TRY(launch_warm_scatter<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, s));
@@ -993,6 +1098,10 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t sc, const nbgs_params *params) {
         set_error("the learned warm start is not available for batched scenes");
         return NBGS_ERR_UNSUPPORTED;
     }
+    if (sc->sub_edge > 0.0 && params->warm_start == NBGS_WS_LEARNED) {
+        set_error("the subdomain solver does not combine with the learned warm start");
+        return NBGS_ERR_UNSUPPORTED;
+    }
     sc->p = *params;
     update_scales(sc);
     return NBGS_OK;
@@ -1106,6 +1215,25 @@ nbgs_status nbgs_get_residuals(nbgs_scene_t sc, int32_t cap, double *hist, int32
         if (sc->hist_partial)  // only the last sweep was summed
             for (int32_t i = 0; i < k && i < n - 1; ++i) hist[i] = std::nan("");
     }
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_set_subdomains(nbgs_scene_t sc, double edge) {
+    NBGS_GUARD(sc);
+    if (!(edge >= 0.0) || !std::isfinite(edge)) {
+        set_error("the subdomain edge must be finite and >= 0");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (edge > 0.0 && sc->n_scenes > 1) {
+        set_error("the subdomain solver is not available for batched scenes");
+        return NBGS_ERR_UNSUPPORTED;
+    }
+    if (edge > 0.0 && sc->p.warm_start == NBGS_WS_LEARNED) {
+        set_error("the subdomain solver does not combine with the learned warm start");
+        return NBGS_ERR_UNSUPPORTED;
+    }
+    sc->sub_edge = edge;
+    sc->state = 0;  // the next step starts with a detection
     return NBGS_OK;
 }
 

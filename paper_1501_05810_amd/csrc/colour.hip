@@ -98,12 +98,15 @@ __global__ void __launch_bounds__(kBlock) k_prio(const uint64_t *key, int64_t nc
     prio[j] = splitmix64(k ^ sd);
 }
 
+// sdom (may be null): subdomain of every contact; contacts of different
+// subdomains do not conflict.
 __global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, const uint64_t *prio, int64_t nc, int32_t nb,
                                                      const double *inv_mass, const int32_t *off1,
                                                      const int32_t *cnt1, const int32_t *off2, const int32_t *inc2,
-                                                     int32_t *remaining, int32_t *overflow) {
+                                                     const int32_t *sdom, int32_t *remaining, int32_t *overflow) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc || c.colour[j] >= 0) return;
+    const int32_t sj = sdom ? sdom[j] : 0;
     Probe pr;
     pr.key = c.key[j];
     pr.prio = prio[j];
@@ -116,11 +119,11 @@ __global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, const uint6
         if (b >= nb || !(inv_mass[b] > 0.0)) continue;
         const int a0 = off1[b], a1 = a0 + cnt1[b];
         for (int l = a0; l < a1 && !pr.blocked; ++l)
-            if (l != j) probe(pr, c, prio, l);
+            if (l != j && (!sdom || sdom[l] == sj)) probe(pr, c, prio, l);
         const int q1 = off2[b + 1];
         for (int q = off2[b]; q < q1 && !pr.blocked; ++q) {
             const int l = inc2[q];
-            if (l != j) probe(pr, c, prio, l);
+            if (l != j && (!sdom || sdom[l] == sj)) probe(pr, c, prio, l);
         }
     }
     if (pr.blocked) return;
@@ -144,9 +147,11 @@ __global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, const uint6
 __global__ void __launch_bounds__(kBlock) k_colour_fix(ContactsView c, const uint64_t *prio, int64_t nc, int32_t nb,
                                                        const double *inv_mass, const int32_t *off1,
                                                        const int32_t *cnt1, const int32_t *off2,
-                                                       const int32_t *inc2, int32_t *changed, int32_t *overflow) {
+                                                       const int32_t *inc2, const int32_t *sdom, int32_t *changed,
+                                                       int32_t *overflow) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc) return;
+    const int32_t sj = sdom ? sdom[j] : 0;
     const uint64_t kj = c.key[j], pj = prio[j];
     uint64_t used[kMaxColours / 64] = {0, 0, 0, 0};
     const int ends[2] = {c.j1[j], c.j2[j]};
@@ -155,14 +160,14 @@ __global__ void __launch_bounds__(kBlock) k_colour_fix(ContactsView c, const uin
         if (b >= nb || !(inv_mass[b] > 0.0)) continue;
         const int a0 = off1[b], a1 = a0 + cnt1[b];
         for (int l = a0; l < a1; ++l) {
-            if (l == j || !precedes(prio[l], c.key[l], pj, kj)) continue;
+            if (l == j || (sdom && sdom[l] != sj) || !precedes(prio[l], c.key[l], pj, kj)) continue;
             const int cl = __hip_atomic_load(&c.colour[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             used[(cl >> 6) & 3] |= 1ull << (cl & 63);
         }
         const int q1 = off2[b + 1];
         for (int q = off2[b]; q < q1; ++q) {
             const int l = inc2[q];
-            if (l == j || !precedes(prio[l], c.key[l], pj, kj)) continue;
+            if (l == j || (sdom && sdom[l] != sj) || !precedes(prio[l], c.key[l], pj, kj)) continue;
             const int cl = __hip_atomic_load(&c.colour[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             used[(cl >> 6) & 3] |= 1ull << (cl & 63);
         }
@@ -200,11 +205,12 @@ __global__ void __launch_bounds__(kBlock) k_colour_hist(ContactsView c, int64_t 
         if (cnt[d]) atomicAdd(&hist[d], cnt[d]);
 }
 
-__global__ void __launch_bounds__(kBlock) k_colour_keys(const int32_t *colour, int64_t nc, uint32_t *keys,
-                                                        uint32_t *ids) {
+// Sort key of the sweep order: colour, or (subdomain, colour) with sdom.
+__global__ void __launch_bounds__(kBlock) k_colour_keys(const int32_t *colour, const int32_t *sdom, int64_t nc,
+                                                        uint32_t *keys, uint32_t *ids) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc) return;
-    keys[j] = (uint32_t)colour[j];
+    keys[j] = sdom ? ((uint32_t)sdom[j] << 8) | (uint32_t)colour[j] : (uint32_t)colour[j];
     ids[j] = (uint32_t)j;
 }
 
@@ -218,12 +224,15 @@ __global__ void __launch_bounds__(kBlock) k_invert(const uint32_t *perm, int64_t
 // contact: the reads stream, and the writes of a colour land in ascending
 // positions, which the L2 merges into whole lines.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_gather_sweep(ContactsView c, const int32_t *pos, int64_t nc, double dt,
-                                                         double erp, SceneTable st, SweepView<T> sv) {
+__global__ void __launch_bounds__(kBlock) k_gather_sweep(ContactsView c, const int32_t *pos, const int32_t *sdom,
+                                                         int64_t nc, double dt, double erp, SceneTable st,
+                                                         SweepView<T> sv) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc) return;
     const int64_t p = pos[j];
     sv.perm[p] = (int32_t)j;
+    if (sv.col) sv.col[p] = c.colour[j];
+    if (sv.sdom) sv.sdom[p] = sdom[j];
     if (sv.mu) sv.mu[p] = (T)st.mu[st.body_scene[c.j1[j]]];
     sv.j1[p] = c.j1[j];
     sv.j2[p] = c.j2[j];
@@ -269,9 +278,10 @@ nbgs_status launch_prio(const ContactsView &c, int64_t nc, uint64_t seed, const 
 
 nbgs_status launch_jp_round(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
                             const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
-                            const int32_t *inc2, int32_t *remaining, int32_t *overflow, hipStream_t s) {
+                            const int32_t *inc2, const int32_t *sdom, int32_t *remaining, int32_t *overflow,
+                            hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_jp_round<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, remaining,
+    k_jp_round<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, sdom, remaining,
                                                overflow);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
@@ -279,9 +289,10 @@ nbgs_status launch_jp_round(const ContactsView &c, const uint64_t *prio, int64_t
 
 nbgs_status launch_colour_fix(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
                               const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
-                              const int32_t *inc2, int32_t *changed, int32_t *overflow, hipStream_t s) {
+                              const int32_t *inc2, const int32_t *sdom, int32_t *changed, int32_t *overflow,
+                              hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_colour_fix<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, changed,
+    k_colour_fix<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, sdom, changed,
                                                  overflow);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
@@ -296,9 +307,10 @@ nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t nb, co
     return NBGS_OK;
 }
 
-nbgs_status launch_colour_keys(const ContactsView &c, int64_t nc, uint32_t *keys, uint32_t *ids, hipStream_t s) {
+nbgs_status launch_colour_keys(const ContactsView &c, const int32_t *sdom, int64_t nc, uint32_t *keys, uint32_t *ids,
+                               hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_colour_keys<<<grid_for(nc), kBlock, 0, s>>>(c.colour, nc, keys, ids);
+    k_colour_keys<<<grid_for(nc), kBlock, 0, s>>>(c.colour, sdom, nc, keys, ids);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -311,17 +323,17 @@ nbgs_status launch_invert(const uint32_t *perm, int64_t nc, int32_t *pos, hipStr
 }
 
 template <class T>
-nbgs_status launch_gather_sweep(const ContactsView &c, const int32_t *pos, int64_t nc, double dt, double erp,
-                                const SceneTable &st, SweepView<T> sv, hipStream_t s) {
+nbgs_status launch_gather_sweep(const ContactsView &c, const int32_t *pos, const int32_t *sdom, int64_t nc, double dt,
+                                double erp, const SceneTable &st, SweepView<T> sv, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, pos, nc, dt, erp, st, sv);
+    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, pos, sdom, nc, dt, erp, st, sv);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
-template nbgs_status launch_gather_sweep<double>(const ContactsView &, const int32_t *, int64_t, double, double,
-                                                 const SceneTable &, SweepView<double>, hipStream_t);
-template nbgs_status launch_gather_sweep<float>(const ContactsView &, const int32_t *, int64_t, double, double,
-                                                const SceneTable &, SweepView<float>, hipStream_t);
+template nbgs_status launch_gather_sweep<double>(const ContactsView &, const int32_t *, const int32_t *, int64_t,
+                                                 double, double, const SceneTable &, SweepView<double>, hipStream_t);
+template nbgs_status launch_gather_sweep<float>(const ContactsView &, const int32_t *, const int32_t *, int64_t,
+                                                double, double, const SceneTable &, SweepView<float>, hipStream_t);
 
 }  // namespace nbgs

@@ -123,6 +123,17 @@ struct SweepView {
     int32_t *perm;  // sweep position -> canonical index
     T *nx, *ny, *nz, *bias, *a1, *a2, *px, *py, *pz;
     T *mu;  // friction coefficient per contact (batched scenes), null: one coefficient for all
+    int32_t *col, *sdom;  // colour and subdomain per sweep position (subdomain solver), else null
+};
+
+// The sweep record as the subdomain solver reads it: ls holds, for end k of
+// the contact at sweep position p, the body's slot local to the contact's
+// subdomain at ls[2 p + k] (-1: wall or static body).
+template <class T>
+struct SubView {
+    const int32_t *j1, *j2, *ls, *col;
+    const T *nx, *ny, *nz, *bias, *a1, *a2;
+    T *px, *py, *pz;
 };
 
 // ------------------------------------------------------- kernel launchers
@@ -169,17 +180,20 @@ nbgs_status launch_prio(const ContactsView &c, int64_t nc, uint64_t seed, const 
                         uint64_t *prio, hipStream_t s);
 nbgs_status launch_jp_round(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
                             const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
-                            const int32_t *inc2, int32_t *remaining, int32_t *overflow, hipStream_t s);
+                            const int32_t *inc2, const int32_t *sdom, int32_t *remaining, int32_t *overflow,
+                            hipStream_t s);
 nbgs_status launch_colour_fix(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
                               const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
-                              const int32_t *inc2, int32_t *changed, int32_t *overflow, hipStream_t s);
+                              const int32_t *inc2, const int32_t *sdom, int32_t *changed, int32_t *overflow,
+                              hipStream_t s);
 nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *hist,
                                hipStream_t s);
-nbgs_status launch_colour_keys(const ContactsView &c, int64_t nc, uint32_t *keys, uint32_t *ids, hipStream_t s);
+nbgs_status launch_colour_keys(const ContactsView &c, const int32_t *sdom, int64_t nc, uint32_t *keys, uint32_t *ids,
+                               hipStream_t s);
 nbgs_status launch_invert(const uint32_t *perm, int64_t nc, int32_t *pos, hipStream_t s);
 template <class T>
-nbgs_status launch_gather_sweep(const ContactsView &c, const int32_t *pos, int64_t nc, double dt, double erp,
-                                const SceneTable &st, SweepView<T> sv, hipStream_t s);
+nbgs_status launch_gather_sweep(const ContactsView &c, const int32_t *pos, const int32_t *sdom, int64_t nc, double dt,
+                                double erp, const SceneTable &st, SweepView<T> sv, hipStream_t s);
 
 // sweep.hip
 struct SweepParams {

@@ -45,15 +45,21 @@ struct ContactBuf {
 
 template <class T>
 struct SweepBuf {
-    DevBuf<int32_t> j1, j2, perm;
+    DevBuf<int32_t> j1, j2, perm, col, sdom, ls;
     DevBuf<T> nx, ny, nz, bias, a1, a2, px, py, pz, mu;
     bool per_contact_mu = false;
+    bool sub = false;  // subdomain solver: colour and subdomain per position, local slots per contact end
     nbgs_status reserve(size_t n) {
         NBGS_TRY(j1.reserve(n));
         NBGS_TRY(j2.reserve(n));
         NBGS_TRY(perm.reserve(n));
         for (DevBuf<T> *b : {&nx, &ny, &nz, &bias, &a1, &a2, &px, &py, &pz}) NBGS_TRY(b->reserve(n));
         if (per_contact_mu) NBGS_TRY(mu.reserve(n));
+        if (sub) {
+            NBGS_TRY(col.reserve(n));
+            NBGS_TRY(sdom.reserve(n));
+            NBGS_TRY(ls.reserve(2 * n));
+        }
         return NBGS_OK;
     }
     SweepView<T> view() {
@@ -71,6 +77,8 @@ struct SweepBuf {
         v.py = py.p;
         v.pz = pz.p;
         v.mu = per_contact_mu ? mu.p : nullptr;
+        v.col = sub ? col.p : nullptr;
+        v.sdom = sub ? sdom.p : nullptr;
         return v;
     }
 };
@@ -191,6 +199,19 @@ struct nbgs_scene_s {
     DevBuf<int64_t> col_d;
     int64_t *col_pinned = nullptr;
     size_t col_pinned_cap = 0;
+    // subdomain solver (Alg. 1 with block subdomains), off when sub_edge == 0
+    double sub_edge = 0.0;
+    bool sub_active = false;  // the current step uses it (edge > 0 and contacts)
+    int32_t n_sub = 0;
+    int64_t n_slots = 0;
+    int32_t max_slots = 0;
+    DevBuf<int32_t> sdom, tile_cnt, tile_off32, tile_scnt, tile_slot_off, eflags, eex, slot_body, slot_sdom, body_cnt,
+        body_slot_off;
+    DevBuf<int64_t> tile_off;
+    DevBuf<uint32_t> ekeys, evals, ekeys2, evals2, bkeys, bvals, bkeys2, bvals2;
+    const uint32_t *body_slots = nullptr;
+    DevBuf<double> corr64;
+    DevBuf<float> corr32;
     // sweep-tuning cache file (empty: none)
     std::string tune_cache;
     bool tuned[2] = {false, false};
@@ -229,6 +250,14 @@ nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int6
 // trace (the initial impulses are restored afterwards).
 nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen, double *best_ms);
 nbgs_status scene_gather(nbgs_scene_t sc);
+nbgs_status scene_sync_small(nbgs_scene_t sc, int first, int count);
+// Subdomain solver: subdomain of every contact (before colouring), then the
+// tile and slot tables (after the sweep record is gathered), and one pass
+// (mode 0: initial impulses, 1: relaxation) with the correction reduction.
+nbgs_status subdomain_assign(nbgs_scene_t sc);
+nbgs_status subdomain_prepare(nbgs_scene_t sc);
+template <class T>
+nbgs_status subdomain_pass(nbgs_scene_t sc, int mode, T *vel, T *corr);
 template <class T>
 nbgs_status scene_sweep_loop(nbgs_scene_t sc, int32_t max_sweeps, double target, const SweepTune &tune);
 
