@@ -157,8 +157,11 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t scene, const nbgs_params *params)
  * inv_mass > 0) and ordered by (colour, key) for the sweeps, and the initial
  * impulses are set (params.warm_start).  stats: [host] or NULL (then only
  * n_contacts of the scene is known after the next synchronising call).
- * Errors: CAPACITY (more than 255 colours, counts >= 2^31), OUT_OF_MEMORY,
- * DEVICE. */
+ * Errors: CAPACITY (more than 255 colours; more than 2^31 - 256 contacts,
+ * counted in 64 bits before any list is sized; a body meeting more than 2^18
+ * hull candidates in its 27 cells, which happens when one hull, e.g. of a
+ * diverged state, makes the cell grid too coarse; in subdomain mode more
+ * than 2^30 contacts), OUT_OF_MEMORY, DEVICE. */
 nbgs_status nbgs_detect(nbgs_scene_t scene, nbgs_stats *stats);
 
 /* NBGS sweeps over the detected contacts (Alg. 1, one subdomain, colour

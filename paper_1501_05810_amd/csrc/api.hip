@@ -219,7 +219,9 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     }
     ContactBuf &prev = sc->cb[1 - sc->cur];
     // hull radii and the largest hull
-    NBGS_HIP(hipMemsetAsync(sc->maxbits.p, 0, sizeof(unsigned long long), s));
+    // maxbits: [0] largest hull (bits of a non-negative double), [1] contact
+    // total in 64 bits, [2] candidate overflow of the pair count
+    NBGS_HIP(hipMemsetAsync(sc->maxbits.p, 0, 3 * sizeof(unsigned long long), s));
     NBGS_TRY(launch_hull(sc->b, sc->p.dt, sc->p.tau, sc->h.p, sc->maxbits.p, s));
     unsigned long long bits = 0;
     NBGS_HIP(hipMemcpyAsync(sc->pinned, sc->maxbits.p, sizeof(bits), hipMemcpyDeviceToHost, s));
@@ -255,12 +257,35 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
                           sc->cell_stamp.p, sc->stamp, sc->sxr.p, sc->cellpos.p, s));
     // count, scan, emit
     NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
-                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p, s));
+                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p,
+                               sc->maxbits.p + 1, s));
     NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, N, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
+    NBGS_HIP(hipMemcpyAsync(sc->pinned + 4, sc->maxbits.p + 1, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            s));
     NBGS_TRY(sync_small(sc, 0, 1));
+    unsigned long long total64 = 0, over = 0;
+    std::memcpy(&total64, sc->pinned + 4, sizeof(total64));
+    std::memcpy(&over, sc->pinned + 6, sizeof(over));
+    if (over) {
+        set_error("a body meets more than 2^18 hull candidates in its 27 cells: the cell grid, sized by the largest "
+                  "hull (radius %g), is too coarse for this state (a diverged solve or a very fast body)",
+                  max_reach);
+        return NBGS_ERR_CAPACITY;
+    }
+    if (total64 > 0x7fffff00ull) {
+        set_error("%llu contacts exceed the 2^31 entries of the contact list (largest hull radius %g)",
+                  (unsigned long long)total64, max_reach);
+        return NBGS_ERR_CAPACITY;
+    }
     const int64_t nc = sc->pinned[0];
-    if (nc < 0 || nc > (int64_t)0x7fffff00) {
-        set_error("contact count out of range");
+    if (nc != (int64_t)total64) {
+        set_error("contact count %lld disagrees with its 64-bit total %llu", (long long)nc,
+                  (unsigned long long)total64);
+        return NBGS_ERR_DEVICE;
+    }
+    if (sc->sub_edge > 0.0 && 2 * nc > (int64_t)0x7fffff00) {
+        set_error("%lld contacts: the subdomain solver indexes both ends of a contact in 32 bits (at most 2^30 "
+                  "contacts)", (long long)nc);
         return NBGS_ERR_CAPACITY;
     }
     sc->nc = nc;
@@ -988,7 +1013,7 @@ nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int6
     chk(sc->radix_hist.reserve(radix_hist_entries((int64_t)N + 1), 1.0));
     chk(sc->scan_tmp.reserve(exclusive_scan_tmp_bytes((int64_t)radix_hist_entries((int64_t)N + 1) + N + 1), 1.0));
     chk(sc->small.reserve(kSmallInts, 1.0));
-    chk(sc->maxbits.reserve(1, 1.0));
+    chk(sc->maxbits.reserve(3, 1.0));
     if (st == NBGS_OK && hipHostMalloc((void **)&sc->pinned, sizeof(int32_t) * kSmallInts * 2) != hipSuccess) {
         set_error("pinned host allocation failed");
         st = NBGS_ERR_OUT_OF_MEMORY;

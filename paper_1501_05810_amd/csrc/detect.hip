@@ -161,6 +161,14 @@ __device__ inline bool plane_hit(const PlaneSet &pl, int w, double x, double y, 
     return gap <= h + tau;
 }
 
+// Hull candidates one body may meet in its 27 cells.  The cell edge follows
+// the largest hull, so a single fast body coarsens the whole grid; past this
+// bound the count gives up (the host reports it) instead of scanning for
+// minutes.  A dense monodisperse packing meets a few hundred.
+constexpr int kMaxCandidates = 1 << 18;
+
+// Partners of body i with k > i, hull overlap tested on the sorted entries;
+// the count variant returns -1 once the candidates pass kMaxCandidates.
 template <bool kEmit>
 __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const uint32_t *sids, const double4 *sxr,
                                      const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
@@ -168,14 +176,18 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
     const double4 me = sxr[p];
     int c[3];
     const NeighbourRange nr = neighbour_range(skeys[p], g, c);
-    int m = 0;
+    int m = 0, seen = 0;
     for (int dz = nr.lo[2]; dz <= nr.hi[2]; ++dz)
         for (int dy = nr.lo[1]; dy <= nr.hi[1]; ++dy)
             for (int dx = nr.lo[0]; dx <= nr.hi[0]; ++dx) {
                 const int cell = neighbour_cell(g, c, dx, dy, dz);
                 if (cell < 0 || cell_stamp[cell] != stamp) continue;
-                const int q1 = cell_end[cell];
-                for (int q = cell_start[cell]; q < q1; ++q) {
+                const int q0 = cell_start[cell], q1 = cell_end[cell];
+                if (!kEmit) {
+                    seen += q1 - q0;
+                    if (seen > kMaxCandidates) return -1;
+                }
+                for (int q = q0; q < q1; ++q) {
                     const int k = (int)sids[q];
                     if (k <= i) continue;
                     const double4 o = sxr[q];
@@ -192,22 +204,90 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, Pl
                                                        const uint32_t *skeys, const uint32_t *sids,
                                                        const double4 *sxr, const double *h,
                                                        const int32_t *cell_start, const int32_t *cell_end,
-                                                       const uint32_t *cell_stamp, uint32_t stamp, int32_t *cnt) {
+                                                       const uint32_t *cell_stamp, uint32_t stamp, int32_t *cnt,
+                                                       unsigned long long *total) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= b.n) return;
-    const int i = (int)sids[p];
-    const int sc = st.body_scene ? st.body_scene[i] : 0;
-    const Grid &g = st.body_scene ? st.grids[sc] : g0;
-    const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
-    int m = visit_partners<false>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, nullptr);
-    if (b.inv_mass[i] != 0.0) {
-        const double4 me = sxr[p];
-        const double r = b.radius[i], hi = h[i];
-        double gap;
-        for (int w = 0; w < pl.n; ++w)
-            if (plane_hit(pl, w, me.x, me.y, me.z, r, hi, tau, &gap)) ++m;
+    unsigned long long m64 = 0;
+    int over = 0;
+    if (p < b.n) {
+        const int i = (int)sids[p];
+        const int sc = st.body_scene ? st.body_scene[i] : 0;
+        const Grid &g = st.body_scene ? st.grids[sc] : g0;
+        const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
+        int m = visit_partners<false>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, nullptr);
+        if (m < 0) {
+            over = 1;
+            m = 0;
+        }
+        if (b.inv_mass[i] != 0.0) {
+            const double4 me = sxr[p];
+            const double r = b.radius[i], hi = h[i];
+            double gap;
+            for (int w = 0; w < pl.n; ++w)
+                if (plane_hit(pl, w, me.x, me.y, me.z, r, hi, tau, &gap)) ++m;
+        }
+        cnt[i] = m;
+        m64 = (unsigned long long)m;
     }
-    cnt[i] = m;
+    // The list length in 64 bits (the 32-bit scan of the counts would wrap
+    // silently past 2^31) and the candidate overflow: one atomic per block.
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m64 += __shfl_xor(m64, o, 64);
+    over = __any(over);
+    __shared__ unsigned long long wsum[kBlock / 64];
+    __shared__ int wover[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wsum[threadIdx.x >> 6] = m64;
+        wover[threadIdx.x >> 6] = over;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        int ov = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            t += wsum[w];
+            ov |= wover[w];
+        }
+        if (t) atomicAdd(&total[0], t);
+        if (ov) atomicOr(&total[1], 1ull);
+    }
+}
+
+// Ascending partner indices: insertion sort for the usual short list, heap
+// sort (bounded work) for the long one of a body with a wide hull.  Partners
+// are distinct, so both give the same order.
+__device__ inline void sort_partners(int32_t *ks, int m) {
+    if (m <= 32) {
+        for (int a = 1; a < m; ++a) {
+            const int v = ks[a];
+            int t = a - 1;
+            while (t >= 0 && ks[t] > v) {
+                ks[t + 1] = ks[t];
+                --t;
+            }
+            ks[t + 1] = v;
+        }
+        return;
+    }
+    auto sift = [ks](int root, int end) {
+        const int v = ks[root];
+        for (;;) {
+            int child = 2 * root + 1;
+            if (child >= end) break;
+            if (child + 1 < end && ks[child + 1] > ks[child]) ++child;
+            if (v >= ks[child]) break;
+            ks[root] = ks[child];
+            root = child;
+        }
+        ks[root] = v;
+    };
+    for (int r = m / 2 - 1; r >= 0; --r) sift(r, m);
+    for (int e = m - 1; e > 0; --e) {
+        const int top = ks[0];
+        ks[0] = ks[e];
+        ks[e] = top;
+        sift(0, e);
+    }
 }
 
 // One thread per body in index order, so that consecutive threads write
@@ -229,16 +309,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, Pla
     const int base = off[i];
     int32_t *ks = c.j2 + base;
     const int m = visit_partners<true>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, ks);
-    // partners in ascending index (insertion sort of a short list)
-    for (int a = 1; a < m; ++a) {
-        const int v = ks[a];
-        int t = a - 1;
-        while (t >= 0 && ks[t] > v) {
-            ks[t + 1] = ks[t];
-            --t;
-        }
-        ks[t + 1] = v;
-    }
+    sort_partners(ks, m);
     const double xi_ = b.x[i], yi = b.y[i], zi = b.z[i], ri = b.radius[i];
     for (int t = 0; t < m; ++t) {
         const int k = ks[t];
@@ -372,9 +443,10 @@ nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *ske
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                               const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
-                              uint32_t stamp, int32_t *cnt, hipStream_t s) {
+                              uint32_t stamp, int32_t *cnt, unsigned long long *total, hipStream_t s) {
+    if (b.n <= 0) return NBGS_OK;
     k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
-                                                  cell_stamp, stamp, cnt);
+                                                  cell_stamp, stamp, cnt, total);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

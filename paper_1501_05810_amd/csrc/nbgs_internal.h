@@ -158,7 +158,7 @@ nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *ske
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                               const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
-                              uint32_t stamp, int32_t *cnt, hipStream_t s);
+                              uint32_t stamp, int32_t *cnt, unsigned long long *total, hipStream_t s);
 nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
