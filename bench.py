@@ -43,7 +43,8 @@ def log(msg):
 CONTACT_BYTES = {"fp64": 104.0, "fp32": 56.0}
 BODY_BYTES = {"fp64": 112.0, "fp32": 56.0}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_dense1m_hbm_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1501_05810_amd", "csrc", f) for f in ("sweep.hip", "nbgs_internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1501_05810_amd", "csrc", f)
+                  for f in ("sweep.hip", "subdomain.hip", "nbgs_internal.h")]
 
 
 def kernel_source_hash() -> str:
@@ -56,7 +57,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str):
+def measured_traffic(key: str):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
     scaled by what they read for a plain copy), or None once the kernel sources differ from those profiled."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -70,7 +71,7 @@ def measured_traffic(precision: str):
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    v = vals.get(f"traffic_bytes_per_launch_{precision}")
+    v = vals.get(f"traffic_bytes_per_launch_{key}")
     return float(v.replace(",", "")) if v else None
 
 
@@ -130,6 +131,42 @@ def other_workloads(nb, sg, torch, dev):
                              "phase_ms_last_step": [round(float(x), 3) for x in g.phase_times()], "dtype": "f64"}
     g.close()
     log(f"dilute gas: {out['dilute_gas_16m']}")
+    return out
+
+
+def subdomain_solver(nb, torch, dev, sc, sweeps, edge=5.0, relax=0.75):
+    """The subdomain NBGS (Alg. 1 with block subdomains of edge 5, one workgroup per subdomain) beside the
+    colour-ordered NBGS on the same packing at the same relaxation: whole-step time, sweep-only contact updates/s
+    and the residual after one step of `sweeps` sweeps (both continued from a load built to 1e-6 or 2000 sweeps)."""
+    out = {"edge": edge, "relax": relax, "sweeps_per_step": sweeps}
+    for prec in ("fp64", "fp32"):
+        for mode in ("colour", "subdomain"):
+            s2 = sc.copy()
+            s2.relax = relax
+            g = nb.GpuScene(s2, device=dev, precision=prec, warm_start="previous")
+            if mode == "subdomain":
+                g.set_subdomains(edge)
+            g.step(2000, 1e-6)
+            g.step(sweeps)
+            g.set_residual_history(False)
+            wall, cs = _timed_steps(nb, torch, g, 5, sweeps)
+            phases = g.phase_times()
+            g.set_profiling(True)
+            nb.nbgs_detect(g.handle)
+            nb.nbgs_solve(g.handle, sweeps, 0.0)
+            nb.nbgs_integrate(g.handle)
+            torch.cuda.synchronize()
+            p = g.profile()
+            g.set_profiling(False)
+            g.set_residual_history(True)
+            st = g.step(sweeps)
+            out[f"{mode}_{prec}"] = {
+                "ms_per_step": wall / 5 * 1e3, "contact_updates_per_s": cs * sweeps / wall,
+                "sweep_only_updates_per_s": p["contact_updates"] / (p["sweep_kernel_ms"] * 1e-3),
+                "sweep_ms_per_step": p["sweep_kernel_ms"], "residual_after_step": st["residual"],
+                "phase_ms_last_step": [round(float(x), 3) for x in phases]}
+            log(f"{mode} {prec}: {out[f'{mode}_{prec}']}")
+            g.close()
     return out
 
 
@@ -284,6 +321,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (to scale HBM traffic counters)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
+    ap.add_argument("--subdomain-edge", type=float, default=0.0,
+                    help="time the subdomain NBGS (Alg. 1, blocks of this edge) instead of the colour-ordered one")
+    ap.add_argument("--relax", type=float, default=None, help="relaxation (default: the scene's)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (walled box, ensemble batch, dilute gas)")
     a = ap.parse_args()
@@ -296,7 +336,16 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        # the copy's own rate (read + write bytes over time): what a plain stream reaches on this device
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = 2 * src.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "copy_rate_gbs": gbs}))
         return
 
     if a.gpus != 1:
@@ -313,8 +362,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     sc = sg.dense_packing(tiles=a.tiles)
+    if a.relax is not None:
+        sc.relax = a.relax
     log(f"scene: {sc.n} spheres, box {sc.hi}")
     g = nb.GpuScene(sc.copy(), device=dev, precision=a.precision, warm_start="previous")
+    if a.subdomain_edge > 0:
+        g.set_subdomains(a.subdomain_edge)
 
     # ---------------------------------------------------- fixed sweeps, FP64
     for i in range(a.warmup):
@@ -356,7 +409,9 @@ def main():
             per_launch_bytes = prof["sweep_bytes"] / prof["sweep_launches"]
             per_launch_ms = prof["sweep_kernel_ms"] / prof["sweep_launches"]
             achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-            traffic = measured_traffic(a.precision)
+            traffic = measured_traffic(("subdomain_" if a.subdomain_edge > 0 else "") + a.precision)
+            tn = "double" if a.precision == "fp64" else "float"
+            kernel_name = (f"k_sub_pass<{tn}> + k_sub_reduce<{tn}>" if a.subdomain_edge > 0 else f"k_sweep<{tn}>")
             # secondary model: every body record read and written once per sweep, as if it stayed cached
             # between the colours of a sweep
             sweep_model_bytes = (CONTACT_BYTES[a.precision] * float(np.mean(pcontacts))
@@ -364,12 +419,30 @@ def main():
             sweep_ms_per_step = prof["sweep_kernel_ms"] / a.profile_steps
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "k_sweep<%s>" % ("double" if a.precision == "fp64" else "float"),
+                    "kernel": kernel_name,
                     "bytes_per_launch": round(per_launch_bytes),
                     "avg_launch_us": round(per_launch_ms * 1e3, 2), "launches": prof["sweep_launches"],
                     "sweep_only_updates_per_s": prof["contact_updates"] / (prof["sweep_kernel_ms"] * 1e-3),
                     "ms_per_step_profiled": pwall / a.profile_steps * 1e3,
                     "sweep_model_frac": round(sweep_model_bytes / (sweep_ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    # what a plain device-to-device copy reaches here (read + write bytes over time): the practical ceiling
+    # that the spec-sheet HBM figure does not show
+    if roof is not None:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * src.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        roof["copy_gbs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+        del src, dst
 
     # ------------------------------------------------ to residual 1e-6 modes
     resid = {}
@@ -401,6 +474,7 @@ def main():
         learned = learned_warm_start(nb, sg, torch, dev, sc, a.max_sweeps, a.target, a.residual_steps)
 
     extra = {} if a.no_extras else other_workloads(nb, sg, torch, dev)
+    sub = None if a.no_extras else subdomain_solver(nb, torch, dev, sc, a.sweeps)
 
     cpu = None
     if a.cpu_tiles > 0:
@@ -421,8 +495,10 @@ def main():
         "dtype": "f64" if a.precision == "fp64" else "f32 sweeps, f64 detection/integration",
         "data": "synthetic: oracle-settled periodic tile of 10,000 spheres replicated to the packing",
         "config": {"workload": f"dense settled packing, {sc.n} polydisperse spheres r~U[0.45,0.55], "
-                               f"periodic 100x100 floor box, phi~0.6, mu=0.5, dt=1e-4, {a.sweeps} {a.precision.upper()} NBGS "
-                               f"sweeps/step, previous-step warm start",
+                               f"periodic 100x100 floor box, phi~0.6, mu=0.5, dt=1e-4, {a.sweeps} {a.precision.upper()} "
+                               + (f"subdomain NBGS (blocks of edge {a.subdomain_edge:g}) " if a.subdomain_edge > 0
+                                  else "NBGS ")
+                               + f"sweeps/step, relaxation {sc.relax:g}, previous-step warm start",
                    "n_bodies": sc.n, "contacts_per_step": float(np.mean(contacts)),
                    "contacts_per_body": float(np.mean(contacts)) / sc.n, "colours": int(np.max(colours)),
                    "sweeps_per_step": a.sweeps},
@@ -432,6 +508,7 @@ def main():
         "to_residual_1e-6": resid,
         "learned_warm_start": learned,
         "other_workloads": extra,
+        "subdomain_nbgs": sub,
         "roofline": roof,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
