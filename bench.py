@@ -17,8 +17,9 @@ Printed JSON line (one, rank 0):
   cpu_baseline  the oracle (sequential FP64 C) on one host core, one step of a
                 bounded sample of the same packing.
 Further fields: steps/s to residual 1e-6 (FP64 and FP32 sweeps), sweeps used,
-phase times, contact statistics, and the other workloads (walled 4,096-sphere
-box, 512-scene ensemble batch, 16.8M-sphere dilute gas).
+phase times, contact statistics, the learned warm start, the subdomain NBGS
+beside the colour-ordered one, and the other workloads (walled 4,096-sphere
+box, 512-scene ensemble batch, 1M-sphere HCP ramp, 16.8M-sphere dilute gas).
 """
 import argparse
 import json
@@ -90,8 +91,9 @@ def _timed_steps(nb, torch, g, steps, sweeps):
 
 def other_workloads(nb, sg, torch, dev):
     """The walled 4,096-sphere box (100 steps x 10 FP64 sweeps), the 512-scene ensemble (FP32, 20 sweeps, 200
-    steps from the lattice, autotuned launch shape, graph-capable batch path) and the 16.8M-sphere dilute gas
-    (10 FP64 sweeps), each timed as whole steps with inputs resident on the device."""
+    steps from the lattice, autotuned launch shape, graph-capable batch path), the 1,048,576-sphere HCP ramp (100
+    FP64 sweeps, relaxation 0.75) and the 16.8M-sphere dilute gas (10 FP64 sweeps), each timed as whole steps with
+    inputs resident on the device."""
     out = {}
     sc = sg.walled_gas()
     g = nb.GpuScene(sc.copy(), device=dev, precision="fp64")
@@ -121,6 +123,24 @@ def other_workloads(nb, sg, torch, dev):
                            "note": "whole steps incl. the first step's autotuning; scenes start on their lattice"}
     gb.close()
     log(f"ensemble: {out['ensemble_512']}")
+
+    nx, ny, nz = 128, 128, 64
+    sc = sg.hcp_ramp(nx, ny, nz)
+    g = nb.GpuScene(sc, device=dev, precision="fp64")
+    g.step(100)
+    g.step(100)
+    wall, cs = _timed_steps(nb, torch, g, 5, 100)
+    st = g.state()
+    out["hcp_ramp_1m"] = {"bodies": sc.n, "steps": 5, "sweeps_per_step": 100, "relax": sc.relax,
+                          "steps_per_s": 5 / wall, "ms_per_step": wall / 5 * 1e3,
+                          "contact_updates_per_s": cs * 100 / wall, "contacts_per_step": cs / 5,
+                          "contacts_formula": nx * ny * (6 * nz - 1),
+                          "mean_downhill_velocity_after": float(st["vel"][:, 0].mean()),
+                          "phase_ms_last_step": [round(float(x), 3) for x in g.phase_times()], "dtype": "f64",
+                          "workload": "HCP 128x128x64 on a 30 degree ramp with a lid, r = 1 mm, 2.65 g/cm^3, "
+                                      "mu = 0.85, dt = 10 us, 10 cm/s downhill start, 100 sweeps, relaxation 0.75"}
+    g.close()
+    log(f"hcp ramp: {out['hcp_ramp_1m']}")
 
     sc = sg.dilute_gas()
     g = nb.GpuScene(sc, device=dev, precision="fp64")

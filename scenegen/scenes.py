@@ -13,7 +13,8 @@ generated scenes only):
   addition start), the single-sphere analogue of the granular-gas family of
   Sect. 7.2.1;
 * hexagonal close packing between two touching walls, periodic in x and y
-  (Sect. 7.2.2), whose contact count n_x n_y (6 n_z - 1) is printed there;
+  (Sect. 7.2.2), whose contact count n_x n_y (6 n_z - 1) is printed there, and
+  the same packing on the tilted ramp of that section (``hcp_ramp``);
 * dilute periodic gas on a jittered Cartesian lattice with Maxwellian
   velocities (Cartesian-grid start as in Sect. 7.2.1);
 * dense settled polydisperse packing on a floor (a periodic tile settled by the
@@ -192,6 +193,19 @@ def hcp_packing(nx, ny, nz, r=0.5, tau=None, dt=1e-3, mu=0.85, gravity=(0.0, 0.0
     vel = np.tile(np.asarray(v0, float), (n, 1))
     return _make(pos, np.full(n, r), vel=vel, lo=lo, hi=hi, periodic=(True, True, False), planes=planes,
                  dt=dt, mu=mu, tau=tau, gravity=gravity)
+
+
+def hcp_ramp(nx, ny, nz, density=2650.0, r=1e-3, dt=1e-5, mu=0.85, incline_deg=30.0, v0=0.1, relax=0.75) -> Scene:
+    """The tilted-ramp HCP workload of Sect. 7.2.2 in SI units: spheres of radius 1 mm and density 2.65 g/cm^3 in a
+    hexagonal close packing between a floor and a lid that both touch it, periodic in x and y; gravity 9.81 m/s^2
+    tilted in the x-z plane as on a 30 degree ramp (downhill +x); every sphere starts downhill at 10 cm/s; mu = 0.85
+    for every contact; dt = 10 us; under-relaxation 0.75.  Contacts: nx ny (6 nz - 1) at all times."""
+    th = math.radians(incline_deg)
+    sc = hcp_packing(nx, ny, nz, r=r, dt=dt, mu=mu, gravity=(9.81 * math.sin(th), 0.0, -9.81 * math.cos(th)),
+                     v0=(v0, 0.0, 0.0))
+    sc.inv_mass, sc.inv_inertia = solid_sphere_masses(sc.radius, density)
+    sc.relax = relax
+    return sc
 
 
 def jittered_lattice(rng, counts, spacing, r_lo, r_hi, origin=(0.0, 0.0, 0.0)):

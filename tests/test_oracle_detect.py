@@ -243,3 +243,21 @@ def test_detect_body_matches_full_list(seed, periodic):
         mask = (full["j1"] == i) | (full["j2"] == i)
         for k in ("j1", "j2", "key", "xi", "a1", "a2", "n"):
             np.testing.assert_array_equal(one[k], full[k][mask])
+
+
+def test_hcp_ramp_keeps_its_contacts_and_sticks():
+    """Sect. 7.2.2: the tilted ramp keeps n_x n_y (6 n_z - 1) contacts and, with mu = 0.85 above tan 30 deg,
+    passes from sliding to sticking shortly after the start."""
+    import oracle
+
+    nx, ny, nz = 6, 6, 4
+    sc = sg.hcp_ramp(nx, ny, nz)
+    w = oracle.World(sc)
+    vx = []
+    for _ in range(15):
+        w.step(100, grid=True)
+        assert w.view()["n_contacts"] == nx * ny * (6 * nz - 1)
+        vx.append(float(w.sc.vel[:, 0].mean()))
+    assert vx[0] > 0.09 and abs(vx[-1]) < 1e-5
+    # decelerating while it slides
+    assert all(b <= a for a, b in zip(vx[:4], vx[1:5]))
