@@ -312,7 +312,7 @@ def cpu_baseline(sample_tiles: int, sweeps: int):
     import scenegen as sg
 
     sc = sg.dense_packing(tiles=sample_tiles)
-    w = oracle.World(sc)
+    w = oracle.World(sc.copy())
     t0 = time.perf_counter()
     w.step(sweeps, grid=True, warm=False)
     t1 = time.perf_counter()
@@ -322,7 +322,33 @@ def cpu_baseline(sample_tiles: int, sweeps: int):
                 sample=f"1 step ({sweeps} FP64 sweeps, detection, colouring, integration) of a "
                        f"{sample_tiles}x{sample_tiles}-tile cut of the packing: {sc.n} spheres, "
                        f"{v['n_contacts']} contacts, {t1 - t0:.1f} s on one host core",
-                seconds=t1 - t0)
+                seconds=t1 - t0), sc, w
+
+
+def errors_against_oracle(nb, torch, dev, sc, w, sweeps):
+    """One GPU step from the scene the oracle stepped, with FP64 and with FP32 sweeps: contact lists compared bit for
+    bit, impulses and velocities as the largest deviation relative to the largest magnitude of the oracle's."""
+    import numpy as np
+
+    v = w.view()
+
+    def rel(a, b):
+        return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+    out = {}
+    for prec in ("fp64", "fp32"):
+        g = nb.GpuScene(sc.copy(), device=dev, precision=prec)
+        g.step(sweeps)
+        c = g.contacts()
+        st = g.state()
+        same = bool(np.array_equal(c["key"], v["key"]) and np.array_equal(c["colour"], v["colour"]))
+        out[prec] = {"contacts_and_colours_identical": same,
+                     "impulse_max_rel_err": rel(c["P"], v["P"]) if same else None,
+                     "velocity_max_rel_err": rel(st["vel"], w.sc.vel),
+                     "angular_velocity_max_rel_err": rel(st["angvel"], w.sc.angvel),
+                     "position_max_rel_err": rel(st["pos"], w.sc.pos)}
+        g.close()
+    return out
 
 
 def main():
@@ -431,7 +457,14 @@ def main():
             achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
             traffic = measured_traffic(("subdomain_" if a.subdomain_edge > 0 else "") + a.precision)
             tn = "double" if a.precision == "fp64" else "float"
-            kernel_name = (f"k_sub_pass<{tn}> + k_sub_reduce<{tn}>" if a.subdomain_edge > 0 else f"k_sweep<{tn}>")
+            tu = g.tuning()
+            if a.subdomain_edge > 0:
+                kernel_name = f"k_sub_pass<{tn}> + k_sub_reduce<{tn}>"
+            elif tu["lane_groups"]:
+                kernel_name = f"k_sweep_grp<{tn}, {tu['block']}, {str(bool(tu['nontemporal'])).lower()}>"
+            else:
+                kernel_name = (f"k_sweep<{tn}, {tu['block']}, {tu['contacts_per_thread']}, "
+                               f"{str(bool(tu['nontemporal'])).lower()}, {str(bool(tu['full_store'])).lower()}>")
             # secondary model: every body record read and written once per sweep, as if it stayed cached
             # between the colours of a sweep
             sweep_model_bytes = (CONTACT_BYTES[a.precision] * float(np.mean(pcontacts))
@@ -497,9 +530,14 @@ def main():
     sub = None if a.no_extras else subdomain_solver(nb, torch, dev, sc, a.sweeps)
 
     cpu = None
+    vs_oracle = None
     if a.cpu_tiles > 0:
-        cpu = cpu_baseline(a.cpu_tiles, a.sweeps)
+        cpu, osc, ow = cpu_baseline(a.cpu_tiles, a.sweeps)
         log(f"cpu baseline: {cpu}")
+        # the same step on the GPU from the same state, FP64 and FP32 sweeps, against the oracle's result
+        vs_oracle = errors_against_oracle(nb, torch, dev, osc, ow, a.sweeps)
+        log(f"against the oracle: {vs_oracle}")
+        del ow
 
     out = {
         "metric": "NBGS contact updates/s + steps/s to residual 1e-6, 1M polydisperse spheres",
@@ -531,6 +569,7 @@ def main():
         "subdomain_nbgs": sub,
         "roofline": roof,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "errors_against_oracle": vs_oracle,
     }
     print(json.dumps(out), flush=True)
     g.close()

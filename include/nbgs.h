@@ -251,11 +251,17 @@ nbgs_status nbgs_get_phase_times(nbgs_scene_t scene, int32_t n, double *out);
  * a multiple of 8 launches at most that many workgroups, 0 one per tile;
  * graph: 1 replays the sweeps from a captured HIP graph (blocks of up to 32
  * sweeps, colour ranges read on the device, persistent workgroups: the
- * resident count unless persistent gives a multiple of 8).  Impulses and
+ * resident count unless persistent gives a multiple of 8); lane_groups: 1
+ * relaxes each contact by a group of lanes, one per 16 B piece of a body
+ * record (4 lanes in FP64, 2 in FP32; needs contacts_per_thread 1): the group
+ * loads and stores each touched record whole in one instruction and shares it
+ * by lane broadcasts, every lane evaluating the contact.  Impulses and
  * velocities do not depend on any of these; the residual's partial sums are
  * grouped per tile (per workgroup with graph), so only its rounding may.
- * Default 256 / 1 / 1 / 0 / 0 / 0 / 0 for a scene, graph 1 and persistent 1
- * for a batch. */
+ * Defaults (block / contacts_per_thread / xcd_remap / nontemporal /
+ * full_store / persistent / graph / lane_groups): FP64 256/1/1/1/0/0/0/1,
+ * FP32 256/1/1/0/0/1/0/1 for a scene; a batch also sets graph 1 and
+ * persistent 1. */
 typedef struct {
     int32_t block;
     int32_t contacts_per_thread;
@@ -264,6 +270,7 @@ typedef struct {
     int32_t full_store;
     int32_t persistent;
     int32_t graph;
+    int32_t lane_groups;
 } nbgs_tuning;
 
 /* Set / read the sweep launch shape used for precision (nbgs_precision).

@@ -65,7 +65,7 @@ class nbgs_profile(C.Structure):
 class nbgs_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("contacts_per_thread", C.c_int32), ("xcd_remap", C.c_int32),
                 ("nontemporal", C.c_int32), ("full_store", C.c_int32), ("persistent", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("lane_groups", C.c_int32)]
 
 
 class NbgsError(RuntimeError):
@@ -234,17 +234,18 @@ def nbgs_get_phase_times(h: int, n: int = 5) -> np.ndarray:
 
 
 def nbgs_set_tuning(h: int, precision: int, block: int, contacts_per_thread: int, xcd_remap: int,
-                    nontemporal: int = 0, full_store: int = 0, persistent: int = 0, graph: int = 0) -> None:
+                    nontemporal: int = 0, full_store: int = 0, persistent: int = 0, graph: int = 0,
+                    lane_groups: int = 0) -> None:
     t = nbgs_tuning(block=block, contacts_per_thread=contacts_per_thread, xcd_remap=xcd_remap,
-                    nontemporal=nontemporal, full_store=full_store, persistent=persistent, graph=graph)
+                    nontemporal=nontemporal, full_store=full_store, persistent=persistent, graph=graph,
+                    lane_groups=lane_groups)
     _check(lib().nbgs_set_tuning(_vp(h), int(precision), C.byref(t)))
 
 
 def nbgs_get_tuning(h: int, precision: int) -> Dict:
     t = nbgs_tuning()
     _check(lib().nbgs_get_tuning(_vp(h), int(precision), C.byref(t)))
-    return dict(block=t.block, contacts_per_thread=t.contacts_per_thread, xcd_remap=t.xcd_remap,
-                nontemporal=t.nontemporal, full_store=t.full_store, persistent=t.persistent, graph=t.graph)
+    return _tuning_dict(t)
 
 
 def nbgs_set_profiling(h: int, enable: bool) -> None:
@@ -333,7 +334,8 @@ def nbgs_get_warm_start_info(h: int) -> Dict:
 
 def _tuning_dict(t: nbgs_tuning) -> Dict:
     return dict(block=t.block, contacts_per_thread=t.contacts_per_thread, xcd_remap=t.xcd_remap,
-                nontemporal=t.nontemporal, full_store=t.full_store, persistent=t.persistent, graph=t.graph)
+                nontemporal=t.nontemporal, full_store=t.full_store, persistent=t.persistent, graph=t.graph,
+                lane_groups=t.lane_groups)
 
 
 def nbgs_autotune(h: int, sweeps: int, cache_path: Optional[str] = None):
@@ -567,10 +569,10 @@ class GpuScene:
         self.stream.synchronize()
 
     def set_tuning(self, block=256, contacts_per_thread=1, xcd_remap=1, nontemporal=0, full_store=0, persistent=0,
-                   graph=0, precision=None):
+                   graph=0, lane_groups=0, precision=None):
         prec = PRECISIONS[precision or self.precision]
         nbgs_set_tuning(self.handle, prec, block, contacts_per_thread, xcd_remap, nontemporal, full_store, persistent,
-                        graph)
+                        graph, lane_groups)
 
     def autotune(self, sweeps: int = 8, cache_path: Optional[str] = None):
         """Choose the sweep launch shape on the detected step (see nbgs_autotune); returns (shape, ms/sweep)."""

@@ -211,7 +211,10 @@ struct SweepTune {
     int32_t full_store = 0;  // write whole body records back
     int32_t persistent = 0;  // at most one resident round of workgroups, each walking several tiles
     int32_t graph = 0;       // sweeps replayed from a captured HIP graph (colour ranges read on the device)
+    int32_t lanes = 0;       // 1: a group of lanes per contact, one lane per 16 B chunk of a body record
 };
+// Contacts per tile (one partial residual sum each).
+template <class T>
 int64_t sweep_tile(const SweepTune &t);
 bool sweep_tune_supported(const SweepTune &t);
 template <class T>

@@ -116,6 +116,53 @@ __device__ inline void apply(Rec<T> &r1, Rec<T> &r2, const T n[3], T a1, T a2, c
     r2.w[2] = r2.w[2] - r2.ii * a2 * m2;
 }
 
+// Relaxation of one contact against the body records r1, r2 (which receive
+// the impulse change): relative velocity at the contact point, the contact's
+// own impulse taken out, the one-contact solution (normal clamp, radial
+// projection onto the cone), relaxation.  One definition for every kernel
+// variant, so that they agree bit for bit.
+template <class T>
+__device__ inline void relax_contact(const T nk[3], T bias, T a1, T a2, const T Pk[3], T mu, T relax, Rec<T> &r1,
+                                     Rec<T> &r2, T Pnew[3], T dP[3]) {
+    // relative velocity at the contact point
+    const T s0 = a1 * r1.w[0] + a2 * r2.w[0];
+    const T s1 = a1 * r1.w[1] + a2 * r2.w[1];
+    const T s2 = a1 * r1.w[2] + a2 * r2.w[2];
+    T du[3];
+    du[0] = (r1.v[0] - r2.v[0]) - (s1 * nk[2] - s2 * nk[1]);
+    du[1] = (r1.v[1] - r2.v[1]) - (s2 * nk[0] - s0 * nk[2]);
+    du[2] = (r1.v[2] - r2.v[2]) - (s0 * nk[1] - s1 * nk[0]);
+    const T dun = nk[0] * du[0] + nk[1] * du[1] + nk[2] * du[2];
+    const T un = bias + dun;
+    const T ut[3] = {du[0] - dun * nk[0], du[1] - dun * nk[1], du[2] - dun * nk[2]};
+    // own impulse in the contact frame
+    const T Pn = nk[0] * Pk[0] + nk[1] * Pk[1] + nk[2] * Pk[2];
+    const T Pt[3] = {Pk[0] - Pn * nk[0], Pk[1] - Pn * nk[1], Pk[2] - Pn * nk[2]};
+    const T wn = r1.im + r2.im;
+    const T wt = wn + r1.ii * a1 * a1 + r2.ii * a2 * a2;
+    const T bn = un - wn * Pn;
+    const T bt[3] = {ut[0] - wt * Pt[0], ut[1] - wt * Pt[1], ut[2] - wt * Pt[2]};
+    // one-contact solve: normal clamp, radial projection onto the cone
+    T pn = -bn / wn;
+    if (!(pn > T(0))) pn = T(0);
+    T t0 = -bt[0] / wt, t1 = -bt[1] / wt, t2 = -bt[2] / wt;
+    const T tl = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    const T lim = mu * pn;
+    if (tl > lim) {
+        const T sc = lim / tl;
+        t0 = t0 * sc;
+        t1 = t1 * sc;
+        t2 = t2 * sc;
+    }
+    const T Ps[3] = {pn * nk[0] + t0, pn * nk[1] + t1, pn * nk[2] + t2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Pnew[a] = relax * Ps[a] + (T(1) - relax) * Pk[a];
+        dP[a] = Pnew[a] - Pk[a];
+    }
+    apply(r1, r2, nk, a1, a2, dP);
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_init_bodies(BodiesView b, double gx, double gy, double gz, double dt,
                                                         T *vel) {
@@ -235,45 +282,9 @@ __device__ inline bool sweep_tile_body(const SweepView<T> &sv, int64_t begin, in
     for (int k = 0; k < CPT; ++k) {
         if (!ok[k]) continue;
         const T *nk = n[k];
-        // relative velocity at the contact point
-        const T s0 = a1[k] * r1[k].w[0] + a2[k] * r2[k].w[0];
-        const T s1 = a1[k] * r1[k].w[1] + a2[k] * r2[k].w[1];
-        const T s2 = a1[k] * r1[k].w[2] + a2[k] * r2[k].w[2];
-        T du[3];
-        du[0] = (r1[k].v[0] - r2[k].v[0]) - (s1 * nk[2] - s2 * nk[1]);
-        du[1] = (r1[k].v[1] - r2[k].v[1]) - (s2 * nk[0] - s0 * nk[2]);
-        du[2] = (r1[k].v[2] - r2[k].v[2]) - (s0 * nk[1] - s1 * nk[0]);
-        const T dun = nk[0] * du[0] + nk[1] * du[1] + nk[2] * du[2];
-        const T un = bias[k] + dun;
-        const T ut[3] = {du[0] - dun * nk[0], du[1] - dun * nk[1], du[2] - dun * nk[2]};
-        // own impulse in the contact frame
         const T *Pk = P[k];
-        const T Pn = nk[0] * Pk[0] + nk[1] * Pk[1] + nk[2] * Pk[2];
-        const T Pt[3] = {Pk[0] - Pn * nk[0], Pk[1] - Pn * nk[1], Pk[2] - Pn * nk[2]};
-        const T wn = r1[k].im + r2[k].im;
-        const T wt = wn + r1[k].ii * a1[k] * a1[k] + r2[k].ii * a2[k] * a2[k];
-        const T bn = un - wn * Pn;
-        const T bt[3] = {ut[0] - wt * Pt[0], ut[1] - wt * Pt[1], ut[2] - wt * Pt[2]};
-        // one-contact solve: normal clamp, radial projection onto the cone
-        T pn = -bn / wn;
-        if (!(pn > T(0))) pn = T(0);
-        T t0 = -bt[0] / wt, t1 = -bt[1] / wt, t2 = -bt[2] / wt;
-        const T tl = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-        const T lim = muk[k] * pn;
-        if (tl > lim) {
-            const T sc = lim / tl;
-            t0 = t0 * sc;
-            t1 = t1 * sc;
-            t2 = t2 * sc;
-        }
-        const T Ps[3] = {pn * nk[0] + t0, pn * nk[1] + t1, pn * nk[2] + t2};
         T Pnew[3], dP[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            Pnew[a] = relax * Ps[a] + (T(1) - relax) * Pk[a];
-            dP[a] = Pnew[a] - Pk[a];
-        }
-        apply(r1[k], r2[k], nk, a1[k], a2[k], dP);
+        relax_contact(nk, bias[k], a1[k], a2[k], Pk, muk[k], relax, r1[k], r2[k], Pnew, dP);
         if (r1[k].im > T(0)) store_vel<FULL>(vel, b1[k], r1[k]);
         if (b2[k] < nb && r2[k].im > T(0)) store_vel<FULL>(vel, b2[k], r2[k]);
         const int64_t p = p0 + (int64_t)k * BLOCK;
@@ -340,6 +351,152 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dev(SweepView<T> sv, const int6
     double sd = 0.0, sp = 0.0;
     for (unsigned t = w.t; t < w.end; t += w.step)
         if (sweep_tile_body<T, BLOCK, CPT, NT, FULL>(sv, begin, end, nb, vel, mu, relax, ctrl, t, sd, sp)) return;
+    block_partials<BLOCK>(sd, sp, red, partials + 2 * blockIdx.x);
+}
+
+
+// Lane groups.  The L lanes of a group relax one contact together (L = 4 in
+// FP64, 2 in FP32: the 16 B chunks of a body record).  Lane q loads chunk q of
+// both body records, so that one load instruction reads each record as one
+// contiguous piece (one memory request per record instead of one per chunk);
+// DPP broadcasts inside the group hand every lane the whole records, every
+// lane evaluates the contact (the same values by the same operations), lane q
+// writes chunk q back (whole records) and lane 0 the impulse and the residual
+// sums.
+template <class T>
+struct Chunks;
+template <>
+struct Chunks<double> {
+    using V = double2;
+    static constexpr int L = 4;
+};
+template <>
+struct Chunks<float> {
+    using V = float4;
+    static constexpr int L = 2;
+};
+
+// Lane K of every group of L consecutive lanes, to each lane of that group
+// (quad_perm selections: all four lanes of a quad read lane K; for pairs, lanes
+// 0, 1 read lane K and lanes 2, 3 read lane 2 + K).
+template <int L, int K>
+__device__ inline int group_bcast_i32(int x) {
+    if constexpr (L == 4) return __builtin_amdgcn_mov_dpp(x, K * 0x55, 0xf, 0xf, true);
+    else return __builtin_amdgcn_mov_dpp(x, K == 0 ? 0xa0 : 0xf5, 0xf, 0xf, true);
+}
+template <int L, int K>
+__device__ inline double group_bcast(double x) {
+    const long long u = __double_as_longlong(x);
+    const unsigned lo = (unsigned)group_bcast_i32<L, K>((int)(unsigned)(u & 0xffffffffll));
+    const unsigned hi = (unsigned)group_bcast_i32<L, K>((int)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int L, int K>
+__device__ inline float group_bcast(float x) {
+    return __int_as_float(group_bcast_i32<L, K>(__float_as_int(x)));
+}
+
+__device__ inline Rec<double> group_rec(const double2 c) {
+    Rec<double> r;
+    r.v[0] = group_bcast<4, 0>(c.x);
+    r.v[1] = group_bcast<4, 0>(c.y);
+    r.v[2] = group_bcast<4, 1>(c.x);
+    r.w[0] = group_bcast<4, 1>(c.y);
+    r.w[1] = group_bcast<4, 2>(c.x);
+    r.w[2] = group_bcast<4, 2>(c.y);
+    r.im = group_bcast<4, 3>(c.x);
+    r.ii = group_bcast<4, 3>(c.y);
+    return r;
+}
+
+__device__ inline Rec<float> group_rec(const float4 c) {
+    Rec<float> r;
+    r.v[0] = group_bcast<2, 0>(c.x);
+    r.v[1] = group_bcast<2, 0>(c.y);
+    r.v[2] = group_bcast<2, 0>(c.z);
+    r.w[0] = group_bcast<2, 0>(c.w);
+    r.w[1] = group_bcast<2, 1>(c.x);
+    r.w[2] = group_bcast<2, 1>(c.y);
+    r.im = group_bcast<2, 1>(c.z);
+    r.ii = group_bcast<2, 1>(c.w);
+    return r;
+}
+
+// Chunk q of a record {v'x, v'y, v'z, w'x, w'y, w'z, 1/m, 1/I}.
+__device__ inline double2 rec_chunk(const Rec<double> &r, int q) {
+    return q == 0 ? make_double2(r.v[0], r.v[1])
+                  : q == 1 ? make_double2(r.v[2], r.w[0]) : q == 2 ? make_double2(r.w[1], r.w[2]) : make_double2(r.im, r.ii);
+}
+__device__ inline float4 rec_chunk(const Rec<float> &r, int q) {
+    return q == 0 ? make_float4(r.v[0], r.v[1], r.v[2], r.w[0]) : make_float4(r.w[1], r.w[2], r.im, r.ii);
+}
+
+// One tile of BLOCK / L contacts.  A group past the end relaxes the colour's
+// first contact on copies and writes nothing; groups never straddle a wave.
+template <class T, int BLOCK, bool NT>
+__device__ inline bool sweep_group_body(const SweepView<T> &sv, int64_t begin, int64_t end, int32_t nb, T *vel, T mu,
+                                        T relax, const int32_t *ctrl, unsigned tile, double &sd, double &sp) {
+    using V = typename Chunks<T>::V;
+    constexpr int L = Chunks<T>::L;
+    const int q = (int)(threadIdx.x & (L - 1));
+    const int64_t p = begin + (int64_t)tile * (BLOCK / L) + (int64_t)(threadIdx.x / L);
+    const bool ok = p < end;
+    const int64_t r = ok ? p : begin;
+    const int b1 = ld<NT>(sv.j1 + r), b2 = ld<NT>(sv.j2 + r);
+    const T n[3] = {ld<NT>(sv.nx + r), ld<NT>(sv.ny + r), ld<NT>(sv.nz + r)};
+    const T bias = ld<NT>(sv.bias + r), a1 = ld<NT>(sv.a1 + r), a2 = ld<NT>(sv.a2 + r);
+    const T P[3] = {ld<NT>(sv.px + r), ld<NT>(sv.py + r), ld<NT>(sv.pz + r)};
+    const T muk = sv.mu ? ld<NT>(sv.mu + r) : mu;
+    if (ctrl[0]) return true;
+    const bool sphere2 = b2 < nb;
+    const V c1 = reinterpret_cast<const V *>(vel + 8 * (int64_t)b1)[q];
+    const V c2 = reinterpret_cast<const V *>(vel + 8 * (int64_t)(sphere2 ? b2 : b1))[q];  // a wall: replaced below
+    Rec<T> r1 = group_rec(c1);
+    const Rec<T> r2g = group_rec(c2);
+    Rec<T> r2 = sphere2 ? r2g : zero_rec<T>();
+    T Pnew[3], dP[3];
+    relax_contact(n, bias, a1, a2, P, muk, relax, r1, r2, Pnew, dP);
+    if (ok) {
+        if (r1.im > T(0)) reinterpret_cast<V *>(vel + 8 * (int64_t)b1)[q] = rec_chunk(r1, q);
+        if (sphere2 && r2.im > T(0)) reinterpret_cast<V *>(vel + 8 * (int64_t)b2)[q] = rec_chunk(r2, q);
+        if (q == 0) {
+            st<NT>(sv.px + p, Pnew[0]);
+            st<NT>(sv.py + p, Pnew[1]);
+            st<NT>(sv.pz + p, Pnew[2]);
+            const double d0 = dP[0], d1 = dP[1], d2 = dP[2];
+            const double q0 = Pnew[0], q1 = Pnew[1], q2 = Pnew[2];
+            sd += d0 * d0 + d1 * d1 + d2 * d2;
+            sp += q0 * q0 + q1 * q1 + q2 * q2;
+        }
+    }
+    return false;
+}
+
+template <class T, int BLOCK, bool NT>
+__global__ void __launch_bounds__(BLOCK) k_sweep_grp(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel,
+                                                     T mu, T relax, double *partials, const int32_t *ctrl, unsigned G,
+                                                     int xcd_remap) {
+    __shared__ double red[2][BLOCK / 64];
+    const TileWalk w = tile_walk(blockIdx.x, gridDim.x, G, xcd_remap);
+    for (unsigned t = w.t; t < w.end; t += w.step) {
+        double sd = 0.0, sp = 0.0;
+        if (sweep_group_body<T, BLOCK, NT>(sv, begin, end, nb, vel, mu, relax, ctrl, t, sd, sp)) return;
+        block_partials<BLOCK>(sd, sp, red, partials + 2 * t);
+    }
+}
+
+template <class T, int BLOCK, bool NT>
+__global__ void __launch_bounds__(BLOCK) k_sweep_grp_dev(SweepView<T> sv, const int64_t *col, int c, int32_t nb,
+                                                         T *vel, T mu, T relax, double *partials, const int32_t *ctrl,
+                                                         int xcd_remap) {
+    __shared__ double red[2][BLOCK / 64];
+    constexpr int PER = BLOCK / Chunks<T>::L;
+    const int64_t begin = col[c], end = col[c + 1];
+    const unsigned G = (unsigned)((end - begin + PER - 1) / PER);
+    const TileWalk w = tile_walk(blockIdx.x, gridDim.x, G, xcd_remap);
+    double sd = 0.0, sp = 0.0;
+    for (unsigned t = w.t; t < w.end; t += w.step)
+        if (sweep_group_body<T, BLOCK, NT>(sv, begin, end, nb, vel, mu, relax, ctrl, t, sd, sp)) return;
     block_partials<BLOCK>(sd, sp, red, partials + 2 * blockIdx.x);
 }
 
@@ -466,14 +623,19 @@ nbgs_status launch_warm_scatter(SweepView<T> sv, int64_t begin, int64_t end, int
     return NBGS_OK;
 }
 
-int64_t sweep_tile(const SweepTune &t) { return (int64_t)t.block * t.cpt; }
+template <class T>
+int64_t sweep_tile(const SweepTune &t) {
+    return t.lanes ? (int64_t)t.block / Chunks<T>::L : (int64_t)t.block * t.cpt;
+}
+template int64_t sweep_tile<double>(const SweepTune &);
+template int64_t sweep_tile<float>(const SweepTune &);
 
 bool sweep_tune_supported(const SweepTune &t) {
     const bool blk = t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512;
     return blk && (t.cpt == 1 || t.cpt == 2 || t.cpt == 4) && (t.xcd_remap == 0 || t.xcd_remap == 1) &&
            (t.nontemporal == 0 || t.nontemporal == 1) && (t.full_store == 0 || t.full_store == 1) &&
            (t.persistent == 0 || t.persistent == 1 || (t.persistent >= 8 && t.persistent % 8 == 0)) &&
-           (t.graph == 0 || t.graph == 1);
+           (t.graph == 0 || t.graph == 1) && (t.lanes == 0 || (t.lanes == 1 && t.cpt == 1));
 }
 
 // Workgroups of a persistent sweep grid: what the device holds resident at
@@ -497,8 +659,38 @@ template <class T>
 nbgs_status launch_sweep_colour(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, SweepParams sp,
                                 const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s) {
     if (end <= begin) return NBGS_OK;
-    const unsigned G = (unsigned)((end - begin + sweep_tile(t) - 1) / sweep_tile(t));
+    const int64_t tile = sweep_tile<T>(t);
+    const unsigned G = (unsigned)((end - begin + tile - 1) / tile);
     const T mu = (T)sp.mu, relax = (T)sp.relax;
+    if (t.lanes) {
+#define NBGS_GRP_LAUNCH(B, NT)                                                                                     \
+    do {                                                                                                           \
+        auto kern = k_sweep_grp<T, B, NT>;                                                                         \
+        unsigned grid = G;                                                                                         \
+        if (t.persistent == 1) {                                                                                   \
+            static const unsigned cap = persistent_cap(kern, B);                                                   \
+            if (cap < grid) grid = cap;                                                                            \
+        } else if (t.persistent > 1 && (unsigned)t.persistent < grid) {                                            \
+            grid = (unsigned)t.persistent;                                                                         \
+        }                                                                                                          \
+        kern<<<grid, B, 0, s>>>(sv, begin, end, nb, vel, mu, relax, partials, ctrl, G, t.xcd_remap);               \
+        NBGS_HIP(hipGetLastError());                                                                               \
+        return NBGS_OK;                                                                                            \
+    } while (0)
+#define NBGS_GRP_CASE(B)                                                                                           \
+    if (t.block == B) {                                                                                            \
+        if (t.nontemporal) NBGS_GRP_LAUNCH(B, true);                                                               \
+        else NBGS_GRP_LAUNCH(B, false);                                                                            \
+    }
+        NBGS_GRP_CASE(64)
+        NBGS_GRP_CASE(128)
+        NBGS_GRP_CASE(256)
+        NBGS_GRP_CASE(512)
+#undef NBGS_GRP_CASE
+#undef NBGS_GRP_LAUNCH
+        set_error("unsupported sweep tuning block=%d with lane groups", t.block);
+        return NBGS_ERR_INVALID_ARG;
+    }
 #define NBGS_SWEEP_LAUNCH(B, C, NT, FULL)                                                                          \
     do {                                                                                                           \
         auto kern = k_sweep<T, B, C, NT, FULL>;                                                                    \
@@ -570,8 +762,29 @@ unsigned dev_grid(const SweepTune &t) {
         else ACTION(B, C, false, false);                                                                           \
     }
 
+template <class T, int B, bool NT>
+unsigned dev_grid_grp(const SweepTune &t) {
+    if (t.persistent > 1) return (unsigned)t.persistent;
+    static const unsigned cap = persistent_cap(k_sweep_grp_dev<T, B, NT>, B);
+    return cap;
+}
+
+#define NBGS_GRP_DEV_DISPATCH(ACTION)                                                                              \
+    do {                                                                                                           \
+        if (t.block == 64) { if (t.nontemporal) ACTION(64, true); else ACTION(64, false); }                        \
+        if (t.block == 128) { if (t.nontemporal) ACTION(128, true); else ACTION(128, false); }                     \
+        if (t.block == 256) { if (t.nontemporal) ACTION(256, true); else ACTION(256, false); }                     \
+        if (t.block == 512) { if (t.nontemporal) ACTION(512, true); else ACTION(512, false); }                     \
+    } while (0)
+
 template <class T>
 unsigned sweep_graph_grid(const SweepTune &t) {
+    if (t.lanes) {
+#define NBGS_GRID_OF_GRP(B, NT) return dev_grid_grp<T, B, NT>(t)
+        NBGS_GRP_DEV_DISPATCH(NBGS_GRID_OF_GRP);
+#undef NBGS_GRID_OF_GRP
+        return 0;
+    }
 #define NBGS_GRID_OF(B, C, NT, FULL) return dev_grid<T, B, C, NT, FULL>(t)
     NBGS_SWEEP_DEV_DISPATCH(NBGS_GRID_OF);
 #undef NBGS_GRID_OF
@@ -582,6 +795,19 @@ template <class T>
 nbgs_status launch_sweep_colour_dev(SweepView<T> sv, const int64_t *col, int32_t c, int32_t nb, T *vel, SweepParams sp,
                                     const SweepTune &t, double *partials, const int32_t *ctrl, hipStream_t s) {
     const T mu = (T)sp.mu, relax = (T)sp.relax;
+    if (t.lanes) {
+#define NBGS_LAUNCH_GRP_DEV(B, NT)                                                                                 \
+    do {                                                                                                           \
+        k_sweep_grp_dev<T, B, NT><<<dev_grid_grp<T, B, NT>(t), B, 0, s>>>(sv, col, c, nb, vel, mu, relax, partials, \
+                                                                         ctrl, t.xcd_remap);                      \
+        NBGS_HIP(hipGetLastError());                                                                               \
+        return NBGS_OK;                                                                                            \
+    } while (0)
+        NBGS_GRP_DEV_DISPATCH(NBGS_LAUNCH_GRP_DEV);
+#undef NBGS_LAUNCH_GRP_DEV
+        set_error("unsupported sweep tuning block=%d with lane groups", t.block);
+        return NBGS_ERR_INVALID_ARG;
+    }
 #define NBGS_LAUNCH_DEV(B, C, NT, FULL)                                                                            \
     do {                                                                                                           \
         k_sweep_dev<T, B, C, NT, FULL><<<dev_grid<T, B, C, NT, FULL>(t), B, 0, s>>>(sv, col, c, nb, vel, mu, relax, \
@@ -596,6 +822,7 @@ nbgs_status launch_sweep_colour_dev(SweepView<T> sv, const int64_t *col, int32_t
 }
 #undef NBGS_SWEEP_DEV_CASE
 #undef NBGS_SWEEP_DEV_DISPATCH
+#undef NBGS_GRP_DEV_DISPATCH
 
 nbgs_status launch_residual(const double *partials, int32_t n_partials, double target, int32_t *ctrl, double *hist,
                             hipStream_t s, int32_t at) {

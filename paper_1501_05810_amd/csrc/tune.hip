@@ -13,7 +13,7 @@
 // Search: coordinate descent from the current shape, one parameter at a time
 // over its allowed values, keeping a change only if it is faster by more than
 // 1 %.  A cache file keeps one line per choice,
-//     <arch>|<fp64|fp32>|<scene|batch>|<ceil log2 contacts> block cpt xcd nt full persistent graph ms
+//     <arch>|<fp64|fp32>|<scene|batch>|<ceil log2 contacts> block cpt xcd nt full persistent graph lanes ms
 // and the last line of a key wins; a missing or unreadable file is ignored.
 #include <cstdio>
 #include <cstring>
@@ -55,8 +55,8 @@ bool cache_lookup(const std::string &path, const std::string &key, SweepTune &t,
         char k[256];
         SweepTune c;
         double m = 0.0;
-        if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %lf", k, &c.block, &c.cpt, &c.xcd_remap, &c.nontemporal,
-                        &c.full_store, &c.persistent, &c.graph, &m) != 9)
+        if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %lf", k, &c.block, &c.cpt, &c.xcd_remap, &c.nontemporal,
+                        &c.full_store, &c.persistent, &c.graph, &c.lanes, &m) != 10)
             continue;
         if (key == k && sweep_tune_supported(c)) {
             t = c;
@@ -72,8 +72,8 @@ void cache_store(const std::string &path, const std::string &key, const SweepTun
     if (path.empty()) return;
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d %d %d %.6g\n", key.c_str(), t.block, t.cpt, t.xcd_remap, t.nontemporal,
-                 t.full_store, t.persistent, t.graph, ms);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.6g\n", key.c_str(), t.block, t.cpt, t.xcd_remap, t.nontemporal,
+                 t.full_store, t.persistent, t.graph, t.lanes, ms);
     std::fclose(f);
 }
 
@@ -155,7 +155,7 @@ nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen,
         st = trial(sc, best, sweeps, saved, e0, e1, ms);
         if (st == NBGS_OK) st = trial(sc, best, sweeps, saved, e0, e1, best_t);
         const int blocks[] = {64, 128, 256, 512}, cpts[] = {1, 2, 4}, bits[] = {0, 1};
-        for (int dim = 0; dim < 7 && st == NBGS_OK; ++dim) {
+        for (int dim = 0; dim < 8 && st == NBGS_OK; ++dim) {
             const int *vals = dim == 0 ? blocks : dim == 1 ? cpts : bits;
             const int nv = dim == 0 ? 4 : dim == 1 ? 3 : 2;
             for (int v = 0; v < nv && st == NBGS_OK; ++v) {
@@ -166,7 +166,8 @@ nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen,
                                  : dim == 3 ? &c.nontemporal
                                  : dim == 4 ? &c.full_store
                                  : dim == 5 ? &c.persistent
-                                            : &c.graph;
+                                 : dim == 6 ? &c.graph
+                                            : &c.lanes;
                 if (*field == vals[v]) continue;
                 *field = vals[v];
                 if (!sweep_tune_supported(c)) continue;
@@ -196,6 +197,7 @@ nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen,
         chosen->full_store = best.full_store;
         chosen->persistent = best.persistent;
         chosen->graph = best.graph;
+        chosen->lane_groups = best.lanes;
     }
     if (best_ms) *best_ms = best_t;
     return NBGS_OK;

@@ -82,7 +82,8 @@ def test_batch_members_equal_standalone_scenes(precision, tmp_path):
 
 @pytest.mark.parametrize("shape", [dict(graph=0, persistent=0), dict(graph=1, persistent=8),
                                    dict(graph=1, persistent=1, block=128, contacts_per_thread=2),
-                                   dict(graph=0, persistent=16, block=64)])
+                                   dict(graph=0, persistent=16, block=64), dict(graph=1, persistent=1, lane_groups=1),
+                                   dict(graph=0, persistent=0, lane_groups=1, block=64)])
 def test_batch_launch_shapes(shape):
     """Explicit shapes (no autotuning): graph replay and direct launches, resident and capped workgroups."""
     nb = _nb()

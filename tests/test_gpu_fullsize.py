@@ -148,3 +148,33 @@ def test_dilute_gas_16m():
     g.integrate()
     _integration_properties(sc, before, g.state())
     g.close()
+
+
+@pytest.mark.skipif(not os.path.exists(sg.DENSE_TILE), reason="dense tile not generated")
+def test_dense_packing_1m_subdomain_solver():
+    """The subdomain solver at full size (blocks of edge 5, relaxation 0.75): the colouring is valid inside every
+    subdomain of the oracle's assignment (contacts of one subdomain and one colour share no dynamic body), and the
+    solve and integration meet the same size-independent properties as the colour-ordered solver."""
+    nb = _nb()
+    sc = sg.dense_packing(tiles=10)
+    sc.relax = 0.75
+    g = nb.GpuScene(sc.copy()).set_subdomains(5.0)
+    st = g.detect()
+    c = g.contacts()
+    assert st["n_contacts"] == len(c["key"])
+    sdom, n_sub = oracle.subdomains(sc, c["j1"].astype(np.int32), 5.0)
+    assert n_sub == 20 * 20 * 17
+    col = c["colour"].astype(np.int64) * n_sub + sdom
+    dyn1 = sc.inv_mass[c["j1"]] > 0
+    j2 = c["j2"]
+    sph2 = j2 < sc.n
+    dyn2 = np.zeros_like(sph2)
+    dyn2[sph2] = sc.inv_mass[j2[sph2]] > 0
+    pairs = np.concatenate([col[dyn1] * sc.n + c["j1"][dyn1], col[dyn2] * sc.n + j2[dyn2]])
+    assert np.unique(pairs).size == pairs.size, "two contacts of one subdomain and colour share a dynamic body"
+    before = g.state()
+    g.solve(50)
+    _solve_properties(sc, g, g.contacts(), before["vel"])
+    g.integrate()
+    _integration_properties(sc, before, g.state())
+    g.close()

@@ -321,12 +321,16 @@ def test_colouring_from_previous_step_equals_greedy():
 
 @pytest.mark.parametrize("shape", [(64, 1, 0), (128, 2, 1), (256, 4, 1), (512, 1, 1), (512, 4, 0),
                                    (256, 1, 1, 1, 1), (128, 2, 1, 0, 1), (64, 1, 1, 0, 0, 8), (64, 2, 0, 1, 1, 16),
-                                   (128, 1, 1, 0, 0, 24), (256, 1, 1, 1, 1, 1)])
+                                   (128, 1, 1, 0, 0, 24), (256, 1, 1, 1, 1, 1),
+                                   (256, 1, 1, 0, 0, 0, 0, 1), (64, 1, 0, 1, 0, 0, 0, 1), (512, 1, 1, 0, 0, 1, 0, 1),
+                                   (128, 1, 1, 1, 0, 16, 0, 1)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_launch_shapes_are_bit_identical(shape, precision):
     """Every supported sweep launch shape (block, contacts per thread, XCD remap, non-temporal hint, whole-record
-    store, persistent workgroup cap) relaxes each contact with the same arithmetic: impulses and velocities are
-    bit-identical.  Caps of 8 to 24 workgroups make each workgroup walk many tiles of a colour."""
+    store, persistent workgroup cap, graph, lane groups) relaxes each contact with the same arithmetic: impulses and
+    velocities are bit-identical.  Caps of 8 to 24 workgroups make each workgroup walk many tiles of a colour; lane
+    groups (a group of lanes per contact sharing the body records by lane broadcasts) must reproduce the one-thread
+    result exactly, walls and tails included."""
     nb = _nb()
     sc = sg.packed_cluster(10, counts=(16, 16, 8))
     outs = []
@@ -341,3 +345,21 @@ def test_launch_shapes_are_bit_identical(shape, precision):
     assert np.array_equal(Pa, Pb) and np.array_equal(va, vb)
     # the residual's partial sums are grouped per tile, so only its rounding may differ
     np.testing.assert_allclose(ra, rb, rtol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lane_groups_with_graph_replay_and_residual_target(precision):
+    """Lane groups in graph-replayed sweeps (device-read colour ranges, resident workgroups): the same impulses and
+    velocities as the default shape, and with a residual target the same stopping sweep."""
+    nb = _nb()
+    sc = sg.packed_cluster(17, counts=(14, 12, 8))
+    runs = []
+    for shape in (dict(), dict(graph=1, persistent=1, lane_groups=1), dict(graph=1, persistent=16, lane_groups=1)):
+        g = nb.GpuScene(sc.copy(), precision=precision)
+        g.set_tuning(**shape)
+        g.step(40)
+        st = g.step(300, 1e-5)
+        runs.append((g.contacts()["P"], g.state()["vel"], st["sweeps"]))
+        g.close()
+    for P, v, k in runs[1:]:
+        assert np.array_equal(P, runs[0][0]) and np.array_equal(v, runs[0][1]) and k == runs[0][2]
