@@ -104,7 +104,9 @@ def lib():
         L.nbgs_ref_world_set_impulses.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.nbgs_ref_world_set_prev.argtypes = [C.c_void_p, C.c_int64, _u64p, _dp, _dp, _dp]
         L.nbgs_ref_world_set_subdomains.argtypes = [C.c_void_p, C.c_double]
+        L.nbgs_ref_world_set_block_order.argtypes = [C.c_void_p, C.c_double]
         L.nbgs_ref_subdomains.restype = C.c_int32
+        L.nbgs_ref_block_local.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -243,6 +245,21 @@ def subdomains(sc, j1: np.ndarray, edge: float):
     return out[:m].copy(), int(n)
 
 
+def block_local(sc, j1: np.ndarray, j2: np.ndarray, edge: float):
+    """Block-local id of every contact (the block of its dynamic bodies if they share one, else the number of
+    blocks); returns (id, number of ids = blocks + 1)."""
+    held = _Held()
+    b = make_bodies(sc, held)
+    dom = make_domain(sc, held)
+    m = int(j1.shape[0])
+    out = np.zeros(max(m, 1), dtype=np.int32)
+    j1c = np.ascontiguousarray(j1, dtype=np.int32)
+    j2c = np.ascontiguousarray(j2, dtype=np.int32)
+    n = lib().nbgs_ref_block_local(C.byref(b), C.byref(dom), C.c_double(edge), C.c_int64(m), _ptr(j1c, _i32p),
+                                   _ptr(j2c, _i32p), _ptr(out, _i32p))
+    return out[:m].copy(), int(n)
+
+
 def solve_sub(sc, c: Dict[str, np.ndarray], order: np.ndarray, sdom: np.ndarray, P0: np.ndarray, sweeps: int):
     """Subdomain NBGS on a given contact list, sweep order and subdomain of every contact (the order must group
     the subdomains in ascending order).  Returns (P, v', w', residual history)."""
@@ -367,6 +384,12 @@ class World:
     def set_subdomains(self, edge: float):
         """edge > 0: subdomain NBGS with blocks of about this edge from the next detection on; 0: classic."""
         lib().nbgs_ref_world_set_subdomains(self._w, C.c_double(edge))
+        return self
+
+    def set_block_order(self, edge: float):
+        """edge > 0: the plain NBGS swept in the block-local order (blocks of about this edge) from the next
+        detection on; 0: (colour, key) order."""
+        lib().nbgs_ref_world_set_block_order(self._w, C.c_double(edge))
         return self
 
 

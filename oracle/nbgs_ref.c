@@ -12,6 +12,10 @@
  *   colouring of contacts (no two contacts in a colour
  *     share a dynamic body; replaces the subdomain
  *     affinity s_c(j) of Alg. 1)                       -> nbgs_ref_colour, nbgs_ref_sweep_order
+ *   block-local sweep order (block by block, then the
+ *     contacts between blocks)                         -> nbgs_ref_block_local, nbgs_ref_sweep_order_sub
+ *   subdomain NBGS (Alg. 1 with block subdomains,
+ *     Sect. 6.1, 6.3)                                  -> nbgs_ref_subdomains, nbgs_ref_solve_sub
  *   warm start from the previous step (Sect. 5)        -> nbgs_ref_warm_match
  *   accumulator init + NBGS sweeps (Alg. 1 with one
  *     subdomain, Sect. 6.3 velocity accumulators,
@@ -462,11 +466,8 @@ void nbgs_ref_sweep_order(int64_t nc, const int32_t *colour, int32_t n_colours, 
  * L_a / nb_a, and contact j belongs to the block holding the centre of body
  * j1 (block coordinates clamped into the box).  Block id (c_z nb_y + c_y)
  * nb_x + c_x.  Returns the number of blocks. */
-int32_t nbgs_ref_subdomains(const ref_bodies *b, const ref_domain *dom, double edge, int64_t nc, const int32_t *j1,
-                            int32_t *sdom)
+static void block_grid(const ref_domain *dom, double edge, int64_t nb[3], double e[3])
 {
-    int64_t nb[3];
-    double e[3];
     for (int a = 0; a < 3; ++a) {
         double L = dom->hi[a] - dom->lo[a];
         double c = floor(L / edge);
@@ -474,18 +475,58 @@ int32_t nbgs_ref_subdomains(const ref_bodies *b, const ref_domain *dom, double e
         nb[a] = (int64_t)c;
         e[a] = L / c;
     }
-    for (int64_t j = 0; j < nc; ++j) {
-        int64_t i = j1[j];
-        double x[3] = {b->x[i], b->y[i], b->z[i]};
-        int64_t c[3];
-        for (int a = 0; a < 3; ++a) {
-            double f = floor((x[a] - dom->lo[a]) / e[a]);
-            f = fmax(0.0, fmin(f, (double)(nb[a] - 1)));
-            c[a] = (int64_t)f;
-        }
-        sdom[j] = (int32_t)((c[2] * nb[1] + c[1]) * nb[0] + c[0]);
+}
+
+/* Block holding the centre of body i (coordinates clamped into the box). */
+static int32_t block_of(const ref_bodies *b, const ref_domain *dom, const int64_t nb[3], const double e[3], int64_t i)
+{
+    double x[3] = {b->x[i], b->y[i], b->z[i]};
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) {
+        double f = floor((x[a] - dom->lo[a]) / e[a]);
+        f = fmax(0.0, fmin(f, (double)(nb[a] - 1)));
+        c[a] = (int64_t)f;
     }
+    return (int32_t)((c[2] * nb[1] + c[1]) * nb[0] + c[0]);
+}
+
+int32_t nbgs_ref_subdomains(const ref_bodies *b, const ref_domain *dom, double edge, int64_t nc, const int32_t *j1,
+                            int32_t *sdom)
+{
+    int64_t nb[3];
+    double e[3];
+    block_grid(dom, edge, nb, e);
+    for (int64_t j = 0; j < nc; ++j) sdom[j] = block_of(b, dom, nb, e, j1[j]);
     return (int32_t)(nb[0] * nb[1] * nb[2]);
+}
+
+/* Block-local sweep order of the plain NBGS (one subdomain in Alg. 1; any
+ * order of the contacts is a Gauss-Seidel sweep).  With the blocks of
+ * nbgs_ref_subdomains, a contact whose dynamic bodies all lie in one block
+ * is local to that block and gets its id; a contact between dynamic bodies of
+ * two different blocks gets the id nblocks.  Sorting by (id, colour, key),
+ * the colouring restricted to equal ids, sweeps every block's local contacts
+ * (blocks share no dynamic body through them) and then the others.  Returns
+ * nblocks + 1, the number of ids. */
+int32_t nbgs_ref_block_local(const ref_bodies *b, const ref_domain *dom, double edge, int64_t nc, const int32_t *j1,
+                             const int32_t *j2, int32_t *id)
+{
+    int64_t nb[3];
+    double e[3];
+    block_grid(dom, edge, nb, e);
+    int32_t nblocks = (int32_t)(nb[0] * nb[1] * nb[2]);
+    int64_t N = b->n;
+    for (int64_t j = 0; j < nc; ++j) {
+        int d1 = b->inv_mass[j1[j]] > 0.0;
+        int d2 = j2[j] < N && b->inv_mass[j2[j]] > 0.0;
+        if (d1 && d2) {
+            int32_t k1 = block_of(b, dom, nb, e, j1[j]), k2 = block_of(b, dom, nb, e, j2[j]);
+            id[j] = k1 == k2 ? k1 : nblocks;
+        } else {
+            id[j] = block_of(b, dom, nb, e, d1 ? j1[j] : j2[j]);
+        }
+    }
+    return nblocks + 1;
 }
 
 /* Sweep order of the subdomain solver: contacts sorted by (subdomain, colour,
@@ -963,6 +1004,7 @@ typedef struct {
     double *residual_hist;
     int32_t hist_cap;
     double sub_edge; /* > 0: subdomain NBGS with blocks of about this edge */
+    double blk_edge; /* > 0: plain NBGS in the block-local order with blocks of about this edge */
     int32_t *sdom;
     int32_t n_sub;
 } ref_world;
@@ -1073,6 +1115,12 @@ void nbgs_ref_world_detect(ref_world *W, int32_t use_grid, int32_t warm)
         W->n_colours =
             nbgs_ref_colour(W->b.n, W->b.inv_mass, m, W->c.j1, W->c.j2, W->c.key, W->p.colour_seed, W->sdom, W->colour);
         nbgs_ref_sweep_order_sub(m, W->sdom, W->n_sub, W->colour, W->n_colours, W->order);
+    } else if (W->blk_edge > 0.0) {
+        W->sdom = (int32_t *)realloc(W->sdom, n * sizeof(int32_t));
+        W->n_sub = nbgs_ref_block_local(&W->b, &W->dom, W->blk_edge, m, W->c.j1, W->c.j2, W->sdom);
+        W->n_colours =
+            nbgs_ref_colour(W->b.n, W->b.inv_mass, m, W->c.j1, W->c.j2, W->c.key, W->p.colour_seed, W->sdom, W->colour);
+        nbgs_ref_sweep_order_sub(m, W->sdom, W->n_sub, W->colour, W->n_colours, W->order);
     } else {
         W->n_colours =
             nbgs_ref_colour(W->b.n, W->b.inv_mass, m, W->c.j1, W->c.j2, W->c.key, W->p.colour_seed, NULL, W->colour);
@@ -1161,13 +1209,17 @@ void nbgs_ref_world_view_get(const ref_world *W, ref_world_view *out)
     out->v = W->v;
     out->w = W->w;
     out->residual_hist = W->residual_hist;
-    out->sdom = W->sub_edge > 0.0 ? W->sdom : NULL;
-    out->n_sub = W->sub_edge > 0.0 ? W->n_sub : 0;
+    out->sdom = W->sub_edge > 0.0 || W->blk_edge > 0.0 ? W->sdom : NULL;
+    out->n_sub = W->sub_edge > 0.0 || W->blk_edge > 0.0 ? W->n_sub : 0;
 }
 
 /* edge > 0: later detections assign subdomains and solves run the subdomain
  * NBGS; edge = 0: one subdomain, the classic NBGS. */
 void nbgs_ref_world_set_subdomains(ref_world *W, double edge) { W->sub_edge = edge > 0.0 ? edge : 0.0; }
+
+/* edge > 0: later detections sweep in the block-local order (plain NBGS);
+ * edge = 0: (colour, key) order. */
+void nbgs_ref_world_set_block_order(ref_world *W, double edge) { W->blk_edge = edge > 0.0 ? edge : 0.0; }
 
 /* Replace the previous-step impulse table (key-sorted) used by the warm start. */
 void nbgs_ref_world_set_prev(ref_world *W, int64_t n, const uint64_t *key, const double *px, const double *py,
