@@ -4,9 +4,13 @@
 Workload: dense settled packing of 1,000,000 polydisperse spheres (radii
 U[0.45, 0.55], density 1), laterally periodic 100 x 100 box on a floor plane,
 solid fraction about 0.6, coordination about 6, mu = 0.5, dt = 1e-4, gravity
--9.81 z, penetration correction scaled to zero, previous-step warm start.  A step is one full pass of the hot path: contact detection (hull
-radii, cell list, pair search, narrow phase), colouring and colour-major
-ordering, accumulator init, 50 NBGS sweeps, integration.
+-9.81 z, penetration correction scaled to zero, previous-step warm start.  A
+step is one full pass of the hot path: contact detection (hull radii, cell
+list, pair search, narrow phase), colouring and ordering, accumulator init,
+50 NBGS sweeps, integration.  The sweeps visit the contacts in the block-local
+order (blocks of edge 6.5: every block's local contacts in one workgroup with
+its bodies in LDS, then the contacts between blocks by colour); --block-edge 0
+gives the (colour, key) order, which is also timed beside it.
 
 Printed JSON line (one, rank 0):
   value         contact updates per second over the timed steps (FP64 sweeps,
@@ -306,26 +310,29 @@ def _warm_run(nb, torch, g2, mlp, ws, cap, target, steps):
     return rec
 
 
-def cpu_baseline(sample_tiles: int, sweeps: int):
-    """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres)."""
+def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0):
+    """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres), in the sweep order
+    the GPU run uses."""
     import oracle
     import scenegen as sg
 
     sc = sg.dense_packing(tiles=sample_tiles)
-    w = oracle.World(sc.copy())
+    w = oracle.World(sc.copy()).set_block_order(block_edge)
     t0 = time.perf_counter()
     w.step(sweeps, grid=True, warm=False)
     t1 = time.perf_counter()
     v = w.view()
     upd = v["n_contacts"] * sweeps
     return dict(value=upd / (t1 - t0), unit="contact updates/s", cores=1, kind="oracle",
-                sample=f"1 step ({sweeps} FP64 sweeps, detection, colouring, integration) of a "
+                sample=f"1 step ({sweeps} FP64 sweeps" + (f" in the block-local order, edge {block_edge:g}"
+                                                           if block_edge > 0 else "")
+                       + ", detection, colouring, integration) of a "
                        f"{sample_tiles}x{sample_tiles}-tile cut of the packing: {sc.n} spheres, "
                        f"{v['n_contacts']} contacts, {t1 - t0:.1f} s on one host core",
                 seconds=t1 - t0), sc, w
 
 
-def errors_against_oracle(nb, torch, dev, sc, w, sweeps):
+def errors_against_oracle(nb, torch, dev, sc, w, sweeps, block_edge=0.0):
     """One GPU step from the scene the oracle stepped, with FP64 and with FP32 sweeps: contact lists compared bit for
     bit, impulses and velocities as the largest deviation relative to the largest magnitude of the oracle's."""
     import numpy as np
@@ -337,7 +344,7 @@ def errors_against_oracle(nb, torch, dev, sc, w, sweeps):
 
     out = {}
     for prec in ("fp64", "fp32"):
-        g = nb.GpuScene(sc.copy(), device=dev, precision=prec)
+        g = nb.GpuScene(sc.copy(), device=dev, precision=prec).set_block_order(block_edge)
         g.step(sweeps)
         c = g.contacts()
         st = g.state()
@@ -370,6 +377,9 @@ def main():
     ap.add_argument("--subdomain-edge", type=float, default=0.0,
                     help="time the subdomain NBGS (Alg. 1, blocks of this edge) instead of the colour-ordered one")
     ap.add_argument("--relax", type=float, default=None, help="relaxation (default: the scene's)")
+    ap.add_argument("--block-edge", type=float, default=6.5,
+                    help="sweep the plain NBGS in the block-local order with blocks of this edge (0: (colour, key) "
+                         "order)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (walled box, ensemble batch, dilute gas)")
     a = ap.parse_args()
@@ -413,7 +423,10 @@ def main():
     log(f"scene: {sc.n} spheres, box {sc.hi}")
     g = nb.GpuScene(sc.copy(), device=dev, precision=a.precision, warm_start="previous")
     if a.subdomain_edge > 0:
+        a.block_edge = 0.0
         g.set_subdomains(a.subdomain_edge)
+    elif a.block_edge > 0:
+        g.set_block_order(a.block_edge)
 
     # ---------------------------------------------------- fixed sweeps, FP64
     for i in range(a.warmup):
@@ -455,11 +468,15 @@ def main():
             per_launch_bytes = prof["sweep_bytes"] / prof["sweep_launches"]
             per_launch_ms = prof["sweep_kernel_ms"] / prof["sweep_launches"]
             achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-            traffic = measured_traffic(("subdomain_" if a.subdomain_edge > 0 else "") + a.precision)
+            traffic = measured_traffic(("subdomain_" if a.subdomain_edge > 0 else "block_" if a.block_edge > 0 else "")
+                                       + a.precision)
             tn = "double" if a.precision == "fp64" else "float"
             tu = g.tuning()
             if a.subdomain_edge > 0:
                 kernel_name = f"k_sub_pass<{tn}> + k_sub_reduce<{tn}>"
+            elif a.block_edge > 0:
+                kernel_name = (f"k_blk_pass<{tn}, 1> + k_sweep_grp<{tn}, {tu['block']}, "
+                               f"{str(bool(tu['nontemporal'])).lower()}> (one sweep)")
             elif tu["lane_groups"]:
                 kernel_name = f"k_sweep_grp<{tn}, {tu['block']}, {str(bool(tu['nontemporal'])).lower()}>"
             else:
@@ -497,6 +514,19 @@ def main():
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
         del src, dst
 
+    # the same steps in the (colour, key) order, for comparison with the block-local order
+    order_cmp = None
+    if a.block_edge > 0 and a.subdomain_edge <= 0 and not a.no_extras:
+        gc = nb.GpuScene(sc.copy(), device=dev, precision=a.precision, warm_start="previous")
+        gc.step(a.max_sweeps, a.target)
+        gc.step(a.sweeps)
+        gc.set_residual_history(False)
+        wall_c, cs_c = _timed_steps(nb, torch, gc, 5, a.sweeps)
+        order_cmp = {"steps": 5, "ms_per_step": wall_c / 5 * 1e3, "contact_updates_per_s": cs_c * a.sweeps / wall_c,
+                     "phase_ms_last_step": [round(float(x), 3) for x in gc.phase_times()]}
+        gc.close()
+        log(f"colour order: {order_cmp}")
+
     # ------------------------------------------------ to residual 1e-6 modes
     resid = {}
     if a.residual_steps > 0:
@@ -532,10 +562,10 @@ def main():
     cpu = None
     vs_oracle = None
     if a.cpu_tiles > 0:
-        cpu, osc, ow = cpu_baseline(a.cpu_tiles, a.sweeps)
+        cpu, osc, ow = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge)
         log(f"cpu baseline: {cpu}")
         # the same step on the GPU from the same state, FP64 and FP32 sweeps, against the oracle's result
-        vs_oracle = errors_against_oracle(nb, torch, dev, osc, ow, a.sweeps)
+        vs_oracle = errors_against_oracle(nb, torch, dev, osc, ow, a.sweeps, a.block_edge)
         log(f"against the oracle: {vs_oracle}")
         del ow
 
@@ -555,7 +585,8 @@ def main():
         "config": {"workload": f"dense settled packing, {sc.n} polydisperse spheres r~U[0.45,0.55], "
                                f"periodic 100x100 floor box, phi~0.6, mu=0.5, dt=1e-4, {a.sweeps} {a.precision.upper()} "
                                + (f"subdomain NBGS (blocks of edge {a.subdomain_edge:g}) " if a.subdomain_edge > 0
-                                  else "NBGS ")
+                                  else f"NBGS in the block-local order (blocks of edge {a.block_edge:g}) "
+                                  if a.block_edge > 0 else "NBGS in (colour, key) order ")
                                + f"sweeps/step, relaxation {sc.relax:g}, previous-step warm start",
                    "n_bodies": sc.n, "contacts_per_step": float(np.mean(contacts)),
                    "contacts_per_body": float(np.mean(contacts)) / sc.n, "colours": int(np.max(colours)),
@@ -567,6 +598,7 @@ def main():
         "learned_warm_start": learned,
         "other_workloads": extra,
         "subdomain_nbgs": sub,
+        "colour_order_same_workload": order_cmp,
         "roofline": roof,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
         "errors_against_oracle": vs_oracle,

@@ -218,6 +218,24 @@ nbgs_status nbgs_get_residuals(nbgs_scene_t scene, int32_t cap, double *hist, in
  * UNSUPPORTED for batches and with the learned warm start. */
 nbgs_status nbgs_set_subdomains(nbgs_scene_t scene, double edge);
 
+/* Sweep order of later steps: edge = 0 (default) the (colour, key) order;
+ * edge > 0 the block-local order of the same plain NBGS (Alg. 1 with one
+ * subdomain: every contact sees the newest impulses of all others, only the
+ * order in which the contacts are visited changes).  With the box cut into
+ * blocks as for nbgs_set_subdomains, a contact whose dynamic bodies lie in
+ * one block is local to it; a contact between dynamic bodies of two blocks
+ * is a cross contact.  A sweep takes every block's local contacts in
+ * (colour, key) order, blocks in ascending order (local contacts of different
+ * blocks share no dynamic body, so the blocks run as independent workgroups
+ * with their bodies' velocities held in LDS), then the cross contacts in
+ * (colour, key) order; each colouring covers one block's local contacts or
+ * the cross contacts.  The initial impulses are applied in the same order.
+ * CAPACITY at detection if a block holds too many bodies for the
+ * workgroup's local memory (about 960 in FP64, 1,900 in FP32): use a smaller
+ * edge.  INVALID_ARG while the subdomain solver is on; UNSUPPORTED for
+ * batches and with the learned warm start. */
+nbgs_status nbgs_set_block_order(nbgs_scene_t scene, double edge);
+
 /* enable = 1 (default): the residual R_k of every sweep is formed.  enable =
  * 0: a solve without a residual target forms only the last sweep's residual
  * (the one nbgs_stats reports); impulses and velocities are unchanged.  A
@@ -282,7 +300,8 @@ nbgs_status nbgs_get_tuning(nbgs_scene_t scene, int32_t precision, nbgs_tuning *
 /* Choose the sweep launch shape for the scene's precision by timing trial
  * solves of `sweeps` sweeps on the contacts of the current step (call after
  * nbgs_detect, before nbgs_solve): coordinate descent over the nbgs_tuning
- * fields from the current shape.  The trials leave no trace: the initial
+ * fields from the current shape (UNSUPPORTED with the subdomain solver or
+ * the block-local order).  The trials leave no trace: the initial
  * impulses are restored, and the solve that follows gives the same impulses
  * and velocities as without tuning.  cache_path [host, may be NULL]: a text
  * file of earlier choices, one line per (GPU architecture, precision,

@@ -92,6 +92,7 @@ _SIGNATURES = [
     ("nbgs_set_warm_start", C.c_int, [_vp, C.c_int64, _vp, _vp]),
     ("nbgs_set_residual_history", C.c_int, [_vp, C.c_int32]),
     ("nbgs_set_subdomains", C.c_int, [_vp, C.c_double]),
+    ("nbgs_set_block_order", C.c_int, [_vp, C.c_double]),
     ("nbgs_get_phase_times", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     ("nbgs_mlp_param_count", C.c_int32, []),
     ("nbgs_mlp_create", C.c_int, [C.c_uint64, _vp, C.POINTER(_vp)]),
@@ -221,6 +222,10 @@ def nbgs_set_warm_start(h: int, n: int, keys_ptr: int, impulse_ptr: int) -> None
 
 def nbgs_set_subdomains(h: int, edge: float) -> None:
     _check(lib().nbgs_set_subdomains(_vp(h), float(edge)))
+
+
+def nbgs_set_block_order(h: int, edge: float) -> None:
+    _check(lib().nbgs_set_block_order(_vp(h), float(edge)))
 
 
 def nbgs_set_residual_history(h: int, enable: bool) -> None:
@@ -558,6 +563,12 @@ class GpuScene:
     def set_subdomains(self, edge: float):
         """edge > 0: subdomain NBGS with blocks of about this edge from the next step on; 0: colour-order NBGS."""
         nbgs_set_subdomains(self.handle, edge)
+        return self
+
+    def set_block_order(self, edge: float):
+        """edge > 0: the plain NBGS swept in the block-local order (blocks of about this edge) from the next step
+        on; 0: (colour, key) order."""
+        nbgs_set_block_order(self.handle, edge)
         return self
 
     def set_warm_start(self, keys: np.ndarray, P: np.ndarray):

@@ -203,9 +203,9 @@ template <class T>
 nbgs_status gather_for_sweeps(nbgs_scene_t sc) {
     SweepBuf<T> &sw = sweep_buf<T>(sc);
     sw.per_contact_mu = sc->n_scenes > 1;
-    sw.sub = sc->sub_active;
+    sw.sub = sc->sub_active || sc->blk_active;
     NBGS_TRY(sw.reserve((size_t)sc->nc));
-    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), sc->spos.p, sc->sub_active ? sc->sdom.p : nullptr, sc->nc,
+    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), sc->spos.p, sw.sub ? sc->sdom.p : nullptr, sc->nc,
                                   sc->p.dt, sc->p.erp, sc->table(), sw.view(), sc->s);
 }
 
@@ -283,7 +283,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
                   (unsigned long long)total64);
         return NBGS_ERR_DEVICE;
     }
-    if (sc->sub_edge > 0.0 && 2 * nc > (int64_t)0x7fffff00) {
+    if ((sc->sub_edge > 0.0 || sc->blk_edge > 0.0) && 2 * nc > (int64_t)0x7fffff00) {
         set_error("%lld contacts: the subdomain solver indexes both ends of a contact in 32 bits (at most 2^30 "
                   "contacts)", (long long)nc);
         return NBGS_ERR_CAPACITY;
@@ -326,8 +326,10 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     record(sc, kColour);
     // subdomain solver: the colouring is restricted to the contacts of one subdomain
     sc->sub_active = sc->sub_edge > 0.0 && nc > 0;
+    sc->blk_active = !sc->sub_active && sc->blk_edge > 0.0 && nc > 0;
     if (sc->sub_active) NBGS_TRY(subdomain_assign(sc));
-    const int32_t *sdom = sc->sub_active ? sc->sdom.p : nullptr;
+    if (sc->blk_active) NBGS_TRY(block_assign(sc));
+    const int32_t *sdom = sc->sub_active || sc->blk_active ? sc->sdom.p : nullptr;
     // colouring: body -> contacts where it is j2 (as j1 it owns the segment off[i] .. off[i] + cnt[i])
     NBGS_TRY(sc->inc2.reserve((size_t)(nc > 0 ? nc : 1)));
     NBGS_TRY(sc->prio.reserve((size_t)(nc > 0 ? nc : 1)));
@@ -412,6 +414,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     sc->precision_used = sc->p.precision;
     NBGS_TRY(scene_gather(sc));
     if (sc->sub_active) NBGS_TRY(subdomain_prepare(sc));
+    if (sc->blk_active) NBGS_TRY(block_prepare(sc));
     sc->state = 1;
     sc->stats.n_contacts = nc;
     sc->stats.n_colours = sc->n_colours;
@@ -642,9 +645,12 @@ template nbgs_status scene_sweep_loop<float>(nbgs_scene_t, int32_t, double, cons
 
 namespace {
 
+constexpr int kSolveColour = 0, kSolveSubdomain = 1, kSolveBlock = 2;
+
 // Stop flag, sweep count and last residual after a solve; NUMERIC / NOT_CONVERGED as nbgs_solve reports them.
+// mode: which solver ran (the profile's byte count of the subdomain and block-local solvers is made here).
 template <class T>
-nbgs_status finish_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats, bool sub) {
+nbgs_status finish_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats, int mode) {
     hipStream_t s = sc->s;
     SweepBuf<T> &sw = sweep_buf<T>(sc);
     NBGS_TRY(launch_save_impulses<T>(sw.view(), sc->nc, sc->cb[sc->cur].view(), s));
@@ -663,17 +669,27 @@ nbgs_status finish_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbg
     sc->stats.sweeps = sweeps;
     sc->stats.residual = R;
     if (stats) *stats = sc->stats;
-    if (sub && sc->profiling) {
+    if (mode != kSolveColour && sc->profiling) {
         for (int32_t k = 0; k < sweeps && k < max_sweeps; ++k) {
             float ms = 0.0f;
             NBGS_HIP(hipEventElapsedTime(&ms, sc->pev[2 * k], sc->pev[2 * k + 1]));
             sc->prof.sweep_kernel_ms += ms;
         }
-        // compulsory bytes of a sweep: every contact record, every slot read (v', w', 1/m, 1/I) and its
-        // correction written and read back, every corrected body's v', w' read and written
         const double tb = (double)sizeof(T);
-        const double per_sweep = (2 * 4 + 12 * tb) * (double)sc->nc + 4 * 2 * (double)sc->nc +
-                                 (8 * tb + 6 * tb + 6 * tb) * (double)sc->n_slots + 12 * tb * (double)sc->b.n;
+        double per_sweep;
+        if (mode == kSolveSubdomain) {
+            // every contact record and its two slot indices, every slot read (v', w', 1/m, 1/I) and its
+            // correction written and read back, every corrected body's v', w' read and written
+            per_sweep = (2 * 4 + 12 * tb) * (double)sc->nc + 4 * 2 * (double)sc->nc +
+                        (8 * tb + 6 * tb + 6 * tb) * (double)sc->n_slots + 12 * tb * (double)sc->b.n;
+        } else {
+            // every contact record, the slot indices of the local contacts, every slot read and written once,
+            // every dynamic end of a contact between blocks read and written
+            double xd = 0.0;
+            for (int64_t d : sc->xdyn) xd += (double)d;
+            per_sweep = (2 * 4 + 12 * tb) * (double)sc->nc + 4 * 2 * (double)sc->blk_n_local +
+                        14 * tb * ((double)sc->blk_dyn_local + xd);
+        }
         sc->prof.sweep_launches += sweeps;
         sc->prof.contact_updates += (int64_t)sweeps * sc->nc;
         sc->prof.sweep_bytes += per_sweep * sweeps;
@@ -723,7 +739,68 @@ nbgs_status sub_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
             chunk = std::min(chunk * 2, 64);
         }
     }
-    return finish_solve<T>(sc, max_sweeps, target, stats, true);
+    return finish_solve<T>(sc, max_sweeps, target, stats, kSolveSubdomain);
+}
+
+// Block-local order: the initial impulses (the local part in the block pass,
+// then the contacts between blocks colour by colour), then per sweep the block
+// pass and the cross colours, and the residual over the blocks' and the cross
+// tiles' partial sums.  The sequence of contacts is that of the sweep record:
+// blocks in ascending id, each in (colour, key) order, then the cross
+// contacts in (colour, key) order.
+template <class T>
+nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_stats *stats) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    SweepBuf<T> &sw = sweep_buf<T>(sc);
+    DevBuf<T> &vel = vel_buf<T>(sc);
+    const SweepTune &tune = sc->tune[sc->precision_used == NBGS_FP32_SWEEP ? 1 : 0];
+    const int nx = (int)sc->xcol.size() - 1;
+    const int64_t tile = sweep_tile<T>(tune);
+    sc->xpart_off.assign((size_t)nx + 1, (int64_t)sc->n_blk);
+    for (int c = 0; c < nx; ++c) {
+        const int64_t m = sc->xcol[c + 1] - sc->xcol[c];
+        sc->xpart_off[c + 1] = sc->xpart_off[c] + (m + tile - 1) / tile;
+    }
+    const int64_t n_partials = sc->xpart_off[(size_t)nx];
+    if (n_partials > 0x7fffffff) {
+        set_error("too many partial sums");
+        return NBGS_ERR_CAPACITY;
+    }
+    NBGS_TRY(sc->partials.reserve(2 * (size_t)(n_partials > 0 ? n_partials : 1)));
+    NBGS_HIP(hipMemsetAsync(sc->ctrl(), 0, 4 * sizeof(int32_t), s));
+    sc->hist_partial = false;
+    sc->graph_pairs = 0;
+    if (sc->p.warm_start != NBGS_WS_ZERO) {
+        NBGS_TRY(block_pass<T>(sc, 0, vel.p));
+        for (int c = 0; c < nx; ++c)
+            NBGS_TRY(launch_warm_scatter<T>(sw.view(), sc->xcol[c], sc->xcol[c + 1], N, vel.p, s));
+    }
+    record(sc, kSweeps);
+    const bool prof = sc->profiling;
+    if (prof) NBGS_TRY(ensure_profile_events(sc, (size_t)max_sweeps));
+    const SweepParams sp{sc->p.mu, sc->p.relax};
+    int32_t launched = 0, chunk = target > 0.0 ? 4 : max_sweeps;
+    bool done = false;
+    while (launched < max_sweeps && !done) {
+        const int32_t k = std::min(chunk, max_sweeps - launched);
+        for (int32_t it = 0; it < k; ++it) {
+            if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it)], s));
+            NBGS_TRY(block_pass<T>(sc, 1, vel.p));
+            for (int c = 0; c < nx; ++c)
+                NBGS_TRY(launch_sweep_colour<T>(sw.view(), sc->xcol[c], sc->xcol[c + 1], N, vel.p, sp, tune,
+                                                sc->partials.p + 2 * sc->xpart_off[c], sc->ctrl(), s));
+            if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it) + 1], s));
+            NBGS_TRY(launch_residual(sc->partials.p, (int32_t)n_partials, target, sc->ctrl(), sc->res_hist.p, s));
+        }
+        launched += k;
+        if (target > 0.0 && launched < max_sweeps) {
+            NBGS_TRY(sync_small(sc, 8, 3));
+            done = sc->pinned[8] != 0;
+            chunk = std::min(chunk * 2, 64);
+        }
+    }
+    return finish_solve<T>(sc, max_sweeps, target, stats, kSolveBlock);
 }
 
 template <class T>
@@ -739,6 +816,7 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
     if (sc->p.warm_start == NBGS_WS_LEARNED && sc->have_learned) NBGS_TRY(judge_warm_start<T>(sc));
     NBGS_TRY(launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel.p, s));
     if (sc->sub_active) return sub_solve<T>(sc, max_sweeps, target, stats);
+    if (sc->blk_active) return blk_solve<T>(sc, max_sweeps, target, stats);
     if (sc->p.warm_start != NBGS_WS_ZERO)
         for (int c = 0; c < sc->n_colours; ++c)
             NBGS_TRY(launch_warm_scatter<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, s));
@@ -1133,6 +1211,10 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t sc, const nbgs_params *params) {
         set_error("the subdomain solver does not combine with the learned warm start");
         return NBGS_ERR_UNSUPPORTED;
     }
+    if (sc->blk_edge > 0.0 && params->warm_start == NBGS_WS_LEARNED) {
+        set_error("the block-local order does not combine with the learned warm start");
+        return NBGS_ERR_UNSUPPORTED;
+    }
     sc->p = *params;
     update_scales(sc);
     return NBGS_OK;
@@ -1263,7 +1345,34 @@ nbgs_status nbgs_set_subdomains(nbgs_scene_t sc, double edge) {
         set_error("the subdomain solver does not combine with the learned warm start");
         return NBGS_ERR_UNSUPPORTED;
     }
+    if (edge > 0.0 && sc->blk_edge > 0.0) {
+        set_error("the block-local order is set: switch it off first");
+        return NBGS_ERR_INVALID_ARG;
+    }
     sc->sub_edge = edge;
+    sc->state = 0;  // the next step starts with a detection
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_set_block_order(nbgs_scene_t sc, double edge) {
+    NBGS_GUARD(sc);
+    if (!(edge >= 0.0) || !std::isfinite(edge)) {
+        set_error("the block edge must be finite and >= 0");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (edge > 0.0 && sc->n_scenes > 1) {
+        set_error("the block-local order is not available for batched scenes");
+        return NBGS_ERR_UNSUPPORTED;
+    }
+    if (edge > 0.0 && sc->p.warm_start == NBGS_WS_LEARNED) {
+        set_error("the block-local order does not combine with the learned warm start");
+        return NBGS_ERR_UNSUPPORTED;
+    }
+    if (edge > 0.0 && sc->sub_edge > 0.0) {
+        set_error("the subdomain solver is set: switch it off first");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    sc->blk_edge = edge;
     sc->state = 0;  // the next step starts with a detection
     return NBGS_OK;
 }

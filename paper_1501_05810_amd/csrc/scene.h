@@ -212,6 +212,20 @@ struct nbgs_scene_s {
     const uint32_t *body_slots = nullptr;
     DevBuf<double> corr64;
     DevBuf<float> corr32;
+    // block-local sweep order of the plain NBGS, off when blk_edge == 0: the
+    // ids of the contacts are their blocks (local) or n_blk (between blocks);
+    // the tables above then describe the local part, the cross part is swept
+    // colour by colour over xcol[c] .. xcol[c + 1] of the sweep record
+    double blk_edge = 0.0;
+    bool blk_active = false;
+    int32_t n_blk = 0;
+    std::vector<int64_t> xcol;       // positions of the cross colours' ranges (size colours + 1)
+    std::vector<int64_t> xdyn;       // dynamic contact ends per cross colour
+    std::vector<int64_t> xpart_off;  // first partial of every cross colour, after the n_blk block partials
+    int64_t blk_dyn_local = 0;       // slots of the local part (each read and written once per sweep)
+    int64_t blk_n_local = 0;         // contacts of the local part
+    DevBuf<int64_t> xcol_d;
+    DevBuf<int32_t> xncol_d;
     // sweep-tuning cache file (empty: none)
     std::string tune_cache;
     bool tuned[2] = {false, false};
@@ -258,6 +272,14 @@ nbgs_status subdomain_assign(nbgs_scene_t sc);
 nbgs_status subdomain_prepare(nbgs_scene_t sc);
 template <class T>
 nbgs_status subdomain_pass(nbgs_scene_t sc, int mode, T *vel, T *corr);
+// Block-local order: ids of the contacts (before colouring), then the local
+// tables and the cross colours' ranges (after the gather), and the pass over
+// the local part (mode 0: initial impulses, 1: relaxation), each block's
+// velocities updated in place in LDS.
+nbgs_status block_assign(nbgs_scene_t sc);
+nbgs_status block_prepare(nbgs_scene_t sc);
+template <class T>
+nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel);
 template <class T>
 nbgs_status scene_sweep_loop(nbgs_scene_t sc, int32_t max_sweeps, double target, const SweepTune &tune);
 

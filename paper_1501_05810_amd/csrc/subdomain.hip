@@ -22,6 +22,7 @@
 // ascending subdomain.
 #include <algorithm>
 
+#include "contact_math.h"
 #include "scene.h"
 
 namespace nbgs {
@@ -38,11 +39,8 @@ struct Blocks {
     int32_t nb[3];
 };
 
-__global__ void __launch_bounds__(kBlock) k_subdomain(BodiesView b, const int32_t *j1, int64_t nc, Blocks bl,
-                                                      int32_t *sdom) {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= nc) return;
-    const int i = j1[j];
+// Block holding the centre of body i (coordinates clamped into the box).
+__device__ inline int32_t block_of(const BodiesView &b, const Blocks &bl, int i) {
     const double x[3] = {b.x[i], b.y[i], b.z[i]};
     int64_t c[3];
 #pragma unroll
@@ -51,7 +49,31 @@ __global__ void __launch_bounds__(kBlock) k_subdomain(BodiesView b, const int32_
         f = fmax(0.0, fmin(f, (double)(bl.nb[a] - 1)));
         c[a] = (int64_t)f;
     }
-    sdom[j] = (int32_t)((c[2] * bl.nb[1] + c[1]) * bl.nb[0] + c[0]);
+    return (int32_t)((c[2] * bl.nb[1] + c[1]) * bl.nb[0] + c[0]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_subdomain(BodiesView b, const int32_t *j1, int64_t nc, Blocks bl,
+                                                      int32_t *sdom) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    sdom[j] = block_of(b, bl, j1[j]);
+}
+
+// Block-local id: the block of the contact's dynamic bodies if they share one,
+// else nblocks (a contact between blocks).
+__global__ void __launch_bounds__(kBlock) k_block_local(BodiesView b, const int32_t *j1, const int32_t *j2,
+                                                        int64_t nc, Blocks bl, int32_t nblocks, int32_t *id) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    const int i1 = j1[j], i2 = j2[j];
+    const bool d1 = b.inv_mass[i1] > 0.0;
+    const bool d2 = i2 < b.n && b.inv_mass[i2] > 0.0;
+    if (d1 && d2) {
+        const int32_t k1 = block_of(b, bl, i1), k2 = block_of(b, bl, i2);
+        id[j] = k1 == k2 ? k1 : nblocks;
+    } else {
+        id[j] = block_of(b, bl, d1 ? i1 : i2);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_hist(const int32_t *v, int64_t n, int32_t *cnt) {
@@ -128,6 +150,83 @@ __global__ void __launch_bounds__(kBlock) k_end_slots(const uint32_t *vals, int6
     const uint32_t e = vals[i];
     const int32_t b = end_body(sj1, sj2, nb, inv_mass, e);
     ls[e] = b < nb ? ex[i] + flags[i] - 1 - tile_slot_off[ssd[e >> 1]] : -1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill64(int64_t *p, int64_t n, int64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// first[k] = first position of the run of key k in the sorted keys (untouched for absent keys)
+__global__ void __launch_bounds__(kBlock) k_first_of_runs(const int32_t *key, int64_t n, int64_t *first) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    if (p == 0 || key[p - 1] != key[p]) first[key[p]] = p;
+}
+__global__ void __launch_bounds__(kBlock) k_first_of_runs32(const uint32_t *key, int64_t n, int32_t *first) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    if (p == 0 || key[p - 1] != key[p]) first[key[p]] = (int32_t)p;
+}
+
+// Sort keys of the bodies: the block of a dynamic body, nblocks for a static one.
+__global__ void __launch_bounds__(kBlock) k_body_blocks(BodiesView b, Blocks bl, int32_t nblocks, uint32_t *keys,
+                                                        uint32_t *vals) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= b.n) return;
+    keys[i] = (uint32_t)(b.inv_mass[i] > 0.0 ? block_of(b, bl, i) : nblocks);
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(kBlock) k_slot_of(const uint32_t *sorted_body, int32_t n, int32_t *slot) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) slot[sorted_body[p]] = p;
+}
+
+// Slot (local to the contact's block) of both ends of a local contact; -1 for
+// a wall, a static body and every end of a contact between blocks.
+__global__ void __launch_bounds__(kBlock) k_block_ends(const int32_t *sj1, const int32_t *sj2, const int32_t *ssd,
+                                                       int64_t nc, int32_t nblocks, int32_t nb,
+                                                       const double *inv_mass, const int32_t *slot,
+                                                       const int32_t *first_slot, int32_t *ls) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nc) return;
+    const int32_t id = ssd[p];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int32_t b = k ? sj2[p] : sj1[p];
+        ls[2 * p + k] = (id < nblocks && b < nb && inv_mass[b] > 0.0) ? slot[b] - first_slot[id] : -1;
+    }
+}
+
+// Colour ranges of positions begin .. end of the sweep record (sorted by
+// colour): cstart[c] = first position of colour c, *ncol = last colour + 1;
+// cstart must hold end in every entry beforehand.
+__global__ void __launch_bounds__(kBlock) k_range_colours(const int32_t *col, int64_t begin, int64_t end,
+                                                          int64_t *cstart, int32_t *ncol) {
+    const int64_t p = begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= end) return;
+    const int c = col[p];
+    if (p == begin || col[p - 1] != c) cstart[c] = p;
+    if (p == end - 1) *ncol = c + 1;
+}
+
+// Dynamic contact ends per colour over positions begin .. end.
+__global__ void __launch_bounds__(kBlock) k_range_dyn(const int32_t *sj1, const int32_t *sj2, const int32_t *col,
+                                                      int64_t begin, int64_t end, int32_t nb, const double *inv_mass,
+                                                      unsigned long long *cnt) {
+    __shared__ unsigned int h[kMaxCol];
+    for (int c = threadIdx.x; c < kMaxCol; c += kBlock) h[c] = 0u;
+    __syncthreads();
+    const int64_t p = begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < end) {
+        const int32_t b1 = sj1[p], b2 = sj2[p];
+        const unsigned d = (inv_mass[b1] > 0.0 ? 1u : 0u) + ((b2 < nb && inv_mass[b2] > 0.0) ? 1u : 0u);
+        if (d) atomicAdd(&h[col[p]], d);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kMaxCol; c += kBlock)
+        if (h[c]) atomicAdd(&cnt[c], (unsigned long long)h[c]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_iota(uint32_t *v, int64_t n) {
@@ -363,32 +462,322 @@ __global__ void __launch_bounds__(kBlock) k_sub_reduce(T *vel, int32_t nb, const
     for (int a = 0; a < 6; ++a) r[a] = v[a];
 }
 
+
+// Block-local order, local part: one workgroup per block.  Its slots (the
+// dynamic bodies of its local contacts, all inside the block and touched by
+// no other block's local contact) are copied into LDS, the local contacts are
+// taken colour by colour (no two contacts of a colour share a slot), each
+// reading and updating the slot records in place -- the sequential
+// Gauss-Seidel order of the block -- and the slots are written back.  mode 0
+// applies the initial impulses in the same order, mode 1 relaxes (relax_contact,
+// the arithmetic of every sweep kernel) and writes the impulses and the block's
+// residual sums.  A static partner's record is read from the accumulators (it
+// never changes), a wall is zero.
+constexpr int kBlkThreads = 128;
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t nb, T *vel, T mu, T relax,
+                                                          const int64_t *tile_off, const int32_t *tile_slot_off,
+                                                          const int32_t *slot_body, double *partials,
+                                                          const int32_t *ctrl) {
+    if (MODE == 1 && ctrl[0]) return;  // an earlier sweep met the target (uniform over the grid)
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int s = blockIdx.x;
+    const int64_t c0 = tile_off[s], c1 = tile_off[s + 1];
+    const int s0 = tile_slot_off[s], ns = tile_slot_off[s + 1] - s0;
+    T *Vs = reinterpret_cast<T *>(smem);  // [8][ns]: v'x v'y v'z w'x w'y w'z 1/m 1/I
+    __shared__ int64_t cstart[kMaxCol + 1];
+    __shared__ int ncol;
+    for (int i = threadIdx.x; i < ns; i += kBlkThreads) {
+        const T *r = vel + 8 * (int64_t)slot_body[s0 + i];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) Vs[a * ns + i] = r[a];
+    }
+    for (int c = threadIdx.x; c <= kMaxCol; c += kBlkThreads) cstart[c] = c1;
+    if (threadIdx.x == 0) ncol = 0;
+    __syncthreads();
+    for (int64_t p = c0 + threadIdx.x; p < c1; p += kBlkThreads) {
+        const int cp = sv.col[p];
+        if (p == c0 || sv.col[p - 1] != cp) cstart[cp] = p;
+        if (p == c1 - 1) ncol = cp + 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)  // empty colours start where the next one does
+        for (int c = ncol - 1; c >= 0; --c)
+            if (cstart[c] == c1 && c + 1 <= kMaxCol) cstart[c] = cstart[c + 1];
+    __syncthreads();
+    double sd = 0.0, sp = 0.0;
+    for (int c = 0; c < ncol; ++c) {
+        const int64_t pa = cstart[c], pb = c + 1 < ncol ? cstart[c + 1] : c1;
+        for (int64_t p = pa + threadIdx.x; p < pb; p += kBlkThreads) {
+            const int l1 = sv.ls[2 * p], l2 = sv.ls[2 * p + 1];
+            const int b1 = sv.j1[p], b2 = sv.j2[p];
+            const T n[3] = {sv.nx[p], sv.ny[p], sv.nz[p]};
+            const T a1 = sv.a1[p], a2 = sv.a2[p];
+            const T P[3] = {sv.px[p], sv.py[p], sv.pz[p]};
+            if (MODE == 0 && P[0] == T(0) && P[1] == T(0) && P[2] == T(0)) continue;
+            Rec<T> r1, r2;
+            if (l1 >= 0) {
+                r1.v[0] = Vs[0 * ns + l1];
+                r1.v[1] = Vs[1 * ns + l1];
+                r1.v[2] = Vs[2 * ns + l1];
+                r1.w[0] = Vs[3 * ns + l1];
+                r1.w[1] = Vs[4 * ns + l1];
+                r1.w[2] = Vs[5 * ns + l1];
+                r1.im = Vs[6 * ns + l1];
+                r1.ii = Vs[7 * ns + l1];
+            } else {
+                const T *r = vel + 8 * (int64_t)b1;
+                r1.v[0] = r[0];
+                r1.v[1] = r[1];
+                r1.v[2] = r[2];
+                r1.w[0] = r[3];
+                r1.w[1] = r[4];
+                r1.w[2] = r[5];
+                r1.im = r[6];
+                r1.ii = r[7];
+            }
+            if (l2 >= 0) {
+                r2.v[0] = Vs[0 * ns + l2];
+                r2.v[1] = Vs[1 * ns + l2];
+                r2.v[2] = Vs[2 * ns + l2];
+                r2.w[0] = Vs[3 * ns + l2];
+                r2.w[1] = Vs[4 * ns + l2];
+                r2.w[2] = Vs[5 * ns + l2];
+                r2.im = Vs[6 * ns + l2];
+                r2.ii = Vs[7 * ns + l2];
+            } else if (b2 < nb) {
+                const T *r = vel + 8 * (int64_t)b2;
+                r2.v[0] = r[0];
+                r2.v[1] = r[1];
+                r2.v[2] = r[2];
+                r2.w[0] = r[3];
+                r2.w[1] = r[4];
+                r2.w[2] = r[5];
+                r2.im = r[6];
+                r2.ii = r[7];
+            } else {
+                r2 = zero_rec<T>();
+            }
+            if (MODE == 0) {
+                apply(r1, r2, n, a1, a2, P);
+            } else {
+                T Pnew[3], dP[3];
+                relax_contact(n, sv.bias[p], a1, a2, P, mu, relax, r1, r2, Pnew, dP);
+                sv.px[p] = Pnew[0];
+                sv.py[p] = Pnew[1];
+                sv.pz[p] = Pnew[2];
+                const double d0 = dP[0], d1 = dP[1], d2 = dP[2];
+                const double q0 = Pnew[0], q1 = Pnew[1], q2 = Pnew[2];
+                sd += d0 * d0 + d1 * d1 + d2 * d2;
+                sp += q0 * q0 + q1 * q1 + q2 * q2;
+            }
+            if (l1 >= 0 && r1.im > T(0)) {
+                Vs[0 * ns + l1] = r1.v[0];
+                Vs[1 * ns + l1] = r1.v[1];
+                Vs[2 * ns + l1] = r1.v[2];
+                Vs[3 * ns + l1] = r1.w[0];
+                Vs[4 * ns + l1] = r1.w[1];
+                Vs[5 * ns + l1] = r1.w[2];
+            }
+            if (l2 >= 0 && r2.im > T(0)) {
+                Vs[0 * ns + l2] = r2.v[0];
+                Vs[1 * ns + l2] = r2.v[1];
+                Vs[2 * ns + l2] = r2.v[2];
+                Vs[3 * ns + l2] = r2.w[0];
+                Vs[4 * ns + l2] = r2.w[1];
+                Vs[5 * ns + l2] = r2.w[2];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < ns; i += kBlkThreads) {
+        T *r = vel + 8 * (int64_t)slot_body[s0 + i];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) r[a] = Vs[a * ns + i];
+    }
+    if (MODE == 1) {
+        __shared__ double red[2][kBlkThreads / 64];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sd += __shfl_xor(sd, o, 64);
+            sp += __shfl_xor(sp, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = sd;
+            red[1][threadIdx.x >> 6] = sp;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0, c = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlkThreads / 64; ++w) {
+                a += red[0][w];
+                c += red[1][w];
+            }
+            partials[2 * s + 0] = a;
+            partials[2 * s + 1] = c;
+        }
+    }
+}
+
 }  // namespace
+
+// The box cut into max(1, floor(L_a / edge)) blocks of edge L_a / that count per axis.
+static nbgs_status make_blocks(nbgs_scene_t sc, double edge, Blocks &bl, int64_t &nblocks) {
+    nblocks = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double L = sc->hi[a] - sc->lo[a];
+        double c = std::floor(L / edge);
+        if (!(c >= 1.0)) c = 1.0;
+        if (c > 4096.0) {
+            set_error("%g blocks along an axis are too many: use a larger edge", c);
+            return NBGS_ERR_INVALID_ARG;
+        }
+        bl.lo[a] = sc->lo[a];
+        bl.nb[a] = (int32_t)c;
+        bl.e[a] = L / c;
+        nblocks *= (int64_t)c;
+    }
+    if (nblocks > (1 << 23) - 1) {
+        set_error("%lld blocks are too many: use a larger edge", (long long)nblocks);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    return NBGS_OK;
+}
 
 // Subdomains of the contacts and, when the colouring is done, the tile and slot tables.
 nbgs_status subdomain_assign(nbgs_scene_t sc) {
     hipStream_t s = sc->s;
     Blocks bl;
     int64_t nsub = 1;
-    for (int a = 0; a < 3; ++a) {
-        const double L = sc->hi[a] - sc->lo[a];
-        double c = std::floor(L / sc->sub_edge);
-        if (!(c >= 1.0)) c = 1.0;
-        if (c > 4096.0) c = 4096.0;
-        bl.lo[a] = sc->lo[a];
-        bl.nb[a] = (int32_t)c;
-        bl.e[a] = L / c;
-        nsub *= (int64_t)c;
-    }
-    if (nsub > (1 << 23)) {
-        set_error("%lld subdomains are too many: use a larger edge", (long long)nsub);
-        return NBGS_ERR_INVALID_ARG;
-    }
+    NBGS_TRY(make_blocks(sc, sc->sub_edge, bl, nsub));
     sc->n_sub = (int32_t)nsub;
     const int64_t nc = sc->nc;
     NBGS_TRY(sc->sdom.reserve((size_t)nc + 1));
     k_subdomain<<<grid_for(nc), kBlock, 0, s>>>(sc->b, sc->cb[sc->cur].j1.p, nc, bl, sc->sdom.p);
     NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+// Block-local ids of the contacts: ids 0 .. n_blk - 1 local, n_blk between blocks.
+nbgs_status block_assign(nbgs_scene_t sc) {
+    hipStream_t s = sc->s;
+    Blocks bl;
+    int64_t nblocks = 1;
+    NBGS_TRY(make_blocks(sc, sc->blk_edge, bl, nblocks));
+    sc->n_blk = (int32_t)nblocks;
+    sc->n_sub = (int32_t)nblocks + 1;
+    const int64_t nc = sc->nc;
+    NBGS_TRY(sc->sdom.reserve((size_t)nc + 1));
+    const ContactsView c = sc->cb[sc->cur].view();
+    k_block_local<<<grid_for(nc), kBlock, 0, s>>>(sc->b, c.j1, c.j2, nc, bl, (int32_t)nblocks, sc->sdom.p);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+// Block-local order, per step: contact ranges of the ids (the sweep record
+// is sorted by id), the slots -- every dynamic body of a block, bodies sorted
+// by block (index order inside a block) -- and each local contact end's slot,
+// the LDS limit, and the colour ranges and dynamic ends of the contacts
+// between blocks.
+template <class T>
+static nbgs_status block_prepare_impl(nbgs_scene_t sc) {
+    hipStream_t s = sc->s;
+    const int64_t nc = sc->nc;
+    const int32_t N = sc->b.n;
+    const int32_t nsub = sc->n_sub, nblk = sc->n_blk;
+    SweepBuf<T> &sw = sc->precision_used == NBGS_FP32_SWEEP ? *reinterpret_cast<SweepBuf<T> *>(&sc->sw32)
+                                                            : *reinterpret_cast<SweepBuf<T> *>(&sc->sw64);
+    const int32_t *ssd = sw.sdom.p;
+    // first sweep position of every id
+    NBGS_TRY(sc->tile_off.reserve((size_t)nsub + 1));
+    k_fill64<<<grid_for((int64_t)nsub + 1), kBlock, 0, s>>>(sc->tile_off.p, (int64_t)nsub + 1, -1);
+    k_first_of_runs<<<grid_for(nc), kBlock, 0, s>>>(ssd, nc, sc->tile_off.p);
+    NBGS_HIP(hipGetLastError());
+    // bodies sorted by block (static bodies last), the slot of every body, the first slot of every block
+    Blocks bl;
+    int64_t nblocks = 1;
+    NBGS_TRY(make_blocks(sc, sc->blk_edge, bl, nblocks));
+    for (DevBuf<uint32_t> *b : {&sc->bkeys, &sc->bvals, &sc->bkeys2, &sc->bvals2}) NBGS_TRY(b->reserve((size_t)N + 1));
+    NBGS_TRY(sc->body_cnt.reserve((size_t)N + 1));  // the slot of every body
+    NBGS_TRY(sc->tile_slot_off.reserve((size_t)nblk + 2));
+    k_body_blocks<<<grid_for(N), kBlock, 0, s>>>(sc->b, bl, nblk, sc->bkeys.p, sc->bvals.p);
+    NBGS_HIP(hipGetLastError());
+    if ((size_t)radix_hist_entries(N) > sc->radix_hist.cap) NBGS_TRY(sc->radix_hist.reserve(radix_hist_entries(N)));
+    const size_t need_tmp = exclusive_scan_tmp_bytes((int64_t)radix_hist_entries(N));
+    if (need_tmp > sc->scan_tmp.cap) NBGS_TRY(sc->scan_tmp.reserve(need_tmp));
+    int bits = 1;
+    while (((int64_t)1 << bits) < (int64_t)nblk + 1) ++bits;
+    bool alt = false;
+    NBGS_TRY(radix_sort_pairs(sc->bkeys.p, sc->bvals.p, sc->bkeys2.p, sc->bvals2.p, N, bits, sc->radix_hist.p,
+                              sc->scan_tmp.p, sc->scan_tmp.cap, &alt, s));
+    const uint32_t *skeys = alt ? sc->bkeys2.p : sc->bkeys.p;
+    const uint32_t *sbody = alt ? sc->bvals2.p : sc->bvals.p;
+    if (N == 1) {
+        skeys = sc->bkeys.p;
+        sbody = sc->bvals.p;
+    }
+    sc->body_slots = sbody;
+    k_slot_of<<<grid_for(N), kBlock, 0, s>>>(sbody, N, sc->body_cnt.p);
+    k_fill<<<grid_for((int64_t)nblk + 2), kBlock, 0, s>>>(sc->tile_slot_off.p, (int64_t)nblk + 2, -1);
+    k_first_of_runs32<<<grid_for(N), kBlock, 0, s>>>(skeys, N, sc->tile_slot_off.p);
+    NBGS_HIP(hipGetLastError());
+    // empty ids and blocks start where the next one does (host, small tables)
+    std::vector<int64_t> toff((size_t)nsub + 1);
+    std::vector<int32_t> soff((size_t)nblk + 2);
+    NBGS_HIP(hipMemcpyAsync(toff.data(), sc->tile_off.p, sizeof(int64_t) * (nsub + 1), hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipMemcpyAsync(soff.data(), sc->tile_slot_off.p, sizeof(int32_t) * (nblk + 2), hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipStreamSynchronize(s));
+    toff[(size_t)nsub] = nc;
+    for (int32_t t = nsub - 1; t >= 0; --t)
+        if (toff[(size_t)t] < 0) toff[(size_t)t] = toff[(size_t)t + 1];
+    soff[(size_t)nblk + 1] = N;
+    for (int32_t t = nblk; t >= 0; --t)
+        if (soff[(size_t)t] < 0) soff[(size_t)t] = soff[(size_t)t + 1];
+    int32_t max_slots = 0;
+    for (int32_t t = 0; t < nblk; ++t) max_slots = std::max(max_slots, soff[(size_t)t + 1] - soff[(size_t)t]);
+    const size_t lds = (size_t)max_slots * 8 * sizeof(T);
+    if (lds > 60 * 1024) {
+        set_error("a block holds %d bodies (%zu bytes of LDS); use a smaller block edge", max_slots, lds);
+        return NBGS_ERR_CAPACITY;
+    }
+    sc->max_slots = max_slots;
+    sc->n_slots = soff[(size_t)nblk];
+    NBGS_HIP(hipMemcpyAsync(sc->tile_off.p, toff.data(), sizeof(int64_t) * (nsub + 1), hipMemcpyHostToDevice, s));
+    NBGS_HIP(hipMemcpyAsync(sc->tile_slot_off.p, soff.data(), sizeof(int32_t) * (nblk + 2), hipMemcpyHostToDevice, s));
+    // slot of every local contact end
+    NBGS_TRY(sw.ls.reserve(2 * (size_t)nc + 1));
+    k_block_ends<<<grid_for(nc), kBlock, 0, s>>>(sw.j1.p, sw.j2.p, ssd, nc, nblk, N, sc->b.inv_mass, sc->body_cnt.p,
+                                                  sc->tile_slot_off.p, sw.ls.p);
+    NBGS_HIP(hipGetLastError());
+    // colours of the contacts between blocks (the last id's range)
+    const int64_t xb = toff[(size_t)nblk], xe = toff[(size_t)nsub];
+    NBGS_TRY(sc->xcol_d.reserve(kMaxCol + 1 + kMaxCol));
+    NBGS_TRY(sc->xncol_d.reserve(1));
+    std::vector<int64_t> init((size_t)kMaxCol + 1, xe);
+    NBGS_HIP(hipMemcpyAsync(sc->xcol_d.p, init.data(), sizeof(int64_t) * (kMaxCol + 1), hipMemcpyHostToDevice, s));
+    NBGS_HIP(hipMemsetAsync(sc->xcol_d.p + kMaxCol + 1, 0, sizeof(int64_t) * kMaxCol, s));
+    NBGS_HIP(hipMemsetAsync(sc->xncol_d.p, 0, sizeof(int32_t), s));
+    if (xe > xb) {
+        const unsigned g = grid_for(xe - xb);
+        k_range_colours<<<g, kBlock, 0, s>>>(sw.col.p, xb, xe, sc->xcol_d.p, sc->xncol_d.p);
+        k_range_dyn<<<g, kBlock, 0, s>>>(sw.j1.p, sw.j2.p, sw.col.p, xb, xe, N, sc->b.inv_mass,
+                                          reinterpret_cast<unsigned long long *>(sc->xcol_d.p + kMaxCol + 1));
+        NBGS_HIP(hipGetLastError());
+    }
+    std::vector<int64_t> xc((size_t)2 * kMaxCol + 1);
+    int32_t ncol = 0;
+    NBGS_HIP(hipMemcpyAsync(xc.data(), sc->xcol_d.p, sizeof(int64_t) * (2 * kMaxCol + 1), hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipMemcpyAsync(&ncol, sc->xncol_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipStreamSynchronize(s));  // the host vectors above are temporaries
+    for (int c = ncol - 1; c >= 0; --c)  // empty colours start where the next one does
+        if (xc[(size_t)c] == xe) xc[(size_t)c] = c + 1 < ncol ? xc[(size_t)c + 1] : xe;
+    sc->xcol.assign(xc.begin(), xc.begin() + ncol);
+    sc->xcol.push_back(xe);
+    sc->xdyn.assign(xc.begin() + kMaxCol + 1, xc.begin() + kMaxCol + 1 + ncol);
+    sc->blk_dyn_local = sc->n_slots;
+    sc->blk_n_local = xb;
     return NBGS_OK;
 }
 
@@ -507,6 +896,48 @@ nbgs_status subdomain_prepare(nbgs_scene_t sc) {
     if (sc->precision_used == NBGS_FP32_SWEEP) return prepare_impl<float>(sc);
     return prepare_impl<double>(sc);
 }
+
+nbgs_status block_prepare(nbgs_scene_t sc) {
+    if (sc->precision_used == NBGS_FP32_SWEEP) return block_prepare_impl<float>(sc);
+    return block_prepare_impl<double>(sc);
+}
+
+template <class T>
+nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
+    if (sc->n_blk <= 0) return NBGS_OK;
+    hipStream_t s = sc->s;
+    SweepBuf<T> &sw = sc->precision_used == NBGS_FP32_SWEEP ? *reinterpret_cast<SweepBuf<T> *>(&sc->sw32)
+                                                            : *reinterpret_cast<SweepBuf<T> *>(&sc->sw64);
+    SubView<T> v;
+    v.j1 = sw.j1.p;
+    v.j2 = sw.j2.p;
+    v.ls = sw.ls.p;
+    v.col = sw.col.p;
+    v.nx = sw.nx.p;
+    v.ny = sw.ny.p;
+    v.nz = sw.nz.p;
+    v.bias = sw.bias.p;
+    v.a1 = sw.a1.p;
+    v.a2 = sw.a2.p;
+    v.px = sw.px.p;
+    v.py = sw.py.p;
+    v.pz = sw.pz.p;
+    const size_t lds = (size_t)std::max(sc->max_slots, 1) * 8 * sizeof(T);
+    const unsigned grid = (unsigned)sc->n_blk;
+    const T mu = (T)sc->p.mu, relax = (T)sc->p.relax;
+    const int32_t *slot_body = reinterpret_cast<const int32_t *>(sc->body_slots);  // bodies sorted by block
+    if (mode == 0)
+        k_blk_pass<T, 0><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
+                                                         sc->tile_slot_off.p, slot_body, sc->partials.p, sc->ctrl());
+    else
+        k_blk_pass<T, 1><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
+                                                         sc->tile_slot_off.p, slot_body, sc->partials.p, sc->ctrl());
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template nbgs_status block_pass<double>(nbgs_scene_t, int, double *);
+template nbgs_status block_pass<float>(nbgs_scene_t, int, float *);
 
 template <class T>
 nbgs_status subdomain_pass(nbgs_scene_t sc, int mode, T *vel, T *corr) {

@@ -2,7 +2,7 @@
 //
 // The launch shape of the sweep (workgroup size, contacts per thread, XCD
 // tile remap, non-temporal contact stream, whole-record stores, persistent
-// workgroups, graph replay) changes no result, only the time.  The tuner
+// workgroups, graph replay, lane groups) changes no result, only the time.  The tuner
 // times trial solves on the scene's own contacts of the current step and
 // keeps the fastest shape.  A trial changes the sweep record, the body
 // accumulators and the canonical impulses; the initial impulses are saved
@@ -132,6 +132,11 @@ nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen,
     if (sweeps < 1) {
         set_error("sweeps must be >= 1");
         return NBGS_ERR_INVALID_ARG;
+    }
+    if (sc->sub_active || sc->blk_active) {
+        set_error("autotuning times the colour-ordered sweep; the subdomain solver and the block-local order "
+                  "are not tuned");
+        return NBGS_ERR_UNSUPPORTED;
     }
     const int prec = sc->precision_used == NBGS_FP32_SWEEP ? 1 : 0;
     const std::string key = cache_key(sc);

@@ -1,0 +1,141 @@
+"""The block-local sweep order of the plain NBGS through the C ABI, against the oracle's block-local order.
+
+Ids, restricted colouring and the (id, colour, key) order are integer work and compared bit for bit; FP64 impulses,
+velocities and states are compared bit for bit as well (every contact is relaxed by the same arithmetic in the same
+sequence: a block's local contacts in its workgroup with the velocities in LDS, the contacts between blocks in the
+colour launches); the residual's partial sums are grouped per block and per tile, so only its rounding may differ.
+In its two limits the order is the classic one, so the GPU result must equal the GPU's classic sweep bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _nb():
+    import paper_1501_05810_amd as nb
+
+    return nb
+
+
+CASES = {
+    "walled block": (lambda: sg.packed_cluster(61, counts=(12, 10, 8)), 2.5, 1.0),
+    "periodic block, relaxed": (lambda: sg.packed_cluster(62, counts=(10, 10, 6), periodic=(True, True, False)),
+                                3.0, 0.75),
+    "static bodies": (lambda: _with_static(sg.packed_cluster(63, counts=(10, 8, 6))), 2.0, 1.0),
+    "dense tile": (lambda: sg.dense_packing(tiles=1), 5.0, 1.0),
+    "hcp ramp": (lambda: sg.hcp_ramp(8, 8, 4), 2.0e-3, 0.75),
+}
+
+
+def _with_static(sc):
+    # the bottom layer held in place: static partners of local and of cross contacts
+    low = sc.pos[:, 2] < sc.pos[:, 2].min() + 0.3
+    sc.inv_mass[low] = 0.0
+    sc.inv_inertia[low] = 0.0
+    sc.vel[low] = 0.0
+    sc.angvel[low] = 0.0
+    return sc
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_block_order_steps_match_oracle(name):
+    nb = _nb()
+    make, edge, relax = CASES[name]
+    sc = make()
+    sc.relax = relax
+    g = nb.GpuScene(sc.copy()).set_block_order(edge)
+    w = oracle.World(sc.copy()).set_block_order(edge)
+    steps = 2 if name == "dense tile" else 3
+    for step in range(steps):
+        g.step(12)
+        w.step(12, grid=True)
+        v = w.view()
+        nblocks = v["n_sub"] - 1
+        assert 0 < np.sum(v["sdom"] < nblocks) < len(v["sdom"]), "both kinds of contacts occur"
+        c = g.contacts()
+        assert np.array_equal(c["key"], v["key"]), step
+        assert np.array_equal(c["colour"], v["colour"]), step
+        assert np.array_equal(c["P"], v["P"]), step
+        gv, gw = g.accumulators()
+        assert np.array_equal(gv, v["v"]) and np.array_equal(gw, v["w"]), step
+        np.testing.assert_allclose(g.residuals(), v["residual_hist"], rtol=1e-9)
+    st = g.state()
+    assert np.array_equal(st["pos"], w.sc.pos) and np.array_equal(st["vel"], w.sc.vel)
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_block_order_limits_equal_the_classic_sweep(precision):
+    """One block over the whole box (every contact local) and blocks too small to hold two touching centres in a
+    scene without walls (every contact between blocks) both sweep in the classic order."""
+    nb = _nb()
+    for sc, edge in ((sg.packed_cluster(64, counts=(10, 8, 6)), 1e6),
+                     (sg.random_cluster(6, 400, box=9.0, periodic=(True, True, True), overlap=0.05), 0.3)):
+        runs = []
+        for e in (0.0, edge):
+            g = nb.GpuScene(sc.copy(), precision=precision).set_block_order(e)
+            for _ in range(2):
+                g.step(15)
+            runs.append((g.contacts()["P"], g.state()["vel"]))
+            g.close()
+        assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_block_order_residual_target_and_fp32():
+    nb = _nb()
+    sc = sg.packed_cluster(65, counts=(10, 10, 6))
+    w = oracle.World(sc.copy()).set_block_order(2.5)
+    w.detect(grid=True)
+    w.solve(400, 1e-7)
+    v = w.view()
+    g = nb.GpuScene(sc.copy()).set_block_order(2.5)
+    g.detect()
+    st = g.solve(400, 1e-7)
+    assert abs(st["sweeps"] - v["sweeps"]) <= 1  # the residual's rounding may move the stop by one sweep
+    g.close()
+    g32 = nb.GpuScene(sc.copy(), precision="fp32").set_block_order(2.5)
+    g32.detect()
+    g32.solve(25)
+    w2 = oracle.World(sc.copy()).set_block_order(2.5)
+    w2.detect(grid=True)
+    w2.solve(25)
+    v2 = w2.view()
+    c = g32.contacts()
+    assert np.abs(c["P"] - v2["P"]).max() <= 2e-4 * np.abs(v2["P"]).max()
+    g32.close()
+
+
+def test_block_order_errors():
+    nb = _nb()
+    sc = sg.packed_cluster(66, counts=(4, 4, 3))
+    g = nb.GpuScene(sc.copy())
+    with pytest.raises(nb.NbgsError):
+        g.set_block_order(-1.0)
+    g.set_subdomains(2.0)
+    with pytest.raises(nb.NbgsError):
+        g.set_block_order(2.0)  # the subdomain solver is on
+    g.set_subdomains(0.0)
+    g.set_block_order(2.0)
+    with pytest.raises(nb.NbgsError):
+        g.set_subdomains(2.0)
+    with pytest.raises(nb.NbgsError):
+        g.set_params(warm_start="learned")
+    g.detect()
+    with pytest.raises(nb.NbgsError):
+        g.autotune(4)
+    g.close()
+    # a block too large for the workgroup's local memory
+    g = nb.GpuScene(sg.dense_packing(tiles=1)).set_block_order(1e6)
+    with pytest.raises(nb.NbgsError) as e:
+        g.detect()
+    assert "block" in str(e.value)
+    g.close()
+    gb = nb.GpuBatch([sg.packed_cluster(67, counts=(4, 4, 3)), sg.packed_cluster(68, counts=(3, 3, 3))],
+                     precision="fp64")
+    with pytest.raises(nb.NbgsError):
+        gb.set_block_order(2.0)
+    gb.close()
