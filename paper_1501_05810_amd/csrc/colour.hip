@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(kBlock) k_colour_hist(ContactsView c, int64_t 
     __shared__ int cnt[2 * kMaxColours];
     for (int d = threadIdx.x; d < 2 * kMaxColours; d += kBlock) cnt[d] = 0;
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < nc) {
+    // a bounded grid walks the contacts, so that few workgroups meet at the global counters
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < nc; j += (int64_t)gridDim.x * kBlock) {
         const int col = c.colour[j] & (kMaxColours - 1);
         atomicAdd(&cnt[col], 1);
         const int b1 = c.j1[j], b2 = c.j2[j];
@@ -302,7 +302,8 @@ nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t nb, co
                                hipStream_t s) {
     NBGS_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * 2 * kMaxColours, s));
     if (nc == 0) return NBGS_OK;
-    k_colour_hist<<<grid_for(nc), kBlock, 0, s>>>(c, nc, nb, inv_mass, hist);
+    const unsigned g = grid_for(nc);
+    k_colour_hist<<<g < 1024u ? g : 1024u, kBlock, 0, s>>>(c, nc, nb, inv_mass, hist);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
