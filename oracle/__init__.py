@@ -21,7 +21,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnbgs_ref.so")
-SOURCES = [os.path.join(HERE, "nbgs_ref.c"), os.path.join(HERE, "mlp_ref.c")]
+SOURCES = [os.path.join(HERE, "nbgs_ref.c"), os.path.join(HERE, "mlp_ref.c"), os.path.join(HERE, "composite_ref.c")]
+HEADERS = [os.path.join(HERE, "nbgs_ref.h")]
 
 _dp = C.POINTER(C.c_double)
 _i32p = C.POINTER(C.c_int32)
@@ -66,10 +67,31 @@ class RefWorldView(C.Structure):
                 ("n_sub", C.c_int32)]
 
 
+class RefCompBodies(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, _dp) for f in
+                                      ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
+                                       "inv_mass", "inv_inertia", "bound")] + \
+               [("elem_start", _i32p), ("n_elem", C.c_int64), ("elem_offset", _dp), ("elem_radius", _dp)]
+
+
+class RefCompContacts(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("j1", _i32p), ("j2", _i32p), ("e1", _i32p), ("e2", _i32p), ("key", _u64p)] + \
+               [(f, _dp) for f in ("nx", "ny", "nz", "xi", "r1x", "r1y", "r1z", "r2x", "r2y", "r2z")]
+
+
+class RefCompView(C.Structure):
+    _fields_ = [("n_contacts", C.c_int64), ("n_colours", C.c_int32), ("sweeps", C.c_int32),
+                ("residual", C.c_double)] + [(f, _i32p) for f in ("j1", "j2", "e1", "e2", "colour")] + \
+               [("key", _u64p)] + \
+               [(f, _dp) for f in ("nx", "ny", "nz", "xi", "r1x", "r1y", "r1z", "r2x", "r2y", "r2z", "px", "py",
+                                   "pz")] + \
+               [("order", _i64p), ("v", _dp), ("w", _dp), ("iw", _dp), ("residual_hist", _dp)]
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (strict IEEE evaluation, no contraction)."""
     srcs = [s for s in SOURCES if os.path.exists(s)]
-    if not force and os.path.exists(LIB_PATH) and all(os.path.getmtime(LIB_PATH) >= os.path.getmtime(s) for s in srcs):
+    if not force and os.path.exists(LIB_PATH) and all(os.path.getmtime(LIB_PATH) >= os.path.getmtime(s) for s in srcs + HEADERS):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11",
@@ -107,6 +129,18 @@ def lib():
         L.nbgs_ref_world_set_block_order.argtypes = [C.c_void_p, C.c_double]
         L.nbgs_ref_subdomains.restype = C.c_int32
         L.nbgs_ref_block_local.restype = C.c_int32
+        L.nbgs_ref_comp_detect_brute.restype = C.c_int64
+        L.nbgs_ref_comp_detect_element.restype = C.c_int64
+        L.nbgs_ref_comp_world_create.restype = C.c_void_p
+        L.nbgs_ref_comp_world_create.argtypes = [C.POINTER(RefCompBodies), C.POINTER(RefDomain), C.POINTER(RefParams)]
+        for f in ("destroy", "integrate"):
+            getattr(L, "nbgs_ref_comp_world_" + f).argtypes = [C.c_void_p]
+        L.nbgs_ref_comp_world_detect.argtypes = [C.c_void_p, C.c_int32]
+        L.nbgs_ref_comp_world_solve.argtypes = [C.c_void_p, C.c_int32, C.c_double]
+        L.nbgs_ref_comp_world_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double]
+        L.nbgs_ref_comp_world_view_get.argtypes = [C.c_void_p, C.POINTER(RefCompView)]
+        L.nbgs_ref_comp_world_set_impulses.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.nbgs_ref_comp_one_contact.argtypes = [_dp, _dp, C.c_double, _dp]
         _lib = L
     return _lib
 
@@ -476,3 +510,137 @@ def mlp_targets(frame: np.ndarray, P: np.ndarray, ms: float, vs: float) -> np.nd
     lib().nbgs_ref_mlp_targets(C.c_int64(nc), _ptr(frame), _ptr(_c(P[:, 0])), _ptr(_c(P[:, 1])),
                                _ptr(_c(P[:, 2])), C.c_double(ms), C.c_double(vs), _ptr(t))
     return t[:nc].copy()
+
+
+# ------------------------------------------------------------- composite particles
+
+_STATE = (("x", "pos", 0), ("y", "pos", 1), ("z", "pos", 2), ("qw", "quat", 0), ("qx", "quat", 1),
+          ("qy", "quat", 2), ("qz", "quat", 3), ("vx", "vel", 0), ("vy", "vel", 1), ("vz", "vel", 2),
+          ("wx", "angvel", 0), ("wy", "angvel", 1), ("wz", "angvel", 2))
+
+
+def make_comp_bodies(cs, held: _Held) -> RefCompBodies:
+    cols = {name: np.ascontiguousarray(getattr(cs, arr)[:, k], dtype=np.float64) for name, arr, k in _STATE}
+    cols["inv_mass"] = np.ascontiguousarray(cs.inv_mass, dtype=np.float64)
+    cols["inv_inertia"] = np.ascontiguousarray(cs.inv_inertia, dtype=np.float64).reshape(-1)
+    cols["bound"] = np.ascontiguousarray(cs.bound, dtype=np.float64)
+    cols["elem_offset"] = np.ascontiguousarray(cs.elem_offset, dtype=np.float64).reshape(-1)
+    cols["elem_radius"] = np.ascontiguousarray(cs.elem_radius, dtype=np.float64)
+    start = np.ascontiguousarray(cs.elem_start, dtype=np.int32)
+    held.arrays.append((cols, start))
+    b = RefCompBodies(n=cs.n, n_elem=cs.n_elements, elem_start=_ptr(start, _i32p),
+                      **{k: _ptr(v) for k, v in cols.items()})
+    b._cols = cols
+    return b
+
+
+_CCOLS = (("j1", np.int32), ("j2", np.int32), ("e1", np.int32), ("e2", np.int32), ("key", np.uint64)) + \
+         tuple((f, np.float64) for f in ("nx", "ny", "nz", "xi", "r1x", "r1y", "r1z", "r2x", "r2y", "r2z"))
+
+
+def _comp_contacts_dict(raw, m):
+    out = {k: raw[k][:m].copy() for k in ("j1", "j2", "e1", "e2", "key", "xi")}
+    out["n"] = np.stack([raw["nx"][:m], raw["ny"][:m], raw["nz"][:m]], axis=1)
+    out["r1"] = np.stack([raw["r1x"][:m], raw["r1y"][:m], raw["r1z"][:m]], axis=1)
+    out["r2"] = np.stack([raw["r2x"][:m], raw["r2y"][:m], raw["r2z"][:m]], axis=1)
+    return out
+
+
+def comp_detect(cs, element: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Contact set of a composite scene in key order (exhaustive element-pair test), or only the contacts of one
+    element: j1, j2 (bodies), e1, e2 (elements), key, n (m x 3), xi, r1, r2 (lever arms, m x 3)."""
+    L = lib()
+    held = _Held()
+    b, d, p = make_comp_bodies(cs, held), make_domain(cs, held), make_params(cs)
+    cap = max(16, 8 * cs.n_elements) if element is None else 256
+    while True:
+        raw = {k: np.zeros(cap, dtype=t) for k, t in _CCOLS}
+        rc = RefCompContacts(cap=cap, **{k: _ptr(v, _i32p if v.dtype == np.int32 else
+                                                   (_u64p if v.dtype == np.uint64 else _dp)) for k, v in raw.items()})
+        if element is None:
+            m = L.nbgs_ref_comp_detect_brute(C.byref(b), C.byref(d), C.byref(p), C.byref(rc))
+        else:
+            m = L.nbgs_ref_comp_detect_element(C.byref(b), C.byref(d), C.byref(p), C.c_int64(element), C.byref(rc))
+        if m <= cap:
+            return _comp_contacts_dict(raw, m)
+        cap = 2 * m
+
+
+def comp_one_contact(Wc, bc, mu: float) -> np.ndarray:
+    """Exact one-contact solution in the contact frame: Wc = (a, c0, c1, B00, B01, B11), bc = (b_n, b_t0, b_t1);
+    returns (p_n, p_t0, p_t1)."""
+    w = np.ascontiguousarray(Wc, dtype=np.float64)
+    bb = np.ascontiguousarray(bc, dtype=np.float64)
+    out = np.zeros(3)
+    lib().nbgs_ref_comp_one_contact(_ptr(w), _ptr(bb), C.c_double(mu), _ptr(out))
+    return out
+
+
+class CompWorld:
+    """Stateful oracle scene of composite bodies (borrowed CompositeScene arrays are written back on integrate)."""
+
+    def __init__(self, cs):
+        self.sc = cs
+        self._held = _Held()
+        self._b = make_comp_bodies(cs, self._held)
+        self._d = make_domain(cs, self._held)
+        self._p = make_params(cs)
+        self._w = lib().nbgs_ref_comp_world_create(C.byref(self._b), C.byref(self._d), C.byref(self._p))
+
+    def __del__(self):
+        try:
+            if self._w:
+                lib().nbgs_ref_comp_world_destroy(self._w)
+                self._w = None
+        except Exception:
+            pass
+
+    def _pull(self):
+        cols = self._b._cols
+        for name, arr, k in _STATE:
+            getattr(self.sc, arr)[:, k] = cols[name]
+
+    def detect(self, warm: bool = True):
+        lib().nbgs_ref_comp_world_detect(self._w, int(warm))
+        return self
+
+    def set_impulses(self, P: np.ndarray):
+        cols = [np.ascontiguousarray(P[:, k], dtype=np.float64) for k in range(3)]
+        lib().nbgs_ref_comp_world_set_impulses(self._w, *[_ptr(c) for c in cols])
+        return self
+
+    def solve(self, max_sweeps: int, target: float = 0.0):
+        lib().nbgs_ref_comp_world_solve(self._w, int(max_sweeps), float(target))
+        return self
+
+    def integrate(self):
+        lib().nbgs_ref_comp_world_integrate(self._w)
+        self._pull()
+        return self
+
+    def step(self, max_sweeps: int, target: float = 0.0, warm: bool = True):
+        lib().nbgs_ref_comp_world_step(self._w, int(warm), int(max_sweeps), float(target))
+        self._pull()
+        return self
+
+    def view(self) -> Dict[str, np.ndarray]:
+        v = RefCompView()
+        lib().nbgs_ref_comp_world_view_get(self._w, C.byref(v))
+        m = int(v.n_contacts)
+        n = self.sc.n
+
+        def arr(p, count, dtype):
+            if count == 0 or not p:
+                return np.zeros(0, dtype=dtype)
+            return np.ctypeslib.as_array(p, shape=(count,)).astype(dtype, copy=True)
+
+        raw = {k: arr(getattr(v, k), m, t) for k, t in _CCOLS}
+        out = _comp_contacts_dict(raw, m)
+        out.update(n_contacts=m, n_colours=int(v.n_colours), sweeps=int(v.sweeps), residual=float(v.residual),
+                   colour=arr(v.colour, m, np.int32), order=arr(v.order, m, np.int64))
+        out["P"] = np.stack([arr(v.px, m, np.float64), arr(v.py, m, np.float64), arr(v.pz, m, np.float64)], axis=1)
+        out["v"] = arr(v.v, 3 * n, np.float64).reshape(n, 3)
+        out["w"] = arr(v.w, 3 * n, np.float64).reshape(n, 3)
+        out["iw"] = arr(v.iw, 9 * n, np.float64).reshape(n, 3, 3)
+        out["residual_hist"] = arr(v.residual_hist, int(v.sweeps), np.float64)
+        return out

@@ -42,48 +42,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-/* ------------------------------------------------------------------ types */
-
-typedef struct {
-    int64_t n;
-    double *x, *y, *z;
-    double *qw, *qx, *qy, *qz;
-    double *vx, *vy, *vz;
-    double *wx, *wy, *wz;
-    const double *radius, *inv_mass, *inv_inertia;
-} ref_bodies;
-
-typedef struct {
-    double point[3];
-    double normal[3]; /* unit, pointing into the domain */
-} ref_plane;
-
-typedef struct {
-    double lo[3], hi[3];
-    int32_t periodic[3];
-    int32_t n_planes;
-    const ref_plane *planes;
-} ref_domain;
-
-typedef struct {
-    double dt;
-    double gravity[3];
-    double mu;    /* coefficient of friction, eq. (coulomb) */
-    double tau;   /* hull safety margin, eq. (expansionradius) */
-    double relax; /* relaxation parameter omega of Alg. 1 */
-    double erp;   /* scale of the penetration correction xi/dt when xi < 0, Sect. 3 */
-    uint64_t colour_seed;
-} ref_params;
-
-/* Contact list, structure of arrays, capacity cap. */
-typedef struct {
-    int64_t cap;
-    int32_t *j1, *j2;
-    uint64_t *key;
-    double *nx, *ny, *nz; /* unit normal, outward from body j2 */
-    double *xi;           /* signed contact distance */
-    double *a1, *a2;      /* lever arms: x_hat - x_j1 = -a1 n, x_hat - x_j2 = a2 n */
-} ref_contacts;
+#include "nbgs_ref.h"
 
 /* ------------------------------------------------------------ hull radii */
 
@@ -596,11 +555,6 @@ void nbgs_ref_warm_match(int64_t nc, const uint64_t *key, const double *nx, cons
 }
 
 /* ----------------------------------------------------------------- solve */
-
-typedef struct {
-    int32_t sweeps;
-    double residual;
-} ref_solve_stats;
 
 /* Apply impulse dP at contact j (acting +dP on j1 and -dP on j2 at the
  * contact point, eq. (wrench)) to the velocity accumulators.  With
