@@ -448,6 +448,109 @@ typedef struct {
 } nbgs_warm_info;
 nbgs_status nbgs_get_warm_start_info(nbgs_scene_t scene, nbgs_warm_info *out);
 
+/* ------------------------------------------------------------------------
+ * Composite particles: rigid clusters of element spheres (Sect. 2 builds
+ * non-spherical particles from primitives glued together; the granular gas of
+ * Sect. 7.2.1 uses two to four spheres per particle).
+ *
+ * A body is its centre of mass x, an orientation q (unit quaternion mapping
+ * the principal body frame to the world), velocities v and w (world frame),
+ * 1/m, the principal inverse moments (body frame), the bounding radius rbar
+ * about the centre of mass and its elements: spheres of radius r_e centred at
+ * o_e in body coordinates.  One time step:
+ *   detect     hull radius h = dt (|v| + |w| rbar) + tau (eq. (expansionradius));
+ *              every pair of elements of different bodies whose spheres grown
+ *              by their bodies' h meet, and every element whose grown sphere
+ *              reaches a wall, is a contact (eq. (contactpos) of two spheres:
+ *              normal from the centre of j2's element to j1's, contact point
+ *              on the surface of j2's element); then colouring as for
+ *              spheres and initial impulses (zero or the previous step's);
+ *   solve      accumulators v' = v + dt g, w' = w + dt I^-1 (-w x I w) (the
+ *              gyroscopic term of eq. (integrationscheme)), then NBGS sweeps
+ *              colour by colour with the full 3x3 Delassus block of the two
+ *              bodies at the contact (eq. (wrench)) and the exact solution of
+ *              the one-contact problem of eqs. (nonpenetration), (coulomb):
+ *              separate, stick, or slide with the tangential multiplier found
+ *              by bisection;
+ *   integrate  eq. (integrationscheme) as for spheres.
+ * Conventions as above, except that a contact joins ELEMENTS: j1 < j2 are the
+ * bodies, the key is (element of j1 << 32) | element of j2, a wall w is body
+ * n_bodies + w and element n_elements + w, and the lever arms r1 = x_hat - x_j1,
+ * r2 = x_hat - x_j2 (zero for a wall) are part of the contact.  FP64 only.
+ * ------------------------------------------------------------------------ */
+
+typedef struct nbgs_composite_s *nbgs_composite_t;
+
+typedef struct {
+    int64_t n; /* bodies */
+    /* [device] body state, n each, updated in place by integrate / step */
+    double *x, *y, *z, *qw, *qx, *qy, *qz, *vx, *vy, *vz, *wx, *wy, *wz;
+    const double *inv_mass;    /* [device] n; 0: static body */
+    const double *inv_inertia; /* [device] 3 n principal inverse moments, xyz interleaved; 0 0 0: no rotation */
+    const double *bound;       /* [device] n bounding radius about the centre of mass */
+    const int32_t *elem_start; /* [device] n + 1: body i owns elements elem_start[i] .. elem_start[i+1]-1 */
+    int64_t n_elements;
+    const double *elem_offset; /* [device] 3 E element centres in body coordinates, xyz interleaved */
+    const double *elem_radius; /* [device] E */
+} nbgs_composite_bodies;
+
+/* Create a composite scene that borrows the arrays.  bodies, domain, params:
+ * [host] structs.  Errors: INVALID_ARG (null pointer, n < 1, fewer elements
+ * than bodies, elem_start not running from 0 to n_elements, bad parameters or
+ * domain as for nbgs_scene_create), UNSUPPORTED (precision other than
+ * NBGS_FP64, learned warm start), OUT_OF_MEMORY, DEVICE.  Release the handle
+ * with nbgs_composite_destroy. */
+nbgs_status nbgs_composite_create(const nbgs_composite_bodies *bodies, const nbgs_domain *domain,
+                                  const nbgs_params *params, void *hip_stream, nbgs_composite_t *out);
+nbgs_status nbgs_composite_destroy(nbgs_composite_t scene);
+
+/* Detection, colouring, initial impulses (see above).  stats [host, may be
+ * NULL]: contact and colour counts.  Errors: STATE (detected twice without a
+ * solve and integrate), CAPACITY (an element meets more than 2^18 hull
+ * candidates, 2^31 contacts or more, more than 255 colours), NUMERIC (a
+ * non-finite body state). */
+nbgs_status nbgs_composite_detect(nbgs_composite_t scene, nbgs_stats *stats);
+
+/* Accumulator init and NBGS sweeps: exactly max_sweeps (residual_target <= 0)
+ * or until R <= residual_target (checked after every sweep; the host looks
+ * every 8 sweeps, later sweeps are no-ops).  Errors: STATE (not detected, or
+ * solved already), NOT_CONVERGED (impulses still valid), NUMERIC. */
+nbgs_status nbgs_composite_solve(nbgs_composite_t scene, int32_t max_sweeps, double residual_target,
+                                 nbgs_stats *stats);
+
+/* Semi-implicit Euler of the body state with the solved accumulators.
+ * STATE if the step is not solved. */
+nbgs_status nbgs_composite_integrate(nbgs_composite_t scene);
+
+/* detect + solve + integrate; returns NOT_CONVERGED after integrating if the
+ * target was missed. */
+nbgs_status nbgs_composite_step(nbgs_composite_t scene, int32_t max_sweeps, double residual_target,
+                                nbgs_stats *stats);
+
+/* The current contact list in canonical (key) order into [device] buffers of
+ * capacity cap (any may be NULL): j1, j2 (bodies), key, colour, impulse
+ * (3 cap doubles: planes x[cap], y[cap], z[cap], the solved impulse after a
+ * solve, else the initial one) and geometry (10 cap doubles, planes n_x, n_y,
+ * n_z, xi, r1 (3), r2 (3)).  *n_out [host] = contact count.  cap = 0 only
+ * queries the count.  CAPACITY if 0 < cap < count; STATE before the first
+ * detection.  Synchronises. */
+nbgs_status nbgs_composite_get_contacts(nbgs_composite_t scene, int64_t cap, int32_t *j1, int32_t *j2, uint64_t *key,
+                                        int32_t *colour, double *impulse, double *geometry, int64_t *n_out);
+
+/* Velocity accumulators v', w' after the last solve into [device] buffers of
+ * 3 n doubles each (planes x[n], y[n], z[n]).  STATE before the first solve. */
+nbgs_status nbgs_composite_get_accumulators(nbgs_composite_t scene, double *v, double *w);
+
+/* Residuals R of sweeps 1 .. min(cap, sweeps) of the last solve into hist
+ * [host]; *n_out [host] = sweeps done.  Synchronises. */
+nbgs_status nbgs_composite_get_residuals(nbgs_composite_t scene, int32_t cap, double *hist, int32_t *n_out);
+
+/* Wall-clock milliseconds [host, n <= 5] of the last step's phases from
+ * events on the scene's stream: detection, colouring and sweep order,
+ * accumulator init with initial impulses, sweeps, integration (-1 where a
+ * phase did not run).  Synchronises. */
+nbgs_status nbgs_composite_get_phase_times(nbgs_composite_t scene, int32_t n, double *out);
+
 #ifdef __cplusplus
 }
 #endif

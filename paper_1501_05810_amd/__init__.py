@@ -68,6 +68,13 @@ class nbgs_tuning(C.Structure):
                 ("graph", C.c_int32), ("lane_groups", C.c_int32)]
 
 
+class nbgs_composite_bodies(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, _vp) for f in
+                                      ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
+                                       "inv_mass", "inv_inertia", "bound", "elem_start")] + \
+               [("n_elements", C.c_int64), ("elem_offset", _vp), ("elem_radius", _vp)]
+
+
 class NbgsError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"nbgs status {STATUS_NAMES.get(status, status)}: {msg}")
@@ -119,6 +126,17 @@ _SIGNATURES = [
     ("nbgs_batch_scene", C.c_int, [_vp, C.POINTER(_vp)]),
     ("nbgs_batch_step", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_double, C.POINTER(nbgs_stats)]),
     ("nbgs_batch_scene_stats", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    ("nbgs_composite_create", C.c_int, [C.POINTER(nbgs_composite_bodies), C.POINTER(nbgs_domain),
+                                        C.POINTER(nbgs_params), _vp, C.POINTER(_vp)]),
+    ("nbgs_composite_destroy", C.c_int, [_vp]),
+    ("nbgs_composite_detect", C.c_int, [_vp, C.POINTER(nbgs_stats)]),
+    ("nbgs_composite_solve", C.c_int, [_vp, C.c_int32, C.c_double, C.POINTER(nbgs_stats)]),
+    ("nbgs_composite_integrate", C.c_int, [_vp]),
+    ("nbgs_composite_step", C.c_int, [_vp, C.c_int32, C.c_double, C.POINTER(nbgs_stats)]),
+    ("nbgs_composite_get_contacts", C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_int64)]),
+    ("nbgs_composite_get_accumulators", C.c_int, [_vp, _vp, _vp]),
+    ("nbgs_composite_get_residuals", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    ("nbgs_composite_get_phase_times", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
 ]
 
 _lib = None
@@ -733,3 +751,136 @@ class GpuBatch(GpuScene):
         out["j1"], out["j2"] = j1.astype(np.int32), j2.astype(np.int32)
         out["key"] = ((j1.astype(np.uint64) << np.uint64(32)) | j2.astype(np.uint64)).astype(np.uint64)
         return out
+
+
+# ------------------------------------------------------------- composite particles
+
+COMPOSITE_FIELDS = ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz")
+
+
+class GpuComposite:
+    """A scene of composite particles (rigid clusters of element spheres) on the GPU.
+
+    ``cs`` is a :class:`scenegen.CompositeScene`; its arrays are copied to the device once and ``state()`` copies
+    the body state back.  Every step runs in the HIP library (FP64)."""
+
+    def __init__(self, cs, device="cuda", warm_start="previous", stream=None):
+        import torch
+
+        self.torch = torch
+        self.sc = cs
+        self.device = torch.device(device)
+        self.n = cs.n
+        self.n_elements = cs.n_elements
+        f64 = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.device)  # noqa: E731
+        cols = {"x": cs.pos[:, 0], "y": cs.pos[:, 1], "z": cs.pos[:, 2], "qw": cs.quat[:, 0], "qx": cs.quat[:, 1],
+                "qy": cs.quat[:, 2], "qz": cs.quat[:, 3], "vx": cs.vel[:, 0], "vy": cs.vel[:, 1],
+                "vz": cs.vel[:, 2], "wx": cs.angvel[:, 0], "wy": cs.angvel[:, 1], "wz": cs.angvel[:, 2]}
+        self.t = {k: f64(v) for k, v in cols.items()}
+        self.t["inv_mass"] = f64(cs.inv_mass)
+        self.t["inv_inertia"] = f64(np.asarray(cs.inv_inertia).reshape(-1))
+        self.t["bound"] = f64(cs.bound)
+        self.t["elem_offset"] = f64(np.asarray(cs.elem_offset).reshape(-1))
+        self.t["elem_radius"] = f64(cs.elem_radius)
+        self.t["elem_start"] = torch.tensor(np.ascontiguousarray(cs.elem_start, dtype=np.int32), device=self.device)
+        ptr = {k: v.data_ptr() for k, v in self.t.items()}
+        self._bodies = nbgs_composite_bodies(n=self.n, n_elements=self.n_elements, **ptr)
+        self._planes = (nbgs_plane * max(1, len(cs.planes)))()
+        for i, (pt, nm) in enumerate(cs.planes):
+            self._planes[i].point[:] = list(pt)
+            self._planes[i].normal[:] = list(nm)
+        self._domain = nbgs_domain(lo=(C.c_double * 3)(*cs.lo), hi=(C.c_double * 3)(*cs.hi),
+                                   periodic=(C.c_int32 * 3)(*[int(bool(p)) for p in cs.periodic]),
+                                   n_planes=len(cs.planes), planes=C.cast(self._planes, C.POINTER(nbgs_plane)))
+        self._params = make_params(cs, "fp64", warm_start)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        _check(lib().nbgs_composite_create(C.byref(self._bodies), C.byref(self._domain), C.byref(self._params),
+                                           _vp(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nbgs_composite_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stats(st, code):
+        return dict(n_contacts=int(st.n_contacts), n_colours=int(st.n_colours), sweeps=int(st.sweeps),
+                    residual=float(st.residual), converged=code == NBGS_OK)
+
+    def detect(self) -> Dict:
+        st = nbgs_stats()
+        code = _check(lib().nbgs_composite_detect(self.handle, C.byref(st)))
+        return self._stats(st, code)
+
+    def solve(self, max_sweeps: int, target: float = 0.0) -> Dict:
+        st = nbgs_stats()
+        code = _check(lib().nbgs_composite_solve(self.handle, int(max_sweeps), float(target), C.byref(st)),
+                      allow=(NBGS_ERR_NOT_CONVERGED,))
+        return self._stats(st, code)
+
+    def integrate(self):
+        _check(lib().nbgs_composite_integrate(self.handle))
+
+    def step(self, max_sweeps: int, target: float = 0.0, stats: bool = True) -> Dict:
+        st = nbgs_stats()
+        code = _check(lib().nbgs_composite_step(self.handle, int(max_sweeps), float(target),
+                                                C.byref(st) if stats else None),
+                      allow=(NBGS_ERR_NOT_CONVERGED,))
+        return self._stats(st, code)
+
+    def contacts(self) -> Dict[str, np.ndarray]:
+        torch = self.torch
+        n0 = C.c_int64()
+        _check(lib().nbgs_composite_get_contacts(self.handle, 0, None, None, None, None, None, None, C.byref(n0)))
+        m = int(n0.value)
+        cap = max(1, m)
+        dev = self.device
+        j1 = torch.empty(cap, dtype=torch.int32, device=dev)
+        j2 = torch.empty(cap, dtype=torch.int32, device=dev)
+        key = torch.empty(cap, dtype=torch.int64, device=dev)
+        col = torch.empty(cap, dtype=torch.int32, device=dev)
+        imp = torch.empty(3 * cap, dtype=torch.float64, device=dev)
+        geo = torch.empty(10 * cap, dtype=torch.float64, device=dev)
+        _check(lib().nbgs_composite_get_contacts(self.handle, cap, j1.data_ptr(), j2.data_ptr(), key.data_ptr(),
+                                                 col.data_ptr(), imp.data_ptr(), geo.data_ptr(), C.byref(n0)))
+        g = geo.view(10, cap)[:, :m].T.cpu().numpy().copy()
+        k = key[:m].cpu().numpy().view(np.uint64)
+        E = np.uint64(self.n_elements)
+        return dict(j1=j1[:m].cpu().numpy(), j2=j2[:m].cpu().numpy(), key=k, colour=col[:m].cpu().numpy(),
+                    e1=(k >> np.uint64(32)).astype(np.int64), e2=(k & np.uint64(0xFFFFFFFF)).astype(np.int64),
+                    P=imp.view(3, cap)[:, :m].T.cpu().numpy().copy(), n=g[:, 0:3].copy(), xi=g[:, 3].copy(),
+                    r1=g[:, 4:7].copy(), r2=g[:, 7:10].copy(), n_elements=int(E))
+
+    def accumulators(self):
+        torch = self.torch
+        v = torch.empty(3 * self.n, dtype=torch.float64, device=self.device)
+        w = torch.empty(3 * self.n, dtype=torch.float64, device=self.device)
+        _check(lib().nbgs_composite_get_accumulators(self.handle, v.data_ptr(), w.data_ptr()))
+        return v.view(3, self.n).T.cpu().numpy().copy(), w.view(3, self.n).T.cpu().numpy().copy()
+
+    def residuals(self, cap: int = 100000) -> np.ndarray:
+        buf = (C.c_double * cap)()
+        n = C.c_int32()
+        _check(lib().nbgs_composite_get_residuals(self.handle, cap, buf, C.byref(n)))
+        return np.array(buf[:min(cap, n.value)])
+
+    def phase_times(self) -> np.ndarray:
+        out = (C.c_double * 5)()
+        _check(lib().nbgs_composite_get_phase_times(self.handle, 5, out))
+        return np.array(out[:])
+
+    def state(self) -> Dict[str, np.ndarray]:
+        self.stream.synchronize()
+        t = {k: self.t[k].cpu().numpy() for k in COMPOSITE_FIELDS}
+        return dict(pos=np.stack([t["x"], t["y"], t["z"]], axis=1), quat=np.stack([t["qw"], t["qx"], t["qy"], t["qz"]],
+                                                                                   axis=1),
+                    vel=np.stack([t["vx"], t["vy"], t["vz"]], axis=1), angvel=np.stack([t["wx"], t["wy"], t["wz"]],
+                                                                                        axis=1))

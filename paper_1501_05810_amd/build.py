@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("NBGS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "sort.hip", "detect.hip", "colour.hip", "sweep.hip", "mlp.hip", "warmstart.hip", "tune.hip",
-           "batch.hip", "subdomain.hip"]
+           "batch.hip", "subdomain.hip", "composite.hip"]
 
 COMMON = [
     "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -27,9 +27,7 @@ void set_error(const char *fmt, ...) {
 
 }  // namespace nbgs
 
-using namespace nbgs;
-
-namespace {
+namespace nbgs {
 
 nbgs_status check_params(const nbgs_params *p) {
     if (!p) {
@@ -72,16 +70,40 @@ nbgs_status check_params(const nbgs_params *p) {
     return NBGS_OK;
 }
 
-void update_scales(nbgs_scene_t sc) {
-    const double g = std::sqrt(sc->p.gravity[0] * sc->p.gravity[0] + sc->p.gravity[1] * sc->p.gravity[1] +
-                               sc->p.gravity[2] * sc->p.gravity[2]);
-    sc->fs.vs = g * sc->p.dt > 0.0 ? g * sc->p.dt : 1e-3;
-    sc->fs.ms = sc->mean_mass;
-    sc->fs.rs = sc->mean_radius;
+nbgs_status check_domain(const nbgs_domain *domain) {
+    if (!domain) {
+        set_error("domain is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (domain->n_planes < 0 || domain->n_planes > PlaneSet::kMax || (domain->n_planes > 0 && !domain->planes)) {
+        set_error("n_planes must lie in [0, %d] with a plane array", PlaneSet::kMax);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!(domain->hi[a] > domain->lo[a]) || !std::isfinite(domain->hi[a] - domain->lo[a])) {
+            set_error("domain box must have hi > lo on every axis");
+            return NBGS_ERR_INVALID_ARG;
+        }
+    for (int w = 0; w < domain->n_planes; ++w) {
+        const double *nm = domain->planes[w].normal;
+        const double len = std::sqrt(nm[0] * nm[0] + nm[1] * nm[1] + nm[2] * nm[2]);
+        if (!(std::fabs(len - 1.0) < 1e-12)) {
+            set_error("plane %d normal is not unit length", w);
+            return NBGS_ERR_INVALID_ARG;
+        }
+    }
+    return NBGS_OK;
 }
 
-void record(nbgs_scene_t sc, int i) {
-    if (sc->ev[i]) sc->ev_ok[i] = hipEventRecord(sc->ev[i], sc->s) == hipSuccess;
+PlaneSet plane_set(const nbgs_domain *domain) {
+    PlaneSet ps{};
+    ps.n = domain->n_planes;
+    for (int w = 0; w < domain->n_planes; ++w)
+        for (int a = 0; a < 3; ++a) {
+            ps.p[w][a] = domain->planes[w].point[a];
+            ps.nrm[w][a] = domain->planes[w].normal[a];
+        }
+    return ps;
 }
 
 int bits_for(int64_t n) {
@@ -130,6 +152,27 @@ Grid grid_for_box(const double lo[3], const double hi[3], const int32_t periodic
     g.cell_off = 0;
     return g;
 }
+
+}  // namespace nbgs
+
+using namespace nbgs;
+
+namespace {
+
+
+void update_scales(nbgs_scene_t sc) {
+    const double g = std::sqrt(sc->p.gravity[0] * sc->p.gravity[0] + sc->p.gravity[1] * sc->p.gravity[1] +
+                               sc->p.gravity[2] * sc->p.gravity[2]);
+    sc->fs.vs = g * sc->p.dt > 0.0 ? g * sc->p.dt : 1e-3;
+    sc->fs.ms = sc->mean_mass;
+    sc->fs.rs = sc->mean_radius;
+}
+
+void record(nbgs_scene_t sc, int i) {
+    if (sc->ev[i]) sc->ev_ok[i] = hipEventRecord(sc->ev[i], sc->s) == hipSuccess;
+}
+
+
 
 // The scene's grid, or for batched scenes one grid per scene laid out one
 // after another in a shared cell table (sc->grid then only carries the total
@@ -912,20 +955,7 @@ nbgs_status integrate_impl(nbgs_scene_t sc) {
     return NBGS_OK;
 }
 
-nbgs_status check_domain(const nbgs_domain *domain) {
-    return NBGS_OK;
-}
 
-PlaneSet plane_set(const nbgs_domain *domain) {
-    PlaneSet ps{};
-    ps.n = domain->n_planes;
-    for (int w = 0; w < domain->n_planes; ++w)
-        for (int a = 0; a < 3; ++a) {
-            ps.p[w][a] = domain->planes[w].point[a];
-            ps.nrm[w][a] = domain->planes[w].normal[a];
-        }
-    return ps;
-}
 
 // Per-scene tables of a batch: body -> scene, body and wall offsets, walls,
 // friction coefficients and colouring seeds (device copies), boxes (host).

@@ -136,6 +136,15 @@ struct SubView {
     T *px, *py, *pz;
 };
 
+// ------------------------------------------------------- host helpers (api.hip)
+
+nbgs_status check_params(const nbgs_params *p);
+nbgs_status check_domain(const nbgs_domain *domain);  // box, walls (at most PlaneSet::kMax, unit normals)
+PlaneSet plane_set(const nbgs_domain *domain);
+int bits_for(int64_t n);
+// Cell grid of one box whose cells are at least 2 max_reach wide, with at most max(8 n, 2^16) cells.
+Grid grid_for_box(const double lo[3], const double hi[3], const int32_t periodic[3], int64_t n, double max_reach);
+
 // ------------------------------------------------------- kernel launchers
 
 // scan.hip / sort.hip
