@@ -23,7 +23,9 @@ Printed JSON line (one, rank 0):
 Further fields: steps/s to residual 1e-6 (FP64 and FP32 sweeps), sweeps used,
 phase times, contact statistics, the learned warm start, the subdomain NBGS
 beside the colour-ordered one, and the other workloads (walled 4,096-sphere
-box, 512-scene ensemble batch, 1M-sphere HCP ramp, 16.8M-sphere dilute gas).
+box, 512-scene ensemble batch, 1M-sphere HCP ramp, 16.8M-sphere dilute gas,
+1M composite particles of two to four spheres: the paper's granular gas and a
+contact-rich packing of the same particles).
 """
 import argparse
 import json
@@ -155,6 +157,54 @@ def other_workloads(nb, sg, torch, dev):
                              "phase_ms_last_step": [round(float(x), 3) for x in g.phase_times()], "dtype": "f64"}
     g.close()
     log(f"dilute gas: {out['dilute_gas_16m']}")
+    out.update(composite_workloads(nb, sg, torch, dev))
+    return out
+
+
+# bytes of one composite contact update (gather model): the sweep record (ends 8, normal 24, bias 8, lever arms
+# 48, impulse read and write 48) and, per dynamic end, the accumulator record read (56) and its velocities written
+# (48) plus the world inverse inertia read (72)
+COMPOSITE_CONTACT_BYTES = 136
+COMPOSITE_BODY_BYTES = 176
+
+
+def composite_workloads(nb, sg, torch, dev):
+    """Composite particles (two to four spheres each): the paper's granular gas of 100^3 particles (1.1 cm grid,
+    1 cm bounding spheres, |v| up to 0.35 m/s, mu = 0.1, dt = 100 us, 10 sweeps; timed from step 150, once the
+    particles collide), and the same particles packed 0.2 mm apart at 2 m/s (contact-rich, for the sweep
+    kernel)."""
+    import numpy as np
+
+    out = {}
+    for name, kw, warm, steps in (("composite_gas_1m", {}, 150, 20),
+                                  ("composite_dense_1m", {"spacing": 0.0102, "vmax": 2.0}, 3, 10)):
+        cs = sg.composite_gas(5, counts=(100, 100, 100), **kw)
+        g = nb.GpuComposite(cs, device=dev)
+        for _ in range(warm):
+            g.step(10, stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_c, ph = 0, np.zeros(5)
+        for _ in range(steps):
+            st = g.step(10)
+            n_c += st["n_contacts"]
+            ph += g.phase_times()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ph /= steps
+        upd = n_c / steps * 10
+        out[name] = {"bodies": cs.n, "elements": cs.n_elements, "steps": steps, "warmup_steps": warm,
+                     "sweeps_per_step": 10, "steps_per_s": steps / wall, "ms_per_step": wall / steps * 1e3,
+                     "contact_updates_per_s": upd / (wall / steps), "mean_contacts": n_c / steps,
+                     "colours_last_step": st["n_colours"],
+                     "phase_ms": {k: round(float(x), 4) for k, x in
+                                  zip(("detect", "colour_order", "init", "sweeps", "integrate"), ph)},
+                     "sweep_only_updates_per_s": upd / (ph[3] * 1e-3) if ph[3] > 0 else None,
+                     "sweep_gbs_gather_model": upd * (COMPOSITE_CONTACT_BYTES + 2 * COMPOSITE_BODY_BYTES) /
+                     (ph[3] * 1e-3) / 1e9 if ph[3] > 0 else None,
+                     "dtype": "f64", "data": "synthetic"}
+        g.close()
+        log(f"{name}: {out[name]}")
     return out
 
 

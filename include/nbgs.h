@@ -471,7 +471,7 @@ nbgs_status nbgs_get_warm_start_info(nbgs_scene_t scene, nbgs_warm_info *out);
  *              bodies at the contact (eq. (wrench)) and the exact solution of
  *              the one-contact problem of eqs. (nonpenetration), (coulomb):
  *              separate, stick, or slide with the tangential multiplier found
- *              by bisection;
+ *              by safeguarded Newton steps;
  *   integrate  eq. (integrationscheme) as for spheres.
  * Conventions as above, except that a contact joins ELEMENTS: j1 < j2 are the
  * bodies, the key is (element of j1 << 32) | element of j2, a wall w is body

@@ -28,8 +28,8 @@
  *   the one-contact solve is exact: separate if the free normal velocity is
  *     non-negative, else stick if the unconstrained 3x3 solution lies in the
  *     cone, else slide on the cone's boundary, found as the root of a scalar
- *     equation in the multiplier of the tangential constraint (bisection with a
- *     fixed number of halvings);
+ *     equation in the multiplier of the tangential constraint (safeguarded
+ *     Newton steps);
  *   a body with any principal inverse moment zero gets no gyroscopic term.
  *
  * Compile with -ffp-contract=off: every expression is evaluated as written.
@@ -290,30 +290,41 @@ int64_t nbgs_ref_comp_detect_element(const ref_comp_bodies *b, const ref_domain 
 
 /* --------------------------------------------------- one-contact problem */
 
-/* Free tangential solution of the sliding case for the multiplier lam >= 0 of
- * the constraint |p_t| = mu p_n.  In the contact frame (n, t, o) the post-step
- * relative velocity is u = Wc p + b with
+/* Sliding case for the multiplier lam >= 0 of the constraint |p_t| = mu p_n.
+ * In the contact frame (n, t, o) the post-step relative velocity is u = Wc p + b
+ * with
  *     Wc = [ a  c^T ]      b = [ b_n ]
  *          [ c  B   ],         [ b_t ].
  * Sliding means u_n = 0 and u_t = -lam p_t (opposite to the friction impulse,
- * eq. (coulomb)), so (B + lam 1) p_t = -(c p_n + b_t) and a p_n + c.p_t = -b_n:
- * p_t = p_n alpha + beta with alpha = -(B + lam)^-1 c, beta = -(B + lam)^-1 b_t,
- * and p_n = -(b_n + c.beta) / (a + c.alpha).  Returns |p_t| - mu p_n. */
+ * eq. (coulomb)), so with M = B + lam 1:  p_t = p_n alpha + beta,
+ * alpha = -M^-1 c, beta = -M^-1 b_t, and p_n = -(b_n + c.beta) / (a + c.alpha).
+ * Returns phi(lam) = |p_t| - mu p_n and its derivative (d alpha = -M^-1 alpha,
+ * d beta = -M^-1 beta). */
 static double slide_eval(const double Wc[6], const double bc[3], double mu, double lam, double *pn, double *pt0,
-                         double *pt1)
+                         double *pt1, double *dphi)
 {
     double a = Wc[0], c0 = Wc[1], c1 = Wc[2], B00 = Wc[3], B01 = Wc[4], B11 = Wc[5];
     double m00 = B00 + lam, m11 = B11 + lam;
-    double dm = m00 * m11 - B01 * B01;
-    double al0 = -(m11 * c0 - B01 * c1) / dm;
-    double al1 = -(m00 * c1 - B01 * c0) / dm;
-    double be0 = -(m11 * bc[1] - B01 * bc[2]) / dm;
-    double be1 = -(m00 * bc[2] - B01 * bc[1]) / dm;
-    double q = -(bc[0] + (c0 * be0 + c1 * be1)) / (a + (c0 * al0 + c1 * al1));
+    double r = 1.0 / (m00 * m11 - B01 * B01);
+    double al0 = -(m11 * c0 - B01 * c1) * r;
+    double al1 = -(m00 * c1 - B01 * c0) * r;
+    double be0 = -(m11 * bc[1] - B01 * bc[2]) * r;
+    double be1 = -(m00 * bc[2] - B01 * bc[1]) * r;
+    double da0 = -(m11 * al0 - B01 * al1) * r;
+    double da1 = -(m00 * al1 - B01 * al0) * r;
+    double db0 = -(m11 * be0 - B01 * be1) * r;
+    double db1 = -(m00 * be1 - B01 * be0) * r;
+    double D = a + (c0 * al0 + c1 * al1);
+    double q = -(bc[0] + (c0 * be0 + c1 * be1)) / D;
+    double dq = (-(c0 * db0 + c1 * db1) - q * (c0 * da0 + c1 * da1)) / D;
+    double t0 = q * al0 + be0, t1 = q * al1 + be1;
+    double d0 = (dq * al0 + q * da0) + db0, d1 = (dq * al1 + q * da1) + db1;
+    double tl = sqrt(t0 * t0 + t1 * t1);
     *pn = q;
-    *pt0 = q * al0 + be0;
-    *pt1 = q * al1 + be1;
-    return sqrt(*pt0 * *pt0 + *pt1 * *pt1) - mu * q;
+    *pt0 = t0;
+    *pt1 = t1;
+    *dphi = (tl > 0.0 ? (t0 * d0 + t1 * d1) / tl : 0.0) - mu * dq;
+    return tl - mu * q;
 }
 
 /* The one-contact problem F_j(P) = 0 of Sect. 3 with a full symmetric
@@ -323,13 +334,17 @@ static double slide_eval(const double Wc[6], const double bc[3], double mu, doub
  *   separate: b_n >= 0 -> p = 0 (u = b has u_n >= 0, eq. (nonpenetration));
  *   frictionless (mu = 0): p_n = -b_n / a, p_t = 0;
  *   stick: p = -Wc^-1 b if p_n > 0 and |p_t| <= mu p_n (then u = 0);
- *   slide: the root lam* > 0 of |p_t(lam)| = mu p_n(lam); starting from
- *     lam = B00 + B11 the upper end doubles (at most 128 times) until the
- *     impulse lies in the cone, then 64 bisections keep the lower end outside
- *     and the upper end inside the cone; the result is the impulse at the
- *     upper end, clipped onto the cone if the doubling ran out.
- * For a block that is diagonal in the contact frame (two spheres) the cases
- * reduce to the normal clamp and radial cone clip of the sphere solver. */
+ *   slide: the root lam* > 0 of phi(lam) = |p_t(lam)| - mu p_n(lam), by Newton
+ *     steps from lam = 0 (where phi >= 0) kept inside the bracket of the
+ *     points seen so far (a step that leaves it bisects the bracket, or, with
+ *     no point beyond the root yet, doubles the lower end, starting from
+ *     B00 + B11); it stops when the Newton correction falls below 2^-50 lam or
+ *     a step no longer moves lam, after 40 steps at most, and returns the
+ *     impulse at the last lam, clipped onto the cone.
+ *     For two spheres (c = 0, B = w_t 1) phi = |b_t| / (w_t + lam) - mu p_n and
+ *     Newton from the left converges quadratically from the first step.
+ * For a block that is diagonal in the contact frame the cases reduce to the
+ * normal clamp and radial cone clip of the sphere solver. */
 void nbgs_ref_comp_one_contact(const double Wc[6], const double bc[3], double mu, double p[3])
 {
     double a = Wc[0], c0 = Wc[1], c1 = Wc[2], B00 = Wc[3], B01 = Wc[4], B11 = Wc[5];
@@ -360,15 +375,20 @@ void nbgs_ref_comp_one_contact(const double Wc[6], const double bc[3], double mu
         return;
     }
     /* slide */
-    double pn, pt0, pt1;
-    double lo = 0.0, hi = B00 + B11;
-    for (int k = 0; k < 128 && slide_eval(Wc, bc, mu, hi, &pn, &pt0, &pt1) > 0.0; ++k) hi = 2.0 * hi;
-    for (int k = 0; k < 64; ++k) {
-        double mid = 0.5 * (lo + hi);
-        if (slide_eval(Wc, bc, mu, mid, &pn, &pt0, &pt1) > 0.0) lo = mid;
-        else hi = mid;
+    double pn, pt0, pt1, dphi;
+    double lo = 0.0, hi = INFINITY, lam = 0.0;
+    for (int k = 0; k < 40; ++k) {
+        double phi = slide_eval(Wc, bc, mu, lam, &pn, &pt0, &pt1, &dphi);
+        if (phi > 0.0) lo = lam;
+        else hi = lam;
+        double step = phi / dphi;
+        if (fabs(step) <= 0x1p-50 * lam) break; /* the Newton correction is below the last bits of lam */
+        double next = lam - step;
+        if (!(next > lo && next < hi)) next = hi < INFINITY ? 0.5 * (lo + hi) : (lo > 0.0 ? 2.0 * lo : B00 + B11);
+        if (next == lam) break;
+        lam = next;
     }
-    slide_eval(Wc, bc, mu, hi, &pn, &pt0, &pt1);
+    slide_eval(Wc, bc, mu, lam, &pn, &pt0, &pt1, &dphi);
     if (!(pn > 0.0)) return;
     double tl = sqrt(pt0 * pt0 + pt1 * pt1);
     double lim = mu * pn;

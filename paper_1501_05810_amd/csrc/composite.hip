@@ -22,7 +22,7 @@
 //               W = (1/m1 + 1/m2) 1 - [r1]x Iw1 [r1]x - [r2]x Iw2 [r2]x
 //               (eq. (wrench)), and the exact one-contact solution of
 //               eqs. (nonpenetration) and (coulomb): separate, stick, or slide
-//               with the tangential multiplier found by bisection;
+//               with the tangential multiplier found by safeguarded Newton steps;
 //   integrate   as for spheres.
 //
 // Every contact is relaxed with the same operations in the same order as the
@@ -567,27 +567,43 @@ __device__ inline void rot_block(const double r[3], const double *Iw, double K[9
         for (int j = 0; j < 3; ++j) K[3 * i + j] = X[0 + i] * A[0 + j] + X[3 + i] * A[3 + j] + X[6 + i] * A[6 + j];
 }
 
-// Sliding case for the tangential multiplier lam: (B + lam) p_t = -(c p_n + b_t),
-// a p_n + c.p_t = -b_n; returns |p_t| - mu p_n.
+// Sliding case for the multiplier lam of the constraint |p_t| = mu p_n: with
+// M = B + lam 1, p_t = p_n alpha + beta, alpha = -M^-1 c, beta = -M^-1 b_t,
+// p_n = -(b_n + c.beta) / (a + c.alpha).  Returns phi = |p_t| - mu p_n and
+// its derivative in lam (d alpha = -M^-1 alpha, d beta = -M^-1 beta).
 __device__ inline double slide_eval(const double Wc[6], const double bc[3], double mu, double lam, double *pn,
-                                    double *pt0, double *pt1) {
+                                    double *pt0, double *pt1, double *dphi) {
     const double a = Wc[0], c0 = Wc[1], c1 = Wc[2], B00 = Wc[3], B01 = Wc[4], B11 = Wc[5];
     const double m00 = B00 + lam, m11 = B11 + lam;
-    const double dm = m00 * m11 - B01 * B01;
-    const double al0 = -(m11 * c0 - B01 * c1) / dm;
-    const double al1 = -(m00 * c1 - B01 * c0) / dm;
-    const double be0 = -(m11 * bc[1] - B01 * bc[2]) / dm;
-    const double be1 = -(m00 * bc[2] - B01 * bc[1]) / dm;
-    const double q = -(bc[0] + (c0 * be0 + c1 * be1)) / (a + (c0 * al0 + c1 * al1));
+    const double r = 1.0 / (m00 * m11 - B01 * B01);
+    const double al0 = -(m11 * c0 - B01 * c1) * r;
+    const double al1 = -(m00 * c1 - B01 * c0) * r;
+    const double be0 = -(m11 * bc[1] - B01 * bc[2]) * r;
+    const double be1 = -(m00 * bc[2] - B01 * bc[1]) * r;
+    const double da0 = -(m11 * al0 - B01 * al1) * r;
+    const double da1 = -(m00 * al1 - B01 * al0) * r;
+    const double db0 = -(m11 * be0 - B01 * be1) * r;
+    const double db1 = -(m00 * be1 - B01 * be0) * r;
+    const double D = a + (c0 * al0 + c1 * al1);
+    const double q = -(bc[0] + (c0 * be0 + c1 * be1)) / D;
+    const double dq = (-(c0 * db0 + c1 * db1) - q * (c0 * da0 + c1 * da1)) / D;
+    const double t0 = q * al0 + be0, t1 = q * al1 + be1;
+    const double d0 = (dq * al0 + q * da0) + db0, d1 = (dq * al1 + q * da1) + db1;
+    const double tl = sqrt(t0 * t0 + t1 * t1);
     *pn = q;
-    *pt0 = q * al0 + be0;
-    *pt1 = q * al1 + be1;
-    return sqrt(*pt0 * *pt0 + *pt1 * *pt1) - mu * q;
+    *pt0 = t0;
+    *pt1 = t1;
+    *dphi = (tl > 0.0 ? (t0 * d0 + t1 * d1) / tl : 0.0) - mu * dq;
+    return tl - mu * q;
 }
 
 // Exact solution of the one-contact problem in the contact frame: separate
 // (b_n >= 0), frictionless, stick (unconstrained solution inside the cone),
-// or slide (128 doublings at most, then 64 bisections of the multiplier).
+// or slide: Newton steps on phi from lam = 0 kept inside the bracket of the
+// points seen (bisection, or doubling the lower end while no point beyond the
+// root is known), stopping when the correction falls below 2^-50 lam or a step
+// no longer moves lam (40 steps at most); the impulse at the last lam is
+// clipped onto the cone.
 __device__ inline void one_contact(const double Wc[6], const double bc[3], double mu, double p[3]) {
     const double a = Wc[0], c0 = Wc[1], c1 = Wc[2], B00 = Wc[3], B01 = Wc[4], B11 = Wc[5];
     const double bn = bc[0], bt0 = bc[1], bt1 = bc[2];
@@ -615,15 +631,20 @@ __device__ inline void one_contact(const double Wc[6], const double bc[3], doubl
         p[2] = s1;
         return;
     }
-    double pn, pt0, pt1;
-    double lo = 0.0, hi = B00 + B11;
-    for (int k = 0; k < 128 && slide_eval(Wc, bc, mu, hi, &pn, &pt0, &pt1) > 0.0; ++k) hi = 2.0 * hi;
-    for (int k = 0; k < 64; ++k) {
-        const double mid = 0.5 * (lo + hi);
-        if (slide_eval(Wc, bc, mu, mid, &pn, &pt0, &pt1) > 0.0) lo = mid;
-        else hi = mid;
+    double pn, pt0, pt1, dphi;
+    double lo = 0.0, hi = INFINITY, lam = 0.0;
+    for (int k = 0; k < 40; ++k) {
+        const double phi = slide_eval(Wc, bc, mu, lam, &pn, &pt0, &pt1, &dphi);
+        if (phi > 0.0) lo = lam;
+        else hi = lam;
+        const double step = phi / dphi;
+        if (fabs(step) <= 0x1p-50 * lam) break;
+        double next = lam - step;
+        if (!(next > lo && next < hi)) next = hi < INFINITY ? 0.5 * (lo + hi) : (lo > 0.0 ? 2.0 * lo : B00 + B11);
+        if (next == lam) break;
+        lam = next;
     }
-    slide_eval(Wc, bc, mu, hi, &pn, &pt0, &pt1);
+    slide_eval(Wc, bc, mu, lam, &pn, &pt0, &pt1, &dphi);
     if (!(pn > 0.0)) return;
     const double tl = sqrt(pt0 * pt0 + pt1 * pt1);
     const double lim = mu * pn;
