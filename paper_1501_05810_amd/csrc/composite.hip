@@ -14,7 +14,8 @@
 //               (eq. (contactpos)); the contact keeps its lever arms from the
 //               two centres of mass;
 //   colouring   as for spheres: no two contacts of a colour share a dynamic
-//               body (several contacts may join the same two bodies);
+//               body (several contacts may join the same two bodies); after
+//               the first step the passes start from the previous colours;
 //   init        v' = v + dt g, w' = w + dt I^-1 (-w x I w): the gyroscopic
 //               term of eq. (integrationscheme), zero for spheres;
 //   sweeps      per colour, per contact: relative velocity at the contact
@@ -981,10 +982,12 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
                                                sc->b.elem_radius, sc->h.p, sc->owx.p, sc->owy.p, sc->owz.p, cb.view());
     NBGS_HIP(hipGetLastError());
     // initial impulses: the previous step's, matched by key and re-projected onto the new cone, else zero
+    // and, when the previous step was coloured, its colours as the start of the colouring passes
     const bool warm = sc->p.warm_start == NBGS_WS_PREVIOUS && sc->n_prev > 0;
+    const bool warm_colours = sc->n_prev > 0 && nc > 0;
     const SceneTable tab{};
-    NBGS_TRY(launch_match_prev(cb.shared_view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, nullptr,
-                               sc->n_prev, sc->p.mu, tab, warm, false, s));
+    NBGS_TRY(launch_match_prev(cb.shared_view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p,
+                               sc->n_prev, sc->p.mu, tab, warm, warm_colours, s));
     if (!warm && nc > 0) {
         NBGS_HIP(hipMemsetAsync(cb.px.p, 0, sizeof(double) * nc, s));
         NBGS_HIP(hipMemsetAsync(cb.py.p, 0, sizeof(double) * nc, s));
@@ -1002,7 +1005,25 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
     NBGS_TRY(exclusive_scan_i32(sc->deg2.p, sc->off2.p, (int64_t)N + 1, nullptr, sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_HIP(hipMemcpyAsync(sc->cursor.p, sc->off2.p, sizeof(int32_t) * ((size_t)N + 1), hipMemcpyDeviceToDevice, s));
     NBGS_TRY(launch_j2_fill(cv, nc, N, sc->b.inv_mass, sc->cursor.p, sc->inc2.p, s));
-    if (nc > 0) {
+    if (warm_colours) {
+        // the greedy rule repeated from the previous colours until a pass changes nothing: its fixed point is the
+        // greedy colouring in priority order, the one the Jones-Plassmann rounds build from scratch
+        for (int pass = 0;; ++pass) {
+            NBGS_HIP(hipMemsetAsync(sc->small.p + 1, 0, 2 * sizeof(int32_t), s));
+            NBGS_TRY(launch_colour_fix(cv, sc->prio.p, nc, N, sc->b.inv_mass, sc->off1.p, sc->cnt1.p, sc->off2.p,
+                                       sc->inc2.p, nullptr, sc->small.p + 1, sc->small.p + 2, s));
+            NBGS_TRY(sync_small(sc, 1, 2));
+            if (sc->pinned[2]) {
+                set_error("more than 255 colours needed");
+                return NBGS_ERR_CAPACITY;
+            }
+            if (sc->pinned[1] == 0) break;
+            if (pass > 100000) {
+                set_error("colouring did not settle");
+                return NBGS_ERR_DEVICE;
+            }
+        }
+    } else if (nc > 0) {
         NBGS_HIP(hipMemsetAsync(cb.colour.p, 0xff, sizeof(int32_t) * nc, s));
         sc->pinned[1] = (int32_t)nc;
         sc->pinned[2] = 0;
