@@ -208,6 +208,7 @@ struct nbgs_scene_s {
     DevBuf<int32_t> sdom, tile_cnt, tile_off32, tile_scnt, tile_slot_off, eflags, eex, slot_body, slot_sdom, body_cnt,
         body_slot_off;
     DevBuf<int64_t> tile_off;
+    DevBuf<int32_t> blk_cs;  // block-local order: per block its colour boundaries and colour count
     DevBuf<uint32_t> ekeys, evals, ekeys2, evals2, bkeys, bvals, bkeys2, bvals2;
     const uint32_t *body_slots = nullptr;
     DevBuf<double> corr64;

@@ -475,43 +475,62 @@ __global__ void __launch_bounds__(kBlock) k_sub_reduce(T *vel, int32_t nb, const
 // never changes), a wall is zero.
 constexpr int kBlkThreads = 128;
 
+// Colour boundaries of every block's local contacts, once per step: cs[b (kMaxCol + 2) + c] = start of colour c
+// relative to the block's first contact (c = 0 .. ncol, the last one is the block's end), cs[b (kMaxCol + 2) +
+// kMaxCol + 1] = ncol.  Empty colours start where the next one does.
+__global__ void __launch_bounds__(kBlkThreads) k_blk_colour_starts(const int32_t *col, const int64_t *tile_off,
+                                                                   int32_t *cs) {
+    const int s = blockIdx.x;
+    const int64_t c0 = tile_off[s], c1 = tile_off[s + 1];
+    __shared__ int64_t cstart[kMaxCol + 1];
+    __shared__ int ncol;
+    for (int c = threadIdx.x; c <= kMaxCol; c += kBlkThreads) cstart[c] = c1;
+    if (threadIdx.x == 0) ncol = 0;
+    __syncthreads();
+    for (int64_t p = c0 + threadIdx.x; p < c1; p += kBlkThreads) {
+        const int cp = col[p];
+        if (p == c0 || col[p - 1] != cp) cstart[cp] = p;
+        if (p == c1 - 1) ncol = cp + 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int c = ncol - 1; c >= 0; --c)
+            if (cstart[c] == c1 && c + 1 <= kMaxCol) cstart[c] = cstart[c + 1];
+        cs[(int64_t)s * (kMaxCol + 2) + kMaxCol + 1] = ncol;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c <= ncol; c += kBlkThreads)
+        cs[(int64_t)s * (kMaxCol + 2) + c] = (int32_t)((c < ncol ? cstart[c] : c1) - c0);
+}
+
 template <class T, int MODE>
 __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t nb, T *vel, T mu, T relax,
                                                           const int64_t *tile_off, const int32_t *tile_slot_off,
-                                                          const int32_t *slot_body, double *partials,
-                                                          const int32_t *ctrl) {
+                                                          const int32_t *slot_body, const int32_t *blk_cs,
+                                                          double *partials, const int32_t *ctrl) {
     if (MODE == 1 && ctrl[0]) return;  // an earlier sweep met the target (uniform over the grid)
     extern __shared__ __align__(16) unsigned char smem[];
     const int s = blockIdx.x;
-    const int64_t c0 = tile_off[s], c1 = tile_off[s + 1];
+    const int64_t c0 = tile_off[s];
     const int s0 = tile_slot_off[s], ns = tile_slot_off[s + 1] - s0;
     T *Vs = reinterpret_cast<T *>(smem);  // [8][ns]: v'x v'y v'z w'x w'y w'z 1/m 1/I
-    __shared__ int64_t cstart[kMaxCol + 1];
-    __shared__ int ncol;
+    __shared__ int32_t cstart[kMaxCol + 1];
+    const int32_t *cs = blk_cs + (int64_t)s * (kMaxCol + 2);
+    const int ncol = cs[kMaxCol + 1];
     for (int i = threadIdx.x; i < ns; i += kBlkThreads) {
         const T *r = vel + 8 * (int64_t)slot_body[s0 + i];
 #pragma unroll
         for (int a = 0; a < 8; ++a) Vs[a * ns + i] = r[a];
     }
-    for (int c = threadIdx.x; c <= kMaxCol; c += kBlkThreads) cstart[c] = c1;
-    if (threadIdx.x == 0) ncol = 0;
-    __syncthreads();
-    for (int64_t p = c0 + threadIdx.x; p < c1; p += kBlkThreads) {
-        const int cp = sv.col[p];
-        if (p == c0 || sv.col[p - 1] != cp) cstart[cp] = p;
-        if (p == c1 - 1) ncol = cp + 1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)  // empty colours start where the next one does
-        for (int c = ncol - 1; c >= 0; --c)
-            if (cstart[c] == c1 && c + 1 <= kMaxCol) cstart[c] = cstart[c + 1];
+    for (int c = threadIdx.x; c <= ncol; c += kBlkThreads) cstart[c] = cs[c];
     __syncthreads();
     double sd = 0.0, sp = 0.0;
     for (int c = 0; c < ncol; ++c) {
-        const int64_t pa = cstart[c], pb = c + 1 < ncol ? cstart[c + 1] : c1;
+        const int64_t pa = c0 + cstart[c], pb = c0 + cstart[c + 1];
         for (int64_t p = pa + threadIdx.x; p < pb; p += kBlkThreads) {
             const int l1 = sv.ls[2 * p], l2 = sv.ls[2 * p + 1];
-            const int b1 = sv.j1[p], b2 = sv.j2[p];
+            // body indices are read only for ends outside the block's slots (walls and static bodies)
+            const int b1 = l1 >= 0 ? 0 : sv.j1[p], b2 = l2 >= 0 ? 0 : sv.j2[p];
             const T n[3] = {sv.nx[p], sv.ny[p], sv.nz[p]};
             const T a1 = sv.a1[p], a2 = sv.a2[p];
             const T P[3] = {sv.px[p], sv.py[p], sv.pz[p]};
@@ -751,6 +770,10 @@ static nbgs_status block_prepare_impl(nbgs_scene_t sc) {
     k_block_ends<<<grid_for(nc), kBlock, 0, s>>>(sw.j1.p, sw.j2.p, ssd, nc, nblk, N, sc->b.inv_mass, sc->body_cnt.p,
                                                   sc->tile_slot_off.p, sw.ls.p);
     NBGS_HIP(hipGetLastError());
+    // colour boundaries of every block's local contacts
+    NBGS_TRY(sc->blk_cs.reserve((size_t)nblk * (kMaxCol + 2)));
+    k_blk_colour_starts<<<(unsigned)nblk, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p);
+    NBGS_HIP(hipGetLastError());
     // colours of the contacts between blocks (the last id's range)
     const int64_t xb = toff[(size_t)nblk], xe = toff[(size_t)nsub];
     NBGS_TRY(sc->xcol_d.reserve(kMaxCol + 1 + kMaxCol));
@@ -928,10 +951,12 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
     const int32_t *slot_body = reinterpret_cast<const int32_t *>(sc->body_slots);  // bodies sorted by block
     if (mode == 0)
         k_blk_pass<T, 0><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
-                                                         sc->tile_slot_off.p, slot_body, sc->partials.p, sc->ctrl());
+                                                         sc->tile_slot_off.p, slot_body, sc->blk_cs.p, sc->partials.p,
+                                                         sc->ctrl());
     else
         k_blk_pass<T, 1><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
-                                                         sc->tile_slot_off.p, slot_body, sc->partials.p, sc->ctrl());
+                                                         sc->tile_slot_off.p, slot_body, sc->blk_cs.p, sc->partials.p,
+                                                         sc->ctrl());
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
