@@ -759,7 +759,9 @@ nbgs_status sub_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
     NBGS_TRY(corr.reserve(6 * (size_t)(sc->n_slots > 0 ? sc->n_slots : 1)));
     NBGS_TRY(sc->partials.reserve(2 * (size_t)sc->n_sub));
     NBGS_HIP(hipMemsetAsync(sc->ctrl(), 0, 4 * sizeof(int32_t), s));
-    sc->hist_partial = false;
+    // with a fixed sweep count and the history off only the last sweep's residual is formed
+    const bool every = target > 0.0 || sc->res_history;
+    sc->hist_partial = !every;
     sc->graph_pairs = 0;
     NBGS_TRY(subdomain_pass<T>(sc, 0, vel.p, corr.p));
     record(sc, kSweeps);
@@ -773,7 +775,10 @@ nbgs_status sub_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
             if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it)], s));
             NBGS_TRY(subdomain_pass<T>(sc, 1, vel.p, corr.p));
             if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it) + 1], s));
-            NBGS_TRY(launch_residual(sc->partials.p, sc->n_sub, target, sc->ctrl(), sc->res_hist.p, s));
+            if (every) NBGS_TRY(launch_residual(sc->partials.p, sc->n_sub, target, sc->ctrl(), sc->res_hist.p, s));
+            else if (launched + it + 1 == max_sweeps)
+                NBGS_TRY(launch_residual(sc->partials.p, sc->n_sub, target, sc->ctrl(), sc->res_hist.p, s,
+                                         max_sweeps - 1));
         }
         launched += k;
         if (target > 0.0 && launched < max_sweeps) {
@@ -812,7 +817,9 @@ nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
     }
     NBGS_TRY(sc->partials.reserve(2 * (size_t)(n_partials > 0 ? n_partials : 1)));
     NBGS_HIP(hipMemsetAsync(sc->ctrl(), 0, 4 * sizeof(int32_t), s));
-    sc->hist_partial = false;
+    // with a fixed sweep count and the history off only the last sweep's residual is formed
+    const bool every = target > 0.0 || sc->res_history;
+    sc->hist_partial = !every;
     sc->graph_pairs = 0;
     if (sc->p.warm_start != NBGS_WS_ZERO) {
         NBGS_TRY(block_pass<T>(sc, 0, vel.p));
@@ -834,7 +841,11 @@ nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
                 NBGS_TRY(launch_sweep_colour<T>(sw.view(), sc->xcol[c], sc->xcol[c + 1], N, vel.p, sp, tune,
                                                 sc->partials.p + 2 * sc->xpart_off[c], sc->ctrl(), s));
             if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it) + 1], s));
-            NBGS_TRY(launch_residual(sc->partials.p, (int32_t)n_partials, target, sc->ctrl(), sc->res_hist.p, s));
+            if (every)
+                NBGS_TRY(launch_residual(sc->partials.p, (int32_t)n_partials, target, sc->ctrl(), sc->res_hist.p, s));
+            else if (launched + it + 1 == max_sweeps)
+                NBGS_TRY(launch_residual(sc->partials.p, (int32_t)n_partials, target, sc->ctrl(), sc->res_hist.p, s,
+                                         max_sweeps - 1));
         }
         launched += k;
         if (target > 0.0 && launched < max_sweeps) {

@@ -139,3 +139,29 @@ def test_block_order_errors():
     with pytest.raises(nb.NbgsError):
         gb.set_block_order(2.0)
     gb.close()
+
+
+@pytest.mark.parametrize("mode", ["block", "subdomain"])
+def test_residual_history_off_forms_the_same_last_residual(mode):
+    """With a fixed sweep count and the history off the block-local and subdomain solves form only the last sweep's
+    residual: the same value from the same partial sums, the same impulses; earlier entries read as NaN."""
+    nb = _nb()
+    sc = sg.packed_cluster(69, counts=(10, 8, 6))
+    sc.relax = 0.75
+    runs = []
+    for hist in (True, False):
+        g = nb.GpuScene(sc.copy())
+        if mode == "block":
+            g.set_block_order(2.5)
+        else:
+            g.set_subdomains(2.5)
+        g.set_residual_history(hist)
+        for _ in range(2):
+            st = g.step(30)
+        runs.append((g.contacts()["P"], g.state()["vel"], g.residuals(), st))
+        g.close()
+    (Pa, va, ra, sa), (Pb, vb, rb, sb) = runs
+    assert np.array_equal(Pa, Pb) and np.array_equal(va, vb)
+    assert sa["sweeps"] == sb["sweeps"] == 30 and len(ra) == len(rb) == 30
+    assert sa["residual"] == ra[-1] and sb["residual"] == rb[-1] and ra[-1] == rb[-1]
+    assert np.all(np.isnan(rb[:-1])) and np.all(np.isfinite(ra))
