@@ -301,7 +301,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     // count, scan, emit
     NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
                                sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p,
-                               sc->maxbits.p + 1, s));
+                               sc->npart.p, sc->partners.p, sc->maxbits.p + 1, s));
     NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, N, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_HIP(hipMemcpyAsync(sc->pinned + 4, sc->maxbits.p + 1, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                             s));
@@ -336,7 +336,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_TRY(cb.reserve((size_t)nc));
     NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p, sc->off.p,
-                              sc->cellpos.p, cb.view(), s));
+                              sc->cellpos.p, sc->npart.p, sc->partners.p, cb.view(), s));
     // initial impulses and, when the previous table carries colours, the start of the colouring
     const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
@@ -1130,6 +1130,8 @@ nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int6
     chk(sc->ids2.reserve(N, 1.0));
     chk(sc->sxr.reserve(N, 1.0));
     chk(sc->cnt.reserve(N + 1, 1.0));
+    chk(sc->npart.reserve(N, 1.0));
+    chk(sc->partners.reserve((size_t)kPartnerCap * N, 1.0));
     chk(sc->cellpos.reserve(N, 1.0));
     chk(sc->off.reserve(N + 1, 1.0));
     chk(sc->deg2.reserve(N + 1, 1.0));

@@ -168,11 +168,12 @@ __device__ inline bool plane_hit(const PlaneSet &pl, int w, double x, double y, 
 constexpr int kMaxCandidates = 1 << 18;
 
 // Partners of body i with k > i, hull overlap tested on the sorted entries;
-// the count variant returns -1 once the candidates pass kMaxCandidates.
+// the count variant returns -1 once the candidates pass kMaxCandidates and
+// keeps the first `cap` partners found in out_k (the emit variant keeps all).
 template <bool kEmit>
 __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const uint32_t *sids, const double4 *sxr,
                                      const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
-                                     uint32_t stamp, int p, int i, int32_t *out_k) {
+                                     uint32_t stamp, int p, int i, int32_t *out_k, int cap = 0) {
     const double4 me = sxr[p];
     int c[3];
     const NeighbourRange nr = neighbour_range(skeys[p], g, c);
@@ -193,7 +194,7 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
                     const double4 o = sxr[q];
                     if (me.w < 0.0 && o.w < 0.0) continue;  // two static bodies
                     if (!hull_hit(me, o, g)) continue;
-                    if (kEmit) out_k[m] = k;
+                    if (kEmit || m < cap) out_k[m] = k;
                     ++m;
                 }
             }
@@ -205,6 +206,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, Pl
                                                        const double4 *sxr, const double *h,
                                                        const int32_t *cell_start, const int32_t *cell_end,
                                                        const uint32_t *cell_stamp, uint32_t stamp, int32_t *cnt,
+                                                       int32_t *npart, int32_t *partners,
                                                        unsigned long long *total) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     unsigned long long m64 = 0;
@@ -214,11 +216,13 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, Pl
         const int sc = st.body_scene ? st.body_scene[i] : 0;
         const Grid &g = st.body_scene ? st.grids[sc] : g0;
         const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
-        int m = visit_partners<false>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, nullptr);
+        int m = visit_partners<false>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i,
+                                      partners + (int64_t)kPartnerCap * i, kPartnerCap);
         if (m < 0) {
             over = 1;
             m = 0;
         }
+        npart[i] = m;
         if (b.inv_mass[i] != 0.0) {
             const double4 me = sxr[p];
             const double r = b.radius[i], hi = h[i];
@@ -292,13 +296,15 @@ __device__ inline void sort_partners(int32_t *ks, int m) {
 
 // One thread per body in index order, so that consecutive threads write
 // consecutive segments of the canonical list; bodies without contacts leave
-// at once.
+// at once.  A body whose partners all fit in the count's store copies them
+// from there; only a longer list is searched again.
 __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                       const uint32_t *skeys, const uint32_t *sids,
                                                       const double4 *sxr, const double *h,
                                                       const int32_t *cell_start, const int32_t *cell_end,
                                                       const uint32_t *cell_stamp, uint32_t stamp, const int32_t *cnt,
-                                                      const int32_t *off, const int32_t *cellpos, ContactsView c) {
+                                                      const int32_t *off, const int32_t *cellpos,
+                                                      const int32_t *npart, const int32_t *partners, ContactsView c) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= b.n || cnt[i] == 0) return;
     const int p = cellpos[i];
@@ -308,7 +314,13 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, Pla
     const int wall0 = b.n + (st.body_scene ? st.wall_off[sc] : 0);
     const int base = off[i];
     int32_t *ks = c.j2 + base;
-    const int m = visit_partners<true>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, ks);
+    int m = npart[i];
+    if (m <= kPartnerCap) {
+        const int32_t *kept = partners + (int64_t)kPartnerCap * i;
+        for (int t = 0; t < m; ++t) ks[t] = kept[t];
+    } else {
+        m = visit_partners<true>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, ks);
+    }
     sort_partners(ks, m);
     const double xi_ = b.x[i], yi = b.y[i], zi = b.z[i], ri = b.radius[i];
     for (int t = 0; t < m; ++t) {
@@ -443,10 +455,11 @@ nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *ske
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                               const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
-                              uint32_t stamp, int32_t *cnt, unsigned long long *total, hipStream_t s) {
+                              uint32_t stamp, int32_t *cnt, int32_t *npart, int32_t *partners,
+                              unsigned long long *total, hipStream_t s) {
     if (b.n <= 0) return NBGS_OK;
     k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
-                                                  cell_stamp, stamp, cnt, total);
+                                                  cell_stamp, stamp, cnt, npart, partners, total);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -455,9 +468,9 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
                              uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
-                             ContactsView c, hipStream_t s) {
+                             const int32_t *npart, const int32_t *partners, ContactsView c, hipStream_t s) {
     k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
-                                                 cell_stamp, stamp, cnt, off, cellpos, c);
+                                                 cell_stamp, stamp, cnt, off, cellpos, npart, partners, c);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

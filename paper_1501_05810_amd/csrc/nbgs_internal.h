@@ -157,6 +157,8 @@ nbgs_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
 size_t radix_hist_entries(int64_t n);
 
 // detect.hip
+// Partners (k > i) of a body kept by the pair count for the emit; longer lists are searched again.
+constexpr int kPartnerCap = 16;
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
                         hipStream_t s);
 nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, uint32_t *keys, uint32_t *ids,
@@ -167,12 +169,13 @@ nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *ske
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                               const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
-                              uint32_t stamp, int32_t *cnt, unsigned long long *total, hipStream_t s);
+                              uint32_t stamp, int32_t *cnt, int32_t *npart, int32_t *partners,
+                              unsigned long long *total, hipStream_t s);
 nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
                              uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
-                             ContactsView c, hipStream_t s);
+                             const int32_t *npart, const int32_t *partners, ContactsView c, hipStream_t s);
 nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
                               const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
                               int64_t n_prev, double mu, const SceneTable &st, bool impulses, bool colours,

@@ -103,6 +103,7 @@ struct nbgs_scene_s {
     DevBuf<uint32_t> keys, ids, keys2, ids2;
     DevBuf<double4> sxr;
     DevBuf<int32_t> cnt, off, cellpos;
+    DevBuf<int32_t> npart, partners;  // the pair count's partner store (kPartnerCap per body) for the emit
     DevBuf<int32_t> deg2, off2, cursor;
     DevBuf<double> vel64;
     DevBuf<float> vel32;
