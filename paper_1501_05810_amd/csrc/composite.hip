@@ -178,11 +178,13 @@ __device__ inline double min_image(double d, int periodic, double L) {
 
 // Partner elements f of element e (sorted position p, body A) on bodies B > A
 // whose grown spheres meet it; the count variant returns -1 past
-// kMaxCandidates.
+// kMaxCandidates and keeps the first `cap` partners found in out (the emit
+// variant keeps all).
 template <bool kEmit>
 __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const uint32_t *sids, const double4 *sec,
                                      const int32_t *sbody, const int32_t *cell_start, const int32_t *cell_end,
-                                     const uint32_t *cell_stamp, uint32_t stamp, int p, int A, int32_t *out) {
+                                     const uint32_t *cell_stamp, uint32_t stamp, int p, int A, int32_t *out,
+                                     int cap = 0) {
     const double4 me = sec[p];
     const uint32_t key = skeys[p];
     int c[3];
@@ -227,7 +229,7 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
                     const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
                     const double reach = fabs(me.w) + fabs(o.w);
                     if (!(d2 <= reach * reach)) continue;
-                    if (kEmit) out[m] = (int32_t)sids[s];
+                    if (kEmit || m < cap) out[m] = (int32_t)sids[s];
                     ++m;
                 }
             }
@@ -250,6 +252,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(int64_t ne, Grid g, Plane
                                                        const double *erad, const double *h,
                                                        const int32_t *cell_start, const int32_t *cell_end,
                                                        const uint32_t *cell_stamp, uint32_t stamp, int32_t *cnt,
+                                                       int32_t *npart, int32_t *partners,
                                                        unsigned long long *total) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     unsigned long long m64 = 0;
@@ -258,11 +261,12 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(int64_t ne, Grid g, Plane
         const int e = (int)sids[p];
         const int A = sbody[p];
         int m = visit_partners<false>(g, skeys, sids, sec, sbody, cell_start, cell_end, cell_stamp, stamp, (int)p, A,
-                                      nullptr);
+                                      partners + (int64_t)kPartnerCap * e, kPartnerCap);
         if (m < 0) {
             over = 1;
             m = 0;
         }
+        npart[e] = m;
         const double4 me = sec[p];
         if (me.w >= 0.0) {
             double gap;
@@ -330,7 +334,9 @@ __device__ inline void sort_partners(int32_t *ks, int m) {
 }
 
 // One thread per element in index order: its segment of the canonical list,
-// partners on higher bodies in ascending element index, then walls.
+// partners on higher bodies in ascending element index, then walls.  The
+// partners come from the count's store when they all fit, else from a new
+// search.
 // Geometry of a pair (eq. (contactpos) for two spheres): n from c_f to c_e,
 // xi = |c_e - c_f| - r_e - r_f, lever arms from the centres of mass
 // r1 = R_A o_e - (r_e + xi) n, r2 = R_B o_f + r_f n.
@@ -340,6 +346,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(int64_t ne, int32_t nb, Gr
                                                       const int32_t *cell_start, const int32_t *cell_end,
                                                       const uint32_t *cell_stamp, uint32_t stamp,
                                                       const int32_t *cnt, const int32_t *off,
+                                                      const int32_t *npart, const int32_t *partners,
                                                       const int32_t *cellpos, const double4 *ec,
                                                       const int32_t *ebody, const double *erad, const double *h,
                                                       const double *owx, const double *owy, const double *owz,
@@ -350,7 +357,13 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(int64_t ne, int32_t nb, Gr
     const int A = ebody[e];
     const int base = off[e];
     int32_t *ks = c.e2 + base;
-    const int m = visit_partners<true>(g, skeys, sids, sec, sbody, cell_start, cell_end, cell_stamp, stamp, p, A, ks);
+    int m = npart[e];
+    if (m <= kPartnerCap) {
+        const int32_t *kept = partners + (int64_t)kPartnerCap * e;
+        for (int t = 0; t < m; ++t) ks[t] = kept[t];
+    } else {
+        m = visit_partners<true>(g, skeys, sids, sec, sbody, cell_start, cell_end, cell_stamp, stamp, p, A, ks);
+    }
     sort_partners(ks, m);
     const double4 ce = ec[e];
     const double re = erad[e];
@@ -863,7 +876,7 @@ struct nbgs_composite_s {
     nbgs_params p{};
     Grid grid{};
     DevBuf<int32_t> ebody, sbody, cellpos, cnt, off, off1, cnt1, deg2, off2, cursor, inc2, cell_start, cell_end,
-        radix_hist, spos, small, ctrl;
+        radix_hist, spos, small, ctrl, npart, partners;
     DevBuf<uint32_t> keys, ids, keys2, ids2, cell_stamp, ckeys, cids, ckeys2, cids2;
     DevBuf<double4> ec, sec;
     DevBuf<double> h, owx, owy, owz, vel, iw, partials, hist;
@@ -948,7 +961,8 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
     NBGS_HIP(hipGetLastError());
     k_pair_count<<<grid_for(E), kBlock, 0, s>>>(E, g, sc->planes, sc->p.tau, skeys, sids, sc->sec.p, sc->sbody.p,
                                                 sc->b.elem_radius, sc->h.p, sc->cell_start.p, sc->cell_end.p,
-                                                sc->cell_stamp.p, sc->stamp, sc->cnt.p, sc->maxbits.p + 1);
+                                                sc->cell_stamp.p, sc->stamp, sc->cnt.p, sc->npart.p, sc->partners.p,
+                                                sc->maxbits.p + 1);
     NBGS_HIP(hipGetLastError());
     NBGS_HIP(hipMemsetAsync(sc->cnt.p + E, 0, sizeof(int32_t), s));  // off[E] = the total
     NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, E + 1, sc->small.p, sc->scan_tmp.p, sc->scan_tmp.cap, s));
@@ -978,7 +992,8 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
     NBGS_TRY(cb.reserve((size_t)(nc > 0 ? nc : 1)));
     k_pair_emit<<<grid_for(E), kBlock, 0, s>>>(E, N, g, sc->planes, sc->p.tau, skeys, sids, sc->sec.p, sc->sbody.p,
                                                sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp,
-                                               sc->cnt.p, sc->off.p, sc->cellpos.p, sc->ec.p, sc->ebody.p,
+                                               sc->cnt.p, sc->off.p, sc->npart.p, sc->partners.p, sc->cellpos.p,
+                                               sc->ec.p, sc->ebody.p,
                                                sc->b.elem_radius, sc->h.p, sc->owx.p, sc->owy.p, sc->owz.p, cb.view());
     NBGS_HIP(hipGetLastError());
     // initial impulses: the previous step's, matched by key and re-projected onto the new cone, else zero
@@ -1315,6 +1330,8 @@ nbgs_status nbgs_composite_create(const nbgs_composite_bodies *bodies, const nbg
     }
     for (DevBuf<int32_t> *bb : {&sc->ebody, &sc->sbody, &sc->cellpos}) NBGS_TRY(bb->reserve(E, 1.0));
     NBGS_TRY(sc->cnt.reserve(E + 1, 1.0));
+    NBGS_TRY(sc->npart.reserve(E, 1.0));
+    NBGS_TRY(sc->partners.reserve((size_t)kPartnerCap * E, 1.0));
     NBGS_TRY(sc->off.reserve(E + 1, 1.0));
     for (DevBuf<int32_t> *bb : {&sc->off1, &sc->cnt1}) NBGS_TRY(bb->reserve(N, 1.0));
     for (DevBuf<int32_t> *bb : {&sc->deg2, &sc->off2, &sc->cursor}) NBGS_TRY(bb->reserve(N + 1, 1.0));

@@ -38,7 +38,14 @@ CASES = {
     "frictionless": lambda: sg.composite_cluster(35, counts=(4, 4, 3), mu=0.0),
     "spheres": lambda: sg.from_spheres(sg.packed_cluster(36, counts=(5, 4, 4))),
     "gas": lambda: sg.composite_gas(37, counts=(6, 6, 6), vmax=2.0, dt=5e-4),
+    "fast body": lambda: _fast(sg.composite_cluster(42, counts=(5, 4, 4))),
 }
+
+
+def _fast(cs):
+    # one body fast enough that an element meets more partners than the pair count keeps (the emit searches again)
+    cs.vel[0] = (60.0, 0.0, 0.0)
+    return cs
 
 
 def _compare(g, w, n_elements, step):
