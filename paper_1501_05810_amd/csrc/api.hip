@@ -248,7 +248,7 @@ nbgs_status gather_for_sweeps(nbgs_scene_t sc) {
     sw.per_contact_mu = sc->n_scenes > 1;
     sw.sub = sc->sub_active || sc->blk_active;
     NBGS_TRY(sw.reserve((size_t)sc->nc));
-    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), sc->spos.p, sw.sub ? sc->sdom.p : nullptr, sc->nc,
+    return launch_gather_sweep<T>(sc->cb[sc->cur].view(), sc->perm, sw.sub ? sc->sdom.p : nullptr, sc->nc,
                                   sc->p.dt, sc->p.erp, sc->table(), sw.view(), sc->s);
 }
 
@@ -452,8 +452,6 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     const uint32_t *perm = calt ? sc->cids2.p : sc->cids.p;
     if (nc == 1) perm = sc->cids.p;
     sc->perm = perm;
-    NBGS_TRY(sc->spos.reserve((size_t)nc + 1));
-    NBGS_TRY(launch_invert(perm, nc, sc->spos.p, s));
     sc->precision_used = sc->p.precision;
     NBGS_TRY(scene_gather(sc));
     if (sc->sub_active) NBGS_TRY(subdomain_prepare(sc));

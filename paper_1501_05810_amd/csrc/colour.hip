@@ -220,16 +220,16 @@ __global__ void __launch_bounds__(kBlock) k_invert(const uint32_t *perm, int64_t
     if (p < nc) pos[perm[p]] = (int32_t)p;
 }
 
-// Canonical record j -> sweep position pos[j].  One thread per canonical
-// contact: the reads stream, and the writes of a colour land in ascending
-// positions, which the L2 merges into whole lines.
+// Sweep position p <- canonical record perm[p].  One thread per sweep
+// position: the writes stream, and the reads of neighbouring positions (one
+// colour of one region of the box) fall on a few canonical segments.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_gather_sweep(ContactsView c, const int32_t *pos, const int32_t *sdom,
+__global__ void __launch_bounds__(kBlock) k_gather_sweep(ContactsView c, const uint32_t *perm, const int32_t *sdom,
                                                          int64_t nc, double dt, double erp, SceneTable st,
                                                          SweepView<T> sv) {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= nc) return;
-    const int64_t p = pos[j];
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nc) return;
+    const int64_t j = perm[p];
     sv.perm[p] = (int32_t)j;
     if (sv.col) sv.col[p] = c.colour[j];
     if (sv.sdom) sv.sdom[p] = sdom[j];
@@ -324,17 +324,17 @@ nbgs_status launch_invert(const uint32_t *perm, int64_t nc, int32_t *pos, hipStr
 }
 
 template <class T>
-nbgs_status launch_gather_sweep(const ContactsView &c, const int32_t *pos, const int32_t *sdom, int64_t nc, double dt,
-                                double erp, const SceneTable &st, SweepView<T> sv, hipStream_t s) {
+nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, const int32_t *sdom, int64_t nc,
+                                double dt, double erp, const SceneTable &st, SweepView<T> sv, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, pos, sdom, nc, dt, erp, st, sv);
+    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, perm, sdom, nc, dt, erp, st, sv);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
-template nbgs_status launch_gather_sweep<double>(const ContactsView &, const int32_t *, const int32_t *, int64_t,
+template nbgs_status launch_gather_sweep<double>(const ContactsView &, const uint32_t *, const int32_t *, int64_t,
                                                  double, double, const SceneTable &, SweepView<double>, hipStream_t);
-template nbgs_status launch_gather_sweep<float>(const ContactsView &, const int32_t *, const int32_t *, int64_t,
+template nbgs_status launch_gather_sweep<float>(const ContactsView &, const uint32_t *, const int32_t *, int64_t,
                                                 double, double, const SceneTable &, SweepView<float>, hipStream_t);
 
 }  // namespace nbgs

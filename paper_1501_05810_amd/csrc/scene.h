@@ -128,7 +128,6 @@ struct nbgs_scene_s {
     int32_t colour_passes = 0;  // > 0: passes from the previous colours, < 0: Jones-Plassmann rounds
     DevBuf<uint32_t> ckeys, cids, ckeys2, cids2;
     const uint32_t *perm = nullptr;  // sweep position -> canonical index (in ckeys/cids storage)
-    DevBuf<int32_t> spos;            // canonical index -> sweep position
     SweepBuf<double> sw64;
     SweepBuf<float> sw32;
     int32_t n_colours = 0;
