@@ -252,6 +252,9 @@ nbgs_status gather_for_sweeps(nbgs_scene_t sc) {
                                   sc->p.dt, sc->p.erp, sc->table(), sw.view(), sc->s);
 }
 
+nbgs_status colour_and_order(nbgs_scene_t sc, ContactBuf &cb, const SceneTable &tab, const int32_t *sdom,
+                             bool warm_colours);
+
 nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     hipStream_t s = sc->s;
     const int32_t N = sc->b.n;
@@ -340,12 +343,14 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     // initial impulses and, when the previous table carries colours, the start of the colouring
     const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
+    // new pairs are counted when the previous colouring may be reused whole (same pair count)
+    const bool maybe_same = warm_colours && nc == sc->n_prev;
+    if (maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 4, 0, 2 * sizeof(int32_t), s));
     NBGS_TRY(launch_match_prev(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p, sc->n_prev,
-                               sc->p.mu, tab, warm_impulses, warm_colours, s));
-    if (!warm_impulses) {
-        NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
-        NBGS_TRY(launch_fill_i32(cb.matched.p, nc, 0, s));
-    }
+                               sc->p.mu, tab, warm_impulses, warm_colours, maybe_same ? sc->small.p + 4 : nullptr,
+                               s));
+    if (!warm_impulses) NBGS_TRY(launch_zero_impulses(cb.view(), nc, s));
+    if (!warm_impulses && !warm_colours) NBGS_TRY(launch_fill_i32(cb.matched.p, nc, 0, s));
     // network features and prediction (from the state before the step and the previous impulses)
     sc->have_features = false;
     sc->have_learned = false;
@@ -373,6 +378,51 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     if (sc->sub_active) NBGS_TRY(subdomain_assign(sc));
     if (sc->blk_active) NBGS_TRY(block_assign(sc));
     const int32_t *sdom = sc->sub_active || sc->blk_active ? sc->sdom.p : nullptr;
+    // The greedy colouring and the (id, colour, key) order are functions of the pair keys, the ids, the seed and the
+    // static bodies only.  When every pair of this step is a pair of the last one (same count, none new), every id
+    // is the same and the mode and seed are too, the last colours (already copied by the match), colour counts and
+    // sweep permutation are this step's.
+    const double sig[4] = {(double)sc->p.colour_seed, sc->sub_active ? sc->sub_edge : -1.0,
+                           sc->blk_active ? sc->blk_edge : -1.0, (double)(sdom ? sc->n_sub : 0)};
+    bool same = maybe_same && sc->prev_sig_valid && std::memcmp(sig, sc->prev_sig, sizeof(sig)) == 0 &&
+                sc->prev_seed == sc->p.colour_seed && sc->perm != nullptr;
+    if (same && sdom) NBGS_TRY(launch_ids_changed(sdom, sc->prev_sdom.p, cb.matched.p, nc, sc->small.p + 5, s));
+    if (same) {
+        NBGS_TRY(sync_small(sc, 4, 2));
+        same = sc->pinned[4] == 0 && sc->pinned[5] == 0;
+    }
+    sc->colouring_reused = same;
+    if (same) sc->colour_passes = 0;
+    else NBGS_TRY(colour_and_order(sc, cb, tab, sdom, warm_colours));
+    // ids of this step's pairs, for the next step's comparison
+    if (sdom) {
+        NBGS_TRY(sc->prev_sdom.reserve((size_t)nc));
+        NBGS_HIP(hipMemcpyAsync(sc->prev_sdom.p, sdom, sizeof(int32_t) * nc, hipMemcpyDeviceToDevice, s));
+    }
+    std::memcpy(sc->prev_sig, sig, sizeof(sig));
+    sc->prev_seed = sc->p.colour_seed;
+    sc->prev_sig_valid = nc > 0;
+    sc->precision_used = sc->p.precision;
+    NBGS_TRY(scene_gather(sc));
+    if (sc->sub_active) NBGS_TRY(subdomain_prepare(sc));
+    if (sc->blk_active) NBGS_TRY(block_prepare(sc));
+    sc->state = 1;
+    sc->stats.n_contacts = nc;
+    sc->stats.n_colours = sc->n_colours;
+    sc->stats.sweeps = 0;
+    sc->stats.residual = 0.0;
+    record(sc, kInit);
+    if (stats) *stats = sc->stats;
+    return NBGS_OK;
+}
+
+// Greedy colouring (from the previous colours where the match supplied them, else Jones-Plassmann rounds from
+// scratch), the colour histogram and the colour-major (id, colour, key) permutation.
+nbgs_status colour_and_order(nbgs_scene_t sc, ContactBuf &cb, const SceneTable &tab, const int32_t *sdom,
+                             bool warm_colours) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    const int64_t nc = sc->nc;
     // colouring: body -> contacts where it is j2 (as j1 it owns the segment off[i] .. off[i] + cnt[i])
     NBGS_TRY(sc->inc2.reserve((size_t)(nc > 0 ? nc : 1)));
     NBGS_TRY(sc->prio.reserve((size_t)(nc > 0 ? nc : 1)));
@@ -452,17 +502,6 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     const uint32_t *perm = calt ? sc->cids2.p : sc->cids.p;
     if (nc == 1) perm = sc->cids.p;
     sc->perm = perm;
-    sc->precision_used = sc->p.precision;
-    NBGS_TRY(scene_gather(sc));
-    if (sc->sub_active) NBGS_TRY(subdomain_prepare(sc));
-    if (sc->blk_active) NBGS_TRY(block_prepare(sc));
-    sc->state = 1;
-    sc->stats.n_contacts = nc;
-    sc->stats.n_colours = sc->n_colours;
-    sc->stats.sweeps = 0;
-    sc->stats.residual = 0.0;
-    record(sc, kInit);
-    if (stats) *stats = sc->stats;
     return NBGS_OK;
 }
 

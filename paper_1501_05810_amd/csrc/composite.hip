@@ -1002,7 +1002,7 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
     const bool warm_colours = sc->n_prev > 0 && nc > 0;
     const SceneTable tab{};
     NBGS_TRY(launch_match_prev(cb.shared_view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p,
-                               sc->n_prev, sc->p.mu, tab, warm, warm_colours, s));
+                               sc->n_prev, sc->p.mu, tab, warm, warm_colours, nullptr, s));
     if (!warm && nc > 0) {
         NBGS_HIP(hipMemsetAsync(cb.px.p, 0, sizeof(double) * nc, s));
         NBGS_HIP(hipMemsetAsync(cb.py.p, 0, sizeof(double) * nc, s));

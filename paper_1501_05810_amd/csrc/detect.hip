@@ -374,6 +374,8 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, Pla
 }
 
 // Look each contact's pair key up in the previous step's key-sorted table.
+// matched: 1 + the previous index of the same pair, 0 if the pair is new;
+// unmatched (may be null): the number of new pairs is added to it.
 // impulses: the previous impulse of the same pair re-projected onto the new
 // cone (P_n = max(0, n.P), tangential part clipped to mu P_n), zero if the pair
 // is new.  colours: the previous colour as the start of the colouring passes
@@ -382,21 +384,36 @@ __global__ void __launch_bounds__(kBlock) k_match_prev(ContactsView c, int64_t n
                                                        const double *prev_px, const double *prev_py,
                                                        const double *prev_pz, const int32_t *prev_colour,
                                                        int64_t n_prev, double mu0, SceneTable st, int impulses,
-                                                       int colours) {
+                                                       int colours, int32_t *unmatched) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool found = false;
+    int64_t lo = 0;
+    if (j < nc) {
+        const uint64_t key = c.key[j];
+        int64_t hi = n_prev;
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (prev_key[mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        found = lo < n_prev && prev_key[lo] == key;
+    }
+    if (unmatched) {
+        const unsigned long long nf = __ballot(j < nc && !found);
+        __shared__ int wcount[kBlock / 64];
+        if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = __popcll(nf);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int w = 0; w < kBlock / 64; ++w) t += wcount[w];
+            if (t) atomicAdd(unmatched, t);
+        }
+    }
     if (j >= nc) return;
     const double mu = st.body_scene ? st.mu[st.body_scene[c.j1[j]]] : mu0;
-    const uint64_t key = c.key[j];
-    int64_t lo = 0, hi = n_prev;
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (prev_key[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    const bool found = lo < n_prev && prev_key[lo] == key;
+    c.matched[j] = found ? (int32_t)(lo + 1) : 0;
     if (colours) c.colour[j] = found ? prev_colour[lo] : 0;
     if (!impulses) return;
-    c.matched[j] = found ? 1 : 0;
     double P0 = 0.0, P1 = 0.0, P2 = 0.0;
     if (found) {
         const double n0 = c.nx[j], n1 = c.ny[j], n2 = c.nz[j];
@@ -419,6 +436,23 @@ __global__ void __launch_bounds__(kBlock) k_match_prev(ContactsView c, int64_t n
     c.px[j] = P0;
     c.py[j] = P1;
     c.pz[j] = P2;
+}
+
+// Contacts whose id (block or subdomain) differs from the one the same pair had
+// in the previous step (matched = 1 + previous index); every contact is matched.
+__global__ void __launch_bounds__(kBlock) k_ids_changed(const int32_t *sdom, const int32_t *prev_sdom,
+                                                        const int32_t *matched, int64_t nc, int32_t *changed) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool diff = j < nc && sdom[j] != prev_sdom[matched[j] - 1];
+    const unsigned long long m = __ballot(diff);
+    __shared__ int wcount[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wcount[w];
+        if (t) atomicAdd(changed, t);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -478,10 +512,18 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
 nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
                               const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
                               int64_t n_prev, double mu, const SceneTable &st, bool impulses, bool colours,
-                              hipStream_t s) {
+                              int32_t *unmatched, hipStream_t s) {
     if (nc == 0 || (!impulses && !colours)) return NBGS_OK;
     k_match_prev<<<grid_for(nc), kBlock, 0, s>>>(c, nc, prev_key, prev_px, prev_py, prev_pz, prev_colour, n_prev, mu,
-                                                 st, impulses ? 1 : 0, colours ? 1 : 0);
+                                                 st, impulses ? 1 : 0, colours ? 1 : 0, unmatched);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_ids_changed(const int32_t *sdom, const int32_t *prev_sdom, const int32_t *matched, int64_t nc,
+                               int32_t *changed, hipStream_t s) {
+    if (nc == 0) return NBGS_OK;
+    k_ids_changed<<<grid_for(nc), kBlock, 0, s>>>(sdom, prev_sdom, matched, nc, changed);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

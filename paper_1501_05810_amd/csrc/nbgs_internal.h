@@ -179,7 +179,9 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
 nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
                               const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
                               int64_t n_prev, double mu, const SceneTable &st, bool impulses, bool colours,
-                              hipStream_t s);
+                              int32_t *unmatched, hipStream_t s);
+nbgs_status launch_ids_changed(const int32_t *sdom, const int32_t *prev_sdom, const int32_t *matched, int64_t nc,
+                               int32_t *changed, hipStream_t s);
 nbgs_status launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 nbgs_status launch_zero_impulses(ContactsView c, int64_t nc, hipStream_t s);
 

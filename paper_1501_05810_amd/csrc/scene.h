@@ -128,6 +128,12 @@ struct nbgs_scene_s {
     int32_t colour_passes = 0;  // > 0: passes from the previous colours, < 0: Jones-Plassmann rounds
     DevBuf<uint32_t> ckeys, cids, ckeys2, cids2;
     const uint32_t *perm = nullptr;  // sweep position -> canonical index (in ckeys/cids storage)
+    // the last step's colouring inputs: ids of its pairs (canonical order), mode and seed; reused whole when equal
+    DevBuf<int32_t> prev_sdom;
+    double prev_sig[4] = {0.0, 0.0, 0.0, 0.0};
+    uint64_t prev_seed = 0;
+    bool prev_sig_valid = false;
+    bool colouring_reused = false;
     SweepBuf<double> sw64;
     SweepBuf<float> sw32;
     int32_t n_colours = 0;

@@ -165,3 +165,28 @@ def test_residual_history_off_forms_the_same_last_residual(mode):
     assert sa["sweeps"] == sb["sweeps"] == 30 and len(ra) == len(rb) == 30
     assert sa["residual"] == ra[-1] and sb["residual"] == rb[-1] and ra[-1] == rb[-1]
     assert np.all(np.isnan(rb[:-1])) and np.all(np.isfinite(ra))
+
+
+def test_colouring_follows_ids_when_pairs_stay():
+    """A row of three touching spheres drifts across a block face: the pairs stay the same, but the ids of their
+    contacts change (local, then one between blocks, then local in the next block), and with them the restricted
+    colouring; the colours and order must follow the oracle's at every step (the last step's colouring is reused
+    only while pairs and ids are both unchanged)."""
+    nb = _nb()
+    pos = [[0.5, 5.0, 5.0], [1.5, 5.0, 5.0], [2.5, 5.0, 5.0]]
+    sc = sg.scenes._make(np.array(pos), np.array([0.5, 0.5, 0.5]), vel=np.array([[1.0, 0.0, 0.0]] * 3),
+                         lo=(0.0, 0.0, 0.0), hi=(10.0, 10.0, 10.0), periodic=(False, False, False), planes=[],
+                         gravity=(0.0, 0.0, 0.0), dt=0.2, mu=0.5, tau=0.01)
+    g = nb.GpuScene(sc.copy()).set_block_order(5.0)
+    w = oracle.World(sc.copy()).set_block_order(5.0)
+    ids_seen = set()
+    for step in range(30):
+        g.step(4)
+        w.step(4, grid=True)
+        v = w.view()
+        c = g.contacts()
+        assert v["n_contacts"] == 2
+        ids_seen.add(tuple(v["sdom"].tolist()))
+        assert np.array_equal(c["key"], v["key"]) and np.array_equal(c["colour"], v["colour"]), step
+        assert np.array_equal(g.state()["pos"], w.sc.pos), step
+    assert len(ids_seen) >= 3  # local, mixed, local in the next block
