@@ -345,7 +345,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
     // new pairs are counted when the previous colouring may be reused whole (same pair count)
     const bool maybe_same = warm_colours && nc == sc->n_prev;
-    if (maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 4, 0, 2 * sizeof(int32_t), s));
+    if (maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 4, 0, 3 * sizeof(int32_t), s));
     NBGS_TRY(launch_match_prev(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p, sc->n_prev,
                                sc->p.mu, tab, warm_impulses, warm_colours, maybe_same ? sc->small.p + 4 : nullptr,
                                s));
@@ -376,7 +376,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     sc->sub_active = sc->sub_edge > 0.0 && nc > 0;
     sc->blk_active = !sc->sub_active && sc->blk_edge > 0.0 && nc > 0;
     if (sc->sub_active) NBGS_TRY(subdomain_assign(sc));
-    if (sc->blk_active) NBGS_TRY(block_assign(sc));
+    if (sc->blk_active) NBGS_TRY(block_assign(sc, sc->small.p + 6));
     const int32_t *sdom = sc->sub_active || sc->blk_active ? sc->sdom.p : nullptr;
     // The greedy colouring and the (id, colour, key) order are functions of the pair keys, the ids, the seed and the
     // static bodies only.  When every pair of this step is a pair of the last one (same count, none new), every id
@@ -387,9 +387,13 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     bool same = maybe_same && sc->prev_sig_valid && std::memcmp(sig, sc->prev_sig, sizeof(sig)) == 0 &&
                 sc->prev_seed == sc->p.colour_seed && sc->perm != nullptr;
     if (same && sdom) NBGS_TRY(launch_ids_changed(sdom, sc->prev_sdom.p, cb.matched.p, nc, sc->small.p + 5, s));
+    // the block set-up (slots, per-id ranges, cross colours) depends on these and on every body's block
+    bool prep_same = false;
     if (same) {
-        NBGS_TRY(sync_small(sc, 4, 2));
+        NBGS_TRY(sync_small(sc, 4, 3));
         same = sc->pinned[4] == 0 && sc->pinned[5] == 0;
+        prep_same = same && sc->blk_active && sc->bblk_compared && sc->pinned[6] == 0 &&
+                    sc->prev_precision == sc->p.precision;
     }
     sc->colouring_reused = same;
     if (same) sc->colour_passes = 0;
@@ -405,7 +409,11 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     sc->precision_used = sc->p.precision;
     NBGS_TRY(scene_gather(sc));
     if (sc->sub_active) NBGS_TRY(subdomain_prepare(sc));
-    if (sc->blk_active) NBGS_TRY(block_prepare(sc));
+    if (sc->blk_active && !prep_same) NBGS_TRY(block_prepare(sc));
+    sc->blk_prep_reused = prep_same;
+    sc->prev_precision = sc->p.precision;
+    if (sc->blk_active) sc->bblk_cur = 1 - sc->bblk_cur;
+    sc->bblk_valid = sc->blk_active;
     sc->state = 1;
     sc->stats.n_contacts = nc;
     sc->stats.n_colours = sc->n_colours;

@@ -134,6 +134,12 @@ struct nbgs_scene_s {
     uint64_t prev_seed = 0;
     bool prev_sig_valid = false;
     bool colouring_reused = false;
+    int32_t prev_precision = -1;
+    // every body's block in the block-local order, this step's and the last one's (alternating)
+    DevBuf<uint32_t> bblk[2];
+    int bblk_cur = 0;
+    bool bblk_valid = false, bblk_compared = false, blk_prep_reused = false;
+    int64_t bblk_nblocks = 0;
     SweepBuf<double> sw64;
     SweepBuf<float> sw32;
     int32_t n_colours = 0;
@@ -283,7 +289,9 @@ nbgs_status subdomain_pass(nbgs_scene_t sc, int mode, T *vel, T *corr);
 // tables and the cross colours' ranges (after the gather), and the pass over
 // the local part (mode 0: initial impulses, 1: relaxation), each block's
 // velocities updated in place in LDS.
-nbgs_status block_assign(nbgs_scene_t sc);
+// Contact ids of the block-local order; every body's block, the number that changed since the last step added to
+// changed.
+nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed);
 nbgs_status block_prepare(nbgs_scene_t sc);
 template <class T>
 nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel);

@@ -178,6 +178,27 @@ __global__ void __launch_bounds__(kBlock) k_body_blocks(BodiesView b, Blocks bl,
     vals[i] = (uint32_t)i;
 }
 
+// The same keys kept for the next step, and the number of bodies whose key differs from the last step's.
+__global__ void __launch_bounds__(kBlock) k_body_blocks_cmp(BodiesView b, Blocks bl, int32_t nblocks, uint32_t *cur,
+                                                            const uint32_t *prev, int compare, int32_t *changed) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    bool diff = false;
+    if (i < b.n) {
+        const uint32_t k = (uint32_t)(b.inv_mass[i] > 0.0 ? block_of(b, bl, i) : nblocks);
+        cur[i] = k;
+        diff = compare && prev[i] != k;
+    }
+    const unsigned long long m = __ballot(diff);
+    __shared__ int wcount[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wcount[w];
+        if (t) atomicAdd(changed, t);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_slot_of(const uint32_t *sorted_body, int32_t n, int32_t *slot) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p < n) slot[sorted_body[p]] = p;
@@ -680,7 +701,7 @@ nbgs_status subdomain_assign(nbgs_scene_t sc) {
 }
 
 // Block-local ids of the contacts: ids 0 .. n_blk - 1 local, n_blk between blocks.
-nbgs_status block_assign(nbgs_scene_t sc) {
+nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed) {
     hipStream_t s = sc->s;
     Blocks bl;
     int64_t nblocks = 1;
@@ -692,6 +713,18 @@ nbgs_status block_assign(nbgs_scene_t sc) {
     const ContactsView c = sc->cb[sc->cur].view();
     k_block_local<<<grid_for(nc), kBlock, 0, s>>>(sc->b, c.j1, c.j2, nc, bl, (int32_t)nblocks, sc->sdom.p);
     NBGS_HIP(hipGetLastError());
+    // every body's block, compared with the last step's (bodies without local contacts count too: they decide the
+    // slots); the number of changes is added to changed
+    const int32_t N = sc->b.n;
+    NBGS_TRY(sc->bblk[0].reserve((size_t)N + 1));
+    NBGS_TRY(sc->bblk[1].reserve((size_t)N + 1));
+    const int k = sc->bblk_cur;
+    const int compare = sc->bblk_valid && sc->bblk_nblocks == nblocks ? 1 : 0;
+    k_body_blocks_cmp<<<grid_for(N), kBlock, 0, s>>>(sc->b, bl, (int32_t)nblocks, sc->bblk[k].p, sc->bblk[1 - k].p,
+                                                     compare, changed);
+    NBGS_HIP(hipGetLastError());
+    sc->bblk_compared = compare != 0;
+    sc->bblk_nblocks = nblocks;
     return NBGS_OK;
 }
 
