@@ -243,13 +243,13 @@ nbgs_status sync_small(nbgs_scene_t sc, int first, int count) {
 }
 
 template <class T>
-nbgs_status gather_for_sweeps(nbgs_scene_t sc) {
+nbgs_status gather_for_sweeps(nbgs_scene_t sc, bool indices) {
     SweepBuf<T> &sw = sweep_buf<T>(sc);
     sw.per_contact_mu = sc->n_scenes > 1;
     sw.sub = sc->sub_active || sc->blk_active;
     NBGS_TRY(sw.reserve((size_t)sc->nc));
     return launch_gather_sweep<T>(sc->cb[sc->cur].view(), sc->perm, sw.sub ? sc->sdom.p : nullptr, sc->nc,
-                                  sc->p.dt, sc->p.erp, sc->table(), sw.view(), sc->s);
+                                  sc->p.dt, sc->p.erp, sc->table(), sw.view(), indices, sc->s);
 }
 
 nbgs_status colour_and_order(nbgs_scene_t sc, ContactBuf &cb, const SceneTable &tab, const int32_t *sdom,
@@ -407,7 +407,8 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     sc->prev_seed = sc->p.colour_seed;
     sc->prev_sig_valid = nc > 0;
     sc->precision_used = sc->p.precision;
-    NBGS_TRY(scene_gather(sc));
+    // a reused order keeps the sweep record's ends, order, colours and ids (same precision, same buffers)
+    NBGS_TRY(scene_gather(sc, !(same && sc->prev_precision == sc->p.precision)));
     if (sc->sub_active) NBGS_TRY(subdomain_prepare(sc));
     if (sc->blk_active && !prep_same) NBGS_TRY(block_prepare(sc));
     sc->blk_prep_reused = prep_same;
@@ -624,9 +625,9 @@ namespace nbgs {
 
 nbgs_status scene_sync_small(nbgs_scene_t sc, int first, int count) { return sync_small(sc, first, count); }
 
-nbgs_status scene_gather(nbgs_scene_t sc) {
-    if (sc->precision_used == NBGS_FP32_SWEEP) return gather_for_sweeps<float>(sc);
-    return gather_for_sweeps<double>(sc);
+nbgs_status scene_gather(nbgs_scene_t sc, bool indices) {
+    if (sc->precision_used == NBGS_FP32_SWEEP) return gather_for_sweeps<float>(sc, indices);
+    return gather_for_sweeps<double>(sc, indices);
 }
 
 // The sweep loop replayed from a captured graph: blocks of up to 32 sweeps

@@ -223,19 +223,24 @@ __global__ void __launch_bounds__(kBlock) k_invert(const uint32_t *perm, int64_t
 // Sweep position p <- canonical record perm[p].  One thread per sweep
 // position: the writes stream, and the reads of neighbouring positions (one
 // colour of one region of the box) fall on a few canonical segments.
+// indices = 0: the record's ends, order, colours, ids and friction
+// coefficients are those of the last gather (same pairs in the same order);
+// only geometry and impulses are written.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_gather_sweep(ContactsView c, const uint32_t *perm, const int32_t *sdom,
                                                          int64_t nc, double dt, double erp, SceneTable st,
-                                                         SweepView<T> sv) {
+                                                         SweepView<T> sv, int indices) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= nc) return;
     const int64_t j = perm[p];
-    sv.perm[p] = (int32_t)j;
-    if (sv.col) sv.col[p] = c.colour[j];
-    if (sv.sdom) sv.sdom[p] = sdom[j];
-    if (sv.mu) sv.mu[p] = (T)st.mu[st.body_scene[c.j1[j]]];
-    sv.j1[p] = c.j1[j];
-    sv.j2[p] = c.j2[j];
+    if (indices) {
+        sv.perm[p] = (int32_t)j;
+        if (sv.col) sv.col[p] = c.colour[j];
+        if (sv.sdom) sv.sdom[p] = sdom[j];
+        if (sv.mu) sv.mu[p] = (T)st.mu[st.body_scene[c.j1[j]]];
+        sv.j1[p] = c.j1[j];
+        sv.j2[p] = c.j2[j];
+    }
     sv.nx[p] = (T)c.nx[j];
     sv.ny[p] = (T)c.ny[j];
     sv.nz[p] = (T)c.nz[j];
@@ -325,16 +330,19 @@ nbgs_status launch_invert(const uint32_t *perm, int64_t nc, int32_t *pos, hipStr
 
 template <class T>
 nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, const int32_t *sdom, int64_t nc,
-                                double dt, double erp, const SceneTable &st, SweepView<T> sv, hipStream_t s) {
+                                double dt, double erp, const SceneTable &st, SweepView<T> sv, bool indices,
+                                hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, perm, sdom, nc, dt, erp, st, sv);
+    k_gather_sweep<T><<<grid_for(nc), kBlock, 0, s>>>(c, perm, sdom, nc, dt, erp, st, sv, indices ? 1 : 0);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
 template nbgs_status launch_gather_sweep<double>(const ContactsView &, const uint32_t *, const int32_t *, int64_t,
-                                                 double, double, const SceneTable &, SweepView<double>, hipStream_t);
+                                                 double, double, const SceneTable &, SweepView<double>, bool,
+                                                 hipStream_t);
 template nbgs_status launch_gather_sweep<float>(const ContactsView &, const uint32_t *, const int32_t *, int64_t,
-                                                double, double, const SceneTable &, SweepView<float>, hipStream_t);
+                                                double, double, const SceneTable &, SweepView<float>, bool,
+                                                hipStream_t);
 
 }  // namespace nbgs

@@ -207,7 +207,8 @@ nbgs_status launch_colour_keys(const ContactsView &c, const int32_t *sdom, int64
 nbgs_status launch_invert(const uint32_t *perm, int64_t nc, int32_t *pos, hipStream_t s);
 template <class T>
 nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, const int32_t *sdom, int64_t nc,
-                                double dt, double erp, const SceneTable &st, SweepView<T> sv, hipStream_t s);
+                                double dt, double erp, const SceneTable &st, SweepView<T> sv, bool indices,
+                                hipStream_t s);
 
 // sweep.hip
 struct SweepParams {

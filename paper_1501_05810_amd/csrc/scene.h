@@ -276,7 +276,8 @@ nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int6
 // launch shapes on the scene's current contacts whose trial sweeps leave no
 // trace (the initial impulses are restored afterwards).
 nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen, double *best_ms);
-nbgs_status scene_gather(nbgs_scene_t sc);
+// The sweep record from the canonical contacts; indices = false rewrites only geometry and impulses.
+nbgs_status scene_gather(nbgs_scene_t sc, bool indices = true);
 nbgs_status scene_sync_small(nbgs_scene_t sc, int first, int count);
 // Subdomain solver: subdomain of every contact (before colouring), then the
 // tile and slot tables (after the sweep record is gathered), and one pass
