@@ -51,7 +51,7 @@ CONTACT_BYTES = {"fp64": 104.0, "fp32": 56.0}
 BODY_BYTES = {"fp64": 112.0, "fp32": 56.0}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_dense1m_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1501_05810_amd", "csrc", f)
-                  for f in ("sweep.hip", "subdomain.hip", "contact_math.h", "nbgs_internal.h")]
+                  for f in ("sweep.hip", "subdomain.hip", "contact_math.h", "sweep_types.h")]
 
 
 def kernel_source_hash() -> str:
