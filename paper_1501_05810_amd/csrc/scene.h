@@ -45,7 +45,8 @@ struct ContactBuf {
 
 template <class T>
 struct SweepBuf {
-    DevBuf<int32_t> j1, j2, perm, col, sdom, ls;
+    DevBuf<int32_t> j1, j2, perm, col, sdom;
+    DevBuf<int16_t> ls;  // slot of each contact end inside its block or subdomain (block-local and subdomain modes)
     DevBuf<T> nx, ny, nz, bias, a1, a2, px, py, pz, mu;
     bool per_contact_mu = false;
     bool sub = false;  // subdomain solver: colour and subdomain per position, local slots per contact end

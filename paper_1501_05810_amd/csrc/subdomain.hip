@@ -144,12 +144,12 @@ __global__ void __launch_bounds__(kBlock) k_end_slots(const uint32_t *vals, int6
                                                       const int32_t *sj2, const int32_t *ssd, int32_t nb,
                                                       const double *inv_mass, const int32_t *flags,
                                                       const int32_t *ex, const int32_t *tile_slot_off,
-                                                      int32_t *ls) {
+                                                      int16_t *ls) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const uint32_t e = vals[i];
     const int32_t b = end_body(sj1, sj2, nb, inv_mass, e);
-    ls[e] = b < nb ? ex[i] + flags[i] - 1 - tile_slot_off[ssd[e >> 1]] : -1;
+    ls[e] = (int16_t)(b < nb ? ex[i] + flags[i] - 1 - tile_slot_off[ssd[e >> 1]] : -1);
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill64(int64_t *p, int64_t n, int64_t v) {
@@ -209,14 +209,14 @@ __global__ void __launch_bounds__(kBlock) k_slot_of(const uint32_t *sorted_body,
 __global__ void __launch_bounds__(kBlock) k_block_ends(const int32_t *sj1, const int32_t *sj2, const int32_t *ssd,
                                                        int64_t nc, int32_t nblocks, int32_t nb,
                                                        const double *inv_mass, const int32_t *slot,
-                                                       const int32_t *first_slot, int32_t *ls) {
+                                                       const int32_t *first_slot, int16_t *ls) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= nc) return;
     const int32_t id = ssd[p];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int32_t b = k ? sj2[p] : sj1[p];
-        ls[2 * p + k] = (id < nblocks && b < nb && inv_mass[b] > 0.0) ? slot[b] - first_slot[id] : -1;
+        ls[2 * p + k] = (int16_t)((id < nblocks && b < nb && inv_mass[b] > 0.0) ? slot[b] - first_slot[id] : -1);
     }
 }
 

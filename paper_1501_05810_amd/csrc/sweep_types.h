@@ -21,7 +21,8 @@ struct SweepView {
 // subdomain at ls[2 p + k] (-1: wall or static body).
 template <class T>
 struct SubView {
-    const int32_t *j1, *j2, *ls, *col;
+    const int32_t *j1, *j2, *col;
+    const int16_t *ls;  // slots stay below the LDS limit (at most a few thousand)
     const T *nx, *ny, *nz, *bias, *a1, *a2;
     T *px, *py, *pz;
 };
