@@ -18,8 +18,9 @@ Printed JSON line (one, rank 0):
   roofline      the NBGS sweep kernel: compulsory bytes per launch over its
                 average launch time, from a HIP event pair around every sweep
                 launch of extra profiled steps (the timed steps run without);
-  cpu_baseline  the oracle (sequential FP64 C) on one host core, one step of a
-                bounded sample of the same packing.
+  cpu_baseline  the oracle (FP64 C) in its OpenMP mode on the host cores (at
+                most 16), one step of the same packing; its results equal the
+                one-core run's to the last bit.
 Further fields: steps/s to residual 1e-6 (FP64 and FP32 sweeps), sweeps used,
 phase times, contact statistics, the learned warm start, the subdomain NBGS
 beside the colour-ordered one, and the other workloads (walled 4,096-sphere
@@ -360,12 +361,25 @@ def _warm_run(nb, torch, g2, mlp, ws, cap, target, steps):
     return rec
 
 
-def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0):
+def cpu_threads(requested: int) -> int:
+    """Host threads for the oracle: the request, else the cores this process may run on, at most 16."""
+    if requested > 0:
+        return requested
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0, threads: int = 1):
     """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres), in the sweep order
-    the GPU run uses."""
+    the GPU run uses; the sweeps on `threads` host threads (the oracle's OpenMP mode; detection, colouring and
+    integration stay sequential)."""
     import oracle
     import scenegen as sg
 
+    oracle.set_threads(threads)
     sc = sg.dense_packing(tiles=sample_tiles)
     w = oracle.World(sc.copy()).set_block_order(block_edge)
     t0 = time.perf_counter()
@@ -373,12 +387,13 @@ def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0):
     t1 = time.perf_counter()
     v = w.view()
     upd = v["n_contacts"] * sweeps
-    return dict(value=upd / (t1 - t0), unit="contact updates/s", cores=1, kind="oracle",
+    where = "on one host core" if threads == 1 else f"on {threads} host threads (OpenMP mode of the sweeps)"
+    return dict(value=upd / (t1 - t0), unit="contact updates/s", cores=threads, kind="oracle",
                 sample=f"1 step ({sweeps} FP64 sweeps" + (f" in the block-local order, edge {block_edge:g}"
                                                            if block_edge > 0 else "")
                        + ", detection, colouring, integration) of a "
                        f"{sample_tiles}x{sample_tiles}-tile cut of the packing: {sc.n} spheres, "
-                       f"{v['n_contacts']} contacts, {t1 - t0:.1f} s on one host core",
+                       f"{v['n_contacts']} contacts, {t1 - t0:.1f} s {where}",
                 seconds=t1 - t0), sc, w
 
 
@@ -419,6 +434,8 @@ def main():
     ap.add_argument("--target", type=float, default=1e-6)
     ap.add_argument("--max-sweeps", type=int, default=2000)
     ap.add_argument("--cpu-tiles", type=int, default=10, help="sample for the oracle timing (0: skip)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the oracle's sweeps (0: the cores available, at most 16)")
     ap.add_argument("--profile-steps", type=int, default=5,
                     help="steps re-run with a HIP event pair per sweep launch, for the roofline (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -623,7 +640,7 @@ def main():
     cpu = None
     vs_oracle = None
     if a.cpu_tiles > 0:
-        cpu, osc, ow = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge)
+        cpu, osc, ow = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge, cpu_threads(a.cpu_threads))
         log(f"cpu baseline: {cpu}")
         # the same step on the GPU from the same state, FP64 and FP32 sweeps, against the oracle's result
         vs_oracle = errors_against_oracle(nb, torch, dev, osc, ow, a.sweeps, a.block_edge)

@@ -89,12 +89,13 @@ class RefCompView(C.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (strict IEEE evaluation, no contraction)."""
+    """Compile the oracle with gcc (strict IEEE evaluation, no contraction; OpenMP for the optional
+    parallel sweeps)."""
     srcs = [s for s in SOURCES if os.path.exists(s)]
     if not force and os.path.exists(LIB_PATH) and all(os.path.getmtime(LIB_PATH) >= os.path.getmtime(s) for s in srcs + HEADERS):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11",
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11",
            "-Wall", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
@@ -115,6 +116,11 @@ def lib():
         L.nbgs_ref_colour.restype = C.c_int32
         L.nbgs_ref_splitmix64.restype = C.c_uint64
         L.nbgs_ref_splitmix64.argtypes = [C.c_uint64]
+        L.nbgs_ref_set_threads.argtypes = [C.c_int32]
+        L.nbgs_ref_get_threads.restype = C.c_int32
+        L.nbgs_ref_order_levels.restype = C.c_int64
+        L.nbgs_ref_order_levels.argtypes = [C.c_int64, _dp, C.c_int64, _i32p, _i32p, _i64p, _i64p,
+                                            C.POINTER(_i64p)]
         L.nbgs_ref_world_create.restype = C.c_void_p
         L.nbgs_ref_world_create.argtypes = [C.POINTER(RefBodies), C.POINTER(RefDomain), C.POINTER(RefParams)]
         for f in ("destroy", "integrate"):
@@ -316,6 +322,31 @@ def solve_sub(sc, c: Dict[str, np.ndarray], order: np.ndarray, sdom: np.ndarray,
                              _ptr(px), _ptr(py), _ptr(pz), C.c_int32(sweeps), C.c_double(0.0), _ptr(v), _ptr(w),
                              _ptr(hist), C.byref(st))
     return np.stack([px, py, pz], axis=1), v.reshape(-1, 3), w.reshape(-1, 3), hist[:st.sweeps].copy()
+
+
+def set_threads(threads: int) -> None:
+    """Threads of the sweeps' OpenMP mode (1: the sequential loops).  Every result is the same to the last bit."""
+    lib().nbgs_ref_set_threads(int(threads))
+
+
+def get_threads() -> int:
+    return int(lib().nbgs_ref_get_threads())
+
+
+def order_levels(inv_mass: np.ndarray, j1: np.ndarray, j2: np.ndarray, order: np.ndarray):
+    """Dependency levels of a sweep order (the OpenMP mode's schedule): the positions of the order grouped by level
+    and where each level starts."""
+    im = np.ascontiguousarray(inv_mass, dtype=np.float64)
+    a1 = np.ascontiguousarray(j1, dtype=np.int32)
+    a2 = np.ascontiguousarray(j2, dtype=np.int32)
+    o = np.ascontiguousarray(order, dtype=np.int64)
+    pos = np.empty(max(len(o), 1), dtype=np.int64)
+    start = _i64p()
+    L = lib().nbgs_ref_order_levels(len(im), _ptr(im), len(o), _ptr(a1, _i32p), _ptr(a2, _i32p), _ptr(o, _i64p),
+                                    _ptr(pos, _i64p), C.byref(start))
+    starts = np.array([start[i] for i in range(L + 1)], dtype=np.int64)
+    C.CDLL(None).free(C.cast(start, C.c_void_p))
+    return pos[:len(o)], starts
 
 
 def sweep_order(col: np.ndarray, n_colours: int) -> np.ndarray:

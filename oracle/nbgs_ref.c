@@ -614,6 +614,129 @@ static void one_contact(double bn, const double *bt, double wn, double wt, doubl
     P[2] = pn * n[2] + t2;
 }
 
+/* The arrays one sweep reads and writes. */
+typedef struct {
+    int64_t N;
+    const double *im, *ii;
+    const ref_params *p;
+    const int32_t *j1, *j2;
+    const double *nx, *ny, *nz, *xi, *a1, *a2;
+    double *px, *py, *pz, *v, *w;
+} sweep_arrays;
+
+/* One relaxation of contact j (the loop body of a sweep below); *dp2 = |dP|^2
+ * and *p2 = |P_new|^2 for the residual. */
+static void relax_one(const sweep_arrays *s, int64_t j, double *dp2, double *p2)
+{
+    const int64_t N = s->N;
+    const double *im = s->im, *ii = s->ii, *v = s->v, *w = s->w;
+    const ref_params *p = s->p;
+    int32_t b1 = s->j1[j], b2 = s->j2[j];
+    double n[3] = {s->nx[j], s->ny[j], s->nz[j]};
+    double im1 = im[b1], ii1 = ii[b1];
+    double im2 = 0.0, ii2 = 0.0;
+    double v2[3] = {0.0, 0.0, 0.0}, w2[3] = {0.0, 0.0, 0.0};
+    if (b2 < N) {
+        im2 = im[b2];
+        ii2 = ii[b2];
+        for (int a = 0; a < 3; ++a) {
+            v2[a] = v[3 * b2 + a];
+            w2[a] = w[3 * b2 + a];
+        }
+    }
+    double s0 = s->a1[j] * w[3 * b1 + 0] + s->a2[j] * w2[0];
+    double s1 = s->a1[j] * w[3 * b1 + 1] + s->a2[j] * w2[1];
+    double s2 = s->a1[j] * w[3 * b1 + 2] + s->a2[j] * w2[2];
+    double du[3];
+    du[0] = (v[3 * b1 + 0] - v2[0]) - (s1 * n[2] - s2 * n[1]);
+    du[1] = (v[3 * b1 + 1] - v2[1]) - (s2 * n[0] - s0 * n[2]);
+    du[2] = (v[3 * b1 + 2] - v2[2]) - (s0 * n[1] - s1 * n[0]);
+    double dun = n[0] * du[0] + n[1] * du[1] + n[2] * du[2];
+    double corr = s->xi[j] < 0.0 ? p->erp * s->xi[j] : s->xi[j];
+    double un = corr / p->dt + dun;
+    double ut[3] = {du[0] - dun * n[0], du[1] - dun * n[1], du[2] - dun * n[2]};
+    double P[3] = {s->px[j], s->py[j], s->pz[j]};
+    double Pn = n[0] * P[0] + n[1] * P[1] + n[2] * P[2];
+    double Pt[3] = {P[0] - Pn * n[0], P[1] - Pn * n[1], P[2] - Pn * n[2]};
+    double wn = im1 + im2;
+    double wt = wn + ii1 * s->a1[j] * s->a1[j] + ii2 * s->a2[j] * s->a2[j];
+    double bn = un - wn * Pn;
+    double bt[3] = {ut[0] - wt * Pt[0], ut[1] - wt * Pt[1], ut[2] - wt * Pt[2]};
+    double Ps[3];
+    one_contact(bn, bt, wn, wt, p->mu, n, Ps);
+    double Pnew[3], dP[3];
+    for (int a = 0; a < 3; ++a) {
+        Pnew[a] = p->relax * Ps[a] + (1.0 - p->relax) * P[a];
+        dP[a] = Pnew[a] - P[a];
+    }
+    apply_impulse(N, im, ii, s->v, s->w, b1, b2, n, s->a1[j], s->a2[j], dP);
+    s->px[j] = Pnew[0];
+    s->py[j] = Pnew[1];
+    s->pz[j] = Pnew[2];
+    *dp2 = dP[0] * dP[0] + dP[1] * dP[1] + dP[2] * dP[2];
+    *p2 = Pnew[0] * Pnew[0] + Pnew[1] * Pnew[1] + Pnew[2] * Pnew[2];
+}
+
+/* The initial impulse of contact j applied to its bodies (nothing when zero). */
+static void apply_initial(const sweep_arrays *s, int64_t j)
+{
+    double n[3] = {s->nx[j], s->ny[j], s->nz[j]};
+    double P0[3] = {s->px[j], s->py[j], s->pz[j]};
+    if (P0[0] != 0.0 || P0[1] != 0.0 || P0[2] != 0.0)
+        apply_impulse(s->N, s->im, s->ii, s->v, s->w, s->j1[j], s->j2[j], n, s->a1[j], s->a2[j], P0);
+}
+
+/* Threads of the OpenMP mode (1: the plain sequential loops). */
+static int32_t ref_threads = 1;
+
+void nbgs_ref_set_threads(int32_t threads) { ref_threads = threads > 1 ? threads : 1; }
+
+int32_t nbgs_ref_get_threads(void) { return ref_threads; }
+
+/* Dependency levels of a sweep order (the OpenMP mode).  Position t of the
+ * order waits for the last earlier position that shares one of its dynamic
+ * bodies (a wall or a static body is never written, so it links nothing):
+ *   level(t) = 1 + the largest level among those positions, 1 without any.
+ * Two positions of one level share no dynamic body, and each body meets its
+ * contacts level by level in the order's sequence; so running the levels one
+ * after another, each in any order or in parallel, gives every body the same
+ * impulses in the same sequence as the sequential loop: the same result to the
+ * last bit.  lev_pos (nc entries) receives the positions grouped by level,
+ * ascending inside a level; *lev_start (levels + 1 entries, allocated here and
+ * freed by the caller) where level l (0-based) starts.  Returns the number of
+ * levels. */
+int64_t nbgs_ref_order_levels(int64_t N, const double *inv_mass, int64_t nc, const int32_t *j1, const int32_t *j2,
+                              const int64_t *order, int64_t *lev_pos, int64_t **lev_start)
+{
+    int64_t *last = (int64_t *)calloc((size_t)(N > 0 ? N : 1), sizeof(int64_t));
+    int64_t *lev = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc > 0 ? nc : 1));
+    int64_t L = 0;
+    for (int64_t t = 0; t < nc; ++t) {
+        int64_t j = order[t];
+        int32_t b1 = j1[j], b2 = j2[j];
+        int d1 = inv_mass[b1] > 0.0, d2 = b2 < N && inv_mass[b2] > 0.0;
+        int64_t l = 0;
+        if (d1 && last[b1] > l) l = last[b1];
+        if (d2 && last[b2] > l) l = last[b2];
+        l += 1;
+        if (d1) last[b1] = l;
+        if (d2) last[b2] = l;
+        lev[t] = l - 1;
+        if (l > L) L = l;
+    }
+    int64_t *start = (int64_t *)calloc((size_t)L + 1, sizeof(int64_t));
+    for (int64_t t = 0; t < nc; ++t) start[lev[t] + 1] += 1;
+    for (int64_t l = 0; l < L; ++l) start[l + 1] += start[l];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(L > 0 ? L : 1));
+    memcpy(fill, start, sizeof(int64_t) * (size_t)L);
+    for (int64_t t = 0; t < nc; ++t) lev_pos[fill[lev[t]]++] = t;
+    free(fill);
+    free(lev);
+    free(last);
+    *lev_start = start;
+    return L;
+}
+
 /* NBGS solve of one time step.
  *
  * Accumulators (Sect. 6.3, velocity form; the paper's experiments use it):
@@ -634,7 +757,12 @@ static void one_contact(double bn, const double *bt, double wn, double wt, doubl
  *
  * order[t] is the t-th contact of the sweep; P arrays are in contact order,
  * in/out.  v_out, w_out (3 n each, interleaved xyz) receive v', w'.
- * residual_hist (max_sweeps entries, may be NULL) receives R_k. */
+ * residual_hist (max_sweeps entries, may be NULL) receives R_k.
+ *
+ * With more than one thread (nbgs_ref_set_threads) the initial impulses and
+ * every sweep run level by level (nbgs_ref_order_levels), the contacts of a
+ * level in parallel; the per-contact residual terms are kept by position and
+ * summed in the order's sequence, so every output is the sequential one. */
 void nbgs_ref_solve(const ref_bodies *b, const ref_params *p, int64_t nc, const int32_t *j1, const int32_t *j2,
                     const double *nx, const double *ny, const double *nz, const double *xi, const double *a1,
                     const double *a2, const int64_t *order, double *px, double *py, double *pz, int32_t max_sweeps,
@@ -652,63 +780,47 @@ void nbgs_ref_solve(const ref_bodies *b, const ref_params *p, int64_t nc, const 
         w[3 * i + 1] = b->wy[i];
         w[3 * i + 2] = b->wz[i];
     }
-    for (int64_t t = 0; t < nc; ++t) {
-        int64_t j = order[t];
-        double n[3] = {nx[j], ny[j], nz[j]};
-        double P0[3] = {px[j], py[j], pz[j]};
-        if (P0[0] != 0.0 || P0[1] != 0.0 || P0[2] != 0.0)
-            apply_impulse(N, im, ii, v, w, j1[j], j2[j], n, a1[j], a2[j], P0);
+    const sweep_arrays s = {N, im, ii, p, j1, j2, nx, ny, nz, xi, a1, a2, px, py, pz, v, w};
+    const int par = ref_threads > 1 && nc > 0;
+    int64_t L = 0, *lev_pos = NULL, *lev_start = NULL;
+    double *term_dp = NULL, *term_p = NULL;
+    if (par) {
+        lev_pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)nc);
+        L = nbgs_ref_order_levels(N, im, nc, j1, j2, order, lev_pos, &lev_start);
+        term_dp = (double *)malloc(sizeof(double) * (size_t)nc);
+        term_p = (double *)malloc(sizeof(double) * (size_t)nc);
+        #pragma omp parallel num_threads(ref_threads)
+        for (int64_t l = 0; l < L; ++l) {
+            #pragma omp for schedule(static)
+            for (int64_t q = lev_start[l]; q < lev_start[l + 1]; ++q) apply_initial(&s, order[lev_pos[q]]);
+        }
+    } else {
+        for (int64_t t = 0; t < nc; ++t) apply_initial(&s, order[t]);
     }
     int32_t k = 0;
     double R = 0.0;
     while (k < max_sweeps) {
         double sum_dp = 0.0, sum_p = 0.0;
-        for (int64_t t = 0; t < nc; ++t) {
-            int64_t j = order[t];
-            int32_t b1 = j1[j], b2 = j2[j];
-            double n[3] = {nx[j], ny[j], nz[j]};
-            double im1 = im[b1], ii1 = ii[b1];
-            double im2 = 0.0, ii2 = 0.0;
-            double v2[3] = {0.0, 0.0, 0.0}, w2[3] = {0.0, 0.0, 0.0};
-            if (b2 < N) {
-                im2 = im[b2];
-                ii2 = ii[b2];
-                for (int a = 0; a < 3; ++a) {
-                    v2[a] = v[3 * b2 + a];
-                    w2[a] = w[3 * b2 + a];
+        if (par) {
+            #pragma omp parallel num_threads(ref_threads)
+            for (int64_t l = 0; l < L; ++l) {
+                #pragma omp for schedule(static)
+                for (int64_t q = lev_start[l]; q < lev_start[l + 1]; ++q) {
+                    int64_t t = lev_pos[q];
+                    relax_one(&s, order[t], &term_dp[t], &term_p[t]);
                 }
             }
-            double s0 = a1[j] * w[3 * b1 + 0] + a2[j] * w2[0];
-            double s1 = a1[j] * w[3 * b1 + 1] + a2[j] * w2[1];
-            double s2 = a1[j] * w[3 * b1 + 2] + a2[j] * w2[2];
-            double du[3];
-            du[0] = (v[3 * b1 + 0] - v2[0]) - (s1 * n[2] - s2 * n[1]);
-            du[1] = (v[3 * b1 + 1] - v2[1]) - (s2 * n[0] - s0 * n[2]);
-            du[2] = (v[3 * b1 + 2] - v2[2]) - (s0 * n[1] - s1 * n[0]);
-            double dun = n[0] * du[0] + n[1] * du[1] + n[2] * du[2];
-            double corr = xi[j] < 0.0 ? p->erp * xi[j] : xi[j];
-            double un = corr / p->dt + dun;
-            double ut[3] = {du[0] - dun * n[0], du[1] - dun * n[1], du[2] - dun * n[2]};
-            double P[3] = {px[j], py[j], pz[j]};
-            double Pn = n[0] * P[0] + n[1] * P[1] + n[2] * P[2];
-            double Pt[3] = {P[0] - Pn * n[0], P[1] - Pn * n[1], P[2] - Pn * n[2]};
-            double wn = im1 + im2;
-            double wt = wn + ii1 * a1[j] * a1[j] + ii2 * a2[j] * a2[j];
-            double bn = un - wn * Pn;
-            double bt[3] = {ut[0] - wt * Pt[0], ut[1] - wt * Pt[1], ut[2] - wt * Pt[2]};
-            double Ps[3];
-            one_contact(bn, bt, wn, wt, p->mu, n, Ps);
-            double Pnew[3], dP[3];
-            for (int a = 0; a < 3; ++a) {
-                Pnew[a] = p->relax * Ps[a] + (1.0 - p->relax) * P[a];
-                dP[a] = Pnew[a] - P[a];
+            for (int64_t t = 0; t < nc; ++t) {
+                sum_dp += term_dp[t];
+                sum_p += term_p[t];
             }
-            apply_impulse(N, im, ii, v, w, b1, b2, n, a1[j], a2[j], dP);
-            px[j] = Pnew[0];
-            py[j] = Pnew[1];
-            pz[j] = Pnew[2];
-            sum_dp += dP[0] * dP[0] + dP[1] * dP[1] + dP[2] * dP[2];
-            sum_p += Pnew[0] * Pnew[0] + Pnew[1] * Pnew[1] + Pnew[2] * Pnew[2];
+        } else {
+            for (int64_t t = 0; t < nc; ++t) {
+                double dp2, p2;
+                relax_one(&s, order[t], &dp2, &p2);
+                sum_dp += dp2;
+                sum_p += p2;
+            }
         }
         double den = sqrt(sum_p);
         R = sqrt(sum_dp) / (den > 1e-300 ? den : 1e-300);
@@ -716,6 +828,10 @@ void nbgs_ref_solve(const ref_bodies *b, const ref_params *p, int64_t nc, const 
         ++k;
         if (target > 0.0 && R <= target) break;
     }
+    free(lev_pos);
+    free(lev_start);
+    free(term_dp);
+    free(term_p);
     if (stats) {
         stats->sweeps = k;
         stats->residual = R;

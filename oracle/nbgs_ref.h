@@ -59,3 +59,8 @@ void nbgs_ref_warm_match(int64_t nc, const uint64_t *key, const double *nx, cons
                          double mu, int64_t n_prev, const uint64_t *prev_key, const double *prev_px,
                          const double *prev_py, const double *prev_pz, double *px, double *py, double *pz);
 void nbgs_ref_integrate(ref_bodies *b, const ref_domain *dom, const ref_params *p, const double *v, const double *w);
+/* OpenMP mode of the sweeps (1 thread: the sequential loops; results identical either way). */
+void nbgs_ref_set_threads(int32_t threads);
+int32_t nbgs_ref_get_threads(void);
+int64_t nbgs_ref_order_levels(int64_t N, const double *inv_mass, int64_t nc, const int32_t *j1, const int32_t *j2,
+                              const int64_t *order, int64_t *lev_pos, int64_t **lev_start);
