@@ -210,17 +210,94 @@ int64_t nbgs_ref_detect_body(const ref_bodies *b, const ref_domain *dom, const r
     return m;
 }
 
-/* Same contact set with a uniform cell grid (broad phase by spatial
- * partitioning, Sect. 4) so that larger scenes stay tractable.  Cell edge >=
- * the largest possible reach 2 max(r + h), so every contact partner lies in
- * one of the 27 surrounding cells.  Candidates of body i with k > i are
- * sorted ascending before testing, giving the same order as the brute force. */
+static void contacts_alloc(ref_contacts *c, int64_t cap);
+static void contacts_free(ref_contacts *c);
+static int32_t ref_threads;
+
 static int cmp_i64(const void *a, const void *b)
 {
     int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
     return (x > y) - (x < y);
 }
 
+/* The cell lists of one grid detection. */
+typedef struct {
+    const ref_bodies *b;
+    const ref_domain *dom;
+    const ref_params *p;
+    const double *h;
+    const int64_t *dims, *head, *next, *cidx;
+} grid_lists;
+
+/* The contacts of body i found through the cell lists (its partners k > i in
+ * ascending index, then its walls), written from position m of out; returns
+ * the new count. */
+static int64_t grid_body(const grid_lists *g, int64_t i, int64_t **cand_p, int64_t *cand_cap_p, ref_contacts *out,
+                         int64_t m)
+{
+    const ref_bodies *b = g->b;
+    const ref_domain *dom = g->dom;
+    const ref_params *p = g->p;
+    const double *h = g->h;
+    const int64_t *dims = g->dims, *head = g->head, *next = g->next, *cidx = g->cidx;
+    const int64_t N = b->n;
+    int64_t *cand = *cand_p, cand_cap = *cand_cap_p;
+    double n[3], xi, a1, a2;
+    int64_t nc = 0;
+    int64_t lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] == 1) {
+            lo[a] = 0;
+            hi[a] = 0;
+        } else {
+            lo[a] = cidx[3 * i + a] - 1;
+            hi[a] = cidx[3 * i + a] + 1;
+        }
+    }
+    for (int64_t cz = lo[2]; cz <= hi[2]; ++cz)
+        for (int64_t cy = lo[1]; cy <= hi[1]; ++cy)
+            for (int64_t cx = lo[0]; cx <= hi[0]; ++cx) {
+                int64_t c3[3] = {cx, cy, cz}, ok = 1;
+                for (int a = 0; a < 3; ++a) {
+                    if (c3[a] < 0 || c3[a] >= dims[a]) {
+                        if (!dom->periodic[a]) ok = 0;
+                        else c3[a] = (c3[a] + dims[a]) % dims[a];
+                    }
+                }
+                if (!ok) continue;
+                int64_t lin = (c3[2] * dims[1] + c3[1]) * dims[0] + c3[0];
+                for (int64_t k = head[lin]; k >= 0; k = next[k]) {
+                    if (k <= i) continue;
+                    if (nc == cand_cap) {
+                        cand_cap *= 2;
+                        cand = (int64_t *)realloc(cand, sizeof(int64_t) * (size_t)cand_cap);
+                    }
+                    cand[nc++] = k;
+                }
+            }
+    *cand_p = cand;
+    *cand_cap_p = cand_cap;
+    qsort(cand, (size_t)nc, sizeof(int64_t), cmp_i64);
+    for (int64_t t = 0; t < nc; ++t) {
+        int64_t k = cand[t];
+        if (t > 0 && cand[t - 1] == k) continue; /* a periodic axis with one cell lists a body once per image */
+        if (is_static(b, i) && is_static(b, k)) continue;
+        if (sphere_pair(b, dom, h, i, k, n, &xi, &a1, &a2)) put_contact(out, m++, i, k, n, xi, a1, a2);
+    }
+    if (is_static(b, i)) return m;
+    for (int32_t w = 0; w < dom->n_planes; ++w)
+        if (sphere_plane(b, &dom->planes[w], h[i], p->tau, i, n, &xi, &a1, &a2))
+            put_contact(out, m++, i, N + w, n, xi, a1, a2);
+    return m;
+}
+
+/* Same contact set with a uniform cell grid (broad phase by spatial
+ * partitioning, Sect. 4) so that larger scenes stay tractable.  Cell edge >=
+ * the largest possible reach 2 max(r + h), so every contact partner lies in
+ * one of the 27 surrounding cells.  Candidates of body i with k > i are
+ * sorted ascending before testing, giving the same order as the brute force.
+ * In the OpenMP mode runs of consecutive bodies are searched in parallel,
+ * each into a list of its own, and the lists joined in body order. */
 int64_t nbgs_ref_detect_grid(const ref_bodies *b, const ref_domain *dom, const ref_params *p, ref_contacts *out)
 {
     int64_t N = b->n;
@@ -260,55 +337,54 @@ int64_t nbgs_ref_detect_grid(const ref_bodies *b, const ref_domain *dom, const r
         next[i] = head[lin];
         head[lin] = i;
     }
-    int64_t cand_cap = 64, m = 0;
-    int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cand_cap);
-    double n[3], xi, a1, a2;
-    for (int64_t i = 0; i < N; ++i) {
-        int64_t nc = 0;
-        int64_t lo[3], hi[3];
-        for (int a = 0; a < 3; ++a) {
-            if (dims[a] == 1) {
-                lo[a] = 0;
-                hi[a] = 0;
-            } else {
-                lo[a] = cidx[3 * i + a] - 1;
-                hi[a] = cidx[3 * i + a] + 1;
+    const grid_lists g = {b, dom, p, h, dims, head, next, cidx};
+    int64_t m = 0;
+    if (ref_threads > 1) {
+        /* OpenMP mode: contiguous runs of bodies, each into a list of its own,
+         * joined in run order: the same contacts in the same order. */
+        const int64_t runs = 8 * (int64_t)ref_threads;
+        ref_contacts *part = (ref_contacts *)calloc((size_t)runs, sizeof(ref_contacts));
+        int64_t *pm = (int64_t *)calloc((size_t)runs, sizeof(int64_t));
+        #pragma omp parallel for num_threads(ref_threads) schedule(dynamic, 1)
+        for (int64_t r = 0; r < runs; ++r) {
+            const int64_t i0 = N * r / runs, i1 = N * (r + 1) / runs;
+            int64_t cap = 64, cand_cap = 64, k;
+            int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cand_cap);
+            for (;;) {
+                contacts_alloc(&part[r], cap);
+                k = 0;
+                for (int64_t i = i0; i < i1; ++i) k = grid_body(&g, i, &cand, &cand_cap, &part[r], k);
+                if (k <= cap) break;
+                contacts_free(&part[r]);
+                cap = 2 * k;
             }
+            free(cand);
+            pm[r] = k;
         }
-        for (int64_t cz = lo[2]; cz <= hi[2]; ++cz)
-            for (int64_t cy = lo[1]; cy <= hi[1]; ++cy)
-                for (int64_t cx = lo[0]; cx <= hi[0]; ++cx) {
-                    int64_t c3[3] = {cx, cy, cz}, ok = 1;
-                    for (int a = 0; a < 3; ++a) {
-                        if (c3[a] < 0 || c3[a] >= dims[a]) {
-                            if (!dom->periodic[a]) ok = 0;
-                            else c3[a] = (c3[a] + dims[a]) % dims[a];
-                        }
-                    }
-                    if (!ok) continue;
-                    int64_t lin = (c3[2] * dims[1] + c3[1]) * dims[0] + c3[0];
-                    for (int64_t k = head[lin]; k >= 0; k = next[k]) {
-                        if (k <= i) continue;
-                        if (nc == cand_cap) {
-                            cand_cap *= 2;
-                            cand = (int64_t *)realloc(cand, sizeof(int64_t) * (size_t)cand_cap);
-                        }
-                        cand[nc++] = k;
-                    }
-                }
-        qsort(cand, (size_t)nc, sizeof(int64_t), cmp_i64);
-        for (int64_t t = 0; t < nc; ++t) {
-            int64_t k = cand[t];
-            if (t > 0 && cand[t - 1] == k) continue; /* a periodic axis with one cell lists a body once per image */
-            if (is_static(b, i) && is_static(b, k)) continue;
-            if (sphere_pair(b, dom, h, i, k, n, &xi, &a1, &a2)) put_contact(out, m++, i, k, n, xi, a1, a2);
+        for (int64_t r = 0; r < runs; ++r) {
+            const ref_contacts *c = &part[r];
+            for (int64_t q = 0; q < pm[r]; ++q, ++m) {
+                if (m >= out->cap) continue;
+                out->j1[m] = c->j1[q];
+                out->j2[m] = c->j2[q];
+                out->key[m] = c->key[q];
+                out->nx[m] = c->nx[q];
+                out->ny[m] = c->ny[q];
+                out->nz[m] = c->nz[q];
+                out->xi[m] = c->xi[q];
+                out->a1[m] = c->a1[q];
+                out->a2[m] = c->a2[q];
+            }
+            contacts_free(&part[r]);
         }
-        if (is_static(b, i)) continue;
-        for (int32_t w = 0; w < dom->n_planes; ++w)
-            if (sphere_plane(b, &dom->planes[w], h[i], p->tau, i, n, &xi, &a1, &a2))
-                put_contact(out, m++, i, N + w, n, xi, a1, a2);
+        free(pm);
+        free(part);
+    } else {
+        int64_t cand_cap = 64;
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cand_cap);
+        for (int64_t i = 0; i < N; ++i) m = grid_body(&g, i, &cand, &cand_cap, out, m);
+        free(cand);
     }
-    free(cand);
     free(cidx);
     free(next);
     free(head);

@@ -9,8 +9,9 @@ terms are summed in the order's sequence afterwards.  Pinned here:
 * on real orders (the (colour, key) order and the block-local order, walls, static bodies, periodic axes) the schedule
   is a valid one: every position exactly once, no two positions of a level share a dynamic body, and every dynamic
   body meets its contacts level by level in the order's sequence;
-* every output of a multi-threaded run (impulses, accumulators, residual history, sweeps used, the integrated
-  state over several warm-started steps) equals the sequential run's to the last bit.
+* every output of a multi-threaded run (the grid detection's contact list, impulses, accumulators, residual
+  history, sweeps used, the integrated state over several warm-started steps) equals the sequential run's to the
+  last bit, and the multi-threaded grid detection equals the brute-force definition.
 """
 import numpy as np
 import pytest
@@ -107,7 +108,7 @@ def test_threads_give_the_sequential_result(name, edge):
         for step in range(3):
             w.step(12, grid=True, warm=True)
             v = w.view()
-            out.append({k: np.array(v[k], copy=True) for k in ("P", "v", "w", "residual_hist")})
+            out.append({k: np.array(v[k], copy=True) for k in ("key", "colour", "order", "P", "v", "w", "residual_hist")})
             out[-1]["pos"] = w.sc.pos.copy()
             out[-1]["vel"] = w.sc.vel.copy()
             out[-1]["quat"] = w.sc.quat.copy()
@@ -119,3 +120,27 @@ def test_threads_give_the_sequential_result(name, edge):
     for a, b in zip(*runs):
         for k in a:
             assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("case", ["few bodies", "periodic, one cell per axis", "static bodies", "packing"])
+def test_threaded_grid_detection_is_the_definition(case):
+    if case == "few bodies":
+        sc = sg.packed_cluster(63, counts=(2, 2, 2))  # fewer bodies than the runs the threads split them into
+    elif case == "periodic, one cell per axis":
+        sc = sg.packed_cluster(64, counts=(2, 2, 1))
+        sc.periodic = (True, True, False)
+        sc.planes = [p for p in sc.planes if abs(p[1][2]) > 0.5]
+    elif case == "static bodies":
+        sc = _with_static(sg.packed_cluster(65, counts=(5, 4, 4)), k=12)
+    else:
+        sc = sg.dense_packing(tiles=1)
+    brute = oracle.detect(sc, "brute") if sc.n <= 2000 else None
+    oracle.set_threads(1)
+    one = oracle.detect(sc, "grid")
+    oracle.set_threads(5)
+    many = oracle.detect(sc, "grid")
+    assert len(one["key"]) > 0
+    for k in one:
+        assert np.array_equal(one[k], many[k]), k
+        if brute is not None:
+            assert np.array_equal(brute[k], many[k]), k
