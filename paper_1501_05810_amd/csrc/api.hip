@@ -772,11 +772,11 @@ nbgs_status finish_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbg
             per_sweep = (2 * 4 + 12 * tb) * (double)sc->nc + 4 * 2 * (double)sc->nc +
                         (8 * tb + 6 * tb + 6 * tb) * (double)sc->n_slots + 12 * tb * (double)sc->b.n;
         } else {
-            // every contact record, the slot indices of the local contacts, every slot read and written once,
-            // every dynamic end of a contact between blocks read and written
+            // every contact record, the two 16-bit slot indices of every local contact, every slot read and
+            // written once, every dynamic end of a contact between blocks read and written
             double xd = 0.0;
             for (int64_t d : sc->xdyn) xd += (double)d;
-            per_sweep = (2 * 4 + 12 * tb) * (double)sc->nc + 4 * 2 * (double)sc->blk_n_local +
+            per_sweep = (2 * 4 + 12 * tb) * (double)sc->nc + 2 * 2 * (double)sc->blk_n_local +
                         14 * tb * ((double)sc->blk_dyn_local + xd);
         }
         sc->prof.sweep_launches += sweeps;
