@@ -213,15 +213,19 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
                 }
                 if (out_of_box) continue;
                 const int cell = (q[2] * g.dims[1] + q[1]) * g.dims[0] + q[0];
-                if (cell_stamp[cell] != stamp) continue;
+                // the cell's stamp and range are read together (one round trip); a range whose stamp is stale is
+                // left unused
+                const uint32_t cs = cell_stamp[cell];
                 const int q0 = cell_start[cell], q1 = cell_end[cell];
+                if (cs != stamp) continue;
                 if (!kEmit) {
                     seen += q1 - q0;
                     if (seen > kMaxCandidates) return -1;
                 }
                 for (int s = q0; s < q1; ++s) {
-                    if (sbody[s] <= A) continue;
+                    const int B = sbody[s];
                     const double4 o = sec[s];
+                    if (B <= A) continue;
                     if (me.w < 0.0 && o.w < 0.0) continue;  // two static bodies
                     const double ddx = min_image(me.x - o.x, g.periodic[0], g.L[0]);
                     const double ddy = min_image(me.y - o.y, g.periodic[1], g.L[1]);

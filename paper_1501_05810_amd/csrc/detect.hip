@@ -182,16 +182,20 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
         for (int dy = nr.lo[1]; dy <= nr.hi[1]; ++dy)
             for (int dx = nr.lo[0]; dx <= nr.hi[0]; ++dx) {
                 const int cell = neighbour_cell(g, c, dx, dy, dz);
-                if (cell < 0 || cell_stamp[cell] != stamp) continue;
-                const int q0 = cell_start[cell], q1 = cell_end[cell];
+                // the cell's stamp and range are read together (one round trip); a range whose stamp is stale is
+                // left unused
+                const int cc = cell < 0 ? 0 : cell;
+                const uint32_t cs = cell_stamp[cc];
+                const int q0 = cell_start[cc], q1 = cell_end[cc];
+                if (cell < 0 || cs != stamp) continue;
                 if (!kEmit) {
                     seen += q1 - q0;
                     if (seen > kMaxCandidates) return -1;
                 }
                 for (int q = q0; q < q1; ++q) {
                     const int k = (int)sids[q];
-                    if (k <= i) continue;
                     const double4 o = sxr[q];
+                    if (k <= i) continue;
                     if (me.w < 0.0 && o.w < 0.0) continue;  // two static bodies
                     if (!hull_hit(me, o, g)) continue;
                     if (kEmit || m < cap) out_k[m] = k;
