@@ -339,7 +339,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_TRY(cb.reserve((size_t)nc));
     NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p, sc->off.p,
-                              sc->cellpos.p, sc->npart.p, sc->partners.p, cb.view(), s));
+                              sc->cellpos.p, sc->npart.p, sc->partners.p, cb.view(), nc, s));
     // initial impulses and, when the previous table carries colours, the start of the colouring
     const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;

@@ -298,10 +298,10 @@ __device__ inline void sort_partners(int32_t *ks, int m) {
     }
 }
 
-// One thread per body in index order, so that consecutive threads write
-// consecutive segments of the canonical list; bodies without contacts leave
-// at once.  A body whose partners all fit in the count's store copies them
-// from there; only a longer list is searched again.
+// The canonical list in two passes.  First one thread per body: its segment
+// of body indices (partners ascending, then the walls its hull meets); a body
+// whose partners all fit in the count's store copies them from there, only a
+// longer list is searched again; bodies without contacts leave at once.
 __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                       const uint32_t *skeys, const uint32_t *sids,
                                                       const double4 *sxr, const double *h,
@@ -326,10 +326,35 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, Pla
         m = visit_partners<true>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, ks);
     }
     sort_partners(ks, m);
+    for (int t = 0; t < m; ++t) c.j1[base + t] = i;
+    if (b.inv_mass[i] != 0.0) {
+        int t = m;
+        const double xi_ = b.x[i], yi = b.y[i], zi = b.z[i], ri = b.radius[i], hi = h[i];
+        double gap;
+        for (int w = 0; w < pl.n; ++w) {
+            if (!plane_hit(pl, w, xi_, yi, zi, ri, hi, tau, &gap)) continue;
+            const int j = base + t++;
+            c.j1[j] = i;
+            c.j2[j] = wall0 + w;
+        }
+    }
+}
+
+// Then one thread per contact, so that neighbouring threads write neighbouring
+// entries: the key and the geometry of eq. (contactpos) for two spheres (n from
+// the centre of j2 to that of j1, xi = |x1 - x2| - r1 - r2, arms r1 + xi and
+// r2) or for a sphere and a wall (the wall's normal, xi its gap to the sphere,
+// arms r1 + xi and 0).
+__global__ void __launch_bounds__(kBlock) k_pair_geometry(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st,
+                                                          int64_t nc, ContactsView c) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    const int i = c.j1[j], k = c.j2[j];
+    c.key[j] = ((uint64_t)(uint32_t)i << 32) | (uint64_t)(uint32_t)k;
     const double xi_ = b.x[i], yi = b.y[i], zi = b.z[i], ri = b.radius[i];
-    for (int t = 0; t < m; ++t) {
-        const int k = ks[t];
-        const int j = base + t;
+    if (k < b.n) {
+        const int sc = st.body_scene ? st.body_scene[i] : 0;
+        const Grid &g = st.body_scene ? st.grids[sc] : g0;
         const double dx = min_image(xi_ - b.x[k], g.periodic[0], g.L[0]);
         const double dy = min_image(yi - b.y[k], g.periodic[1], g.L[1]);
         const double dz = min_image(zi - b.z[k], g.periodic[2], g.L[2]);
@@ -347,33 +372,24 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, Pla
         }
         const double rk = b.radius[k];
         const double xi = (d - ri) - rk;
-        c.j1[j] = i;
-        c.key[j] = ((uint64_t)(uint32_t)i << 32) | (uint64_t)(uint32_t)k;
         c.nx[j] = nx;
         c.ny[j] = ny;
         c.nz[j] = nz;
         c.xi[j] = xi;
         c.a1[j] = ri + xi;
         c.a2[j] = rk;
-    }
-    if (b.inv_mass[i] != 0.0) {
-        int t = m;
-        const double hi = h[i];
+    } else {
+        const int sc = st.body_scene ? st.body_scene[i] : 0;
+        const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
+        const int w = k - (b.n + (st.body_scene ? st.wall_off[sc] : 0));
         double gap;
-        for (int w = 0; w < pl.n; ++w) {
-            if (!plane_hit(pl, w, xi_, yi, zi, ri, hi, tau, &gap)) continue;
-            const int j = base + t++;
-            const int k = wall0 + w;
-            c.j1[j] = i;
-            c.j2[j] = k;
-            c.key[j] = ((uint64_t)(uint32_t)i << 32) | (uint64_t)(uint32_t)k;
-            c.nx[j] = pl.nrm[w][0];
-            c.ny[j] = pl.nrm[w][1];
-            c.nz[j] = pl.nrm[w][2];
-            c.xi[j] = gap;
-            c.a1[j] = ri + gap;
-            c.a2[j] = 0.0;
-        }
+        (void)plane_hit(pl, w, xi_, yi, zi, ri, 0.0, 0.0, &gap);  // the gap the first pass tested
+        c.nx[j] = pl.nrm[w][0];
+        c.ny[j] = pl.nrm[w][1];
+        c.nz[j] = pl.nrm[w][2];
+        c.xi[j] = gap;
+        c.a1[j] = ri + gap;
+        c.a2[j] = 0.0;
     }
 }
 
@@ -506,10 +522,15 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
                              uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
-                             const int32_t *npart, const int32_t *partners, ContactsView c, hipStream_t s) {
+                             const int32_t *npart, const int32_t *partners, ContactsView c, int64_t nc,
+                             hipStream_t s) {
     k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
                                                  cell_stamp, stamp, cnt, off, cellpos, npart, partners, c);
     NBGS_HIP(hipGetLastError());
+    if (nc > 0) {
+        k_pair_geometry<<<grid_for(nc), kBlock, 0, s>>>(b, g, pl, st, nc, c);
+        NBGS_HIP(hipGetLastError());
+    }
     return NBGS_OK;
 }
 
