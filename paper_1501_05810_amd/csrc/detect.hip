@@ -410,13 +410,20 @@ __global__ void __launch_bounds__(kBlock) k_match_prev(ContactsView c, int64_t n
     int64_t lo = 0;
     if (j < nc) {
         const uint64_t key = c.key[j];
-        int64_t hi = n_prev;
-        while (lo < hi) {
-            const int64_t mid = lo + ((hi - lo) >> 1);
-            if (prev_key[mid] < key) lo = mid + 1;
-            else hi = mid;
+        if (j < n_prev && prev_key[j] == key) {
+            // the same place in the last list (keys are unique there): what the search below would find, without
+            // its dependent reads; in a settled packing this holds for every pair
+            lo = j;
+            found = true;
+        } else {
+            int64_t hi = n_prev;
+            while (lo < hi) {
+                const int64_t mid = lo + ((hi - lo) >> 1);
+                if (prev_key[mid] < key) lo = mid + 1;
+                else hi = mid;
+            }
+            found = lo < n_prev && prev_key[lo] == key;
         }
-        found = lo < n_prev && prev_key[lo] == key;
     }
     if (unmatched) {
         const unsigned long long nf = __ballot(j < nc && !found);
