@@ -199,44 +199,84 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
         hi[a] = g.dims[a] == 1 ? 0 : 1;
     }
     int m = 0, seen = 0;
+    // the entries of one sorted range [q0, q1)
+    auto scan = [&](int q0, int q1) -> bool {
+        if (!kEmit) {
+            seen += q1 - q0;
+            if (seen > kMaxCandidates) return false;
+        }
+        for (int s = q0; s < q1; ++s) {
+            const int B = sbody[s];
+            const double4 o = sec[s];
+            if (B <= A) continue;
+            if (me.w < 0.0 && o.w < 0.0) continue;  // two static bodies
+            const double ddx = min_image(me.x - o.x, g.periodic[0], g.L[0]);
+            const double ddy = min_image(me.y - o.y, g.periodic[1], g.L[1]);
+            const double ddz = min_image(me.z - o.z, g.periodic[2], g.L[2]);
+            const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            const double reach = fabs(me.w) + fabs(o.w);
+            if (!(d2 <= reach * reach)) continue;
+            if (kEmit || m < cap) out[m] = (int32_t)sids[s];
+            ++m;
+        }
+        return true;
+    };
     for (int dz = lo[2]; dz <= hi[2]; ++dz)
-        for (int dy = lo[1]; dy <= hi[1]; ++dy)
-            for (int dx = lo[0]; dx <= hi[0]; ++dx) {
-                int q[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-                bool out_of_box = false;
+        for (int dy = lo[1]; dy <= hi[1]; ++dy) {
+            int qy = c[1] + dy, qz = c[2] + dz;
+            bool out_of_box = false;
+            if (qy < 0 || qy >= g.dims[1]) {
+                if (!g.periodic[1]) out_of_box = true;
+                qy = qy < 0 ? qy + g.dims[1] : qy - g.dims[1];
+            }
+            if (qz < 0 || qz >= g.dims[2]) {
+                if (!g.periodic[2]) out_of_box = true;
+                qz = qz < 0 ? qz + g.dims[2] : qz - g.dims[2];
+            }
+            if (out_of_box) continue;
+            const int row = (qz * g.dims[1] + qy) * g.dims[0];  // the row's cell at x = 0
+            // consecutive x cells hold consecutive sorted entries, so unless the row wraps round a periodic x
+            // axis its stamped cells form one range, from the first one's start to the last one's end (cells
+            // between them without a stamp hold no entries)
+            int xa = c[0] + lo[0], xb = c[0] + hi[0];
+            bool wrap = false;
+            if (xa < 0) {
+                if (g.periodic[0]) wrap = true;
+                else xa = 0;
+            }
+            if (xb >= g.dims[0]) {
+                if (g.periodic[0]) wrap = true;
+                else xb = g.dims[0] - 1;
+            }
+            if (!wrap) {
+                int q0 = 0, q1 = 0;
+                bool any = false;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (q[a] < 0 || q[a] >= g.dims[a]) {
-                        if (!g.periodic[a]) out_of_box = true;
-                        q[a] = q[a] < 0 ? q[a] + g.dims[a] : q[a] - g.dims[a];
-                    }
+                for (int x = 0; x < 3; ++x) {
+                    const int cell = row + (xa + x <= xb ? xa + x : xa);  // past xb: a repeat, left unused
+                    const uint32_t cs = cell_stamp[cell];
+                    const int s0 = cell_start[cell], s1 = cell_end[cell];
+                    if (xa + x > xb || cs != stamp) continue;
+                    if (!any) q0 = s0;
+                    q1 = s1;
+                    any = true;
                 }
-                if (out_of_box) continue;
-                const int cell = (q[2] * g.dims[1] + q[1]) * g.dims[0] + q[0];
-                // the cell's stamp and range are read together (one round trip); a range whose stamp is stale is
-                // left unused
-                const uint32_t cs = cell_stamp[cell];
-                const int q0 = cell_start[cell], q1 = cell_end[cell];
-                if (cs != stamp) continue;
-                if (!kEmit) {
-                    seen += q1 - q0;
-                    if (seen > kMaxCandidates) return -1;
-                }
-                for (int s = q0; s < q1; ++s) {
-                    const int B = sbody[s];
-                    const double4 o = sec[s];
-                    if (B <= A) continue;
-                    if (me.w < 0.0 && o.w < 0.0) continue;  // two static bodies
-                    const double ddx = min_image(me.x - o.x, g.periodic[0], g.L[0]);
-                    const double ddy = min_image(me.y - o.y, g.periodic[1], g.L[1]);
-                    const double ddz = min_image(me.z - o.z, g.periodic[2], g.L[2]);
-                    const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                    const double reach = fabs(me.w) + fabs(o.w);
-                    if (!(d2 <= reach * reach)) continue;
-                    if (kEmit || m < cap) out[m] = (int32_t)sids[s];
-                    ++m;
+                if (any && !scan(q0, q1)) return -1;
+            } else {
+                for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+                    int qx = c[0] + dx;
+                    if (qx < 0) qx += g.dims[0];
+                    else if (qx >= g.dims[0]) qx -= g.dims[0];
+                    const int cell = row + qx;
+                    // the cell's stamp and range are read together (one round trip); a range whose stamp is
+                    // stale is left unused
+                    const uint32_t cs = cell_stamp[cell];
+                    const int q0 = cell_start[cell], q1 = cell_end[cell];
+                    if (cs != stamp) continue;
+                    if (!scan(q0, q1)) return -1;
                 }
             }
+        }
     return m;
 }
 
