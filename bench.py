@@ -374,8 +374,8 @@ def cpu_threads(requested: int) -> int:
 
 def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0, threads: int = 1):
     """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres), in the sweep order
-    the GPU run uses; the sweeps on `threads` host threads (the oracle's OpenMP mode; detection, colouring and
-    integration stay sequential)."""
+    the GPU run uses; the sweeps and the grid detection on `threads` host threads (the oracle's OpenMP mode;
+    colouring and integration stay sequential)."""
     import oracle
     import scenegen as sg
 
@@ -387,7 +387,8 @@ def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0, thread
     t1 = time.perf_counter()
     v = w.view()
     upd = v["n_contacts"] * sweeps
-    where = "on one host core" if threads == 1 else f"on {threads} host threads (OpenMP mode of the sweeps)"
+    where = ("on one host core" if threads == 1
+             else f"on {threads} host threads (the oracle's OpenMP mode: sweeps and grid detection in parallel)")
     return dict(value=upd / (t1 - t0), unit="contact updates/s", cores=threads, kind="oracle",
                 sample=f"1 step ({sweeps} FP64 sweeps" + (f" in the block-local order, edge {block_edge:g}"
                                                            if block_edge > 0 else "")
