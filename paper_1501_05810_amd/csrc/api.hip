@@ -242,6 +242,26 @@ nbgs_status sync_small(nbgs_scene_t sc, int first, int count) {
     return NBGS_OK;
 }
 
+// The last completed sweep's residual, staged beside the control words so that
+// one copy brings both to the host.
+__global__ void __launch_bounds__(64) k_last_residual(const int32_t *ctrl, const double *hist, double *out) {
+    if (threadIdx.x != 0) return;
+    const int32_t k = ctrl[1];
+    out[0] = k > 0 ? hist[k - 1] : 0.0;
+}
+
+// Stop flag, sweeps completed, numeric-error flag and the last residual of a
+// solve in one host round trip.
+nbgs_status read_solve_result(nbgs_scene_t sc, int32_t &sweeps, double &R) {
+    k_last_residual<<<1, 64, 0, sc->s>>>(sc->ctrl(), sc->res_hist.p, reinterpret_cast<double *>(sc->small.p + 12));
+    NBGS_HIP(hipGetLastError());
+    NBGS_TRY(sync_small(sc, 8, 6));
+    sweeps = sc->pinned[8 + 1];
+    R = 0.0;
+    if (sweeps > 0) std::memcpy(&R, sc->pinned + 12, sizeof(double));
+    return NBGS_OK;
+}
+
 template <class T>
 nbgs_status gather_for_sweeps(nbgs_scene_t sc, bool indices) {
     SweepBuf<T> &sw = sweep_buf<T>(sc);
@@ -746,15 +766,9 @@ nbgs_status finish_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbg
     record(sc, kIntegrate);
     sc->state = 2;
     sc->solved = true;
-    NBGS_TRY(sync_small(sc, 8, 3));
-    const int32_t sweeps = sc->pinned[8 + 1];
+    int32_t sweeps = 0;
     double R = 0.0;
-    if (sweeps > 0) {
-        NBGS_HIP(hipMemcpyAsync(sc->pinned + 32, sc->res_hist.p + (sweeps - 1), sizeof(double), hipMemcpyDeviceToHost,
-                                s));
-        NBGS_HIP(hipStreamSynchronize(s));
-        std::memcpy(&R, sc->pinned + 32, sizeof(double));
-    }
+    NBGS_TRY(read_solve_result(sc, sweeps, R));
     sc->stats.sweeps = sweeps;
     sc->stats.residual = R;
     if (stats) *stats = sc->stats;
@@ -972,15 +986,9 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
     sc->state = 2;
     sc->solved = true;
     if (stats || target > 0.0) {
-        NBGS_TRY(sync_small(sc, 8, 3));
-        const int32_t sweeps = sc->pinned[8 + 1];
+        int32_t sweeps = 0;
         double R = 0.0;
-        if (sweeps > 0) {
-            NBGS_HIP(hipMemcpyAsync(sc->pinned + 32, sc->res_hist.p + (sweeps - 1), sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
-            NBGS_HIP(hipStreamSynchronize(s));
-            std::memcpy(&R, sc->pinned + 32, sizeof(double));
-        }
+        NBGS_TRY(read_solve_result(sc, sweeps, R));
         sc->stats.sweeps = sweeps;
         sc->stats.residual = R;
         if (stats) *stats = sc->stats;
