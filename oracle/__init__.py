@@ -543,6 +543,29 @@ def mlp_targets(frame: np.ndarray, P: np.ndarray, ms: float, vs: float) -> np.nd
     return t[:nc].copy()
 
 
+def jacobi_residual(sc, contacts: Dict[str, np.ndarray], order: np.ndarray, P0: np.ndarray):
+    """Jacobi residual of the initial impulses P0 (n x 3, contact order) of scene sc's contacts: every contact's
+    one-contact solution P* against the accumulators of P0 (applied in the sweep order ``order``), nothing written
+    back; returns (|P* - P0| / |P*|, P* (n x 3), v' (N x 3), w' (N x 3))."""
+    nc = int(contacts["j1"].shape[0])
+    held = _Held()
+    b = make_bodies(sc, held)
+    prm = make_params(sc)
+    n = _c(contacts["n"]).reshape(-1, 3)
+    cols = [_c(n[:, 0]), _c(n[:, 1]), _c(n[:, 2]), _c(contacts["xi"]), _c(contacts["a1"]), _c(contacts["a2"])]
+    P0 = _c(P0).reshape(-1, 3)
+    p0 = [_c(P0[:, k]) for k in range(3)]
+    ps = [np.zeros(max(nc, 1)) for _ in range(3)]
+    v = np.zeros((max(sc.n, 1), 3))
+    w = np.zeros((max(sc.n, 1), 3))
+    f = lib().nbgs_ref_jacobi_residual
+    f.restype = C.c_double
+    r = f(C.byref(b), C.byref(prm), C.c_int64(nc), _ptr(_c(contacts["j1"], np.int32), _i32p),
+          _ptr(_c(contacts["j2"], np.int32), _i32p), *[_ptr(c) for c in cols],
+          _ptr(_c(order, np.int64), _i64p), *[_ptr(c) for c in p0], *[_ptr(c) for c in ps], _ptr(v), _ptr(w))
+    return float(r), np.stack([c[:nc] for c in ps], axis=1), v[:sc.n].copy(), w[:sc.n].copy()
+
+
 # ------------------------------------------------------------- composite particles
 
 _STATE = (("x", "pos", 0), ("y", "pos", 1), ("z", "pos", 2), ("qw", "quat", 0), ("qx", "quat", 1),

@@ -1,8 +1,10 @@
 /*
  * mlp_ref.c -- ORACLE (test infrastructure only) for the learned warm start:
  * per-contact features, a 12-128-128-3 ReLU multilayer perceptron in FP64
- * (forward, loss, gradient), the decoding of its output into an initial
- * impulse, and the Jacobi residual used to judge an initial impulse.
+ * (forward, loss, gradient), Adam, the decoding of its output into an
+ * initial impulse and the training targets.  The Jacobi residual that judges
+ * an initial impulse is nbgs_ref_jacobi_residual in nbgs_ref.c (it needs the
+ * solve's one-contact problem).
  *
  * The network predicts each contact's impulse at the start of a time step
  * (the paper allows any initial solution of Alg. 1, Sect. 5).  Features are

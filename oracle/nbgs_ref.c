@@ -700,9 +700,10 @@ typedef struct {
     double *px, *py, *pz, *v, *w;
 } sweep_arrays;
 
-/* One relaxation of contact j (the loop body of a sweep below); *dp2 = |dP|^2
- * and *p2 = |P_new|^2 for the residual. */
-static void relax_one(const sweep_arrays *s, int64_t j, double *dp2, double *p2)
+/* The one-contact solution P* = F_j^-1(0, P_jbar) of contact j against the
+ * accumulators as they stand (its own impulse P_j taken out of them); P
+ * receives the contact's current impulse P_j. */
+static void contact_target(const sweep_arrays *s, int64_t j, double *P, double *Ps)
 {
     const int64_t N = s->N;
     const double *im = s->im, *ii = s->ii, *v = s->v, *w = s->w;
@@ -731,21 +732,32 @@ static void relax_one(const sweep_arrays *s, int64_t j, double *dp2, double *p2)
     double corr = s->xi[j] < 0.0 ? p->erp * s->xi[j] : s->xi[j];
     double un = corr / p->dt + dun;
     double ut[3] = {du[0] - dun * n[0], du[1] - dun * n[1], du[2] - dun * n[2]};
-    double P[3] = {s->px[j], s->py[j], s->pz[j]};
+    P[0] = s->px[j];
+    P[1] = s->py[j];
+    P[2] = s->pz[j];
     double Pn = n[0] * P[0] + n[1] * P[1] + n[2] * P[2];
     double Pt[3] = {P[0] - Pn * n[0], P[1] - Pn * n[1], P[2] - Pn * n[2]};
     double wn = im1 + im2;
     double wt = wn + ii1 * s->a1[j] * s->a1[j] + ii2 * s->a2[j] * s->a2[j];
     double bn = un - wn * Pn;
     double bt[3] = {ut[0] - wt * Pt[0], ut[1] - wt * Pt[1], ut[2] - wt * Pt[2]};
-    double Ps[3];
     one_contact(bn, bt, wn, wt, p->mu, n, Ps);
+}
+
+/* One relaxation of contact j (the loop body of a sweep below); *dp2 = |dP|^2
+ * and *p2 = |P_new|^2 for the residual. */
+static void relax_one(const sweep_arrays *s, int64_t j, double *dp2, double *p2)
+{
+    const ref_params *p = s->p;
+    double n[3] = {s->nx[j], s->ny[j], s->nz[j]};
+    double P[3], Ps[3];
+    contact_target(s, j, P, Ps);
     double Pnew[3], dP[3];
     for (int a = 0; a < 3; ++a) {
         Pnew[a] = p->relax * Ps[a] + (1.0 - p->relax) * P[a];
         dP[a] = Pnew[a] - P[a];
     }
-    apply_impulse(N, im, ii, s->v, s->w, b1, b2, n, s->a1[j], s->a2[j], dP);
+    apply_impulse(s->N, s->im, s->ii, s->v, s->w, s->j1[j], s->j2[j], n, s->a1[j], s->a2[j], dP);
     s->px[j] = Pnew[0];
     s->py[j] = Pnew[1];
     s->pz[j] = Pnew[2];
@@ -912,6 +924,65 @@ void nbgs_ref_solve(const ref_bodies *b, const ref_params *p, int64_t nc, const 
         stats->sweeps = k;
         stats->residual = R;
     }
+}
+
+/* Jacobi residual of an initial impulse (the judge of a learned warm start,
+ * Sect. 5: any initial solution may start Alg. 1, so two candidates are
+ * compared by how far each is from its own one-contact solutions).
+ *
+ * Definition: from the accumulators of the initial impulses P0 (v' = v + dt g
+ * for dynamic bodies, w' = w, then every contact's P0 applied in sweep
+ * order, exactly as a solve starts), every contact takes its one-contact
+ * solution P*_j with its own impulse taken out, all against the same
+ * accumulators and nothing written back (one nonlinear Jacobi step); then
+ *   R_J = |P* - P0|_2 / max(|P*|_2, 1e-300)
+ * over all contacts, the squares summed in sweep order.  P* of every contact
+ * (contact order) is written to ps_x/ps_y/ps_z when they are not NULL; v_out
+ * and w_out (3 n each, may be NULL) receive the accumulators.  Returns R_J
+ * (0 when there is no contact). */
+double nbgs_ref_jacobi_residual(const ref_bodies *b, const ref_params *p, int64_t nc, const int32_t *j1,
+                                const int32_t *j2, const double *nx, const double *ny, const double *nz,
+                                const double *xi, const double *a1, const double *a2, const int64_t *order,
+                                const double *px, const double *py, const double *pz, double *ps_x, double *ps_y,
+                                double *ps_z, double *v_out, double *w_out)
+{
+    int64_t N = b->n;
+    const double *im = b->inv_mass;
+    double *v = (double *)malloc(sizeof(double) * 3 * (size_t)(N > 0 ? N : 1));
+    double *w = (double *)malloc(sizeof(double) * 3 * (size_t)(N > 0 ? N : 1));
+    for (int64_t i = 0; i < N; ++i) {
+        int dyn = im[i] > 0.0;
+        v[3 * i + 0] = dyn ? b->vx[i] + p->dt * p->gravity[0] : b->vx[i];
+        v[3 * i + 1] = dyn ? b->vy[i] + p->dt * p->gravity[1] : b->vy[i];
+        v[3 * i + 2] = dyn ? b->vz[i] + p->dt * p->gravity[2] : b->vz[i];
+        w[3 * i + 0] = b->wx[i];
+        w[3 * i + 1] = b->wy[i];
+        w[3 * i + 2] = b->wz[i];
+    }
+    /* the sweep arrays read the initial impulses only (nothing is relaxed) */
+    const sweep_arrays s = {N, im, b->inv_inertia, p, j1, j2, nx, ny, nz, xi, a1, a2,
+                            (double *)px, (double *)py, (double *)pz, v, w};
+    for (int64_t t = 0; t < nc; ++t) apply_initial(&s, order[t]);
+    double sum_d = 0.0, sum_s = 0.0;
+    for (int64_t t = 0; t < nc; ++t) {
+        int64_t j = order[t];
+        double P[3], Ps[3];
+        contact_target(&s, j, P, Ps);
+        double d0 = Ps[0] - P[0], d1 = Ps[1] - P[1], d2 = Ps[2] - P[2];
+        sum_d += d0 * d0 + d1 * d1 + d2 * d2;
+        sum_s += Ps[0] * Ps[0] + Ps[1] * Ps[1] + Ps[2] * Ps[2];
+        if (ps_x) {
+            ps_x[j] = Ps[0];
+            ps_y[j] = Ps[1];
+            ps_z[j] = Ps[2];
+        }
+    }
+    if (v_out) memcpy(v_out, v, sizeof(double) * 3 * (size_t)N);
+    if (w_out) memcpy(w_out, w, sizeof(double) * 3 * (size_t)N);
+    free(v);
+    free(w);
+    double den = sqrt(sum_s);
+    return nc > 0 ? sqrt(sum_d) / (den > 1e-300 ? den : 1e-300) : 0.0;
 }
 
 /* Velocities of body i as a contact of subdomain s sees them: accumulator
