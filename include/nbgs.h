@@ -211,8 +211,10 @@ nbgs_status nbgs_get_residuals(nbgs_scene_t scene, int32_t cap, double *hist, in
  * (colouring restricted to the subdomain, order (subdomain, colour, key)) and
  * the last iteration's impulses of all others; with accumulated velocities
  * and per-subdomain velocity corrections summed at the end of every sweep in
- * ascending subdomain (Sect. 6.3).  Use a relaxation below 1 (the paper's
- * runs use 0.75): across subdomains the iteration is a Jacobi one.
+ * ascending subdomain (Sect. 6.3).  The relaxation must be below 1 (the
+ * paper's runs use 0.75): across subdomains the iteration is a Jacobi one,
+ * which diverges unrelaxed on dense packings; INVALID_ARG at relaxation 1
+ * here and from nbgs_scene_set_params while the solver is on.
  * CAPACITY at detection if a subdomain touches too many bodies for the
  * workgroup's local memory (about 540 in FP64): use a smaller edge.
  * UNSUPPORTED for batches and with the learned warm start. */
@@ -447,6 +449,16 @@ typedef struct {
     double r_learned;
 } nbgs_warm_info;
 nbgs_status nbgs_get_warm_start_info(nbgs_scene_t scene, nbgs_warm_info *out);
+
+/* The learned initial impulses of the last nbgs_detect (NBGS_WS_LEARNED with
+ * a network attached): for a contact the previous step also had, its
+ * re-projected previous impulse; for a new contact the network output decoded
+ * from the contact frame and projected onto the friction cone (the initial
+ * solution of Alg. 1 may be any estimate, Sect. 5).  impulse [device]: three
+ * planes of cap doubles (x[cap], y[cap], z[cap]), canonical (key) order.
+ * *n_out [host] = contact count; CAPACITY if it exceeds cap; STATE if the
+ * last detection made no learned start.  Synchronises. */
+nbgs_status nbgs_get_learned_start(nbgs_scene_t scene, int64_t cap, double *impulse, int64_t *n_out);
 
 /* ------------------------------------------------------------------------
  * Composite particles: rigid clusters of element spheres (Sect. 2 builds

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "libnbgs.so")
 NBGS_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "CAPACITY", 4: "DEVICE", 5: "NOT_CONVERGED",
                 6: "STATE", 7: "NUMERIC", 8: "UNSUPPORTED"}
+NBGS_ERR_CAPACITY = 3
 NBGS_ERR_NOT_CONVERGED = 5
 NBGS_FP64, NBGS_FP32_SWEEP = 0, 1
 NBGS_WS_ZERO, NBGS_WS_PREVIOUS, NBGS_WS_LEARNED = 0, 1, 2
@@ -115,6 +116,7 @@ _SIGNATURES = [
     ("nbgs_get_feature_scales", C.c_int, [_vp, C.POINTER(C.c_double)]),
     ("nbgs_get_training_data", C.c_int, [_vp, C.c_int64, _vp, _vp, C.POINTER(C.c_int64)]),
     ("nbgs_get_warm_start_info", C.c_int, [_vp, _vp]),
+    ("nbgs_get_learned_start", C.c_int, [_vp, C.c_int64, _vp, C.POINTER(C.c_int64)]),
     ("nbgs_set_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
     ("nbgs_get_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(nbgs_tuning)]),
     ("nbgs_set_profiling", C.c_int, [_vp, C.c_int32]),
@@ -636,6 +638,16 @@ class GpuScene:
 
     def warm_start_info(self) -> Dict:
         return nbgs_get_warm_start_info(self.handle)
+
+    def learned_start(self) -> np.ndarray:
+        """Initial impulses (n x 3, canonical order) that the learned warm start proposed at the last detect."""
+        torch = self.torch
+        n0 = C.c_int64()
+        _check(lib().nbgs_get_learned_start(_vp(self.handle), 0, None, C.byref(n0)), allow=(NBGS_ERR_CAPACITY,))
+        n = int(n0.value)
+        buf = torch.empty((3, max(n, 1)), dtype=torch.float64, device=self.device)
+        _check(lib().nbgs_get_learned_start(_vp(self.handle), max(n, 1), _vp(buf.data_ptr()), C.byref(n0)))
+        return buf[:, :n].T.contiguous().cpu().numpy()
 
     def set_profiling(self, enable: bool = True):
         nbgs_set_profiling(self.handle, enable)

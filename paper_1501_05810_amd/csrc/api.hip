@@ -365,7 +365,13 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
     // new pairs are counted when the previous colouring may be reused whole (same pair count)
     const bool maybe_same = warm_colours && nc == sc->n_prev;
-    if (maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 4, 0, 3 * sizeof(int32_t), s));
+    if (maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 4, 0, 4 * sizeof(int32_t), s));
+    // every body's dynamic bit, compared with the last detection's (kept current at every detection)
+    NBGS_TRY(sc->dyn_bits.reserve((size_t)((sc->b.n + 63) / 64 + 1), 1.0));
+    if (!maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 7, 0, sizeof(int32_t), s));
+    NBGS_TRY(launch_dyn_bits(sc->b.inv_mass, sc->b.n, sc->dyn_bits.p, sc->small.p + 7, s));
+    const bool dyn_bits_known = sc->dyn_bits_valid;
+    sc->dyn_bits_valid = true;
     NBGS_TRY(launch_match_prev(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p, sc->n_prev,
                                sc->p.mu, tab, warm_impulses, warm_colours, maybe_same ? sc->small.p + 4 : nullptr,
                                s));
@@ -398,20 +404,21 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     if (sc->sub_active) NBGS_TRY(subdomain_assign(sc));
     if (sc->blk_active) NBGS_TRY(block_assign(sc, sc->small.p + 6));
     const int32_t *sdom = sc->sub_active || sc->blk_active ? sc->sdom.p : nullptr;
-    // The greedy colouring and the (id, colour, key) order are functions of the pair keys, the ids, the seed and the
-    // static bodies only.  When every pair of this step is a pair of the last one (same count, none new), every id
-    // is the same and the mode and seed are too, the last colours (already copied by the match), colour counts and
-    // sweep permutation are this step's.
+    // The greedy colouring and the (id, colour, key) order are functions of the pair keys, the ids, the seed and
+    // which bodies are dynamic only.  When every pair of this step is a pair of the last one (same count, none new),
+    // every id and every body's dynamic bit is the same and the mode and seed are too, the last colours (already
+    // copied by the match), colour counts and sweep permutation are this step's.
     const double sig[4] = {(double)sc->p.colour_seed, sc->sub_active ? sc->sub_edge : -1.0,
                            sc->blk_active ? sc->blk_edge : -1.0, (double)(sdom ? sc->n_sub : 0)};
-    bool same = maybe_same && sc->prev_sig_valid && std::memcmp(sig, sc->prev_sig, sizeof(sig)) == 0 &&
-                sc->prev_seed == sc->p.colour_seed && sc->perm != nullptr;
+    bool same = maybe_same && dyn_bits_known && sc->prev_sig_valid &&
+                std::memcmp(sig, sc->prev_sig, sizeof(sig)) == 0 && sc->prev_seed == sc->p.colour_seed &&
+                sc->perm != nullptr;
     if (same && sdom) NBGS_TRY(launch_ids_changed(sdom, sc->prev_sdom.p, cb.matched.p, nc, sc->small.p + 5, s));
     // the block set-up (slots, per-id ranges, cross colours) depends on these and on every body's block
     bool prep_same = false;
     if (same) {
-        NBGS_TRY(sync_small(sc, 4, 3));
-        same = sc->pinned[4] == 0 && sc->pinned[5] == 0;
+        NBGS_TRY(sync_small(sc, 4, 4));
+        same = sc->pinned[4] == 0 && sc->pinned[5] == 0 && sc->pinned[7] == 0;
         prep_same = same && sc->blk_active && sc->bblk_compared && sc->pinned[6] == 0 &&
                     sc->prev_precision == sc->p.precision;
     }
@@ -701,6 +708,7 @@ nbgs_status scene_sweep_loop(nbgs_scene_t sc, int32_t max_sweeps, double target,
     // without a target and without history only the last sweep's residual is formed (after the replays)
     const bool every = target > 0.0 || sc->res_history;
     key.every = every;
+    key.alloc_gen = g_alloc_generation.load(std::memory_order_relaxed);
     if (!sc->gexec || !(key == sc->gkey)) {
         if (sc->gexec) (void)hipGraphExecDestroy(sc->gexec);
         sc->gexec = nullptr;
@@ -1312,6 +1320,10 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t sc, const nbgs_params *params) {
         set_error("the block-local order does not combine with the learned warm start");
         return NBGS_ERR_UNSUPPORTED;
     }
+    if (sc->sub_edge > 0.0 && !(params->relax < 1.0)) {
+        set_error("the subdomain solver needs a relaxation below 1: switch it off first");
+        return NBGS_ERR_INVALID_ARG;
+    }
     sc->p = *params;
     update_scales(sc);
     return NBGS_OK;
@@ -1446,6 +1458,11 @@ nbgs_status nbgs_set_subdomains(nbgs_scene_t sc, double edge) {
         set_error("the block-local order is set: switch it off first");
         return NBGS_ERR_INVALID_ARG;
     }
+    if (edge > 0.0 && !(sc->p.relax < 1.0)) {
+        set_error("the subdomain solver needs a relaxation below 1 (across subdomains it is a Jacobi iteration, "
+                  "which diverges unrelaxed on dense packings); the paper's runs use 0.75");
+        return NBGS_ERR_INVALID_ARG;
+    }
     sc->sub_edge = edge;
     sc->state = 0;  // the next step starts with a detection
     return NBGS_OK;
@@ -1578,6 +1595,26 @@ nbgs_status nbgs_get_warm_start_info(nbgs_scene_t sc, nbgs_warm_info *out) {
         return NBGS_ERR_INVALID_ARG;
     }
     *out = sc->winfo;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_learned_start(nbgs_scene_t sc, int64_t cap, double *impulse, int64_t *n_out) {
+    NBGS_GUARD(sc);
+    if (n_out) *n_out = sc->nc;
+    if (!sc->have_learned) {
+        set_error("no learned start: the last nbgs_detect ran without NBGS_WS_LEARNED and an attached network");
+        return NBGS_ERR_STATE;
+    }
+    if (sc->nc > cap) {
+        set_error("%lld contacts do not fit into %lld", (long long)sc->nc, (long long)cap);
+        return NBGS_ERR_CAPACITY;
+    }
+    if (sc->nc == 0 || !impulse) return NBGS_OK;
+    const size_t bytes = sizeof(double) * (size_t)sc->nc;
+    NBGS_HIP(hipMemcpyAsync(impulse, sc->lpx.p, bytes, hipMemcpyDeviceToDevice, sc->s));
+    NBGS_HIP(hipMemcpyAsync(impulse + cap, sc->lpy.p, bytes, hipMemcpyDeviceToDevice, sc->s));
+    NBGS_HIP(hipMemcpyAsync(impulse + 2 * cap, sc->lpz.p, bytes, hipMemcpyDeviceToDevice, sc->s));
+    NBGS_HIP(hipStreamSynchronize(sc->s));
     return NBGS_OK;
 }
 

@@ -7,9 +7,12 @@
 // colours, order and arithmetic it would get alone (the per-scene friction
 // coefficient travels with each contact).  Colour c of every scene is relaxed
 // by the same launch, so a sweep costs as many launches as the largest
-// colour count, not the sum over scenes; the sweeps are replayed from a
-// captured HIP graph over resident (persistent) workgroups, and the launch
-// shape comes from the autotuner on the first step of each precision.
+// colour count, not the sum over scenes.  nbgs_batch_step drives each step
+// from the host (detection, colouring, solve, integration enqueued one after
+// another on the batch's stream); the launch shape of the sweeps comes from
+// the autotuner on the first step of each precision, whose candidates
+// include persistent workgroups and replay of the sweeps from a captured HIP
+// graph.
 #include <algorithm>
 #include <new>
 

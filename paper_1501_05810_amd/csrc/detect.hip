@@ -482,6 +482,25 @@ __global__ void __launch_bounds__(kBlock) k_ids_changed(const int32_t *sdom, con
     }
 }
 
+// Which bodies are dynamic (1/m > 0), one bit per body in 64-bit words (a
+// wave's 64 consecutive bodies per word): the words are rewritten, and the
+// number of words that differ from the stored ones is added to changed.  The
+// colouring and the block slots depend on these bits (a conflict is a shared
+// dynamic body), so a colouring is reused only while they stay the same.
+__global__ void __launch_bounds__(kBlock) k_dyn_bits(const double *inv_mass, int64_t n, uint64_t *bits,
+                                                     int32_t *changed) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool dyn = i < n && inv_mass[i] > 0.0;
+    const unsigned long long m = __ballot(dyn);
+    const int64_t word = i >> 6;
+    if ((threadIdx.x & 63) == 0 && word * 64 < n) {
+        if (bits[word] != (uint64_t)m) {
+            bits[word] = (uint64_t)m;
+            atomicAdd(changed, 1);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = v;
@@ -556,6 +575,14 @@ nbgs_status launch_ids_changed(const int32_t *sdom, const int32_t *prev_sdom, co
                                int32_t *changed, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
     k_ids_changed<<<grid_for(nc), kBlock, 0, s>>>(sdom, prev_sdom, matched, nc, changed);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_dyn_bits(const double *inv_mass, int64_t n, uint64_t *bits, int32_t *changed, hipStream_t s) {
+    if (n == 0) return NBGS_OK;
+    static_assert(kBlock % 64 == 0, "a word is one wave's bodies");
+    k_dyn_bits<<<grid_for(n), kBlock, 0, s>>>(inv_mass, n, bits, changed);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

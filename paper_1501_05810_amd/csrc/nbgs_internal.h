@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -32,6 +33,10 @@ void set_error(const char *fmt, ...);
         if (s_ != NBGS_OK) return s_;                                                                           \
     } while (0)
 
+// Bumped by every (re)allocation of a DevBuf: a captured graph holds raw
+// device addresses and stays valid only while no buffer has moved since.
+inline std::atomic<uint64_t> g_alloc_generation{0};
+
 // A device allocation that only grows.  Contents are not preserved on growth.
 template <class T>
 struct DevBuf {
@@ -57,6 +62,7 @@ struct DevBuf {
             return NBGS_ERR_OUT_OF_MEMORY;
         }
         cap = want;
+        g_alloc_generation.fetch_add(1, std::memory_order_relaxed);
         return NBGS_OK;
     }
 };
@@ -164,6 +170,9 @@ nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_k
                               int32_t *unmatched, hipStream_t s);
 nbgs_status launch_ids_changed(const int32_t *sdom, const int32_t *prev_sdom, const int32_t *matched, int64_t nc,
                                int32_t *changed, hipStream_t s);
+// One bit per body (1/m > 0) in (n + 63) / 64 words; words that differ from the stored ones are rewritten and
+// counted into changed.
+nbgs_status launch_dyn_bits(const double *inv_mass, int64_t n, uint64_t *bits, int32_t *changed, hipStream_t s);
 nbgs_status launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 nbgs_status launch_zero_impulses(ContactsView c, int64_t nc, hipStream_t s);
 

@@ -115,7 +115,9 @@ struct nbgs_scene_s {
     // scratch
     DevBuf<int32_t> radix_hist;
     DevBuf<char> scan_tmp;
-    DevBuf<int32_t> small;  // [0] total, [1] remaining, [2] overflow, [8..12) ctrl, [16..528) colour histograms
+    DevBuf<int32_t> small;  // [0] total, [1] remaining, [2] overflow, [4] new pairs, [5] changed ids, [6] changed
+                            // blocks, [7] changed dynamic bits, [8..12) ctrl, [12..14) last residual, [16..528)
+                            // colour histograms
     DevBuf<unsigned long long> maxbits;
     int32_t *pinned = nullptr;  // host mirror of small
     // contacts
@@ -134,6 +136,10 @@ struct nbgs_scene_s {
     double prev_sig[4] = {0.0, 0.0, 0.0, 0.0};
     uint64_t prev_seed = 0;
     bool prev_sig_valid = false;
+    // every body's dynamic bit (1/m > 0) as the last detection saw it; the colouring and the block slots depend
+    // on it, so a change forbids their reuse
+    DevBuf<uint64_t> dyn_bits;
+    bool dyn_bits_valid = false;
     bool colouring_reused = false;
     int32_t prev_precision = -1;
     // every body's block in the block-local order, this step's and the last one's (alternating)
@@ -196,9 +202,10 @@ struct nbgs_scene_s {
         const void *col = nullptr;
         double target = 0.0, mu = 0.0, relax = 0.0;
         bool every = true;  // residual after every sweep
+        uint64_t alloc_gen = 0;  // no device buffer (re)allocated since the capture
         bool operator==(const GraphKey &o) const {
             if (sweeps != o.sweeps || colours != o.colours || prec != o.prec || grid != o.grid || col != o.col ||
-                target != o.target || mu != o.mu || relax != o.relax || every != o.every)
+                target != o.target || mu != o.mu || relax != o.relax || every != o.every || alloc_gen != o.alloc_gen)
                 return false;
             if (std::memcmp(&tune, &o.tune, sizeof(tune)) != 0) return false;
             for (int i = 0; i < 6; ++i)

@@ -97,7 +97,9 @@ def test_subdomain_contact_bound_is_refused():
     nb = _nb()
     n = 50_000
     total = n * (n - 1) // 2  # 1,249,975,000 < 2^31 but twice that is not
-    g = nb.GpuScene(_all_pairs_scene(n, 5)).set_subdomains(5.0)
+    sc = _all_pairs_scene(n, 5)
+    sc.relax = 0.75  # the subdomain solver needs a relaxation below 1
+    g = nb.GpuScene(sc).set_subdomains(5.0)
     with pytest.raises(nb.NbgsError) as e:
         g.detect()
     assert e.value.status == _CAPACITY and str(total) in str(e.value)

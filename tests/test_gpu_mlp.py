@@ -120,3 +120,36 @@ def test_training_fits_a_smooth_map():
     l1, _ = m.loss_grad(xd, td)
     assert l1 < 0.05 * l0, (l0, lfin, l1)
     m.close()
+
+
+def test_adam_steps_match_oracle():
+    """Three Adam steps of the training kernels against the oracle's Adam (Kingma & Ba) on the same gradient.
+
+    One sample, one batch: the GPU gradient of nbgs_mlp_loss_grad and the one the training loop forms are then the
+    same sum (one block, no summation order), so the step can be replayed by the oracle from the GPU's own weights
+    and gradient; the oracle keeps its moments in FP64, the GPU in FP32 (a few FP32 round-offs of a move of lr)."""
+    import torch
+
+    nb = _nb()
+    w0 = weights(8)
+    rng = np.random.default_rng(9)
+    x = torch.tensor(bf16(rng.normal(size=(1, NF))), device="cuda")
+    t = torch.tensor(rng.normal(size=(1, NO)).astype(np.float32), device="cuda")
+    m = nb.GpuMlp()
+    m.set_weights(w0)
+    lr = 1e-3
+    wr = w0.astype(np.float64)
+    mr, vr = np.zeros_like(wr), np.zeros_like(wr)
+    for k in (1, 2, 3):
+        _, g = m.loss_grad(x, t)
+        g = g.cpu().numpy().astype(np.float64)
+        assert np.count_nonzero(g) > 1000
+        wprev = m.weights().astype(np.float64)
+        m.train(x, t, epochs=1, batch=1, lr=lr, seed=k)
+        wg = m.weights().astype(np.float64)
+        wr = wprev.copy()
+        oracle.mlp_adam(wr, g, mr, vr, k, lr=lr)
+        moved = np.abs(wr - wprev)
+        assert np.median(moved[g != 0]) > 0.5 * lr  # the steps are not vanishing
+        np.testing.assert_allclose(wg, wr, rtol=3e-7, atol=1e-8 * lr / 1e-3)
+    m.close()

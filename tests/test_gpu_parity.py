@@ -363,3 +363,47 @@ def test_lane_groups_with_graph_replay_and_residual_target(precision):
         g.close()
     for P, v, k in runs[1:]:
         assert np.array_equal(P, runs[0][0]) and np.array_equal(v, runs[0][1]) and k == runs[0][2]
+
+
+@pytest.mark.parametrize("block_edge", [0.0, 2.5])
+def test_colouring_not_reused_when_a_body_turns_dynamic(block_edge):
+    """The colouring (and the block slots) depend on which bodies are dynamic: a body that turns from static to
+    dynamic (or back) between two steps with the same pairs must not keep the last step's colours.  Colours,
+    impulses and velocities against the oracle, which colours every step from scratch."""
+    nb = _nb()
+    sc = sg.packed_cluster(71, counts=(6, 6, 4), vmax=0.0, wmax=0.0, dt=1e-5, tau=0.02)
+    sc.erp = 0.0
+    c0 = oracle.detect(sc)
+    pair = c0["j2"] < sc.n
+    deg = np.bincount(np.concatenate([c0["j1"][pair], c0["j2"][pair]]), minlength=sc.n)
+    deg[c0["j1"][~pair]] = -1  # a body touching a wall would lose that contact while static
+    k = int(np.argmax(deg))
+    assert deg[k] >= 4
+    im_k, ii_k = float(sc.inv_mass[k]), float(sc.inv_inertia[k])
+    sc.inv_mass[k] = 0.0
+    sc.inv_inertia[k] = 0.0
+    ref = sc.copy()
+    g = nb.GpuScene(sc.copy())
+    if block_edge:
+        g.set_block_order(block_edge)
+    w = oracle.World(ref)
+    if block_edge:
+        w.set_block_order(block_edge)
+    keys = None
+    for step, dynamic in enumerate((False, True, True, False, False)):
+        mass = (im_k, ii_k) if dynamic else (0.0, 0.0)
+        g.t["inv_mass"][k] = mass[0]
+        g.t["inv_inertia"][k] = mass[1]
+        ref.inv_mass[k], ref.inv_inertia[k] = mass
+        w._b._cols["inv_mass"][k], w._b._cols["inv_inertia"][k] = mass
+        g.step(10)
+        w.step(10, grid=True)
+        c, v = g.contacts(), w.view()
+        assert np.array_equal(c["key"], v["key"])
+        if keys is not None:
+            assert np.array_equal(c["key"], keys)  # the pairs stay: only the dynamic bit changes
+        keys = c["key"].copy()
+        np.testing.assert_array_equal(c["colour"], v["colour"])
+        np.testing.assert_array_equal(c["P"], v["P"])
+        np.testing.assert_array_equal(g.state()["vel"], ref.vel)
+    g.close()

@@ -84,9 +84,20 @@ def test_subdomain_errors():
     g = nb.GpuScene(sc.copy())
     with pytest.raises(nb.NbgsError):
         g.set_subdomains(-1.0)
+    with pytest.raises(nb.NbgsError) as e:
+        g.set_subdomains(2.0)  # relaxation 1: the Jacobi coupling across subdomains diverges
+    assert e.value.status == 1 and "relaxation" in str(e.value)
+    g.close()
+    sc.relax = 0.75
+    g = nb.GpuScene(sc.copy())
     g.set_subdomains(2.0)
     with pytest.raises(nb.NbgsError):
         g.set_params(warm_start="learned")
+    with pytest.raises(nb.NbgsError) as e:
+        g.set_params(relax=1.0)
+    assert e.value.status == 1
+    g.set_subdomains(0.0)
+    g.set_params(relax=1.0)  # the colour-order solver takes it
     g.close()
     gb = nb.GpuBatch([sg.packed_cluster(56, counts=(4, 4, 3)), sg.packed_cluster(57, counts=(3, 3, 3))],
                      precision="fp64")
