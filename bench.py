@@ -15,18 +15,26 @@ gives the (colour, key) order, which is also timed beside it.
 Printed JSON line (one, rank 0):
   value         contact updates per second over the timed steps (FP64 sweeps,
                 50 sweeps/step, whole-step wall time, inputs resident in HBM);
-  roofline      the NBGS sweep kernel: compulsory bytes per launch over its
-                average launch time, from a HIP event pair around every sweep
-                launch of extra profiled steps (the timed steps run without);
+  roofline      one NBGS sweep (the unit of work): its compulsory bytes
+                (every contact record read and its impulse written, every
+                dynamic body's record read and v', w' written once) over its
+                average device time, from HIP event pairs around the sweep
+                launches of extra profiled steps (the timed steps run
+                without); the library's own per-launch byte count and the
+                counted HBM traffic beside it;
   cpu_baseline  the oracle (FP64 C) in its OpenMP mode on the host cores (at
-                most 16), one step of the same packing; its results equal the
-                one-core run's to the last bit.
-Further fields: steps/s to residual 1e-6 (FP64 and FP32 sweeps), sweeps used,
-phase times, contact statistics, the learned warm start, the subdomain NBGS
-beside the colour-ordered one, and the other workloads (walled 4,096-sphere
-box, 512-scene ensemble batch, 1M-sphere HCP ramp, 16.8M-sphere dilute gas,
-1M composite particles of two to four spheres: the paper's granular gas and a
-contact-rich packing of the same particles).
+                most 16), one step of the same packing (its results equal the
+                one-core run's to the last bit), and the one-core run.
+Further fields: steps/s and sweeps to residual 1e-6 on the frictionless
+variant of the packing (which reaches it every step) beside capped runs of the
+mu = 0.5 packing (which levels off near 1e-5), FP64 and FP32 sweeps; the same
+packing with moving bodies (contacts appear and vanish every step); phase
+times, contact statistics, the learned warm start (against the plain FP64
+form, to 1e-6), the subdomain NBGS beside the colour-ordered one, and the other
+workloads (walled 4,096-sphere box, 512-scene ensemble batch, 1M-sphere HCP
+ramp in both sweep orders, 16.8M-sphere dilute gas, 1M composite particles of
+two to four spheres: the paper's granular gas and a contact-rich packing of
+the same particles).
 """
 import argparse
 import json
@@ -101,6 +109,8 @@ def other_workloads(nb, sg, torch, dev):
     steps from the lattice, autotuned launch shape, graph-capable batch path), the 1,048,576-sphere HCP ramp (100
     FP64 sweeps, relaxation 0.75) and the 16.8M-sphere dilute gas (10 FP64 sweeps), each timed as whole steps with
     inputs resident on the device."""
+    import numpy as np
+
     out = {}
     sc = sg.walled_gas()
     g = nb.GpuScene(sc.copy(), device=dev, precision="fp64")
@@ -132,22 +142,41 @@ def other_workloads(nb, sg, torch, dev):
     log(f"ensemble: {out['ensemble_512']}")
 
     nx, ny, nz = 128, 128, 64
-    sc = sg.hcp_ramp(nx, ny, nz)
-    g = nb.GpuScene(sc, device=dev, precision="fp64")
-    g.step(100)
-    g.step(100)
-    wall, cs = _timed_steps(nb, torch, g, 5, 100)
-    st = g.state()
-    out["hcp_ramp_1m"] = {"bodies": sc.n, "steps": 5, "sweeps_per_step": 100, "relax": sc.relax,
-                          "steps_per_s": 5 / wall, "ms_per_step": wall / 5 * 1e3,
-                          "contact_updates_per_s": cs * 100 / wall, "contacts_per_step": cs / 5,
-                          "contacts_formula": nx * ny * (6 * nz - 1),
-                          "mean_downhill_velocity_after": float(st["vel"][:, 0].mean()),
-                          "phase_ms_last_step": [round(float(x), 3) for x in g.phase_times()], "dtype": "f64",
+    ramp = {}
+    # blocks of about six diameters per edge, as for the dense packing (about 300 spheres per block at the HCP
+    # solid fraction), against the (colour, key) order
+    for order, edge in (("block_local", 12e-3), ("colour", 0.0)):
+        sc = sg.hcp_ramp(nx, ny, nz)
+        g = nb.GpuScene(sc, device=dev, precision="fp64")
+        g.set_block_order(edge)
+        g.step(100)
+        g.step(100)
+        g.set_residual_history(False)
+        wall, cs = _timed_steps(nb, torch, g, 5, 100)
+        g.set_profiling(True)
+        nb.nbgs_detect(g.handle)
+        nb.nbgs_solve(g.handle, 100, 0.0)
+        nb.nbgs_integrate(g.handle)
+        torch.cuda.synchronize()
+        p = g.profile()
+        g.set_profiling(False)
+        st = g.state()
+        nc = cs / 5
+        sweep_us = p["sweep_kernel_ms"] / 100 * 1e3
+        alg = CONTACT_BYTES["fp64"] * nc + BODY_BYTES["fp64"] * float(np.sum(sc.inv_mass > 0))
+        ramp[order] = {"block_edge": edge, "steps_per_s": 5 / wall, "ms_per_step": wall / 5 * 1e3,
+                       "contact_updates_per_s": cs * 100 / wall, "contacts_per_step": nc,
+                       "avg_sweep_us": sweep_us, "algorithmic_bytes_per_sweep": alg,
+                       "roofline_frac": alg / (sweep_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                       "mean_downhill_velocity_after": float(st["vel"][:, 0].mean()),
+                       "phase_ms_last_step": [round(float(x), 3) for x in g.phase_times()]}
+        g.close()
+        log(f"hcp ramp ({order}): {ramp[order]}")
+    out["hcp_ramp_1m"] = {"bodies": nx * ny * nz, "steps": 5, "sweeps_per_step": 100, "relax": 0.75,
+                          "contacts_formula": nx * ny * (6 * nz - 1), "dtype": "f64",
                           "workload": "HCP 128x128x64 on a 30 degree ramp with a lid, r = 1 mm, 2.65 g/cm^3, "
-                                      "mu = 0.85, dt = 10 us, 10 cm/s downhill start, 100 sweeps, relaxation 0.75"}
-    g.close()
-    log(f"hcp ramp: {out['hcp_ramp_1m']}")
+                                      "mu = 0.85, dt = 10 us, 10 cm/s downhill start, 100 sweeps, relaxation 0.75",
+                          **{k: v for k, v in ramp["block_local"].items()}, "colour_order": ramp["colour"]}
 
     sc = sg.dilute_gas()
     g = nb.GpuScene(sc, device=dev, precision="fp64")
@@ -257,7 +286,7 @@ def _clone(nb, sg, g, sc, dev, precision, warm_start):
 
 
 def learned_warm_start(nb, sg, torch, dev, sc, cap, target, steps, train_steps=2, samples=1 << 20):
-    """Learned warm start on the dense packing.  The network supplies the initial impulse of contacts that the
+    """Learned warm start on the dense packing (the frictionless variant, whose steps reach the residual target).  The network supplies the initial impulse of contacts that the
     previous step did not have; it is trained on the solver's own impulses (FP64 solves capped at `cap` sweeps)
     with the previous-impulse features set to zero, as they are for a new contact.  Two situations are compared,
     FP64 and FP32 sweeps, each step solved to `target` or the cap: a continued run (every contact matched, so the
@@ -333,6 +362,18 @@ def learned_warm_start(nb, sg, torch, dev, sc, cap, target, steps, train_steps=2
                                      "residual": rec["residual_at_end"][0]}
             g2.close()
     out["cold_start_time_to_plain_residual"] = reach
+    # the extension's target: the learned start with FP32 sweeps reaches the residual target in less wall-clock
+    # time than the plain FP64 form (previous-step start), in continued steps and from a cold start
+    c5 = {"target": target}
+    for case in ("continued", "cold"):
+        plain, fast = runs[f"{case}_previous_fp64"], runs[f"{case}_learned_fp32"]
+        c5[case] = {"plain_fp64_seconds_per_step": plain["seconds_per_step"],
+                    "learned_fp32_seconds_per_step": fast["seconds_per_step"],
+                    "plain_fp64_sweeps": plain["sweeps"], "learned_fp32_sweeps": fast["sweeps"],
+                    "both_reached_target": bool(max(plain["residual_at_end"]) <= target
+                                                and max(fast["residual_at_end"]) <= target),
+                    "learned_fp32_faster": bool(fast["seconds_per_step"] < plain["seconds_per_step"])}
+    out["c5_learned_fp32_vs_plain_fp64"] = c5
     g.close()
     mlp.close()
     return out
@@ -544,11 +585,21 @@ def main():
         pwall, pcontacts, _, _, prof = run_steps(a.profile_steps, True)
         log(f"profiled: {a.profile_steps} steps in {pwall:.3f} s, {prof}")
         if prof["sweep_launches"] > 0 and prof["sweep_kernel_ms"] > 0:
-            per_launch_bytes = prof["sweep_bytes"] / prof["sweep_launches"]
-            per_launch_ms = prof["sweep_kernel_ms"] / prof["sweep_launches"]
-            achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+            # the unit of work is one sweep (every contact relaxed once: the block pass plus the cross colours in
+            # the block-local order, the colour launches in the (colour, key) order); its algorithmic bytes are the
+            # compulsory count: every contact record read and its impulse written (104 B FP64 / 56 B FP32) and every
+            # dynamic body's record read and v', w' written once (112 B / 56 B)
+            n_sweeps = a.profile_steps * a.sweeps
+            sweep_ms = prof["sweep_kernel_ms"] / n_sweeps
+            n_dyn = float(np.sum(sc.inv_mass > 0))
+            alg_bytes = CONTACT_BYTES[a.precision] * float(np.mean(pcontacts)) + BODY_BYTES[a.precision] * n_dyn
+            achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
+            # the library's own per-launch count (body records once per launch that touches them, slot indices)
+            lib_bytes = prof["sweep_bytes"] / n_sweeps
             traffic = measured_traffic(("subdomain_" if a.subdomain_edge > 0 else "block_" if a.block_edge > 0 else "")
                                        + a.precision)
+            if traffic is not None and a.subdomain_edge <= 0 and a.block_edge <= 0:
+                traffic *= prof["sweep_launches"] / n_sweeps  # the colour order's counters are per colour launch
             tn = "double" if a.precision == "fp64" else "float"
             tu = g.tuning()
             if a.subdomain_edge > 0:
@@ -557,23 +608,22 @@ def main():
                 kernel_name = (f"k_blk_pass<{tn}, 1> + k_sweep_grp<{tn}, {tu['block']}, "
                                f"{str(bool(tu['nontemporal'])).lower()}> (one sweep)")
             elif tu["lane_groups"]:
-                kernel_name = f"k_sweep_grp<{tn}, {tu['block']}, {str(bool(tu['nontemporal'])).lower()}>"
+                kernel_name = f"k_sweep_grp<{tn}, {tu['block']}, {str(bool(tu['nontemporal'])).lower()}> (one sweep)"
             else:
                 kernel_name = (f"k_sweep<{tn}, {tu['block']}, {tu['contacts_per_thread']}, "
-                               f"{str(bool(tu['nontemporal'])).lower()}, {str(bool(tu['full_store'])).lower()}>")
-            # secondary model: every body record read and written once per sweep, as if it stayed cached
-            # between the colours of a sweep
-            sweep_model_bytes = (CONTACT_BYTES[a.precision] * float(np.mean(pcontacts))
-                                 + BODY_BYTES[a.precision] * float(np.sum(sc.inv_mass > 0))) * a.sweeps
-            sweep_ms_per_step = prof["sweep_kernel_ms"] / a.profile_steps
+                               f"{str(bool(tu['nontemporal'])).lower()}, {str(bool(tu['full_store'])).lower()}> "
+                               f"(one sweep)")
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": kernel_name,
-                    "bytes_per_launch": round(per_launch_bytes),
-                    "avg_launch_us": round(per_launch_ms * 1e3, 2), "launches": prof["sweep_launches"],
+                    "kernel": kernel_name, "unit_of_work": "one sweep",
+                    "algorithmic_bytes_per_sweep": round(alg_bytes),
+                    "avg_sweep_us": round(sweep_ms * 1e3, 2), "sweeps": n_sweeps,
+                    "launches_per_sweep": prof["sweep_launches"] / n_sweeps,
+                    "traffic_over_algorithmic": None if traffic is None else round(traffic / alg_bytes, 3),
+                    "library_model_bytes_per_sweep": round(lib_bytes),
+                    "library_model_frac": round(lib_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "sweep_only_updates_per_s": prof["contact_updates"] / (prof["sweep_kernel_ms"] * 1e-3),
-                    "ms_per_step_profiled": pwall / a.profile_steps * 1e3,
-                    "sweep_model_frac": round(sweep_model_bytes / (sweep_ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                    "ms_per_step_profiled": pwall / a.profile_steps * 1e3}
 
     # what a plain device-to-device copy reaches here (read + write bytes over time): the practical ceiling
     # that the spec-sheet HBM figure does not show
@@ -607,33 +657,76 @@ def main():
         log(f"colour order: {order_cmp}")
 
     # ------------------------------------------------ to residual 1e-6 modes
+    # With mu = 0.5 the step's problem on this packing has a continuum of impulse solutions (friction in a packing
+    # with more contact constraints than degrees of freedom): the sweeps settle the velocities, but the impulses keep
+    # creeping along that set by nearly self-equilibrated changes, and R_k levels off near 1e-5 (the capped runs are
+    # reported beside).  The same packing without friction (mu = 0: the same bodies and contacts) reaches 1e-6 every
+    # step; it is the workload of the steps/s-to-1e-6 figure.
     resid = {}
+    sc0 = sc.copy()
+    sc0.mu = 0.0
     if a.residual_steps > 0:
-        for prec in ("fp64", "fp32"):
-            gr = nb.GpuScene(sc.copy(), device=dev, precision=prec, warm_start="previous")
-            gr.step(a.max_sweeps, a.target)  # load built from zero impulses, as in the warm-up above
-            gr.step(a.sweeps)
-            torch.cuda.synchronize()
-            sweeps_used = []
-            conv = []
-            res_end = []
-            r0 = time.perf_counter()
-            for i in range(a.residual_steps):
-                st = gr.step(a.max_sweeps, a.target)
-                sweeps_used.append(st["sweeps"])
-                conv.append(bool(st["converged"]))
-                res_end.append(st["residual"])
-            torch.cuda.synchronize()
-            r1 = time.perf_counter()
-            resid[prec] = {"steps_per_s": a.residual_steps / (r1 - r0), "sweeps_per_step": sweeps_used,
-                           "converged": conv, "residual_at_end": res_end, "sweep_cap": a.max_sweeps,
-                           "seconds_per_step": (r1 - r0) / a.residual_steps}
-            log(f"to-residual {prec}: {resid[prec]}")
-            gr.close()
+        for label, scene in (("mu0", sc0), ("mu05_capped", sc)):
+            resid[label] = {"workload": f"the same {sc.n}-sphere packing, mu = {scene.mu:g}, block-local order "
+                                        f"(edge {a.block_edge:g}), previous-step warm start, each step swept to "
+                                        f"R <= {a.target:g} or {a.max_sweeps} sweeps"}
+            for prec in ("fp64", "fp32"):
+                gr = nb.GpuScene(scene.copy(), device=dev, precision=prec, warm_start="previous")
+                gr.set_block_order(a.block_edge)
+                gr.step(a.max_sweeps, a.target)  # load built from zero impulses, as in the warm-up above
+                gr.step(a.max_sweeps, a.target)
+                torch.cuda.synchronize()
+                sweeps_used, conv, res_end, secs = [], [], [], []
+                r0 = time.perf_counter()
+                for i in range(a.residual_steps):
+                    t0 = time.perf_counter()
+                    st = gr.step(a.max_sweeps, a.target)
+                    secs.append(time.perf_counter() - t0)
+                    sweeps_used.append(st["sweeps"])
+                    conv.append(bool(st["converged"]))
+                    res_end.append(st["residual"])
+                torch.cuda.synchronize()
+                r1 = time.perf_counter()
+                resid[label][prec] = {"steps_per_s": a.residual_steps / (r1 - r0), "sweeps_per_step": sweeps_used,
+                                      "converged": conv, "residual_at_end": res_end, "sweep_cap": a.max_sweeps,
+                                      "seconds_per_step": (r1 - r0) / a.residual_steps, "seconds": secs}
+                log(f"to-residual {label} {prec}: {resid[label][prec]}")
+                gr.close()
 
     learned = None
     if a.residual_steps > 0 and not a.no_extras:
-        learned = learned_warm_start(nb, sg, torch, dev, sc, a.max_sweeps, a.target, a.residual_steps)
+        learned = learned_warm_start(nb, sg, torch, dev, sc0, a.max_sweeps, a.target, a.residual_steps)
+
+    # the same packing shaken (Maxwellian velocities): pairs appear and vanish every step, so the colouring and the
+    # block set-up run every step instead of being reused
+    moving = None
+    if not a.no_extras:
+        sm = sc.copy()
+        rng = np.random.default_rng(8)
+        sm.vel = rng.normal(0.0, 1.0, size=(sm.n, 3))
+        sm.angvel = rng.normal(0.0, 1.0, size=(sm.n, 3))
+        gm = nb.GpuScene(sm, device=dev, precision=a.precision, warm_start="previous")
+        gm.set_block_order(a.block_edge)
+        gm.step(a.sweeps)
+        gm.step(a.sweeps)
+        gm.set_residual_history(False)
+        k0 = gm.contacts()["key"]
+        wall_m, cs_m = _timed_steps(nb, torch, gm, 10, a.sweeps)
+        ph_m = gm.phase_times()
+        k1 = gm.contacts()["key"]
+        gm.step(a.sweeps)
+        k2 = gm.contacts()["key"]
+        moving = {"workload": f"the same {sc.n}-sphere packing (mu = 0.5, FP64 block-local order) with Maxwellian "
+                              "velocities and spins (sigma = 1), 50 sweeps per step",
+                  "steps": 10, "ms_per_step": wall_m / 10 * 1e3, "contact_updates_per_s": cs_m * a.sweeps / wall_m,
+                  "mean_contacts": cs_m / 10,
+                  "pairs_new_in_last_step": int(np.setdiff1d(k2, k1).size),
+                  "pairs_gone_in_last_step": int(np.setdiff1d(k1, k2).size),
+                  "pairs_changed_over_timed_steps": int(np.setdiff1d(k1, k0).size + np.setdiff1d(k0, k1).size),
+                  "phase_ms_last_step": {k: round(float(x), 3) for k, x in
+                                         zip(("detect", "colour_order", "init", "sweeps", "integrate"), ph_m)}}
+        gm.close()
+        log(f"moving packing: {moving}")
 
     extra = {} if a.no_extras else other_workloads(nb, sg, torch, dev)
     sub = None if a.no_extras else subdomain_solver(nb, torch, dev, sc, a.sweeps)
@@ -643,6 +736,12 @@ def main():
     if a.cpu_tiles > 0:
         cpu, osc, ow = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge, cpu_threads(a.cpu_threads))
         log(f"cpu baseline: {cpu}")
+        if cpu["cores"] > 1:
+            # the sequential oracle (one core) on the same sample: the parity reference as it runs in the tests
+            one, _, w1 = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge, 1)
+            cpu["one_core"] = {"value": one["value"], "unit": one["unit"], "cores": 1, "seconds": one["seconds"]}
+            log(f"cpu baseline, one core: {one}")
+            del w1
         # the same step on the GPU from the same state, FP64 and FP32 sweeps, against the oracle's result
         vs_oracle = errors_against_oracle(nb, torch, dev, osc, ow, a.sweeps, a.block_edge)
         log(f"against the oracle: {vs_oracle}")
@@ -673,13 +772,17 @@ def main():
         "steps_per_s": a.steps / wall,
         "phase_ms_last_step": {"detect": phases[0], "colour_order": phases[1], "init": phases[2],
                                "sweeps": phases[3], "integrate": phases[4]},
+        "steps_per_s_to_residual_1e-6": (resid.get("mu0", {}).get("fp64", {}).get("steps_per_s")
+                                         if resid else None),
         "to_residual_1e-6": resid,
+        "changing_contact_set": moving,
         "learned_warm_start": learned,
         "other_workloads": extra,
         "subdomain_nbgs": sub,
         "colour_order_same_workload": order_cmp,
         "roofline": roof,
-        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                                     "one_core") if k in cpu},
         "errors_against_oracle": vs_oracle,
     }
     print(json.dumps(out), flush=True)
