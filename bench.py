@@ -104,13 +104,28 @@ def _timed_steps(nb, torch, g, steps, sweeps):
     return time.perf_counter() - t0, cs
 
 
-def other_workloads(nb, sg, torch, dev):
+def other_workloads(nb, sg, torch, dev, only=None):
     """The walled 4,096-sphere box (100 steps x 10 FP64 sweeps), the 512-scene ensemble (FP32, 20 sweeps, 200
     steps from the lattice, autotuned launch shape, graph-capable batch path), the 1,048,576-sphere HCP ramp (100
     FP64 sweeps, relaxation 0.75) and the 16.8M-sphere dilute gas (10 FP64 sweeps), each timed as whole steps with
     inputs resident on the device."""
     import numpy as np
 
+    out = {}
+    if only in (None, "walled"):
+        out.update(_walled(nb, sg, torch, dev))
+    if only in (None, "ensemble"):
+        out.update(_ensemble(nb, sg, torch, dev))
+    if only in (None, "ramp"):
+        out.update(_ramp(nb, sg, torch, dev))
+    if only in (None, "gas"):
+        out.update(_gas(nb, sg, torch, dev))
+    if only in (None, "composite"):
+        out.update(composite_workloads(nb, sg, torch, dev))
+    return out
+
+
+def _walled(nb, sg, torch, dev):
     out = {}
     sc = sg.walled_gas()
     g = nb.GpuScene(sc.copy(), device=dev, precision="fp64")
@@ -120,7 +135,11 @@ def other_workloads(nb, sg, torch, dev):
                               "contact_updates_per_s": cs * 10 / wall, "mean_contacts": cs / 100, "dtype": "f64"}
     g.close()
     log(f"walled box: {out['walled_box_4096']}")
+    return out
 
+
+def _ensemble(nb, sg, torch, dev):
+    out = {}
     scenes = sg.batch_scenes()
     gb = nb.GpuBatch(scenes, device=dev, precision="fp32")
     torch.cuda.synchronize()
@@ -140,7 +159,13 @@ def other_workloads(nb, sg, torch, dev):
                            "note": "whole steps incl. the first step's autotuning; scenes start on their lattice"}
     gb.close()
     log(f"ensemble: {out['ensemble_512']}")
+    return out
 
+
+def _ramp(nb, sg, torch, dev):
+    import numpy as np
+
+    out = {}
     nx, ny, nz = 128, 128, 64
     ramp = {}
     # blocks of about six diameters per edge, as for the dense packing (about 300 spheres per block at the HCP
@@ -148,7 +173,7 @@ def other_workloads(nb, sg, torch, dev):
     for order, edge in (("block_local", 12e-3), ("colour", 0.0)):
         sc = sg.hcp_ramp(nx, ny, nz)
         g = nb.GpuScene(sc, device=dev, precision="fp64")
-        g.set_block_order(edge)
+        g.set_block_order(edge, grids=4)
         g.step(100)
         g.step(100)
         g.set_residual_history(False)
@@ -177,7 +202,11 @@ def other_workloads(nb, sg, torch, dev):
                           "workload": "HCP 128x128x64 on a 30 degree ramp with a lid, r = 1 mm, 2.65 g/cm^3, "
                                       "mu = 0.85, dt = 10 us, 10 cm/s downhill start, 100 sweeps, relaxation 0.75",
                           **{k: v for k, v in ramp["block_local"].items()}, "colour_order": ramp["colour"]}
+    return out
 
+
+def _gas(nb, sg, torch, dev):
+    out = {}
     sc = sg.dilute_gas()
     g = nb.GpuScene(sc, device=dev, precision="fp64")
     g.step(10)
@@ -187,7 +216,6 @@ def other_workloads(nb, sg, torch, dev):
                              "phase_ms_last_step": [round(float(x), 3) for x in g.phase_times()], "dtype": "f64"}
     g.close()
     log(f"dilute gas: {out['dilute_gas_16m']}")
-    out.update(composite_workloads(nb, sg, torch, dev))
     return out
 
 
@@ -413,7 +441,7 @@ def cpu_threads(requested: int) -> int:
     return max(1, min(16, avail))
 
 
-def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0, threads: int = 1):
+def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0, threads: int = 1, grids: int = 1):
     """The oracle, one step of a sample of the packing (sample_tiles^2 tiles of 10,000 spheres), in the sweep order
     the GPU run uses; the sweeps and the grid detection on `threads` host threads (the oracle's OpenMP mode;
     colouring and integration stay sequential)."""
@@ -422,7 +450,7 @@ def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0, thread
 
     oracle.set_threads(threads)
     sc = sg.dense_packing(tiles=sample_tiles)
-    w = oracle.World(sc.copy()).set_block_order(block_edge)
+    w = oracle.World(sc.copy()).set_block_order(block_edge, grids=grids)
     t0 = time.perf_counter()
     w.step(sweeps, grid=True, warm=False)
     t1 = time.perf_counter()
@@ -431,7 +459,8 @@ def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0, thread
     where = ("on one host core" if threads == 1
              else f"on {threads} host threads (the oracle's OpenMP mode: sweeps and grid detection in parallel)")
     return dict(value=upd / (t1 - t0), unit="contact updates/s", cores=threads, kind="oracle",
-                sample=f"1 step ({sweeps} FP64 sweeps" + (f" in the block-local order, edge {block_edge:g}"
+                sample=f"1 step ({sweeps} FP64 sweeps" + (f" in the block-local order, edge {block_edge:g}, "
+                                                           f"{grids} grid{'s' if grids > 1 else ''}"
                                                            if block_edge > 0 else "")
                        + ", detection, colouring, integration) of a "
                        f"{sample_tiles}x{sample_tiles}-tile cut of the packing: {sc.n} spheres, "
@@ -439,7 +468,7 @@ def cpu_baseline(sample_tiles: int, sweeps: int, block_edge: float = 0.0, thread
                 seconds=t1 - t0), sc, w
 
 
-def errors_against_oracle(nb, torch, dev, sc, w, sweeps, block_edge=0.0):
+def errors_against_oracle(nb, torch, dev, sc, w, sweeps, block_edge=0.0, grids=1):
     """One GPU step from the scene the oracle stepped, with FP64 and with FP32 sweeps: contact lists compared bit for
     bit, impulses and velocities as the largest deviation relative to the largest magnitude of the oracle's."""
     import numpy as np
@@ -451,7 +480,7 @@ def errors_against_oracle(nb, torch, dev, sc, w, sweeps, block_edge=0.0):
 
     out = {}
     for prec in ("fp64", "fp32"):
-        g = nb.GpuScene(sc.copy(), device=dev, precision=prec).set_block_order(block_edge)
+        g = nb.GpuScene(sc.copy(), device=dev, precision=prec).set_block_order(block_edge, grids=grids)
         g.step(sweeps)
         c = g.contacts()
         st = g.state()
@@ -489,10 +518,15 @@ def main():
     ap.add_argument("--block-edge", type=float, default=6.5,
                     help="sweep the plain NBGS in the block-local order with blocks of this edge (0: (colour, key) "
                          "order)")
+    ap.add_argument("--block-grids", type=int, default=4,
+                    help="block grids of the block-local order, shifted by 1/grids of an edge (1: one grid, the "
+                         "contacts between its blocks swept by colour)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (walled box, ensemble batch, dilute gas)")
     ap.add_argument("--composite-only", action="store_true",
                     help="only time the composite-particle workloads and print them as the JSON line")
+    ap.add_argument("--only", choices=("walled", "ensemble", "ramp", "gas", "composite"), default=None,
+                    help="only time one of the other workloads and print it as the JSON line (for profiling)")
     a = ap.parse_args()
 
     if a.calibrate_copy > 0:
@@ -528,6 +562,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.only is not None:
+        print(json.dumps(other_workloads(nb, sg, torch, dev, only=a.only)), flush=True)
+        return
     if a.composite_only:
         comp = composite_workloads(nb, sg, torch, dev)
         gas = comp["composite_gas_1m"]
@@ -546,7 +583,7 @@ def main():
         a.block_edge = 0.0
         g.set_subdomains(a.subdomain_edge)
     elif a.block_edge > 0:
-        g.set_block_order(a.block_edge)
+        g.set_block_order(a.block_edge, grids=a.block_grids)
 
     # ---------------------------------------------------- fixed sweeps, FP64
     for i in range(a.warmup):
@@ -596,14 +633,16 @@ def main():
             achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
             # the library's own per-launch count (body records once per launch that touches them, slot indices)
             lib_bytes = prof["sweep_bytes"] / n_sweeps
-            traffic = measured_traffic(("subdomain_" if a.subdomain_edge > 0 else "block_" if a.block_edge > 0 else "")
-                                       + a.precision)
+            traffic = measured_traffic(("subdomain_" if a.subdomain_edge > 0 else
+                                        f"block{a.block_grids}_" if a.block_edge > 0 else "") + a.precision)
             if traffic is not None and a.subdomain_edge <= 0 and a.block_edge <= 0:
                 traffic *= prof["sweep_launches"] / n_sweeps  # the colour order's counters are per colour launch
             tn = "double" if a.precision == "fp64" else "float"
             tu = g.tuning()
             if a.subdomain_edge > 0:
                 kernel_name = f"k_sub_pass<{tn}> + k_sub_reduce<{tn}>"
+            elif a.block_edge > 0 and a.block_grids > 1:
+                kernel_name = f"k_blk_pass<{tn}, 1> x {a.block_grids} grids (one sweep)"
             elif a.block_edge > 0:
                 kernel_name = (f"k_blk_pass<{tn}, 1> + k_sweep_grp<{tn}, {tu['block']}, "
                                f"{str(bool(tu['nontemporal'])).lower()}> (one sweep)")
@@ -672,7 +711,7 @@ def main():
                                         f"R <= {a.target:g} or {a.max_sweeps} sweeps"}
             for prec in ("fp64", "fp32"):
                 gr = nb.GpuScene(scene.copy(), device=dev, precision=prec, warm_start="previous")
-                gr.set_block_order(a.block_edge)
+                gr.set_block_order(a.block_edge, grids=a.block_grids)
                 gr.step(a.max_sweeps, a.target)  # load built from zero impulses, as in the warm-up above
                 gr.step(a.max_sweeps, a.target)
                 torch.cuda.synchronize()
@@ -706,7 +745,7 @@ def main():
         sm.vel = rng.normal(0.0, 1.0, size=(sm.n, 3))
         sm.angvel = rng.normal(0.0, 1.0, size=(sm.n, 3))
         gm = nb.GpuScene(sm, device=dev, precision=a.precision, warm_start="previous")
-        gm.set_block_order(a.block_edge)
+        gm.set_block_order(a.block_edge, grids=a.block_grids)
         gm.step(a.sweeps)
         gm.step(a.sweeps)
         gm.set_residual_history(False)
@@ -734,16 +773,16 @@ def main():
     cpu = None
     vs_oracle = None
     if a.cpu_tiles > 0:
-        cpu, osc, ow = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge, cpu_threads(a.cpu_threads))
+        cpu, osc, ow = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge, cpu_threads(a.cpu_threads), a.block_grids)
         log(f"cpu baseline: {cpu}")
         if cpu["cores"] > 1:
             # the sequential oracle (one core) on the same sample: the parity reference as it runs in the tests
-            one, _, w1 = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge, 1)
+            one, _, w1 = cpu_baseline(a.cpu_tiles, a.sweeps, a.block_edge, 1, a.block_grids)
             cpu["one_core"] = {"value": one["value"], "unit": one["unit"], "cores": 1, "seconds": one["seconds"]}
             log(f"cpu baseline, one core: {one}")
             del w1
         # the same step on the GPU from the same state, FP64 and FP32 sweeps, against the oracle's result
-        vs_oracle = errors_against_oracle(nb, torch, dev, osc, ow, a.sweeps, a.block_edge)
+        vs_oracle = errors_against_oracle(nb, torch, dev, osc, ow, a.sweeps, a.block_edge, a.block_grids)
         log(f"against the oracle: {vs_oracle}")
         del ow
 
@@ -763,7 +802,8 @@ def main():
         "config": {"workload": f"dense settled packing, {sc.n} polydisperse spheres r~U[0.45,0.55], "
                                f"periodic 100x100 floor box, phi~0.6, mu=0.5, dt=1e-4, {a.sweeps} {a.precision.upper()} "
                                + (f"subdomain NBGS (blocks of edge {a.subdomain_edge:g}) " if a.subdomain_edge > 0
-                                  else f"NBGS in the block-local order (blocks of edge {a.block_edge:g}) "
+                                  else f"NBGS in the block-local order (blocks of edge {a.block_edge:g}, "
+                                       f"{a.block_grids} shifted grid{'s' if a.block_grids > 1 else ''}) "
                                   if a.block_edge > 0 else "NBGS in (colour, key) order ")
                                + f"sweeps/step, relaxation {sc.relax:g}, previous-step warm start",
                    "n_bodies": sc.n, "contacts_per_step": float(np.mean(contacts)),

@@ -19,8 +19,15 @@
  *   - Pointers marked [device] are HIP device pointers, [host] are host
  *     pointers.  Body arrays are owned by the caller (e.g. torch tensors) and
  *     borrowed by the scene for its lifetime; nbgs_integrate / nbgs_step write
- *     positions, orientations and velocities in place.  Everything else the
- *     scene needs it allocates itself and frees in nbgs_scene_destroy.
+ *     positions, orientations and velocities in place.
+ *   - Device memory: the library allocates none.  Every handle (scene, batch,
+ *     composite scene, network) is given a workspace [device] by its caller
+ *     (e.g. a torch byte tensor), sized by the matching *_workspace_query, and
+ *     carves all its buffers from it; the workspace stays owned by the caller
+ *     and must outlive the handle.  A detection whose contacts exceed the
+ *     workspace's contact capacity returns CAPACITY with the contact count in
+ *     nbgs_stats.n_contacts and leaves the scene as it was: query the size for
+ *     that count, allocate, nbgs_scene_set_workspace, detect again.
  *   - All device work is enqueued on the stream passed to nbgs_scene_create
  *     (NULL = the legacy default stream).  Entry points that return counts in a
  *     host nbgs_stats synchronise that stream before returning.
@@ -44,7 +51,7 @@
 extern "C" {
 #endif
 
-#define NBGS_ABI_VERSION 1
+#define NBGS_ABI_VERSION 2
 
 typedef enum {
     NBGS_OK = 0,
@@ -131,17 +138,43 @@ int32_t nbgs_abi_version(void);
  * pointer stays valid until the next failing call on the same thread. */
 const char *nbgs_last_error(void);
 
-/* Create a scene that borrows the body arrays.  bodies, domain, params:
- * [host] structs (the body pointers inside are [device]).  hip_stream: a
- * hipStream_t or NULL.  Errors: INVALID_ARG (n < 1, n >= 2^31 - 64, null
- * pointer, dt <= 0, relax not in (0,1], a static body with inv_inertia != 0,
- * a non-unit plane normal), OUT_OF_MEMORY, DEVICE.  *out receives the handle,
- * which the caller releases with nbgs_scene_destroy. */
-nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *domain, const nbgs_params *params,
-                              void *hip_stream, nbgs_scene_t *out);
+/* Bytes of device workspace a scene of n_bodies bodies with up to
+ * contact_capacity contacts needs, in every sweep order, precision and warm
+ * start (an upper bound: per body 613 B, per contact 1,000 B, plus a cell
+ * table of 2^16 cells, 16 MiB, and ten per cent).  params [host] may be NULL
+ * (checked when given).  *bytes [host].  Pure host computation: no device is
+ * touched.  Errors: INVALID_ARG. */
+nbgs_status nbgs_workspace_query(int64_t n_bodies, int64_t contact_capacity, const nbgs_params *params,
+                                 size_t *bytes);
 
-/* Release the scene and everything it allocated (synchronises its stream).
- * The body arrays are not touched.  NULL is accepted. */
+/* Create a scene that borrows the body arrays.  bodies, domain, params:
+ * [host] structs (the body pointers inside are [device]).  workspace
+ * [device], workspace_bytes: the caller's region the scene carves all its
+ * device buffers from (nbgs_workspace_query; at least 256-byte aligned use is
+ * made of it), borrowed until nbgs_scene_destroy or the next
+ * nbgs_scene_set_workspace.  hip_stream: a hipStream_t or NULL.  Errors:
+ * INVALID_ARG (n < 1, n >= 2^31 - 64, null pointer or workspace, dt <= 0,
+ * relax not in (0,1], a static body with inv_inertia != 0, a non-unit plane
+ * normal), CAPACITY (the workspace cannot hold the per-body buffers),
+ * OUT_OF_MEMORY (host), DEVICE.  *out receives the handle, which the caller
+ * releases with nbgs_scene_destroy. */
+nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *domain, const nbgs_params *params,
+                              void *workspace, size_t workspace_bytes, void *hip_stream, nbgs_scene_t *out);
+
+/* Move the scene into another workspace [device] of `bytes` (typically a
+ * larger one after nbgs_detect returned CAPACITY): every buffer in use is
+ * copied, packed, into the new region on the scene's stream, which is then
+ * synchronised, so the old workspace may be released once this returns.  The
+ * regions must not overlap.  Errors: INVALID_ARG (NULL, too small, overlap),
+ * CAPACITY (the buffers in use do not fit; nothing moved), DEVICE. */
+nbgs_status nbgs_scene_set_workspace(nbgs_scene_t scene, void *workspace, size_t bytes);
+
+/* Size of the scene's workspace, the bytes its buffers use now and the most
+ * they used at once, each [host] and NULL-able. */
+nbgs_status nbgs_scene_workspace_usage(nbgs_scene_t scene, size_t *size, size_t *used, size_t *peak);
+
+/* Release the scene (synchronises its stream).  The body arrays and the
+ * workspace are not touched.  NULL is accepted. */
 nbgs_status nbgs_scene_destroy(nbgs_scene_t scene);
 
 /* Replace the parameters (e.g. switch precision or warm start between steps).
@@ -157,11 +190,14 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t scene, const nbgs_params *params)
  * inv_mass > 0) and ordered by (colour, key) for the sweeps, and the initial
  * impulses are set (params.warm_start).  stats: [host] or NULL (then only
  * n_contacts of the scene is known after the next synchronising call).
- * Errors: CAPACITY (more than 255 colours; more than 2^31 - 256 contacts,
- * counted in 64 bits before any list is sized; a body meeting more than 2^18
- * hull candidates in its 27 cells, which happens when one hull, e.g. of a
- * diverged state, makes the cell grid too coarse; in subdomain mode more
- * than 2^30 contacts), OUT_OF_MEMORY, DEVICE. */
+ * Errors: CAPACITY (more contacts than the workspace holds, found before
+ * any list is written: stats->n_contacts = the contact count, the scene
+ * unchanged, see nbgs_scene_set_workspace; more than 255 colours; more than
+ * 2^31 - 256 contacts, counted in 64 bits before any list is sized; a body
+ * meeting more than 2^18 hull candidates in its 27 cells, which happens when
+ * one hull, e.g. of a diverged state, makes the cell grid too coarse; in
+ * subdomain mode more than 2^30 contacts; block or subdomain tables larger
+ * than the workspace allows), OUT_OF_MEMORY, DEVICE. */
 nbgs_status nbgs_detect(nbgs_scene_t scene, nbgs_stats *stats);
 
 /* NBGS sweeps over the detected contacts (Alg. 1, one subdomain, colour
@@ -237,6 +273,22 @@ nbgs_status nbgs_set_subdomains(nbgs_scene_t scene, double edge);
  * edge.  INVALID_ARG while the subdomain solver is on; UNSUPPORTED for
  * batches and with the learned warm start. */
 nbgs_status nbgs_set_block_order(nbgs_scene_t scene, double edge);
+
+/* Number of block grids of the block-local order (1 .. 8, default 1): grid g
+ * is the block grid of nbgs_set_block_order shifted by g/grids of a block edge
+ * along every axis (taken modulo the box along a periodic axis; along another
+ * axis a shifted grid has one block more).  A contact is local to the first
+ * grid in one of whose blocks all its dynamic bodies lie, with the id g B +
+ * block (B blocks per grid), or a contact between blocks if there is none.  A
+ * sweep takes the local contacts grid by grid (blocks ascending, each in
+ * (colour, key) order; the local contacts of two blocks of a grid share no
+ * dynamic body, so a grid's blocks run as independent workgroups), then the
+ * rest in (colour, key) order: the same plain NBGS (Alg. 1 with one
+ * subdomain), visited in another order.  With four grids a contact whose
+ * centres differ by less than a quarter block edge along every axis is
+ * always local.  Takes effect at the next detection; INVALID_ARG outside
+ * 1 .. 8. */
+nbgs_status nbgs_set_block_grids(nbgs_scene_t scene, int32_t grids);
 
 /* enable = 1 (default): the residual R_k of every sweep is formed.  enable =
  * 0: a solve without a residual target forms only the last sweep's residual
@@ -355,12 +407,22 @@ typedef struct nbgs_batch_s *nbgs_batch_t;
  * NBGS_WS_LEARNED is UNSUPPORTED.  Wall w of scene s has body id
  * bodies->n + (walls of scenes 0 .. s-1) + w in contact lists.
  * tune_cache_path [host, may be NULL, copied]: autotuner cache file (see
- * nbgs_autotune).  The batch replays its sweeps from a captured HIP graph over
- * resident workgroups and autotunes the launch shape on its first step of
- * each precision unless nbgs_set_tuning set one. */
+ * nbgs_autotune).  workspace [device], workspace_bytes: as for
+ * nbgs_scene_create, sized by nbgs_batch_workspace_query; a batch moves to a
+ * larger one with nbgs_scene_set_workspace on nbgs_batch_scene's handle.  The
+ * batch autotunes the launch shape of its sweeps on its first step of each
+ * precision unless nbgs_set_tuning set one (the candidates include replay of
+ * the sweeps from a captured HIP graph over resident workgroups). */
 nbgs_status nbgs_batch_create(int32_t n_scenes, const int64_t *body_offsets, const nbgs_bodies *bodies,
                               const nbgs_domain *domains, const nbgs_params *params, const char *tune_cache_path,
-                              void *hip_stream, nbgs_batch_t *out);
+                              void *workspace, size_t workspace_bytes, void *hip_stream, nbgs_batch_t *out);
+
+/* Bytes of device workspace a batch of n_scenes scenes, n_bodies bodies in all
+ * and up to contact_capacity contacts in all needs (nbgs_workspace_query's
+ * bound with one cell table per scene).  params [host, n_scenes, may be
+ * NULL].  Errors: INVALID_ARG. */
+nbgs_status nbgs_batch_workspace_query(int32_t n_scenes, int64_t n_bodies, int64_t contact_capacity,
+                                       const nbgs_params *params, size_t *bytes);
 nbgs_status nbgs_batch_destroy(nbgs_batch_t batch);
 
 /* The scene handle behind the batch (owned by the batch): every nbgs_scene_t
@@ -371,9 +433,13 @@ nbgs_status nbgs_batch_scene(nbgs_batch_t batch, nbgs_scene_t *scene);
 
 /* n_steps time steps of every scene (detect, solve with max_sweeps /
  * residual_target as nbgs_solve, integrate).  *stats [host, may be NULL]: the
- * last step's totals.  NOT_CONVERGED if the last solve missed its target. */
+ * last step's totals.  *steps_done [host, may be NULL]: steps completed.
+ * NOT_CONVERGED if the last solve missed its target.  CAPACITY when a
+ * detection finds more contacts than the workspace holds: that step has not
+ * run, stats->n_contacts holds the count (grow the workspace through
+ * nbgs_batch_scene's handle and continue with the remaining steps). */
 nbgs_status nbgs_batch_step(nbgs_batch_t batch, int32_t n_steps, int32_t max_sweeps, double residual_target,
-                            nbgs_stats *stats);
+                            nbgs_stats *stats, int32_t *steps_done);
 
 /* Per-scene contact and colour counts of the last detected step into
  * n_contacts, n_colours [host, n entries, n = the scene count].  Synchronises. */
@@ -392,10 +458,20 @@ typedef struct nbgs_mlp_s *nbgs_mlp_t;
 /* Number of weights (18,563). */
 int32_t nbgs_mlp_param_count(void);
 
+/* Bytes of device workspace of a network whose store of collected training
+ * pairs holds max_samples samples and which trains on at most that many at a
+ * time (weights, Adam moments, gradient partials of up to 1,024 blocks, and
+ * 64 B per sample).  Errors: INVALID_ARG. */
+nbgs_status nbgs_mlp_workspace_query(int64_t max_samples, size_t *bytes);
+
 /* Create a network with deterministic initial weights (He-uniform hidden
  * layers, output layer scaled by 0.1, zero biases; uniforms from
- * splitmix64(seed + index)).  hip_stream as for scenes. */
-nbgs_status nbgs_mlp_create(uint64_t seed, void *hip_stream, nbgs_mlp_t *out);
+ * splitmix64(seed + index)).  max_samples: capacity of its store of collected
+ * training pairs (nbgs_mlp_collect).  workspace [device], workspace_bytes:
+ * the caller's region (nbgs_mlp_workspace_query), borrowed until
+ * nbgs_mlp_destroy.  hip_stream as for scenes. */
+nbgs_status nbgs_mlp_create(uint64_t seed, int64_t max_samples, void *workspace, size_t workspace_bytes,
+                            void *hip_stream, nbgs_mlp_t *out);
 nbgs_status nbgs_mlp_destroy(nbgs_mlp_t mlp);
 
 /* Replace / read the FP32 master weights ([host], 18,563 floats).  Setting
@@ -420,6 +496,28 @@ nbgs_status nbgs_mlp_loss_grad(nbgs_mlp_t mlp, const float *feat, const float *t
  * *final_loss [host, may be NULL] = mean L over the last epoch. */
 nbgs_status nbgs_mlp_train(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n, int32_t epochs,
                            int32_t batch, float lr, uint64_t shuffle_seed, double *final_loss);
+
+/* Append the training pairs of the scene's last solved step (every contact's
+ * features at the step's start and its solved impulse in the contact frame
+ * scaled by 1/(ms vs), the network being trained on impulses the solver
+ * itself produced) to the network's store.  The step's nbgs_detect must have
+ * computed features (learned warm start or nbgs_set_feature_capture).
+ * *n_stored [host, may be NULL] = samples held afterwards.  Synchronises the
+ * scene's stream.  Errors: STATE (no features or no solve), CAPACITY (the
+ * store's max_samples would be exceeded; nothing appended). */
+nbgs_status nbgs_mlp_collect(nbgs_scene_t scene, nbgs_mlp_t mlp, int64_t *n_stored);
+
+/* nbgs_mlp_train on every collected pair.  STATE if none. */
+nbgs_status nbgs_mlp_train_collected(nbgs_mlp_t mlp, int32_t epochs, int32_t batch, float lr, uint64_t shuffle_seed,
+                                     double *final_loss);
+
+/* The collected store: *n [host] pairs, *feat [device n x 12], *target
+ * [device n x 3] (FP32, owned by the network, valid until the next collect or
+ * clear); each output NULL-able. */
+nbgs_status nbgs_mlp_collected(nbgs_mlp_t mlp, int64_t *n, const float **feat, const float **target);
+
+/* Empty the store. */
+nbgs_status nbgs_mlp_clear_collected(nbgs_mlp_t mlp);
 
 /* Use `mlp` (NULL detaches) for NBGS_WS_LEARNED; the scene borrows it. */
 nbgs_status nbgs_scene_attach_mlp(nbgs_scene_t scene, nbgs_mlp_t mlp);
@@ -506,14 +604,28 @@ typedef struct {
     const double *elem_radius; /* [device] E */
 } nbgs_composite_bodies;
 
+/* Bytes of device workspace of a composite scene of n_bodies bodies,
+ * n_elements elements and up to contact_capacity contacts (an upper bound:
+ * per element 352 B, per body 164 B, per contact 525 B, a cell table of 2^16
+ * cells, 16 MiB, ten per cent).  params may be NULL.  Errors: INVALID_ARG. */
+nbgs_status nbgs_composite_workspace_query(int64_t n_bodies, int64_t n_elements, int64_t contact_capacity,
+                                           const nbgs_params *params, size_t *bytes);
+
 /* Create a composite scene that borrows the arrays.  bodies, domain, params:
- * [host] structs.  Errors: INVALID_ARG (null pointer, n < 1, fewer elements
- * than bodies, elem_start not running from 0 to n_elements, bad parameters or
- * domain as for nbgs_scene_create), UNSUPPORTED (precision other than
- * NBGS_FP64, learned warm start), OUT_OF_MEMORY, DEVICE.  Release the handle
- * with nbgs_composite_destroy. */
+ * [host] structs.  workspace [device], workspace_bytes: as for
+ * nbgs_scene_create (nbgs_composite_workspace_query).  Errors: INVALID_ARG
+ * (null pointer or workspace, n < 1, fewer elements than bodies, elem_start
+ * not running from 0 to n_elements, bad parameters or domain as for
+ * nbgs_scene_create), UNSUPPORTED (precision other than NBGS_FP64, learned
+ * warm start), CAPACITY, OUT_OF_MEMORY (host), DEVICE.  Release the handle
+ * with nbgs_composite_destroy.  nbgs_composite_detect returns CAPACITY with
+ * the contact count in stats->n_contacts when the workspace holds fewer. */
 nbgs_status nbgs_composite_create(const nbgs_composite_bodies *bodies, const nbgs_domain *domain,
-                                  const nbgs_params *params, void *hip_stream, nbgs_composite_t *out);
+                                  const nbgs_params *params, void *workspace, size_t workspace_bytes,
+                                  void *hip_stream, nbgs_composite_t *out);
+
+/* Move the composite scene into another workspace, as nbgs_scene_set_workspace. */
+nbgs_status nbgs_composite_set_workspace(nbgs_composite_t scene, void *workspace, size_t bytes);
 nbgs_status nbgs_composite_destroy(nbgs_composite_t scene);
 
 /* Detection, colouring, initial impulses (see above).  stats [host, may be

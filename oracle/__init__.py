@@ -133,6 +133,8 @@ def lib():
         L.nbgs_ref_world_set_prev.argtypes = [C.c_void_p, C.c_int64, _u64p, _dp, _dp, _dp]
         L.nbgs_ref_world_set_subdomains.argtypes = [C.c_void_p, C.c_double]
         L.nbgs_ref_world_set_block_order.argtypes = [C.c_void_p, C.c_double]
+        L.nbgs_ref_world_set_block_grids.argtypes = [C.c_void_p, C.c_int32]
+        L.nbgs_ref_block_local_grids.restype = C.c_int32
         L.nbgs_ref_subdomains.restype = C.c_int32
         L.nbgs_ref_block_local.restype = C.c_int32
         L.nbgs_ref_comp_detect_brute.restype = C.c_int64
@@ -285,9 +287,10 @@ def subdomains(sc, j1: np.ndarray, edge: float):
     return out[:m].copy(), int(n)
 
 
-def block_local(sc, j1: np.ndarray, j2: np.ndarray, edge: float):
-    """Block-local id of every contact (the block of its dynamic bodies if they share one, else the number of
-    blocks); returns (id, number of ids = blocks + 1)."""
+def block_local(sc, j1: np.ndarray, j2: np.ndarray, edge: float, grids: int = 1):
+    """Block-local id of every contact (grids = 1: the block of its dynamic bodies if they share one, else the
+    number of blocks; grids > 1: g B + block for the first of the shifted grids g in which they share a block, else
+    grids B); returns (id, number of ids)."""
     held = _Held()
     b = make_bodies(sc, held)
     dom = make_domain(sc, held)
@@ -295,8 +298,8 @@ def block_local(sc, j1: np.ndarray, j2: np.ndarray, edge: float):
     out = np.zeros(max(m, 1), dtype=np.int32)
     j1c = np.ascontiguousarray(j1, dtype=np.int32)
     j2c = np.ascontiguousarray(j2, dtype=np.int32)
-    n = lib().nbgs_ref_block_local(C.byref(b), C.byref(dom), C.c_double(edge), C.c_int64(m), _ptr(j1c, _i32p),
-                                   _ptr(j2c, _i32p), _ptr(out, _i32p))
+    n = lib().nbgs_ref_block_local_grids(C.byref(b), C.byref(dom), C.c_double(edge), C.c_int32(grids), C.c_int64(m),
+                                         _ptr(j1c, _i32p), _ptr(j2c, _i32p), _ptr(out, _i32p))
     return out[:m].copy(), int(n)
 
 
@@ -451,10 +454,11 @@ class World:
         lib().nbgs_ref_world_set_subdomains(self._w, C.c_double(edge))
         return self
 
-    def set_block_order(self, edge: float):
-        """edge > 0: the plain NBGS swept in the block-local order (blocks of about this edge) from the next
-        detection on; 0: (colour, key) order."""
+    def set_block_order(self, edge: float, grids: int = 1):
+        """edge > 0: the plain NBGS swept in the block-local order (blocks of about this edge, over `grids` block
+        grids shifted by 1/grids of an edge) from the next detection on; 0: (colour, key) order."""
         lib().nbgs_ref_world_set_block_order(self._w, C.c_double(edge))
+        lib().nbgs_ref_world_set_block_grids(self._w, C.c_int32(grids))
         return self
 
 

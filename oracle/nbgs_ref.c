@@ -564,6 +564,71 @@ int32_t nbgs_ref_block_local(const ref_bodies *b, const ref_domain *dom, double 
     return nblocks + 1;
 }
 
+/* Block of body i in grid g of `grids` grids shifted by g/grids of a block
+ * edge along every axis: c_a = floor((x_a - lo_a) / e_a + g / grids), taken
+ * modulo nb_a along a periodic axis (the block across the boundary is one
+ * block) and clamped along another one, to [0, nb_a - 1] in grid 0 (as
+ * block_of) and to [0, nb_a] in a shifted grid (whose last block reaches past
+ * the box).  Block id (c_z M_y + c_y) M_x + c_x with M_a = nb_a, plus one
+ * along a non-periodic axis when there are several grids. */
+static int64_t block_in_grid(const ref_bodies *b, const ref_domain *dom, const int64_t nb[3], const double e[3],
+                             const int64_t M[3], int g, int grids, int64_t i)
+{
+    double x[3] = {b->x[i], b->y[i], b->z[i]};
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) {
+        double f = floor((x[a] - dom->lo[a]) / e[a] + (double)g / (double)grids);
+        if (dom->periodic[a]) {
+            int64_t q = (int64_t)f % nb[a];
+            c[a] = q < 0 ? q + nb[a] : q;
+        } else {
+            double top = g == 0 ? (double)(nb[a] - 1) : (double)nb[a];
+            c[a] = (int64_t)fmax(0.0, fmin(f, top));
+        }
+    }
+    return (c[2] * M[1] + c[1]) * M[0] + c[0];
+}
+
+/* Block-local order over several shifted block grids (the same plain NBGS,
+ * visited in another order).  Grid g (g = 0 .. grids - 1) cuts the box as
+ * nbgs_ref_block_local does, shifted by g/grids of a block edge along every
+ * axis.  A contact is local to grid g if all its dynamic bodies lie in one
+ * block of that grid; it takes the id g B + block for the first such grid
+ * (B blocks per grid), or the id grids B if it is local to none.  Sorted by
+ * (id, colour, key) with the colouring restricted to equal ids, a sweep takes
+ * grid 0's blocks, then grid 1's, ..., then the remaining contacts; the local
+ * contacts of two blocks of one grid share no dynamic body.  A contact whose
+ * centres differ by less than a quarter of the block edge along every axis is
+ * local to one of four grids (along each axis the faces of the four grids are a
+ * quarter edge apart, so at most one grid has a face between the centres).
+ * grids = 1 is nbgs_ref_block_local.  Returns grids B + 1, the number of ids. */
+int32_t nbgs_ref_block_local_grids(const ref_bodies *b, const ref_domain *dom, double edge, int32_t grids,
+                                   int64_t nc, const int32_t *j1, const int32_t *j2, int32_t *id)
+{
+    if (grids <= 1) return nbgs_ref_block_local(b, dom, edge, nc, j1, j2, id);
+    int64_t nb[3], M[3];
+    double e[3];
+    block_grid(dom, edge, nb, e);
+    for (int a = 0; a < 3; ++a) M[a] = nb[a] + (dom->periodic[a] ? 0 : 1);
+    int64_t B = M[0] * M[1] * M[2];
+    int64_t N = b->n;
+    for (int64_t j = 0; j < nc; ++j) {
+        int d1 = b->inv_mass[j1[j]] > 0.0;
+        int d2 = j2[j] < N && b->inv_mass[j2[j]] > 0.0;
+        int64_t out = (int64_t)grids * B;
+        for (int g = 0; g < grids; ++g) {
+            int64_t k1 = block_in_grid(b, dom, nb, e, M, g, grids, d1 ? j1[j] : j2[j]);
+            int64_t k2 = d1 && d2 ? block_in_grid(b, dom, nb, e, M, g, grids, j2[j]) : k1;
+            if (k1 == k2) {
+                out = (int64_t)g * B + k1;
+                break;
+            }
+        }
+        id[j] = (int32_t)out;
+    }
+    return (int32_t)((int64_t)grids * B + 1);
+}
+
 /* Sweep order of the subdomain solver: contacts sorted by (subdomain, colour,
  * key); the list is in key order, so a stable grouping suffices. */
 void nbgs_ref_sweep_order_sub(int64_t nc, const int32_t *sdom, int32_t n_sub, const int32_t *colour, int32_t n_colours,
@@ -1222,6 +1287,7 @@ typedef struct {
     int32_t hist_cap;
     double sub_edge; /* > 0: subdomain NBGS with blocks of about this edge */
     double blk_edge; /* > 0: plain NBGS in the block-local order with blocks of about this edge */
+    int32_t blk_grids; /* shifted block grids of that order (1: one grid) */
     int32_t *sdom;
     int32_t n_sub;
 } ref_world;
@@ -1334,7 +1400,8 @@ void nbgs_ref_world_detect(ref_world *W, int32_t use_grid, int32_t warm)
         nbgs_ref_sweep_order_sub(m, W->sdom, W->n_sub, W->colour, W->n_colours, W->order);
     } else if (W->blk_edge > 0.0) {
         W->sdom = (int32_t *)realloc(W->sdom, n * sizeof(int32_t));
-        W->n_sub = nbgs_ref_block_local(&W->b, &W->dom, W->blk_edge, m, W->c.j1, W->c.j2, W->sdom);
+        W->n_sub = nbgs_ref_block_local_grids(&W->b, &W->dom, W->blk_edge, W->blk_grids > 1 ? W->blk_grids : 1, m,
+                                              W->c.j1, W->c.j2, W->sdom);
         W->n_colours =
             nbgs_ref_colour(W->b.n, W->b.inv_mass, m, W->c.j1, W->c.j2, W->c.key, W->p.colour_seed, W->sdom, W->colour);
         nbgs_ref_sweep_order_sub(m, W->sdom, W->n_sub, W->colour, W->n_colours, W->order);
@@ -1437,6 +1504,9 @@ void nbgs_ref_world_set_subdomains(ref_world *W, double edge) { W->sub_edge = ed
 /* edge > 0: later detections sweep in the block-local order (plain NBGS);
  * edge = 0: (colour, key) order. */
 void nbgs_ref_world_set_block_order(ref_world *W, double edge) { W->blk_edge = edge > 0.0 ? edge : 0.0; }
+
+/* Shifted block grids of the block-local order (nbgs_ref_block_local_grids); 1 by default. */
+void nbgs_ref_world_set_block_grids(ref_world *W, int32_t grids) { W->blk_grids = grids > 1 ? grids : 1; }
 
 /* Replace the previous-step impulse table (key-sorted) used by the warm start. */
 void nbgs_ref_world_set_prev(ref_world *W, int64_t n, const uint64_t *key, const double *px, const double *py,

@@ -86,8 +86,12 @@ class NbgsError(RuntimeError):
 _SIGNATURES = [
     ("nbgs_abi_version", C.c_int32, []),
     ("nbgs_last_error", C.c_char_p, []),
+    ("nbgs_workspace_query", C.c_int, [C.c_int64, C.c_int64, C.POINTER(nbgs_params), C.POINTER(C.c_size_t)]),
     ("nbgs_scene_create", C.c_int, [C.POINTER(nbgs_bodies), C.POINTER(nbgs_domain), C.POINTER(nbgs_params), _vp,
-                                    C.POINTER(_vp)]),
+                                    C.c_size_t, _vp, C.POINTER(_vp)]),
+    ("nbgs_scene_set_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
+    ("nbgs_scene_workspace_usage", C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                             C.POINTER(C.c_size_t)]),
     ("nbgs_scene_destroy", C.c_int, [_vp]),
     ("nbgs_scene_set_params", C.c_int, [_vp, C.POINTER(nbgs_params)]),
     ("nbgs_detect", C.c_int, [_vp, C.POINTER(nbgs_stats)]),
@@ -101,9 +105,15 @@ _SIGNATURES = [
     ("nbgs_set_residual_history", C.c_int, [_vp, C.c_int32]),
     ("nbgs_set_subdomains", C.c_int, [_vp, C.c_double]),
     ("nbgs_set_block_order", C.c_int, [_vp, C.c_double]),
+    ("nbgs_set_block_grids", C.c_int, [_vp, C.c_int32]),
     ("nbgs_get_phase_times", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     ("nbgs_mlp_param_count", C.c_int32, []),
-    ("nbgs_mlp_create", C.c_int, [C.c_uint64, _vp, C.POINTER(_vp)]),
+    ("nbgs_mlp_workspace_query", C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),
+    ("nbgs_mlp_create", C.c_int, [C.c_uint64, C.c_int64, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    ("nbgs_mlp_collect", C.c_int, [_vp, _vp, C.POINTER(C.c_int64)]),
+    ("nbgs_mlp_train_collected", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, C.POINTER(C.c_double)]),
+    ("nbgs_mlp_collected", C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(_vp), C.POINTER(_vp)]),
+    ("nbgs_mlp_clear_collected", C.c_int, [_vp]),
     ("nbgs_mlp_destroy", C.c_int, [_vp]),
     ("nbgs_mlp_set_weights", C.c_int, [_vp, C.POINTER(C.c_float)]),
     ("nbgs_mlp_get_weights", C.c_int, [_vp, C.POINTER(C.c_float)]),
@@ -122,14 +132,20 @@ _SIGNATURES = [
     ("nbgs_set_profiling", C.c_int, [_vp, C.c_int32]),
     ("nbgs_get_profile", C.c_int, [_vp, C.POINTER(nbgs_profile)]),
     ("nbgs_autotune", C.c_int, [_vp, C.c_int32, C.c_char_p, C.POINTER(nbgs_tuning), C.POINTER(C.c_double)]),
+    ("nbgs_batch_workspace_query", C.c_int, [C.c_int32, C.c_int64, C.c_int64, C.POINTER(nbgs_params),
+                                             C.POINTER(C.c_size_t)]),
     ("nbgs_batch_create", C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(nbgs_bodies), C.POINTER(nbgs_domain),
-                                    C.POINTER(nbgs_params), C.c_char_p, _vp, C.POINTER(_vp)]),
+                                    C.POINTER(nbgs_params), C.c_char_p, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     ("nbgs_batch_destroy", C.c_int, [_vp]),
     ("nbgs_batch_scene", C.c_int, [_vp, C.POINTER(_vp)]),
-    ("nbgs_batch_step", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_double, C.POINTER(nbgs_stats)]),
+    ("nbgs_batch_step", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_double, C.POINTER(nbgs_stats),
+                                  C.POINTER(C.c_int32)]),
     ("nbgs_batch_scene_stats", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    ("nbgs_composite_workspace_query", C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.POINTER(nbgs_params),
+                                                 C.POINTER(C.c_size_t)]),
     ("nbgs_composite_create", C.c_int, [C.POINTER(nbgs_composite_bodies), C.POINTER(nbgs_domain),
-                                        C.POINTER(nbgs_params), _vp, C.POINTER(_vp)]),
+                                        C.POINTER(nbgs_params), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    ("nbgs_composite_set_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
     ("nbgs_composite_destroy", C.c_int, [_vp]),
     ("nbgs_composite_detect", C.c_int, [_vp, C.POINTER(nbgs_stats)]),
     ("nbgs_composite_solve", C.c_int, [_vp, C.c_int32, C.c_double, C.POINTER(nbgs_stats)]),
@@ -180,10 +196,58 @@ def nbgs_last_error() -> str:
     return lib().nbgs_last_error().decode()
 
 
-def nbgs_scene_create(bodies: nbgs_bodies, domain: nbgs_domain, params: nbgs_params, stream: int = 0) -> int:
+class Workspace:
+    """A device region handed to a library handle: a torch uint8 tensor (PyTorch is the only allocator)."""
+
+    def __init__(self, nbytes: int, device):
+        import torch
+
+        self.nbytes = int(nbytes)
+        self.tensor = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self) -> int:
+        return self.tensor.data_ptr()
+
+
+# handle -> callable(contacts needed) that gives the handle a larger workspace (the CAPACITY round trip)
+_GROWERS: Dict[int, object] = {}
+_MAX_CONTACTS = 0x7FFFFF00
+
+
+def nbgs_workspace_query(n_bodies: int, contact_capacity: int, params: Optional[nbgs_params] = None) -> int:
+    b = C.c_size_t()
+    _check(lib().nbgs_workspace_query(int(n_bodies), int(contact_capacity),
+                                      C.byref(params) if params is not None else None, C.byref(b)))
+    return int(b.value)
+
+
+def nbgs_scene_create(bodies: nbgs_bodies, domain: nbgs_domain, params: nbgs_params, workspace: int,
+                      workspace_bytes: int, stream: int = 0) -> int:
     h = _vp()
-    _check(lib().nbgs_scene_create(C.byref(bodies), C.byref(domain), C.byref(params), _vp(stream), C.byref(h)))
+    _check(lib().nbgs_scene_create(C.byref(bodies), C.byref(domain), C.byref(params), _vp(workspace),
+                                   C.c_size_t(workspace_bytes), _vp(stream), C.byref(h)))
     return h.value
+
+
+def nbgs_scene_set_workspace(h: int, workspace: int, nbytes: int) -> None:
+    _check(lib().nbgs_scene_set_workspace(_vp(h), _vp(workspace), C.c_size_t(nbytes)))
+
+
+def nbgs_scene_workspace_usage(h: int):
+    a, b, c = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    _check(lib().nbgs_scene_workspace_usage(_vp(h), C.byref(a), C.byref(b), C.byref(c)))
+    return int(a.value), int(b.value), int(c.value)
+
+
+def _capacity_retry(h: int, call):
+    """Run call() -> (status, stats); on CAPACITY with a contact count the handle's workspace can be grown for,
+    grow it (query, allocate, set_workspace) and run it once more."""
+    code, st = call()
+    if code == NBGS_ERR_CAPACITY and h in _GROWERS and 0 <= int(st.n_contacts) <= _MAX_CONTACTS:
+        if _GROWERS[h](int(st.n_contacts)):
+            code, st = call()
+    return code, st
 
 
 def nbgs_scene_destroy(h: int) -> None:
@@ -195,8 +259,12 @@ def nbgs_scene_set_params(h: int, params: nbgs_params) -> None:
 
 
 def nbgs_detect(h: int) -> nbgs_stats:
-    st = nbgs_stats()
-    _check(lib().nbgs_detect(_vp(h), C.byref(st)))
+    def call():
+        st = nbgs_stats()
+        return lib().nbgs_detect(_vp(h), C.byref(st)), st
+
+    code, st = _capacity_retry(h, call)
+    _check(code)
     return st
 
 
@@ -212,9 +280,12 @@ def nbgs_integrate(h: int) -> None:
 
 
 def nbgs_step(h: int, max_sweeps: int, residual_target: float = 0.0, allow_not_converged: bool = True):
-    st = nbgs_stats()
-    code = _check(lib().nbgs_step(_vp(h), int(max_sweeps), float(residual_target), C.byref(st)),
-                  allow=(NBGS_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    def call():
+        st = nbgs_stats()
+        return lib().nbgs_step(_vp(h), int(max_sweeps), float(residual_target), C.byref(st)), st
+
+    code, st = _capacity_retry(h, call)
+    _check(code, allow=(NBGS_ERR_NOT_CONVERGED,) if allow_not_converged else ())
     return st, code
 
 
@@ -246,6 +317,10 @@ def nbgs_set_subdomains(h: int, edge: float) -> None:
 
 def nbgs_set_block_order(h: int, edge: float) -> None:
     _check(lib().nbgs_set_block_order(_vp(h), float(edge)))
+
+
+def nbgs_set_block_grids(h: int, grids: int) -> None:
+    _check(lib().nbgs_set_block_grids(_vp(h), int(grids)))
 
 
 def nbgs_set_residual_history(h: int, enable: bool) -> None:
@@ -288,10 +363,36 @@ def nbgs_mlp_param_count() -> int:
     return int(lib().nbgs_mlp_param_count())
 
 
-def nbgs_mlp_create(seed: int = 0, stream: int = 0) -> int:
+def nbgs_mlp_workspace_query(max_samples: int) -> int:
+    b = C.c_size_t()
+    _check(lib().nbgs_mlp_workspace_query(int(max_samples), C.byref(b)))
+    return int(b.value)
+
+
+def nbgs_mlp_create(seed: int, max_samples: int, workspace: int, workspace_bytes: int, stream: int = 0) -> int:
     h = _vp()
-    _check(lib().nbgs_mlp_create(C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _vp(stream), C.byref(h)))
+    _check(lib().nbgs_mlp_create(C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), int(max_samples), _vp(workspace),
+                                 C.c_size_t(workspace_bytes), _vp(stream), C.byref(h)))
     return h.value
+
+
+def nbgs_mlp_collect(scene: int, mlp: int) -> int:
+    n = C.c_int64()
+    _check(lib().nbgs_mlp_collect(_vp(scene), _vp(mlp), C.byref(n)))
+    return int(n.value)
+
+
+def nbgs_mlp_train_collected(h: int, epochs: int, batch: int, lr: float, seed: int = 0) -> float:
+    loss = C.c_double()
+    _check(lib().nbgs_mlp_train_collected(_vp(h), int(epochs), int(batch), C.c_float(lr),
+                                          C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), C.byref(loss)))
+    return float(loss.value)
+
+
+def nbgs_mlp_collected(h: int):
+    n, f, t = C.c_int64(), _vp(), _vp()
+    _check(lib().nbgs_mlp_collected(_vp(h), C.byref(n), C.byref(f), C.byref(t)))
+    return int(n.value), f.value or 0, t.value or 0
 
 
 def nbgs_mlp_destroy(h: int) -> None:
@@ -371,12 +472,20 @@ def nbgs_autotune(h: int, sweeps: int, cache_path: Optional[str] = None):
     return _tuning_dict(t), float(ms.value)
 
 
+def nbgs_batch_workspace_query(n_scenes: int, n_bodies: int, contact_capacity: int, params=None) -> int:
+    b = C.c_size_t()
+    _check(lib().nbgs_batch_workspace_query(int(n_scenes), int(n_bodies), int(contact_capacity), params,
+                                            C.byref(b)))
+    return int(b.value)
+
+
 def nbgs_batch_create(n_scenes: int, body_offsets, bodies: nbgs_bodies, domains, params, cache_path=None,
-                      stream: int = 0) -> int:
+                      workspace: int = 0, workspace_bytes: int = 0, stream: int = 0) -> int:
     off = (C.c_int64 * (n_scenes + 1))(*[int(v) for v in body_offsets])
     h = _vp()
     _check(lib().nbgs_batch_create(n_scenes, off, C.byref(bodies), domains, params,
-                                   cache_path.encode() if cache_path else None, _vp(stream), C.byref(h)))
+                                   cache_path.encode() if cache_path else None, _vp(workspace),
+                                   C.c_size_t(workspace_bytes), _vp(stream), C.byref(h)))
     return h.value
 
 
@@ -390,9 +499,20 @@ def nbgs_batch_scene(h: int) -> int:
     return out.value
 
 
-def nbgs_batch_step(h: int, n_steps: int, max_sweeps: int, residual_target: float = 0.0):
-    st = nbgs_stats()
-    code = lib().nbgs_batch_step(_vp(h), n_steps, max_sweeps, residual_target, C.byref(st))
+def nbgs_batch_step(h: int, n_steps: int, max_sweeps: int, residual_target: float = 0.0, scene: int = 0):
+    """n_steps steps of the batch; on CAPACITY the batch's workspace (grown through its scene handle) is enlarged
+    and the remaining steps run."""
+    done = 0
+    while True:
+        st = nbgs_stats()
+        k = C.c_int32()
+        code = lib().nbgs_batch_step(_vp(h), n_steps - done, max_sweeps, residual_target, C.byref(st), C.byref(k))
+        done += int(k.value)
+        if code != NBGS_ERR_CAPACITY or not scene or scene not in _GROWERS:
+            break
+        # the steps before the failing one have run; the failing detection left the scenes as they were
+        if not (0 <= int(st.n_contacts) <= _MAX_CONTACTS) or not _GROWERS[scene](int(st.n_contacts)):
+            break
     _check(code, allow=(NBGS_ERR_NOT_CONVERGED,))
     return st, code
 
@@ -407,17 +527,35 @@ def nbgs_batch_scene_stats(h: int, n: int):
 class GpuMlp:
     """Owner of an nbgs_mlp_t; tensors in and out are torch CUDA float32."""
 
-    def __init__(self, seed: int = 0, stream=None):
+    def __init__(self, seed: int = 0, stream=None, max_samples: int = 1 << 20, device="cuda"):
         import torch
 
         self.torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.handle = nbgs_mlp_create(seed, self.stream.cuda_stream)
+        self.max_samples = int(max_samples)
+        self.workspace = Workspace(nbgs_mlp_workspace_query(self.max_samples), torch.device(device))
+        self.handle = nbgs_mlp_create(seed, self.max_samples, self.workspace.ptr, self.workspace.nbytes,
+                                      self.stream.cuda_stream)
 
     def close(self):
         if getattr(self, "handle", None):
             nbgs_mlp_destroy(self.handle)
             self.handle = None
+        self.workspace = None
+
+    def collect(self, scene) -> int:
+        """Append the training pairs of the scene's last solved step to the network's store; samples held."""
+        return nbgs_mlp_collect(scene.handle, self.handle)
+
+    def train_collected(self, epochs=20, batch=4096, lr=1e-3, seed=0) -> float:
+        return nbgs_mlp_train_collected(self.handle, epochs, batch, lr, seed)
+
+    def collected_count(self) -> int:
+        """Training pairs held by the network's store."""
+        return nbgs_mlp_collected(self.handle)[0]
+
+    def clear_collected(self):
+        _check(lib().nbgs_mlp_clear_collected(_vp(self.handle)))
 
     def __del__(self):
         try:
@@ -473,7 +611,8 @@ class GpuScene:
     the device once.  ``state()`` copies the current body state back.
     """
 
-    def __init__(self, sc, device="cuda", precision="fp64", warm_start="previous", stream=None):
+    def __init__(self, sc, device="cuda", precision="fp64", warm_start="previous", stream=None,
+                 contact_capacity=None):
         import torch
 
         self.torch = torch
@@ -498,12 +637,37 @@ class GpuScene:
         self.warm_start = warm_start
         self._params = make_params(sc, precision, warm_start)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.handle = nbgs_scene_create(self._bodies, self._domain, self._params, self.stream.cuda_stream)
+        # the device workspace: sized for a first guess of the contact count, grown on CAPACITY
+        self.contact_capacity = int(contact_capacity if contact_capacity is not None else self.n // 4 + 4096)
+        self.workspace = Workspace(self._query(self.contact_capacity), self.device)
+        self.handle = nbgs_scene_create(self._bodies, self._domain, self._params, self.workspace.ptr,
+                                        self.workspace.nbytes, self.stream.cuda_stream)
+        _GROWERS[self.handle] = self._grow
+
+    def _query(self, capacity: int) -> int:
+        return nbgs_workspace_query(self.n, capacity, self._params)
+
+    def _grow(self, needed: int) -> bool:
+        """A larger workspace for `needed` contacts (or twice the capacity when something else ran short); the
+        scene moves into it (nbgs_scene_set_workspace) and the old one is released."""
+        cap = int(needed * 1.25) + 1024
+        if cap <= self.contact_capacity:
+            cap = 2 * self.contact_capacity
+        ws = Workspace(self._query(cap), self.device)
+        nbgs_scene_set_workspace(self.handle, ws.ptr, ws.nbytes)
+        self.workspace, self.contact_capacity = ws, cap
+        return True
+
+    def workspace_usage(self) -> Dict:
+        size, used, peak = nbgs_scene_workspace_usage(self.handle)
+        return dict(size=size, used=used, peak=peak, contact_capacity=self.contact_capacity)
 
     def close(self):
         if getattr(self, "handle", None):
+            _GROWERS.pop(self.handle, None)
             nbgs_scene_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -512,14 +676,20 @@ class GpuScene:
             pass
 
     def set_params(self, precision=None, warm_start=None, **overrides):
-        if precision is not None:
-            self.precision = precision
-        if warm_start is not None:
-            self.warm_start = warm_start
+        """New parameters for later steps; nothing changes when the library refuses them."""
+        prec = self.precision if precision is None else precision
+        ws = self.warm_start if warm_start is None else warm_start
+        old = {k: getattr(self.sc, k) for k in overrides}
         for k, v in overrides.items():
             setattr(self.sc, k, v)
-        self._params = make_params(self.sc, self.precision, self.warm_start)
-        nbgs_scene_set_params(self.handle, self._params)
+        params = make_params(self.sc, prec, ws)
+        try:
+            nbgs_scene_set_params(self.handle, params)
+        except NbgsError:
+            for k, v in old.items():
+                setattr(self.sc, k, v)
+            raise
+        self.precision, self.warm_start, self._params = prec, ws, params
 
     @staticmethod
     def _stats(st: nbgs_stats) -> Dict:
@@ -585,10 +755,13 @@ class GpuScene:
         nbgs_set_subdomains(self.handle, edge)
         return self
 
-    def set_block_order(self, edge: float):
-        """edge > 0: the plain NBGS swept in the block-local order (blocks of about this edge) from the next step
-        on; 0: (colour, key) order."""
+    def set_block_order(self, edge: float, grids: int = None):
+        """edge > 0: the plain NBGS swept in the block-local order (blocks of about this edge, over `grids` block
+        grids shifted by 1/grids of an edge; None keeps the current count) from the next step on; 0: (colour, key)
+        order."""
         nbgs_set_block_order(self.handle, edge)
+        if grids is not None:
+            nbgs_set_block_grids(self.handle, grids)
         return self
 
     def set_warm_start(self, keys: np.ndarray, P: np.ndarray):
@@ -685,7 +858,7 @@ class GpuBatch(GpuScene):
     """
 
     def __init__(self, scenes, device="cuda", precision="fp32", warm_start="previous", stream=None,
-                 cache_path=None):
+                 cache_path=None, contact_capacity=None):
         import torch
 
         self.torch = torch
@@ -723,22 +896,30 @@ class GpuBatch(GpuScene):
         self.warm_start = warm_start
         self._params = self._params_arr[0]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.contact_capacity = int(contact_capacity if contact_capacity is not None else self.n // 4 + 4096)
+        self.workspace = Workspace(self._query(self.contact_capacity), self.device)
         self.batch = nbgs_batch_create(ns, self.offsets, self._bodies, self._domains, self._params_arr, cache_path,
-                                       self.stream.cuda_stream)
+                                       self.workspace.ptr, self.workspace.nbytes, self.stream.cuda_stream)
         self.handle = nbgs_batch_scene(self.batch)
+        _GROWERS[self.handle] = self._grow
         self.walls = np.concatenate([[0], np.cumsum([len(s.planes) for s in scenes])]).astype(np.int64)
+
+    def _query(self, capacity: int) -> int:
+        return nbgs_batch_workspace_query(len(self.scenes), self.n, capacity, self._params_arr)
 
     def close(self):
         if getattr(self, "batch", None):
+            _GROWERS.pop(self.handle, None)
             nbgs_batch_destroy(self.batch)
             self.batch = None
             self.handle = None
+        self.workspace = None
 
     def set_params(self, precision=None, warm_start=None, **overrides):
         raise NotImplementedError("batched scenes keep the parameters they were created with")
 
     def step_batch(self, n_steps: int, max_sweeps: int, target: float = 0.0) -> Dict:
-        st, code = nbgs_batch_step(self.batch, n_steps, max_sweeps, target)
+        st, code = nbgs_batch_step(self.batch, n_steps, max_sweeps, target, scene=self.handle)
         d = self._stats(st)
         d["converged"] = code == NBGS_OK
         return d
@@ -776,7 +957,7 @@ class GpuComposite:
     ``cs`` is a :class:`scenegen.CompositeScene`; its arrays are copied to the device once and ``state()`` copies
     the body state back.  Every step runs in the HIP library (FP64)."""
 
-    def __init__(self, cs, device="cuda", warm_start="previous", stream=None):
+    def __init__(self, cs, device="cuda", warm_start="previous", stream=None, contact_capacity=None):
         import torch
 
         self.torch = torch
@@ -806,15 +987,37 @@ class GpuComposite:
                                    n_planes=len(cs.planes), planes=C.cast(self._planes, C.POINTER(nbgs_plane)))
         self._params = make_params(cs, "fp64", warm_start)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.contact_capacity = int(contact_capacity if contact_capacity is not None
+                                    else self.n_elements // 4 + 4096)
+        self.workspace = Workspace(self._query(self.contact_capacity), self.device)
         h = _vp()
         _check(lib().nbgs_composite_create(C.byref(self._bodies), C.byref(self._domain), C.byref(self._params),
+                                           _vp(self.workspace.ptr), C.c_size_t(self.workspace.nbytes),
                                            _vp(self.stream.cuda_stream), C.byref(h)))
         self.handle = h
+        _GROWERS[h.value] = self._grow
+
+    def _query(self, capacity: int) -> int:
+        b = C.c_size_t()
+        _check(lib().nbgs_composite_workspace_query(int(self.n), int(self.n_elements), int(capacity), None,
+                                                    C.byref(b)))
+        return int(b.value)
+
+    def _grow(self, needed: int) -> bool:
+        cap = int(needed * 1.25) + 1024
+        if cap <= self.contact_capacity:
+            cap = 2 * self.contact_capacity
+        ws = Workspace(self._query(cap), self.device)
+        _check(lib().nbgs_composite_set_workspace(self.handle, _vp(ws.ptr), C.c_size_t(ws.nbytes)))
+        self.workspace, self.contact_capacity = ws, cap
+        return True
 
     def close(self):
         if getattr(self, "handle", None):
+            _GROWERS.pop(self.handle.value, None)
             lib().nbgs_composite_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -828,8 +1031,12 @@ class GpuComposite:
                     residual=float(st.residual), converged=code == NBGS_OK)
 
     def detect(self) -> Dict:
-        st = nbgs_stats()
-        code = _check(lib().nbgs_composite_detect(self.handle, C.byref(st)))
+        def call():
+            st = nbgs_stats()
+            return lib().nbgs_composite_detect(self.handle, C.byref(st)), st
+
+        code, st = _capacity_retry(self.handle.value, call)
+        _check(code)
         return self._stats(st, code)
 
     def solve(self, max_sweeps: int, target: float = 0.0) -> Dict:
@@ -842,10 +1049,12 @@ class GpuComposite:
         _check(lib().nbgs_composite_integrate(self.handle))
 
     def step(self, max_sweeps: int, target: float = 0.0, stats: bool = True) -> Dict:
-        st = nbgs_stats()
-        code = _check(lib().nbgs_composite_step(self.handle, int(max_sweeps), float(target),
-                                                C.byref(st) if stats else None),
-                      allow=(NBGS_ERR_NOT_CONVERGED,))
+        def call():
+            st = nbgs_stats()
+            return lib().nbgs_composite_step(self.handle, int(max_sweeps), float(target), C.byref(st)), st
+
+        code, st = _capacity_retry(self.handle.value, call)
+        _check(code, allow=(NBGS_ERR_NOT_CONVERGED,))
         return self._stats(st, code)
 
     def contacts(self) -> Dict[str, np.ndarray]:

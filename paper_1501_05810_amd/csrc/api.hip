@@ -29,6 +29,133 @@ void set_error(const char *fmt, ...) {
 
 namespace nbgs {
 
+// ------------------------------------------------------------------ arena
+
+void Arena::reset(void *base, size_t bytes) {
+    free_.clear();
+    live_.clear();
+    moved_.clear();
+    used_ = peak_ = 0;
+    base_ = nullptr;
+    size_ = 0;
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+    const uintptr_t a = (b + kAlign - 1) & ~(uintptr_t)(kAlign - 1);
+    if (!base || bytes < (a - b) + kAlign) return;
+    base_ = reinterpret_cast<char *>(a);
+    size_ = (bytes - (a - b)) & ~(size_t)(kAlign - 1);
+    free_[0] = size_;
+}
+
+void *Arena::alloc(size_t bytes, ArenaBuf *owner) {
+    if (!base_) return nullptr;
+    const size_t len = (bytes + kAlign - 1) & ~(size_t)(kAlign - 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < len) continue;
+        const size_t off = it->first, rest = it->second - len;
+        free_.erase(it);
+        if (rest) free_[off + len] = rest;
+        live_[off] = {len, owner};
+        used_ += len;
+        peak_ = std::max(peak_, used_);
+        return base_ + off;
+    }
+    return nullptr;
+}
+
+void Arena::release(void *p) {
+    if (!p || !base_) return;
+    const size_t off = (size_t)(static_cast<char *>(p) - base_);
+    auto it = live_.find(off);
+    if (it == live_.end()) return;
+    size_t start = off, len = it->second.first;
+    used_ -= len;
+    live_.erase(it);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + len) {  // join the free run after it
+        len += nx->second;
+        nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {  // and the one before it
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == start) {
+            start = pv->first;
+            len += pv->second;
+            free_.erase(pv);
+        }
+    }
+    free_[start] = len;
+}
+
+nbgs_status Arena::move_to(void *base, size_t bytes, hipStream_t s) {
+    Arena fresh;
+    fresh.reset(base, bytes);
+    if (!fresh.bound()) {
+        set_error("the new workspace is NULL or smaller than %zu bytes", (size_t)kAlign);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (base_ && fresh.base_ < base_ + size_ && fresh.base_ + fresh.size_ > base_) {
+        set_error("the new workspace overlaps the current one");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    size_t need = 0;
+    for (const auto &kv : live_) need += kv.second.first;
+    if (need > fresh.size_) {
+        set_error("the new workspace (%zu bytes) cannot hold the %zu bytes in use", fresh.size_, need);
+        return NBGS_ERR_CAPACITY;
+    }
+    std::vector<std::array<uintptr_t, 3>> moved;
+    std::map<size_t, std::pair<size_t, ArenaBuf *>> live;
+    size_t off = 0;
+    for (const auto &kv : live_) {
+        const size_t len = kv.second.first;
+        char *src = base_ + kv.first, *dst = fresh.base_ + off;
+        NBGS_HIP(hipMemcpyAsync(dst, src, len, hipMemcpyDeviceToDevice, s));
+        moved.push_back({reinterpret_cast<uintptr_t>(src), reinterpret_cast<uintptr_t>(src) + len,
+                         reinterpret_cast<uintptr_t>(dst)});
+        live[off] = kv.second;
+        off += len;
+    }
+    NBGS_HIP(hipStreamSynchronize(s));
+    for (const auto &kv : live) kv.second.second->arena_moved(fresh.base_ + kv.first);
+    base_ = fresh.base_;
+    size_ = fresh.size_;
+    live_ = std::move(live);
+    free_.clear();
+    if (off < size_) free_[off] = size_ - off;
+    used_ = off;
+    peak_ = std::max(peak_, used_);
+    moved_ = std::move(moved);
+    g_alloc_generation.fetch_add(1, std::memory_order_relaxed);
+    return NBGS_OK;
+}
+
+const void *Arena::relocate(const void *old) const {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(old);
+    for (const auto &m : moved_)
+        if (a >= m[0] && a < m[1]) return reinterpret_cast<const void *>(m[2] + (a - m[0]));
+    return old;
+}
+
+// Upper bound of a sphere scene's device memory (nbgs_workspace_query): every
+// buffer at its largest size for n bodies in `scenes` scenes and c contacts,
+// with the growth slack of the buffers that grow, in every sweep order,
+// precision and warm start.  Per body 613 B (detection 148 B, accumulator
+// records of both precisions 96 B, block and subdomain tables of blocks
+// holding eight bodies or more on average 165 B, cells of 16 B at most eight
+// per body 160 B, and the rest); per contact 1000 B (two contact tables 192 B, sweep
+// records of both precisions 168 B, colouring 36 B, learned start 156 B,
+// subdomain ends, slots and corrections 208 B, partial sums and tuning copies
+// 40 B, times 1.25); per scene its cell table of at least 2^16 cells and its
+// tables; a fixed 16 MiB (residual history of 131,072 sweeps, colour-start
+// tables of 4,096 blocks, sort scratch); ten per cent for the alignment of
+// every buffer and for runs left between freed buffers.
+size_t scene_workspace_bytes(int64_t n, int64_t c, int64_t scenes) {
+    const double per_body = 613.0, per_contact = 1000.0, per_scene = 65536.0 * 16.0 * 1.25 + 4096.0;
+    const double fixed = 16.0 * 1024.0 * 1024.0;
+    const double b = 1.1 * (per_body * (double)n + per_contact * (double)c + per_scene * (double)scenes + fixed);
+    return (size_t)b;
+}
+
 nbgs_status check_params(const nbgs_params *p) {
     if (!p) {
         set_error("params is NULL");
@@ -308,22 +435,19 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
                               sc->radix_hist.p, sc->scan_tmp.p, sc->scan_tmp.cap, &alt, s));
     const uint32_t *skeys = alt ? sc->keys2.p : sc->keys.p;
     const uint32_t *sids = alt ? sc->ids2.p : sc->ids.p;
-    if ((size_t)sc->grid.ncells > sc->cell_stamp.cap) {
-        NBGS_TRY(sc->cell_start.reserve(sc->grid.ncells));
-        NBGS_TRY(sc->cell_end.reserve(sc->grid.ncells));
-        NBGS_TRY(sc->cell_stamp.reserve(sc->grid.ncells));
-        NBGS_HIP(hipMemsetAsync(sc->cell_stamp.p, 0, sizeof(uint32_t) * sc->cell_stamp.cap, s));
+    if ((size_t)sc->grid.ncells > sc->cells.cap) {
+        NBGS_TRY(sc->cells.reserve(sc->grid.ncells));
+        NBGS_HIP(hipMemsetAsync(sc->cells.p, 0, sizeof(int4) * sc->cells.cap, s));
         sc->stamp = 0;
     }
     if (++sc->stamp == 0) {  // wrapped: clear the table once
-        NBGS_HIP(hipMemsetAsync(sc->cell_stamp.p, 0, sizeof(uint32_t) * sc->cell_stamp.cap, s));
+        NBGS_HIP(hipMemsetAsync(sc->cells.p, 0, sizeof(int4) * sc->cells.cap, s));
         sc->stamp = 1;
     }
-    NBGS_TRY(launch_cells(sc->b, sc->grid, skeys, sids, sc->h.p, sc->cell_start.p, sc->cell_end.p,
-                          sc->cell_stamp.p, sc->stamp, sc->sxr.p, sc->cellpos.p, s));
+    NBGS_TRY(launch_cells(sc->b, sc->grid, skeys, sids, sc->h.p, sc->cells.p, sc->stamp, sc->sxr.p, sc->cellpos.p, s));
     // count, scan, emit
     NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
-                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p,
+                               sc->cells.p, sc->stamp, sc->cnt.p,
                                sc->npart.p, sc->partners.p, sc->maxbits.p + 1, s));
     NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, N, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_HIP(hipMemcpyAsync(sc->pinned + 4, sc->maxbits.p + 1, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
@@ -332,6 +456,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     unsigned long long total64 = 0, over = 0;
     std::memcpy(&total64, sc->pinned + 4, sizeof(total64));
     std::memcpy(&over, sc->pinned + 6, sizeof(over));
+    sc->nc_needed = (int64_t)std::min<unsigned long long>(total64, (unsigned long long)INT64_MAX);
     if (over) {
         set_error("a body meets more than 2^18 hull candidates in its 27 cells: the cell grid, sized by the largest "
                   "hull (radius %g), is too coarse for this state (a diverged solve or a very fast body)",
@@ -344,6 +469,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
         return NBGS_ERR_CAPACITY;
     }
     const int64_t nc = sc->pinned[0];
+    sc->nc_needed = nc;
     if (nc != (int64_t)total64) {
         set_error("contact count %lld disagrees with its 64-bit total %llu", (long long)nc,
                   (unsigned long long)total64);
@@ -354,11 +480,18 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
                   "contacts)", (long long)nc);
         return NBGS_ERR_CAPACITY;
     }
+    // the contact capacity of the workspace (nbgs_workspace_query's sizes): refused before any list is touched
+    const size_t need = scene_workspace_bytes(N, nc, sc->n_scenes);
+    if (need > sc->arena.size()) {
+        set_error("%lld contacts need a workspace of %zu bytes (nbgs_workspace_query), this one has %zu",
+                  (long long)nc, need, sc->arena.size());
+        return NBGS_ERR_CAPACITY;
+    }
     sc->nc = nc;
     ContactBuf &cb = sc->cb[sc->cur];
     NBGS_TRY(cb.reserve((size_t)nc));
     NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
-                              sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp, sc->cnt.p, sc->off.p,
+                              sc->cells.p, sc->stamp, sc->cnt.p, sc->off.p,
                               sc->cellpos.p, sc->npart.p, sc->partners.p, cb.view(), nc, s));
     // initial impulses and, when the previous table carries colours, the start of the colouring
     const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
@@ -1087,7 +1220,8 @@ nbgs_status setup_scene_tables(nbgs_scene_t sc, int32_t n_scenes, const int64_t 
 
 namespace nbgs {
 
-nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int64_t *body_off,
+nbgs_status scene_create(void *workspace, size_t workspace_bytes, const nbgs_bodies *bodies, int32_t n_scenes,
+                         const int64_t *body_off,
                          const nbgs_domain *domains, const nbgs_params *params, void *hip_stream, nbgs_scene_t *out) {
     *out = nullptr;
     if (!bodies || !domains || !params || !body_off) {
@@ -1148,6 +1282,13 @@ nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int6
         return NBGS_ERR_OUT_OF_MEMORY;
     }
     sc->s = (hipStream_t)hip_stream;
+    sc->arena.reset(workspace, workspace_bytes);
+    if (!sc->arena.bound()) {
+        delete sc;
+        set_error("the workspace is NULL or too small (nbgs_workspace_query gives its size)");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    ArenaScope arena_scope(&sc->arena);
     // default launch shapes, the fastest measured on the dense 1M packing: lane groups with non-temporal contact
     // loads in FP64, lane groups over a resident grid in FP32
     sc->tune[0].lanes = 1;
@@ -1261,13 +1402,14 @@ namespace nbgs {
 const char *last_error_cstr();
 }
 
+// A NULL handle is refused; the handle's arena takes the buffers allocated
+// until the entry point returns.
 #define NBGS_GUARD(sc)                                                                                          \
-    do {                                                                                                        \
-        if (!(sc)) {                                                                                            \
-            set_error("scene handle is NULL");                                                                  \
-            return NBGS_ERR_INVALID_ARG;                                                                        \
-        }                                                                                                       \
-    } while (0)
+    if (!(sc)) {                                                                                                \
+        set_error("scene handle is NULL");                                                                      \
+        return NBGS_ERR_INVALID_ARG;                                                                            \
+    }                                                                                                           \
+    ArenaScope arena_scope_(&(sc)->arena)
 
 extern "C" {
 
@@ -1275,8 +1417,19 @@ int32_t nbgs_abi_version(void) { return NBGS_ABI_VERSION; }
 
 const char *nbgs_last_error(void) { return nbgs::last_error_cstr(); }
 
+nbgs_status nbgs_workspace_query(int64_t n_bodies, int64_t contact_capacity, const nbgs_params *params,
+                                 size_t *bytes) {
+    if (!bytes || n_bodies < 0 || contact_capacity < 0) {
+        set_error("bad arguments to nbgs_workspace_query");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (params) NBGS_TRY(check_params(params));
+    *bytes = scene_workspace_bytes(n_bodies, contact_capacity, 1);
+    return NBGS_OK;
+}
+
 nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *domain, const nbgs_params *params,
-                              void *hip_stream, nbgs_scene_t *out) {
+                              void *workspace, size_t workspace_bytes, void *hip_stream, nbgs_scene_t *out) {
     if (!out) {
         set_error("out is NULL");
         return NBGS_ERR_INVALID_ARG;
@@ -1287,7 +1440,24 @@ nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *doma
         return NBGS_ERR_INVALID_ARG;
     }
     const int64_t off[2] = {0, bodies->n};
-    return scene_create(bodies, 1, off, domain, params, hip_stream, out);
+    return scene_create(workspace, workspace_bytes, bodies, 1, off, domain, params, hip_stream, out);
+}
+
+nbgs_status nbgs_scene_set_workspace(nbgs_scene_t sc, void *workspace, size_t bytes) {
+    NBGS_GUARD(sc);
+    NBGS_TRY(sc->arena.move_to(workspace, bytes, sc->s));
+    // addresses kept inside moved buffers
+    sc->perm = static_cast<const uint32_t *>(sc->arena.relocate(sc->perm));
+    sc->body_slots = static_cast<const uint32_t *>(sc->arena.relocate(sc->body_slots));
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_scene_workspace_usage(nbgs_scene_t sc, size_t *size, size_t *used, size_t *peak) {
+    NBGS_GUARD(sc);
+    if (size) *size = sc->arena.size();
+    if (used) *used = sc->arena.used();
+    if (peak) *peak = sc->arena.peak();
+    return NBGS_OK;
 }
 
 nbgs_status nbgs_scene_destroy(nbgs_scene_t sc) {
@@ -1332,7 +1502,17 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t sc, const nbgs_params *params) {
 nbgs_status nbgs_detect(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_GUARD(sc);
     sc->state = 0;
-    return detect_impl(sc, stats);
+    sc->nc_needed = -1;
+    const nbgs_status st = detect_impl(sc, stats);
+    if (st == NBGS_ERR_CAPACITY) {
+        // what was lacking: the contact count found, for nbgs_workspace_query
+        sc->prev_sig_valid = false;
+        if (stats) {
+            *stats = nbgs_stats{};
+            stats->n_contacts = sc->nc_needed;
+        }
+    }
+    return st;
 }
 
 nbgs_status nbgs_solve(nbgs_scene_t sc, int32_t max_sweeps, double residual_target, nbgs_stats *stats) {
@@ -1361,7 +1541,12 @@ nbgs_status nbgs_integrate(nbgs_scene_t sc) {
 
 nbgs_status nbgs_step(nbgs_scene_t sc, int32_t max_sweeps, double residual_target, nbgs_stats *stats) {
     NBGS_GUARD(sc);
-    NBGS_TRY(nbgs_detect(sc, nullptr));
+    nbgs_stats dst{};
+    const nbgs_status ds = nbgs_detect(sc, &dst);
+    if (ds != NBGS_OK) {
+        if (ds == NBGS_ERR_CAPACITY && stats) *stats = dst;  // the contact count the workspace lacks
+        return ds;
+    }
     nbgs_status st = nbgs_solve(sc, max_sweeps, residual_target, stats);
     if (st != NBGS_OK && st != NBGS_ERR_NOT_CONVERGED) return st;
     NBGS_TRY(nbgs_integrate(sc));
@@ -1491,6 +1676,17 @@ nbgs_status nbgs_set_block_order(nbgs_scene_t sc, double edge) {
     return NBGS_OK;
 }
 
+nbgs_status nbgs_set_block_grids(nbgs_scene_t sc, int32_t grids) {
+    NBGS_GUARD(sc);
+    if (grids < 1 || grids > 8) {
+        set_error("block grids must be 1 .. 8");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    sc->blk_grids = grids;
+    sc->state = 0;  // the next step starts with a detection
+    return NBGS_OK;
+}
+
 nbgs_status nbgs_set_residual_history(nbgs_scene_t sc, int32_t enable) {
     NBGS_GUARD(sc);
     sc->res_history = enable != 0;
@@ -1585,6 +1781,28 @@ nbgs_status nbgs_get_training_data(nbgs_scene_t sc, int64_t cap, float *feat, fl
         NBGS_HIP(hipMemcpyAsync(feat, sc->feat.p, sizeof(float) * 12 * sc->nc, hipMemcpyDeviceToDevice, sc->s));
     if (target) NBGS_TRY(launch_targets(sc->frame.p, sc->cb[sc->cur].view(), sc->nc, sc->fs, target, sc->s));
     NBGS_HIP(hipStreamSynchronize(sc->s));
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_mlp_collect(nbgs_scene_t sc, nbgs_mlp_t mlp, int64_t *n_stored) {
+    NBGS_GUARD(sc);
+    if (!mlp) {
+        set_error("network handle is NULL");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (!sc->have_features || !sc->solved) {
+        set_error("collecting needs features from nbgs_detect (capture or learned warm start) and a solve");
+        return NBGS_ERR_STATE;
+    }
+    float *feat = nullptr, *tgt = nullptr;
+    NBGS_TRY(mlp_store_slot(mlp, sc->nc, &feat, &tgt));
+    if (sc->nc > 0) {
+        NBGS_HIP(hipMemcpyAsync(feat, sc->feat.p, sizeof(float) * 12 * sc->nc, hipMemcpyDeviceToDevice, sc->s));
+        NBGS_TRY(launch_targets(sc->frame.p, sc->cb[sc->cur].view(), sc->nc, sc->fs, tgt, sc->s));
+        NBGS_HIP(hipStreamSynchronize(sc->s));  // the network's stream reads the store next
+    }
+    mlp_store_commit(mlp, sc->nc);
+    if (n_stored) NBGS_TRY(nbgs_mlp_collected(mlp, n_stored, nullptr, nullptr));
     return NBGS_OK;
 }
 

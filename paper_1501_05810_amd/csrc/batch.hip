@@ -27,9 +27,21 @@ using namespace nbgs;
 
 extern "C" {
 
+nbgs_status nbgs_batch_workspace_query(int32_t n_scenes, int64_t n_bodies, int64_t contact_capacity,
+                                       const nbgs_params *params, size_t *bytes) {
+    if (!bytes || n_scenes < 1 || n_bodies < 0 || contact_capacity < 0) {
+        set_error("bad arguments to nbgs_batch_workspace_query");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (params)
+        for (int32_t s = 0; s < n_scenes; ++s) NBGS_TRY(check_params(&params[s]));
+    *bytes = scene_workspace_bytes(n_bodies, contact_capacity, n_scenes);
+    return NBGS_OK;
+}
+
 nbgs_status nbgs_batch_create(int32_t n_scenes, const int64_t *body_offsets, const nbgs_bodies *bodies,
                               const nbgs_domain *domains, const nbgs_params *params, const char *tune_cache_path,
-                              void *hip_stream, nbgs_batch_t *out) {
+                              void *workspace, size_t workspace_bytes, void *hip_stream, nbgs_batch_t *out) {
     if (!out) {
         set_error("out is NULL");
         return NBGS_ERR_INVALID_ARG;
@@ -40,7 +52,8 @@ nbgs_status nbgs_batch_create(int32_t n_scenes, const int64_t *body_offsets, con
         set_error("host allocation failed");
         return NBGS_ERR_OUT_OF_MEMORY;
     }
-    const nbgs_status st = scene_create(bodies, n_scenes, body_offsets, domains, params, hip_stream, &bt->sc);
+    const nbgs_status st = scene_create(workspace, workspace_bytes, bodies, n_scenes, body_offsets, domains, params,
+                                        hip_stream, &bt->sc);
     if (st != NBGS_OK) {
         delete bt;
         return st;
@@ -67,7 +80,8 @@ nbgs_status nbgs_batch_scene(nbgs_batch_t bt, nbgs_scene_t *scene) {
 }
 
 nbgs_status nbgs_batch_step(nbgs_batch_t bt, int32_t n_steps, int32_t max_sweeps, double residual_target,
-                            nbgs_stats *stats) {
+                            nbgs_stats *stats, int32_t *steps_done) {
+    if (steps_done) *steps_done = 0;
     if (!bt) {
         set_error("batch handle is NULL");
         return NBGS_ERR_INVALID_ARG;
@@ -77,15 +91,22 @@ nbgs_status nbgs_batch_step(nbgs_batch_t bt, int32_t n_steps, int32_t max_sweeps
         return NBGS_ERR_INVALID_ARG;
     }
     nbgs_scene_t sc = bt->sc;
+    ArenaScope arena_scope(&sc->arena);
     nbgs_status last = NBGS_OK;
     for (int32_t k = 0; k < n_steps; ++k) {
-        NBGS_TRY(nbgs_detect(sc, nullptr));
+        nbgs_stats dst{};
+        const nbgs_status ds = nbgs_detect(sc, &dst);
+        if (ds != NBGS_OK) {
+            if (ds == NBGS_ERR_CAPACITY && stats) *stats = dst;  // the contact count the workspace lacks
+            return ds;
+        }
         const int prec = sc->precision_used == NBGS_FP32_SWEEP ? 1 : 0;
         if (!sc->tuned[prec] && sc->nc > 0)
             NBGS_TRY(scene_autotune(sc, std::min(max_sweeps, bt->tune_sweeps), nullptr, nullptr));
         last = nbgs_solve(sc, max_sweeps, residual_target, k + 1 == n_steps ? stats : nullptr);
         if (last != NBGS_OK && last != NBGS_ERR_NOT_CONVERGED) return last;
         NBGS_TRY(nbgs_integrate(sc));
+        if (steps_done) *steps_done = k + 1;
     }
     return last;
 }

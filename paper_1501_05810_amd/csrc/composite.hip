@@ -152,17 +152,16 @@ __global__ void __launch_bounds__(kBlock) k_cell_keys(const double4 *ec, int64_t
 }
 
 __global__ void __launch_bounds__(kBlock) k_cells(int64_t ne, const uint32_t *skeys, const uint32_t *sids,
-                                                  const double4 *ec, const int32_t *ebody, int32_t *cell_start,
-                                                  int32_t *cell_end, uint32_t *cell_stamp, uint32_t stamp,
+                                                  const double4 *ec, const int32_t *ebody, int4 *cells, uint32_t stamp,
                                                   double4 *sec, int32_t *sbody, int32_t *cellpos) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= ne) return;
     const uint32_t key = skeys[p];
     if (p == 0 || skeys[p - 1] != key) {
-        cell_start[key] = (int32_t)p;
-        cell_stamp[key] = stamp;
+        cells[key].x = (int32_t)p;
+        cells[key].z = (int)stamp;
     }
-    if (p == ne - 1 || skeys[p + 1] != key) cell_end[key] = (int32_t)(p + 1);
+    if (p == ne - 1 || skeys[p + 1] != key) cells[key].y = (int32_t)(p + 1);
     const int e = (int)sids[p];
     cellpos[e] = (int32_t)p;
     sec[p] = ec[e];
@@ -182,8 +181,7 @@ __device__ inline double min_image(double d, int periodic, double L) {
 // variant keeps all).
 template <bool kEmit>
 __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const uint32_t *sids, const double4 *sec,
-                                     const int32_t *sbody, const int32_t *cell_start, const int32_t *cell_end,
-                                     const uint32_t *cell_stamp, uint32_t stamp, int p, int A, int32_t *out,
+                                     const int32_t *sbody, const int4 *cells, uint32_t stamp, int p, int A, int32_t *out,
                                      int cap = 0) {
     const double4 me = sec[p];
     const uint32_t key = skeys[p];
@@ -254,8 +252,9 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
 #pragma unroll
                 for (int x = 0; x < 3; ++x) {
                     const int cell = row + (xa + x <= xb ? xa + x : xa);  // past xb: a repeat, left unused
-                    const uint32_t cs = cell_stamp[cell];
-                    const int s0 = cell_start[cell], s1 = cell_end[cell];
+                    const int4 cr = cells[cell];
+                    const uint32_t cs = (uint32_t)cr.z;
+                    const int s0 = cr.x, s1 = cr.y;
                     if (xa + x > xb || cs != stamp) continue;
                     if (!any) q0 = s0;
                     q1 = s1;
@@ -270,8 +269,9 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
                     const int cell = row + qx;
                     // the cell's stamp and range are read together (one round trip); a range whose stamp is
                     // stale is left unused
-                    const uint32_t cs = cell_stamp[cell];
-                    const int q0 = cell_start[cell], q1 = cell_end[cell];
+                    const int4 cr = cells[cell];
+                    const uint32_t cs = (uint32_t)cr.z;
+                    const int q0 = cr.x, q1 = cr.y;
                     if (cs != stamp) continue;
                     if (!scan(q0, q1)) return -1;
                 }
@@ -294,8 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(int64_t ne, Grid g, Plane
                                                        const uint32_t *skeys, const uint32_t *sids,
                                                        const double4 *sec, const int32_t *sbody,
                                                        const double *erad, const double *h,
-                                                       const int32_t *cell_start, const int32_t *cell_end,
-                                                       const uint32_t *cell_stamp, uint32_t stamp, int32_t *cnt,
+                                                       const int4 *cells, uint32_t stamp, int32_t *cnt,
                                                        int32_t *npart, int32_t *partners,
                                                        unsigned long long *total) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -304,7 +303,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(int64_t ne, Grid g, Plane
     if (p < ne) {
         const int e = (int)sids[p];
         const int A = sbody[p];
-        int m = visit_partners<false>(g, skeys, sids, sec, sbody, cell_start, cell_end, cell_stamp, stamp, (int)p, A,
+        int m = visit_partners<false>(g, skeys, sids, sec, sbody, cells, stamp, (int)p, A,
                                       partners + (int64_t)kPartnerCap * e, kPartnerCap);
         if (m < 0) {
             over = 1;
@@ -387,8 +386,7 @@ __device__ inline void sort_partners(int32_t *ks, int m) {
 __global__ void __launch_bounds__(kBlock) k_pair_emit(int64_t ne, int32_t nb, Grid g, PlaneSet pl, double tau,
                                                       const uint32_t *skeys, const uint32_t *sids,
                                                       const double4 *sec, const int32_t *sbody,
-                                                      const int32_t *cell_start, const int32_t *cell_end,
-                                                      const uint32_t *cell_stamp, uint32_t stamp,
+                                                      const int4 *cells, uint32_t stamp,
                                                       const int32_t *cnt, const int32_t *off,
                                                       const int32_t *npart, const int32_t *partners,
                                                       const int32_t *cellpos, const double4 *ec,
@@ -406,7 +404,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(int64_t ne, int32_t nb, Gr
         const int32_t *kept = partners + (int64_t)kPartnerCap * e;
         for (int t = 0; t < m; ++t) ks[t] = kept[t];
     } else {
-        m = visit_partners<true>(g, skeys, sids, sec, sbody, cell_start, cell_end, cell_stamp, stamp, p, A, ks);
+        m = visit_partners<true>(g, skeys, sids, sec, sbody, cells, stamp, p, A, ks);
     }
     sort_partners(ks, m);
     const double4 ce = ec[e];
@@ -911,6 +909,9 @@ enum { kPhDetect = 0, kPhColour, kPhInit, kPhSweeps, kPhIntegrate, kPhEnd, kPhN 
 using namespace nbgs;
 
 struct nbgs_composite_s {
+    // device memory of the scene (the caller's workspace); first, so that it outlives every buffer carved from it
+    Arena arena;
+    int64_t nc_needed = -1;  // the contact count the last detection found (reported with CAPACITY)
     hipStream_t s = nullptr;
     CompBodies b{};
     BodiesView bv{};  // the body state as the shared integrator reads it
@@ -919,9 +920,10 @@ struct nbgs_composite_s {
     int32_t periodic[3] = {0, 0, 0};
     nbgs_params p{};
     Grid grid{};
-    DevBuf<int32_t> ebody, sbody, cellpos, cnt, off, off1, cnt1, deg2, off2, cursor, inc2, cell_start, cell_end,
+    DevBuf<int4> cells;  // per cell (start, end, stamp, -) of its sorted range
+    DevBuf<int32_t> ebody, sbody, cellpos, cnt, off, off1, cnt1, deg2, off2, cursor, inc2,
         radix_hist, spos, small, ctrl, npart, partners;
-    DevBuf<uint32_t> keys, ids, keys2, ids2, cell_stamp, ckeys, cids, ckeys2, cids2;
+    DevBuf<uint32_t> keys, ids, keys2, ids2, ckeys, cids, ckeys2, cids2;
     DevBuf<double4> ec, sec;
     DevBuf<double> h, owx, owy, owz, vel, iw, partials, hist;
     DevBuf<unsigned long long> maxbits;
@@ -944,6 +946,20 @@ struct nbgs_composite_s {
     hipEvent_t ev[kPhN] = {};
     bool ev_ok[kPhN] = {};
 };
+
+// Upper bound of a composite scene's device memory (nbgs_composite_workspace_query):
+// per element 352 B (its world offset, grown sphere, sorted copies, partner
+// store, sort keys 192 B; cells of 16 B at most eight per element 160 B), per body
+// 164 B (accumulator record, world inverse inertia, hull radius, colouring
+// counters), per contact 525 B (two contact tables 272 B, the sweep record
+// 116 B, colouring 32 B, times 1.25), a cell table of at least 2^16 cells and
+// a fixed 16 MiB; ten per cent for alignment and the runs between freed
+// buffers.
+size_t composite_workspace_bytes(int64_t n, int64_t e, int64_t c) {
+    const double b = 1.1 * (352.0 * (double)e + 164.0 * (double)n + 525.0 * (double)c + 65536.0 * 16.0 * 1.25 +
+                            16.0 * 1024.0 * 1024.0);
+    return (size_t)b;
+}
 
 namespace {
 
@@ -989,23 +1005,19 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
                               sc->scan_tmp.p, sc->scan_tmp.cap, &alt, s));
     const uint32_t *skeys = alt ? sc->keys2.p : sc->keys.p;
     const uint32_t *sids = alt ? sc->ids2.p : sc->ids.p;
-    if ((size_t)g.ncells > sc->cell_stamp.cap) {
-        NBGS_TRY(sc->cell_start.reserve(g.ncells));
-        NBGS_TRY(sc->cell_end.reserve(g.ncells));
-        NBGS_TRY(sc->cell_stamp.reserve(g.ncells));
-        NBGS_HIP(hipMemsetAsync(sc->cell_stamp.p, 0, sizeof(uint32_t) * sc->cell_stamp.cap, s));
+    if ((size_t)g.ncells > sc->cells.cap) {
+        NBGS_TRY(sc->cells.reserve(g.ncells));
+        NBGS_HIP(hipMemsetAsync(sc->cells.p, 0, sizeof(int4) * sc->cells.cap, s));
         sc->stamp = 0;
     }
     if (++sc->stamp == 0) {
-        NBGS_HIP(hipMemsetAsync(sc->cell_stamp.p, 0, sizeof(uint32_t) * sc->cell_stamp.cap, s));
+        NBGS_HIP(hipMemsetAsync(sc->cells.p, 0, sizeof(int4) * sc->cells.cap, s));
         sc->stamp = 1;
     }
-    k_cells<<<grid_for(E), kBlock, 0, s>>>(E, skeys, sids, sc->ec.p, sc->ebody.p, sc->cell_start.p, sc->cell_end.p,
-                                           sc->cell_stamp.p, sc->stamp, sc->sec.p, sc->sbody.p, sc->cellpos.p);
+    k_cells<<<grid_for(E), kBlock, 0, s>>>(E, skeys, sids, sc->ec.p, sc->ebody.p, sc->cells.p, sc->stamp, sc->sec.p, sc->sbody.p, sc->cellpos.p);
     NBGS_HIP(hipGetLastError());
     k_pair_count<<<grid_for(E), kBlock, 0, s>>>(E, g, sc->planes, sc->p.tau, skeys, sids, sc->sec.p, sc->sbody.p,
-                                                sc->b.elem_radius, sc->h.p, sc->cell_start.p, sc->cell_end.p,
-                                                sc->cell_stamp.p, sc->stamp, sc->cnt.p, sc->npart.p, sc->partners.p,
+                                                sc->b.elem_radius, sc->h.p, sc->cells.p, sc->stamp, sc->cnt.p, sc->npart.p, sc->partners.p,
                                                 sc->maxbits.p + 1);
     NBGS_HIP(hipGetLastError());
     NBGS_HIP(hipMemsetAsync(sc->cnt.p + E, 0, sizeof(int32_t), s));  // off[E] = the total
@@ -1016,6 +1028,7 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
     unsigned long long total64 = 0, over = 0;
     std::memcpy(&total64, sc->pinned + 4, sizeof(total64));
     std::memcpy(&over, sc->pinned + 6, sizeof(over));
+    sc->nc_needed = (int64_t)std::min<unsigned long long>(total64, (unsigned long long)INT64_MAX);
     if (over) {
         set_error("an element meets more than 2^18 hull candidates in its 27 cells (largest grown element %g)",
                   max_reach);
@@ -1031,11 +1044,18 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
                   (unsigned long long)total64);
         return NBGS_ERR_DEVICE;
     }
+    sc->nc_needed = nc;
+    const size_t need = composite_workspace_bytes(N, E, nc);
+    if (need > sc->arena.size()) {
+        set_error("%lld contacts need a workspace of %zu bytes (nbgs_composite_workspace_query), this one has %zu",
+                  (long long)nc, need, sc->arena.size());
+        return NBGS_ERR_CAPACITY;
+    }
     sc->nc = nc;
     CompContactBuf &cb = sc->cb[sc->cur];
     NBGS_TRY(cb.reserve((size_t)(nc > 0 ? nc : 1)));
     k_pair_emit<<<grid_for(E), kBlock, 0, s>>>(E, N, g, sc->planes, sc->p.tau, skeys, sids, sc->sec.p, sc->sbody.p,
-                                               sc->cell_start.p, sc->cell_end.p, sc->cell_stamp.p, sc->stamp,
+                                               sc->cells.p, sc->stamp,
                                                sc->cnt.p, sc->off.p, sc->npart.p, sc->partners.p, sc->cellpos.p,
                                                sc->ec.p, sc->ebody.p,
                                                sc->b.elem_radius, sc->h.p, sc->owx.p, sc->owy.p, sc->owz.p, cb.view());
@@ -1246,18 +1266,36 @@ nbgs_status comp_integrate(nbgs_composite_t sc) {
 
 }  // namespace
 
+// A NULL handle is refused; the handle's arena takes the buffers allocated
+// until the entry point returns.
 #define NBGS_CGUARD(sc)                                                                                         \
-    do {                                                                                                        \
-        if (!(sc)) {                                                                                            \
-            set_error("composite scene handle is NULL");                                                        \
-            return NBGS_ERR_INVALID_ARG;                                                                        \
-        }                                                                                                       \
-    } while (0)
+    if (!(sc)) {                                                                                                \
+        set_error("composite scene handle is NULL");                                                            \
+        return NBGS_ERR_INVALID_ARG;                                                                            \
+    }                                                                                                           \
+    ArenaScope arena_scope_(&(sc)->arena)
 
 extern "C" {
 
+nbgs_status nbgs_composite_workspace_query(int64_t n_bodies, int64_t n_elements, int64_t contact_capacity,
+                                           const nbgs_params *params, size_t *bytes) {
+    if (!bytes || n_bodies < 0 || n_elements < 0 || contact_capacity < 0) {
+        set_error("bad arguments to nbgs_composite_workspace_query");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (params) NBGS_TRY(check_params(params));
+    *bytes = composite_workspace_bytes(n_bodies, n_elements, contact_capacity);
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_composite_set_workspace(nbgs_composite_t sc, void *workspace, size_t bytes) {
+    NBGS_CGUARD(sc);
+    return sc->arena.move_to(workspace, bytes, sc->s);
+}
+
 nbgs_status nbgs_composite_create(const nbgs_composite_bodies *bodies, const nbgs_domain *domain,
-                                  const nbgs_params *params, void *hip_stream, nbgs_composite_t *out) {
+                                  const nbgs_params *params, void *workspace, size_t workspace_bytes,
+                                  void *hip_stream, nbgs_composite_t *out) {
     if (!out) {
         set_error("out is NULL");
         return NBGS_ERR_INVALID_ARG;
@@ -1308,6 +1346,12 @@ nbgs_status nbgs_composite_create(const nbgs_composite_bodies *bodies, const nbg
         }
     } guard{sc};
     sc->s = (hipStream_t)hip_stream;
+    sc->arena.reset(workspace, workspace_bytes);
+    if (!sc->arena.bound()) {
+        set_error("the workspace is NULL or too small (nbgs_composite_workspace_query gives its size)");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    ArenaScope arena_scope(&sc->arena);
     CompBodies &b = sc->b;
     b.n = (int32_t)bodies->n;
     b.ne = bodies->n_elements;
@@ -1423,7 +1467,13 @@ nbgs_status nbgs_composite_detect(nbgs_composite_t sc, nbgs_stats *stats) {
         set_error("detect after detect: solve and integrate first");
         return NBGS_ERR_STATE;
     }
-    return comp_detect(sc, stats);
+    sc->nc_needed = -1;
+    const nbgs_status st = comp_detect(sc, stats);
+    if (st == NBGS_ERR_CAPACITY && stats) {
+        *stats = nbgs_stats{};
+        stats->n_contacts = sc->nc_needed;
+    }
+    return st;
 }
 
 nbgs_status nbgs_composite_solve(nbgs_composite_t sc, int32_t max_sweeps, double residual_target,
@@ -1443,7 +1493,15 @@ nbgs_status nbgs_composite_step(nbgs_composite_t sc, int32_t max_sweeps, double 
         set_error("step needs an integrated (or fresh) scene");
         return NBGS_ERR_STATE;
     }
-    NBGS_TRY(comp_detect(sc, nullptr));
+    sc->nc_needed = -1;
+    const nbgs_status ds = comp_detect(sc, nullptr);
+    if (ds != NBGS_OK) {
+        if (ds == NBGS_ERR_CAPACITY && stats) {  // the contact count the workspace lacks
+            *stats = nbgs_stats{};
+            stats->n_contacts = sc->nc_needed;
+        }
+        return ds;
+    }
     const nbgs_status st = comp_solve(sc, max_sweeps, residual_target, stats);
     if (st != NBGS_OK && st != NBGS_ERR_NOT_CONVERGED) return st;
     NBGS_TRY(comp_integrate(sc));

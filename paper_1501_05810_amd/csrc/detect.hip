@@ -82,17 +82,16 @@ __global__ void __launch_bounds__(kBlock) k_cell_keys(BodiesView b, Grid g0, Sce
 // for coalesced neighbour reads (the sign marks static bodies), and each
 // body's sorted position.
 __global__ void __launch_bounds__(kBlock) k_cells(BodiesView b, int32_t n, const uint32_t *skeys,
-                                                  const uint32_t *sids, const double *h, int32_t *cell_start,
-                                                  int32_t *cell_end, uint32_t *cell_stamp, uint32_t stamp,
+                                                  const uint32_t *sids, const double *h, int4 *cells, uint32_t stamp,
                                                   double4 *sxr, int32_t *cellpos) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     const uint32_t key = skeys[p];
     if (p == 0 || skeys[p - 1] != key) {
-        cell_start[key] = p;
-        cell_stamp[key] = stamp;
+        cells[key].x = p;
+        cells[key].z = (int)stamp;
     }
-    if (p == n - 1 || skeys[p + 1] != key) cell_end[key] = p + 1;
+    if (p == n - 1 || skeys[p + 1] != key) cells[key].y = p + 1;
     const int i = (int)sids[p];
     cellpos[i] = p;
     const double rh = b.radius[i] + h[i];
@@ -172,7 +171,7 @@ constexpr int kMaxCandidates = 1 << 18;
 // keeps the first `cap` partners found in out_k (the emit variant keeps all).
 template <bool kEmit>
 __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const uint32_t *sids, const double4 *sxr,
-                                     const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                                     const int4 *cells,
                                      uint32_t stamp, int p, int i, int32_t *out_k, int cap = 0) {
     const double4 me = sxr[p];
     int c[3];
@@ -182,11 +181,12 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
         for (int dy = nr.lo[1]; dy <= nr.hi[1]; ++dy)
             for (int dx = nr.lo[0]; dx <= nr.hi[0]; ++dx) {
                 const int cell = neighbour_cell(g, c, dx, dy, dz);
-                // the cell's stamp and range are read together (one round trip); a range whose stamp is stale is
+                // the cell's record (start, end, stamp) is read in one 16-byte load; a range whose stamp is stale is
                 // left unused
                 const int cc = cell < 0 ? 0 : cell;
-                const uint32_t cs = cell_stamp[cc];
-                const int q0 = cell_start[cc], q1 = cell_end[cc];
+                const int4 cr = cells[cc];
+                const uint32_t cs = (uint32_t)cr.z;
+                const int q0 = cr.x, q1 = cr.y;
                 if (cell < 0 || cs != stamp) continue;
                 if (!kEmit) {
                     seen += q1 - q0;
@@ -208,8 +208,7 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
 __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                        const uint32_t *skeys, const uint32_t *sids,
                                                        const double4 *sxr, const double *h,
-                                                       const int32_t *cell_start, const int32_t *cell_end,
-                                                       const uint32_t *cell_stamp, uint32_t stamp, int32_t *cnt,
+                                                       const int4 *cells, uint32_t stamp, int32_t *cnt,
                                                        int32_t *npart, int32_t *partners,
                                                        unsigned long long *total) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
@@ -220,7 +219,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, Pl
         const int sc = st.body_scene ? st.body_scene[i] : 0;
         const Grid &g = st.body_scene ? st.grids[sc] : g0;
         const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
-        int m = visit_partners<false>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i,
+        int m = visit_partners<false>(g, skeys, sids, sxr, cells, stamp, p, i,
                                       partners + (int64_t)kPartnerCap * i, kPartnerCap);
         if (m < 0) {
             over = 1;
@@ -305,8 +304,7 @@ __device__ inline void sort_partners(int32_t *ks, int m) {
 __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                       const uint32_t *skeys, const uint32_t *sids,
                                                       const double4 *sxr, const double *h,
-                                                      const int32_t *cell_start, const int32_t *cell_end,
-                                                      const uint32_t *cell_stamp, uint32_t stamp, const int32_t *cnt,
+                                                      const int4 *cells, uint32_t stamp, const int32_t *cnt,
                                                       const int32_t *off, const int32_t *cellpos,
                                                       const int32_t *npart, const int32_t *partners, ContactsView c) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -323,7 +321,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, Pla
         const int32_t *kept = partners + (int64_t)kPartnerCap * i;
         for (int t = 0; t < m; ++t) ks[t] = kept[t];
     } else {
-        m = visit_partners<true>(g, skeys, sids, sxr, cell_start, cell_end, cell_stamp, stamp, p, i, ks);
+        m = visit_partners<true>(g, skeys, sids, sxr, cells, stamp, p, i, ks);
     }
     sort_partners(ks, m);
     for (int t = 0; t < m; ++t) c.j1[base + t] = i;
@@ -523,10 +521,10 @@ nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTabl
 }
 
 nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
-                         const double *h, int32_t *cell_start, int32_t *cell_end, uint32_t *cell_stamp,
+                         const double *h, int4 *cells,
                          uint32_t stamp, double4 *sxr, int32_t *cellpos, hipStream_t s) {
     (void)g;
-    k_cells<<<grid_for(b.n), kBlock, 0, s>>>(b, b.n, skeys, sids, h, cell_start, cell_end, cell_stamp, stamp, sxr,
+    k_cells<<<grid_for(b.n), kBlock, 0, s>>>(b, b.n, skeys, sids, h, cells, stamp, sxr,
                                              cellpos);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
@@ -534,24 +532,22 @@ nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *ske
 
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
-                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                              const int4 *cells,
                               uint32_t stamp, int32_t *cnt, int32_t *npart, int32_t *partners,
                               unsigned long long *total, hipStream_t s) {
     if (b.n <= 0) return NBGS_OK;
-    k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
-                                                  cell_stamp, stamp, cnt, npart, partners, total);
+    k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cells, stamp, cnt, npart, partners, total);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
 nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
-                             const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                             const int4 *cells,
                              uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
                              const int32_t *npart, const int32_t *partners, ContactsView c, int64_t nc,
                              hipStream_t s) {
-    k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cell_start, cell_end,
-                                                 cell_stamp, stamp, cnt, off, cellpos, npart, partners, c);
+    k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cells, stamp, cnt, off, cellpos, npart, partners, c);
     NBGS_HIP(hipGetLastError());
     if (nc > 0) {
         k_pair_geometry<<<grid_for(nc), kBlock, 0, s>>>(b, g, pl, st, nc, c);

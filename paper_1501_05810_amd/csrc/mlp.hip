@@ -513,10 +513,15 @@ nbgs_status launch_mlp_adam(float *w, const float *g, float *m, float *v, int64_
 // ------------------------------------------------------------------ C ABI
 
 struct nbgs_mlp_s {
+    // device memory of the network (the caller's workspace); first, so that it outlives every buffer carved from it
+    nbgs::Arena arena;
     hipStream_t s = nullptr;
     nbgs::DevBuf<float> w, m, v, grad, part, lpart;
     nbgs::DevBuf<unsigned short> fr;
     nbgs::DevBuf<int32_t> idx;
+    // training pairs collected from solved steps (nbgs_mlp_collect): features [max_samples x 12], targets [x 3]
+    nbgs::DevBuf<float> store_feat, store_tgt;
+    int64_t max_samples = 0, n_stored = 0;
     int64_t step = 0;
     float *host = nullptr;  // pinned staging
 };
@@ -526,7 +531,43 @@ using namespace nbgs;
 namespace nbgs {
 const unsigned short *mlp_frag_ptr(nbgs_mlp_t mlp) { return mlp->fr.p; }
 const float *mlp_weight_ptr(nbgs_mlp_t mlp) { return mlp->w.p; }
+
+// Upper bound of a network's device memory (nbgs_mlp_workspace_query): the
+// weights, Adam moments, gradient and packed BF16 fragments, the per-block
+// gradient partials of up to 1,024 blocks (76 MB), and per training sample
+// its shuffled index and its collected features and targets (64 B); ten per
+// cent for alignment.
+size_t mlp_workspace_bytes(int64_t max_samples) {
+    const double fixed = 4.0 * NPAR * 4.0 + 2.0 * NFRAG + 1025.0 * NPAR * 4.0 + 1024.0 * 4.0 + 1024.0 * 1024.0;
+    return (size_t)(1.1 * (fixed + 64.0 * (double)max_samples));
+}
+
+// Room for n more collected samples (CAPACITY past max_samples): where they go.
+nbgs_status mlp_store_slot(nbgs_mlp_t mlp, int64_t n, float **feat, float **tgt) {
+    if (mlp->n_stored + n > mlp->max_samples) {
+        set_error("%lld more samples do not fit into the %lld the network's store holds (%lld taken)", (long long)n,
+                  (long long)mlp->max_samples, (long long)mlp->n_stored);
+        return NBGS_ERR_CAPACITY;
+    }
+    ArenaScope arena_scope(&mlp->arena);
+    NBGS_TRY(mlp->store_feat.reserve(12 * (size_t)(mlp->max_samples > 0 ? mlp->max_samples : 1), 1.0));
+    NBGS_TRY(mlp->store_tgt.reserve(3 * (size_t)(mlp->max_samples > 0 ? mlp->max_samples : 1), 1.0));
+    *feat = mlp->store_feat.p + 12 * mlp->n_stored;
+    *tgt = mlp->store_tgt.p + 3 * mlp->n_stored;
+    return NBGS_OK;
+}
+
+void mlp_store_commit(nbgs_mlp_t mlp, int64_t n) { mlp->n_stored += n; }
 }  // namespace nbgs
+
+// A NULL network is refused; its arena takes the buffers allocated until the
+// entry point returns.
+#define NBGS_MGUARD(mlp)                                                                                        \
+    if (!(mlp)) {                                                                                               \
+        set_error("network handle is NULL");                                                                    \
+        return NBGS_ERR_INVALID_ARG;                                                                            \
+    }                                                                                                           \
+    ArenaScope arena_scope_(&(mlp)->arena)
 
 namespace {
 
@@ -561,9 +602,19 @@ nbgs_status upload(nbgs_mlp_t mlp, const float *host_w) {
 
 extern "C" {
 
-nbgs_status nbgs_mlp_create(uint64_t seed, void *hip_stream, nbgs_mlp_t *out) {
-    if (!out) {
-        set_error("out is NULL");
+nbgs_status nbgs_mlp_workspace_query(int64_t max_samples, size_t *bytes) {
+    if (!bytes || max_samples < 0) {
+        set_error("bad arguments to nbgs_mlp_workspace_query");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    *bytes = mlp_workspace_bytes(max_samples);
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_mlp_create(uint64_t seed, int64_t max_samples, void *workspace, size_t workspace_bytes,
+                            void *hip_stream, nbgs_mlp_t *out) {
+    if (!out || max_samples < 0) {
+        set_error("out is NULL or max_samples negative");
         return NBGS_ERR_INVALID_ARG;
     }
     *out = nullptr;
@@ -573,6 +624,14 @@ nbgs_status nbgs_mlp_create(uint64_t seed, void *hip_stream, nbgs_mlp_t *out) {
         return NBGS_ERR_OUT_OF_MEMORY;
     }
     mlp->s = (hipStream_t)hip_stream;
+    mlp->max_samples = max_samples;
+    mlp->arena.reset(workspace, workspace_bytes);
+    if (!mlp->arena.bound()) {
+        delete mlp;
+        set_error("the workspace is NULL or too small (nbgs_mlp_workspace_query gives its size)");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    ArenaScope arena_scope(&mlp->arena);
     nbgs_status st = NBGS_OK;
     for (DevBuf<float> *b : {&mlp->w, &mlp->m, &mlp->v, &mlp->grad})
         if (st == NBGS_OK) st = b->reserve(NPAR, 1.0);
@@ -610,6 +669,7 @@ nbgs_status nbgs_mlp_set_weights(nbgs_mlp_t mlp, const float *w) {
         set_error("mlp or weights NULL");
         return NBGS_ERR_INVALID_ARG;
     }
+    ArenaScope arena_scope(&mlp->arena);
     std::memcpy(mlp->host, w, sizeof(float) * NPAR);
     return upload(mlp, mlp->host);
 }
@@ -619,6 +679,7 @@ nbgs_status nbgs_mlp_get_weights(nbgs_mlp_t mlp, float *w) {
         set_error("mlp or weights NULL");
         return NBGS_ERR_INVALID_ARG;
     }
+    ArenaScope arena_scope(&mlp->arena);
     NBGS_HIP(hipMemcpyAsync(mlp->host, mlp->w.p, sizeof(float) * NPAR, hipMemcpyDeviceToHost, mlp->s));
     NBGS_HIP(hipStreamSynchronize(mlp->s));
     std::memcpy(w, mlp->host, sizeof(float) * NPAR);
@@ -630,6 +691,7 @@ nbgs_status nbgs_mlp_forward(nbgs_mlp_t mlp, const float *feat, int64_t n, float
         set_error("bad arguments to nbgs_mlp_forward");
         return NBGS_ERR_INVALID_ARG;
     }
+    ArenaScope arena_scope(&mlp->arena);
     if (reinterpret_cast<uintptr_t>(feat) % 16 != 0) {
         set_error("nbgs_mlp_forward needs 16-byte aligned features");
         return NBGS_ERR_INVALID_ARG;
@@ -643,6 +705,7 @@ nbgs_status nbgs_mlp_loss_grad(nbgs_mlp_t mlp, const float *feat, const float *t
         set_error("bad arguments to nbgs_mlp_loss_grad");
         return NBGS_ERR_INVALID_ARG;
     }
+    ArenaScope arena_scope(&mlp->arena);
     const int nb = mlp_grad_blocks(n);
     NBGS_TRY(mlp->part.reserve((size_t)nb * NPAR));
     NBGS_TRY(mlp->lpart.reserve((size_t)nb));
@@ -668,6 +731,7 @@ nbgs_status nbgs_mlp_train(nbgs_mlp_t mlp, const float *feat, const float *targe
         set_error("bad arguments to nbgs_mlp_train");
         return NBGS_ERR_INVALID_ARG;
     }
+    ArenaScope arena_scope(&mlp->arena);
     const int64_t bsz_max = std::min<int64_t>(batch, n);
     const int nb = mlp_grad_blocks(bsz_max);
     NBGS_TRY(mlp->part.reserve((size_t)nb * NPAR));
@@ -711,6 +775,31 @@ nbgs_status nbgs_mlp_train(nbgs_mlp_t mlp, const float *feat, const float *targe
     }
     if (final_loss) *final_loss = last;
     NBGS_HIP(hipStreamSynchronize(mlp->s));
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_mlp_train_collected(nbgs_mlp_t mlp, int32_t epochs, int32_t batch, float lr, uint64_t shuffle_seed,
+                                     double *final_loss) {
+    NBGS_MGUARD(mlp);
+    if (mlp->n_stored < 1) {
+        set_error("no samples collected (nbgs_mlp_collect)");
+        return NBGS_ERR_STATE;
+    }
+    return nbgs_mlp_train(mlp, mlp->store_feat.p, mlp->store_tgt.p, mlp->n_stored, epochs, batch, lr, shuffle_seed,
+                          final_loss);
+}
+
+nbgs_status nbgs_mlp_collected(nbgs_mlp_t mlp, int64_t *n, const float **feat, const float **target) {
+    NBGS_MGUARD(mlp);
+    if (n) *n = mlp->n_stored;
+    if (feat) *feat = mlp->store_feat.p;
+    if (target) *target = mlp->store_tgt.p;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_mlp_clear_collected(nbgs_mlp_t mlp) {
+    NBGS_MGUARD(mlp);
+    mlp->n_stored = 0;
     return NBGS_OK;
 }
 

@@ -3,9 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -33,35 +35,110 @@ void set_error(const char *fmt, ...);
         if (s_ != NBGS_OK) return s_;                                                                           \
     } while (0)
 
-// Bumped by every (re)allocation of a DevBuf: a captured graph holds raw
-// device addresses and stays valid only while no buffer has moved since.
+// Bumped by every (re)allocation or move of a device buffer: a captured graph
+// holds raw device addresses and stays valid only while no buffer has moved
+// since.
 inline std::atomic<uint64_t> g_alloc_generation{0};
 
-// A device allocation that only grows.  Contents are not preserved on growth.
+// A buffer that lives in an Arena and can be told where it moved.
+struct ArenaBuf {
+    virtual void arena_moved(void *p) = 0;
+
+   protected:
+    ~ArenaBuf() = default;
+};
+
+// The device memory of one handle (scene, batch, composite scene, network):
+// a region the caller allocated (a torch byte tensor) from which the handle's
+// buffers are carved, first fit, 256-byte aligned.  The library allocates no
+// device memory of its own.  Host-side bookkeeping only; every buffer is used
+// on the handle's stream, so a released range can be handed out again at
+// once (later work on the stream runs after earlier work).
+class Arena {
+   public:
+    static constexpr size_t kAlign = 256;
+    Arena() = default;
+    Arena(const Arena &) = delete;
+    Arena &operator=(const Arena &) = delete;
+    // an empty arena over [base, base + bytes) (the base is aligned up to kAlign)
+    void reset(void *base, size_t bytes);
+    bool bound() const { return base_ != nullptr; }
+    size_t size() const { return size_; }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+    // nullptr when no free run of that many bytes is left
+    void *alloc(size_t bytes, ArenaBuf *owner);
+    void release(void *p);
+    // Copy every live buffer, packed, into the region [base, base + bytes) on
+    // stream s, tell each one where it went, and continue in that region; the
+    // old region is free once the call returns (it synchronises the stream).
+    // CAPACITY (nothing moved) if the live buffers do not fit.
+    nbgs_status move_to(void *base, size_t bytes, hipStream_t s);
+    // Where an address inside a buffer moved by the last move_to went (the
+    // address itself if it was not inside a moved buffer).
+    const void *relocate(const void *old) const;
+
+   private:
+    char *base_ = nullptr;
+    size_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;                         // offset -> length, coalesced
+    std::map<size_t, std::pair<size_t, ArenaBuf *>> live_;  // offset -> (length, owner)
+    std::vector<std::array<uintptr_t, 3>> moved_;           // old begin, old end, new begin
+};
+
+// The arena that buffers allocated now are carved from (bound by each entry
+// point for the handle it works on).
+inline thread_local Arena *tl_arena = nullptr;
+
+struct ArenaScope {
+    Arena *prev;
+    explicit ArenaScope(Arena *a) : prev(tl_arena) { tl_arena = a; }
+    ~ArenaScope() { tl_arena = prev; }
+    ArenaScope(const ArenaScope &) = delete;
+    ArenaScope &operator=(const ArenaScope &) = delete;
+};
+
+// A device buffer carved from the arena of its handle that only grows.
+// Contents are not preserved on growth.
 template <class T>
-struct DevBuf {
+struct DevBuf final : ArenaBuf {
     T *p = nullptr;
     size_t cap = 0;
+    Arena *owner = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owner) owner->release(p);
         p = nullptr;
         cap = 0;
+        owner = nullptr;
     }
+    void arena_moved(void *np) override { p = static_cast<T *>(np); }
     nbgs_status reserve(size_t n, double slack = 1.25) {
         if (n <= cap && p) return NBGS_OK;
+        Arena *a = owner ? owner : tl_arena;
+        if (!a || !a->bound()) {
+            set_error("no workspace is bound to the handle");
+            return NBGS_ERR_STATE;
+        }
         release();
         size_t want = n < 16 ? 16 : (size_t)((double)n * slack) + 16;
-        hipError_t e = hipMalloc((void **)&p, want * sizeof(T));
-        if (e != hipSuccess) {
-            p = nullptr;
-            set_error("hipMalloc of %zu bytes failed: %s", want * sizeof(T), hipGetErrorString(e));
-            return NBGS_ERR_OUT_OF_MEMORY;
+        void *q = a->alloc(want * sizeof(T), this);
+        if (!q && want > n) {  // without the growth slack
+            want = n < 16 ? 16 : n;
+            q = a->alloc(want * sizeof(T), this);
         }
+        if (!q) {
+            set_error("the workspace (%zu bytes, %zu in use) cannot hold another %zu bytes: give the handle a larger "
+                      "one (nbgs_workspace_query, then nbgs_scene_set_workspace or its composite/network form)",
+                      a->size(), a->used(), want * sizeof(T));
+            return NBGS_ERR_CAPACITY;
+        }
+        p = static_cast<T *>(q);
         cap = want;
+        owner = a;
         g_alloc_generation.fetch_add(1, std::memory_order_relaxed);
         return NBGS_OK;
     }
@@ -151,16 +228,16 @@ nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, u
 nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, uint32_t *keys, uint32_t *ids,
                              hipStream_t s);
 nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
-                         const double *h, int32_t *cell_start, int32_t *cell_end, uint32_t *cell_stamp,
+                         const double *h, int4 *cells,
                          uint32_t stamp, double4 *sxr, int32_t *cellpos, hipStream_t s);
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
-                              const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                              const int4 *cells,
                               uint32_t stamp, int32_t *cnt, int32_t *npart, int32_t *partners,
                               unsigned long long *total, hipStream_t s);
 nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
-                             const int32_t *cell_start, const int32_t *cell_end, const uint32_t *cell_stamp,
+                             const int4 *cells,
                              uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
                              const int32_t *npart, const int32_t *partners, ContactsView c, int64_t nc,
                              hipStream_t s);
@@ -262,6 +339,9 @@ nbgs_status launch_mlp_grad(const unsigned short *fr, const float *w, const floa
 nbgs_status launch_mlp_adam(float *w, const float *g, float *m, float *v, int64_t step, float lr, hipStream_t s);
 const unsigned short *mlp_frag_ptr(nbgs_mlp_t mlp);
 const float *mlp_weight_ptr(nbgs_mlp_t mlp);
+// The network's store of collected training pairs: room for n more (CAPACITY past its size), then taken.
+nbgs_status mlp_store_slot(nbgs_mlp_t mlp, int64_t n, float **feat, float **tgt);
+void mlp_store_commit(nbgs_mlp_t mlp, int64_t n);
 
 constexpr int kSweepBlock = 256;
 

@@ -91,6 +91,8 @@ enum Phase { kDetect = 0, kColour = 1, kInit = 2, kSweeps = 3, kIntegrate = 4, k
 using namespace nbgs;
 
 struct nbgs_scene_s {
+    // device memory of the scene (the caller's workspace); first, so that it outlives every buffer carved from it
+    Arena arena;
     BodiesView b{};
     PlaneSet planes{};
     double lo[3], hi[3];
@@ -109,8 +111,7 @@ struct nbgs_scene_s {
     DevBuf<double> vel64;
     DevBuf<float> vel32;
     // cells
-    DevBuf<int32_t> cell_start, cell_end;
-    DevBuf<uint32_t> cell_stamp;
+    DevBuf<int4> cells;  // per cell (start, end, stamp, -) of its sorted range, read in one 16-byte load
     uint32_t stamp = 0;
     // scratch
     DevBuf<int32_t> radix_hist;
@@ -125,6 +126,7 @@ struct nbgs_scene_s {
     int cur = 0;
     bool table_in_cur = false;
     int64_t nc = 0, n_prev = 0;
+    int64_t nc_needed = -1;  // the contact count the last detection found (reported with CAPACITY)
     DevBuf<int32_t> inc2;
     DevBuf<uint64_t> prio;
     bool prev_colours = false;  // the previous table holds the colours of its contact set
@@ -240,6 +242,9 @@ struct nbgs_scene_s {
     double blk_edge = 0.0;
     bool blk_active = false;
     int32_t n_blk = 0;
+    int32_t blk_grids = 1;     // block grids shifted by 1/blk_grids of an edge (nbgs_set_block_grids)
+    int32_t blk_grid_ids = 0;  // ids (blocks) per grid: n_blk = blk_grids * blk_grid_ids
+    int64_t blk_first_cross = 0;  // first sweep position of the contacts between blocks
     std::vector<int64_t> xcol;       // positions of the cross colours' ranges (size colours + 1)
     std::vector<int64_t> xdyn;       // dynamic contact ends per cross colour
     std::vector<int64_t> xpart_off;  // first partial of every cross colour, after the n_blk block partials
@@ -278,7 +283,10 @@ constexpr int kSmallInts = 16 + 512;
 
 // Scene set-up shared by nbgs_scene_create (one scene) and nbgs_batch_create
 // (n_scenes scenes in one body array; body_off: n_scenes + 1 host offsets).
-nbgs_status scene_create(const nbgs_bodies *bodies, int32_t n_scenes, const int64_t *body_off,
+// Device bytes a scene (or a batch of `scenes` scenes) of n bodies with up to c contacts needs.
+size_t scene_workspace_bytes(int64_t n, int64_t c, int64_t scenes);
+nbgs_status scene_create(void *workspace, size_t workspace_bytes, const nbgs_bodies *bodies, int32_t n_scenes,
+                         const int64_t *body_off,
                          const nbgs_domain *domains, const nbgs_params *params, void *hip_stream, nbgs_scene_t *out);
 // Sweep tuning: the cached choice for this scene's size, else a search over
 // launch shapes on the scene's current contacts whose trial sweeps leave no

@@ -76,6 +76,53 @@ __global__ void __launch_bounds__(kBlock) k_block_local(BodiesView b, const int3
     }
 }
 
+// Block of body i in grid g of `grids` grids shifted by g/grids of an edge:
+// c_a = floor((x_a - lo_a) / e_a + g / grids), modulo nb_a along a periodic
+// axis, clamped to [0, nb_a - 1] in grid 0 and to [0, nb_a] in a shifted grid
+// along another axis; id (c_z M_y + c_y) M_x + c_x.
+__device__ inline int32_t block_in_grid(const BodiesView &b, const Blocks &bl, const int32_t M[3],
+                                        const int32_t periodic[3], int g, int grids, int i) {
+    const double x[3] = {b.x[i], b.y[i], b.z[i]};
+    int64_t c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double f = floor((x[a] - bl.lo[a]) / bl.e[a] + (double)g / (double)grids);
+        if (periodic[a]) {
+            const int64_t q = (int64_t)f % bl.nb[a];
+            c[a] = q < 0 ? q + bl.nb[a] : q;
+        } else {
+            const double top = g == 0 ? (double)(bl.nb[a] - 1) : (double)bl.nb[a];
+            c[a] = (int64_t)fmax(0.0, fmin(f, top));
+        }
+    }
+    return (int32_t)((c[2] * M[1] + c[1]) * M[0] + c[0]);
+}
+
+// Ids of the block-local order over several grids: g B + block for the first
+// grid g whose block holds every dynamic body of the contact, grids B if none.
+__global__ void __launch_bounds__(kBlock) k_block_local_grids(BodiesView b, const int32_t *j1, const int32_t *j2,
+                                                              int64_t nc, Blocks bl, int32_t grids, int32_t Mx,
+                                                              int32_t My, int32_t Mz, int32_t px, int32_t py,
+                                                              int32_t pz, int32_t *id) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    const int32_t M[3] = {Mx, My, Mz}, per[3] = {px, py, pz};
+    const int32_t B = Mx * My * Mz;
+    const int i1 = j1[j], i2 = j2[j];
+    const bool d1 = b.inv_mass[i1] > 0.0;
+    const bool d2 = i2 < b.n && b.inv_mass[i2] > 0.0;
+    int32_t out = grids * B;
+    for (int g = 0; g < grids; ++g) {
+        const int32_t k1 = block_in_grid(b, bl, M, per, g, grids, d1 ? i1 : i2);
+        const int32_t k2 = d1 && d2 ? block_in_grid(b, bl, M, per, g, grids, i2) : k1;
+        if (k1 == k2) {
+            out = g * B + k1;
+            break;
+        }
+    }
+    id[j] = out;
+}
+
 __global__ void __launch_bounds__(kBlock) k_hist(const int32_t *v, int64_t n, int32_t *cnt) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) atomicAdd(&cnt[v[i]], 1);
@@ -87,18 +134,22 @@ __global__ void __launch_bounds__(kBlock) k_fill(int32_t *p, int64_t n, int32_t 
 }
 
 // Contact end e = 2 p + k (k = 0: j1, 1: j2) of sweep position p; its body if
-// dynamic, else nb (sorts after every body).
+// dynamic, else nb (sorts after every body).  The ends of contacts with the id
+// no_slot (the contacts between blocks of the block-local order, swept from
+// global memory) count as not dynamic: they take no slot.
 __device__ inline int32_t end_body(const int32_t *sj1, const int32_t *sj2, int32_t nb, const double *inv_mass,
-                                   uint32_t e) {
+                                   uint32_t e, const int32_t *ssd = nullptr, int32_t no_slot = -1) {
+    if (no_slot >= 0 && ssd[e >> 1] == no_slot) return nb;
     const int32_t b = (e & 1u) ? sj2[e >> 1] : sj1[e >> 1];
     return (b < nb && inv_mass[b] > 0.0) ? b : nb;
 }
 
 __global__ void __launch_bounds__(kBlock) k_ends(const int32_t *sj1, const int32_t *sj2, int64_t nends, int32_t nb,
-                                                 const double *inv_mass, uint32_t *keys, uint32_t *vals) {
+                                                 const double *inv_mass, uint32_t *keys, uint32_t *vals,
+                                                 const int32_t *ssd, int32_t no_slot) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= nends) return;
-    keys[e] = (uint32_t)end_body(sj1, sj2, nb, inv_mass, (uint32_t)e);
+    keys[e] = (uint32_t)end_body(sj1, sj2, nb, inv_mass, (uint32_t)e, ssd, no_slot);
     vals[e] = (uint32_t)e;
 }
 
@@ -111,18 +162,18 @@ __global__ void __launch_bounds__(kBlock) k_end_tiles(const uint32_t *vals, int6
 // First end of every (subdomain, dynamic body) group, ends sorted by (subdomain, body).
 __global__ void __launch_bounds__(kBlock) k_slot_flags(const uint32_t *vals, int64_t n, const int32_t *sj1,
                                                        const int32_t *sj2, const int32_t *ssd, int32_t nb,
-                                                       const double *inv_mass, int32_t *flags) {
+                                                       const double *inv_mass, int32_t *flags, int32_t no_slot) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const uint32_t e = vals[i];
-    const int32_t b = end_body(sj1, sj2, nb, inv_mass, e);
+    const int32_t b = end_body(sj1, sj2, nb, inv_mass, e, ssd, no_slot);
     int f = 0;
     if (b < nb) {
         if (i == 0) {
             f = 1;
         } else {
             const uint32_t e0 = vals[i - 1];
-            f = (ssd[e0 >> 1] != ssd[e >> 1] || end_body(sj1, sj2, nb, inv_mass, e0) != b) ? 1 : 0;
+            f = (ssd[e0 >> 1] != ssd[e >> 1] || end_body(sj1, sj2, nb, inv_mass, e0, ssd, no_slot) != b) ? 1 : 0;
         }
     }
     flags[i] = f;
@@ -131,24 +182,25 @@ __global__ void __launch_bounds__(kBlock) k_slot_flags(const uint32_t *vals, int
 __global__ void __launch_bounds__(kBlock) k_slot_write(const uint32_t *vals, int64_t n, const int32_t *sj1,
                                                        const int32_t *sj2, const int32_t *ssd, int32_t nb,
                                                        const double *inv_mass, const int32_t *flags,
-                                                       const int32_t *ex, int32_t *slot_body, int32_t *slot_sdom) {
+                                                       const int32_t *ex, int32_t *slot_body, int32_t *slot_sdom,
+                                                       int32_t no_slot) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n || !flags[i]) return;
     const uint32_t e = vals[i];
-    slot_body[ex[i]] = end_body(sj1, sj2, nb, inv_mass, e);
+    slot_body[ex[i]] = end_body(sj1, sj2, nb, inv_mass, e, ssd, no_slot);
     slot_sdom[ex[i]] = ssd[e >> 1];
 }
 
-// Local slot of every contact end (-1: wall or static body).
+// Local slot of every contact end (-1: wall, static body, or a contact that takes no slot).
 __global__ void __launch_bounds__(kBlock) k_end_slots(const uint32_t *vals, int64_t n, const int32_t *sj1,
                                                       const int32_t *sj2, const int32_t *ssd, int32_t nb,
                                                       const double *inv_mass, const int32_t *flags,
                                                       const int32_t *ex, const int32_t *tile_slot_off,
-                                                      int16_t *ls) {
+                                                      int16_t *ls, int32_t no_slot) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const uint32_t e = vals[i];
-    const int32_t b = end_body(sj1, sj2, nb, inv_mass, e);
+    const int32_t b = end_body(sj1, sj2, nb, inv_mass, e, ssd, no_slot);
     ls[e] = (int16_t)(b < nb ? ex[i] + flags[i] - 1 - tile_slot_off[ssd[e >> 1]] : -1);
 }
 
@@ -528,10 +580,10 @@ template <class T, int MODE>
 __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t nb, T *vel, T mu, T relax,
                                                           const int64_t *tile_off, const int32_t *tile_slot_off,
                                                           const int32_t *slot_body, const int32_t *blk_cs,
-                                                          double *partials, const int32_t *ctrl) {
+                                                          double *partials, const int32_t *ctrl, int32_t id0) {
     if (MODE == 1 && ctrl[0]) return;  // an earlier sweep met the target (uniform over the grid)
     extern __shared__ __align__(16) unsigned char smem[];
-    const int s = blockIdx.x;
+    const int s = id0 + (int)blockIdx.x;  // this launch's blocks: ids id0 .. id0 + gridDim.x - 1
     const int64_t c0 = tile_off[s];
     const int s0 = tile_slot_off[s], ns = tile_slot_off[s + 1] - s0;
     T *Vs = reinterpret_cast<T *>(smem);  // [8][ns]: v'x v'y v'z w'x w'y w'z 1/m 1/I
@@ -706,12 +758,32 @@ nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed) {
     Blocks bl;
     int64_t nblocks = 1;
     NBGS_TRY(make_blocks(sc, sc->blk_edge, bl, nblocks));
-    sc->n_blk = (int32_t)nblocks;
-    sc->n_sub = (int32_t)nblocks + 1;
     const int64_t nc = sc->nc;
     NBGS_TRY(sc->sdom.reserve((size_t)nc + 1));
     const ContactsView c = sc->cb[sc->cur].view();
-    k_block_local<<<grid_for(nc), kBlock, 0, s>>>(sc->b, c.j1, c.j2, nc, bl, (int32_t)nblocks, sc->sdom.p);
+    if (sc->blk_grids <= 1) {
+        sc->n_blk = (int32_t)nblocks;
+        sc->blk_grid_ids = (int32_t)nblocks;
+        k_block_local<<<grid_for(nc), kBlock, 0, s>>>(sc->b, c.j1, c.j2, nc, bl, (int32_t)nblocks, sc->sdom.p);
+    } else {
+        // a shifted grid has one more block along a non-periodic axis
+        int32_t M[3];
+        int64_t B = 1;
+        for (int a = 0; a < 3; ++a) {
+            M[a] = bl.nb[a] + (sc->periodic[a] ? 0 : 1);
+            B *= M[a];
+        }
+        if ((int64_t)sc->blk_grids * B > (1 << 23) - 1) {
+            set_error("%lld blocks in %d grids are too many: use a larger edge", (long long)B, sc->blk_grids);
+            return NBGS_ERR_INVALID_ARG;
+        }
+        sc->n_blk = sc->blk_grids * (int32_t)B;
+        sc->blk_grid_ids = (int32_t)B;
+        k_block_local_grids<<<grid_for(nc), kBlock, 0, s>>>(sc->b, c.j1, c.j2, nc, bl, sc->blk_grids, M[0], M[1], M[2],
+                                                            sc->periodic[0], sc->periodic[1], sc->periodic[2],
+                                                            sc->sdom.p);
+    }
+    sc->n_sub = sc->n_blk + 1;
     NBGS_HIP(hipGetLastError());
     // every body's block, compared with the last step's (bodies without local contacts count too: they decide the
     // slots); the number of changes is added to changed
@@ -727,6 +799,12 @@ nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed) {
     sc->bblk_nblocks = nblocks;
     return NBGS_OK;
 }
+
+static nbgs_status cross_colours(nbgs_scene_t sc, const int32_t *col, const int32_t *sj1, const int32_t *sj2,
+                                 int64_t xb, int64_t xe);
+template <class T>
+static nbgs_status prepare_impl(nbgs_scene_t sc, int32_t no_slot = -1, int values_per_slot = 14,
+                                bool body_lists = true);
 
 // Block-local order, per step: contact ranges of the ids (the sweep record
 // is sorted by id), the slots -- every dynamic body of a block, bodies sorted
@@ -808,7 +886,17 @@ static nbgs_status block_prepare_impl(nbgs_scene_t sc) {
     k_blk_colour_starts<<<(unsigned)nblk, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p);
     NBGS_HIP(hipGetLastError());
     // colours of the contacts between blocks (the last id's range)
-    const int64_t xb = toff[(size_t)nblk], xe = toff[(size_t)nsub];
+    NBGS_TRY(cross_colours(sc, sw.col.p, sw.j1.p, sw.j2.p, toff[(size_t)nblk], toff[(size_t)nsub]));
+    sc->blk_dyn_local = sc->n_slots;
+    sc->blk_n_local = toff[(size_t)nblk];
+    return NBGS_OK;
+}
+
+// Colour ranges and dynamic ends of the contacts between blocks, sweep positions [xb, xe), to the host.
+static nbgs_status cross_colours(nbgs_scene_t sc, const int32_t *col, const int32_t *sj1, const int32_t *sj2,
+                                 int64_t xb, int64_t xe) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
     NBGS_TRY(sc->xcol_d.reserve(kMaxCol + 1 + kMaxCol));
     NBGS_TRY(sc->xncol_d.reserve(1));
     std::vector<int64_t> init((size_t)kMaxCol + 1, xe);
@@ -817,8 +905,8 @@ static nbgs_status block_prepare_impl(nbgs_scene_t sc) {
     NBGS_HIP(hipMemsetAsync(sc->xncol_d.p, 0, sizeof(int32_t), s));
     if (xe > xb) {
         const unsigned g = grid_for(xe - xb);
-        k_range_colours<<<g, kBlock, 0, s>>>(sw.col.p, xb, xe, sc->xcol_d.p, sc->xncol_d.p);
-        k_range_dyn<<<g, kBlock, 0, s>>>(sw.j1.p, sw.j2.p, sw.col.p, xb, xe, N, sc->b.inv_mass,
+        k_range_colours<<<g, kBlock, 0, s>>>(col, xb, xe, sc->xcol_d.p, sc->xncol_d.p);
+        k_range_dyn<<<g, kBlock, 0, s>>>(sj1, sj2, col, xb, xe, N, sc->b.inv_mass,
                                           reinterpret_cast<unsigned long long *>(sc->xcol_d.p + kMaxCol + 1));
         NBGS_HIP(hipGetLastError());
     }
@@ -832,13 +920,39 @@ static nbgs_status block_prepare_impl(nbgs_scene_t sc) {
     sc->xcol.assign(xc.begin(), xc.begin() + ncol);
     sc->xcol.push_back(xe);
     sc->xdyn.assign(xc.begin() + kMaxCol + 1, xc.begin() + kMaxCol + 1 + ncol);
-    sc->blk_dyn_local = sc->n_slots;
-    sc->blk_n_local = xb;
     return NBGS_OK;
 }
 
+// Block-local order over several grids, per step: the slot tables built from
+// the ends of the local contacts (every dynamic body a block's local contacts
+// touch; the contacts between blocks take none), each block's colour
+// boundaries, and the colour ranges of the contacts between blocks.
 template <class T>
-static nbgs_status prepare_impl(nbgs_scene_t sc) {
+static nbgs_status block_grids_prepare_impl(nbgs_scene_t sc) {
+    hipStream_t s = sc->s;
+    const int32_t nblk = sc->n_blk;
+    SweepBuf<T> &sw = sc->precision_used == NBGS_FP32_SWEEP ? *reinterpret_cast<SweepBuf<T> *>(&sc->sw32)
+                                                            : *reinterpret_cast<SweepBuf<T> *>(&sc->sw64);
+    NBGS_TRY(prepare_impl<T>(sc, nblk, 8, false));
+    NBGS_TRY(sc->blk_cs.reserve((size_t)nblk * (kMaxCol + 2)));
+    k_blk_colour_starts<<<(unsigned)nblk, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p);
+    NBGS_HIP(hipGetLastError());
+    NBGS_TRY(cross_colours(sc, sw.col.p, sw.j1.p, sw.j2.p, sc->blk_first_cross, sc->nc));
+    sc->blk_dyn_local = sc->n_slots;
+    sc->blk_n_local = sc->blk_first_cross;
+    return NBGS_OK;
+}
+
+static nbgs_status body_slot_lists(nbgs_scene_t sc, int64_t nslots);
+
+// Slot tables of the subdomain solver (no_slot = -1, 14 values per slot in
+// LDS, per-body slot lists for the correction reduction), also used for the
+// block-local order over several grids (no_slot = the id of the contacts
+// between blocks, 8 values per slot, no per-body lists): per id its contact
+// range, per slot its body and id, per id its slot range, per contact end its
+// local slot.
+template <class T>
+static nbgs_status prepare_impl(nbgs_scene_t sc, int32_t no_slot, int values_per_slot, bool body_lists) {
     hipStream_t s = sc->s;
     const int64_t nc = sc->nc;
     const int32_t N = sc->b.n;
@@ -860,7 +974,7 @@ static nbgs_status prepare_impl(nbgs_scene_t sc) {
     if ((size_t)radix_hist_entries(ne) > sc->radix_hist.cap) NBGS_TRY(sc->radix_hist.reserve(radix_hist_entries(ne)));
     const size_t need_tmp2 = exclusive_scan_tmp_bytes((int64_t)radix_hist_entries(ne));
     if (need_tmp2 > sc->scan_tmp.cap) NBGS_TRY(sc->scan_tmp.reserve(need_tmp2));
-    k_ends<<<grid_for(ne), kBlock, 0, s>>>(sj1, sj2, ne, N, sc->b.inv_mass, sc->ekeys.p, sc->evals.p);
+    k_ends<<<grid_for(ne), kBlock, 0, s>>>(sj1, sj2, ne, N, sc->b.inv_mass, sc->ekeys.p, sc->evals.p, ssd, no_slot);
     NBGS_HIP(hipGetLastError());
     auto bits_for = [](int64_t n) {
         int b = 0;
@@ -883,7 +997,7 @@ static nbgs_status prepare_impl(nbgs_scene_t sc) {
     // slots
     NBGS_TRY(sc->eflags.reserve((size_t)ne + 1));
     NBGS_TRY(sc->eex.reserve((size_t)ne + 1));
-    k_slot_flags<<<grid_for(ne), kBlock, 0, s>>>(svals, ne, sj1, sj2, ssd, N, sc->b.inv_mass, sc->eflags.p);
+    k_slot_flags<<<grid_for(ne), kBlock, 0, s>>>(svals, ne, sj1, sj2, ssd, N, sc->b.inv_mass, sc->eflags.p, no_slot);
     NBGS_HIP(hipGetLastError());
     NBGS_TRY(exclusive_scan_i32(sc->eflags.p, sc->eex.p, ne, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_TRY(scene_sync_small(sc, 0, 1));
@@ -892,7 +1006,7 @@ static nbgs_status prepare_impl(nbgs_scene_t sc) {
     NBGS_TRY(sc->slot_body.reserve((size_t)nslots + 1));
     NBGS_TRY(sc->slot_sdom.reserve((size_t)nslots + 1));
     k_slot_write<<<grid_for(ne), kBlock, 0, s>>>(svals, ne, sj1, sj2, ssd, N, sc->b.inv_mass, sc->eflags.p, sc->eex.p,
-                                                 sc->slot_body.p, sc->slot_sdom.p);
+                                                 sc->slot_body.p, sc->slot_sdom.p, no_slot);
     NBGS_HIP(hipGetLastError());
     NBGS_TRY(sc->tile_scnt.reserve((size_t)nsub + 1));
     NBGS_TRY(sc->tile_slot_off.reserve((size_t)nsub + 1));
@@ -903,15 +1017,48 @@ static nbgs_status prepare_impl(nbgs_scene_t sc) {
                                 sc->scan_tmp.cap, s));
     NBGS_TRY(sw.ls.reserve((size_t)ne + 1));
     k_end_slots<<<grid_for(ne), kBlock, 0, s>>>(svals, ne, sj1, sj2, ssd, N, sc->b.inv_mass, sc->eflags.p, sc->eex.p,
-                                                sc->tile_slot_off.p, sw.ls.p);
+                                                sc->tile_slot_off.p, sw.ls.p, no_slot);
     NBGS_HIP(hipGetLastError());
-    // per body its slots in ascending subdomain (slots are numbered in (subdomain, body) order)
-    for (DevBuf<uint32_t> *b : {&sc->bkeys, &sc->bvals, &sc->bkeys2, &sc->bvals2})
-        NBGS_TRY(b->reserve((size_t)nslots + 1));
-    if (nslots == 0) {
+    if (nslots == 0 && body_lists) {
         set_error("no dynamic body in any subdomain");
         return NBGS_ERR_STATE;
     }
+    if (body_lists) NBGS_TRY(body_slot_lists(sc, nslots));
+    // tile sizes against the kernel's limits
+    std::vector<int32_t> cnt((size_t)nsub), scnt((size_t)nsub);
+    NBGS_HIP(hipMemcpyAsync(cnt.data(), sc->tile_cnt.p, sizeof(int32_t) * nsub, hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipMemcpyAsync(scnt.data(), sc->tile_scnt.p, sizeof(int32_t) * nsub, hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipStreamSynchronize(s));
+    int32_t max_slots = 0;
+    for (int32_t t = 0; t < nsub; ++t) max_slots = std::max(max_slots, scnt[(size_t)t]);
+    const size_t lds = (size_t)max_slots * values_per_slot * sizeof(T);
+    if (lds > 60 * 1024) {
+        set_error("a %s touches %d bodies (%zu bytes of LDS); use a smaller %s edge", body_lists ? "subdomain" : "block",
+                  max_slots, lds, body_lists ? "subdomain" : "block");
+        return NBGS_ERR_CAPACITY;
+    }
+    sc->max_slots = max_slots;
+    // 64-bit contact offsets of the tiles
+    std::vector<int64_t> toff((size_t)nsub + 1, 0);
+    for (int32_t t = 0; t < nsub; ++t) toff[(size_t)t + 1] = toff[(size_t)t] + cnt[(size_t)t];
+    NBGS_HIP(hipMemcpyAsync(sc->tile_off.p, toff.data(), sizeof(int64_t) * (nsub + 1), hipMemcpyHostToDevice, s));
+    NBGS_HIP(hipStreamSynchronize(s));  // toff is a host temporary
+    sc->blk_first_cross = toff[(size_t)nsub - 1];
+    return NBGS_OK;
+}
+
+// Per body its slots in ascending subdomain (slots are numbered in (subdomain,
+// body) order), for the subdomain solver's correction reduction.
+static nbgs_status body_slot_lists(nbgs_scene_t sc, int64_t nslots) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    auto bits_for = [](int64_t n) {
+        int b = 0;
+        while (((int64_t)1 << b) < n) ++b;
+        return b;
+    };
+    for (DevBuf<uint32_t> *b : {&sc->bkeys, &sc->bvals, &sc->bkeys2, &sc->bvals2})
+        NBGS_TRY(b->reserve((size_t)nslots + 1));
     k_copy_u32<<<grid_for(nslots), kBlock, 0, s>>>(sc->slot_body.p, nslots, sc->bkeys.p);
     k_iota<<<grid_for(nslots), kBlock, 0, s>>>(sc->bvals.p, nslots);
     NBGS_HIP(hipGetLastError());
@@ -927,24 +1074,6 @@ static nbgs_status prepare_impl(nbgs_scene_t sc) {
     NBGS_HIP(hipGetLastError());
     NBGS_TRY(exclusive_scan_i32(sc->body_cnt.p, sc->body_slot_off.p, (int64_t)N + 1, nullptr, sc->scan_tmp.p,
                                 sc->scan_tmp.cap, s));
-    // tile sizes against the kernel's limits
-    std::vector<int32_t> cnt((size_t)nsub), scnt((size_t)nsub);
-    NBGS_HIP(hipMemcpyAsync(cnt.data(), sc->tile_cnt.p, sizeof(int32_t) * nsub, hipMemcpyDeviceToHost, s));
-    NBGS_HIP(hipMemcpyAsync(scnt.data(), sc->tile_scnt.p, sizeof(int32_t) * nsub, hipMemcpyDeviceToHost, s));
-    NBGS_HIP(hipStreamSynchronize(s));
-    int32_t max_slots = 0;
-    for (int32_t t = 0; t < nsub; ++t) max_slots = std::max(max_slots, scnt[(size_t)t]);
-    const size_t lds = (size_t)max_slots * 14 * sizeof(T);
-    if (lds > 60 * 1024) {
-        set_error("a subdomain touches %d bodies (%zu bytes of LDS); use a smaller subdomain edge", max_slots, lds);
-        return NBGS_ERR_CAPACITY;
-    }
-    sc->max_slots = max_slots;
-    // 64-bit contact offsets of the tiles
-    std::vector<int64_t> toff((size_t)nsub + 1, 0);
-    for (int32_t t = 0; t < nsub; ++t) toff[(size_t)t + 1] = toff[(size_t)t] + cnt[(size_t)t];
-    NBGS_HIP(hipMemcpyAsync(sc->tile_off.p, toff.data(), sizeof(int64_t) * (nsub + 1), hipMemcpyHostToDevice, s));
-    NBGS_HIP(hipStreamSynchronize(s));  // toff is a host temporary
     return NBGS_OK;
 }
 
@@ -954,6 +1083,10 @@ nbgs_status subdomain_prepare(nbgs_scene_t sc) {
 }
 
 nbgs_status block_prepare(nbgs_scene_t sc) {
+    if (sc->blk_grids > 1) {
+        if (sc->precision_used == NBGS_FP32_SWEEP) return block_grids_prepare_impl<float>(sc);
+        return block_grids_prepare_impl<double>(sc);
+    }
     if (sc->precision_used == NBGS_FP32_SWEEP) return block_prepare_impl<float>(sc);
     return block_prepare_impl<double>(sc);
 }
@@ -979,18 +1112,23 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
     v.py = sw.py.p;
     v.pz = sw.pz.p;
     const size_t lds = (size_t)std::max(sc->max_slots, 1) * 8 * sizeof(T);
-    const unsigned grid = (unsigned)sc->n_blk;
     const T mu = (T)sc->p.mu, relax = (T)sc->p.relax;
-    const int32_t *slot_body = reinterpret_cast<const int32_t *>(sc->body_slots);  // bodies sorted by block
-    if (mode == 0)
-        k_blk_pass<T, 0><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
-                                                         sc->tile_slot_off.p, slot_body, sc->blk_cs.p, sc->partials.p,
-                                                         sc->ctrl());
-    else
-        k_blk_pass<T, 1><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
-                                                         sc->tile_slot_off.p, slot_body, sc->blk_cs.p, sc->partials.p,
-                                                         sc->ctrl());
-    NBGS_HIP(hipGetLastError());
+    // one grid: every dynamic body of a block, sorted by block; several: the bodies the local contacts touch
+    const int32_t *slot_body = sc->blk_grids > 1 ? sc->slot_body.p : reinterpret_cast<const int32_t *>(sc->body_slots);
+    // one launch per grid: a grid's blocks share no dynamic body, the next grid sees their results
+    const int32_t B = sc->blk_grid_ids;
+    for (int32_t id0 = 0; id0 < sc->n_blk; id0 += B) {
+        const unsigned grid = (unsigned)std::min(B, sc->n_blk - id0);
+        if (mode == 0)
+            k_blk_pass<T, 0><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
+                                                             sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
+                                                             sc->partials.p, sc->ctrl(), id0);
+        else
+            k_blk_pass<T, 1><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
+                                                             sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
+                                                             sc->partials.p, sc->ctrl(), id0);
+        NBGS_HIP(hipGetLastError());
+    }
     return NBGS_OK;
 }
 

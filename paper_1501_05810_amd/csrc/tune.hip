@@ -125,6 +125,7 @@ nbgs_status trial(nbgs_scene_t sc, const SweepTune &t, int32_t sweeps, const Sav
 }  // namespace
 
 nbgs_status scene_autotune(nbgs_scene_t sc, int32_t sweeps, nbgs_tuning *chosen, double *best_ms) {
+    ArenaScope arena_scope(&sc->arena);  // the trial copies are carved from the scene's workspace
     if (sc->state != 1) {
         set_error("autotuning needs a detected, not yet solved step");
         return NBGS_ERR_STATE;

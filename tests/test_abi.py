@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     # the binding wraps exactly the declared set
     assert sorted(n for n, _, _ in nb._SIGNATURES) == _declared()
-    assert nb.nbgs_abi_version() == 1
+    assert nb.nbgs_abi_version() == 2
 
 
 def test_binding_has_no_cpu_fallback(tmp_path, monkeypatch):
@@ -90,7 +90,8 @@ def test_batch_create_rejects_bad_arguments(case):
     n = 0 if case == "no scenes" else k
     arr = (C.c_int64 * 4)(*offs)
     out = C.c_void_p()
-    st = L.nbgs_batch_create(n, arr, C.byref(_dummy_bodies(nb, 12)), doms, pars, None, None, C.byref(out))
+    st = L.nbgs_batch_create(n, arr, C.byref(_dummy_bodies(nb, 12)), doms, pars, None, None, 0, None,
+                             C.byref(out))
     want = 8 if case == "learned" else 1  # UNSUPPORTED, INVALID_ARG
     assert st == want, (case, st, nb.nbgs_last_error())
     assert not out.value
@@ -107,3 +108,45 @@ def test_tuning_rejects_unsupported_shapes():
     t = nb.nbgs_tuning(block=96, contacts_per_thread=1, xcd_remap=1, nontemporal=0, full_store=0, persistent=0,
                        graph=0)
     assert nb.lib().nbgs_set_tuning(None, 0, C.byref(t)) == 1
+
+
+def test_workspace_queries_are_host_only_and_grow_with_the_workload():
+    """The workspace sizes are pure host computations (no device needed): linear in bodies and contacts, one cell
+    table more per batched scene, and the network's in the samples its store holds."""
+    import paper_1501_05810_amd as nb
+
+    q = nb.nbgs_workspace_query
+    base = q(1000, 0)
+    assert base > 16 << 20
+    assert q(2000, 0) - base == pytest.approx(1.1 * 613 * 1000, abs=2)
+    assert q(1000, 5000) - base == pytest.approx(1.1 * 1000 * 5000, abs=2)
+    assert nb.nbgs_batch_workspace_query(3, 1000, 0) - base == pytest.approx(1.1 * 2 * (65536 * 20 + 4096), abs=4)
+    m0, m1 = nb.nbgs_mlp_workspace_query(0), nb.nbgs_mlp_workspace_query(1 << 20)
+    assert m1 - m0 == pytest.approx(1.1 * 64 * (1 << 20), abs=2)
+    with pytest.raises(nb.NbgsError):
+        q(-1, 0)
+
+
+def test_scene_create_needs_a_workspace():
+    """Without a workspace (NULL, or smaller than one aligned block) the scene is refused before any device work:
+    the library allocates no device memory of its own."""
+    import ctypes as C
+
+    import paper_1501_05810_amd as nb
+
+    doms, pars = _domains_params(nb, 1)
+    out = C.c_void_p()
+    L = nb.lib()
+    for ws, size in ((None, 0), (None, 1 << 20), (0x100000, 100)):
+        st = L.nbgs_scene_create(C.byref(_dummy_bodies(nb, 12)), C.byref(doms[0]), C.byref(pars[0]), ws, size,
+                                 None, C.byref(out))
+        assert st == 1 and not out.value and "workspace" in nb.nbgs_last_error()
+
+
+def test_no_device_allocation_in_the_library_sources():
+    """Every device buffer is carved from the caller's workspace: no allocation call in the library's sources."""
+    pkg = os.path.join(ROOT, "paper_1501_05810_amd", "csrc")
+    pat = re.compile(r"\bhip(Malloc|MallocAsync|MallocManaged|ExtMallocWithFlags|MallocPitch|Malloc3D|Free|FreeAsync)\s*\(")
+    for f in sorted(os.listdir(pkg)):
+        txt = open(os.path.join(pkg, f)).read()
+        assert not pat.search(txt), f

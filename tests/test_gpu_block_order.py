@@ -41,21 +41,26 @@ def _with_static(sc):
     return sc
 
 
+@pytest.mark.parametrize("grids", [1, 4])
 @pytest.mark.parametrize("name", list(CASES))
-def test_block_order_steps_match_oracle(name):
+def test_block_order_steps_match_oracle(name, grids):
     nb = _nb()
     make, edge, relax = CASES[name]
     sc = make()
     sc.relax = relax
-    g = nb.GpuScene(sc.copy()).set_block_order(edge)
-    w = oracle.World(sc.copy()).set_block_order(edge)
+    g = nb.GpuScene(sc.copy()).set_block_order(edge, grids=grids)
+    w = oracle.World(sc.copy()).set_block_order(edge, grids=grids)
     steps = 2 if name == "dense tile" else 3
     for step in range(steps):
         g.step(12)
         w.step(12, grid=True)
         v = w.view()
         nblocks = v["n_sub"] - 1
-        assert 0 < np.sum(v["sdom"] < nblocks) < len(v["sdom"]), "both kinds of contacts occur"
+        if grids == 1:
+            assert 0 < np.sum(v["sdom"] < nblocks) < len(v["sdom"]), "both kinds of contacts occur"
+        else:
+            # several grids take part (the later ones hold what grid 0 cuts)
+            assert len(set((v["sdom"][v["sdom"] < nblocks] // (nblocks // grids)).tolist())) >= 2
         c = g.contacts()
         assert np.array_equal(c["key"], v["key"]), step
         assert np.array_equal(c["colour"], v["colour"]), step
@@ -68,16 +73,17 @@ def test_block_order_steps_match_oracle(name):
     g.close()
 
 
+@pytest.mark.parametrize("grids", [1, 4])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_block_order_limits_equal_the_classic_sweep(precision):
+def test_block_order_limits_equal_the_classic_sweep(precision, grids):
     """One block over the whole box (every contact local) and blocks too small to hold two touching centres in a
-    scene without walls (every contact between blocks) both sweep in the classic order."""
+    scene without walls (every contact between blocks) both sweep in the classic order, with one grid or four."""
     nb = _nb()
     for sc, edge in ((sg.packed_cluster(64, counts=(10, 8, 6)), 1e6),
                      (sg.random_cluster(6, 400, box=9.0, periodic=(True, True, True), overlap=0.05), 0.3)):
         runs = []
         for e in (0.0, edge):
-            g = nb.GpuScene(sc.copy(), precision=precision).set_block_order(e)
+            g = nb.GpuScene(sc.copy(), precision=precision).set_block_order(e, grids=grids)
             for _ in range(2):
                 g.step(15)
             runs.append((g.contacts()["P"], g.state()["vel"]))
@@ -191,3 +197,25 @@ def test_colouring_follows_ids_when_pairs_stay():
         assert np.array_equal(c["key"], v["key"]) and np.array_equal(c["colour"], v["colour"]), step
         assert np.array_equal(g.state()["pos"], w.sc.pos), step
     assert len(ids_seen) >= 3  # local, mixed, local in the next block
+
+
+def test_block_grids_errors_and_fp32():
+    nb = _nb()
+    sc = sg.packed_cluster(67, counts=(10, 10, 6))
+    g = nb.GpuScene(sc.copy())
+    for bad in (0, 9, -1):
+        with pytest.raises(nb.NbgsError):
+            nb.nbgs_set_block_grids(g.handle, bad)
+    g.close()
+    # FP32 sweeps in the four-grid order at the FP32 bar against the oracle's FP64 run of the same order
+    g32 = nb.GpuScene(sc.copy(), precision="fp32").set_block_order(2.5, grids=4)
+    g32.detect()
+    g32.solve(25)
+    w = oracle.World(sc.copy()).set_block_order(2.5, grids=4)
+    w.detect(grid=True)
+    w.solve(25)
+    v = w.view()
+    c = g32.contacts()
+    assert np.array_equal(c["key"], v["key"]) and np.array_equal(c["colour"], v["colour"])
+    assert np.abs(c["P"] - v["P"]).max() <= 2e-4 * np.abs(v["P"]).max()
+    g32.close()

@@ -188,17 +188,17 @@ def test_learned_start_and_judge_match_oracle():
         assert np.array_equal(c["key"], v["key"])
         np.testing.assert_array_equal(c["P"], v["P"])  # the re-projected previous impulses
         lstart = g.learned_start()
-        info = g.warm_start_info()
         # the oracle's judge on the same state: both candidates
         r_prev, _, _, _ = oracle.jacobi_residual(ref, v, v["order"], v["P"])
         r_learn, _, _, _ = oracle.jacobi_residual(ref, v, v["order"], lstart)
+        g.solve(12)  # the judge runs at the start of the solve
+        info = g.warm_start_info()
         assert info["r_previous"] == pytest.approx(r_prev, rel=1e-12, abs=1e-300)
         assert info["r_learned"] == pytest.approx(r_learn, rel=1e-12, abs=1e-300)
         assert info["choice"] == (1 if info["r_learned"] <= info["r_previous"] else 0)
         seen_choice.add(info["choice"])
         start = lstart if info["choice"] == 1 else v["P"]
         w.set_impulses(start)
-        g.solve(12)
         w.solve(12)
         # decode: the network on the step's own features (after the solve they are still the detect's)
         feat, _ = g.training_data()
