@@ -27,7 +27,8 @@
  *     and must outlive the handle.  A detection whose contacts exceed the
  *     workspace's contact capacity returns CAPACITY with the contact count in
  *     nbgs_stats.n_contacts and leaves the scene as it was: query the size for
- *     that count, allocate, nbgs_scene_set_workspace, detect again.
+ *     that count, allocate, nbgs_scene_set_workspace, detect again.  (Every
+ *     other CAPACITY, a limit that no workspace lifts, reports -1 there.)
  *   - All device work is enqueued on the stream passed to nbgs_scene_create
  *     (NULL = the legacy default stream).  Entry points that return counts in a
  *     host nbgs_stats synchronise that stream before returning.
@@ -141,7 +142,8 @@ const char *nbgs_last_error(void);
 /* Bytes of device workspace a scene of n_bodies bodies with up to
  * contact_capacity contacts needs, in every sweep order, precision and warm
  * start (an upper bound: per body 613 B, per contact 1,000 B, plus a cell
- * table of 2^16 cells, 16 MiB, and ten per cent).  params [host] may be NULL
+ * table of 2^16 cells, 16 MiB, and ten per cent), a multiple of 256 (all of
+ * it usable from a 256-byte aligned base).  params [host] may be NULL
  * (checked when given).  *bytes [host].  Pure host computation: no device is
  * touched.  Errors: INVALID_ARG. */
 nbgs_status nbgs_workspace_query(int64_t n_bodies, int64_t contact_capacity, const nbgs_params *params,
@@ -192,7 +194,8 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t scene, const nbgs_params *params)
  * n_contacts of the scene is known after the next synchronising call).
  * Errors: CAPACITY (more contacts than the workspace holds, found before
  * any list is written: stats->n_contacts = the contact count, the scene
- * unchanged, see nbgs_scene_set_workspace; more than 255 colours; more than
+ * unchanged, see nbgs_scene_set_workspace; for every other CAPACITY, which
+ * no workspace can lift, stats->n_contacts = -1: more than 255 colours; more than
  * 2^31 - 256 contacts, counted in 64 bits before any list is sized; a body
  * meeting more than 2^18 hull candidates in its 27 cells, which happens when
  * one hull, e.g. of a diverged state, makes the cell grid too coarse; in
@@ -619,7 +622,8 @@ nbgs_status nbgs_composite_workspace_query(int64_t n_bodies, int64_t n_elements,
  * nbgs_scene_create), UNSUPPORTED (precision other than NBGS_FP64, learned
  * warm start), CAPACITY, OUT_OF_MEMORY (host), DEVICE.  Release the handle
  * with nbgs_composite_destroy.  nbgs_composite_detect returns CAPACITY with
- * the contact count in stats->n_contacts when the workspace holds fewer. */
+ * the contact count in stats->n_contacts when the workspace holds fewer, and
+ * with stats->n_contacts = -1 for the limits no workspace lifts. */
 nbgs_status nbgs_composite_create(const nbgs_composite_bodies *bodies, const nbgs_domain *domain,
                                   const nbgs_params *params, void *workspace, size_t workspace_bytes,
                                   void *hip_stream, nbgs_composite_t *out);

@@ -245,7 +245,13 @@ def _capacity_retry(h: int, call):
     grow it (query, allocate, set_workspace) and run it once more."""
     code, st = call()
     if code == NBGS_ERR_CAPACITY and h in _GROWERS and 0 <= int(st.n_contacts) <= _MAX_CONTACTS:
-        if _GROWERS[h](int(st.n_contacts)):
+        msg = nbgs_last_error()
+        try:
+            grown = _GROWERS[h](int(st.n_contacts))
+        except RuntimeError as e:  # the device cannot hold the larger workspace: the library's refusal stands
+            raise NbgsError(NBGS_ERR_CAPACITY, f"{msg} (a workspace for {int(st.n_contacts)} contacts could not be "
+                                               f"allocated: {e})") from None
+        if grown:
             code, st = call()
     return code, st
 

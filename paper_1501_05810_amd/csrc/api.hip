@@ -153,7 +153,7 @@ size_t scene_workspace_bytes(int64_t n, int64_t c, int64_t scenes) {
     const double per_body = 613.0, per_contact = 1000.0, per_scene = 65536.0 * 16.0 * 1.25 + 4096.0;
     const double fixed = 16.0 * 1024.0 * 1024.0;
     const double b = 1.1 * (per_body * (double)n + per_contact * (double)c + per_scene * (double)scenes + fixed);
-    return (size_t)b;
+    return ((size_t)b + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1);  // all of it usable at an aligned base
 }
 
 nbgs_status check_params(const nbgs_params *p) {
@@ -456,7 +456,6 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     unsigned long long total64 = 0, over = 0;
     std::memcpy(&total64, sc->pinned + 4, sizeof(total64));
     std::memcpy(&over, sc->pinned + 6, sizeof(over));
-    sc->nc_needed = (int64_t)std::min<unsigned long long>(total64, (unsigned long long)INT64_MAX);
     if (over) {
         set_error("a body meets more than 2^18 hull candidates in its 27 cells: the cell grid, sized by the largest "
                   "hull (radius %g), is too coarse for this state (a diverged solve or a very fast body)",
@@ -469,7 +468,6 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
         return NBGS_ERR_CAPACITY;
     }
     const int64_t nc = sc->pinned[0];
-    sc->nc_needed = nc;
     if (nc != (int64_t)total64) {
         set_error("contact count %lld disagrees with its 64-bit total %llu", (long long)nc,
                   (unsigned long long)total64);
@@ -480,6 +478,8 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
                   "contacts)", (long long)nc);
         return NBGS_ERR_CAPACITY;
     }
+    // from here on a CAPACITY is the workspace's: its count is reported (the refusals above report none)
+    sc->nc_needed = nc;
     // the contact capacity of the workspace (nbgs_workspace_query's sizes): refused before any list is touched
     const size_t need = scene_workspace_bytes(N, nc, sc->n_scenes);
     if (need > sc->arena.size()) {
@@ -487,6 +487,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
                   (long long)nc, need, sc->arena.size());
         return NBGS_ERR_CAPACITY;
     }
+    sc->nc_needed = -1;  // a later refusal (colours, block sizes) is not lifted by a larger workspace
     sc->nc = nc;
     ContactBuf &cb = sc->cb[sc->cur];
     NBGS_TRY(cb.reserve((size_t)nc));

@@ -958,7 +958,7 @@ struct nbgs_composite_s {
 size_t composite_workspace_bytes(int64_t n, int64_t e, int64_t c) {
     const double b = 1.1 * (352.0 * (double)e + 164.0 * (double)n + 525.0 * (double)c + 65536.0 * 16.0 * 1.25 +
                             16.0 * 1024.0 * 1024.0);
-    return (size_t)b;
+    return ((size_t)b + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1);
 }
 
 namespace {
@@ -1028,7 +1028,6 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
     unsigned long long total64 = 0, over = 0;
     std::memcpy(&total64, sc->pinned + 4, sizeof(total64));
     std::memcpy(&over, sc->pinned + 6, sizeof(over));
-    sc->nc_needed = (int64_t)std::min<unsigned long long>(total64, (unsigned long long)INT64_MAX);
     if (over) {
         set_error("an element meets more than 2^18 hull candidates in its 27 cells (largest grown element %g)",
                   max_reach);
@@ -1051,6 +1050,7 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
                   (long long)nc, need, sc->arena.size());
         return NBGS_ERR_CAPACITY;
     }
+    sc->nc_needed = -1;  // a later refusal (colours, block sizes) is not lifted by a larger workspace
     sc->nc = nc;
     CompContactBuf &cb = sc->cb[sc->cur];
     NBGS_TRY(cb.reserve((size_t)(nc > 0 ? nc : 1)));

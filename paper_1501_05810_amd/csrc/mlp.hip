@@ -539,7 +539,8 @@ const float *mlp_weight_ptr(nbgs_mlp_t mlp) { return mlp->w.p; }
 // cent for alignment.
 size_t mlp_workspace_bytes(int64_t max_samples) {
     const double fixed = 4.0 * NPAR * 4.0 + 2.0 * NFRAG + 1025.0 * NPAR * 4.0 + 1024.0 * 4.0 + 1024.0 * 1024.0;
-    return (size_t)(1.1 * (fixed + 64.0 * (double)max_samples));
+    const size_t b = (size_t)(1.1 * (fixed + 64.0 * (double)max_samples));
+    return (b + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1);
 }
 
 // Room for n more collected samples (CAPACITY past max_samples): where they go.

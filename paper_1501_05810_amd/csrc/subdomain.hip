@@ -32,7 +32,10 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kMaxCol = 256;
 
-inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+// At least one workgroup: counts here may be zero (no slot at all when every
+// contact of the block-local order lies between blocks), and every element
+// kernel below guards its index.
+inline unsigned grid_for(int64_t n) { return n > 0 ? (unsigned)((n + kBlock - 1) / kBlock) : 1u; }
 
 struct Blocks {
     double lo[3], e[3];

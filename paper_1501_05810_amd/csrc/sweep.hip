@@ -75,22 +75,37 @@ __device__ inline void store_vel(float *vel, int b, const Rec<float> &r) {
     }
 }
 
+// Row length of the LDS stage of a workgroup's body records (8 rows, one per
+// record value): 32 bytes of padding put the 8 rows that a transposed access
+// of neighbouring lanes touches in distinct banks.
+template <class T>
+constexpr int kStageRow = kBlock + 32 / (int)sizeof(T);
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_init_bodies(BodiesView b, double gx, double gy, double gz, double dt,
                                                         T *vel) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= b.n) return;
-    const double im = b.inv_mass[i];
-    const bool dyn = im > 0.0;
-    T *r = vel + 8 * (int64_t)i;
-    r[0] = (T)(dyn ? b.vx[i] + dt * gx : b.vx[i]);
-    r[1] = (T)(dyn ? b.vy[i] + dt * gy : b.vy[i]);
-    r[2] = (T)(dyn ? b.vz[i] + dt * gz : b.vz[i]);
-    r[3] = (T)b.wx[i];
-    r[4] = (T)b.wy[i];
-    r[5] = (T)b.wz[i];
-    r[6] = (T)im;
-    r[7] = (T)b.inv_inertia[i];
+    // the workgroup's records are staged in LDS (value-major) and written as one contiguous run, so that
+    // neighbouring lanes store neighbouring words
+    constexpr int S = kStageRow<T>;
+    __shared__ T stage[8 * S];
+    const int i0 = blockIdx.x * kBlock;
+    const int t = threadIdx.x, i = i0 + t;
+    if (i < b.n) {
+        const double im = b.inv_mass[i];
+        const bool dyn = im > 0.0;
+        stage[0 * S + t] = (T)(dyn ? b.vx[i] + dt * gx : b.vx[i]);
+        stage[1 * S + t] = (T)(dyn ? b.vy[i] + dt * gy : b.vy[i]);
+        stage[2 * S + t] = (T)(dyn ? b.vz[i] + dt * gz : b.vz[i]);
+        stage[3 * S + t] = (T)b.wx[i];
+        stage[4 * S + t] = (T)b.wy[i];
+        stage[5 * S + t] = (T)b.wz[i];
+        stage[6 * S + t] = (T)im;
+        stage[7 * S + t] = (T)b.inv_inertia[i];
+    }
+    __syncthreads();
+    const int nvalid = b.n - i0 < kBlock ? b.n - i0 : kBlock;
+    T *out = vel + 8 * (int64_t)i0;
+    for (int q = t; q < 8 * nvalid; q += kBlock) out[q] = stage[(q & 7) * S + (q >> 3)];
 }
 
 // Initial impulses applied in colour order (one launch per colour), so every
@@ -457,12 +472,21 @@ __global__ void __launch_bounds__(kResBlock) k_residual(const double *partials, 
 // eq. (integrationscheme) with quaternion renormalisation; periodic wrap.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, SceneTable st, double dt, const T *vel) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    // the workgroup's records are read as one contiguous run into LDS (neighbouring lanes load neighbouring words)
+    constexpr int S = kStageRow<T>;
+    __shared__ T stage[8 * S];
+    const int i0 = blockIdx.x * kBlock;
+    const int t = threadIdx.x, i = i0 + t;
+    const int nvalid = b.n - i0 < kBlock ? b.n - i0 : kBlock;
+    const T *in = vel + 8 * (int64_t)i0;
+    for (int q = t; q < 8 * nvalid; q += kBlock) stage[(q & 7) * S + (q >> 3)] = in[q];
+    __syncthreads();
     if (i >= b.n) return;
     const Grid &g = st.body_scene ? st.grids[st.body_scene[i]] : g0;
-    const T *r = vel + 8 * (int64_t)i;
-    const double vx = (double)r[0], vy = (double)r[1], vz = (double)r[2];
-    const double ox = (double)r[3], oy = (double)r[4], oz = (double)r[5];
+    const double vx = (double)stage[0 * S + t], vy = (double)stage[1 * S + t],
+                 vz = (double)stage[2 * S + t];
+    const double ox = (double)stage[3 * S + t], oy = (double)stage[4 * S + t],
+                 oz = (double)stage[5 * S + t];
     b.vx[i] = vx;
     b.vy[i] = vy;
     b.vz[i] = vz;

@@ -117,6 +117,29 @@ def test_batch_member_against_oracle():
     gb.close()
 
 
+def test_fp32_batch_member_against_oracle():
+    """An FP32-sweep member of a batch against the oracle's FP64 step at the FP32 bar (the same bar as a standalone
+    FP32 scene): identical contacts and colours, impulses within 2e-4 of the largest, velocities and positions
+    close."""
+    nb = _nb()
+    members = _members()
+    gb = nb.GpuBatch([s.copy() for s in members], precision="fp32")
+    i = 1
+    w = oracle.World(members[i].copy())
+    for _ in range(2):
+        gb.step_batch(1, 15)
+        w.step(15, grid=True)
+    v = w.view()
+    mine = gb.scene_contacts(gb.contacts(), i)
+    assert np.array_equal(mine["key"], v["key"]) and np.array_equal(mine["colour"], v["colour"])
+    assert np.abs(mine["P"] - v["P"]).max() <= 2e-4 * np.abs(v["P"]).max()
+    st = gb.state()
+    ref = w.sc
+    assert np.abs(gb.split(st["vel"])[i] - ref.vel).max() <= 2e-4 * max(np.abs(ref.vel).max(), 1e-300)
+    assert np.abs(gb.split(st["pos"])[i] - ref.pos).max() <= 1e-7 * np.abs(ref.pos).max()
+    gb.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_graph_replay_single_scene(precision):
     """Graph-replayed sweeps give the direct loop's impulses and velocities bit for bit; with a residual target
