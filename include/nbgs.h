@@ -140,12 +140,13 @@ int32_t nbgs_abi_version(void);
 const char *nbgs_last_error(void);
 
 /* Bytes of device workspace a scene of n_bodies bodies with up to
- * contact_capacity contacts needs, in every sweep order, precision and warm
- * start (an upper bound: per body 613 B, per contact 1,000 B, plus a cell
- * table of 2^16 cells, 16 MiB, and ten per cent), a multiple of 256 (all of
- * it usable from a 256-byte aligned base).  params [host] may be NULL
- * (checked when given).  *bytes [host].  Pure host computation: no device is
- * touched.  Errors: INVALID_ARG. */
+ * contact_capacity contacts needs, in the classic order in every precision
+ * and warm start (an upper bound: per body 613 B, per contact 1,000 B, plus a
+ * cell table of 2^16 cells, 16 MiB, and ten per cent), a multiple of 256 (all
+ * of it usable from a 256-byte aligned base).  The block-local order and the
+ * subdomain solver add 88 B per id (nbgs_scene_workspace_query).  params
+ * [host] may be NULL (checked when given).  *bytes [host].  Pure host
+ * computation: no device is touched.  Errors: INVALID_ARG. */
 nbgs_status nbgs_workspace_query(int64_t n_bodies, int64_t contact_capacity, const nbgs_params *params,
                                  size_t *bytes);
 
@@ -170,6 +171,16 @@ nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *doma
  * regions must not overlap.  Errors: INVALID_ARG (NULL, too small, overlap),
  * CAPACITY (the buffers in use do not fit; nothing moved), DEVICE. */
 nbgs_status nbgs_scene_set_workspace(nbgs_scene_t scene, void *workspace, size_t bytes);
+
+/* Bytes of workspace this scene needs for contact_capacity contacts in its
+ * current sweep order: nbgs_workspace_query's figure plus, for the
+ * block-local order (nbgs_set_block_order) or the subdomain solver
+ * (nbgs_set_subdomains), 88 B per id (every block of every grid and the id of
+ * the contacts between blocks, or every subdomain), rounded up to 256.  This
+ * is the size a detection checks its workspace against.  *bytes [host].  Host
+ * arithmetic only.  Errors: INVALID_ARG (NULL, negative capacity, an edge
+ * giving too many blocks). */
+nbgs_status nbgs_scene_workspace_query(nbgs_scene_t scene, int64_t contact_capacity, size_t *bytes);
 
 /* Size of the scene's workspace, the bytes its buffers use now and the most
  * they used at once, each [host] and NULL-able. */

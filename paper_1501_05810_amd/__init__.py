@@ -89,6 +89,7 @@ _SIGNATURES = [
     ("nbgs_workspace_query", C.c_int, [C.c_int64, C.c_int64, C.POINTER(nbgs_params), C.POINTER(C.c_size_t)]),
     ("nbgs_scene_create", C.c_int, [C.POINTER(nbgs_bodies), C.POINTER(nbgs_domain), C.POINTER(nbgs_params), _vp,
                                     C.c_size_t, _vp, C.POINTER(_vp)]),
+    ("nbgs_scene_workspace_query", C.c_int, [_vp, C.c_int64, C.POINTER(C.c_size_t)]),
     ("nbgs_scene_set_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
     ("nbgs_scene_workspace_usage", C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
                                              C.POINTER(C.c_size_t)]),
@@ -228,6 +229,12 @@ def nbgs_scene_create(bodies: nbgs_bodies, domain: nbgs_domain, params: nbgs_par
     _check(lib().nbgs_scene_create(C.byref(bodies), C.byref(domain), C.byref(params), _vp(workspace),
                                    C.c_size_t(workspace_bytes), _vp(stream), C.byref(h)))
     return h.value
+
+
+def nbgs_scene_workspace_query(h: int, contact_capacity: int) -> int:
+    b = C.c_size_t()
+    _check(lib().nbgs_scene_workspace_query(_vp(h), int(contact_capacity), C.byref(b)))
+    return int(b.value)
 
 
 def nbgs_scene_set_workspace(h: int, workspace: int, nbytes: int) -> None:
@@ -651,6 +658,8 @@ class GpuScene:
         _GROWERS[self.handle] = self._grow
 
     def _query(self, capacity: int) -> int:
+        if getattr(self, "handle", None):  # the scene's own figure: its sweep order's per-id tables included
+            return nbgs_scene_workspace_query(self.handle, capacity)
         return nbgs_workspace_query(self.n, capacity, self._params)
 
     def _grow(self, needed: int) -> bool:

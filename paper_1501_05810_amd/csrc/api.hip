@@ -146,14 +146,30 @@ const void *Arena::relocate(const void *old) const {
 // records of both precisions 168 B, colouring 36 B, learned start 156 B,
 // subdomain ends, slots and corrections 208 B, partial sums and tuning copies
 // 40 B, times 1.25); per scene its cell table of at least 2^16 cells and its
-// tables; a fixed 16 MiB (residual history of 131,072 sweeps, colour-start
-// tables of 4,096 blocks, sort scratch); ten per cent for the alignment of
-// every buffer and for runs left between freed buffers.
+// tables; a fixed 16 MiB (residual history of 131,072 sweeps, sort
+// scratch); ten per cent for the alignment of every buffer and for runs left
+// between freed buffers.  The per-id tables of the block-local order and of the
+// subdomain solver come on top (scene_need_bytes).
 size_t scene_workspace_bytes(int64_t n, int64_t c, int64_t scenes) {
     const double per_body = 613.0, per_contact = 1000.0, per_scene = 65536.0 * 16.0 * 1.25 + 4096.0;
     const double fixed = 16.0 * 1024.0 * 1024.0;
     const double b = 1.1 * (per_body * (double)n + per_contact * (double)c + per_scene * (double)scenes + fixed);
     return ((size_t)b + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1);  // all of it usable at an aligned base
+}
+
+// Per id of the block-local order or of the subdomain solver: contact range
+// (8 B), its count (4 B), slot count and range (8 B), colour runs and their
+// count (8 B), residual partial sums (16 B), scan scratch, times 1.25 for the
+// growth slack, rounded up.
+constexpr double kPerIdBytes = 80.0;
+
+nbgs_status scene_need_bytes(nbgs_scene_t sc, int64_t c, size_t *bytes) {
+    int64_t ids = 0;
+    NBGS_TRY(order_ids(sc, &ids));
+    const size_t id_bytes = ids > 0 ? (size_t)(1.1 * kPerIdBytes * (double)(ids + 2)) : 0;
+    *bytes = scene_workspace_bytes(sc->b.n, c, sc->n_scenes) +
+             ((id_bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1));
+    return NBGS_OK;
 }
 
 nbgs_status check_params(const nbgs_params *p) {
@@ -480,11 +496,12 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     }
     // from here on a CAPACITY is the workspace's: its count is reported (the refusals above report none)
     sc->nc_needed = nc;
-    // the contact capacity of the workspace (nbgs_workspace_query's sizes): refused before any list is touched
-    const size_t need = scene_workspace_bytes(N, nc, sc->n_scenes);
+    // the contact capacity of the workspace (nbgs_scene_workspace_query's sizes): refused before any list is touched
+    size_t need = 0;
+    NBGS_TRY(scene_need_bytes(sc, nc, &need));
     if (need > sc->arena.size()) {
-        set_error("%lld contacts need a workspace of %zu bytes (nbgs_workspace_query), this one has %zu",
-                  (long long)nc, need, sc->arena.size());
+        set_error("%lld contacts need a workspace of %zu bytes in this sweep order (nbgs_scene_workspace_query), "
+                  "this one has %zu", (long long)nc, need, sc->arena.size());
         return NBGS_ERR_CAPACITY;
     }
     sc->nc_needed = -1;  // a later refusal (colours, block sizes) is not lifted by a larger workspace
@@ -1427,6 +1444,14 @@ nbgs_status nbgs_workspace_query(int64_t n_bodies, int64_t contact_capacity, con
     if (params) NBGS_TRY(check_params(params));
     *bytes = scene_workspace_bytes(n_bodies, contact_capacity, 1);
     return NBGS_OK;
+}
+
+nbgs_status nbgs_scene_workspace_query(nbgs_scene_t sc, int64_t contact_capacity, size_t *bytes) {
+    if (!sc || !bytes || contact_capacity < 0) {
+        set_error("bad arguments to nbgs_scene_workspace_query");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    return scene_need_bytes(sc, contact_capacity, bytes);
 }
 
 nbgs_status nbgs_scene_create(const nbgs_bodies *bodies, const nbgs_domain *domain, const nbgs_params *params,

@@ -230,7 +230,8 @@ struct nbgs_scene_s {
     DevBuf<int32_t> sdom, tile_cnt, tile_off32, tile_scnt, tile_slot_off, eflags, eex, slot_body, slot_sdom, body_cnt,
         body_slot_off;
     DevBuf<int64_t> tile_off;
-    DevBuf<int32_t> blk_cs;  // block-local order: per block its colour boundaries and colour count
+    DevBuf<int32_t> blk_cs;    // block-local order: per block its colour runs (k_blk_colour_runs)
+    DevBuf<int32_t> blk_nrun;  // and their count
     DevBuf<uint32_t> ekeys, evals, ekeys2, evals2, bkeys, bvals, bkeys2, bvals2;
     const uint32_t *body_slots = nullptr;
     DevBuf<double> corr64;
@@ -285,6 +286,8 @@ constexpr int kSmallInts = 16 + 512;
 // (n_scenes scenes in one body array; body_off: n_scenes + 1 host offsets).
 // Device bytes a scene (or a batch of `scenes` scenes) of n bodies with up to c contacts needs.
 size_t scene_workspace_bytes(int64_t n, int64_t c, int64_t scenes);
+// scene_workspace_bytes plus the per-id tables of the scene's current sweep order.
+nbgs_status scene_need_bytes(nbgs_scene_t sc, int64_t c, size_t *bytes);
 nbgs_status scene_create(void *workspace, size_t workspace_bytes, const nbgs_bodies *bodies, int32_t n_scenes,
                          const int64_t *body_off,
                          const nbgs_domain *domains, const nbgs_params *params, void *hip_stream, nbgs_scene_t *out);
@@ -299,6 +302,7 @@ nbgs_status scene_sync_small(nbgs_scene_t sc, int first, int count);
 // tile and slot tables (after the sweep record is gathered), and one pass
 // (mode 0: initial impulses, 1: relaxation) with the correction reduction.
 nbgs_status subdomain_assign(nbgs_scene_t sc);
+nbgs_status order_ids(nbgs_scene_t sc, int64_t *ids);
 nbgs_status subdomain_prepare(nbgs_scene_t sc);
 template <class T>
 nbgs_status subdomain_pass(nbgs_scene_t sc, int mode, T *vel, T *corr);

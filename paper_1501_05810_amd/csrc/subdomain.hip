@@ -551,39 +551,49 @@ __global__ void __launch_bounds__(kBlock) k_sub_reduce(T *vel, int32_t nb, const
 // never changes), a wall is zero.
 constexpr int kBlkThreads = 128;
 
-// Colour boundaries of every block's local contacts, once per step: cs[b (kMaxCol + 2) + c] = start of colour c
-// relative to the block's first contact (c = 0 .. ncol, the last one is the block's end), cs[b (kMaxCol + 2) +
-// kMaxCol + 1] = ncol.  Empty colours start where the next one does.
-__global__ void __launch_bounds__(kBlkThreads) k_blk_colour_starts(const int32_t *col, const int64_t *tile_off,
-                                                                   int32_t *cs) {
+// Colour runs of every block's local contacts, once per step.  A block's
+// contacts are in (colour, key) order, so every colour present in it is one
+// run: cs[tile_off[s] + s + r] = start of run r relative to the block's first
+// contact (r = 0 .. nrun[s], the last entry the block's contact count).  A
+// block has at most as many runs as contacts, so block s's entries fit in its
+// count + 1 places and the table in (local contacts + blocks) entries.
+__global__ void __launch_bounds__(kBlkThreads) k_blk_colour_runs(const int32_t *col, const int64_t *tile_off,
+                                                                 int32_t *cs, int32_t *nrun) {
+    constexpr int kWaves = kBlkThreads / 64;
     const int s = blockIdx.x;
     const int64_t c0 = tile_off[s], c1 = tile_off[s + 1];
-    __shared__ int64_t cstart[kMaxCol + 1];
-    __shared__ int ncol;
-    for (int c = threadIdx.x; c <= kMaxCol; c += kBlkThreads) cstart[c] = c1;
-    if (threadIdx.x == 0) ncol = 0;
+    int32_t *out = cs + c0 + s;
+    __shared__ int wave_cnt[kWaves];
+    __shared__ int base;
+    if (threadIdx.x == 0) base = 0;
     __syncthreads();
-    for (int64_t p = c0 + threadIdx.x; p < c1; p += kBlkThreads) {
-        const int cp = col[p];
-        if (p == c0 || col[p - 1] != cp) cstart[cp] = p;
-        if (p == c1 - 1) ncol = cp + 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t q0 = c0; q0 < c1; q0 += kBlkThreads) {
+        const int64_t p = q0 + threadIdx.x;
+        const bool first = p < c1 && (p == c0 || col[p - 1] != col[p]);
+        const unsigned long long m = __ballot(first);
+        if (lane == 0) wave_cnt[wv] = __popcll(m);
+        __syncthreads();
+        int off = base + __popcll(m & ((1ull << lane) - 1ull));
+        for (int w = 0; w < wv; ++w) off += wave_cnt[w];
+        if (first) out[off] = (int32_t)(p - c0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kWaves; ++w) base += wave_cnt[w];
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x == 0) {
-        for (int c = ncol - 1; c >= 0; --c)
-            if (cstart[c] == c1 && c + 1 <= kMaxCol) cstart[c] = cstart[c + 1];
-        cs[(int64_t)s * (kMaxCol + 2) + kMaxCol + 1] = ncol;
+        out[base] = (int32_t)(c1 - c0);
+        nrun[s] = base;
     }
-    __syncthreads();
-    for (int c = threadIdx.x; c <= ncol; c += kBlkThreads)
-        cs[(int64_t)s * (kMaxCol + 2) + c] = (int32_t)((c < ncol ? cstart[c] : c1) - c0);
 }
 
 template <class T, int MODE>
 __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t nb, T *vel, T mu, T relax,
                                                           const int64_t *tile_off, const int32_t *tile_slot_off,
                                                           const int32_t *slot_body, const int32_t *blk_cs,
-                                                          double *partials, const int32_t *ctrl, int32_t id0) {
+                                                          const int32_t *blk_nrun, double *partials,
+                                                          const int32_t *ctrl, int32_t id0) {
     if (MODE == 1 && ctrl[0]) return;  // an earlier sweep met the target (uniform over the grid)
     extern __shared__ __align__(16) unsigned char smem[];
     const int s = id0 + (int)blockIdx.x;  // this launch's blocks: ids id0 .. id0 + gridDim.x - 1
@@ -591,8 +601,8 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t
     const int s0 = tile_slot_off[s], ns = tile_slot_off[s + 1] - s0;
     T *Vs = reinterpret_cast<T *>(smem);  // [8][ns]: v'x v'y v'z w'x w'y w'z 1/m 1/I
     __shared__ int32_t cstart[kMaxCol + 1];
-    const int32_t *cs = blk_cs + (int64_t)s * (kMaxCol + 2);
-    const int ncol = cs[kMaxCol + 1];
+    const int32_t *cs = blk_cs + c0 + s;  // the block's colour runs
+    const int ncol = blk_nrun[s];
     for (int i = threadIdx.x; i < ns; i += kBlkThreads) {
         const T *r = vel + 8 * (int64_t)slot_body[s0 + i];
 #pragma unroll
@@ -741,6 +751,29 @@ static nbgs_status make_blocks(nbgs_scene_t sc, double edge, Blocks &bl, int64_t
     return NBGS_OK;
 }
 
+// Ids of the scene's sweep order: the subdomains, or the blocks of the
+// block-local order over all its grids plus the id of the contacts between
+// blocks; 0 in the classic order.  Host arithmetic only (the tables sized by
+// it count towards the workspace a detection needs).
+nbgs_status order_ids(nbgs_scene_t sc, int64_t *ids) {
+    *ids = 0;
+    Blocks bl;
+    int64_t nblocks = 1;
+    if (sc->sub_edge > 0.0) {
+        NBGS_TRY(make_blocks(sc, sc->sub_edge, bl, nblocks));
+        *ids = nblocks;
+    } else if (sc->blk_edge > 0.0) {
+        NBGS_TRY(make_blocks(sc, sc->blk_edge, bl, nblocks));
+        if (sc->blk_grids > 1) {
+            int64_t B = 1;  // a shifted grid has one more block along a non-periodic axis
+            for (int a = 0; a < 3; ++a) B *= bl.nb[a] + (sc->periodic[a] ? 0 : 1);
+            nblocks = (int64_t)sc->blk_grids * B;
+        }
+        *ids = nblocks + 1;
+    }
+    return NBGS_OK;
+}
+
 // Subdomains of the contacts and, when the colouring is done, the tile and slot tables.
 nbgs_status subdomain_assign(nbgs_scene_t sc) {
     hipStream_t s = sc->s;
@@ -884,9 +917,11 @@ static nbgs_status block_prepare_impl(nbgs_scene_t sc) {
     k_block_ends<<<grid_for(nc), kBlock, 0, s>>>(sw.j1.p, sw.j2.p, ssd, nc, nblk, N, sc->b.inv_mass, sc->body_cnt.p,
                                                   sc->tile_slot_off.p, sw.ls.p);
     NBGS_HIP(hipGetLastError());
-    // colour boundaries of every block's local contacts
-    NBGS_TRY(sc->blk_cs.reserve((size_t)nblk * (kMaxCol + 2)));
-    k_blk_colour_starts<<<(unsigned)nblk, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p);
+    // colour runs of every block's local contacts
+    NBGS_TRY(sc->blk_cs.reserve((size_t)nc + nblk + 1));
+    NBGS_TRY(sc->blk_nrun.reserve((size_t)nblk + 1));
+    k_blk_colour_runs<<<(unsigned)nblk, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p,
+                                                             sc->blk_nrun.p);
     NBGS_HIP(hipGetLastError());
     // colours of the contacts between blocks (the last id's range)
     NBGS_TRY(cross_colours(sc, sw.col.p, sw.j1.p, sw.j2.p, toff[(size_t)nblk], toff[(size_t)nsub]));
@@ -937,8 +972,10 @@ static nbgs_status block_grids_prepare_impl(nbgs_scene_t sc) {
     SweepBuf<T> &sw = sc->precision_used == NBGS_FP32_SWEEP ? *reinterpret_cast<SweepBuf<T> *>(&sc->sw32)
                                                             : *reinterpret_cast<SweepBuf<T> *>(&sc->sw64);
     NBGS_TRY(prepare_impl<T>(sc, nblk, 8, false));
-    NBGS_TRY(sc->blk_cs.reserve((size_t)nblk * (kMaxCol + 2)));
-    k_blk_colour_starts<<<(unsigned)nblk, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p);
+    NBGS_TRY(sc->blk_cs.reserve((size_t)sc->nc + nblk + 1));
+    NBGS_TRY(sc->blk_nrun.reserve((size_t)nblk + 1));
+    k_blk_colour_runs<<<(unsigned)nblk, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p,
+                                                             sc->blk_nrun.p);
     NBGS_HIP(hipGetLastError());
     NBGS_TRY(cross_colours(sc, sw.col.p, sw.j1.p, sw.j2.p, sc->blk_first_cross, sc->nc));
     sc->blk_dyn_local = sc->n_slots;
@@ -969,7 +1006,8 @@ static nbgs_status prepare_impl(nbgs_scene_t sc, int32_t no_slot, int values_per
     k_fill<<<grid_for(nsub + 1), kBlock, 0, s>>>(sc->tile_cnt.p, nsub + 1, 0);
     k_hist<<<grid_for(nc), kBlock, 0, s>>>(ssd, nc, sc->tile_cnt.p);
     NBGS_HIP(hipGetLastError());
-    const size_t need_tmp = exclusive_scan_tmp_bytes(std::max<int64_t>(2 * nc, (int64_t)N) + 2);
+    // (scans over contact ends, bodies and the ids' tables)
+    const size_t need_tmp = exclusive_scan_tmp_bytes(std::max<int64_t>(std::max<int64_t>(2 * nc, N), nsub) + 2);
     if (need_tmp > sc->scan_tmp.cap) NBGS_TRY(sc->scan_tmp.reserve(need_tmp));
     // contact ends sorted by body, then stably by subdomain
     const int64_t ne = 2 * nc;
@@ -1125,11 +1163,11 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
         if (mode == 0)
             k_blk_pass<T, 0><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
                                                              sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
-                                                             sc->partials.p, sc->ctrl(), id0);
+                                                             sc->blk_nrun.p, sc->partials.p, sc->ctrl(), id0);
         else
             k_blk_pass<T, 1><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
                                                              sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
-                                                             sc->partials.p, sc->ctrl(), id0);
+                                                             sc->blk_nrun.p, sc->partials.p, sc->ctrl(), id0);
         NBGS_HIP(hipGetLastError());
     }
     return NBGS_OK;

@@ -49,9 +49,10 @@ def test_capacity_round_trip_leaves_the_scene_unchanged():
             code, st = _detect_raw(nb, g)
             assert code == nb.NBGS_ERR_CAPACITY and "workspace" in nb.nbgs_last_error()
             assert st.n_contacts == v["n_contacts"]
-            _move(nb, g, nb.nbgs_workspace_query(g.n, int(st.n_contacts), g._params))
+            # room for this count and a quarter more (the pair count changes from step to step)
+            _move(nb, g, nb.nbgs_scene_workspace_query(g.handle, int(st.n_contacts) * 5 // 4))
         code, st = _detect_raw(nb, g)
-        assert code == 0 and st.n_contacts == v["n_contacts"]
+        assert code == 0 and st.n_contacts == v["n_contacts"], (step, code, nb.nbgs_last_error())
         c = g.contacts()
         np.testing.assert_array_equal(c["key"], v["key"])
         np.testing.assert_array_equal(c["colour"], v["colour"])
@@ -132,3 +133,24 @@ def test_collected_training_pairs():
     for m in (mlp, ref):
         m.close()
     g.close()
+
+
+def test_block_order_tables_count_towards_the_workspace():
+    """The block-local order adds its per-id tables (88 B per id) to the scene's workspace figure; a scene sized for
+    the classic order grows into it at its first detection in that order and then steps as usual."""
+    nb = _nb()
+    sc = sg.random_cluster(6, 400, box=9.0, periodic=(True, True, True), overlap=0.05)
+    g = nb.GpuScene(sc.copy())
+    q0 = nb.nbgs_scene_workspace_query(g.handle, 1000)
+    assert q0 == nb.nbgs_workspace_query(g.n, 1000, g._params)
+    g.set_block_order(0.3, grids=4)
+    nb_axis = int(np.floor(9.0 / 0.3))  # blocks per (periodic) axis
+    ids = 4 * nb_axis ** 3 + 1
+    q4 = nb.nbgs_scene_workspace_query(g.handle, 1000)
+    assert q4 - q0 == pytest.approx(88 * (ids + 2), abs=512)
+    before = g.workspace.nbytes
+    g.step(10)
+    assert g.workspace.nbytes >= nb.nbgs_scene_workspace_query(g.handle, g.contacts()["key"].shape[0]) > before
+    g.close()
+    with pytest.raises(nb.NbgsError):
+        nb.nbgs_scene_workspace_query(0, 10)
