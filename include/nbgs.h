@@ -504,6 +504,18 @@ nbgs_status nbgs_mlp_forward(nbgs_mlp_t mlp, const float *feat, int64_t n, float
 nbgs_status nbgs_mlp_loss_grad(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n, float *grad,
                                double *loss);
 
+/* nbgs_mlp_loss_grad for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels, with the per-block gradient and loss partials in a fixed device
+ * array of the library (4.75 MB, one per GPU, kept until the process ends)
+ * instead of the network's workspace; no allocation of any kind.  At most
+ * 4,096 samples per call (INVALID_ARG beyond); grad [device] must be given.
+ * Every call on one GPU shares that array: calls that overlap in time on one
+ * GPU (several streams or threads) race and must be serialised by the caller.
+ * Results equal nbgs_mlp_loss_grad's bit for bit. */
+nbgs_status nbgs_mlp_loss_grad_static(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n,
+                                      float *grad, double *loss);
+
 /* Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) over `epochs` passes of
  * minibatches of `batch` samples drawn in a splitmix64 Fisher-Yates order
  * from shuffle_seed; feat [device n x 12], target [device n x 3].

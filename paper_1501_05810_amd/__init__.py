@@ -120,6 +120,7 @@ _SIGNATURES = [
     ("nbgs_mlp_get_weights", C.c_int, [_vp, C.POINTER(C.c_float)]),
     ("nbgs_mlp_forward", C.c_int, [_vp, _vp, C.c_int64, _vp]),
     ("nbgs_mlp_loss_grad", C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, C.POINTER(C.c_double)]),
+    ("nbgs_mlp_loss_grad_static", C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, C.POINTER(C.c_double)]),
     ("nbgs_mlp_train", C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64,
                                  C.POINTER(C.c_double)]),
     ("nbgs_scene_attach_mlp", C.c_int, [_vp, _vp]),

@@ -18,7 +18,9 @@
 // Weight vector layout (18,563 values): W1[12][128], b1[128], W2[128][128],
 // b2[128], W3[128][3], b3[3]; y = x W + b per layer, ReLU after layers 1, 2.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <mutex>
 #include <new>
 
 #include "nbgs_internal.h"
@@ -561,6 +563,52 @@ nbgs_status mlp_store_slot(nbgs_mlp_t mlp, int64_t n, float **feat, float **tgt)
 void mlp_store_commit(nbgs_mlp_t mlp, int64_t n) { mlp->n_stored += n; }
 }  // namespace nbgs
 
+// Scratch of nbgs_mlp_loss_grad_static: the per-block gradient partials and
+// loss partials of at most kStaticGradBlocks blocks of 64 samples (4.75 MB),
+// a copy on every GPU the library runs on, held until the process ends.  In
+// host code the array's name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, once per device (scratch_ptr).
+constexpr int kStaticGradBlocks = 64;
+constexpr int64_t kStaticMaxSamples = (int64_t)kStaticGradBlocks * 64;
+constexpr size_t kScratchFloats = (size_t)kStaticGradBlocks * NPAR + kStaticGradBlocks;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::atomic<float *> g_scratch_dev[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// The current device's copy of the scratch array.
+nbgs_status scratch_ptr(float **out) {
+    int dev = 0;
+    NBGS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d: the static scratch is kept for devices 0 .. %d", dev, kMaxDevices - 1);
+        return NBGS_ERR_DEVICE;
+    }
+    float *p = g_scratch_dev[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_dev[dev].load(std::memory_order_acquire);
+        if (!p) {
+            void *q = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !q) {
+                set_error("hipGetSymbolAddress of the static scratch failed on device %d: %s", dev,
+                          hipGetErrorString(e));
+                return NBGS_ERR_DEVICE;
+            }
+            p = static_cast<float *>(q);
+            g_scratch_dev[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return NBGS_OK;
+}
+
+}  // namespace
+
 // A NULL network is refused; its arena takes the buffers allocated until the
 // entry point returns.
 #define NBGS_MGUARD(mlp)                                                                                        \
@@ -721,6 +769,32 @@ nbgs_status nbgs_mlp_loss_grad(nbgs_mlp_t mlp, const float *feat, const float *t
         else std::memcpy(lp.data(), mlp->host, sizeof(float) * nb);
         double s = 0.0;
         for (int b = 0; b < nb; ++b) s += lp[b];
+        *loss = s / (2.0 * (double)n);
+    }
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_mlp_loss_grad_static(nbgs_mlp_t mlp, const float *feat, const float *target, int64_t n,
+                                      float *grad, double *loss) {
+    if (!mlp || n < 1 || !feat || !target || !grad) {
+        set_error("bad arguments to nbgs_mlp_loss_grad_static");
+        return NBGS_ERR_INVALID_ARG;
+    }
+    if (n > kStaticMaxSamples) {
+        set_error("%lld samples: nbgs_mlp_loss_grad_static takes at most %lld (its static scratch holds the partial "
+                  "sums of %d blocks of 64)", (long long)n, (long long)kStaticMaxSamples, kStaticGradBlocks);
+        return NBGS_ERR_INVALID_ARG;
+    }
+    float *scr = nullptr;
+    NBGS_TRY(scratch_ptr(&scr));
+    const int nb = mlp_grad_blocks(n);  // at most kStaticGradBlocks here; every block writes its partials whole
+    float *part = scr, *lpart = scr + (size_t)kStaticGradBlocks * NPAR;
+    NBGS_TRY(launch_mlp_grad(mlp->fr.p, mlp->w.p, feat, target, nullptr, 0, n, part, lpart, grad, mlp->s));
+    if (loss) {
+        NBGS_HIP(hipMemcpyAsync(mlp->host, lpart, sizeof(float) * nb, hipMemcpyDeviceToHost, mlp->s));
+        NBGS_HIP(hipStreamSynchronize(mlp->s));
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += mlp->host[b];
         *loss = s / (2.0 * (double)n);
     }
     return NBGS_OK;
