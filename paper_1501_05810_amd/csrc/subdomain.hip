@@ -194,7 +194,8 @@ __global__ void __launch_bounds__(kBlock) k_slot_write(const uint32_t *vals, int
     slot_sdom[ex[i]] = ssd[e >> 1];
 }
 
-// Local slot of every contact end (-1: wall, static body, or a contact that takes no slot).
+// Local slot of every contact end: -1 for a static body and for every end of
+// a contact that takes no slot, -2 for a wall.
 __global__ void __launch_bounds__(kBlock) k_end_slots(const uint32_t *vals, int64_t n, const int32_t *sj1,
                                                       const int32_t *sj2, const int32_t *ssd, int32_t nb,
                                                       const double *inv_mass, const int32_t *flags,
@@ -204,7 +205,8 @@ __global__ void __launch_bounds__(kBlock) k_end_slots(const uint32_t *vals, int6
     if (i >= n) return;
     const uint32_t e = vals[i];
     const int32_t b = end_body(sj1, sj2, nb, inv_mass, e, ssd, no_slot);
-    ls[e] = (int16_t)(b < nb ? ex[i] + flags[i] - 1 - tile_slot_off[ssd[e >> 1]] : -1);
+    const int32_t raw = (e & 1u) ? sj2[e >> 1] : sj1[e >> 1];
+    ls[e] = (int16_t)(b < nb ? ex[i] + flags[i] - 1 - tile_slot_off[ssd[e >> 1]] : (raw < nb ? -1 : -2));
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill64(int64_t *p, int64_t n, int64_t v) {
@@ -260,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_slot_of(const uint32_t *sorted_body,
 }
 
 // Slot (local to the contact's block) of both ends of a local contact; -1 for
-// a wall, a static body and every end of a contact between blocks.
+// a static body and every end of a contact between blocks, -2 for a wall.
 __global__ void __launch_bounds__(kBlock) k_block_ends(const int32_t *sj1, const int32_t *sj2, const int32_t *ssd,
                                                        int64_t nc, int32_t nblocks, int32_t nb,
                                                        const double *inv_mass, const int32_t *slot,
@@ -271,7 +273,8 @@ __global__ void __launch_bounds__(kBlock) k_block_ends(const int32_t *sj1, const
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int32_t b = k ? sj2[p] : sj1[p];
-        ls[2 * p + k] = (int16_t)((id < nblocks && b < nb && inv_mass[b] > 0.0) ? slot[b] - first_slot[id] : -1);
+        ls[2 * p + k] = (int16_t)((id < nblocks && b < nb && inv_mass[b] > 0.0) ? slot[b] - first_slot[id]
+                                                                                  : (b < nb ? -1 : -2));
     }
 }
 
@@ -549,7 +552,8 @@ __global__ void __launch_bounds__(kBlock) k_sub_reduce(T *vel, int32_t nb, const
 // the arithmetic of every sweep kernel) and writes the impulses and the block's
 // residual sums.  A static partner's record is read from the accumulators (it
 // never changes), a wall is zero.
-constexpr int kBlkThreads = 128;
+constexpr int kBlkThreads = 64;         // the held form (k_blk_pass) and k_blk_colour_runs
+constexpr int kBlkStreamThreads = 128;  // the streamed form (k_blk_pass_stream)
 
 // Colour runs of every block's local contacts, once per step.  A block's
 // contacts are in (colour, key) order, so every colour present in it is one
@@ -588,8 +592,186 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk_colour_runs(const int32_t *
     }
 }
 
+// Contacts of a block held in each thread's registers at once: a chunk of
+// kBlkThreads * kBlkHeld positions is loaded before its colour runs are
+// relaxed, so the chain of runs waits on LDS and barriers only, not on a
+// global load per colour.  Thread t holds positions t, t + kBlkThreads, ...
+// of the chunk (ascending, hence in colour order).
+constexpr int kBlkHeld = 3;
+
+// One local contact's data, loaded ahead of its colour run.
+template <class T>
+struct HeldContact {
+    T n[3], a1, a2, P[3], bias;
+    int32_t ls;  // the two int16 end slots (>= 0 slot, -1 static body, -2 wall)
+};
+
+template <class T, int MODE>
+__device__ inline void blk_load(const SubView<T> &sv, int64_t p, HeldContact<T> &h) {
+    h.n[0] = sv.nx[p];
+    h.n[1] = sv.ny[p];
+    h.n[2] = sv.nz[p];
+    h.a1 = sv.a1[p];
+    h.a2 = sv.a2[p];
+    h.P[0] = sv.px[p];
+    h.P[1] = sv.py[p];
+    h.P[2] = sv.pz[p];
+    h.bias = MODE == 1 ? sv.bias[p] : T(0);
+    h.ls = reinterpret_cast<const int32_t *>(sv.ls)[p];  // ls[2 p], ls[2 p + 1] in one aligned word
+}
+
+template <class T>
+__device__ inline void blk_end_rec(const T *Vs, int ns, const T *vel, int l, const int32_t *j, int64_t p,
+                                   Rec<T> &r) {
+    if (l >= 0) {
+        r.v[0] = Vs[0 * ns + l];
+        r.v[1] = Vs[1 * ns + l];
+        r.v[2] = Vs[2 * ns + l];
+        r.w[0] = Vs[3 * ns + l];
+        r.w[1] = Vs[4 * ns + l];
+        r.w[2] = Vs[5 * ns + l];
+        r.im = Vs[6 * ns + l];
+        r.ii = Vs[7 * ns + l];
+    } else if (l == -1) {  // a static body: its record never changes
+        const T *g = vel + 8 * (int64_t)j[p];
+        r.v[0] = g[0];
+        r.v[1] = g[1];
+        r.v[2] = g[2];
+        r.w[0] = g[3];
+        r.w[1] = g[4];
+        r.w[2] = g[5];
+        r.im = g[6];
+        r.ii = g[7];
+    } else {  // a wall
+        r = zero_rec<T>();
+    }
+}
+
+template <class T>
+__device__ inline void blk_store_rec(T *Vs, int ns, int l, const Rec<T> &r) {
+    if (l >= 0 && r.im > T(0)) {
+        Vs[0 * ns + l] = r.v[0];
+        Vs[1 * ns + l] = r.v[1];
+        Vs[2 * ns + l] = r.v[2];
+        Vs[3 * ns + l] = r.w[0];
+        Vs[4 * ns + l] = r.w[1];
+        Vs[5 * ns + l] = r.w[2];
+    }
+}
+
+// One pass over the local contacts of every block of one grid, one workgroup
+// per block, the block's body records in LDS.  MODE 0 applies the initial
+// impulses, MODE 1 relaxes (Alg. 1) and leaves the block's residual sums in
+// partials[2 s], [2 s + 1].  Colour runs in order, a barrier after each.
 template <class T, int MODE>
 __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t nb, T *vel, T mu, T relax,
+                                                          const int64_t *tile_off, const int32_t *tile_slot_off,
+                                                          const int32_t *slot_body, const int32_t *blk_cs,
+                                                          const int32_t *blk_nrun, double *partials,
+                                                          const int32_t *ctrl, int32_t id0) {
+    (void)nb;
+    if (MODE == 1 && ctrl[0]) return;  // an earlier sweep met the target (uniform over the grid)
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int s = id0 + (int)blockIdx.x;  // this launch's blocks: ids id0 .. id0 + gridDim.x - 1
+    const int64_t c0 = tile_off[s];
+    const int count = (int)(tile_off[s + 1] - c0);
+    const int s0 = tile_slot_off[s], ns = tile_slot_off[s + 1] - s0;
+    T *Vs = reinterpret_cast<T *>(smem);  // [8][ns]: v'x v'y v'z w'x w'y w'z 1/m 1/I
+    __shared__ int32_t cstart[kMaxCol + 1];
+    const int32_t *cs = blk_cs + c0 + s;  // the block's colour runs
+    const int ncol = blk_nrun[s];
+    constexpr int kHeld = kBlkHeld, kChunk = kBlkThreads * kHeld;
+    const int t = threadIdx.x;
+    HeldContact<T> held[kHeld];
+    // the first chunk's loads go out before the block's records are staged
+#pragma unroll
+    for (int k = 0; k < kHeld; ++k)
+        if (t + k * kBlkThreads < count) blk_load<T, MODE>(sv, c0 + t + k * kBlkThreads, held[k]);
+    for (int i = t; i < ns; i += kBlkThreads) {
+        const T *r = vel + 8 * (int64_t)slot_body[s0 + i];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) Vs[a * ns + i] = r[a];
+    }
+    for (int c = t; c <= ncol; c += kBlkThreads) cstart[c] = cs[c];
+    __syncthreads();
+    double sd = 0.0, sp = 0.0;
+    int run = 0;  // the colour run being relaxed (uniform)
+    for (int q0 = 0; q0 < count; q0 += kChunk) {
+        const int qend = min(count, q0 + kChunk);
+        if (q0 > 0) {
+#pragma unroll
+            for (int k = 0; k < kHeld; ++k)
+                if (q0 + t + k * kBlkThreads < qend) blk_load<T, MODE>(sv, c0 + q0 + t + k * kBlkThreads, held[k]);
+        }
+        while (run < ncol && cstart[run] < qend) {
+            const int qa = max(cstart[run], q0), qb = min(cstart[run + 1], qend);
+#pragma unroll
+            for (int k = 0; k < kHeld; ++k) {
+                const int q = q0 + t + k * kBlkThreads;
+                if (q < qa || q >= qb) continue;
+                const HeldContact<T> &h = held[k];
+                if (MODE == 0 && h.P[0] == T(0) && h.P[1] == T(0) && h.P[2] == T(0)) continue;
+                const int64_t p = c0 + q;
+                const int l1 = (int)(int16_t)(h.ls & 0xffff), l2 = (int)(int16_t)((uint32_t)h.ls >> 16);
+                Rec<T> r1, r2;
+                blk_end_rec(Vs, ns, vel, l1, sv.j1, p, r1);
+                blk_end_rec(Vs, ns, vel, l2, sv.j2, p, r2);
+                if (MODE == 0) {
+                    apply(r1, r2, h.n, h.a1, h.a2, h.P);
+                } else {
+                    T Pnew[3], dP[3];
+                    relax_contact(h.n, h.bias, h.a1, h.a2, h.P, mu, relax, r1, r2, Pnew, dP);
+                    sv.px[p] = Pnew[0];
+                    sv.py[p] = Pnew[1];
+                    sv.pz[p] = Pnew[2];
+                    const double d0 = dP[0], d1 = dP[1], d2 = dP[2];
+                    const double e0 = Pnew[0], e1 = Pnew[1], e2 = Pnew[2];
+                    sd += d0 * d0 + d1 * d1 + d2 * d2;
+                    sp += e0 * e0 + e1 * e1 + e2 * e2;
+                }
+                blk_store_rec(Vs, ns, l1, r1);
+                blk_store_rec(Vs, ns, l2, r2);
+            }
+            __syncthreads();
+            if (cstart[run + 1] > qend) break;  // the run goes on in the next chunk
+            ++run;
+        }
+    }
+    for (int i = threadIdx.x; i < ns; i += kBlkThreads) {
+        T *r = vel + 8 * (int64_t)slot_body[s0 + i];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) r[a] = Vs[a * ns + i];
+    }
+    if (MODE == 1) {
+        __shared__ double red[2][kBlkThreads / 64];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sd += __shfl_xor(sd, o, 64);
+            sp += __shfl_xor(sp, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = sd;
+            red[1][threadIdx.x >> 6] = sp;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0, c = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlkThreads / 64; ++w) {
+                a += red[0][w];
+                c += red[1][w];
+            }
+            partials[2 * s + 0] = a;
+            partials[2 * s + 1] = c;
+        }
+    }
+}
+
+// The same pass with each colour run's contacts loaded when the run starts
+// (one thread per contact of the run, 128 threads): fewer registers, so more
+// workgroups per CU hide the load of each run; the faster form for FP32 records.
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBlkStreamThreads) k_blk_pass_stream(SubView<T> sv, int32_t nb, T *vel, T mu, T relax,
                                                           const int64_t *tile_off, const int32_t *tile_slot_off,
                                                           const int32_t *slot_body, const int32_t *blk_cs,
                                                           const int32_t *blk_nrun, double *partials,
@@ -603,17 +785,17 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t
     __shared__ int32_t cstart[kMaxCol + 1];
     const int32_t *cs = blk_cs + c0 + s;  // the block's colour runs
     const int ncol = blk_nrun[s];
-    for (int i = threadIdx.x; i < ns; i += kBlkThreads) {
+    for (int i = threadIdx.x; i < ns; i += kBlkStreamThreads) {
         const T *r = vel + 8 * (int64_t)slot_body[s0 + i];
 #pragma unroll
         for (int a = 0; a < 8; ++a) Vs[a * ns + i] = r[a];
     }
-    for (int c = threadIdx.x; c <= ncol; c += kBlkThreads) cstart[c] = cs[c];
+    for (int c = threadIdx.x; c <= ncol; c += kBlkStreamThreads) cstart[c] = cs[c];
     __syncthreads();
     double sd = 0.0, sp = 0.0;
     for (int c = 0; c < ncol; ++c) {
         const int64_t pa = c0 + cstart[c], pb = c0 + cstart[c + 1];
-        for (int64_t p = pa + threadIdx.x; p < pb; p += kBlkThreads) {
+        for (int64_t p = pa + threadIdx.x; p < pb; p += kBlkStreamThreads) {
             const int l1 = sv.ls[2 * p], l2 = sv.ls[2 * p + 1];
             // body indices are read only for ends outside the block's slots (walls and static bodies)
             const int b1 = l1 >= 0 ? 0 : sv.j1[p], b2 = l2 >= 0 ? 0 : sv.j2[p];
@@ -696,13 +878,13 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < ns; i += kBlkThreads) {
+    for (int i = threadIdx.x; i < ns; i += kBlkStreamThreads) {
         T *r = vel + 8 * (int64_t)slot_body[s0 + i];
 #pragma unroll
         for (int a = 0; a < 6; ++a) r[a] = Vs[a * ns + i];
     }
     if (MODE == 1) {
-        __shared__ double red[2][kBlkThreads / 64];
+        __shared__ double red[2][kBlkStreamThreads / 64];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             sd += __shfl_xor(sd, o, 64);
@@ -716,7 +898,7 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t
         if (threadIdx.x == 0) {
             double a = 0.0, c = 0.0;
 #pragma unroll
-            for (int w = 0; w < kBlkThreads / 64; ++w) {
+            for (int w = 0; w < kBlkStreamThreads / 64; ++w) {
                 a += red[0][w];
                 c += red[1][w];
             }
@@ -1160,14 +1342,26 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
     const int32_t B = sc->blk_grid_ids;
     for (int32_t id0 = 0; id0 < sc->n_blk; id0 += B) {
         const unsigned grid = (unsigned)std::min(B, sc->n_blk - id0);
-        if (mode == 0)
-            k_blk_pass<T, 0><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
-                                                             sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
-                                                             sc->blk_nrun.p, sc->partials.p, sc->ctrl(), id0);
-        else
-            k_blk_pass<T, 1><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
-                                                             sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
-                                                             sc->blk_nrun.p, sc->partials.p, sc->ctrl(), id0);
+        // FP64 records: the held form; FP32 records: the streamed form (the faster of the two for each)
+        if constexpr (sizeof(T) == 8) {
+            if (mode == 0)
+                k_blk_pass<T, 0><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
+                                                                 sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
+                                                                 sc->blk_nrun.p, sc->partials.p, sc->ctrl(), id0);
+            else
+                k_blk_pass<T, 1><<<grid, kBlkThreads, lds, s>>>(v, sc->b.n, vel, mu, relax, sc->tile_off.p,
+                                                                 sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
+                                                                 sc->blk_nrun.p, sc->partials.p, sc->ctrl(), id0);
+        } else {
+            if (mode == 0)
+                k_blk_pass_stream<T, 0><<<grid, kBlkStreamThreads, lds, s>>>(
+                    v, sc->b.n, vel, mu, relax, sc->tile_off.p, sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
+                    sc->blk_nrun.p, sc->partials.p, sc->ctrl(), id0);
+            else
+                k_blk_pass_stream<T, 1><<<grid, kBlkStreamThreads, lds, s>>>(
+                    v, sc->b.n, vel, mu, relax, sc->tile_off.p, sc->tile_slot_off.p, slot_body, sc->blk_cs.p,
+                    sc->blk_nrun.p, sc->partials.p, sc->ctrl(), id0);
+        }
         NBGS_HIP(hipGetLastError());
     }
     return NBGS_OK;
