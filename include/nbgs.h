@@ -141,7 +141,7 @@ const char *nbgs_last_error(void);
 
 /* Bytes of device workspace a scene of n_bodies bodies with up to
  * contact_capacity contacts needs, in the classic order in every precision
- * and warm start (an upper bound: per body 613 B, per contact 1,000 B, plus a
+ * and warm start (an upper bound: per body 567 B, per contact 1,000 B, plus a
  * cell table of 2^16 cells, 16 MiB, and ten per cent), a multiple of 256 (all
  * of it usable from a 256-byte aligned base).  The block-local order and the
  * subdomain solver add 88 B per id (nbgs_scene_workspace_query).  params

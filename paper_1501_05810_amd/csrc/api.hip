@@ -139,10 +139,11 @@ const void *Arena::relocate(const void *old) const {
 // Upper bound of a sphere scene's device memory (nbgs_workspace_query): every
 // buffer at its largest size for n bodies in `scenes` scenes and c contacts,
 // with the growth slack of the buffers that grow, in every sweep order,
-// precision and warm start.  Per body 613 B (detection 148 B, accumulator
+// precision and warm start.  Per body 567 B (detection 180 B, accumulator
 // records of both precisions 96 B, block and subdomain tables of blocks
-// holding eight bodies or more on average 165 B, cells of 16 B at most eight
-// per body 160 B, and the rest); per contact 1000 B (two contact tables 192 B, sweep
+// holding eight bodies or more on average 165 B, cell ranges of 8 B and
+// their occupancy bits at most eight per body 82 B, and the rest); per
+// contact 1000 B (two contact tables 192 B, sweep
 // records of both precisions 168 B, colouring 36 B, learned start 156 B,
 // subdomain ends, slots and corrections 208 B, partial sums and tuning copies
 // 40 B, times 1.25); per scene its cell table of at least 2^16 cells and its
@@ -151,7 +152,7 @@ const void *Arena::relocate(const void *old) const {
 // between freed buffers.  The per-id tables of the block-local order and of the
 // subdomain solver come on top (scene_need_bytes).
 size_t scene_workspace_bytes(int64_t n, int64_t c, int64_t scenes) {
-    const double per_body = 613.0, per_contact = 1000.0, per_scene = 65536.0 * 16.0 * 1.25 + 4096.0;
+    const double per_body = 567.0, per_contact = 1000.0, per_scene = 65536.0 * 9.0 * 1.25 + 4096.0;
     const double fixed = 16.0 * 1024.0 * 1024.0;
     const double b = 1.1 * (per_body * (double)n + per_contact * (double)c + per_scene * (double)scenes + fixed);
     return ((size_t)b + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1);  // all of it usable at an aligned base
@@ -275,7 +276,8 @@ Grid grid_for_box(const double lo[3], const double hi[3], const int32_t periodic
         dims[a] = (int64_t)c;
         edge[a] = periodic[a] ? L / c : cell;
     }
-    // keep the table within a few cells per body
+    // keep the table within a few cells per body (a finer grid means fewer hull tests; the neighbour search reads
+    // the records of occupied cells only)
     const int64_t cap = std::max<int64_t>(8 * n, 1 << 16);
     while (dims[0] * dims[1] * dims[2] > cap) {
         for (int a = 0; a < 3; ++a) {
@@ -445,26 +447,20 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_TRY(make_grid(sc, max_reach));
     // cell list
     const SceneTable tab = sc->table();
-    NBGS_TRY(launch_cell_keys(sc->b, sc->grid, tab, sc->keys.p, sc->ids.p, s));
+    NBGS_TRY(launch_cell_keys(sc->b, sc->grid, tab, sc->h.p, sc->keys.p, sc->ids.p, sc->xr.p, s));
     bool alt = false;
     NBGS_TRY(radix_sort_pairs(sc->keys.p, sc->ids.p, sc->keys2.p, sc->ids2.p, N, sc->grid.key_bits,
                               sc->radix_hist.p, sc->scan_tmp.p, sc->scan_tmp.cap, &alt, s));
     const uint32_t *skeys = alt ? sc->keys2.p : sc->keys.p;
     const uint32_t *sids = alt ? sc->ids2.p : sc->ids.p;
-    if ((size_t)sc->grid.ncells > sc->cells.cap) {
-        NBGS_TRY(sc->cells.reserve(sc->grid.ncells));
-        NBGS_HIP(hipMemsetAsync(sc->cells.p, 0, sizeof(int4) * sc->cells.cap, s));
-        sc->stamp = 0;
-    }
-    if (++sc->stamp == 0) {  // wrapped: clear the table once
-        NBGS_HIP(hipMemsetAsync(sc->cells.p, 0, sizeof(int4) * sc->cells.cap, s));
-        sc->stamp = 1;
-    }
-    NBGS_TRY(launch_cells(sc->b, sc->grid, skeys, sids, sc->h.p, sc->cells.p, sc->stamp, sc->sxr.p, sc->cellpos.p, s));
+    // cell ranges (entries of occupied cells are rewritten every step) and the occupancy bitmap
+    NBGS_TRY(sc->cells.reserve(sc->grid.ncells));
+    NBGS_TRY(sc->occ.reserve(((size_t)sc->grid.ncells + 31) / 32));
+    NBGS_TRY(launch_cells(N, sc->grid.ncells, skeys, sids, sc->xr.p, sc->cells.p, sc->occ.p, sc->sxr.p, s));
     // count, scan, emit
     NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
-                               sc->cells.p, sc->stamp, sc->cnt.p,
-                               sc->npart.p, sc->partners.p, sc->maxbits.p + 1, s));
+                               sc->cells.p, sc->occ.p, sc->cnt.p,
+                               sc->npart.p, sc->partners.p, sc->cellpos.p, sc->maxbits.p + 1, s));
     NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, N, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_HIP(hipMemcpyAsync(sc->pinned + 4, sc->maxbits.p + 1, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                             s));
@@ -509,7 +505,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     ContactBuf &cb = sc->cb[sc->cur];
     NBGS_TRY(cb.reserve((size_t)nc));
     NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
-                              sc->cells.p, sc->stamp, sc->cnt.p, sc->off.p,
+                              sc->cells.p, sc->occ.p, sc->cnt.p, sc->off.p,
                               sc->cellpos.p, sc->npart.p, sc->partners.p, cb.view(), nc, s));
     // initial impulses and, when the previous table carries colours, the start of the colouring
     const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
@@ -1350,6 +1346,7 @@ nbgs_status scene_create(void *workspace, size_t workspace_bytes, const nbgs_bod
     chk(sc->keys2.reserve(N, 1.0));
     chk(sc->ids2.reserve(N, 1.0));
     chk(sc->sxr.reserve(N, 1.0));
+    chk(sc->xr.reserve(N, 1.0));
     chk(sc->cnt.reserve(N + 1, 1.0));
     chk(sc->npart.reserve(N, 1.0));
     chk(sc->partners.reserve((size_t)kPartnerCap * N, 1.0));

@@ -4,8 +4,10 @@
 // h_i = dt (|v_i| + |w_i| r_i) + tau (eq. (expansionradius)), lies in the cell
 // of its centre, and the cell edge is at least the largest hull diameter, so
 // partners of a body are found in the 27 surrounding cells.  Bodies are radix
-// sorted by cell key; a stamp-validated table gives each occupied cell its
-// range of sorted positions (no per-step clearing of the table).
+// sorted by cell key; a table gives each occupied cell its range of sorted
+// positions, and a bitmap of the occupied cells (cleared every step, 1 bit per
+// cell) says which entries of the table are current, so that the neighbour
+// search loads the records of occupied cells only.
 //
 // Narrow phase: eq. (contactpos) has a closed form for spheres (contact point
 // on the surface of j2, normal from j2 to j1) and for wall planes.
@@ -28,11 +30,15 @@ constexpr int kBlock = 256;
 
 inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
 
+// Workgroups of the hull pass: each walks bodies i, i + kHullBlocks kBlock, ...
+// and adds one atomic maximum, so a few thousand atomics meet on the largest
+// hull rather than one per 256 bodies.
+constexpr int kHullBlocks = 2048;
+
 __global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double tau, double *h,
                                                  unsigned long long *max_bits) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double rh = 0.0;
-    if (i < b.n) {
+    double rmax = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < b.n; i += gridDim.x * kBlock) {
         const double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
         const double wx = b.wx[i], wy = b.wy[i], wz = b.wz[i];
         const double r = b.radius[i];
@@ -40,15 +46,16 @@ __global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double
         const double spin = sqrt(wx * wx + wy * wy + wz * wz);
         const double hi = dt * (speed + spin * r) + tau;
         h[i] = hi;
-        rh = r + hi;
+        double rh = r + hi;
         if (!(rh == rh)) rh = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf: caught on the host
+        rmax = fmax(rmax, rh);
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) rh = fmax(rh, __shfl_xor(rh, o, 64));
+    for (int o = 32; o > 0; o >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
     __shared__ double wmax[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = rh;
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = rmax;
     __syncthreads();
-    if (threadIdx.x == 0) {  // one atomic per block: the largest hull is order-independent
+    if (threadIdx.x == 0) {  // the largest hull is order-independent
         double m = wmax[0];
         for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, wmax[w]);
         atomicMax(max_bits, (unsigned long long)__double_as_longlong(m));
@@ -66,36 +73,47 @@ __device__ inline const Grid &grid_of(const Grid &g, const SceneTable &st, int i
     return st.body_scene ? st.grids[st.body_scene[i]] : g;
 }
 
-__global__ void __launch_bounds__(kBlock) k_cell_keys(BodiesView b, Grid g0, SceneTable st, uint32_t *keys,
-                                                      uint32_t *ids) {
+// Cell key of every body and its packed record (centre, +-(r + h), the sign
+// marking static bodies) in body order, for the one gather of k_cells.
+__global__ void __launch_bounds__(kBlock) k_cell_keys(BodiesView b, Grid g0, SceneTable st, const double *h,
+                                                      uint32_t *keys, uint32_t *ids, double4 *xr) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= b.n) return;
     const Grid &g = grid_of(g0, st, i);
-    const int cx = cell_coord(b.x[i], g.lo[0], g.edge[0], g.dims[0]);
-    const int cy = cell_coord(b.y[i], g.lo[1], g.edge[1], g.dims[1]);
-    const int cz = cell_coord(b.z[i], g.lo[2], g.edge[2], g.dims[2]);
+    const double x = b.x[i], y = b.y[i], z = b.z[i];
+    const int cx = cell_coord(x, g.lo[0], g.edge[0], g.dims[0]);
+    const int cy = cell_coord(y, g.lo[1], g.edge[1], g.dims[1]);
+    const int cz = cell_coord(z, g.lo[2], g.edge[2], g.dims[2]);
     keys[i] = g.cell_off + (uint32_t)((cz * g.dims[1] + cy) * g.dims[0] + cx);
     ids[i] = (uint32_t)i;
+    const double rh = b.radius[i] + h[i];
+    xr[i] = make_double4(x, y, z, b.inv_mass[i] == 0.0 ? -rh : rh);
 }
 
-// Cell ranges from the sorted keys, a sorted copy of (centre, +-(r + h))
-// for coalesced neighbour reads (the sign marks static bodies), and each
-// body's sorted position.
-__global__ void __launch_bounds__(kBlock) k_cells(BodiesView b, int32_t n, const uint32_t *skeys,
-                                                  const uint32_t *sids, const double *h, int4 *cells, uint32_t stamp,
-                                                  double4 *sxr, int32_t *cellpos) {
+// Cell ranges from the sorted keys (the first body of a cell's run writes its
+// start, the last one the end), the cells' occupancy bits, and the packed
+// records in sorted order (for coalesced neighbour reads).  The keys rise
+// along the wave, so lanes whose cells share a bitmap word are neighbours: the
+// word's bits are OR-ed across them and set by one atomic.
+__global__ void __launch_bounds__(kBlock) k_cells(int32_t n, const uint32_t *skeys, const uint32_t *sids,
+                                                  const double4 *xr, int2 *cells, uint32_t *occ, double4 *sxr) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t key = skeys[p];
-    if (p == 0 || skeys[p - 1] != key) {
-        cells[key].x = p;
-        cells[key].z = (int)stamp;
+    const int lane = threadIdx.x & 63;
+    const bool valid = p < n;
+    const uint32_t key = valid ? skeys[p] : 0xffffffffu;
+    const bool first = valid && (p == 0 || skeys[p - 1] != key);
+    if (first) cells[key].x = p;
+    if (valid && (p == n - 1 || skeys[p + 1] != key)) cells[key].y = p + 1;
+    if (valid) sxr[p] = xr[sids[p]];
+    const uint32_t word = key >> 5;
+    uint32_t bits = first ? (1u << (key & 31u)) : 0u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {  // OR over the following lanes of the same word
+        const uint32_t ow = __shfl_down(word, o, 64), ob = __shfl_down(bits, o, 64);
+        if (lane + o < 64 && ow == word) bits |= ob;
     }
-    if (p == n - 1 || skeys[p + 1] != key) cells[key].y = p + 1;
-    const int i = (int)sids[p];
-    cellpos[i] = p;
-    const double rh = b.radius[i] + h[i];
-    sxr[p] = make_double4(b.x[i], b.y[i], b.z[i], b.inv_mass[i] == 0.0 ? -rh : rh);
+    const uint32_t prev_word = __shfl_up(word, 1, 64);
+    if (valid && bits && (lane == 0 || prev_word != word)) atomicOr(&occ[word], bits);
 }
 
 __device__ inline double min_image(double d, int periodic, double L) {
@@ -171,23 +189,32 @@ constexpr int kMaxCandidates = 1 << 18;
 // keeps the first `cap` partners found in out_k (the emit variant keeps all).
 template <bool kEmit>
 __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const uint32_t *sids, const double4 *sxr,
-                                     const int4 *cells,
-                                     uint32_t stamp, int p, int i, int32_t *out_k, int cap = 0) {
+                                     const int2 *cells, const uint32_t *occ, int p, int i, int32_t *out_k,
+                                     int cap = 0) {
     const double4 me = sxr[p];
     int c[3];
     const NeighbourRange nr = neighbour_range(skeys[p], g, c);
     int m = 0, seen = 0;
     for (int dz = nr.lo[2]; dz <= nr.hi[2]; ++dz)
-        for (int dy = nr.lo[1]; dy <= nr.hi[1]; ++dy)
-            for (int dx = nr.lo[0]; dx <= nr.hi[0]; ++dx) {
-                const int cell = neighbour_cell(g, c, dx, dy, dz);
-                // the cell's record (start, end, stamp) is read in one 16-byte load; a range whose stamp is stale is
-                // left unused
-                const int cc = cell < 0 ? 0 : cell;
-                const int4 cr = cells[cc];
-                const uint32_t cs = (uint32_t)cr.z;
-                const int q0 = cr.x, q1 = cr.y;
-                if (cell < 0 || cs != stamp) continue;
+        for (int dy = nr.lo[1]; dy <= nr.hi[1]; ++dy) {
+            // the row's (up to) three cells: their occupancy bits first, then the ranges (start, end) of the
+            // occupied ones, loaded together
+            int cell[3];
+            bool used[3];
+            int2 cr[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int dx = nr.lo[0] + t;
+                cell[t] = dx <= nr.hi[0] ? neighbour_cell(g, c, dx, dy, dz) : -1;
+                const uint32_t cc = cell[t] < 0 ? 0u : (uint32_t)cell[t];
+                used[t] = cell[t] >= 0 && ((occ[cc >> 5] >> (cc & 31u)) & 1u);
+            }
+#pragma unroll
+            for (int t = 0; t < 3; ++t) cr[t] = used[t] ? cells[cell[t]] : make_int2(0, 0);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                if (!used[t]) continue;
+                const int q0 = cr[t].x, q1 = cr[t].y;
                 if (!kEmit) {
                     seen += q1 - q0;
                     if (seen > kMaxCandidates) return -1;
@@ -202,38 +229,54 @@ __device__ inline int visit_partners(const Grid &g, const uint32_t *skeys, const
                     ++m;
                 }
             }
+        }
     return m;
+}
+
+// Workgroups are dispatched to the 8 XCDs in turn (b mod 8), each XCD with its
+// own L2.  This bijection hands XCD x a contiguous run of the tiles, so the
+// neighbour reads of a body (cells one row and one plane away in sorted
+// order) find the data its XCD's earlier workgroups loaded.
+__device__ inline unsigned xcd_tile(unsigned b, unsigned nb) {
+    const unsigned q = nb / 8, r = nb % 8, x = b % 8, l = b / 8;
+    return x * q + (x < r ? x : r) + l;
 }
 
 __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                        const uint32_t *skeys, const uint32_t *sids,
                                                        const double4 *sxr, const double *h,
-                                                       const int4 *cells, uint32_t stamp, int32_t *cnt,
-                                                       int32_t *npart, int32_t *partners,
+                                                       const int2 *cells, const uint32_t *occ, int32_t *cnt,
+                                                       int32_t *npart, int32_t *partners, int32_t *cellpos,
                                                        unsigned long long *total) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
+    const int p = (int)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     unsigned long long m64 = 0;
     int over = 0;
     if (p < b.n) {
         const int i = (int)sids[p];
         const int sc = st.body_scene ? st.body_scene[i] : 0;
-        const Grid &g = st.body_scene ? st.grids[sc] : g0;
+        const Grid g = st.body_scene ? st.grids[sc] : g0;  // a copy: read once, not at every cell and candidate
         const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
-        int m = visit_partners<false>(g, skeys, sids, sxr, cells, stamp, p, i,
+        int m = visit_partners<false>(g, skeys, sids, sxr, cells, occ, p, i,
                                       partners + (int64_t)kPartnerCap * i, kPartnerCap);
         if (m < 0) {
             over = 1;
             m = 0;
         }
-        npart[i] = m;
-        if (b.inv_mass[i] != 0.0) {
-            const double4 me = sxr[p];
+        const int mp = m;
+        const double4 me = sxr[p];
+        if (pl.n > 0 && me.w >= 0.0) {  // a dynamic body (the sign of its packed reach) meets the walls
             const double r = b.radius[i], hi = h[i];
             double gap;
             for (int w = 0; w < pl.n; ++w)
                 if (plane_hit(pl, w, me.x, me.y, me.z, r, hi, tau, &gap)) ++m;
         }
-        cnt[i] = m;
+        // cnt holds zeros (filled before the count); only bodies with contacts are written, and the emit reads
+        // npart and the sorted position of those alone
+        if (m > 0) {
+            cnt[i] = m;
+            npart[i] = mp;
+            cellpos[i] = p;
+        }
         m64 = (unsigned long long)m;
     }
     // The list length in 64 bits (the 32-bit scan of the counts would wrap
@@ -304,14 +347,14 @@ __device__ inline void sort_partners(int32_t *ks, int m) {
 __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
                                                       const uint32_t *skeys, const uint32_t *sids,
                                                       const double4 *sxr, const double *h,
-                                                      const int4 *cells, uint32_t stamp, const int32_t *cnt,
+                                                      const int2 *cells, const uint32_t *occ, const int32_t *cnt,
                                                       const int32_t *off, const int32_t *cellpos,
                                                       const int32_t *npart, const int32_t *partners, ContactsView c) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= b.n || cnt[i] == 0) return;
     const int p = cellpos[i];
     const int sc = st.body_scene ? st.body_scene[i] : 0;
-    const Grid &g = st.body_scene ? st.grids[sc] : g0;
+    const Grid g = st.body_scene ? st.grids[sc] : g0;
     const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
     const int wall0 = b.n + (st.body_scene ? st.wall_off[sc] : 0);
     const int base = off[i];
@@ -321,7 +364,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_emit(BodiesView b, Grid g0, Pla
         const int32_t *kept = partners + (int64_t)kPartnerCap * i;
         for (int t = 0; t < m; ++t) ks[t] = kept[t];
     } else {
-        m = visit_partners<true>(g, skeys, sids, sxr, cells, stamp, p, i, ks);
+        m = visit_partners<true>(g, skeys, sids, sxr, cells, occ, p, i, ks);
     }
     sort_partners(ks, m);
     for (int t = 0; t < m; ++t) c.j1[base + t] = i;
@@ -491,11 +534,19 @@ __global__ void __launch_bounds__(kBlock) k_dyn_bits(const double *inv_mass, int
     const bool dyn = i < n && inv_mass[i] > 0.0;
     const unsigned long long m = __ballot(dyn);
     const int64_t word = i >> 6;
-    if ((threadIdx.x & 63) == 0 && word * 64 < n) {
-        if (bits[word] != (uint64_t)m) {
-            bits[word] = (uint64_t)m;
-            atomicAdd(changed, 1);
-        }
+    int diff = 0;
+    if ((threadIdx.x & 63) == 0 && word * 64 < n && bits[word] != (uint64_t)m) {
+        bits[word] = (uint64_t)m;
+        diff = 1;
+    }
+    // one atomic per workgroup (the first detection changes every word)
+    __shared__ int wdiff[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wdiff[threadIdx.x >> 6] = diff;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wdiff[w];
+        if (t) atomicAdd(changed, t);
     }
 }
 
@@ -508,46 +559,52 @@ __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *p, int64_t n, int3
 
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
                         hipStream_t s) {
-    k_hull<<<grid_for(b.n), kBlock, 0, s>>>(b, dt, tau, h, max_bits);
+    if (b.n <= 0) return NBGS_OK;
+    const unsigned blocks = std::min<unsigned>(grid_for(b.n), (unsigned)kHullBlocks);
+    k_hull<<<blocks, kBlock, 0, s>>>(b, dt, tau, h, max_bits);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
-nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, uint32_t *keys, uint32_t *ids,
-                             hipStream_t s) {
-    k_cell_keys<<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, keys, ids);
+nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, const double *h,
+                             uint32_t *keys, uint32_t *ids, double4 *xr, hipStream_t s) {
+    if (b.n <= 0) return NBGS_OK;
+    k_cell_keys<<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, h, keys, ids, xr);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
-nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
-                         const double *h, int4 *cells,
-                         uint32_t stamp, double4 *sxr, int32_t *cellpos, hipStream_t s) {
-    (void)g;
-    k_cells<<<grid_for(b.n), kBlock, 0, s>>>(b, b.n, skeys, sids, h, cells, stamp, sxr,
-                                             cellpos);
+nbgs_status launch_cells(int32_t n, int64_t ncells, const uint32_t *skeys, const uint32_t *sids, const double4 *xr,
+                         int2 *cells, uint32_t *occ, double4 *sxr, hipStream_t s) {
+    const int64_t words = (ncells + 31) / 32;
+    k_fill_i32<<<grid_for(words), kBlock, 0, s>>>(reinterpret_cast<int32_t *>(occ), words, 0);
+    NBGS_HIP(hipGetLastError());
+    if (n <= 0) return NBGS_OK;
+    k_cells<<<grid_for(n), kBlock, 0, s>>>(n, skeys, sids, xr, cells, occ, sxr);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
-                              const int4 *cells,
-                              uint32_t stamp, int32_t *cnt, int32_t *npart, int32_t *partners,
+                              const int2 *cells, const uint32_t *occ, int32_t *cnt, int32_t *npart,
+                              int32_t *partners, int32_t *cellpos,
                               unsigned long long *total, hipStream_t s) {
     if (b.n <= 0) return NBGS_OK;
-    k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cells, stamp, cnt, npart, partners, total);
+    k_fill_i32<<<grid_for(b.n), kBlock, 0, s>>>(cnt, b.n, 0);
+    k_pair_count<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cells, occ, cnt, npart,
+                                                  partners, cellpos, total);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
 nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
-                             const int4 *cells,
-                             uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
+                             const int2 *cells, const uint32_t *occ, const int32_t *cnt, const int32_t *off,
+                             const int32_t *cellpos,
                              const int32_t *npart, const int32_t *partners, ContactsView c, int64_t nc,
                              hipStream_t s) {
-    k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cells, stamp, cnt, off, cellpos, npart, partners, c);
+    k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cells, occ, cnt, off, cellpos, npart, partners, c);
     NBGS_HIP(hipGetLastError());
     if (nc > 0) {
         k_pair_geometry<<<grid_for(nc), kBlock, 0, s>>>(b, g, pl, st, nc, c);

@@ -225,22 +225,19 @@ size_t radix_hist_entries(int64_t n);
 constexpr int kPartnerCap = 16;
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
                         hipStream_t s);
-nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, uint32_t *keys, uint32_t *ids,
-                             hipStream_t s);
-nbgs_status launch_cells(const BodiesView &b, const Grid &g, const uint32_t *skeys, const uint32_t *sids,
-                         const double *h, int4 *cells,
-                         uint32_t stamp, double4 *sxr, int32_t *cellpos, hipStream_t s);
+nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, const double *h,
+                             uint32_t *keys, uint32_t *ids, double4 *xr, hipStream_t s);
+nbgs_status launch_cells(int32_t n, int64_t ncells, const uint32_t *skeys, const uint32_t *sids, const double4 *xr,
+                         int2 *cells, uint32_t *occ, double4 *sxr, hipStream_t s);
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                               const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
-                              const int4 *cells,
-                              uint32_t stamp, int32_t *cnt, int32_t *npart, int32_t *partners,
-                              unsigned long long *total, hipStream_t s);
+                              const int2 *cells, const uint32_t *occ, int32_t *cnt, int32_t *npart,
+                              int32_t *partners, int32_t *cellpos, unsigned long long *total, hipStream_t s);
 nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
-                             const int4 *cells,
-                             uint32_t stamp, const int32_t *cnt, const int32_t *off, const int32_t *cellpos,
-                             const int32_t *npart, const int32_t *partners, ContactsView c, int64_t nc,
-                             hipStream_t s);
+                             const int2 *cells, const uint32_t *occ, const int32_t *cnt, const int32_t *off,
+                             const int32_t *cellpos, const int32_t *npart, const int32_t *partners, ContactsView c,
+                             int64_t nc, hipStream_t s);
 nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
                               const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
                               int64_t n_prev, double mu, const SceneTable &st, bool impulses, bool colours,

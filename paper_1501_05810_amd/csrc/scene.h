@@ -104,15 +104,16 @@ struct nbgs_scene_s {
     // per body
     DevBuf<double> h;
     DevBuf<uint32_t> keys, ids, keys2, ids2;
-    DevBuf<double4> sxr;
+    DevBuf<double4> sxr;  // packed records (centre, +-(r + h)) in sorted order
+    DevBuf<double4> xr;   // the same in body order
     DevBuf<int32_t> cnt, off, cellpos;
     DevBuf<int32_t> npart, partners;  // the pair count's partner store (kPartnerCap per body) for the emit
     DevBuf<int32_t> deg2, off2, cursor;
     DevBuf<double> vel64;
     DevBuf<float> vel32;
     // cells
-    DevBuf<int4> cells;  // per cell (start, end, stamp, -) of its sorted range, read in one 16-byte load
-    uint32_t stamp = 0;
+    DevBuf<int2> cells;     // per occupied cell (start, end) of its sorted range
+    DevBuf<uint32_t> occ;   // occupancy bitmap of the cells, rebuilt every step
     // scratch
     DevBuf<int32_t> radix_hist;
     DevBuf<char> scan_tmp;

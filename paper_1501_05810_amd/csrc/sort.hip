@@ -17,7 +17,7 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 
 constexpr int kRadixBlock = 256;
-constexpr int kRadixRounds = 8;
+constexpr int kRadixRounds = 16;
 constexpr int kRadixTile = kRadixBlock * kRadixRounds;
 constexpr int kRadixDigits = 256;
 constexpr int kWaves = kRadixBlock / 64;
@@ -147,16 +147,32 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const uint32_t *keys
         hist[(int64_t)d * nblocks + blockIdx.x] = cnt[d];
 }
 
-// Stable scatter: element order inside a block tile is (round, wave, lane),
-// which is the input order; the global offset of (digit, block) comes from
-// the digit-major scan of the histograms.
+// Stable scatter of one tile of kRadixTile elements.  Element order inside
+// the tile is (round, wave, lane), the input order; each element's place in
+// the tile sorted by digit (the tile's digit starts plus its stable rank) is
+// found with ballots and LDS counts, the tile is rearranged in LDS, and then
+// written out so that neighbouring threads store neighbouring elements of one
+// digit's run.  The global start of (digit, tile) comes from the digit-major
+// scan of the histograms; the tile's count of a digit is the difference of two
+// neighbouring scan entries (the last one's end is n).
 __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter(const uint32_t *keys, const uint32_t *vals,
                                                                uint32_t *okeys, uint32_t *ovals, int64_t n, int shift,
                                                                const int32_t *offs, int nblocks) {
-    __shared__ int run[kRadixDigits];
+    __shared__ uint32_t lk[kRadixTile], lv[kRadixTile];
+    __shared__ int gstart[kRadixDigits], lstart[kRadixDigits], run[kRadixDigits];
     __shared__ int wcnt[kWaves][kRadixDigits];
+    __shared__ int scan_lds[kRadixBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int d = tid; d < kRadixDigits; d += kRadixBlock) run[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+    static_assert(kRadixBlock == kRadixDigits, "one thread per digit");
+    {
+        const int64_t idx = (int64_t)tid * nblocks + blockIdx.x;
+        const int g = offs[idx];
+        const int next = idx + 1 < (int64_t)kRadixDigits * nblocks ? offs[idx + 1] : (int)n;
+        gstart[tid] = g;
+        int total;
+        lstart[tid] = block_exclusive_scan(next - g, scan_lds, &total);
+        run[tid] = 0;
+    }
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (int r = 0; r < kRadixRounds; ++r) {
@@ -178,19 +194,27 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter(const uint32_t *k
         if (valid && rank == 0) wcnt[wave][dig] = __popcll(peers);
         __syncthreads();
         if (valid) {
-            int dst = run[dig] + rank;
-            for (int w = 0; w < wave; ++w) dst += wcnt[w][dig];
-            okeys[dst] = k;
-            ovals[dst] = v;
+            int pos = lstart[dig] + run[dig] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
+            lk[pos] = k;
+            lv[pos] = v;
         }
         __syncthreads();
-        for (int d = tid; d < kRadixDigits; d += kRadixBlock) {
+        {
             int add = 0;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) add += wcnt[w][d];
-            run[d] += add;
+            for (int w = 0; w < kWaves; ++w) add += wcnt[w][tid];
+            run[tid] += add;
         }
-        __syncthreads();
+        __syncthreads();  // before the next round clears the wave counts
+    }
+    const int tile_n = (int)(n - base < (int64_t)kRadixTile ? n - base : (int64_t)kRadixTile);
+    for (int j = tid; j < tile_n; j += kRadixBlock) {
+        const uint32_t k = lk[j];
+        const uint32_t d = (k >> shift) & 255u;
+        const int dst = gstart[d] + (j - lstart[d]);
+        okeys[dst] = k;
+        ovals[dst] = lv[j];
     }
 }
 
