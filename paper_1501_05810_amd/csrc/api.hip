@@ -616,11 +616,16 @@ nbgs_status colour_and_order(nbgs_scene_t sc, ContactBuf &cb, const SceneTable &
     NBGS_TRY(launch_j2_fill(cb.view(), nc, N, sc->b.inv_mass, sc->cursor.p, sc->inc2.p, s));
     sc->colour_passes = 0;
     if (nc > 0 && warm_colours) {
-        // greedy rule repeated from the previous colours until a pass changes nothing
+        // greedy rule repeated from the previous colours until a pass changes nothing; after the first pass only
+        // the contacts a change reached are evaluated
+        NBGS_TRY(sc->dirty[0].reserve((size_t)nc));
+        NBGS_TRY(sc->dirty[1].reserve((size_t)nc));
         for (int pass = 0;; ++pass) {
             NBGS_HIP(hipMemsetAsync(sc->remaining(), 0, 2 * sizeof(int32_t), s));
+            const uint8_t *din = pass == 0 ? nullptr : sc->dirty[(pass + 1) & 1].p;
+            uint8_t *dout = sc->dirty[pass & 1].p;
             NBGS_TRY(launch_colour_fix(cb.view(), sc->prio.p, nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p, sc->off2.p,
-                                       sc->inc2.p, sdom, sc->remaining(), sc->overflow(), s));
+                                       sc->inc2.p, sdom, din, dout, sc->remaining(), sc->overflow(), s));
             NBGS_TRY(sync_small(sc, 1, 2));
             sc->colour_passes = pass + 1;
             if (sc->pinned[2]) {

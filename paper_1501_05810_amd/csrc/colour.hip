@@ -143,14 +143,21 @@ __global__ void __launch_bounds__(kBlock) k_jp_round(ContactsView c, const uint6
 // hist[c]: contacts of colour c; hist[256 + c]: dynamic bodies they touch
 // (the body records a sweep launch of colour c reads and writes).
 // One pass of colour(j) <- smallest colour not held by a higher-priority
-// neighbour; *changed counts the contacts whose colour moved.
+// neighbour; *changed counts the contacts whose colour moved.  With dirty_in
+// given, only the contacts it marks are evaluated: a contact's rule reads only
+// its higher-priority neighbours, so it can change only after one of them
+// did, and every contact that changes marks its lower-priority neighbours in
+// dirty_out (also those it had already been read by in this pass).  The
+// passes then touch the few contacts a change still reaches, and end at the
+// same fixed point.
 __global__ void __launch_bounds__(kBlock) k_colour_fix(ContactsView c, const uint64_t *prio, int64_t nc, int32_t nb,
                                                        const double *inv_mass, const int32_t *off1,
                                                        const int32_t *cnt1, const int32_t *off2,
-                                                       const int32_t *inc2, const int32_t *sdom, int32_t *changed,
+                                                       const int32_t *inc2, const int32_t *sdom,
+                                                       const uint8_t *dirty_in, uint8_t *dirty_out, int32_t *changed,
                                                        int32_t *overflow) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= nc) return;
+    if (j >= nc || (dirty_in && !dirty_in[j])) return;
     const int32_t sj = sdom ? sdom[j] : 0;
     const uint64_t kj = c.key[j], pj = prio[j];
     uint64_t used[kMaxColours / 64] = {0, 0, 0, 0};
@@ -184,7 +191,26 @@ __global__ void __launch_bounds__(kBlock) k_colour_fix(ContactsView c, const uin
     if (col != c.colour[j]) {
         __hip_atomic_store(&c.colour[j], col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         atomicAdd(changed, 1);
+        if (dirty_out) {  // the lower-priority neighbours read this colour
+            for (int e = 0; e < 2; ++e) {
+                const int b = ends[e];
+                if (b >= nb || !(inv_mass[b] > 0.0)) continue;
+                const int a0 = off1[b], a1 = a0 + cnt1[b];
+                for (int l = a0; l < a1; ++l)
+                    if (l != j && (!sdom || sdom[l] == sj) && precedes(pj, kj, prio[l], c.key[l])) dirty_out[l] = 1;
+                const int q1 = off2[b + 1];
+                for (int q = off2[b]; q < q1; ++q) {
+                    const int l = inc2[q];
+                    if (l != j && (!sdom || sdom[l] == sj) && precedes(pj, kj, prio[l], c.key[l])) dirty_out[l] = 1;
+                }
+            }
+        }
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_u8(uint8_t *p, int64_t n, uint8_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 __global__ void __launch_bounds__(kBlock) k_colour_hist(ContactsView c, int64_t nc, int32_t nb,
@@ -292,13 +318,23 @@ nbgs_status launch_jp_round(const ContactsView &c, const uint64_t *prio, int64_t
     return NBGS_OK;
 }
 
+nbgs_status launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
+    if (n <= 0) return NBGS_OK;
+    k_fill_u8<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
 nbgs_status launch_colour_fix(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
                               const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
-                              const int32_t *inc2, const int32_t *sdom, int32_t *changed, int32_t *overflow,
-                              hipStream_t s) {
+                              const int32_t *inc2, const int32_t *sdom, const uint8_t *dirty_in, uint8_t *dirty_out,
+                              int32_t *changed, int32_t *overflow, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    k_colour_fix<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, sdom, changed,
-                                                 overflow);
+    if (dirty_out) {
+        NBGS_TRY(launch_fill_u8(dirty_out, nc, 0, s));
+    }
+    k_colour_fix<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, sdom, dirty_in,
+                                                 dirty_out, changed, overflow);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

@@ -1090,7 +1090,7 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
         for (int pass = 0;; ++pass) {
             NBGS_HIP(hipMemsetAsync(sc->small.p + 1, 0, 2 * sizeof(int32_t), s));
             NBGS_TRY(launch_colour_fix(cv, sc->prio.p, nc, N, sc->b.inv_mass, sc->off1.p, sc->cnt1.p, sc->off2.p,
-                                       sc->inc2.p, nullptr, sc->small.p + 1, sc->small.p + 2, s));
+                                       sc->inc2.p, nullptr, nullptr, nullptr, sc->small.p + 1, sc->small.p + 2, s));
             NBGS_TRY(sync_small(sc, 1, 2));
             if (sc->pinned[2]) {
                 set_error("more than 255 colours needed");

@@ -129,6 +129,7 @@ struct nbgs_scene_s {
     int64_t nc = 0, n_prev = 0;
     int64_t nc_needed = -1;  // the contact count the last detection found (reported with CAPACITY)
     DevBuf<int32_t> inc2;
+    DevBuf<uint8_t> dirty[2];  // colouring passes: the contacts a change reached (ping-pong)
     DevBuf<uint64_t> prio;
     bool prev_colours = false;  // the previous table holds the colours of its contact set
     int32_t colour_passes = 0;  // > 0: passes from the previous colours, < 0: Jones-Plassmann rounds

@@ -126,9 +126,24 @@ __global__ void __launch_bounds__(kBlock) k_block_local_grids(BodiesView b, cons
     id[j] = out;
 }
 
+// cnt[v[i]] += 1 for every i.  The inputs here are sorted (ids of a sweep
+// record, slots by id), so equal values sit in neighbouring lanes: each run of
+// equal values in a wave adds its length with one atomic (exact for any input).
 __global__ void __launch_bounds__(kBlock) k_hist(const int32_t *v, int64_t n, int32_t *cnt) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[v[i]], 1);
+    const int lane = threadIdx.x & 63;
+    const bool valid = i < n;
+    const int32_t x = valid ? v[i] : 0;
+    const int32_t xl = __shfl_up(x, 1, 64);
+    const bool start = valid && (lane == 0 || xl != x);
+    const unsigned long long starts = __ballot(start);
+    const int nvalid = __popcll(__ballot(valid));  // the valid lanes are a prefix of the wave
+    if (start) {
+        const unsigned long long above = lane == 63 ? 0ull : (starts & (~0ull << (lane + 1)));
+        int next = above ? __ffsll((long long)above) - 1 : 64;
+        if (next > nvalid) next = nvalid;
+        atomicAdd(&cnt[x], next - lane);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill(int32_t *p, int64_t n, int32_t v) {
