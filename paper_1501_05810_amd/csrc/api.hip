@@ -620,14 +620,21 @@ nbgs_status colour_and_order(nbgs_scene_t sc, ContactBuf &cb, const SceneTable &
         // the contacts a change reached are evaluated
         NBGS_TRY(sc->dirty[0].reserve((size_t)nc));
         NBGS_TRY(sc->dirty[1].reserve((size_t)nc));
-        for (int pass = 0;; ++pass) {
-            NBGS_HIP(hipMemsetAsync(sc->remaining(), 0, 2 * sizeof(int32_t), s));
-            const uint8_t *din = pass == 0 ? nullptr : sc->dirty[(pass + 1) & 1].p;
-            uint8_t *dout = sc->dirty[pass & 1].p;
-            NBGS_TRY(launch_colour_fix(cb.view(), sc->prio.p, nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p, sc->off2.p,
-                                       sc->inc2.p, sdom, din, dout, sc->remaining(), sc->overflow(), s));
+        // passes go out in growing batches between host checks (a pass after the fixed point finds nothing
+        // marked and changes nothing); the count read back is the last pass's
+        NBGS_HIP(hipMemsetAsync(sc->overflow(), 0, sizeof(int32_t), s));
+        int pass = 0, batch = 1;
+        for (;;) {
+            for (int r = 0; r < batch; ++r, ++pass) {
+                NBGS_HIP(hipMemsetAsync(sc->remaining(), 0, sizeof(int32_t), s));
+                const uint8_t *din = pass == 0 ? nullptr : sc->dirty[(pass + 1) & 1].p;
+                uint8_t *dout = sc->dirty[pass & 1].p;
+                NBGS_TRY(launch_colour_fix(cb.view(), sc->prio.p, nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p,
+                                           sc->off2.p, sc->inc2.p, sdom, din, dout, sc->remaining(), sc->overflow(),
+                                           s));
+            }
             NBGS_TRY(sync_small(sc, 1, 2));
-            sc->colour_passes = pass + 1;
+            sc->colour_passes = pass;
             if (sc->pinned[2]) {
                 set_error("more than 255 colours needed");
                 return NBGS_ERR_CAPACITY;
@@ -637,6 +644,7 @@ nbgs_status colour_and_order(nbgs_scene_t sc, ContactBuf &cb, const SceneTable &
                 set_error("colouring did not settle");
                 return NBGS_ERR_DEVICE;
             }
+            batch = batch < 8 ? 2 * batch : 8;
         }
     } else if (nc > 0) {
         NBGS_HIP(hipMemsetAsync(cb.colour.p, 0xff, sizeof(int32_t) * nc, s));

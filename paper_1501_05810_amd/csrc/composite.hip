@@ -923,6 +923,7 @@ struct nbgs_composite_s {
     DevBuf<int4> cells;  // per cell (start, end, stamp, -) of its sorted range
     DevBuf<int32_t> ebody, sbody, cellpos, cnt, off, off1, cnt1, deg2, off2, cursor, inc2,
         radix_hist, spos, small, ctrl, npart, partners;
+    DevBuf<uint8_t> dirty[2];  // colouring passes: the contacts a change reached (ping-pong)
     DevBuf<uint32_t> keys, ids, keys2, ids2, ckeys, cids, ckeys2, cids2;
     DevBuf<double4> ec, sec;
     DevBuf<double> h, owx, owy, owz, vel, iw, partials, hist;
@@ -1086,11 +1087,20 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
     NBGS_TRY(launch_j2_fill(cv, nc, N, sc->b.inv_mass, sc->cursor.p, sc->inc2.p, s));
     if (warm_colours) {
         // the greedy rule repeated from the previous colours until a pass changes nothing: its fixed point is the
-        // greedy colouring in priority order, the one the Jones-Plassmann rounds build from scratch
-        for (int pass = 0;; ++pass) {
-            NBGS_HIP(hipMemsetAsync(sc->small.p + 1, 0, 2 * sizeof(int32_t), s));
-            NBGS_TRY(launch_colour_fix(cv, sc->prio.p, nc, N, sc->b.inv_mass, sc->off1.p, sc->cnt1.p, sc->off2.p,
-                                       sc->inc2.p, nullptr, nullptr, nullptr, sc->small.p + 1, sc->small.p + 2, s));
+        // greedy colouring in priority order, the one the Jones-Plassmann rounds build from scratch; after the first
+        // pass only the contacts a change reached are evaluated
+        NBGS_TRY(sc->dirty[0].reserve((size_t)(nc > 0 ? nc : 1)));
+        NBGS_TRY(sc->dirty[1].reserve((size_t)(nc > 0 ? nc : 1)));
+        NBGS_HIP(hipMemsetAsync(sc->small.p + 2, 0, sizeof(int32_t), s));
+        int pass = 0, batch = 1;
+        for (;;) {
+            for (int r = 0; r < batch; ++r, ++pass) {
+                NBGS_HIP(hipMemsetAsync(sc->small.p + 1, 0, sizeof(int32_t), s));
+                const uint8_t *din = pass == 0 ? nullptr : sc->dirty[(pass + 1) & 1].p;
+                NBGS_TRY(launch_colour_fix(cv, sc->prio.p, nc, N, sc->b.inv_mass, sc->off1.p, sc->cnt1.p, sc->off2.p,
+                                           sc->inc2.p, nullptr, din, sc->dirty[pass & 1].p, sc->small.p + 1,
+                                           sc->small.p + 2, s));
+            }
             NBGS_TRY(sync_small(sc, 1, 2));
             if (sc->pinned[2]) {
                 set_error("more than 255 colours needed");
@@ -1101,6 +1111,7 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
                 set_error("colouring did not settle");
                 return NBGS_ERR_DEVICE;
             }
+            batch = batch < 8 ? 2 * batch : 8;
         }
     } else if (nc > 0) {
         NBGS_HIP(hipMemsetAsync(cb.colour.p, 0xff, sizeof(int32_t) * nc, s));
