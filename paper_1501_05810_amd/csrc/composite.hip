@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_keys(const double4 *ec, int64_t
 
 __global__ void __launch_bounds__(kBlock) k_cells(int64_t ne, const uint32_t *skeys, const uint32_t *sids,
                                                   const double4 *ec, const int32_t *ebody, int4 *cells, uint32_t stamp,
-                                                  double4 *sec, int32_t *sbody, int32_t *cellpos) {
+                                                  double4 *sec, int32_t *sbody) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= ne) return;
     const uint32_t key = skeys[p];
@@ -163,7 +163,6 @@ __global__ void __launch_bounds__(kBlock) k_cells(int64_t ne, const uint32_t *sk
     }
     if (p == ne - 1 || skeys[p + 1] != key) cells[key].y = (int32_t)(p + 1);
     const int e = (int)sids[p];
-    cellpos[e] = (int32_t)p;
     sec[p] = ec[e];
     sbody[p] = ebody[e];
 }
@@ -289,15 +288,26 @@ __device__ inline bool plane_hit(const PlaneSet &pl, int w, const double4 &c, do
     return gap <= hA + tau;
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn (b mod 8), each XCD with its
+// own L2: this bijection hands XCD x a contiguous run of the tiles, so that the
+// neighbour reads of an element find what its XCD's earlier workgroups loaded.
+__device__ inline unsigned xcd_tile(unsigned b, unsigned nb) {
+    const unsigned q = nb / 8, r = nb % 8, x = b % 8, l = b / 8;
+    return x * q + (x < r ? x : r) + l;
+}
+
 // One thread per sorted position (elements of a cell search the same cells).
+// cnt holds zeros (filled before the count): only elements with contacts are
+// written, with their partner count and sorted position (the emit reads those
+// of such elements alone).
 __global__ void __launch_bounds__(kBlock) k_pair_count(int64_t ne, Grid g, PlaneSet pl, double tau,
                                                        const uint32_t *skeys, const uint32_t *sids,
                                                        const double4 *sec, const int32_t *sbody,
                                                        const double *erad, const double *h,
                                                        const int4 *cells, uint32_t stamp, int32_t *cnt,
-                                                       int32_t *npart, int32_t *partners,
+                                                       int32_t *npart, int32_t *partners, int32_t *cellpos,
                                                        unsigned long long *total) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     unsigned long long m64 = 0;
     int over = 0;
     if (p < ne) {
@@ -309,14 +319,18 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(int64_t ne, Grid g, Plane
             over = 1;
             m = 0;
         }
-        npart[e] = m;
+        const int mp = m;
         const double4 me = sec[p];
-        if (me.w >= 0.0) {
+        if (me.w >= 0.0 && pl.n > 0) {
             double gap;
             for (int w = 0; w < pl.n; ++w)
                 if (plane_hit(pl, w, me, erad[e], h[A], tau, &gap)) ++m;
         }
-        cnt[e] = m;
+        if (m > 0) {
+            cnt[e] = m;
+            npart[e] = mp;
+            cellpos[e] = (int32_t)p;
+        }
         m64 = (unsigned long long)m;
     }
 #pragma unroll
@@ -1015,13 +1029,14 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
         NBGS_HIP(hipMemsetAsync(sc->cells.p, 0, sizeof(int4) * sc->cells.cap, s));
         sc->stamp = 1;
     }
-    k_cells<<<grid_for(E), kBlock, 0, s>>>(E, skeys, sids, sc->ec.p, sc->ebody.p, sc->cells.p, sc->stamp, sc->sec.p, sc->sbody.p, sc->cellpos.p);
+    k_cells<<<grid_for(E), kBlock, 0, s>>>(E, skeys, sids, sc->ec.p, sc->ebody.p, sc->cells.p, sc->stamp, sc->sec.p,
+                                           sc->sbody.p);
     NBGS_HIP(hipGetLastError());
+    NBGS_HIP(hipMemsetAsync(sc->cnt.p, 0, sizeof(int32_t) * (E + 1), s));  // zeros; cnt[E] makes off[E] the total
     k_pair_count<<<grid_for(E), kBlock, 0, s>>>(E, g, sc->planes, sc->p.tau, skeys, sids, sc->sec.p, sc->sbody.p,
-                                                sc->b.elem_radius, sc->h.p, sc->cells.p, sc->stamp, sc->cnt.p, sc->npart.p, sc->partners.p,
-                                                sc->maxbits.p + 1);
+                                                sc->b.elem_radius, sc->h.p, sc->cells.p, sc->stamp, sc->cnt.p,
+                                                sc->npart.p, sc->partners.p, sc->cellpos.p, sc->maxbits.p + 1);
     NBGS_HIP(hipGetLastError());
-    NBGS_HIP(hipMemsetAsync(sc->cnt.p + E, 0, sizeof(int32_t), s));  // off[E] = the total
     NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, E + 1, sc->small.p, sc->scan_tmp.p, sc->scan_tmp.cap, s));
     NBGS_HIP(hipMemcpyAsync(sc->pinned + 4, sc->maxbits.p + 1, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                             s));

@@ -248,10 +248,11 @@ __global__ void __launch_bounds__(kBlock) k_pair_count(BodiesView b, Grid g0, Pl
                                                        const int2 *cells, const uint32_t *occ, int32_t *cnt,
                                                        int32_t *npart, int32_t *partners, int32_t *cellpos,
                                                        unsigned long long *total) {
-    const int p = (int)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t p64 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int p = (int)(p64 < b.n ? p64 : 0);  // (the sorted position, below 2^31 when in range)
     unsigned long long m64 = 0;
     int over = 0;
-    if (p < b.n) {
+    if (p64 < b.n) {
         const int i = (int)sids[p];
         const int sc = st.body_scene ? st.body_scene[i] : 0;
         const Grid g = st.body_scene ? st.grids[sc] : g0;  // a copy: read once, not at every cell and candidate
