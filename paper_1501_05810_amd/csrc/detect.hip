@@ -84,7 +84,9 @@ __global__ void __launch_bounds__(kBlock) k_cell_keys(BodiesView b, Grid g0, Sce
     const int cx = cell_coord(x, g.lo[0], g.edge[0], g.dims[0]);
     const int cy = cell_coord(y, g.lo[1], g.edge[1], g.dims[1]);
     const int cz = cell_coord(z, g.lo[2], g.edge[2], g.dims[2]);
-    keys[i] = g.cell_off + (uint32_t)((cz * g.dims[1] + cy) * g.dims[0] + cx);
+    // the cell's coordinates in key order (g.axis[0] fastest)
+    auto along = [&](int a) { return a == 0 ? cx : (a == 1 ? cy : cz); };
+    keys[i] = g.cell_off + (uint32_t)((along(g.axis[2]) * g.kdims[1] + along(g.axis[1])) * g.kdims[0] + along(g.axis[0]));
     ids[i] = (uint32_t)i;
     const double rh = b.radius[i] + h[i];
     xr[i] = make_double4(x, y, z, b.inv_mass[i] == 0.0 ? -rh : rh);
@@ -127,16 +129,18 @@ struct NeighbourRange {
     int lo[3], hi[3];
 };
 
+// The cell of a key in key order (c[0] along the fastest key axis) and the
+// stencil's extent per key axis.
 __device__ inline NeighbourRange neighbour_range(uint32_t gkey, const Grid &g, int c[3]) {
     const uint32_t key = gkey - g.cell_off;
-    c[0] = (int)(key % (uint32_t)g.dims[0]);
-    const uint32_t t = key / (uint32_t)g.dims[0];
-    c[1] = (int)(t % (uint32_t)g.dims[1]);
-    c[2] = (int)(t / (uint32_t)g.dims[1]);
+    c[0] = (int)(key % (uint32_t)g.kdims[0]);
+    const uint32_t t = key / (uint32_t)g.kdims[0];
+    c[1] = (int)(t % (uint32_t)g.kdims[1]);
+    c[2] = (int)(t / (uint32_t)g.kdims[1]);
     NeighbourRange r;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (g.dims[a] == 1) {
+        if (g.kdims[a] == 1) {
             r.lo[a] = 0;
             r.hi[a] = 0;
         } else {
@@ -147,17 +151,18 @@ __device__ inline NeighbourRange neighbour_range(uint32_t gkey, const Grid &g, i
     return r;
 }
 
-// Linear index of neighbour cell c + d, or -1 outside a non-periodic axis.
+// Linear index of neighbour cell c + d (key order), or -1 outside a
+// non-periodic axis.
 __device__ inline int neighbour_cell(const Grid &g, const int c[3], int dx, int dy, int dz) {
     int q[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (q[a] < 0 || q[a] >= g.dims[a]) {
-            if (!g.periodic[a]) return -1;
-            q[a] = q[a] < 0 ? q[a] + g.dims[a] : q[a] - g.dims[a];
+        if (q[a] < 0 || q[a] >= g.kdims[a]) {
+            if (!g.kperiodic[a]) return -1;
+            q[a] = q[a] < 0 ? q[a] + g.kdims[a] : q[a] - g.kdims[a];
         }
     }
-    return (int)g.cell_off + (q[2] * g.dims[1] + q[1]) * g.dims[0] + q[0];
+    return (int)g.cell_off + (q[2] * g.kdims[1] + q[1]) * g.kdims[0] + q[0];
 }
 
 // Hull overlap of sorted entries (own, other): |x_i - x_k|^2 <= ((r_i + h_i) + (r_k + h_k))^2.
@@ -551,6 +556,35 @@ __global__ void __launch_bounds__(kBlock) k_dyn_bits(const double *inv_mass, int
     }
 }
 
+// Sums of the steps between consecutive bodies per axis (pairs i, i + 1 for
+// i < pairs), one partial per workgroup.
+__global__ void __launch_bounds__(kBlock) k_numbering_steps(BodiesView b, int64_t pairs, double *part) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < pairs; i += (int64_t)gridDim.x * kBlock) {
+        sx += fabs(b.x[i + 1] - b.x[i]);
+        sy += fabs(b.y[i + 1] - b.y[i]);
+        sz += fabs(b.z[i + 1] - b.z[i]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sx += __shfl_xor(sx, o, 64);
+        sy += __shfl_xor(sy, o, 64);
+        sz += __shfl_xor(sz, o, 64);
+    }
+    __shared__ double w[3][kBlock / 64];
+    if ((threadIdx.x & 63) == 0) {
+        w[0][threadIdx.x >> 6] = sx;
+        w[1][threadIdx.x >> 6] = sy;
+        w[2][threadIdx.x >> 6] = sz;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / 64; ++k) t += w[threadIdx.x][k];
+        part[3 * blockIdx.x + threadIdx.x] = t;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = v;
@@ -571,6 +605,12 @@ nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTabl
                              uint32_t *keys, uint32_t *ids, double4 *xr, hipStream_t s) {
     if (b.n <= 0) return NBGS_OK;
     k_cell_keys<<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, h, keys, ids, xr);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_numbering_steps(const BodiesView &b, int64_t pairs, double *part, int blocks, hipStream_t s) {
+    k_numbering_steps<<<blocks, kBlock, 0, s>>>(b, pairs, part);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

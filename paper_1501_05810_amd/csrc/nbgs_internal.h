@@ -169,7 +169,18 @@ struct Grid {
     int32_t ncells;
     int32_t key_bits;
     uint32_t cell_off;  // first global cell of this grid (several scenes share one cell table)
+    // Cell keys run fastest along axis[0], then axis[1], then axis[2]; kdims and
+    // kperiodic are dims and periodic in that order (the neighbour search works
+    // in key order, so the three cells of a stencil row are neighbours in the
+    // table).  The scene picks the order in which its bodies' numbering is
+    // most coherent.
+    int32_t axis[3];
+    int32_t kdims[3];
+    int32_t kperiodic[3];
 };
+
+// Key order of a grid's axes (axis[0] fastest); fills kdims and kperiodic.
+void grid_set_axes(Grid &g, const int32_t axis[3]);
 
 // Several independent scenes held in one body array (batching).  Every array
 // is indexed by scene except body_scene (by body).  All null for a single
@@ -227,6 +238,9 @@ nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, u
                         hipStream_t s);
 nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, const double *h,
                              uint32_t *keys, uint32_t *ids, double4 *xr, hipStream_t s);
+// Per workgroup b (gridDim.x of them) the sums over its sampled consecutive
+// body pairs (i, i + 1) of |x_{i+1} - x_i|, |y..|, |z..|: part[3 b + a].
+nbgs_status launch_numbering_steps(const BodiesView &b, int64_t pairs, double *part, int blocks, hipStream_t s);
 nbgs_status launch_cells(int32_t n, int64_t ncells, const uint32_t *skeys, const uint32_t *sids, const double4 *xr,
                          int2 *cells, uint32_t *occ, double4 *sxr, hipStream_t s);
 nbgs_status launch_pair_count(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st, double tau,

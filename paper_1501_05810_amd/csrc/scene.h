@@ -106,6 +106,8 @@ struct nbgs_scene_s {
     DevBuf<uint32_t> keys, ids, keys2, ids2;
     DevBuf<double4> sxr;  // packed records (centre, +-(r + h)) in sorted order
     DevBuf<double4> xr;   // the same in body order
+    int32_t key_axes[3] = {0, 1, 2};  // cell key order (axis[0] fastest), chosen on the first detection
+    bool key_axes_set = false;
     DevBuf<int32_t> cnt, off, cellpos;
     DevBuf<int32_t> npart, partners;  // the pair count's partner store (kPartnerCap per body) for the emit
     DevBuf<int32_t> deg2, off2, cursor;

@@ -108,18 +108,24 @@ nbgs_status restore_impulses(nbgs_scene_t sc, const Saved &sv) {
     return NBGS_OK;
 }
 
+// The fastest of three timed solves with shape t (a single short solve is
+// noisy enough to pick a shape that is slower by a third in the steps after).
 nbgs_status trial(nbgs_scene_t sc, const SweepTune &t, int32_t sweeps, const Saved &saved, hipEvent_t e0,
                   hipEvent_t e1, double &ms) {
     const int prec = sc->precision_used == NBGS_FP32_SWEEP ? 1 : 0;
     sc->tune[prec] = t;
-    NBGS_HIP(hipEventRecord(e0, sc->s));
-    NBGS_TRY(nbgs_solve(sc, sweeps, 0.0, nullptr));
-    NBGS_HIP(hipEventRecord(e1, sc->s));
-    NBGS_HIP(hipEventSynchronize(e1));
-    float f = 0.0f;
-    NBGS_HIP(hipEventElapsedTime(&f, e0, e1));
-    ms = (double)f;
-    return restore_impulses(sc, saved);
+    ms = 0.0;
+    for (int rep = 0; rep < 3; ++rep) {
+        NBGS_HIP(hipEventRecord(e0, sc->s));
+        NBGS_TRY(nbgs_solve(sc, sweeps, 0.0, nullptr));
+        NBGS_HIP(hipEventRecord(e1, sc->s));
+        NBGS_HIP(hipEventSynchronize(e1));
+        float f = 0.0f;
+        NBGS_HIP(hipEventElapsedTime(&f, e0, e1));
+        if (rep == 0 || (double)f < ms) ms = (double)f;
+        NBGS_TRY(restore_impulses(sc, saved));
+    }
+    return NBGS_OK;
 }
 
 }  // namespace
