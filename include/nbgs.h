@@ -304,6 +304,24 @@ nbgs_status nbgs_set_block_order(nbgs_scene_t scene, double edge);
  * 1 .. 8. */
 nbgs_status nbgs_set_block_grids(nbgs_scene_t scene, int32_t grids);
 
+/* The pair list of the detection (Sect. 4 broad phase), enable = 1 (the
+ * default) or 0.  With it a detection keeps every pair whose hulls would
+ * overlap with hull radius `skin` (max(4 max h, 0.02 max(r + h)) at the
+ * build) and, while every body's displacement since the build plus its hull
+ * plus its radius growth stays below the skin and no body changed between
+ * static and dynamic, finds the step's contacts by testing those pairs only
+ * (the same predicates as the cell-grid phase, so the same contacts, bit for
+ * bit); otherwise it rebuilds the list.  The list is kept only when the
+ * workspace has room for it beside everything the step may need (16 B per
+ * listed pair, 41 B per body); else every detection uses the cell grid.
+ * Setting it drops the current list.  Errors: INVALID_ARG (NULL). */
+nbgs_status nbgs_set_pair_list(nbgs_scene_t scene, int32_t enable);
+
+/* The pair list's state [host, each NULL-able]: *pairs = listed pairs (-1
+ * when no list is held), *skin its hull radius, *builds how many lists the
+ * scene has built. */
+nbgs_status nbgs_get_pair_list_info(nbgs_scene_t scene, int64_t *pairs, double *skin, int64_t *builds);
+
 /* enable = 1 (default): the residual R_k of every sweep is formed.  enable =
  * 0: a solve without a residual target forms only the last sweep's residual
  * (the one nbgs_stats reports); impulses and velocities are unchanged.  A

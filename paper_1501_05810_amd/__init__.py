@@ -103,6 +103,8 @@ _SIGNATURES = [
     ("nbgs_get_accumulators", C.c_int, [_vp, _vp, _vp]),
     ("nbgs_get_residuals", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("nbgs_set_warm_start", C.c_int, [_vp, C.c_int64, _vp, _vp]),
+    ("nbgs_set_pair_list", C.c_int, [_vp, C.c_int32]),
+    ("nbgs_get_pair_list_info", C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("nbgs_set_residual_history", C.c_int, [_vp, C.c_int32]),
     ("nbgs_set_subdomains", C.c_int, [_vp, C.c_double]),
     ("nbgs_set_block_order", C.c_int, [_vp, C.c_double]),
@@ -335,6 +337,16 @@ def nbgs_set_block_order(h: int, edge: float) -> None:
 
 def nbgs_set_block_grids(h: int, grids: int) -> None:
     _check(lib().nbgs_set_block_grids(_vp(h), int(grids)))
+
+
+def nbgs_set_pair_list(h: int, enable: bool) -> None:
+    _check(lib().nbgs_set_pair_list(_vp(h), 1 if enable else 0))
+
+
+def nbgs_get_pair_list_info(h: int) -> Dict:
+    n, sk, b = C.c_int64(), C.c_double(), C.c_int64()
+    _check(lib().nbgs_get_pair_list_info(_vp(h), C.byref(n), C.byref(sk), C.byref(b)))
+    return dict(pairs=int(n.value), skin=float(sk.value), builds=int(b.value))
 
 
 def nbgs_set_residual_history(h: int, enable: bool) -> None:
@@ -765,6 +777,14 @@ class GpuScene:
 
     def set_residual_history(self, enable: bool = True):
         nbgs_set_residual_history(self.handle, enable)
+
+    def set_pair_list(self, enable: bool = True):
+        """Keep (1) or drop (0) the detection's pair list; the contacts found are the same either way."""
+        nbgs_set_pair_list(self.handle, enable)
+        return self
+
+    def pair_list_info(self) -> Dict:
+        return nbgs_get_pair_list_info(self.handle)
 
     def set_subdomains(self, edge: float):
         """edge > 0: subdomain NBGS with blocks of about this edge from the next step on; 0: colour-order NBGS."""

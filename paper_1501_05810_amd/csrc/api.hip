@@ -468,45 +468,28 @@ nbgs_status gather_for_sweeps(nbgs_scene_t sc, bool indices) {
 nbgs_status colour_and_order(nbgs_scene_t sc, ContactBuf &cb, const SceneTable &tab, const int32_t *sdom,
                              bool warm_colours);
 
-nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
+// The broad and narrow phase on the cell grid (Sect. 4) with hull radii `hull`
+// and the largest reach `reach`: cell keys, sort, cell ranges, pair counts and
+// their scan; *total = the pair count, checked against the 32-bit and
+// candidate limits.  The emit follows separately.
+static nbgs_status grid_pairs(nbgs_scene_t sc, const double *hull, double reach, int64_t *total) {
     hipStream_t s = sc->s;
     const int32_t N = sc->b.n;
-    record(sc, kDetect);
-    if (sc->table_in_cur) {  // the solved impulses of the last step become the lookup table
-        sc->cur = 1 - sc->cur;
-        sc->table_in_cur = false;
-    }
-    ContactBuf &prev = sc->cb[1 - sc->cur];
-    // hull radii and the largest hull
-    // maxbits: [0] largest hull (bits of a non-negative double), [1] contact
-    // total in 64 bits, [2] candidate overflow of the pair count
-    NBGS_HIP(hipMemsetAsync(sc->maxbits.p, 0, 3 * sizeof(unsigned long long), s));
-    NBGS_TRY(launch_hull(sc->b, sc->p.dt, sc->p.tau, sc->h.p, sc->maxbits.p, s));
-    unsigned long long bits = 0;
-    NBGS_HIP(hipMemcpyAsync(sc->pinned, sc->maxbits.p, sizeof(bits), hipMemcpyDeviceToHost, s));
-    NBGS_HIP(hipStreamSynchronize(s));
-    std::memcpy(&bits, sc->pinned, sizeof(bits));
-    double max_reach;
-    std::memcpy(&max_reach, &bits, sizeof(max_reach));
-    if (!std::isfinite(max_reach)) {
-        set_error("non-finite velocity or radius in the body state");
-        return NBGS_ERR_NUMERIC;
-    }
-    NBGS_TRY(make_grid(sc, max_reach));
-    // cell list
+    NBGS_TRY(make_grid(sc, reach));
     const SceneTable tab = sc->table();
-    NBGS_TRY(launch_cell_keys(sc->b, sc->grid, tab, sc->h.p, sc->keys.p, sc->ids.p, sc->xr.p, s));
+    NBGS_HIP(hipMemsetAsync(sc->maxbits.p + 1, 0, 2 * sizeof(unsigned long long), s));
+    NBGS_TRY(launch_cell_keys(sc->b, sc->grid, tab, hull, sc->keys.p, sc->ids.p, sc->xr.p, s));
     bool alt = false;
     NBGS_TRY(radix_sort_pairs(sc->keys.p, sc->ids.p, sc->keys2.p, sc->ids2.p, N, sc->grid.key_bits,
                               sc->radix_hist.p, sc->scan_tmp.p, sc->scan_tmp.cap, &alt, s));
-    const uint32_t *skeys = alt ? sc->keys2.p : sc->keys.p;
-    const uint32_t *sids = alt ? sc->ids2.p : sc->ids.p;
+    sc->skeys = alt ? sc->keys2.p : sc->keys.p;
+    sc->sids = alt ? sc->ids2.p : sc->ids.p;
     // cell ranges (entries of occupied cells are rewritten every step) and the occupancy bitmap
     NBGS_TRY(sc->cells.reserve(sc->grid.ncells));
     NBGS_TRY(sc->occ.reserve(((size_t)sc->grid.ncells + 31) / 32));
-    NBGS_TRY(launch_cells(N, sc->grid.ncells, skeys, sids, sc->xr.p, sc->cells.p, sc->occ.p, sc->sxr.p, s));
-    // count, scan, emit
-    NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
+    NBGS_TRY(launch_cells(N, sc->grid.ncells, sc->skeys, sc->sids, sc->xr.p, sc->cells.p, sc->occ.p, sc->sxr.p, s));
+    // count, scan
+    NBGS_TRY(launch_pair_count(sc->b, sc->grid, sc->planes, tab, sc->p.tau, sc->skeys, sc->sids, sc->sxr.p, hull,
                                sc->cells.p, sc->occ.p, sc->cnt.p,
                                sc->npart.p, sc->partners.p, sc->cellpos.p, sc->maxbits.p + 1, s));
     NBGS_TRY(exclusive_scan_i32(sc->cnt.p, sc->off.p, N, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
@@ -519,19 +502,140 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     if (over) {
         set_error("a body meets more than 2^18 hull candidates in its 27 cells: the cell grid, sized by the largest "
                   "hull (radius %g), is too coarse for this state (a diverged solve or a very fast body)",
-                  max_reach);
+                  reach);
         return NBGS_ERR_CAPACITY;
     }
     if (total64 > 0x7fffff00ull) {
         set_error("%llu contacts exceed the 2^31 entries of the contact list (largest hull radius %g)",
-                  (unsigned long long)total64, max_reach);
+                  (unsigned long long)total64, reach);
         return NBGS_ERR_CAPACITY;
     }
-    const int64_t nc = sc->pinned[0];
-    if (nc != (int64_t)total64) {
-        set_error("contact count %lld disagrees with its 64-bit total %llu", (long long)nc,
+    if (sc->pinned[0] != (int32_t)total64) {
+        set_error("contact count %lld disagrees with its 64-bit total %llu", (long long)sc->pinned[0],
                   (unsigned long long)total64);
         return NBGS_ERR_DEVICE;
+    }
+    *total = (int64_t)total64;
+    return NBGS_OK;
+}
+
+// The pair list: every pair (and body-wall pair) whose reaches with hull radius
+// `skin` overlap, in canonical order, built by the grid phase with that hull;
+// with it the positions, radii and static flags of the build.  A later step
+// tests these pairs only, as long as every body's displacement plus hull plus
+// radius growth stays below the skin (checked by the hull pass): a pair further
+// apart than r_i + r_k + 2 skin at the build cannot overlap its hulls then, and
+// a wall further than skin + tau cannot be met.  The contacts are those of the
+// grid phase, bit for bit (the same predicates on the same values); the list
+// saves the sort and the neighbour search of the steps in between.  It is kept
+// only when the workspace has room for it; otherwise every step uses the grid.
+// Bytes of the pair list of nl pairs for n bodies: per pair its two ends, flag
+// and scan offset (16 B), per body the build's position, radius, hull and
+// static flag (41 B), ten per cent and the alignment of eight buffers.
+static size_t list_bytes(int64_t nl, int64_t n) {
+    return (size_t)(1.1 * (16.0 * (double)nl + 41.0 * (double)n)) + 8 * Arena::kAlign;
+}
+
+static nbgs_status build_pair_list(nbgs_scene_t sc, double max_reach, double max_h, bool *built) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    *built = false;
+    sc->vl_valid = false;
+    const double skin = std::max(4.0 * max_h, 0.02 * max_reach);
+    if (!(skin > 0.0) || !std::isfinite(skin)) return NBGS_OK;
+    // room for the list beside everything the step may need (the list is not part of the workspace bound)
+    auto drop = [&]() {
+        for (DevBuf<int32_t> *b : {&sc->vl_j1, &sc->vl_j2, &sc->vl_flag, &sc->vl_off}) b->release();
+        for (DevBuf<double> *b : {&sc->vl_h, &sc->vl_x0, &sc->vl_r0}) b->release();
+        sc->vl_static0.release();
+        set_error("");
+        return NBGS_OK;
+    };
+    for (DevBuf<int32_t> *b : {&sc->vl_j1, &sc->vl_j2, &sc->vl_flag, &sc->vl_off}) b->release();  // the old list
+    if (sc->vl_blocked) return drop();
+    // the contacts the list will serve: a quarter more than the last detection found (all listed pairs on the
+    // first); a step that finds more than fit beside the list gives the list's room back (nbgs_detect)
+    auto contacts_served = [&](int64_t nl) { return sc->nc > 0 ? std::min(nl, sc->nc + sc->nc / 4 + 64) : nl; };
+    size_t base = 0;
+    NBGS_TRY(scene_need_bytes(sc, sc->nc, &base));
+    if (base + list_bytes(0, N) > sc->arena.size()) return drop();
+    if (sc->vl_h.reserve((size_t)N, 1.0) != NBGS_OK || sc->vl_x0.reserve(3 * (size_t)N + 1, 1.0) != NBGS_OK ||
+        sc->vl_r0.reserve((size_t)N, 1.0) != NBGS_OK || sc->vl_static0.reserve((size_t)N, 1.0) != NBGS_OK)
+        return drop();
+    NBGS_TRY(launch_fill_f64(sc->vl_h.p, N, skin, s));
+    int64_t nl = 0;
+    NBGS_TRY(grid_pairs(sc, sc->vl_h.p, max_reach + skin, &nl));
+    size_t need = 0;
+    NBGS_TRY(scene_need_bytes(sc, contacts_served(nl), &need));
+    if (need + list_bytes(nl, N) > sc->arena.size()) return drop();
+    if (sc->vl_j1.reserve((size_t)(nl > 0 ? nl : 1)) != NBGS_OK ||
+        sc->vl_j2.reserve((size_t)(nl > 0 ? nl : 1)) != NBGS_OK || sc->vl_flag.reserve((size_t)nl + 1) != NBGS_OK ||
+        sc->vl_off.reserve((size_t)nl + 1) != NBGS_OK)
+        return drop();
+    ContactsView lv{};
+    lv.j1 = sc->vl_j1.p;
+    lv.j2 = sc->vl_j2.p;
+    NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, sc->table(), sc->p.tau, sc->skeys, sc->sids, sc->sxr.p,
+                              sc->vl_h.p, sc->cells.p, sc->occ.p, sc->cnt.p, sc->off.p, sc->cellpos.p, sc->npart.p,
+                              sc->partners.p, lv, nl, false, s));
+    NBGS_HIP(hipMemcpyAsync(sc->vl_x0.p, sc->b.x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    NBGS_HIP(hipMemcpyAsync(sc->vl_x0.p + N, sc->b.y, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    NBGS_HIP(hipMemcpyAsync(sc->vl_x0.p + 2 * (size_t)N, sc->b.z, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    NBGS_HIP(hipMemcpyAsync(sc->vl_r0.p, sc->b.radius, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    NBGS_TRY(launch_static_flags(sc->b.inv_mass, N, sc->vl_static0.p, s));
+    sc->vl_skin = skin;
+    sc->vl_n = nl;
+    sc->vl_valid = true;
+    sc->vl_builds += 1;
+    *built = true;
+    return NBGS_OK;
+}
+
+nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    record(sc, kDetect);
+    if (sc->table_in_cur) {  // the solved impulses of the last step become the lookup table
+        sc->cur = 1 - sc->cur;
+        sc->table_in_cur = false;
+    }
+    ContactBuf &prev = sc->cb[1 - sc->cur];
+    // hull radii, the largest reach and hull and, with a pair list, its validity
+    // maxbits: [0] largest r + h (bits of a non-negative double), [1] contact total in 64 bits, [2] candidate
+    // overflow of the pair count, [3] largest h, [4] largest displacement + h + radius growth since the list's build
+    const bool have_list = sc->vl_enabled && sc->vl_valid;
+    NBGS_HIP(hipMemsetAsync(sc->maxbits.p, 0, 5 * sizeof(unsigned long long), s));
+    NBGS_TRY(launch_hull(sc->b, sc->p.dt, sc->p.tau, sc->h.p, sc->maxbits.p, have_list ? sc->vl_x0.p : nullptr,
+                         have_list ? sc->vl_r0.p : nullptr, have_list ? sc->vl_static0.p : nullptr, s));
+    unsigned long long mb[5];
+    NBGS_HIP(hipMemcpyAsync(sc->pinned, sc->maxbits.p, sizeof(mb), hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipStreamSynchronize(s));
+    std::memcpy(mb, sc->pinned, sizeof(mb));
+    double max_reach, max_h, max_moved;
+    std::memcpy(&max_reach, &mb[0], sizeof(double));
+    std::memcpy(&max_h, &mb[3], sizeof(double));
+    std::memcpy(&max_moved, &mb[4], sizeof(double));
+    if (!std::isfinite(max_reach)) {
+        set_error("non-finite velocity or radius in the body state");
+        return NBGS_ERR_NUMERIC;
+    }
+    const SceneTable tab = sc->table();
+    // contacts: from the pair list while it holds (rebuilt when it does not), else from the cell grid
+    bool use_list = have_list && max_moved <= 0.999 * sc->vl_skin;
+    if (sc->vl_enabled && !use_list) NBGS_TRY(build_pair_list(sc, max_reach, max_h, &use_list));
+    int64_t nc = 0;
+    if (use_list) {
+        const int64_t nl = sc->vl_n;
+        NBGS_TRY(launch_list_test(sc->b, sc->grid, sc->planes, tab, sc->p.tau, sc->h.p, sc->vl_j1.p, sc->vl_j2.p, nl,
+                                  sc->vl_flag.p, s));
+        const size_t need_tmp = exclusive_scan_tmp_bytes(nl + 1);
+        if (need_tmp > sc->scan_tmp.cap) NBGS_TRY(sc->scan_tmp.reserve(need_tmp));
+        NBGS_TRY(exclusive_scan_i32(sc->vl_flag.p, sc->vl_off.p, nl, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap,
+                                    s));
+        NBGS_TRY(sync_small(sc, 0, 1));
+        nc = nl > 0 ? sc->pinned[0] : 0;
+    } else {
+        NBGS_TRY(grid_pairs(sc, sc->h.p, max_reach, &nc));
     }
     if ((sc->sub_edge > 0.0 || sc->blk_edge > 0.0) && 2 * nc > (int64_t)0x7fffff00) {
         set_error("%lld contacts: the subdomain solver indexes both ends of a contact in 32 bits (at most 2^30 "
@@ -552,9 +656,15 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     sc->nc = nc;
     ContactBuf &cb = sc->cb[sc->cur];
     NBGS_TRY(cb.reserve((size_t)nc));
-    NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, tab, sc->p.tau, skeys, sids, sc->sxr.p, sc->h.p,
-                              sc->cells.p, sc->occ.p, sc->cnt.p, sc->off.p,
-                              sc->cellpos.p, sc->npart.p, sc->partners.p, cb.view(), nc, s));
+    if (use_list) {
+        NBGS_TRY(launch_list_emit(sc->vl_j1.p, sc->vl_j2.p, sc->vl_n, sc->vl_flag.p, sc->vl_off.p, cb.view(), s));
+        NBGS_TRY(launch_pair_geometry(sc->b, sc->grid, sc->planes, tab, cb.view(), nc, s));
+        NBGS_TRY(launch_contact_runs(cb.j1.p, nc, N, sc->cnt.p, sc->off.p, s));  // the colouring's per-body runs
+    } else {
+        NBGS_TRY(launch_pair_emit(sc->b, sc->grid, sc->planes, tab, sc->p.tau, sc->skeys, sc->sids, sc->sxr.p,
+                                  sc->h.p, sc->cells.p, sc->occ.p, sc->cnt.p, sc->off.p, sc->cellpos.p, sc->npart.p,
+                                  sc->partners.p, cb.view(), nc, true, s));
+    }
     // initial impulses and, when the previous table carries colours, the start of the colouring
     const bool warm_impulses = sc->p.warm_start != NBGS_WS_ZERO && sc->n_prev > 0;
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
@@ -1419,7 +1529,7 @@ nbgs_status scene_create(void *workspace, size_t workspace_bytes, const nbgs_bod
     chk(sc->radix_hist.reserve(radix_hist_entries((int64_t)N + 1), 1.0));
     chk(sc->scan_tmp.reserve(exclusive_scan_tmp_bytes((int64_t)radix_hist_entries((int64_t)N + 1) + N + 1), 1.0));
     chk(sc->small.reserve(kSmallInts, 1.0));
-    chk(sc->maxbits.reserve(3, 1.0));
+    chk(sc->maxbits.reserve(5, 1.0));
     if (st == NBGS_OK && hipHostMalloc((void **)&sc->pinned, sizeof(int32_t) * kSmallInts * 2) != hipSuccess) {
         set_error("pinned host allocation failed");
         st = NBGS_ERR_OUT_OF_MEMORY;
@@ -1532,6 +1642,9 @@ nbgs_status nbgs_scene_set_workspace(nbgs_scene_t sc, void *workspace, size_t by
     NBGS_TRY(sc->arena.move_to(workspace, bytes, sc->s));
     // addresses kept inside moved buffers
     sc->perm = static_cast<const uint32_t *>(sc->arena.relocate(sc->perm));
+    sc->skeys = static_cast<const uint32_t *>(sc->arena.relocate(sc->skeys));
+    sc->sids = static_cast<const uint32_t *>(sc->arena.relocate(sc->sids));
+    sc->vl_blocked = false;  // a new workspace may hold the pair list
     sc->body_slots = static_cast<const uint32_t *>(sc->arena.relocate(sc->body_slots));
     return NBGS_OK;
 }
@@ -1579,6 +1692,7 @@ nbgs_status nbgs_scene_set_params(nbgs_scene_t sc, const nbgs_params *params) {
         return NBGS_ERR_INVALID_ARG;
     }
     sc->p = *params;
+    sc->vl_valid = false;  // the pair list was built for the old margin (tau) and step
     update_scales(sc);
     return NBGS_OK;
 }
@@ -1587,7 +1701,20 @@ nbgs_status nbgs_detect(nbgs_scene_t sc, nbgs_stats *stats) {
     NBGS_GUARD(sc);
     sc->state = 0;
     sc->nc_needed = -1;
-    const nbgs_status st = detect_impl(sc, stats);
+    nbgs_status st = detect_impl(sc, stats);
+    if (st == NBGS_ERR_CAPACITY && sc->nc_needed < 0 && (sc->vl_h.p || sc->vl_j1.p)) {
+        // A buffer did not fit beside the pair list although the contact count did: the list gives its room back
+        // and is built no more in this workspace; the detection runs once more with the cell grid (the colouring
+        // of the failed run is not reused).
+        for (DevBuf<int32_t> *b : {&sc->vl_j1, &sc->vl_j2, &sc->vl_flag, &sc->vl_off}) b->release();
+        for (DevBuf<double> *b : {&sc->vl_h, &sc->vl_x0, &sc->vl_r0}) b->release();
+        sc->vl_static0.release();
+        sc->vl_valid = false;
+        sc->vl_blocked = true;
+        sc->prev_sig_valid = false;
+        sc->dyn_bits_valid = false;
+        st = detect_impl(sc, stats);
+    }
     if (st == NBGS_ERR_CAPACITY) {
         // what was lacking: the contact count found, for nbgs_workspace_query
         sc->prev_sig_valid = false;
@@ -1768,6 +1895,21 @@ nbgs_status nbgs_set_block_grids(nbgs_scene_t sc, int32_t grids) {
     }
     sc->blk_grids = grids;
     sc->state = 0;  // the next step starts with a detection
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_set_pair_list(nbgs_scene_t sc, int32_t enable) {
+    NBGS_GUARD(sc);
+    sc->vl_enabled = enable != 0;
+    sc->vl_valid = false;
+    return NBGS_OK;
+}
+
+nbgs_status nbgs_get_pair_list_info(nbgs_scene_t sc, int64_t *pairs, double *skin, int64_t *builds) {
+    NBGS_GUARD(sc);
+    if (pairs) *pairs = sc->vl_valid ? sc->vl_n : -1;
+    if (skin) *skin = sc->vl_valid ? sc->vl_skin : 0.0;
+    if (builds) *builds = sc->vl_builds;
     return NBGS_OK;
 }
 

@@ -35,9 +35,22 @@ inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n +
 // hull rather than one per 256 bodies.
 constexpr int kHullBlocks = 2048;
 
+// State of the pair list at its build (see launch_hull): positions, radii and
+// which bodies were static.
+struct ListRef {
+    const double *x0, *y0, *z0, *r0;
+    const uint8_t *static0;
+};
+
+// Hull radii h_i and the largest r_i + h_i (max_bits[0]), the largest h_i
+// (max_bits[3]) and, when a pair list is held (ref.x0 set), the largest
+// |x_i - x_i(build)| + h_i + max(0, r_i - r_i(build)) (max_bits[4]; +inf when
+// a body's static flag changed).  The list stays exact while that stays below
+// its skin: a pair further apart than r_i + r_k + 2 skin at the build cannot
+// overlap its hulls then.
 __global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double tau, double *h,
-                                                 unsigned long long *max_bits) {
-    double rmax = 0.0;
+                                                 unsigned long long *max_bits, ListRef ref) {
+    double rmax = 0.0, hmax = 0.0, dmax = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < b.n; i += gridDim.x * kBlock) {
         const double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
         const double wx = b.wx[i], wy = b.wy[i], wz = b.wz[i];
@@ -49,16 +62,33 @@ __global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double
         double rh = r + hi;
         if (!(rh == rh)) rh = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf: caught on the host
         rmax = fmax(rmax, rh);
+        hmax = fmax(hmax, hi);
+        if (ref.x0) {
+            const double dx = b.x[i] - ref.x0[i], dy = b.y[i] - ref.y0[i], dz = b.z[i] - ref.z0[i];
+            double d = sqrt(dx * dx + dy * dy + dz * dz) + hi + fmax(0.0, r - ref.r0[i]);
+            if (!(d == d) || (uint8_t)(b.inv_mass[i] == 0.0) != ref.static0[i])
+                d = __longlong_as_double(0x7ff0000000000000ll);
+            dmax = fmax(dmax, d);
+        }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
-    __shared__ double wmax[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = rmax;
+    for (int o = 32; o > 0; o >>= 1) {
+        rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+        hmax = fmax(hmax, __shfl_xor(hmax, o, 64));
+        dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    }
+    __shared__ double wmax[3][kBlock / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wmax[0][threadIdx.x >> 6] = rmax;
+        wmax[1][threadIdx.x >> 6] = hmax;
+        wmax[2][threadIdx.x >> 6] = dmax;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {  // the largest hull is order-independent
-        double m = wmax[0];
-        for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, wmax[w]);
-        atomicMax(max_bits, (unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x < 3) {  // the maxima are order-independent
+        const int k = threadIdx.x;
+        double m = wmax[k][0];
+        for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, wmax[k][w]);
+        if (k == 0 || m > 0.0) atomicMax(&max_bits[k == 0 ? 0 : k + 2], (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -556,6 +586,63 @@ __global__ void __launch_bounds__(kBlock) k_dyn_bits(const double *inv_mass, int
     }
 }
 
+// The pair list's pairs (canonical order) tested with this step's hulls by
+// exactly the predicates of the pair count: two bodies' reaches (r + h, the
+// same roundings) against their minimum-image distance, two static bodies
+// never; a dynamic body's wall by its gap.  flag[q] = 1 for a contact.
+__global__ void __launch_bounds__(kBlock) k_list_test(BodiesView b, Grid g0, PlaneSet pl0, SceneTable st, double tau,
+                                                      const double *h, const int32_t *lj1, const int32_t *lj2,
+                                                      int64_t nl, int32_t *flag) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= nl) return;
+    const int i = lj1[q], k = lj2[q];
+    const int sc = st.body_scene ? st.body_scene[i] : 0;
+    int hit = 0;
+    if (k < b.n) {
+        const Grid &g = st.body_scene ? st.grids[sc] : g0;
+        const double rhi = b.radius[i] + h[i], rhk = b.radius[k] + h[k];
+        const bool si = b.inv_mass[i] == 0.0, sk = b.inv_mass[k] == 0.0;
+        if (!(si && sk)) {
+            const double dx = min_image(b.x[i] - b.x[k], g.periodic[0], g.L[0]);
+            const double dy = min_image(b.y[i] - b.y[k], g.periodic[1], g.L[1]);
+            const double dz = min_image(b.z[i] - b.z[k], g.periodic[2], g.L[2]);
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            const double reach = rhi + rhk;
+            hit = d2 <= reach * reach;
+        }
+    } else if (b.inv_mass[i] != 0.0) {
+        const PlaneSet &pl = st.body_scene ? st.planes[sc] : pl0;
+        const int w = k - (b.n + (st.body_scene ? st.wall_off[sc] : 0));
+        double gap;
+        hit = plane_hit(pl, w, b.x[i], b.y[i], b.z[i], b.radius[i], h[i], tau, &gap);
+    }
+    flag[q] = hit;
+}
+
+// The listed pairs that are contacts, in list order (canonical), at their
+// positions of the exclusive scan of the flags.
+__global__ void __launch_bounds__(kBlock) k_list_emit(const int32_t *lj1, const int32_t *lj2, int64_t nl,
+                                                      const int32_t *flag, const int32_t *off, ContactsView c) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= nl || !flag[q]) return;
+    const int32_t o = off[q];
+    c.j1[o] = lj1[q];
+    c.j2[o] = lj2[q];
+}
+
+// The run of contacts of body j1[j] starts at j when j1[j - 1] differs; its
+// first thread walks to the run's end (runs are a body's few partners).
+__global__ void __launch_bounds__(kBlock) k_contact_runs(const int32_t *j1, int64_t nc, int32_t *cnt, int32_t *off) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    const int32_t b = j1[j];
+    if (j > 0 && j1[j - 1] == b) return;
+    int64_t e = j + 1;
+    while (e < nc && j1[e] == b) ++e;
+    off[b] = (int32_t)j;
+    cnt[b] = (int32_t)(e - j);
+}
+
 // Sums of the steps between consecutive bodies per axis (pairs i, i + 1 for
 // i < pairs), one partial per workgroup.
 __global__ void __launch_bounds__(kBlock) k_numbering_steps(BodiesView b, int64_t pairs, double *part) {
@@ -585,6 +672,16 @@ __global__ void __launch_bounds__(kBlock) k_numbering_steps(BodiesView b, int64_
     }
 }
 
+__global__ void __launch_bounds__(kBlock) k_fill_f64(double *p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_static_flags(const double *inv_mass, int64_t n, uint8_t *flags) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) flags[i] = (uint8_t)(inv_mass[i] == 0.0);
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = v;
@@ -593,10 +690,58 @@ __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *p, int64_t n, int3
 }  // namespace
 
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
-                        hipStream_t s) {
+                        const double *x0, const double *r0, const uint8_t *static0, hipStream_t s) {
     if (b.n <= 0) return NBGS_OK;
     const unsigned blocks = std::min<unsigned>(grid_for(b.n), (unsigned)kHullBlocks);
-    k_hull<<<blocks, kBlock, 0, s>>>(b, dt, tau, h, max_bits);
+    ListRef ref{x0, x0 ? x0 + b.n : nullptr, x0 ? x0 + 2 * (int64_t)b.n : nullptr, r0, static0};
+    k_hull<<<blocks, kBlock, 0, s>>>(b, dt, tau, h, max_bits, ref);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return NBGS_OK;
+    k_fill_f64<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_static_flags(const double *inv_mass, int64_t n, uint8_t *flags, hipStream_t s) {
+    if (n <= 0) return NBGS_OK;
+    k_static_flags<<<grid_for(n), kBlock, 0, s>>>(inv_mass, n, flags);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_list_test(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st,
+                             double tau, const double *h, const int32_t *lj1, const int32_t *lj2, int64_t nl,
+                             int32_t *flag, hipStream_t s) {
+    if (nl <= 0) return NBGS_OK;
+    k_list_test<<<grid_for(nl), kBlock, 0, s>>>(b, g, pl, st, tau, h, lj1, lj2, nl, flag);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_list_emit(const int32_t *lj1, const int32_t *lj2, int64_t nl, const int32_t *flag,
+                             const int32_t *off, ContactsView c, hipStream_t s) {
+    if (nl <= 0) return NBGS_OK;
+    k_list_emit<<<grid_for(nl), kBlock, 0, s>>>(lj1, lj2, nl, flag, off, c);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_contact_runs(const int32_t *j1, int64_t nc, int32_t n, int32_t *cnt, int32_t *off, hipStream_t s) {
+    NBGS_TRY(launch_fill_i32(cnt, n, 0, s));
+    if (nc <= 0) return NBGS_OK;
+    k_contact_runs<<<grid_for(nc), kBlock, 0, s>>>(j1, nc, cnt, off);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_pair_geometry(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st,
+                                 ContactsView c, int64_t nc, hipStream_t s) {
+    if (nc <= 0) return NBGS_OK;
+    k_pair_geometry<<<grid_for(nc), kBlock, 0, s>>>(b, g, pl, st, nc, c);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -644,10 +789,10 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
                              const int2 *cells, const uint32_t *occ, const int32_t *cnt, const int32_t *off,
                              const int32_t *cellpos,
                              const int32_t *npart, const int32_t *partners, ContactsView c, int64_t nc,
-                             hipStream_t s) {
+                             bool geometry, hipStream_t s) {
     k_pair_emit<<<grid_for(b.n), kBlock, 0, s>>>(b, g, pl, st, tau, skeys, sids, sxr, h, cells, occ, cnt, off, cellpos, npart, partners, c);
     NBGS_HIP(hipGetLastError());
-    if (nc > 0) {
+    if (geometry && nc > 0) {
         k_pair_geometry<<<grid_for(nc), kBlock, 0, s>>>(b, g, pl, st, nc, c);
         NBGS_HIP(hipGetLastError());
     }

@@ -235,7 +235,21 @@ size_t radix_hist_entries(int64_t n);
 // Partners (k > i) of a body kept by the pair count for the emit; longer lists are searched again.
 constexpr int kPartnerCap = 16;
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
-                        hipStream_t s);
+                        const double *x0, const double *r0, const uint8_t *static0, hipStream_t s);
+nbgs_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+nbgs_status launch_static_flags(const double *inv_mass, int64_t n, uint8_t *flags, hipStream_t s);
+// The pair list (see detect.hip): test its pairs with this step's hulls, compact the contacts, geometry.
+nbgs_status launch_list_test(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st,
+                             double tau, const double *h, const int32_t *lj1, const int32_t *lj2, int64_t nl,
+                             int32_t *flag, hipStream_t s);
+// Each body's run of contacts as first body in a key-ordered list: its start
+// in off and its length in cnt (zero for bodies without one), as the pair
+// count and its scan leave them for the colouring.
+nbgs_status launch_contact_runs(const int32_t *j1, int64_t nc, int32_t n, int32_t *cnt, int32_t *off, hipStream_t s);
+nbgs_status launch_list_emit(const int32_t *lj1, const int32_t *lj2, int64_t nl, const int32_t *flag,
+                             const int32_t *off, ContactsView c, hipStream_t s);
+nbgs_status launch_pair_geometry(const BodiesView &b, const Grid &g, const PlaneSet &pl, const SceneTable &st,
+                                 ContactsView c, int64_t nc, hipStream_t s);
 nbgs_status launch_cell_keys(const BodiesView &b, const Grid &g, const SceneTable &st, const double *h,
                              uint32_t *keys, uint32_t *ids, double4 *xr, hipStream_t s);
 // Per workgroup b (gridDim.x of them) the sums over its sampled consecutive
@@ -251,7 +265,7 @@ nbgs_status launch_pair_emit(const BodiesView &b, const Grid &g, const PlaneSet 
                              const uint32_t *skeys, const uint32_t *sids, const double4 *sxr, const double *h,
                              const int2 *cells, const uint32_t *occ, const int32_t *cnt, const int32_t *off,
                              const int32_t *cellpos, const int32_t *npart, const int32_t *partners, ContactsView c,
-                             int64_t nc, hipStream_t s);
+                             int64_t nc, bool geometry, hipStream_t s);
 nbgs_status launch_match_prev(ContactsView c, int64_t nc, const uint64_t *prev_key, const double *prev_px,
                               const double *prev_py, const double *prev_pz, const int32_t *prev_colour,
                               int64_t n_prev, double mu, const SceneTable &st, bool impulses, bool colours,

@@ -108,6 +108,16 @@ struct nbgs_scene_s {
     DevBuf<double4> xr;   // the same in body order
     int32_t key_axes[3] = {0, 1, 2};  // cell key order (axis[0] fastest), chosen on the first detection
     bool key_axes_set = false;
+    const uint32_t *skeys = nullptr, *sids = nullptr;  // the last grid phase's sorted keys and bodies
+    // pair list (detect_impl): its pairs, their flags and scan offsets, and the build's positions (3 n), radii,
+    // hull (the skin) and static flags
+    bool vl_enabled = true, vl_valid = false;
+    bool vl_blocked = false;  // a buffer did not fit beside the list in this workspace: no list until it changes
+    double vl_skin = 0.0;
+    int64_t vl_n = 0, vl_builds = 0;
+    DevBuf<int32_t> vl_j1, vl_j2, vl_flag, vl_off;
+    DevBuf<double> vl_h, vl_x0, vl_r0;
+    DevBuf<uint8_t> vl_static0;
     DevBuf<int32_t> cnt, off, cellpos;
     DevBuf<int32_t> npart, partners;  // the pair count's partner store (kPartnerCap per body) for the emit
     DevBuf<int32_t> deg2, off2, cursor;
