@@ -8,9 +8,11 @@ solid fraction about 0.6, coordination about 6, mu = 0.5, dt = 1e-4, gravity
 step is one full pass of the hot path: contact detection (hull radii, cell
 list, pair search, narrow phase), colouring and ordering, accumulator init,
 50 NBGS sweeps, integration.  The sweeps visit the contacts in the block-local
-order (blocks of edge 6.5: every block's local contacts in one workgroup with
-its bodies in LDS, then the contacts between blocks by colour); --block-edge 0
-gives the (colour, key) order, which is also timed beside it.
+order over two grids shifted by half an edge (blocks of edge 6.0: every
+block's local contacts in one workgroup with its bodies in LDS, grid by grid,
+then the contacts local in neither grid, packed by cluster into groups swept
+the same way); --block-edge 0 gives the (colour, key) order, which is also
+timed beside it.
 
 Printed JSON line (one, rank 0):
   value         contact updates per second over the timed steps (FP64 sweeps,
@@ -515,13 +517,14 @@ def main():
     ap.add_argument("--subdomain-edge", type=float, default=0.0,
                     help="time the subdomain NBGS (Alg. 1, blocks of this edge) instead of the colour-ordered one")
     ap.add_argument("--relax", type=float, default=None, help="relaxation (default: the scene's)")
-    ap.add_argument("--block-edge", type=float, default=6.5,
+    ap.add_argument("--block-edge", type=float, default=6.0,
                     help="sweep the plain NBGS in the block-local order with blocks of this edge (0: (colour, key) "
                          "order)")
     ap.add_argument("--block-grids", type=int, default=2,
                     help="block grids of the block-local order, shifted by 1/grids of an edge; the contacts local in "
-                         "no grid are swept by colour (1: one grid; 2, the fastest on the dense packing, leaves 3 %% "
-                         "of its contacts to the colours; 4 leaves none)")
+                         "no grid are swept in groups of whole clusters by the block pass, or by colour when a cluster "
+                         "is too large (1: one grid; 2, the fastest on the dense packing, leaves 3 %% of its "
+                         "contacts to the groups; 4 leaves none)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (walled box, ensemble batch, dilute gas)")
     ap.add_argument("--composite-only", action="store_true",
@@ -644,7 +647,7 @@ def main():
                 kernel_name = f"k_sub_pass<{tn}> + k_sub_reduce<{tn}>"
             elif a.block_edge > 0 and a.block_grids > 1:
                 kernel_name = (f"{'k_blk_pass' if tn == 'double' else 'k_blk_pass_stream'}<{tn}, 1> x {a.block_grids} "
-                               f"grids + k_sweep_grp for the contacts local in none (one sweep)")
+                               f"grids + one launch for the clusters local in none (one sweep)")
             elif a.block_edge > 0:
                 kernel_name = (f"{'k_blk_pass' if tn == 'double' else 'k_blk_pass_stream'}<{tn}, 1> + "
                                f"k_sweep_grp<{tn}, {tu['block']}, "

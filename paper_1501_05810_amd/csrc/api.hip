@@ -1191,7 +1191,7 @@ nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
     const SweepTune &tune = sc->tune[sc->precision_used == NBGS_FP32_SWEEP ? 1 : 0];
     const int nx = (int)sc->xcol.size() - 1;
     const int64_t tile = sweep_tile<T>(tune);
-    sc->xpart_off.assign((size_t)nx + 1, (int64_t)sc->n_blk);
+    sc->xpart_off.assign((size_t)nx + 1, (int64_t)(sc->n_sub - 1));  // after the partials of the blocks and groups
     for (int c = 0; c < nx; ++c) {
         const int64_t m = sc->xcol[c + 1] - sc->xcol[c];
         sc->xpart_off[c + 1] = sc->xpart_off[c] + (m + tile - 1) / tile;

@@ -241,6 +241,8 @@ struct nbgs_scene_s {
     int32_t n_sub = 0;
     int64_t n_slots = 0;
     int32_t max_slots = 0;
+    // block-local order: the launches of the block pass (first id, ids, the largest block's slots)
+    std::vector<int32_t> launch_id0, launch_n, launch_slots;
     DevBuf<int32_t> sdom, tile_cnt, tile_off32, tile_scnt, tile_slot_off, eflags, eex, slot_body, slot_sdom, body_cnt,
         body_slot_off;
     DevBuf<int64_t> tile_off;
@@ -259,6 +261,11 @@ struct nbgs_scene_s {
     int32_t n_blk = 0;
     int32_t blk_grids = 1;     // block grids shifted by 1/blk_grids of an edge (nbgs_set_block_grids)
     int32_t blk_grid_ids = 0;  // ids (blocks) per grid: n_blk = blk_grids * blk_grid_ids
+    // groups of the clusters of contacts no grid holds (ids n_blk .. n_blk + blk_groups - 1, swept by the block
+    // pass; 0: those contacts keep the id n_blk and are swept by colour)
+    int32_t blk_groups = 0;
+    bool blk_group_cross = true;
+    DevBuf<int32_t> xg_ctl, xg_cnt;
     int64_t blk_first_cross = 0;  // first sweep position of the contacts between blocks
     std::vector<int64_t> xcol;       // positions of the cross colours' ranges (size colours + 1)
     std::vector<int64_t> xdyn;       // dynamic contact ends per cross colour

@@ -126,6 +126,92 @@ __global__ void __launch_bounds__(kBlock) k_block_local_grids(BodiesView b, cons
     id[j] = out;
 }
 
+// Groups of the contacts no grid holds (the block-local order over several
+// grids).  Two such contacts interact only through a shared dynamic body, and
+// in a settled packing they form small clusters, each swept in its own
+// (colour, key) order.  Sweeping whole clusters in the block pass, packed
+// into groups, one workgroup each with the group's bodies in LDS, gives every
+// contact the arithmetic and the order of the colour launches (no cluster
+// reaches another) in a single launch.  Clusters are the connected components
+// of the contacts under "shares a dynamic body": every contact takes the
+// smallest list position in its component by alternating minima over bodies
+// and contacts.
+__global__ void __launch_bounds__(kBlock) k_cross_flags(const int32_t *id, int64_t nc, int32_t cross,
+                                                        int32_t *flag) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j < nc) flag[j] = id[j] == cross ? 1 : 0;
+}
+
+// The list of those contacts (pos: exclusive scan of the flags) and their start labels (own position).
+__global__ void __launch_bounds__(kBlock) k_cross_list(const int32_t *id, const int32_t *pos, int64_t nc,
+                                                       int32_t cross, int32_t *xl, int32_t *lab) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc || id[j] != cross) return;
+    xl[pos[j]] = (int32_t)j;
+    lab[pos[j]] = pos[j];
+}
+
+__device__ inline int32_t dyn_end(const int32_t *jj, int32_t j, int32_t nb, const double *inv_mass) {
+    const int32_t b = jj[j];
+    return b < nb && inv_mass[b] > 0.0 ? b : -1;
+}
+
+// Every dynamic body of a listed contact: the smallest label of its listed contacts.
+__global__ void __launch_bounds__(kBlock) k_cc_push(const int32_t *xl, int32_t nx, const int32_t *j1,
+                                                    const int32_t *j2, int32_t nb, const double *inv_mass,
+                                                    const int32_t *lab, int32_t *blab) {
+    const int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (q >= nx) return;
+    const int32_t j = xl[q], l = lab[q];
+    const int32_t b1 = dyn_end(j1, j, nb, inv_mass), b2 = dyn_end(j2, j, nb, inv_mass);
+    if (b1 >= 0) atomicMin(&blab[b1], l);
+    if (b2 >= 0) atomicMin(&blab[b2], l);
+}
+
+// Every listed contact: the smallest label of its dynamic bodies, if smaller; changed counts the moves.
+__global__ void __launch_bounds__(kBlock) k_cc_pull(const int32_t *xl, int32_t nx, const int32_t *j1,
+                                                    const int32_t *j2, int32_t nb, const double *inv_mass,
+                                                    int32_t *lab, const int32_t *blab, int32_t *changed) {
+    const int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    int moved = 0;
+    if (q < nx) {
+        const int32_t j = xl[q];
+        int32_t l = lab[q];
+        const int32_t b1 = dyn_end(j1, j, nb, inv_mass), b2 = dyn_end(j2, j, nb, inv_mass);
+        if (b1 >= 0) l = min(l, blab[b1]);
+        if (b2 >= 0) l = min(l, blab[b2]);
+        if (l < lab[q]) {
+            lab[q] = l;
+            moved = 1;
+        }
+    }
+    if (__ballot(moved) && (threadIdx.x & 63) == 0) atomicAdd(changed, 1);
+}
+
+// Group ids: the cluster of label l goes to group l / per (labels are list positions, so a group holds the
+// clusters whose first contact is among `per` consecutive ones); cnt counts each group's contacts.
+__global__ void __launch_bounds__(kBlock) k_cc_ids(const int32_t *xl, int32_t nx, const int32_t *lab, int32_t base,
+                                                   int32_t per, int32_t *id, int32_t *cnt) {
+    const int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (q >= nx) return;
+    const int32_t g = lab[q] / per;
+    id[xl[q]] = base + g;
+    atomicAdd(&cnt[g], 1);
+}
+
+__global__ void __launch_bounds__(kBlock) k_cc_reset(const int32_t *xl, int32_t nx, int32_t cross, int32_t *id) {
+    const int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (q < nx) id[xl[q]] = cross;
+}
+
+__global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t *v, int32_t n, int32_t *out) {
+    const int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    int32_t m = i < n ? v[i] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(out, m);
+}
+
 // cnt[v[i]] += 1 for every i.  The inputs here are sorted (ids of a sweep
 // record, slots by id), so equal values sit in neighbouring lanes: each run of
 // equal values in a wave adds its length with one atomic (exact for any input).
@@ -985,6 +1071,77 @@ nbgs_status subdomain_assign(nbgs_scene_t sc) {
     return NBGS_OK;
 }
 
+// Groups of the contacts that no grid's block holds (k_cross_flags): with
+// several grids their clusters are packed into *groups ids n_blk .. n_blk +
+// *groups - 1, swept by the block pass, when the labelling settles within its
+// round limit and every group fits a workgroup's LDS (kGroupMaxContacts);
+// otherwise they keep the id n_blk and *groups = 0 (the colour launches).
+// The id after the groups, n_blk + *groups, is that of the contacts swept by
+// colour, which then holds none.
+constexpr int32_t kGroupTarget = 1536;       // about six groups per compute unit
+constexpr int32_t kGroupMaxContacts = 448;   // at most 896 slots: 56 KB of FP64 records
+constexpr int kGroupMaxRounds = 48;
+
+static nbgs_status cross_groups(nbgs_scene_t sc, int32_t *groups) {
+    hipStream_t s = sc->s;
+    *groups = 0;
+    const int64_t nc = sc->nc;
+    const int32_t N = sc->b.n, cross = sc->n_blk;
+    if (nc <= 0 || nc >= (int64_t)0x3fffffff) return NBGS_OK;
+    // scratch: tables the step's later set-up reserves at these sizes anyway
+    const int64_t ne = 2 * nc;
+    for (DevBuf<int32_t> *b : {&sc->eflags, &sc->eex}) NBGS_TRY(b->reserve((size_t)ne + 1));
+    for (DevBuf<uint32_t> *b : {&sc->ekeys, &sc->evals}) NBGS_TRY(b->reserve((size_t)ne + 1));
+    NBGS_TRY(sc->cursor.reserve((size_t)N + 1));
+    NBGS_TRY(sc->xg_ctl.reserve(64, 1.0));
+    const size_t need_tmp = exclusive_scan_tmp_bytes(nc + 2);
+    if (need_tmp > sc->scan_tmp.cap) NBGS_TRY(sc->scan_tmp.reserve(need_tmp));
+    int32_t *flag = sc->eflags.p, *pos = sc->eex.p, *blab = sc->cursor.p;
+    int32_t *xl = reinterpret_cast<int32_t *>(sc->ekeys.p), *lab = reinterpret_cast<int32_t *>(sc->evals.p);
+    const int32_t *j1 = sc->cb[sc->cur].j1.p, *j2 = sc->cb[sc->cur].j2.p;
+    k_cross_flags<<<grid_for(nc), kBlock, 0, s>>>(sc->sdom.p, nc, cross, flag);
+    NBGS_HIP(hipGetLastError());
+    NBGS_TRY(exclusive_scan_i32(flag, pos, nc, sc->total(), sc->scan_tmp.p, sc->scan_tmp.cap, s));
+    NBGS_TRY(scene_sync_small(sc, 0, 1));
+    const int32_t nx = sc->pinned[0];
+    if (nx <= 0) return NBGS_OK;
+    k_cross_list<<<grid_for(nc), kBlock, 0, s>>>(sc->sdom.p, pos, nc, cross, xl, lab);
+    k_fill<<<grid_for(N), kBlock, 0, s>>>(blab, N, 0x7fffffff);
+    k_fill<<<1, kBlock, 0, s>>>(sc->xg_ctl.p, 64, 0);
+    NBGS_HIP(hipGetLastError());
+    const unsigned gx = grid_for(nx);
+    int rounds = 0;
+    bool settled = false;
+    for (int batch = 4; rounds < kGroupMaxRounds && !settled; batch *= 2) {
+        for (int r = 0; r < batch && rounds < kGroupMaxRounds; ++r, ++rounds) {
+            k_cc_push<<<gx, kBlock, 0, s>>>(xl, nx, j1, j2, N, sc->b.inv_mass, lab, blab);
+            k_cc_pull<<<gx, kBlock, 0, s>>>(xl, nx, j1, j2, N, sc->b.inv_mass, lab, blab, sc->xg_ctl.p + rounds);
+        }
+        NBGS_HIP(hipGetLastError());
+        NBGS_HIP(hipMemcpyAsync(sc->pinned + 96, sc->xg_ctl.p + rounds - 1, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                s));
+        NBGS_HIP(hipStreamSynchronize(s));
+        settled = sc->pinned[96] == 0;  // the last round moved no label
+    }
+    if (!settled) return NBGS_OK;
+    const int32_t per = std::max<int32_t>(16, (nx + kGroupTarget - 1) / kGroupTarget);
+    const int32_t ng = (nx + per - 1) / per;
+    NBGS_TRY(sc->xg_cnt.reserve((size_t)ng + 1));
+    k_fill<<<grid_for(ng), kBlock, 0, s>>>(sc->xg_cnt.p, ng, 0);
+    k_cc_ids<<<gx, kBlock, 0, s>>>(xl, nx, lab, cross, per, sc->sdom.p, sc->xg_cnt.p);
+    k_max_i32<<<grid_for(ng), kBlock, 0, s>>>(sc->xg_cnt.p, ng, sc->xg_ctl.p + 63);
+    NBGS_HIP(hipGetLastError());
+    NBGS_HIP(hipMemcpyAsync(sc->pinned + 96, sc->xg_ctl.p + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NBGS_HIP(hipStreamSynchronize(s));
+    if (sc->pinned[96] > kGroupMaxContacts) {  // a group too large for LDS: back to the colour launches
+        k_cc_reset<<<gx, kBlock, 0, s>>>(xl, nx, cross, sc->sdom.p);
+        NBGS_HIP(hipGetLastError());
+        return NBGS_OK;
+    }
+    *groups = ng;
+    return NBGS_OK;
+}
+
 // Block-local ids of the contacts: ids 0 .. n_blk - 1 local, n_blk between blocks.
 nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed) {
     hipStream_t s = sc->s;
@@ -1016,7 +1173,9 @@ nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed) {
                                                             sc->periodic[0], sc->periodic[1], sc->periodic[2],
                                                             sc->sdom.p);
     }
-    sc->n_sub = sc->n_blk + 1;
+    sc->blk_groups = 0;
+    if (sc->blk_grids > 1 && sc->blk_group_cross) NBGS_TRY(cross_groups(sc, &sc->blk_groups));
+    sc->n_sub = sc->n_blk + sc->blk_groups + 1;
     NBGS_HIP(hipGetLastError());
     // every body's block, compared with the last step's (bodies without local contacts count too: they decide the
     // slots); the number of changes is added to changed
@@ -1106,6 +1265,9 @@ static nbgs_status block_prepare_impl(nbgs_scene_t sc) {
         return NBGS_ERR_CAPACITY;
     }
     sc->max_slots = max_slots;
+    sc->launch_id0.assign(1, 0);
+    sc->launch_n.assign(1, nblk);
+    sc->launch_slots.assign(1, max_slots);
     sc->n_slots = soff[(size_t)nblk];
     NBGS_HIP(hipMemcpyAsync(sc->tile_off.p, toff.data(), sizeof(int64_t) * (nsub + 1), hipMemcpyHostToDevice, s));
     NBGS_HIP(hipMemcpyAsync(sc->tile_slot_off.p, soff.data(), sizeof(int32_t) * (nblk + 2), hipMemcpyHostToDevice, s));
@@ -1168,10 +1330,13 @@ static nbgs_status block_grids_prepare_impl(nbgs_scene_t sc) {
     const int32_t nblk = sc->n_blk;
     SweepBuf<T> &sw = sc->precision_used == NBGS_FP32_SWEEP ? *reinterpret_cast<SweepBuf<T> *>(&sc->sw32)
                                                             : *reinterpret_cast<SweepBuf<T> *>(&sc->sw64);
-    NBGS_TRY(prepare_impl<T>(sc, nblk, 8, false));
-    NBGS_TRY(sc->blk_cs.reserve((size_t)sc->nc + nblk + 1));
-    NBGS_TRY(sc->blk_nrun.reserve((size_t)nblk + 1));
-    k_blk_colour_runs<<<(unsigned)nblk, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p,
+    // the last id's contacts (between blocks, swept by colour) take no slot; blocks and groups do
+    const int32_t nids = sc->n_sub - 1;
+    (void)nblk;
+    NBGS_TRY(prepare_impl<T>(sc, nids, 8, false));
+    NBGS_TRY(sc->blk_cs.reserve((size_t)sc->nc + nids + 1));
+    NBGS_TRY(sc->blk_nrun.reserve((size_t)nids + 1));
+    k_blk_colour_runs<<<(unsigned)nids, kBlkThreads, 0, s>>>(sw.col.p, sc->tile_off.p, sc->blk_cs.p,
                                                              sc->blk_nrun.p);
     NBGS_HIP(hipGetLastError());
     NBGS_TRY(cross_colours(sc, sw.col.p, sw.j1.p, sw.j2.p, sc->blk_first_cross, sc->nc));
@@ -1276,6 +1441,24 @@ static nbgs_status prepare_impl(nbgs_scene_t sc, int32_t no_slot, int values_per
         return NBGS_ERR_CAPACITY;
     }
     sc->max_slots = max_slots;
+    // the block-local order launches one grid at a time: each launch takes the local memory of its largest block
+    // (the later grids' blocks hold only the contacts the earlier grids cut, so they need less and more of them
+    // share a compute unit)
+    sc->launch_id0.clear();
+    sc->launch_n.clear();
+    sc->launch_slots.clear();
+    if (!body_lists && sc->blk_grid_ids > 0) {
+        auto group = [&](int32_t id0, int32_t n) {
+            int32_t m = 0;
+            for (int32_t t = id0; t < id0 + n; ++t) m = std::max(m, scnt[(size_t)t]);
+            sc->launch_id0.push_back(id0);
+            sc->launch_n.push_back(n);
+            sc->launch_slots.push_back(m);
+        };
+        for (int32_t id0 = 0; id0 < sc->n_blk; id0 += sc->blk_grid_ids)
+            group(id0, std::min(sc->blk_grid_ids, sc->n_blk - id0));
+        if (sc->blk_groups > 0) group(sc->n_blk, sc->blk_groups);  // the clusters no grid holds
+    }
     // 64-bit contact offsets of the tiles
     std::vector<int64_t> toff((size_t)nsub + 1, 0);
     for (int32_t t = 0; t < nsub; ++t) toff[(size_t)t + 1] = toff[(size_t)t] + cnt[(size_t)t];
@@ -1349,14 +1532,16 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
     v.px = sw.px.p;
     v.py = sw.py.p;
     v.pz = sw.pz.p;
-    const size_t lds = (size_t)std::max(sc->max_slots, 1) * 8 * sizeof(T);
     const T mu = (T)sc->p.mu, relax = (T)sc->p.relax;
     // one grid: every dynamic body of a block, sorted by block; several: the bodies the local contacts touch
     const int32_t *slot_body = sc->blk_grids > 1 ? sc->slot_body.p : reinterpret_cast<const int32_t *>(sc->body_slots);
-    // one launch per grid: a grid's blocks share no dynamic body, the next grid sees their results
-    const int32_t B = sc->blk_grid_ids;
-    for (int32_t id0 = 0; id0 < sc->n_blk; id0 += B) {
-        const unsigned grid = (unsigned)std::min(B, sc->n_blk - id0);
+    // one launch per grid (a grid's blocks share no dynamic body, the next grid sees their results), then the
+    // groups of the clusters no grid holds
+    for (size_t li = 0; li < sc->launch_id0.size(); ++li) {
+        const int32_t id0 = sc->launch_id0[li];
+        const unsigned grid = (unsigned)sc->launch_n[li];
+        if (grid == 0) continue;
+        const size_t lds = (size_t)std::max(sc->launch_slots[li], 1) * 8 * sizeof(T);
         // FP64 records: the held form; FP32 records: the streamed form (the faster of the two for each)
         if constexpr (sizeof(T) == 8) {
             if (mode == 0)

@@ -41,7 +41,7 @@ def _with_static(sc):
     return sc
 
 
-@pytest.mark.parametrize("grids", [1, 4])
+@pytest.mark.parametrize("grids", [1, 2, 4])
 @pytest.mark.parametrize("name", list(CASES))
 def test_block_order_steps_match_oracle(name, grids):
     nb = _nb()
@@ -73,7 +73,7 @@ def test_block_order_steps_match_oracle(name, grids):
     g.close()
 
 
-@pytest.mark.parametrize("grids", [1, 4])
+@pytest.mark.parametrize("grids", [1, 2, 4])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_block_order_limits_equal_the_classic_sweep(precision, grids):
     """One block over the whole box (every contact local) and blocks too small to hold two touching centres in a
@@ -218,4 +218,52 @@ def test_block_grids_errors_and_fp32():
     c = g32.contacts()
     assert np.array_equal(c["key"], v["key"]) and np.array_equal(c["colour"], v["colour"])
     assert np.abs(c["P"] - v["P"]).max() <= 2e-4 * np.abs(v["P"]).max()
+    g32.close()
+
+
+@pytest.mark.parametrize("edge", [2.5, 5.0])
+def test_two_grids_cross_clusters_match_oracle(edge):
+    """Two grids leave a few contacts in no block (cut by both); they form small clusters (contacts joined by a shared
+    dynamic body), which the library packs into groups swept by the block pass in one launch.  Each cluster keeps
+    the (colour, key) order of the colour launches, so the steps equal the oracle's bit for bit."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    nb = _nb()
+    sc = sg.dense_packing(tiles=1)
+    w = oracle.World(sc.copy()).set_block_order(edge, grids=2)
+    g = nb.GpuScene(sc.copy()).set_block_order(edge, grids=2)
+    for step in range(2):
+        g.step(20)
+        w.step(20, grid=True)
+        v = w.view()
+        cross = np.nonzero(v["sdom"] == v["n_sub"] - 1)[0]
+        assert len(cross) > 0
+        # the clusters are small (the condition for the grouped sweep)
+        ends = [np.where((e < sc.n) & (sc.inv_mass[np.minimum(e, sc.n - 1)] > 0), e, -1)
+                for e in (v["j1"][cross].astype(np.int64), v["j2"][cross].astype(np.int64))]
+        r = np.concatenate([np.arange(len(cross))[e >= 0] for e in ends])
+        cidx = np.concatenate([e[e >= 0] for e in ends])
+        A = coo_matrix((np.ones(len(r)), (r, cidx)), shape=(len(cross), sc.n)).tocsr()
+        _, lab = connected_components(A @ A.T, directed=False)
+        assert np.bincount(lab).max() < 100
+        c = g.contacts()
+        assert np.array_equal(c["key"], v["key"]) and np.array_equal(c["colour"], v["colour"]), step
+        assert np.array_equal(c["P"], v["P"]), step
+        gv, gw = g.accumulators()
+        assert np.array_equal(gv, v["v"]) and np.array_equal(gw, v["w"]), step
+        np.testing.assert_allclose(g.residuals(), v["residual_hist"], rtol=1e-9)
+    assert np.array_equal(g.state()["vel"], w.sc.vel)
+    g.close()
+    # FP32 records in the same order, at the FP32 bar
+    g32 = nb.GpuScene(sc.copy(), precision="fp32").set_block_order(edge, grids=2)
+    g32.detect()
+    g32.solve(25)
+    w2 = oracle.World(sc.copy()).set_block_order(edge, grids=2)
+    w2.detect(grid=True)
+    w2.solve(25)
+    v2 = w2.view()
+    c = g32.contacts()
+    assert np.array_equal(c["key"], v2["key"]) and np.array_equal(c["colour"], v2["colour"])
+    assert np.abs(c["P"] - v2["P"]).max() <= 2e-4 * np.abs(v2["P"]).max()
     g32.close()
