@@ -605,8 +605,13 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     // overflow of the pair count, [3] largest h, [4] largest displacement + h + radius growth since the list's build
     const bool have_list = sc->vl_enabled && sc->vl_valid;
     NBGS_HIP(hipMemsetAsync(sc->maxbits.p, 0, 5 * sizeof(unsigned long long), s));
+    // every body's dynamic bit, compared with the last detection's (kept current at every detection): small[7]
+    // counts the words that changed
+    NBGS_TRY(sc->dyn_bits.reserve((size_t)((sc->b.n + 63) / 64 + 1), 1.0));
+    NBGS_HIP(hipMemsetAsync(sc->small.p + 7, 0, sizeof(int32_t), s));
     NBGS_TRY(launch_hull(sc->b, sc->p.dt, sc->p.tau, sc->h.p, sc->maxbits.p, have_list ? sc->vl_x0.p : nullptr,
-                         have_list ? sc->vl_r0.p : nullptr, have_list ? sc->vl_static0.p : nullptr, s));
+                         have_list ? sc->vl_r0.p : nullptr, have_list ? sc->vl_static0.p : nullptr, sc->dyn_bits.p,
+                         sc->small.p + 7, s));
     unsigned long long mb[5];
     NBGS_HIP(hipMemcpyAsync(sc->pinned, sc->maxbits.p, sizeof(mb), hipMemcpyDeviceToHost, s));
     NBGS_HIP(hipStreamSynchronize(s));
@@ -670,11 +675,7 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     const bool warm_colours = sc->prev_colours && sc->n_prev > 0 && nc > 0;
     // new pairs are counted when the previous colouring may be reused whole (same pair count)
     const bool maybe_same = warm_colours && nc == sc->n_prev;
-    if (maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 4, 0, 4 * sizeof(int32_t), s));
-    // every body's dynamic bit, compared with the last detection's (kept current at every detection)
-    NBGS_TRY(sc->dyn_bits.reserve((size_t)((sc->b.n + 63) / 64 + 1), 1.0));
-    if (!maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 7, 0, sizeof(int32_t), s));
-    NBGS_TRY(launch_dyn_bits(sc->b.inv_mass, sc->b.n, sc->dyn_bits.p, sc->small.p + 7, s));
+    if (maybe_same) NBGS_HIP(hipMemsetAsync(sc->small.p + 4, 0, 3 * sizeof(int32_t), s));  // small[7]: the hull pass
     const bool dyn_bits_known = sc->dyn_bits_valid;
     sc->dyn_bits_valid = true;
     NBGS_TRY(launch_match_prev(cb.view(), nc, prev.key.p, prev.px.p, prev.py.p, prev.pz.p, prev.colour.p, sc->n_prev,
@@ -1715,9 +1716,10 @@ nbgs_status nbgs_detect(nbgs_scene_t sc, nbgs_stats *stats) {
         sc->dyn_bits_valid = false;
         st = detect_impl(sc, stats);
     }
+    // a failed detection may have updated per-body state (hull radii, dynamic bits): the next one reuses nothing
+    if (st != NBGS_OK) sc->prev_sig_valid = false;
     if (st == NBGS_ERR_CAPACITY) {
         // what was lacking: the contact count found, for nbgs_workspace_query
-        sc->prev_sig_valid = false;
         if (stats) {
             *stats = nbgs_stats{};
             stats->n_contacts = sc->nc_needed;

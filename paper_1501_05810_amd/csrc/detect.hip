@@ -47,28 +47,51 @@ struct ListRef {
 // |x_i - x_i(build)| + h_i + max(0, r_i - r_i(build)) (max_bits[4]; +inf when
 // a body's static flag changed).  The list stays exact while that stays below
 // its skin: a pair further apart than r_i + r_k + 2 skin at the build cannot
-// overlap its hulls then.
+// overlap its hulls then.  The same pass keeps every body's dynamic bit
+// (bit i of bits, one word per wave of 64 bodies) and adds the number of
+// words that changed since the last detection to *changed (the colouring and
+// the block slots depend on which bodies are dynamic, so a colouring is
+// reused only while no word changed).  Waves walk the
+// bodies in steps of whole 64-body words, so every lane of a wave takes part
+// in each ballot.
 __global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double tau, double *h,
-                                                 unsigned long long *max_bits, ListRef ref) {
+                                                 unsigned long long *max_bits, ListRef ref, uint64_t *bits,
+                                                 int32_t *changed) {
     double rmax = 0.0, hmax = 0.0, dmax = 0.0;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < b.n; i += gridDim.x * kBlock) {
-        const double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
-        const double wx = b.wx[i], wy = b.wy[i], wz = b.wz[i];
-        const double r = b.radius[i];
-        const double speed = sqrt(vx * vx + vy * vy + vz * vz);
-        const double spin = sqrt(wx * wx + wy * wy + wz * wz);
-        const double hi = dt * (speed + spin * r) + tau;
-        h[i] = hi;
-        double rh = r + hi;
-        if (!(rh == rh)) rh = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf: caught on the host
-        rmax = fmax(rmax, rh);
-        hmax = fmax(hmax, hi);
-        if (ref.x0) {
-            const double dx = b.x[i] - ref.x0[i], dy = b.y[i] - ref.y0[i], dz = b.z[i] - ref.z0[i];
-            double d = sqrt(dx * dx + dy * dy + dz * dz) + hi + fmax(0.0, r - ref.r0[i]);
-            if (!(d == d) || (uint8_t)(b.inv_mass[i] == 0.0) != ref.static0[i])
-                d = __longlong_as_double(0x7ff0000000000000ll);
-            dmax = fmax(dmax, d);
+    int diff = 0;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); i0 < b.n; i0 += stride) {
+        const int64_t i = i0 + lane;
+        bool dyn = false;
+        if (i < b.n) {
+            const double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
+            const double wx = b.wx[i], wy = b.wy[i], wz = b.wz[i];
+            const double r = b.radius[i];
+            const double im = b.inv_mass[i];
+            dyn = im > 0.0;
+            const double speed = sqrt(vx * vx + vy * vy + vz * vz);
+            const double spin = sqrt(wx * wx + wy * wy + wz * wz);
+            const double hi = dt * (speed + spin * r) + tau;
+            h[i] = hi;
+            double rh = r + hi;
+            if (!(rh == rh)) rh = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf: caught on the host
+            rmax = fmax(rmax, rh);
+            hmax = fmax(hmax, hi);
+            if (ref.x0) {
+                const double dx = b.x[i] - ref.x0[i], dy = b.y[i] - ref.y0[i], dz = b.z[i] - ref.z0[i];
+                double d = sqrt(dx * dx + dy * dy + dz * dz) + hi + fmax(0.0, r - ref.r0[i]);
+                if (!(d == d) || (uint8_t)(im == 0.0) != ref.static0[i]) d = __longlong_as_double(0x7ff0000000000000ll);
+                dmax = fmax(dmax, d);
+            }
+        }
+        const unsigned long long m = __ballot(dyn);
+        if (lane == 0) {
+            const int64_t word = i0 >> 6;
+            if (bits[word] != (uint64_t)m) {
+                bits[word] = (uint64_t)m;
+                ++diff;
+            }
         }
     }
 #pragma unroll
@@ -78,10 +101,12 @@ __global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double
         dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
     }
     __shared__ double wmax[3][kBlock / 64];
-    if ((threadIdx.x & 63) == 0) {
+    __shared__ int wdiff[kBlock / 64];
+    if (lane == 0) {
         wmax[0][threadIdx.x >> 6] = rmax;
         wmax[1][threadIdx.x >> 6] = hmax;
         wmax[2][threadIdx.x >> 6] = dmax;
+        wdiff[threadIdx.x >> 6] = diff;
     }
     __syncthreads();
     if (threadIdx.x < 3) {  // the maxima are order-independent
@@ -89,6 +114,10 @@ __global__ void __launch_bounds__(kBlock) k_hull(BodiesView b, double dt, double
         double m = wmax[k][0];
         for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, wmax[k][w]);
         if (k == 0 || m > 0.0) atomicMax(&max_bits[k == 0 ? 0 : k + 2], (unsigned long long)__double_as_longlong(m));
+    } else if (threadIdx.x == 64) {  // one atomic per workgroup (the first detection changes every word)
+        int t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wdiff[w];
+        if (t) atomicAdd(changed, t);
     }
 }
 
@@ -559,33 +588,6 @@ __global__ void __launch_bounds__(kBlock) k_ids_changed(const int32_t *sdom, con
     }
 }
 
-// Which bodies are dynamic (1/m > 0), one bit per body in 64-bit words (a
-// wave's 64 consecutive bodies per word): the words are rewritten, and the
-// number of words that differ from the stored ones is added to changed.  The
-// colouring and the block slots depend on these bits (a conflict is a shared
-// dynamic body), so a colouring is reused only while they stay the same.
-__global__ void __launch_bounds__(kBlock) k_dyn_bits(const double *inv_mass, int64_t n, uint64_t *bits,
-                                                     int32_t *changed) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool dyn = i < n && inv_mass[i] > 0.0;
-    const unsigned long long m = __ballot(dyn);
-    const int64_t word = i >> 6;
-    int diff = 0;
-    if ((threadIdx.x & 63) == 0 && word * 64 < n && bits[word] != (uint64_t)m) {
-        bits[word] = (uint64_t)m;
-        diff = 1;
-    }
-    // one atomic per workgroup (the first detection changes every word)
-    __shared__ int wdiff[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wdiff[threadIdx.x >> 6] = diff;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kBlock / 64; ++w) t += wdiff[w];
-        if (t) atomicAdd(changed, t);
-    }
-}
-
 // The pair list's pairs (canonical order) tested with this step's hulls by
 // exactly the predicates of the pair count: two bodies' reaches (r + h, the
 // same roundings) against their minimum-image distance, two static bodies
@@ -690,11 +692,12 @@ __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *p, int64_t n, int3
 }  // namespace
 
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
-                        const double *x0, const double *r0, const uint8_t *static0, hipStream_t s) {
+                        const double *x0, const double *r0, const uint8_t *static0, uint64_t *dyn_bits,
+                        int32_t *dyn_changed, hipStream_t s) {
     if (b.n <= 0) return NBGS_OK;
     const unsigned blocks = std::min<unsigned>(grid_for(b.n), (unsigned)kHullBlocks);
     ListRef ref{x0, x0 ? x0 + b.n : nullptr, x0 ? x0 + 2 * (int64_t)b.n : nullptr, r0, static0};
-    k_hull<<<blocks, kBlock, 0, s>>>(b, dt, tau, h, max_bits, ref);
+    k_hull<<<blocks, kBlock, 0, s>>>(b, dt, tau, h, max_bits, ref, dyn_bits, dyn_changed);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -814,14 +817,6 @@ nbgs_status launch_ids_changed(const int32_t *sdom, const int32_t *prev_sdom, co
                                int32_t *changed, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
     k_ids_changed<<<grid_for(nc), kBlock, 0, s>>>(sdom, prev_sdom, matched, nc, changed);
-    NBGS_HIP(hipGetLastError());
-    return NBGS_OK;
-}
-
-nbgs_status launch_dyn_bits(const double *inv_mass, int64_t n, uint64_t *bits, int32_t *changed, hipStream_t s) {
-    if (n == 0) return NBGS_OK;
-    static_assert(kBlock % 64 == 0, "a word is one wave's bodies");
-    k_dyn_bits<<<grid_for(n), kBlock, 0, s>>>(inv_mass, n, bits, changed);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }

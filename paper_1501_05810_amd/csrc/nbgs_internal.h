@@ -234,8 +234,11 @@ size_t radix_hist_entries(int64_t n);
 // detect.hip
 // Partners (k > i) of a body kept by the pair count for the emit; longer lists are searched again.
 constexpr int kPartnerCap = 16;
+// Hull radii, their maxima, the pair list's validity and every body's dynamic bit (dyn_bits, one word per 64
+// bodies; *dyn_changed += the words that changed), in one pass over the bodies.
 nbgs_status launch_hull(const BodiesView &b, double dt, double tau, double *h, unsigned long long *max_bits,
-                        const double *x0, const double *r0, const uint8_t *static0, hipStream_t s);
+                        const double *x0, const double *r0, const uint8_t *static0, uint64_t *dyn_bits,
+                        int32_t *dyn_changed, hipStream_t s);
 nbgs_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 nbgs_status launch_static_flags(const double *inv_mass, int64_t n, uint8_t *flags, hipStream_t s);
 // The pair list (see detect.hip): test its pairs with this step's hulls, compact the contacts, geometry.
@@ -274,7 +277,6 @@ nbgs_status launch_ids_changed(const int32_t *sdom, const int32_t *prev_sdom, co
                                int32_t *changed, hipStream_t s);
 // One bit per body (1/m > 0) in (n + 63) / 64 words; words that differ from the stored ones are rewritten and
 // counted into changed.
-nbgs_status launch_dyn_bits(const double *inv_mass, int64_t n, uint64_t *bits, int32_t *changed, hipStream_t s);
 nbgs_status launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 nbgs_status launch_zero_impulses(ContactsView c, int64_t nc, hipStream_t s);
 
