@@ -300,7 +300,13 @@ nbgs_status nbgs_set_block_order(nbgs_scene_t scene, double edge);
  * rest in (colour, key) order: the same plain NBGS (Alg. 1 with one
  * subdomain), visited in another order.  With four grids a contact whose
  * centres differ by less than a quarter block edge along every axis is
- * always local.  Takes effect at the next detection; INVALID_ARG outside
+ * always local.  With two or more grids the rest, which touch each other only
+ * through shared dynamic bodies, are swept by cluster (the components of
+ * "shares a dynamic body", packed whole into groups that the block pass runs
+ * as it runs blocks): each cluster in its (colour, key) order, so every
+ * contact is relaxed as in the colour-ordered sweep of the rest, bit for bit;
+ * when a group would exceed the workgroup's local memory they are swept
+ * colour by colour.  Takes effect at the next detection; INVALID_ARG outside
  * 1 .. 8. */
 nbgs_status nbgs_set_block_grids(nbgs_scene_t scene, int32_t grids);
 
