@@ -700,6 +700,84 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk_colour_runs(const int32_t *
 // of the chunk (ascending, hence in colour order).
 constexpr int kBlkHeld = 3;
 
+// s_waitcnt immediate of gfx9-family targets: vector memory count 0 (bits 3:0 and 15:14), export and LDS counts
+// left at their maxima (bits 6:4 = 7, 11:8 = 15).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// A block's slot records staged into LDS ([8][ns]: v'x v'y v'z w'x w'y w'z
+// 1/m 1/I) and written back (the first six) by the held form: kStage slots
+// per thread at a time, their body indices loaded first and then their
+// records as whole 16-byte pieces, so that a block waits on two memory round
+// trips per kStage * NT slots instead of two per NT (the streamed FP32 form
+// keeps one slot per step: measured faster there).
+constexpr int kStage = 8;
+
+__device__ inline void load_rec8(const double *p, double v[8]) {
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2 x = q[k];
+        v[2 * k] = x.x;
+        v[2 * k + 1] = x.y;
+    }
+}
+
+__device__ inline void load_rec8(const float *p, float v[8]) {
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float4 x = q[k];
+        v[4 * k] = x.x;
+        v[4 * k + 1] = x.y;
+        v[4 * k + 2] = x.z;
+        v[4 * k + 3] = x.w;
+    }
+}
+
+template <class T, int NT>
+__device__ inline void blk_stage(T *Vs, int ns, const T *vel, const int32_t *slot_body, int s0, int t) {
+    for (int i0 = 0; i0 < ns; i0 += kStage * NT) {
+        int32_t bi[kStage];
+#pragma unroll
+        for (int k = 0; k < kStage; ++k) {
+            const int i = i0 + t + k * NT;
+            bi[k] = i < ns ? slot_body[s0 + i] : -1;
+        }
+        T rec[kStage][8];
+#pragma unroll
+        for (int k = 0; k < kStage; ++k)
+            if (bi[k] >= 0) load_rec8(vel + 8 * (int64_t)bi[k], rec[k]);
+#pragma unroll
+        for (int k = 0; k < kStage; ++k) {
+            const int i = i0 + t + k * NT;
+            if (i < ns) {
+#pragma unroll
+                for (int a = 0; a < 8; ++a) Vs[a * ns + i] = rec[k][a];
+            }
+        }
+    }
+}
+
+template <class T, int NT>
+__device__ inline void blk_write_back(const T *Vs, int ns, T *vel, const int32_t *slot_body, int s0, int t) {
+    for (int i0 = 0; i0 < ns; i0 += kStage * NT) {
+        int32_t bi[kStage];
+#pragma unroll
+        for (int k = 0; k < kStage; ++k) {
+            const int i = i0 + t + k * NT;
+            bi[k] = i < ns ? slot_body[s0 + i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kStage; ++k)
+            if (bi[k] >= 0) {
+                const int i = i0 + t + k * NT;
+                T *r = vel + 8 * (int64_t)bi[k];
+#pragma unroll
+                for (int a = 0; a < 6; ++a) r[a] = Vs[a * ns + i];
+            }
+    }
+}
+
 // One local contact's data, loaded ahead of its colour run.
 template <class T>
 struct HeldContact {
@@ -743,6 +821,9 @@ __device__ inline void blk_end_rec(const T *Vs, int ns, const T *vel, int l, con
         r.w[2] = g[5];
         r.im = g[6];
         r.ii = g[7];
+        // Wait for these loads here, on this rare path: otherwise the merge with the LDS path above waits for every
+        // outstanding vector memory operation (the impulse stores of the contacts before included) on every contact.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     } else {  // a wall
         r = zero_rec<T>();
     }
@@ -784,16 +865,14 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t
     constexpr int kHeld = kBlkHeld, kChunk = kBlkThreads * kHeld;
     const int t = threadIdx.x;
     HeldContact<T> held[kHeld];
-    // the first chunk's loads go out before the block's records are staged
+    // the first chunk's loads and the colour runs' starts go out before the block's records are staged
 #pragma unroll
     for (int k = 0; k < kHeld; ++k)
         if (t + k * kBlkThreads < count) blk_load<T, MODE>(sv, c0 + t + k * kBlkThreads, held[k]);
-    for (int i = t; i < ns; i += kBlkThreads) {
-        const T *r = vel + 8 * (int64_t)slot_body[s0 + i];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) Vs[a * ns + i] = r[a];
-    }
-    for (int c = t; c <= ncol; c += kBlkThreads) cstart[c] = cs[c];
+    const int32_t cs0 = t <= ncol ? cs[t] : 0;
+    blk_stage<T, kBlkThreads>(Vs, ns, vel, slot_body, s0, t);
+    if (t <= ncol) cstart[t] = cs0;
+    for (int c = t + kBlkThreads; c <= ncol; c += kBlkThreads) cstart[c] = cs[c];
     __syncthreads();
     double sd = 0.0, sp = 0.0;
     int run = 0;  // the colour run being relaxed (uniform)
@@ -838,11 +917,7 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk_pass(SubView<T> sv, int32_t
             ++run;
         }
     }
-    for (int i = threadIdx.x; i < ns; i += kBlkThreads) {
-        T *r = vel + 8 * (int64_t)slot_body[s0 + i];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) r[a] = Vs[a * ns + i];
-    }
+    blk_write_back<T, kBlkThreads>(Vs, ns, vel, slot_body, s0, (int)threadIdx.x);
     if (MODE == 1) {
         __shared__ double red[2][kBlkThreads / 64];
 #pragma unroll
