@@ -708,7 +708,9 @@ nbgs_status detect_impl(nbgs_scene_t sc, nbgs_stats *stats) {
     sc->sub_active = sc->sub_edge > 0.0 && nc > 0;
     sc->blk_active = !sc->sub_active && sc->blk_edge > 0.0 && nc > 0;
     if (sc->sub_active) NBGS_TRY(subdomain_assign(sc));
-    if (sc->blk_active) NBGS_TRY(block_assign(sc, sc->small.p + 6));
+    if (!sc->blk_active) sc->xg_prev_valid = false;  // the last ids kept are not this order's
+    if (sc->blk_active)
+        NBGS_TRY(block_assign(sc, sc->small.p + 6, maybe_same && dyn_bits_known && sc->prev_sig_valid));
     const int32_t *sdom = sc->sub_active || sc->blk_active ? sc->sdom.p : nullptr;
     // The greedy colouring and the (id, colour, key) order are functions of the pair keys, the ids, the seed and
     // which bodies are dynamic only.  When every pair of this step is a pair of the last one (same count, none new),

@@ -265,6 +265,8 @@ struct nbgs_scene_s {
     // pass; 0: those contacts keep the id n_blk and are swept by colour)
     int32_t blk_groups = 0;
     bool blk_group_cross = true;
+    bool xg_prev_valid = false;  // the last detection formed its groups in this order (n_blk blocks)
+    int32_t xg_prev_nblk = 0;
     DevBuf<int32_t> xg_ctl, xg_cnt;
     int64_t blk_first_cross = 0;  // first sweep position of the contacts between blocks
     std::vector<int64_t> xcol;       // positions of the cross colours' ranges (size colours + 1)
@@ -333,7 +335,7 @@ nbgs_status subdomain_pass(nbgs_scene_t sc, int mode, T *vel, T *corr);
 // velocities updated in place in LDS.
 // Contact ids of the block-local order; every body's block, the number that changed since the last step added to
 // changed.
-nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed);
+nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed, bool maybe_reuse);
 nbgs_status block_prepare(nbgs_scene_t sc);
 template <class T>
 nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel);

@@ -204,6 +204,28 @@ __global__ void __launch_bounds__(kBlock) k_cc_reset(const int32_t *xl, int32_t 
     if (q < nx) id[xl[q]] = cross;
 }
 
+// This step's ids from the grids (id n_blk: local in none) against the last step's final ids of the same pairs
+// (matched[j] - 1; ids n_blk and above: local in none, in a group or swept by colour): *changed counts the pairs
+// whose grid id differs or that became or stopped being local in none.
+__global__ void __launch_bounds__(kBlock) k_raw_ids_changed(const int32_t *id, const int32_t *prev,
+                                                            const int32_t *matched, int64_t nc, int32_t nblk,
+                                                            int32_t *changed) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool diff = false;
+    if (j < nc) {
+        const int32_t a = id[j], b = prev[matched[j] - 1];
+        diff = (a >= nblk) != (b >= nblk) || (a < nblk && a != b);
+    }
+    if (__ballot(diff) && (threadIdx.x & 63) == 0) atomicAdd(changed, 1);
+}
+
+// The last step's final ids for the same pairs.
+__global__ void __launch_bounds__(kBlock) k_ids_from_prev(const int32_t *prev, const int32_t *matched, int64_t nc,
+                                                          int32_t *id) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j < nc) id[j] = prev[matched[j] - 1];
+}
+
 __global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t *v, int32_t n, int32_t *out) {
     const int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     int32_t m = i < n ? v[i] : 0;
@@ -1218,7 +1240,10 @@ static nbgs_status cross_groups(nbgs_scene_t sc, int32_t *groups) {
 }
 
 // Block-local ids of the contacts: ids 0 .. n_blk - 1 local, n_blk between blocks.
-nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed) {
+// maybe_reuse: every pair of this step is one of the last step's (as far as the match has counted: small[4]), the
+// dynamic bits are known (small[7] counts their changes) and the last step used this order; then, when no pair's
+// grid id changed either, the clusters of the contacts local in no grid and their groups are the last step's.
+nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed, bool maybe_reuse) {
     hipStream_t s = sc->s;
     Blocks bl;
     int64_t nblocks = 1;
@@ -1248,8 +1273,31 @@ nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed) {
                                                             sc->periodic[0], sc->periodic[1], sc->periodic[2],
                                                             sc->sdom.p);
     }
+    const int32_t prev_groups = sc->blk_groups;
     sc->blk_groups = 0;
-    if (sc->blk_grids > 1 && sc->blk_group_cross) NBGS_TRY(cross_groups(sc, &sc->blk_groups));
+    if (sc->blk_grids > 1 && sc->blk_group_cross) {
+        bool reused = false;
+        if (maybe_reuse && sc->xg_prev_valid && sc->xg_prev_nblk == sc->n_blk && sc->prev_sdom.p && nc > 0) {
+            NBGS_TRY(sc->xg_ctl.reserve(64, 1.0));
+            k_fill<<<1, kBlock, 0, s>>>(sc->xg_ctl.p + 60, 1, 0);
+            k_raw_ids_changed<<<grid_for(nc), kBlock, 0, s>>>(sc->sdom.p, sc->prev_sdom.p, c.matched, nc, sc->n_blk,
+                                                             sc->xg_ctl.p + 60);
+            NBGS_HIP(hipGetLastError());
+            NBGS_HIP(hipMemcpyAsync(sc->pinned + 96, sc->xg_ctl.p + 60, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            NBGS_TRY(scene_sync_small(sc, 4, 4));
+            if (sc->pinned[96] == 0 && sc->pinned[4] == 0 && sc->pinned[7] == 0) {
+                k_ids_from_prev<<<grid_for(nc), kBlock, 0, s>>>(sc->prev_sdom.p, c.matched, nc, sc->sdom.p);
+                NBGS_HIP(hipGetLastError());
+                sc->blk_groups = prev_groups;
+                reused = true;
+            }
+        }
+        if (!reused) NBGS_TRY(cross_groups(sc, &sc->blk_groups));
+        sc->xg_prev_valid = true;
+        sc->xg_prev_nblk = sc->n_blk;
+    } else {
+        sc->xg_prev_valid = false;
+    }
     sc->n_sub = sc->n_blk + sc->blk_groups + 1;
     NBGS_HIP(hipGetLastError());
     // every body's block, compared with the last step's (bodies without local contacts count too: they decide the
