@@ -917,6 +917,13 @@ nbgs_status accumulate_profile(nbgs_scene_t sc, int32_t sweeps) {
     return NBGS_OK;
 }
 
+// The solver's records at the start of a solve: every body's, or with few contacts the touched bodies' only.
+template <class T>
+nbgs_status init_records(nbgs_scene_t sc, T *vel) {
+    if (sc->sparse_bodies) return launch_init_touched<T>(sc->b, sc->p.gravity, sc->p.dt, sc->touched.p, vel, sc->s);
+    return launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel, sc->s);
+}
+
 // Jacobi residual of the previous-step and of the learned initial impulses;
 // the sweep record keeps the better one (ties: the network).
 template <class T>
@@ -930,7 +937,7 @@ nbgs_status judge_warm_start(nbgs_scene_t sc) {
     ContactBuf &cb = sc->cb[sc->cur];
     for (int cand = 0; cand < 2; ++cand) {
         if (cand == 1) NBGS_TRY(launch_set_sweep_impulses<T>(sw.view(), sc->nc, sc->lpx.p, sc->lpy.p, sc->lpz.p, s));
-        NBGS_TRY(launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel.p, s));
+        NBGS_TRY(init_records<T>(sc, vel.p));
         for (int c = 0; c < sc->n_colours; ++c)
             NBGS_TRY(launch_warm_scatter<T>(sw.view(), sc->col_off[c], sc->col_off[c + 1], N, vel.p, s));
         NBGS_TRY(launch_jacobi_residual<T>(sw.view(), sc->nc, N, vel.p, sc->p.mu, sc->jpart.p, sc->jres.p + cand, s));
@@ -1256,8 +1263,16 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
     NBGS_TRY(sc->res_hist.reserve((size_t)max_sweeps));
     record(sc, kInit);
     sc->winfo = nbgs_warm_info{-1, 0.0, 0.0};
+    // few contacts on many bodies: records only for the bodies they touch (the sweeps read no other; the
+    // integration and the export form the rest from the state); a small scene keeps the two launches fewer
+    sc->sparse_bodies = N >= (1 << 16) && sc->nc < (int64_t)N / 8;
+    if (sc->sparse_bodies) {
+        NBGS_TRY(sc->touched.reserve((size_t)N + 1, 1.0));
+        const ContactBuf &cb = sc->cb[sc->cur];
+        NBGS_TRY(launch_mark_touched(cb.j1.p, cb.j2.p, sc->nc, N, sc->touched.p, s));
+    }
     if (sc->p.warm_start == NBGS_WS_LEARNED && sc->have_learned) NBGS_TRY(judge_warm_start<T>(sc));
-    NBGS_TRY(launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel.p, s));
+    NBGS_TRY(init_records<T>(sc, vel.p));
     if (sc->sub_active) return sub_solve<T>(sc, max_sweeps, target, stats);
     if (sc->blk_active) return blk_solve<T>(sc, max_sweeps, target, stats);
     if (sc->p.warm_start != NBGS_WS_ZERO)
@@ -1340,7 +1355,8 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
 template <class T>
 nbgs_status integrate_impl(nbgs_scene_t sc) {
     record(sc, kIntegrate);
-    NBGS_TRY(launch_integrate<T>(sc->b, sc->grid, sc->table(), sc->p.dt, vel_buf<T>(sc).p, sc->s));
+    NBGS_TRY(launch_integrate<T>(sc->b, sc->grid, sc->table(), sc->p.dt, vel_buf<T>(sc).p,
+                                 sc->sparse_bodies ? sc->touched.p : nullptr, sc->p.gravity, sc->s));
     record(sc, kNumPhases);
     sc->table_in_cur = true;
     sc->n_prev = sc->nc;
@@ -1815,13 +1831,17 @@ nbgs_status nbgs_get_accumulators(nbgs_scene_t sc, double *v, double *w) {
             set_error("no solve yet");
             return NBGS_ERR_STATE;
         }
-        return launch_export_accumulators<float>(sc->vel32.p, sc->b.n, v, w, sc->s);
+        return launch_export_accumulators<float>(sc->vel32.p, sc->b.n, v, w, sc->b,
+                                                 sc->sparse_bodies ? sc->touched.p : nullptr, sc->state == 2,
+                                                 sc->p.gravity, sc->p.dt, sc->s);
     }
     if (!sc->vel64.p) {
         set_error("no solve yet");
         return NBGS_ERR_STATE;
     }
-    return launch_export_accumulators<double>(sc->vel64.p, sc->b.n, v, w, sc->s);
+    return launch_export_accumulators<double>(sc->vel64.p, sc->b.n, v, w, sc->b,
+                                              sc->sparse_bodies ? sc->touched.p : nullptr, sc->state == 2,
+                                              sc->p.gravity, sc->p.dt, sc->s);
 }
 
 nbgs_status nbgs_get_residuals(nbgs_scene_t sc, int32_t cap, double *hist, int32_t *n_out) {

@@ -330,11 +330,21 @@ nbgs_status launch_residual(const double *partials, int32_t n_partials, double t
                             double *hist, hipStream_t s, int32_t at = -1);
 template <class T>
 nbgs_status launch_integrate(const BodiesView &b, const Grid &g, const SceneTable &st, double dt, const T *vel,
-                             hipStream_t s);
+                             const uint8_t *touched, const double grav[3], hipStream_t s);
+// Few contacts: touched[i] = 1 for every body a contact of the step touches (launch_mark_touched), the solver's
+// records written for those bodies only (launch_init_touched); the integration and the export take every other
+// body's record from its state (touched passed to them; NULL: every record is read).
+nbgs_status launch_mark_touched(const int32_t *j1, const int32_t *j2, int64_t nc, int32_t nb, uint8_t *touched,
+                                hipStream_t s);
+template <class T>
+nbgs_status launch_init_touched(const BodiesView &b, const double g[3], double dt, const uint8_t *touched, T *vel,
+                                hipStream_t s);
 template <class T>
 nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hipStream_t s);
 template <class T>
-nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, hipStream_t s);
+nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, const BodiesView &b,
+                                       const uint8_t *touched, bool pending, const double g[3], double dt,
+                                       hipStream_t s);
 
 // warmstart.hip
 struct FeatureScales {

@@ -265,6 +265,10 @@ struct nbgs_scene_s {
     // pass; 0: those contacts keep the id n_blk and are swept by colour)
     int32_t blk_groups = 0;
     bool blk_group_cross = true;
+    // few contacts (fewer than one per eight bodies, at least 2^16 bodies): the solver's records are kept for the
+    // touched bodies only
+    bool sparse_bodies = false;
+    DevBuf<uint8_t> touched;
     bool xg_prev_valid = false;  // the last detection formed its groups in this order (n_blk blocks)
     int32_t xg_prev_nblk = 0;
     DevBuf<int32_t> xg_ctl, xg_cnt;

@@ -10,6 +10,8 @@
 // the colour order: the sweep is the sequential Gauss-Seidel in (colour, key)
 // order, bit for bit.  The relaxation of one contact is relax_contact
 // (contact_math.h), shared with the block-local pass.
+#include <algorithm>
+
 #include "contact_math.h"
 #include "nbgs_internal.h"
 
@@ -106,6 +108,47 @@ __global__ void __launch_bounds__(kBlock) k_init_bodies(BodiesView b, double gx,
     const int nvalid = b.n - i0 < kBlock ? b.n - i0 : kBlock;
     T *out = vel + 8 * (int64_t)i0;
     for (int q = t; q < 8 * nvalid; q += kBlock) out[q] = stage[(q & 7) * S + (q >> 3)];
+}
+
+// The solver's record of a body that no contact touches: what k_init_bodies
+// writes, and what the sweeps leave unchanged.
+template <class T>
+__device__ inline void free_record(const BodiesView &b, int64_t i, double gx, double gy, double gz, double dt,
+                                   T r[8]) {
+    const double im = b.inv_mass[i];
+    const bool dyn = im > 0.0;
+    r[0] = (T)(dyn ? b.vx[i] + dt * gx : b.vx[i]);
+    r[1] = (T)(dyn ? b.vy[i] + dt * gy : b.vy[i]);
+    r[2] = (T)(dyn ? b.vz[i] + dt * gz : b.vz[i]);
+    r[3] = (T)b.wx[i];
+    r[4] = (T)b.wy[i];
+    r[5] = (T)b.wz[i];
+    r[6] = (T)im;
+    r[7] = (T)b.inv_inertia[i];
+}
+
+// Bodies that some contact of the step touches (either end, walls excepted).
+__global__ void __launch_bounds__(kBlock) k_mark_touched(const int32_t *j1, const int32_t *j2, int64_t nc, int32_t nb,
+                                                         uint8_t *touched) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nc) return;
+    touched[j1[j]] = 1;
+    const int32_t k = j2[j];
+    if (k < nb) touched[k] = 1;
+}
+
+// k_init_bodies for the touched bodies only (few contacts: the other records are never read).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_init_touched(BodiesView b, double gx, double gy, double gz, double dt,
+                                                         const uint8_t *touched, T *vel) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < b.n; i += (int64_t)gridDim.x * kBlock) {
+        if (!touched[i]) continue;
+        T r[8];
+        free_record<T>(b, i, gx, gy, gz, dt, r);
+        T *out = vel + 8 * i;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) out[a] = r[a];
+    }
 }
 
 // Initial impulses applied in colour order (one launch per colour), so every
@@ -470,23 +513,45 @@ __global__ void __launch_bounds__(kResBlock) k_residual(const double *partials, 
 }
 
 // eq. (integrationscheme) with quaternion renormalisation; periodic wrap.
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, SceneTable st, double dt, const T *vel) {
+// SPARSE (few contacts): only the touched bodies' records are read; every
+// other body takes the record k_init_bodies would have written.
+template <class T, bool SPARSE>
+__global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, SceneTable st, double dt, const T *vel,
+                                                      const uint8_t *touched, double gx, double gy, double gz) {
     // the workgroup's records are read as one contiguous run into LDS (neighbouring lanes load neighbouring words)
     constexpr int S = kStageRow<T>;
-    __shared__ T stage[8 * S];
+    __shared__ T stage[SPARSE ? 1 : 8 * S];
     const int i0 = blockIdx.x * kBlock;
     const int t = threadIdx.x, i = i0 + t;
-    const int nvalid = b.n - i0 < kBlock ? b.n - i0 : kBlock;
-    const T *in = vel + 8 * (int64_t)i0;
-    for (int q = t; q < 8 * nvalid; q += kBlock) stage[(q & 7) * S + (q >> 3)] = in[q];
-    __syncthreads();
-    if (i >= b.n) return;
+    T rec[6];
+    if constexpr (SPARSE) {
+        if (i >= b.n) return;
+        if (touched[i]) {
+            const T *r = vel + 8 * (int64_t)i;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) rec[a] = r[a];
+        } else {
+            T r[8];
+            free_record<T>(b, i, gx, gy, gz, dt, r);
+#pragma unroll
+            for (int a = 0; a < 6; ++a) rec[a] = r[a];
+        }
+    } else {
+        (void)touched;
+        (void)gx;
+        (void)gy;
+        (void)gz;
+        const int nvalid = b.n - i0 < kBlock ? b.n - i0 : kBlock;
+        const T *in = vel + 8 * (int64_t)i0;
+        for (int q = t; q < 8 * nvalid; q += kBlock) stage[(q & 7) * S + (q >> 3)] = in[q];
+        __syncthreads();
+        if (i >= b.n) return;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) rec[a] = stage[a * S + t];
+    }
     const Grid &g = st.body_scene ? st.grids[st.body_scene[i]] : g0;
-    const double vx = (double)stage[0 * S + t], vy = (double)stage[1 * S + t],
-                 vz = (double)stage[2 * S + t];
-    const double ox = (double)stage[3 * S + t], oy = (double)stage[4 * S + t],
-                 oz = (double)stage[5 * S + t];
+    const double vx = (double)rec[0], vy = (double)rec[1], vz = (double)rec[2];
+    const double ox = (double)rec[3], oy = (double)rec[4], oz = (double)rec[5];
     b.vx[i] = vx;
     b.vy[i] = vy;
     b.vz[i] = vz;
@@ -529,11 +594,29 @@ __global__ void __launch_bounds__(kBlock) k_save_impulses(SweepView<T> sv, int64
     c.pz[j] = (double)sv.pz[p];
 }
 
+// touched (few contacts): an untouched body's record is the one k_init_bodies would have written (before the
+// integration) or, after it, the body's velocities (which the integration took from that record).
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_export(const T *vel, int32_t nb, double *v, double *w) {
+__global__ void __launch_bounds__(kBlock) k_export(const T *vel, int32_t nb, double *v, double *w, BodiesView b,
+                                                   const uint8_t *touched, int pending, double gx, double gy,
+                                                   double gz, double dt) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= nb) return;
+    T fr[8];
     const T *r = vel + 8 * (int64_t)i;
+    if (touched && !touched[i]) {
+        if (pending) {
+            free_record<T>(b, i, gx, gy, gz, dt, fr);
+        } else {
+            fr[0] = (T)b.vx[i];
+            fr[1] = (T)b.vy[i];
+            fr[2] = (T)b.vz[i];
+            fr[3] = (T)b.wx[i];
+            fr[4] = (T)b.wy[i];
+            fr[5] = (T)b.wz[i];
+        }
+        r = fr;
+    }
     v[i] = (double)r[0];
     v[nb + i] = (double)r[1];
     v[2 * (int64_t)nb + i] = (double)r[2];
@@ -769,8 +852,30 @@ nbgs_status launch_residual(const double *partials, int32_t n_partials, double t
 
 template <class T>
 nbgs_status launch_integrate(const BodiesView &b, const Grid &g, const SceneTable &st, double dt, const T *vel,
-                             hipStream_t s) {
-    k_integrate<T><<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, dt, vel);
+                             const uint8_t *touched, const double grav[3], hipStream_t s) {
+    if (touched)
+        k_integrate<T, true><<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, dt, vel, touched, grav[0], grav[1], grav[2]);
+    else
+        k_integrate<T, false><<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, dt, vel, nullptr, 0.0, 0.0, 0.0);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+nbgs_status launch_mark_touched(const int32_t *j1, const int32_t *j2, int64_t nc, int32_t nb, uint8_t *touched,
+                                hipStream_t s) {
+    NBGS_HIP(hipMemsetAsync(touched, 0, (size_t)nb + 1, s));
+    if (nc <= 0) return NBGS_OK;
+    k_mark_touched<<<grid_for(nc), kBlock, 0, s>>>(j1, j2, nc, nb, touched);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status launch_init_touched(const BodiesView &b, const double g[3], double dt, const uint8_t *touched, T *vel,
+                                hipStream_t s) {
+    if (b.n <= 0) return NBGS_OK;
+    const unsigned blocks = std::min<unsigned>(grid_for(b.n), 4096u);
+    k_init_touched<T><<<blocks, kBlock, 0, s>>>(b, g[0], g[1], g[2], dt, touched, vel);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -784,8 +889,10 @@ nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hi
 }
 
 template <class T>
-nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, hipStream_t s) {
-    k_export<T><<<grid_for(nb), kBlock, 0, s>>>(vel, nb, v, w);
+nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, const BodiesView &b,
+                                       const uint8_t *touched, bool pending, const double g[3], double dt,
+                                       hipStream_t s) {
+    k_export<T><<<grid_for(nb), kBlock, 0, s>>>(vel, nb, v, w, b, touched, pending ? 1 : 0, g[0], g[1], g[2], dt);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -796,13 +903,16 @@ nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, doub
     template nbgs_status launch_sweep_colour<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, SweepParams,       \
                                                 const SweepTune &, double *, const int32_t *, hipStream_t);       \
     template nbgs_status launch_integrate<T>(const BodiesView &, const Grid &, const SceneTable &, double, const T *, \
-                                             hipStream_t);                                                        \
+                                             const uint8_t *, const double[3], hipStream_t);                     \
+    template nbgs_status launch_init_touched<T>(const BodiesView &, const double[3], double, const uint8_t *, T *, \
+                                                hipStream_t);                                                     \
     template unsigned sweep_graph_grid<T>(const SweepTune &);                                                     \
     template nbgs_status launch_sweep_colour_dev<T>(SweepView<T>, const int64_t *, int32_t, int32_t, T *,         \
                                                     SweepParams, const SweepTune &, double *, const int32_t *,    \
                                                     hipStream_t);                                                 \
     template nbgs_status launch_save_impulses<T>(SweepView<T>, int64_t, ContactsView, hipStream_t);              \
-    template nbgs_status launch_export_accumulators<T>(const T *, int32_t, double *, double *, hipStream_t);
+    template nbgs_status launch_export_accumulators<T>(const T *, int32_t, double *, double *, const BodiesView &, \
+                                                       const uint8_t *, bool, const double[3], double, hipStream_t);
 
 NBGS_INSTANTIATE(double)
 NBGS_INSTANTIATE(float)
