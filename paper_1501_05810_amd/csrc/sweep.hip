@@ -524,6 +524,8 @@ __global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, Sce
     const int i0 = blockIdx.x * kBlock;
     const int t = threadIdx.x, i = i0 + t;
     T rec[6];
+    bool untouched = false;  // a body no contact touched (SPARSE): only the changed velocity words are written
+    double old[6];
     if constexpr (SPARSE) {
         if (i >= b.n) return;
         if (touched[i]) {
@@ -531,10 +533,19 @@ __global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, Sce
 #pragma unroll
             for (int a = 0; a < 6; ++a) rec[a] = r[a];
         } else {
-            T r[8];
-            free_record<T>(b, i, gx, gy, gz, dt, r);
+            untouched = true;
+            old[0] = b.vx[i];
+            old[1] = b.vy[i];
+            old[2] = b.vz[i];
+            old[3] = b.wx[i];
+            old[4] = b.wy[i];
+            old[5] = b.wz[i];
+            const bool dyn = b.inv_mass[i] > 0.0;
+            rec[0] = (T)(dyn ? old[0] + dt * gx : old[0]);
+            rec[1] = (T)(dyn ? old[1] + dt * gy : old[1]);
+            rec[2] = (T)(dyn ? old[2] + dt * gz : old[2]);
 #pragma unroll
-            for (int a = 0; a < 6; ++a) rec[a] = r[a];
+            for (int a = 3; a < 6; ++a) rec[a] = (T)old[a];
         }
     } else {
         (void)touched;
@@ -552,12 +563,20 @@ __global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, Sce
     const Grid &g = st.body_scene ? st.grids[st.body_scene[i]] : g0;
     const double vx = (double)rec[0], vy = (double)rec[1], vz = (double)rec[2];
     const double ox = (double)rec[3], oy = (double)rec[4], oz = (double)rec[5];
-    b.vx[i] = vx;
-    b.vy[i] = vy;
-    b.vz[i] = vz;
-    b.wx[i] = ox;
-    b.wy[i] = oy;
-    b.wz[i] = oz;
+    if (untouched) {  // the same words as the full write, without storing an unchanged one
+        const double nv[6] = {vx, vy, vz, ox, oy, oz};
+        double *dst[6] = {b.vx, b.vy, b.vz, b.wx, b.wy, b.wz};
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            if (__double_as_longlong(nv[a]) != __double_as_longlong(old[a])) dst[a][i] = nv[a];
+    } else {
+        b.vx[i] = vx;
+        b.vy[i] = vy;
+        b.vz[i] = vz;
+        b.wx[i] = ox;
+        b.wy[i] = oy;
+        b.wz[i] = oz;
+    }
     double pos[3] = {b.x[i] + dt * vx, b.y[i] + dt * vy, b.z[i] + dt * vz};
     double qw = b.qw[i], qx = b.qx[i], qy = b.qy[i], qz = b.qz[i];
     const double dw = 0.5 * (-qx * ox - qy * oy - qz * oz);
