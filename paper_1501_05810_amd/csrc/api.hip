@@ -142,7 +142,8 @@ const void *Arena::relocate(const void *old) const {
 // precision and warm start.  Per body 567 B (detection 180 B, accumulator
 // records of both precisions 96 B, block and subdomain tables of blocks
 // holding eight bodies or more on average 165 B, cell ranges of 8 B and
-// their occupancy bits at most eight per body 82 B, and the rest); per
+// their occupancy bits at most eight per body 82 B, the touched flags of the
+// few-contact solve 1 B, and the rest); per
 // contact 1000 B (two contact tables 192 B, sweep
 // records of both precisions 168 B, colouring 36 B, learned start 156 B,
 // subdomain ends, slots and corrections 208 B, partial sums and tuning copies
