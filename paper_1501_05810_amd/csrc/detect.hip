@@ -576,7 +576,8 @@ __global__ void __launch_bounds__(kBlock) k_match_prev(ContactsView c, int64_t n
 __global__ void __launch_bounds__(kBlock) k_ids_changed(const int32_t *sdom, const int32_t *prev_sdom,
                                                         const int32_t *matched, int64_t nc, int32_t *changed) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool diff = j < nc && sdom[j] != prev_sdom[matched[j] - 1];
+    // a new pair (matched 0: no previous id) counts as a change; the host checks the new pairs as well
+    const bool diff = j < nc && (matched[j] == 0 || sdom[j] != prev_sdom[matched[j] - 1]);
     const unsigned long long m = __ballot(diff);
     __shared__ int wcount[kBlock / 64];
     if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = __popcll(m);

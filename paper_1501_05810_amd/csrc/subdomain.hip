@@ -213,8 +213,9 @@ __global__ void __launch_bounds__(kBlock) k_raw_ids_changed(const int32_t *id, c
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     bool diff = false;
     if (j < nc) {
-        const int32_t a = id[j], b = prev[matched[j] - 1];
-        diff = (a >= nblk) != (b >= nblk) || (a < nblk && a != b);
+        const int32_t m = matched[j];  // 0: a new pair (counted as a change; the host checks the new pairs too)
+        const int32_t a = id[j], b = m > 0 ? prev[m - 1] : -1;
+        diff = m == 0 || (a >= nblk) != (b >= nblk) || (a < nblk && a != b);
     }
     if (__ballot(diff) && (threadIdx.x & 63) == 0) atomicAdd(changed, 1);
 }
@@ -223,7 +224,7 @@ __global__ void __launch_bounds__(kBlock) k_raw_ids_changed(const int32_t *id, c
 __global__ void __launch_bounds__(kBlock) k_ids_from_prev(const int32_t *prev, const int32_t *matched, int64_t nc,
                                                           int32_t *id) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < nc) id[j] = prev[matched[j] - 1];
+    if (j < nc && matched[j] > 0) id[j] = prev[matched[j] - 1];  // launched only when no pair is new
 }
 
 __global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t *v, int32_t n, int32_t *out) {
