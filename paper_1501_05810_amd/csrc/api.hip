@@ -164,13 +164,19 @@ size_t scene_workspace_bytes(int64_t n, int64_t c, int64_t scenes) {
 // count (8 B), residual partial sums (16 B), scan scratch, times 1.25 for the
 // growth slack, rounded up.
 constexpr double kPerIdBytes = 80.0;
+constexpr double kRecPerBody = 8.0 * 8.0 + 3.0 * 4.0;
 
 nbgs_status scene_need_bytes(nbgs_scene_t sc, int64_t c, size_t *bytes) {
     int64_t ids = 0;
     NBGS_TRY(order_ids(sc, &ids));
     const size_t id_bytes = ids > 0 ? (size_t)(1.1 * kPerIdBytes * (double)(ids + 2)) : 0;
+    // the block-local order's record copy: per body the copy (8 values) and its three index tables, per contact
+    // its two ends as records and its at most two slots
+    const size_t rec_bytes =
+        sc->blk_edge > 0.0 ? (size_t)(1.1 * (kRecPerBody * (double)sc->b.n + 16.0 * (double)c) + 8 * Arena::kAlign) : 0;
     *bytes = scene_workspace_bytes(sc->b.n, c, sc->n_scenes) +
-             ((id_bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1));
+             ((id_bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1)) +
+             ((rec_bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1));
     return NBGS_OK;
 }
 
@@ -416,6 +422,18 @@ DevBuf<double> &vel_buf<double>(nbgs_scene_t sc) {
 template <>
 DevBuf<float> &vel_buf<float>(nbgs_scene_t sc) {
     return sc->vel32;
+}
+
+// the block-local sweeps' record copy
+template <class T>
+DevBuf<T> &bvel_buf(nbgs_scene_t sc);
+template <>
+DevBuf<double> &bvel_buf<double>(nbgs_scene_t sc) {
+    return sc->bvel64;
+}
+template <>
+DevBuf<float> &bvel_buf<float>(nbgs_scene_t sc) {
+    return sc->bvel32;
 }
 
 template <class T>
@@ -982,6 +1000,7 @@ namespace nbgs {
 nbgs_status scene_sync_small(nbgs_scene_t sc, int first, int count) { return sync_small(sc, first, count); }
 
 nbgs_status scene_gather(nbgs_scene_t sc, bool indices) {
+    if (indices) sc->rec_valid = false;  // new ends in the sweep record
     if (sc->precision_used == NBGS_FP32_SWEEP) return gather_for_sweeps<float>(sc, indices);
     return gather_for_sweeps<double>(sc, indices);
 }
@@ -1218,10 +1237,26 @@ nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
     const bool every = target > 0.0 || sc->res_history;
     sc->hist_partial = !every;
     sc->graph_pairs = 0;
+    // the sweeps run on a copy of the records in the first grid's slot order (same arithmetic, same order of the
+    // contacts: only where each record lies changes), returned to the body order after the last sweep
+    NBGS_TRY(block_records(sc));
+    T *rv = vel.p;
+    SweepView<T> xv = sw.view();
+    if (sc->rec_on) {
+        DevBuf<T> &bv = bvel_buf<T>(sc);
+        if (bv.reserve(8 * (size_t)N, 1.0) != NBGS_OK) {
+            sc->rec_on = false;
+        } else {
+            NBGS_TRY(block_records_in<T>(sc, vel.p, bv.p));
+            rv = bv.p;
+            xv.j1 = sc->j1r.p;
+            xv.j2 = sc->j2r.p;
+        }
+    }
     if (sc->p.warm_start != NBGS_WS_ZERO) {
-        NBGS_TRY(block_pass<T>(sc, 0, vel.p));
+        NBGS_TRY(block_pass<T>(sc, 0, rv));
         for (int c = 0; c < nx; ++c)
-            NBGS_TRY(launch_warm_scatter<T>(sw.view(), sc->xcol[c], sc->xcol[c + 1], N, vel.p, s));
+            NBGS_TRY(launch_warm_scatter<T>(xv, sc->xcol[c], sc->xcol[c + 1], N, rv, s));
     }
     record(sc, kSweeps);
     const bool prof = sc->profiling;
@@ -1233,9 +1268,9 @@ nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
         const int32_t k = std::min(chunk, max_sweeps - launched);
         for (int32_t it = 0; it < k; ++it) {
             if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it)], s));
-            NBGS_TRY(block_pass<T>(sc, 1, vel.p));
+            NBGS_TRY(block_pass<T>(sc, 1, rv));
             for (int c = 0; c < nx; ++c)
-                NBGS_TRY(launch_sweep_colour<T>(sw.view(), sc->xcol[c], sc->xcol[c + 1], N, vel.p, sp, tune,
+                NBGS_TRY(launch_sweep_colour<T>(xv, sc->xcol[c], sc->xcol[c + 1], N, rv, sp, tune,
                                                 sc->partials.p + 2 * sc->xpart_off[c], sc->ctrl(), s));
             if (prof) NBGS_HIP(hipEventRecord(sc->pev[2 * (launched + it) + 1], s));
             if (every)
@@ -1251,6 +1286,7 @@ nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
             chunk = std::min(chunk * 2, 64);
         }
     }
+    if (sc->rec_on) NBGS_TRY(block_records_out<T>(sc, rv, vel.p));
     return finish_solve<T>(sc, max_sweeps, target, stats, kSolveBlock);
 }
 

@@ -757,6 +757,69 @@ __device__ inline void load_rec8(const float *p, float v[8]) {
     }
 }
 
+// The sweeps' record copy of the block-local order (block_records): the first
+// grid's slots take records 0 .. s0 - 1 in slot order, every other body the
+// next records in index order.
+__global__ void __launch_bounds__(kBlock) k_rec_first(const int32_t *slots, int64_t s0, int32_t *rec_of) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s < s0) rec_of[slots[s]] = (int32_t)s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_rec_flags(const int32_t *rec_of, int32_t n, int32_t *flags) {
+    const int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (i < n) flags[i] = rec_of[i] < 0 ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_rec_rest(const int32_t *ex, int32_t n, int32_t s0, int32_t *rec_of,
+                                                     int32_t *body_of) {
+    const int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (i >= n) return;
+    int32_t r = rec_of[i];
+    if (r < 0) {
+        r = s0 + ex[i];
+        rec_of[i] = r;
+    }
+    if (r < n) body_of[r] = i;  // a permutation when no body is a slot of two of the first grid's blocks
+}
+
+__global__ void __launch_bounds__(kBlock) k_slot_rec(const int32_t *slots, int64_t ns, const int32_t *rec_of,
+                                                     int32_t *slot_rec) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s < ns) slot_rec[s] = rec_of[slots[s]];
+}
+
+__global__ void __launch_bounds__(kBlock) k_ends_rec(const int32_t *j1, const int32_t *j2, int64_t m, int32_t n,
+                                                     const int32_t *rec_of, int32_t *j1r, int32_t *j2r) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= m) return;
+    j1r[p] = rec_of[j1[p]];
+    const int32_t k = j2[p];
+    j2r[p] = k < n ? rec_of[k] : k;  // walls keep their index
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_rec_gather(const T *vel, const int32_t *body_of, int32_t n, T *out) {
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= n) return;
+    T v[8];
+    load_rec8(vel + 8 * (int64_t)body_of[r], v);
+    T *o = out + 8 * (int64_t)r;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) o[a] = v[a];
+}
+
+// Back to the body order: the velocities only (1/m and 1/I are unchanged).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_rec_scatter(const T *in, const int32_t *body_of, int32_t n, T *vel) {
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= n) return;
+    T v[8];
+    load_rec8(in + 8 * (int64_t)r, v);
+    T *o = vel + 8 * (int64_t)body_of[r];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) o[a] = v[a];
+}
+
 template <class T, int NT>
 __device__ inline void blk_stage(T *Vs, int ns, const T *vel, const int32_t *slot_body, int s0, int t) {
     for (int i0 = 0; i0 < ns; i0 += kStage * NT) {
@@ -1392,6 +1455,7 @@ static nbgs_status block_prepare_impl(nbgs_scene_t sc) {
     sc->launch_id0.assign(1, 0);
     sc->launch_n.assign(1, nblk);
     sc->launch_slots.assign(1, max_slots);
+    sc->slot_s0 = N;  // one grid: every body has a slot (static bodies last)
     sc->n_slots = soff[(size_t)nblk];
     NBGS_HIP(hipMemcpyAsync(sc->tile_off.p, toff.data(), sizeof(int64_t) * (nsub + 1), hipMemcpyHostToDevice, s));
     NBGS_HIP(hipMemcpyAsync(sc->tile_slot_off.p, soff.data(), sizeof(int32_t) * (nblk + 2), hipMemcpyHostToDevice, s));
@@ -1582,6 +1646,9 @@ static nbgs_status prepare_impl(nbgs_scene_t sc, int32_t no_slot, int values_per
         for (int32_t id0 = 0; id0 < sc->n_blk; id0 += sc->blk_grid_ids)
             group(id0, std::min(sc->blk_grid_ids, sc->n_blk - id0));
         if (sc->blk_groups > 0) group(sc->n_blk, sc->blk_groups);  // the clusters no grid holds
+        int64_t s0 = 0;
+        for (int32_t t = 0; t < std::min(sc->blk_grid_ids, sc->n_blk); ++t) s0 += scnt[(size_t)t];
+        sc->slot_s0 = s0;
     }
     // 64-bit contact offsets of the tiles
     std::vector<int64_t> toff((size_t)nsub + 1, 0);
@@ -1628,6 +1695,7 @@ nbgs_status subdomain_prepare(nbgs_scene_t sc) {
 }
 
 nbgs_status block_prepare(nbgs_scene_t sc) {
+    sc->rec_valid = false;  // new slot tables
     if (sc->blk_grids > 1) {
         if (sc->precision_used == NBGS_FP32_SWEEP) return block_grids_prepare_impl<float>(sc);
         return block_grids_prepare_impl<double>(sc);
@@ -1643,8 +1711,9 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
     SweepBuf<T> &sw = sc->precision_used == NBGS_FP32_SWEEP ? *reinterpret_cast<SweepBuf<T> *>(&sc->sw32)
                                                             : *reinterpret_cast<SweepBuf<T> *>(&sc->sw64);
     SubView<T> v;
-    v.j1 = sw.j1.p;
-    v.j2 = sw.j2.p;
+    // with the record copy (vel in the first grid's slot order) the ends and slots are its records
+    v.j1 = sc->rec_on ? sc->j1r.p : sw.j1.p;
+    v.j2 = sc->rec_on ? sc->j2r.p : sw.j2.p;
     v.ls = sw.ls.p;
     v.col = sw.col.p;
     v.nx = sw.nx.p;
@@ -1658,7 +1727,9 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
     v.pz = sw.pz.p;
     const T mu = (T)sc->p.mu, relax = (T)sc->p.relax;
     // one grid: every dynamic body of a block, sorted by block; several: the bodies the local contacts touch
-    const int32_t *slot_body = sc->blk_grids > 1 ? sc->slot_body.p : reinterpret_cast<const int32_t *>(sc->body_slots);
+    const int32_t *slot_body = sc->rec_on ? sc->slot_rec.p
+                               : sc->blk_grids > 1 ? sc->slot_body.p
+                                                   : reinterpret_cast<const int32_t *>(sc->body_slots);
     // one launch per grid (a grid's blocks share no dynamic body, the next grid sees their results), then the
     // groups of the clusters no grid holds
     for (size_t li = 0; li < sc->launch_id0.size(); ++li) {
@@ -1693,6 +1764,66 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
 
 template nbgs_status block_pass<double>(nbgs_scene_t, int, double *);
 template nbgs_status block_pass<float>(nbgs_scene_t, int, float *);
+
+nbgs_status block_records(nbgs_scene_t sc) {
+    sc->rec_on = false;
+    // few contacts keep records for the touched bodies only: nothing to gain from a copy of every record
+    if (!sc->blk_active || sc->sparse_bodies || sc->nc <= 0 || sc->n_blk <= 0) return NBGS_OK;
+    if (sc->rec_valid) {
+        sc->rec_on = true;
+        return NBGS_OK;
+    }
+    hipStream_t s = sc->s;
+    const int32_t N = sc->b.n;
+    const int64_t nc = sc->nc;
+    const bool multi = sc->blk_grids > 1;
+    const int32_t *slots = multi ? sc->slot_body.p : reinterpret_cast<const int32_t *>(sc->body_slots);
+    const int64_t nslots = multi ? sc->n_slots : (int64_t)N;  // one grid: every body, in block order
+    const int64_t s0 = std::min<int64_t>(multi ? sc->slot_s0 : (int64_t)N, nslots);
+    const int32_t *j1 = sc->precision_used == NBGS_FP32_SWEEP ? sc->sw32.j1.p : sc->sw64.j1.p;
+    const int32_t *j2 = sc->precision_used == NBGS_FP32_SWEEP ? sc->sw32.j2.p : sc->sw64.j2.p;
+    // the copy is part of the block-local order's workspace bound; without room the sweeps use the body order
+    const size_t need_tmp = exclusive_scan_tmp_bytes((int64_t)N + 1);
+    if (sc->rec_of.reserve((size_t)N + 1, 1.0) != NBGS_OK || sc->body_of.reserve((size_t)N + 1, 1.0) != NBGS_OK ||
+        sc->rec_tmp.reserve((size_t)N + 1, 1.0) != NBGS_OK ||
+        sc->slot_rec.reserve((size_t)(nslots > 0 ? nslots : 1)) != NBGS_OK ||
+        sc->j1r.reserve((size_t)nc) != NBGS_OK || sc->j2r.reserve((size_t)nc) != NBGS_OK ||
+        (need_tmp > sc->scan_tmp.cap && sc->scan_tmp.reserve(need_tmp) != NBGS_OK))
+        return NBGS_OK;
+    k_fill<<<grid_for(N), kBlock, 0, s>>>(sc->rec_of.p, N, -1);
+    if (s0 > 0) k_rec_first<<<grid_for(s0), kBlock, 0, s>>>(slots, s0, sc->rec_of.p);
+    k_rec_flags<<<grid_for(N), kBlock, 0, s>>>(sc->rec_of.p, N, sc->body_of.p);
+    NBGS_HIP(hipGetLastError());
+    NBGS_TRY(exclusive_scan_i32(sc->body_of.p, sc->rec_tmp.p, N, nullptr, sc->scan_tmp.p, sc->scan_tmp.cap, s));
+    k_rec_rest<<<grid_for(N), kBlock, 0, s>>>(sc->rec_tmp.p, N, (int32_t)s0, sc->rec_of.p, sc->body_of.p);
+    if (nslots > 0) k_slot_rec<<<grid_for(nslots), kBlock, 0, s>>>(slots, nslots, sc->rec_of.p, sc->slot_rec.p);
+    k_ends_rec<<<grid_for(nc), kBlock, 0, s>>>(j1, j2, nc, N, sc->rec_of.p, sc->j1r.p, sc->j2r.p);
+    NBGS_HIP(hipGetLastError());
+    sc->rec_valid = true;
+    sc->rec_on = true;
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status block_records_in(nbgs_scene_t sc, const T *vel, T *bvel) {
+    const int32_t N = sc->b.n;
+    k_rec_gather<T><<<grid_for(N), kBlock, 0, sc->s>>>(vel, sc->body_of.p, N, bvel);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template <class T>
+nbgs_status block_records_out(nbgs_scene_t sc, const T *bvel, T *vel) {
+    const int32_t N = sc->b.n;
+    k_rec_scatter<T><<<grid_for(N), kBlock, 0, sc->s>>>(bvel, sc->body_of.p, N, vel);
+    NBGS_HIP(hipGetLastError());
+    return NBGS_OK;
+}
+
+template nbgs_status block_records_in<double>(nbgs_scene_t, const double *, double *);
+template nbgs_status block_records_in<float>(nbgs_scene_t, const float *, float *);
+template nbgs_status block_records_out<double>(nbgs_scene_t, const double *, double *);
+template nbgs_status block_records_out<float>(nbgs_scene_t, const float *, float *);
 
 template <class T>
 nbgs_status subdomain_pass(nbgs_scene_t sc, int mode, T *vel, T *corr) {
