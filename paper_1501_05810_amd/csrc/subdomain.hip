@@ -286,6 +286,38 @@ __global__ void __launch_bounds__(kBlock) k_end_tiles(const uint32_t *vals, int6
     if (i < n) keys[i] = (uint32_t)ssd[vals[i] >> 1];
 }
 
+// The same key in the block-local order over several grids, with the slots of
+// a first-grid block sub-ordered by the cell of the body's centre among the
+// grids^3 cells the shifted grids cut the block into (sb bits): the sweeps'
+// records follow the first grid's slot order, and a later grid's block then
+// reads its records in a few short runs.  Which slot a body takes inside its
+// block changes nothing else.
+__global__ void __launch_bounds__(kBlock) k_end_tiles_sub(const uint32_t *vals, int64_t n, const int32_t *ssd,
+                                                          const int32_t *sj1, const int32_t *sj2, BodiesView b,
+                                                          Blocks bl, int32_t grids, int32_t grid_ids,
+                                                          int32_t no_slot, int32_t sb, uint32_t *keys) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t e = vals[i];
+    const int32_t sd = ssd[e >> 1];
+    uint32_t sub = 0;
+    if (sd >= 0 && sd < grid_ids) {
+        const int32_t k = end_body(sj1, sj2, b.n, b.inv_mass, e, ssd, no_slot);
+        if (k < b.n) {
+            const double x[3] = {b.x[k], b.y[k], b.z[k]};
+            uint32_t w = 1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double u = (x[a] - bl.lo[a]) / bl.e[a];
+                const int32_t q = (int32_t)((u - floor(u)) * (double)grids);
+                sub += w * (uint32_t)max(0, min(q, grids - 1));
+                w *= (uint32_t)grids;
+            }
+        }
+    }
+    keys[i] = ((uint32_t)sd << sb) | sub;
+}
+
 // First end of every (subdomain, dynamic body) group, ends sorted by (subdomain, body).
 __global__ void __launch_bounds__(kBlock) k_slot_flags(const uint32_t *vals, int64_t n, const int32_t *sj1,
                                                        const int32_t *sj2, const int32_t *ssd, int32_t nb,
@@ -1579,10 +1611,24 @@ static nbgs_status prepare_impl(nbgs_scene_t sc, int32_t no_slot, int values_per
     uint32_t *keys = alt ? sc->ekeys2.p : sc->ekeys.p;
     uint32_t *vals_o = alt ? sc->evals.p : sc->evals2.p;
     uint32_t *keys_o = alt ? sc->ekeys.p : sc->ekeys2.p;
-    k_end_tiles<<<grid_for(ne), kBlock, 0, s>>>(vals, ne, ssd, keys);
+    // block-local order over several grids: the first grid's slots sub-ordered by cell (k_end_tiles_sub)
+    int32_t sb = 0;
+    if (!body_lists && sc->blk_grids > 1 && sc->blk_grid_ids > 0) {
+        sb = 3 * bits_for(sc->blk_grids);
+        if (bits_for(nsub) + sb > 32) sb = 0;
+    }
+    if (sb > 0) {
+        Blocks bl;
+        int64_t nblocks = 1;
+        NBGS_TRY(make_blocks(sc, sc->blk_edge, bl, nblocks));
+        k_end_tiles_sub<<<grid_for(ne), kBlock, 0, s>>>(vals, ne, ssd, sj1, sj2, sc->b, bl, sc->blk_grids,
+                                                        sc->blk_grid_ids, no_slot, sb, keys);
+    } else {
+        k_end_tiles<<<grid_for(ne), kBlock, 0, s>>>(vals, ne, ssd, keys);
+    }
     NBGS_HIP(hipGetLastError());
     bool alt2 = false;
-    NBGS_TRY(radix_sort_pairs(keys, vals, keys_o, vals_o, ne, std::max(1, bits_for(nsub)), sc->radix_hist.p,
+    NBGS_TRY(radix_sort_pairs(keys, vals, keys_o, vals_o, ne, std::max(1, bits_for(nsub) + sb), sc->radix_hist.p,
                               sc->scan_tmp.p, sc->scan_tmp.cap, &alt2, s));
     const uint32_t *svals = alt2 ? vals_o : vals;
     // slots
