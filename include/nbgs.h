@@ -144,8 +144,8 @@ const char *nbgs_last_error(void);
  * and warm start (an upper bound: per body 567 B, per contact 1,000 B, plus a
  * cell table of 2^16 cells, 16 MiB, and ten per cent), a multiple of 256 (all
  * of it usable from a 256-byte aligned base).  The block-local order and the
- * subdomain solver add 88 B per id, the block-local order also its sweeps'
- * record copy, 76 B per body and 16 B per contact, plus ten per cent
+ * subdomain solver add 88 B per id, the block-local order also the tables
+ * of its record order, 12 B per body and 16 B per contact, plus ten per cent
  * (nbgs_scene_workspace_query).  params
  * [host] may be NULL (checked when given).  *bytes [host].  Pure host
  * computation: no device is touched.  Errors: INVALID_ARG. */

@@ -164,14 +164,14 @@ size_t scene_workspace_bytes(int64_t n, int64_t c, int64_t scenes) {
 // count (8 B), residual partial sums (16 B), scan scratch, times 1.25 for the
 // growth slack, rounded up.
 constexpr double kPerIdBytes = 80.0;
-constexpr double kRecPerBody = 8.0 * 8.0 + 3.0 * 4.0;
+constexpr double kRecPerBody = 3.0 * 4.0;
 
 nbgs_status scene_need_bytes(nbgs_scene_t sc, int64_t c, size_t *bytes) {
     int64_t ids = 0;
     NBGS_TRY(order_ids(sc, &ids));
     const size_t id_bytes = ids > 0 ? (size_t)(1.1 * kPerIdBytes * (double)(ids + 2)) : 0;
-    // the block-local order's record copy: per body the copy (8 values) and its three index tables, per contact
-    // its two ends as records and its at most two slots
+    // the block-local order's record layout: per body its three index tables, per contact its two ends as records
+    // and its at most two slots
     const size_t rec_bytes =
         sc->blk_edge > 0.0 ? (size_t)(1.1 * (kRecPerBody * (double)sc->b.n + 16.0 * (double)c) + 8 * Arena::kAlign) : 0;
     *bytes = scene_workspace_bytes(sc->b.n, c, sc->n_scenes) +
@@ -424,17 +424,8 @@ DevBuf<float> &vel_buf<float>(nbgs_scene_t sc) {
     return sc->vel32;
 }
 
-// the block-local sweeps' record copy
-template <class T>
-DevBuf<T> &bvel_buf(nbgs_scene_t sc);
-template <>
-DevBuf<double> &bvel_buf<double>(nbgs_scene_t sc) {
-    return sc->bvel64;
-}
-template <>
-DevBuf<float> &bvel_buf<float>(nbgs_scene_t sc) {
-    return sc->bvel32;
-}
+// body -> solver record while the records are in the block-local sweeps' order, else null (body order)
+const int32_t *rec_map(nbgs_scene_t sc) { return sc->rec_on ? sc->rec_of.p : nullptr; }
 
 template <class T>
 DevBuf<T> &corr_buf(nbgs_scene_t sc);
@@ -936,11 +927,12 @@ nbgs_status accumulate_profile(nbgs_scene_t sc, int32_t sweeps) {
     return NBGS_OK;
 }
 
-// The solver's records at the start of a solve: every body's, or with few contacts the touched bodies' only.
+// The solver's records at the start of a solve: every body's, or with few contacts the touched bodies' only; in
+// the block-local sweeps' order while rec_on.
 template <class T>
 nbgs_status init_records(nbgs_scene_t sc, T *vel) {
     if (sc->sparse_bodies) return launch_init_touched<T>(sc->b, sc->p.gravity, sc->p.dt, sc->touched.p, vel, sc->s);
-    return launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel, sc->s);
+    return launch_init_bodies<T>(sc->b, sc->p.gravity, sc->p.dt, vel, rec_map(sc), sc->s);
 }
 
 // Jacobi residual of the previous-step and of the learned initial impulses;
@@ -1237,21 +1229,12 @@ nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
     const bool every = target > 0.0 || sc->res_history;
     sc->hist_partial = !every;
     sc->graph_pairs = 0;
-    // the sweeps run on a copy of the records in the first grid's slot order (same arithmetic, same order of the
-    // contacts: only where each record lies changes), returned to the body order after the last sweep
-    NBGS_TRY(block_records(sc));
+    // records in the first grid's slot order (rec_on, set before they were written): the contacts' ends are records
     T *rv = vel.p;
     SweepView<T> xv = sw.view();
     if (sc->rec_on) {
-        DevBuf<T> &bv = bvel_buf<T>(sc);
-        if (bv.reserve(8 * (size_t)N, 1.0) != NBGS_OK) {
-            sc->rec_on = false;
-        } else {
-            NBGS_TRY(block_records_in<T>(sc, vel.p, bv.p));
-            rv = bv.p;
-            xv.j1 = sc->j1r.p;
-            xv.j2 = sc->j2r.p;
-        }
+        xv.j1 = sc->j1r.p;
+        xv.j2 = sc->j2r.p;
     }
     if (sc->p.warm_start != NBGS_WS_ZERO) {
         NBGS_TRY(block_pass<T>(sc, 0, rv));
@@ -1286,7 +1269,6 @@ nbgs_status blk_solve(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_s
             chunk = std::min(chunk * 2, 64);
         }
     }
-    if (sc->rec_on) NBGS_TRY(block_records_out<T>(sc, rv, vel.p));
     return finish_solve<T>(sc, max_sweeps, target, stats, kSolveBlock);
 }
 
@@ -1299,6 +1281,7 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
     NBGS_TRY(vel.reserve(8 * (size_t)N));
     NBGS_TRY(sc->res_hist.reserve((size_t)max_sweeps));
     record(sc, kInit);
+    sc->rec_on = false;  // body order until the block-local order's tables are in place (below)
     sc->winfo = nbgs_warm_info{-1, 0.0, 0.0};
     // few contacts on many bodies: records only for the bodies they touch (the sweeps read no other; the
     // integration and the export form the rest from the state); a small scene keeps the two launches fewer
@@ -1309,6 +1292,10 @@ nbgs_status solve_impl(nbgs_scene_t sc, int32_t max_sweeps, double target, nbgs_
         NBGS_TRY(launch_mark_touched(cb.j1.p, cb.j2.p, sc->nc, N, sc->touched.p, s));
     }
     if (sc->p.warm_start == NBGS_WS_LEARNED && sc->have_learned) NBGS_TRY(judge_warm_start<T>(sc));
+    // the block-local sweeps read and write each first-grid block's records as one contiguous range: the records
+    // of this solve, its integration and its export are laid out in that order (same arithmetic, same order of
+    // the contacts; only where each record lies changes)
+    if (sc->blk_active && !sc->sub_active) NBGS_TRY(block_records(sc));
     NBGS_TRY(init_records<T>(sc, vel.p));
     if (sc->sub_active) return sub_solve<T>(sc, max_sweeps, target, stats);
     if (sc->blk_active) return blk_solve<T>(sc, max_sweeps, target, stats);
@@ -1393,7 +1380,7 @@ template <class T>
 nbgs_status integrate_impl(nbgs_scene_t sc) {
     record(sc, kIntegrate);
     NBGS_TRY(launch_integrate<T>(sc->b, sc->grid, sc->table(), sc->p.dt, vel_buf<T>(sc).p,
-                                 sc->sparse_bodies ? sc->touched.p : nullptr, sc->p.gravity, sc->s));
+                                 sc->sparse_bodies ? sc->touched.p : nullptr, sc->p.gravity, rec_map(sc), sc->s));
     record(sc, kNumPhases);
     sc->table_in_cur = true;
     sc->n_prev = sc->nc;
@@ -1870,7 +1857,7 @@ nbgs_status nbgs_get_accumulators(nbgs_scene_t sc, double *v, double *w) {
         }
         return launch_export_accumulators<float>(sc->vel32.p, sc->b.n, v, w, sc->b,
                                                  sc->sparse_bodies ? sc->touched.p : nullptr, sc->state == 2,
-                                                 sc->p.gravity, sc->p.dt, sc->s);
+                                                 sc->p.gravity, sc->p.dt, rec_map(sc), sc->s);
     }
     if (!sc->vel64.p) {
         set_error("no solve yet");
@@ -1878,7 +1865,7 @@ nbgs_status nbgs_get_accumulators(nbgs_scene_t sc, double *v, double *w) {
     }
     return launch_export_accumulators<double>(sc->vel64.p, sc->b.n, v, w, sc->b,
                                               sc->sparse_bodies ? sc->touched.p : nullptr, sc->state == 2,
-                                              sc->p.gravity, sc->p.dt, sc->s);
+                                              sc->p.gravity, sc->p.dt, rec_map(sc), sc->s);
 }
 
 nbgs_status nbgs_get_residuals(nbgs_scene_t sc, int32_t cap, double *hist, int32_t *n_out) {

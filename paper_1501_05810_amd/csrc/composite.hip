@@ -1282,7 +1282,8 @@ nbgs_status comp_integrate(nbgs_composite_t sc) {
     }
     record(sc, kPhIntegrate);
     const SceneTable tab{};
-    NBGS_TRY(launch_integrate<double>(sc->bv, sc->grid, tab, sc->p.dt, sc->vel.p, nullptr, sc->p.gravity, sc->s));
+    NBGS_TRY(launch_integrate<double>(sc->bv, sc->grid, tab, sc->p.dt, sc->vel.p, nullptr, sc->p.gravity, nullptr,
+                                      sc->s));
     record(sc, kPhEnd);
     sc->table_in_cur = true;
     sc->n_prev = sc->nc;
@@ -1568,7 +1569,7 @@ nbgs_status nbgs_composite_get_accumulators(nbgs_composite_t sc, double *v, doub
         return NBGS_ERR_INVALID_ARG;
     }
     NBGS_TRY(launch_export_accumulators<double>(sc->vel.p, sc->b.n, v, w, sc->bv, nullptr, false, sc->p.gravity,
-                                                sc->p.dt, sc->s));
+                                                sc->p.dt, nullptr, sc->s));
     NBGS_HIP(hipStreamSynchronize(sc->s));
     return NBGS_OK;
 }

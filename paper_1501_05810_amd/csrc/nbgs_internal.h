@@ -307,8 +307,11 @@ nbgs_status launch_gather_sweep(const ContactsView &c, const uint32_t *perm, con
                                 hipStream_t s);
 
 // sweep.hip
+// rec (null: body order): body i's solver record is record rec[i] of vel (the block-local sweeps' order); the
+// integration and the export take the same map.
 template <class T>
-nbgs_status launch_init_bodies(const BodiesView &b, const double g[3], double dt, T *vel, hipStream_t s);
+nbgs_status launch_init_bodies(const BodiesView &b, const double g[3], double dt, T *vel, const int32_t *rec,
+                               hipStream_t s);
 template <class T>
 nbgs_status launch_warm_scatter(SweepView<T> sv, int64_t begin, int64_t end, int32_t nb, T *vel, hipStream_t s);
 // Contacts per tile (one partial residual sum each).
@@ -330,7 +333,7 @@ nbgs_status launch_residual(const double *partials, int32_t n_partials, double t
                             double *hist, hipStream_t s, int32_t at = -1);
 template <class T>
 nbgs_status launch_integrate(const BodiesView &b, const Grid &g, const SceneTable &st, double dt, const T *vel,
-                             const uint8_t *touched, const double grav[3], hipStream_t s);
+                             const uint8_t *touched, const double grav[3], const int32_t *rec, hipStream_t s);
 // Few contacts: touched[i] = 1 for every body a contact of the step touches (launch_mark_touched), the solver's
 // records written for those bodies only (launch_init_touched); the integration and the export take every other
 // body's record from its state (touched passed to them; NULL: every record is read).
@@ -344,7 +347,7 @@ nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hi
 template <class T>
 nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, const BodiesView &b,
                                        const uint8_t *touched, bool pending, const double g[3], double dt,
-                                       hipStream_t s);
+                                       const int32_t *rec, hipStream_t s);
 
 // warmstart.hip
 struct FeatureScales {

@@ -278,14 +278,13 @@ struct nbgs_scene_s {
     std::vector<int64_t> xpart_off;  // first partial of every cross colour, after the n_blk block partials
     int64_t blk_dyn_local = 0;       // slots of the local part (each read and written once per sweep)
     int64_t blk_n_local = 0;         // contacts of the local part
-    // the sweeps' copy of the solver records in the first grid's slot order (record s: slot s of the first grid's
-    // blocks, then every other body in index order), so that a block of the first grid reads and writes one
-    // contiguous range: rec_of (body -> record), body_of (record -> body), the slot table and the sweep record's
-    // ends as records; rebuilt with the block set-up or the sweep record's ends (rec_valid), used while rec_on
+    // the solver records in the first grid's slot order (record s: slot s of the first grid's blocks, then every
+    // other body in index order), so that a block of the first grid reads and writes one contiguous range: rec_of
+    // (body -> record), body_of (record -> body), the slot table and the sweep record's ends as records; rebuilt
+    // with the block set-up or the sweep record's ends (rec_valid); rec_on from a solve's initialisation of the
+    // records to the next one (its sweeps, integration and export use the order)
     int64_t slot_s0 = 0;  // slots of the first grid's blocks
     DevBuf<int32_t> rec_of, body_of, rec_tmp, slot_rec, j1r, j2r;
-    DevBuf<double> bvel64;
-    DevBuf<float> bvel32;
     bool rec_valid = false, rec_on = false;
     DevBuf<int64_t> xcol_d;
     DevBuf<int32_t> xncol_d;
@@ -352,14 +351,9 @@ nbgs_status block_assign(nbgs_scene_t sc, int32_t *changed, bool maybe_reuse);
 nbgs_status block_prepare(nbgs_scene_t sc);
 template <class T>
 nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel);
-// The sweeps' record copy of the block-local order: builds its tables when the order changed and, with room in the
-// workspace, sets rec_on (off: the sweeps use the records in body order, with the same results); records_in gathers
-// the records into the copy, records_out returns the velocities to the body-ordered records.
+// The block-local sweeps' record order: builds its tables when the order changed and, with room in the workspace,
+// sets rec_on (off: the records stay in body order, with the same results).
 nbgs_status block_records(nbgs_scene_t sc);
-template <class T>
-nbgs_status block_records_in(nbgs_scene_t sc, const T *vel, T *bvel);
-template <class T>
-nbgs_status block_records_out(nbgs_scene_t sc, const T *bvel, T *vel);
 template <class T>
 nbgs_status scene_sweep_loop(nbgs_scene_t sc, int32_t max_sweeps, double target, const SweepTune &tune);
 

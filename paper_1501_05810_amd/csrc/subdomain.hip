@@ -789,9 +789,9 @@ __device__ inline void load_rec8(const float *p, float v[8]) {
     }
 }
 
-// The sweeps' record copy of the block-local order (block_records): the first
-// grid's slots take records 0 .. s0 - 1 in slot order, every other body the
-// next records in index order.
+// The solver records in the block-local sweeps' order (block_records): the
+// first grid's slots take records 0 .. s0 - 1 in slot order, every other body
+// the next records in index order.
 __global__ void __launch_bounds__(kBlock) k_rec_first(const int32_t *slots, int64_t s0, int32_t *rec_of) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s < s0) rec_of[slots[s]] = (int32_t)s;
@@ -827,29 +827,6 @@ __global__ void __launch_bounds__(kBlock) k_ends_rec(const int32_t *j1, const in
     j1r[p] = rec_of[j1[p]];
     const int32_t k = j2[p];
     j2r[p] = k < n ? rec_of[k] : k;  // walls keep their index
-}
-
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_rec_gather(const T *vel, const int32_t *body_of, int32_t n, T *out) {
-    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (r >= n) return;
-    T v[8];
-    load_rec8(vel + 8 * (int64_t)body_of[r], v);
-    T *o = out + 8 * (int64_t)r;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) o[a] = v[a];
-}
-
-// Back to the body order: the velocities only (1/m and 1/I are unchanged).
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_rec_scatter(const T *in, const int32_t *body_of, int32_t n, T *vel) {
-    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (r >= n) return;
-    T v[8];
-    load_rec8(in + 8 * (int64_t)r, v);
-    T *o = vel + 8 * (int64_t)body_of[r];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) o[a] = v[a];
 }
 
 template <class T, int NT>
@@ -1757,7 +1734,7 @@ nbgs_status block_pass(nbgs_scene_t sc, int mode, T *vel) {
     SweepBuf<T> &sw = sc->precision_used == NBGS_FP32_SWEEP ? *reinterpret_cast<SweepBuf<T> *>(&sc->sw32)
                                                             : *reinterpret_cast<SweepBuf<T> *>(&sc->sw64);
     SubView<T> v;
-    // with the record copy (vel in the first grid's slot order) the ends and slots are its records
+    // with the records in the first grid's slot order (rec_on) the ends and slots are record indices
     v.j1 = sc->rec_on ? sc->j1r.p : sw.j1.p;
     v.j2 = sc->rec_on ? sc->j2r.p : sw.j2.p;
     v.ls = sw.ls.p;
@@ -1828,7 +1805,7 @@ nbgs_status block_records(nbgs_scene_t sc) {
     const int64_t s0 = std::min<int64_t>(multi ? sc->slot_s0 : (int64_t)N, nslots);
     const int32_t *j1 = sc->precision_used == NBGS_FP32_SWEEP ? sc->sw32.j1.p : sc->sw64.j1.p;
     const int32_t *j2 = sc->precision_used == NBGS_FP32_SWEEP ? sc->sw32.j2.p : sc->sw64.j2.p;
-    // the copy is part of the block-local order's workspace bound; without room the sweeps use the body order
+    // the tables are part of the block-local order's workspace bound; without room the records stay in body order
     const size_t need_tmp = exclusive_scan_tmp_bytes((int64_t)N + 1);
     if (sc->rec_of.reserve((size_t)N + 1, 1.0) != NBGS_OK || sc->body_of.reserve((size_t)N + 1, 1.0) != NBGS_OK ||
         sc->rec_tmp.reserve((size_t)N + 1, 1.0) != NBGS_OK ||
@@ -1849,27 +1826,6 @@ nbgs_status block_records(nbgs_scene_t sc) {
     sc->rec_on = true;
     return NBGS_OK;
 }
-
-template <class T>
-nbgs_status block_records_in(nbgs_scene_t sc, const T *vel, T *bvel) {
-    const int32_t N = sc->b.n;
-    k_rec_gather<T><<<grid_for(N), kBlock, 0, sc->s>>>(vel, sc->body_of.p, N, bvel);
-    NBGS_HIP(hipGetLastError());
-    return NBGS_OK;
-}
-
-template <class T>
-nbgs_status block_records_out(nbgs_scene_t sc, const T *bvel, T *vel) {
-    const int32_t N = sc->b.n;
-    k_rec_scatter<T><<<grid_for(N), kBlock, 0, sc->s>>>(bvel, sc->body_of.p, N, vel);
-    NBGS_HIP(hipGetLastError());
-    return NBGS_OK;
-}
-
-template nbgs_status block_records_in<double>(nbgs_scene_t, const double *, double *);
-template nbgs_status block_records_in<float>(nbgs_scene_t, const float *, float *);
-template nbgs_status block_records_out<double>(nbgs_scene_t, const double *, double *);
-template nbgs_status block_records_out<float>(nbgs_scene_t, const float *, float *);
 
 template <class T>
 nbgs_status subdomain_pass(nbgs_scene_t sc, int mode, T *vel, T *corr) {

@@ -83,15 +83,42 @@ __device__ inline void store_vel(float *vel, int b, const Rec<float> &r) {
 template <class T>
 constexpr int kStageRow = kBlock + 32 / (int)sizeof(T);
 
+// The solver's record of a body that no contact touches: what k_init_bodies
+// writes, and what the sweeps leave unchanged.
+template <class T>
+__device__ inline void free_record(const BodiesView &b, int64_t i, double gx, double gy, double gz, double dt,
+                                   T r[8]) {
+    const double im = b.inv_mass[i];
+    const bool dyn = im > 0.0;
+    r[0] = (T)(dyn ? b.vx[i] + dt * gx : b.vx[i]);
+    r[1] = (T)(dyn ? b.vy[i] + dt * gy : b.vy[i]);
+    r[2] = (T)(dyn ? b.vz[i] + dt * gz : b.vz[i]);
+    r[3] = (T)b.wx[i];
+    r[4] = (T)b.wy[i];
+    r[5] = (T)b.wz[i];
+    r[6] = (T)im;
+    r[7] = (T)b.inv_inertia[i];
+}
+
+// rec (or null: body order): the record of body i is record rec[i] (the block-local sweeps' order).
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_init_bodies(BodiesView b, double gx, double gy, double gz, double dt,
-                                                        T *vel) {
+                                                        T *vel, const int32_t *rec) {
     // the workgroup's records are staged in LDS (value-major) and written as one contiguous run, so that
     // neighbouring lanes store neighbouring words
     constexpr int S = kStageRow<T>;
     __shared__ T stage[8 * S];
     const int i0 = blockIdx.x * kBlock;
     const int t = threadIdx.x, i = i0 + t;
+    if (rec) {  // each record whole at its own place
+        if (i >= b.n) return;
+        T r[8];
+        free_record<T>(b, i, gx, gy, gz, dt, r);
+        T *out = vel + 8 * (int64_t)rec[i];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) out[a] = r[a];
+        return;
+    }
     if (i < b.n) {
         const double im = b.inv_mass[i];
         const bool dyn = im > 0.0;
@@ -110,22 +137,6 @@ __global__ void __launch_bounds__(kBlock) k_init_bodies(BodiesView b, double gx,
     for (int q = t; q < 8 * nvalid; q += kBlock) out[q] = stage[(q & 7) * S + (q >> 3)];
 }
 
-// The solver's record of a body that no contact touches: what k_init_bodies
-// writes, and what the sweeps leave unchanged.
-template <class T>
-__device__ inline void free_record(const BodiesView &b, int64_t i, double gx, double gy, double gz, double dt,
-                                   T r[8]) {
-    const double im = b.inv_mass[i];
-    const bool dyn = im > 0.0;
-    r[0] = (T)(dyn ? b.vx[i] + dt * gx : b.vx[i]);
-    r[1] = (T)(dyn ? b.vy[i] + dt * gy : b.vy[i]);
-    r[2] = (T)(dyn ? b.vz[i] + dt * gz : b.vz[i]);
-    r[3] = (T)b.wx[i];
-    r[4] = (T)b.wy[i];
-    r[5] = (T)b.wz[i];
-    r[6] = (T)im;
-    r[7] = (T)b.inv_inertia[i];
-}
 
 // Bodies that some contact of the step touches (either end, walls excepted).
 __global__ void __launch_bounds__(kBlock) k_mark_touched(const int32_t *j1, const int32_t *j2, int64_t nc, int32_t nb,
@@ -517,7 +528,8 @@ __global__ void __launch_bounds__(kResBlock) k_residual(const double *partials, 
 // other body takes the record k_init_bodies would have written.
 template <class T, bool SPARSE>
 __global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, SceneTable st, double dt, const T *vel,
-                                                      const uint8_t *touched, double gx, double gy, double gz) {
+                                                      const uint8_t *touched, double gx, double gy, double gz,
+                                                      const int32_t *recmap) {
     // the workgroup's records are read as one contiguous run into LDS (neighbouring lanes load neighbouring words)
     constexpr int S = kStageRow<T>;
     __shared__ T stage[SPARSE ? 1 : 8 * S];
@@ -552,13 +564,20 @@ __global__ void __launch_bounds__(kBlock) k_integrate(BodiesView b, Grid g0, Sce
         (void)gx;
         (void)gy;
         (void)gz;
-        const int nvalid = b.n - i0 < kBlock ? b.n - i0 : kBlock;
-        const T *in = vel + 8 * (int64_t)i0;
-        for (int q = t; q < 8 * nvalid; q += kBlock) stage[(q & 7) * S + (q >> 3)] = in[q];
-        __syncthreads();
-        if (i >= b.n) return;
+        if (recmap) {  // records in the block-local sweeps' order: each read whole from its own place
+            if (i >= b.n) return;
+            const T *r = vel + 8 * (int64_t)recmap[i];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) rec[a] = stage[a * S + t];
+            for (int a = 0; a < 6; ++a) rec[a] = r[a];
+        } else {
+            const int nvalid = b.n - i0 < kBlock ? b.n - i0 : kBlock;
+            const T *in = vel + 8 * (int64_t)i0;
+            for (int q = t; q < 8 * nvalid; q += kBlock) stage[(q & 7) * S + (q >> 3)] = in[q];
+            __syncthreads();
+            if (i >= b.n) return;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) rec[a] = stage[a * S + t];
+        }
     }
     const Grid &g = st.body_scene ? st.grids[st.body_scene[i]] : g0;
     const double vx = (double)rec[0], vy = (double)rec[1], vz = (double)rec[2];
@@ -618,11 +637,11 @@ __global__ void __launch_bounds__(kBlock) k_save_impulses(SweepView<T> sv, int64
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_export(const T *vel, int32_t nb, double *v, double *w, BodiesView b,
                                                    const uint8_t *touched, int pending, double gx, double gy,
-                                                   double gz, double dt) {
+                                                   double gz, double dt, const int32_t *rec) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= nb) return;
     T fr[8];
-    const T *r = vel + 8 * (int64_t)i;
+    const T *r = vel + 8 * (int64_t)(rec ? rec[i] : i);
     if (touched && !touched[i]) {
         if (pending) {
             free_record<T>(b, i, gx, gy, gz, dt, fr);
@@ -647,8 +666,9 @@ __global__ void __launch_bounds__(kBlock) k_export(const T *vel, int32_t nb, dou
 }  // namespace
 
 template <class T>
-nbgs_status launch_init_bodies(const BodiesView &b, const double g[3], double dt, T *vel, hipStream_t s) {
-    k_init_bodies<T><<<grid_for(b.n), kBlock, 0, s>>>(b, g[0], g[1], g[2], dt, vel);
+nbgs_status launch_init_bodies(const BodiesView &b, const double g[3], double dt, T *vel, const int32_t *rec,
+                               hipStream_t s) {
+    k_init_bodies<T><<<grid_for(b.n), kBlock, 0, s>>>(b, g[0], g[1], g[2], dt, vel, rec);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -871,11 +891,12 @@ nbgs_status launch_residual(const double *partials, int32_t n_partials, double t
 
 template <class T>
 nbgs_status launch_integrate(const BodiesView &b, const Grid &g, const SceneTable &st, double dt, const T *vel,
-                             const uint8_t *touched, const double grav[3], hipStream_t s) {
+                             const uint8_t *touched, const double grav[3], const int32_t *rec, hipStream_t s) {
     if (touched)
-        k_integrate<T, true><<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, dt, vel, touched, grav[0], grav[1], grav[2]);
+        k_integrate<T, true><<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, dt, vel, touched, grav[0], grav[1], grav[2],
+                                                               nullptr);
     else
-        k_integrate<T, false><<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, dt, vel, nullptr, 0.0, 0.0, 0.0);
+        k_integrate<T, false><<<grid_for(b.n), kBlock, 0, s>>>(b, g, st, dt, vel, nullptr, 0.0, 0.0, 0.0, rec);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
@@ -910,19 +931,21 @@ nbgs_status launch_save_impulses(SweepView<T> sv, int64_t nc, ContactsView c, hi
 template <class T>
 nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, double *w, const BodiesView &b,
                                        const uint8_t *touched, bool pending, const double g[3], double dt,
-                                       hipStream_t s) {
-    k_export<T><<<grid_for(nb), kBlock, 0, s>>>(vel, nb, v, w, b, touched, pending ? 1 : 0, g[0], g[1], g[2], dt);
+                                       const int32_t *rec, hipStream_t s) {
+    k_export<T><<<grid_for(nb), kBlock, 0, s>>>(vel, nb, v, w, b, touched, pending ? 1 : 0, g[0], g[1], g[2], dt,
+                                                rec);
     NBGS_HIP(hipGetLastError());
     return NBGS_OK;
 }
 
 #define NBGS_INSTANTIATE(T)                                                                                       \
-    template nbgs_status launch_init_bodies<T>(const BodiesView &, const double[3], double, T *, hipStream_t);    \
+    template nbgs_status launch_init_bodies<T>(const BodiesView &, const double[3], double, T *, const int32_t *, \
+                                               hipStream_t);                                                      \
     template nbgs_status launch_warm_scatter<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, hipStream_t);      \
     template nbgs_status launch_sweep_colour<T>(SweepView<T>, int64_t, int64_t, int32_t, T *, SweepParams,       \
                                                 const SweepTune &, double *, const int32_t *, hipStream_t);       \
     template nbgs_status launch_integrate<T>(const BodiesView &, const Grid &, const SceneTable &, double, const T *, \
-                                             const uint8_t *, const double[3], hipStream_t);                     \
+                                             const uint8_t *, const double[3], const int32_t *, hipStream_t);    \
     template nbgs_status launch_init_touched<T>(const BodiesView &, const double[3], double, const uint8_t *, T *, \
                                                 hipStream_t);                                                     \
     template unsigned sweep_graph_grid<T>(const SweepTune &);                                                     \
@@ -931,7 +954,8 @@ nbgs_status launch_export_accumulators(const T *vel, int32_t nb, double *v, doub
                                                     hipStream_t);                                                 \
     template nbgs_status launch_save_impulses<T>(SweepView<T>, int64_t, ContactsView, hipStream_t);              \
     template nbgs_status launch_export_accumulators<T>(const T *, int32_t, double *, double *, const BodiesView &, \
-                                                       const uint8_t *, bool, const double[3], double, hipStream_t);
+                                                       const uint8_t *, bool, const double[3], double,            \
+                                                       const int32_t *, hipStream_t);
 
 NBGS_INSTANTIATE(double)
 NBGS_INSTANTIATE(float)

@@ -136,7 +136,7 @@ def test_collected_training_pairs():
 
 
 def test_block_order_tables_count_towards_the_workspace():
-    """The block-local order adds its per-id tables (88 B per id) and its sweeps' record copy (76 B per body, 16 B
+    """The block-local order adds its per-id tables (88 B per id) and its record order's tables (12 B per body, 16 B
     per contact) to the scene's workspace figure; a scene sized for the classic order grows into it at its first
     detection in that order and then steps as usual."""
     nb = _nb()
@@ -148,7 +148,7 @@ def test_block_order_tables_count_towards_the_workspace():
     nb_axis = int(np.floor(9.0 / 0.3))  # blocks per (periodic) axis
     ids = 4 * nb_axis ** 3 + 1
     q4 = nb.nbgs_scene_workspace_query(g.handle, 1000)
-    assert q4 - q0 == pytest.approx(88 * (ids + 2) + 1.1 * (76 * g.n + 16 * 1000) + 8 * 256, abs=768)
+    assert q4 - q0 == pytest.approx(88 * (ids + 2) + 1.1 * (12 * g.n + 16 * 1000) + 8 * 256, abs=768)
     before = g.workspace.nbytes
     g.step(10)
     assert g.workspace.nbytes >= nb.nbgs_scene_workspace_query(g.handle, g.contacts()["key"].shape[0]) > before
