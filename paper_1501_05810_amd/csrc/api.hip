@@ -793,18 +793,25 @@ nbgs_status colour_and_order(nbgs_scene_t sc, ContactBuf &cb, const SceneTable &
         NBGS_TRY(sc->dirty[1].reserve((size_t)nc));
         // passes go out in growing batches between host checks (a pass after the fixed point finds nothing
         // marked and changes nothing); the count read back is the last pass's
+        // (one change counter per pass and flag arrays the passes leave clear: no clearing launch between passes)
+        NBGS_TRY(sc->fixcnt.reserve(kFixCounters, 1.0));
+        NBGS_HIP(hipMemsetAsync(sc->fixcnt.p, 0, sizeof(int32_t) * kFixCounters, s));
         NBGS_HIP(hipMemsetAsync(sc->overflow(), 0, sizeof(int32_t), s));
+        NBGS_TRY(launch_fill_u8(sc->dirty[0].p, nc, 0, s));
+        NBGS_TRY(launch_fill_u8(sc->dirty[1].p, nc, 0, s));
         int pass = 0, batch = 1;
         for (;;) {
             for (int r = 0; r < batch; ++r, ++pass) {
-                NBGS_HIP(hipMemsetAsync(sc->remaining(), 0, sizeof(int32_t), s));
-                const uint8_t *din = pass == 0 ? nullptr : sc->dirty[(pass + 1) & 1].p;
+                int32_t *cnt = sc->fixcnt.p + pass % kFixCounters;
+                if (pass >= kFixCounters) NBGS_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
+                uint8_t *din = pass == 0 ? nullptr : sc->dirty[(pass + 1) & 1].p;
                 uint8_t *dout = sc->dirty[pass & 1].p;
                 NBGS_TRY(launch_colour_fix(cb.view(), sc->prio.p, nc, N, sc->b.inv_mass, sc->off.p, sc->cnt.p,
-                                           sc->off2.p, sc->inc2.p, sdom, din, dout, sc->remaining(), sc->overflow(),
-                                           s));
+                                           sc->off2.p, sc->inc2.p, sdom, din, dout, cnt, sc->overflow(), false, s));
             }
-            NBGS_TRY(sync_small(sc, 1, 2));
+            NBGS_HIP(hipMemcpyAsync(sc->pinned + 1, sc->fixcnt.p + (pass - 1) % kFixCounters, sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, s));
+            NBGS_TRY(sync_small(sc, 2, 1));
             sc->colour_passes = pass;
             if (sc->pinned[2]) {
                 set_error("more than 255 colours needed");

@@ -154,10 +154,11 @@ __global__ void __launch_bounds__(kBlock) k_colour_fix(ContactsView c, const uin
                                                        const double *inv_mass, const int32_t *off1,
                                                        const int32_t *cnt1, const int32_t *off2,
                                                        const int32_t *inc2, const int32_t *sdom,
-                                                       const uint8_t *dirty_in, uint8_t *dirty_out, int32_t *changed,
+                                                       uint8_t *dirty_in, uint8_t *dirty_out, int32_t *changed,
                                                        int32_t *overflow) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nc || (dirty_in && !dirty_in[j])) return;
+    if (dirty_in) dirty_in[j] = 0;  // left clear for the pass after next, which writes its marks there
     const int32_t sj = sdom ? sdom[j] : 0;
     const uint64_t kj = c.key[j], pj = prio[j];
     uint64_t used[kMaxColours / 64] = {0, 0, 0, 0};
@@ -327,10 +328,10 @@ nbgs_status launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
 
 nbgs_status launch_colour_fix(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
                               const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
-                              const int32_t *inc2, const int32_t *sdom, const uint8_t *dirty_in, uint8_t *dirty_out,
-                              int32_t *changed, int32_t *overflow, hipStream_t s) {
+                              const int32_t *inc2, const int32_t *sdom, uint8_t *dirty_in, uint8_t *dirty_out,
+                              int32_t *changed, int32_t *overflow, bool clear_out, hipStream_t s) {
     if (nc == 0) return NBGS_OK;
-    if (dirty_out) {
+    if (dirty_out && clear_out) {
         NBGS_TRY(launch_fill_u8(dirty_out, nc, 0, s));
     }
     k_colour_fix<<<grid_for(nc), kBlock, 0, s>>>(c, prio, nc, nb, inv_mass, off1, cnt1, off2, inc2, sdom, dirty_in,

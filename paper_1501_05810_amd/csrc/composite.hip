@@ -1111,10 +1111,10 @@ nbgs_status comp_detect(nbgs_composite_t sc, nbgs_stats *stats) {
         for (;;) {
             for (int r = 0; r < batch; ++r, ++pass) {
                 NBGS_HIP(hipMemsetAsync(sc->small.p + 1, 0, sizeof(int32_t), s));
-                const uint8_t *din = pass == 0 ? nullptr : sc->dirty[(pass + 1) & 1].p;
+                uint8_t *din = pass == 0 ? nullptr : sc->dirty[(pass + 1) & 1].p;
                 NBGS_TRY(launch_colour_fix(cv, sc->prio.p, nc, N, sc->b.inv_mass, sc->off1.p, sc->cnt1.p, sc->off2.p,
                                            sc->inc2.p, nullptr, din, sc->dirty[pass & 1].p, sc->small.p + 1,
-                                           sc->small.p + 2, s));
+                                           sc->small.p + 2, true, s));
             }
             NBGS_TRY(sync_small(sc, 1, 2));
             if (sc->pinned[2]) {

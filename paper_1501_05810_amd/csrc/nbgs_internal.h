@@ -292,10 +292,15 @@ nbgs_status launch_jp_round(const ContactsView &c, const uint64_t *prio, int64_t
                             const int32_t *inc2, const int32_t *sdom, int32_t *remaining, int32_t *overflow,
                             hipStream_t s);
 nbgs_status launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
+// One pass of the greedy rule; each contact it evaluates clears its dirty_in flag (so the two flag arrays stay
+// clear between the passes that write them); clear_out: clear dirty_out first (it was not left clear).
 nbgs_status launch_colour_fix(const ContactsView &c, const uint64_t *prio, int64_t nc, int32_t nb,
                               const double *inv_mass, const int32_t *off1, const int32_t *cnt1, const int32_t *off2,
-                              const int32_t *inc2, const int32_t *sdom, const uint8_t *dirty_in, uint8_t *dirty_out,
-                              int32_t *changed, int32_t *overflow, hipStream_t s);
+                              const int32_t *inc2, const int32_t *sdom, uint8_t *dirty_in, uint8_t *dirty_out,
+                              int32_t *changed, int32_t *overflow, bool clear_out, hipStream_t s);
+// Per-pass change counters of a colour-fix loop (zeroed once per colouring; a pass far beyond them re-zeroes its
+// slot), and the host check after a batch of passes: the last pass's count and the overflow flag into pinned[1..2].
+constexpr int kFixCounters = 64;
 nbgs_status launch_colour_hist(const ContactsView &c, int64_t nc, int32_t nb, const double *inv_mass, int32_t *hist,
                                hipStream_t s);
 nbgs_status launch_colour_keys(const ContactsView &c, const int32_t *sdom, int64_t nc, uint32_t *keys, uint32_t *ids,

@@ -129,6 +129,7 @@ struct nbgs_scene_s {
     // scratch
     DevBuf<int32_t> radix_hist;
     DevBuf<char> scan_tmp;
+    DevBuf<int32_t> fixcnt;  // per-pass change counters of the colour-fix loop
     DevBuf<int32_t> small;  // [0] total, [1] remaining, [2] overflow, [4] new pairs, [5] changed ids, [6] changed
                             // blocks, [7] changed dynamic bits, [8..12) ctrl, [12..14) last residual, [16..528)
                             // colour histograms
