@@ -132,9 +132,16 @@ def _walled(nb, sg, torch, dev):
     sc = sg.walled_gas()
     g = nb.GpuScene(sc.copy(), device=dev, precision="fp64")
     g.step(10)
+    # a small scene is bound by its launches: the sweep launch shape (graph replay among the candidates) is the
+    # autotuner's, chosen on one detected step (its trials leave no trace)
+    g.detect()
+    shape, _ = g.autotune(10)
+    g.solve(10)
+    g.integrate()
     wall, cs = _timed_steps(nb, torch, g, 100, 10)
     out["walled_box_4096"] = {"steps": 100, "sweeps_per_step": 10, "steps_per_s": 100 / wall,
-                              "contact_updates_per_s": cs * 10 / wall, "mean_contacts": cs / 100, "dtype": "f64"}
+                              "contact_updates_per_s": cs * 10 / wall, "mean_contacts": cs / 100, "dtype": "f64",
+                              "tuning": shape}
     g.close()
     log(f"walled box: {out['walled_box_4096']}")
     return out
